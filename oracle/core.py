@@ -1,0 +1,273 @@
+"""ctypes bindings of the C FP64 oracle (``tkdv_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The shared library is built by ``build_oracle()`` (gcc, -O2, OpenMP); it is
+compiled on first use when it is missing.  The environment variable
+``TKDV_ORACLE_LIB`` points the bindings at another build of the same source
+(used by the mutation test, which plants mistakes in a copy of the source).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tkdv_oracle.c")
+_LIB = os.path.join(_HERE, "libtkdv_oracle.so")
+
+NBINS = 64
+
+
+def build_oracle(extra_flags: list[str] | None = None, out: str | None = None) -> str:
+    """Compile the C oracle with gcc; returns the path of the shared library."""
+    out = out or _LIB
+    cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11",
+           "-o", out, _SRC, "-lm"] + list(extra_flags or [])
+    subprocess.run(cmd, check=True)
+    return out
+
+
+def _load(path: str | None = None) -> C.CDLL:
+    path = path or os.environ.get("TKDV_ORACLE_LIB") or _LIB
+    if not os.path.exists(path):
+        build_oracle(out=path)
+    return C.CDLL(path)
+
+
+class _Point(C.Structure):
+    _fields_ = [
+        ("K", C.c_int32), ("N", C.c_int32), ("proposal", C.c_int32), ("point_id", C.c_uint32),
+        ("E0", C.c_double), ("beta_p", C.c_double), ("c32", C.c_double),
+        ("alpha_star", C.c_double), ("log_M", C.c_double), ("seed", C.c_uint64),
+    ]
+
+
+class _Stats(C.Structure):
+    _fields_ = [
+        ("n_proposed", C.c_uint64), ("n_accepted", C.c_uint64), ("n_written", C.c_uint64),
+        ("n_violations", C.c_uint64), ("n_exceed", C.c_uint64), ("n_grid", C.c_uint64),
+        ("max_log_a", C.c_double),
+        ("S1", C.c_double), ("S2", C.c_double), ("S3", C.c_double), ("S4", C.c_double),
+        ("skewness", C.c_double), ("kurtosis", C.c_double), ("p_exceed", C.c_double),
+        ("hist_lo", C.c_double), ("hist_hi", C.c_double),
+        ("hist", C.c_uint64 * NBINS),
+    ]
+
+
+@dataclass
+class OracleStats:
+    n_proposed: int
+    n_accepted: int
+    n_written: int
+    n_violations: int
+    n_exceed: int
+    n_grid: int
+    max_log_a: float
+    S1: float
+    S2: float
+    S3: float
+    S4: float
+    skewness: float
+    kurtosis: float
+    p_exceed: float
+    hist_lo: float
+    hist_hi: float
+    hist: np.ndarray
+
+    @classmethod
+    def _from(cls, s: _Stats) -> "OracleStats":
+        return cls(s.n_proposed, s.n_accepted, s.n_written, s.n_violations, s.n_exceed,
+                   s.n_grid, s.max_log_a, s.S1, s.S2, s.S3, s.S4, s.skewness, s.kurtosis,
+                   s.p_exceed, s.hist_lo, s.hist_hi, np.array(s.hist[:], dtype=np.uint64))
+
+    @property
+    def acceptance(self) -> float:
+        return self.n_accepted / self.n_proposed if self.n_proposed else float("nan")
+
+
+_D = C.c_double
+_PD = C.POINTER(C.c_double)
+_PU32 = C.POINTER(C.c_uint32)
+
+lib = _load()
+lib.orc_philox4x32_10.argtypes = [_PU32, _PU32, _PU32]
+lib.orc_proposal_words.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int, _PU32]
+lib.orc_uniform.argtypes = [C.c_uint32]
+lib.orc_uniform.restype = _D
+lib.orc_normals.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_int, _PD, _PD, _PD]
+lib.orc_sigma2.argtypes = [C.c_int, _D, _D, C.c_int]
+lib.orc_sigma2.restype = _D
+lib.orc_F_alpha.argtypes = [C.c_int, _D, _D]
+lib.orc_F_alpha.restype = _D
+lib.orc_t.argtypes = [C.c_int, _PD]
+lib.orc_t.restype = _D
+lib.orc_H2.argtypes = [C.c_int, _D, _PD]
+lib.orc_H2.restype = _D
+lib.orc_H3_triad.argtypes = [C.c_int, _D, _PD]
+lib.orc_H3_triad.restype = _D
+lib.orc_H3_quad.argtypes = [C.c_int, _D, C.c_int, _PD]
+lib.orc_H3_quad.restype = _D
+lib.orc_grid.argtypes = [C.c_int, _D, C.c_int, _PD, _PD]
+lib.orc_log_ratio.argtypes = [C.c_int, _D, _D, _D, _D, C.c_int, _PD]
+lib.orc_log_ratio.restype = _D
+lib.orc_log_ratio_unnorm.argtypes = [C.c_int, _D, _D, _D, _D, C.c_int, _PD]
+lib.orc_log_ratio_unnorm.restype = _D
+lib.orc_proposal.argtypes = [C.POINTER(_Point), C.c_uint64, _PD, _PD]
+lib.orc_proposal.restype = _D
+lib.orc_sample.argtypes = [C.POINTER(_Point), C.c_uint64, C.c_uint64, C.POINTER(C.c_uint8),
+                           _PD, _PD, _PD, C.POINTER(C.c_uint64), C.c_uint64,
+                           C.POINTER(_Stats), C.c_int]
+lib.orc_sample.restype = C.c_uint64
+lib.orc_sample_until.argtypes = [C.POINTER(_Point), C.c_uint64, C.c_uint64, _PD,
+                                 C.POINTER(C.c_uint64), C.c_uint64, C.POINTER(_Stats), C.c_int]
+lib.orc_sample_until.restype = C.c_uint64
+lib.orc_stats_of.argtypes = [C.c_int, C.c_int, _D, _PD, C.c_uint64, C.POINTER(_Stats)]
+lib.orc_hist_bin.argtypes = [_D, _D]
+lib.orc_hist_bin.restype = C.c_int
+lib.orc_max_threads.restype = C.c_int
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(_PD)
+
+
+def _f64(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32))
+    out = np.zeros(4, dtype=np.uint32)
+    lib.orc_philox4x32_10(c.ctypes.data_as(_PU32), k.ctypes.data_as(_PU32), out.ctypes.data_as(_PU32))
+    return out
+
+
+def proposal_words(seed: int, i: int, point_id: int, K: int, tag: int = 0) -> np.ndarray:
+    nw = 2 * K + 2
+    out = np.zeros(nw, dtype=np.uint32)
+    lib.orc_proposal_words(seed, i, point_id, tag, nw, out.ctypes.data_as(_PU32))
+    return out
+
+
+def uniform_of_word(w: int) -> float:
+    return lib.orc_uniform(int(w))
+
+
+def normals(seed: int, i: int, point_id: int, K: int):
+    """(z[2K], U_accept, U_mix) of proposal i."""
+    z = np.zeros(2 * K)
+    ua = C.c_double()
+    um = C.c_double()
+    lib.orc_normals(seed, i, point_id, K, _dp(z), C.byref(ua), C.byref(um))
+    return z, ua.value, um.value
+
+
+def t_of(xh) -> float:
+    x = _f64(xh)
+    return lib.orc_t(x.size // 2, _dp(x))
+
+
+def H2(xh, E0: float) -> float:
+    x = _f64(xh)
+    return lib.orc_H2(x.size // 2, E0, _dp(x))
+
+
+def H3_triad(xh, E0: float) -> float:
+    x = _f64(xh)
+    return lib.orc_H3_triad(x.size // 2, E0, _dp(x))
+
+
+def H3_quad(xh, E0: float, N: int) -> float:
+    x = _f64(xh)
+    return lib.orc_H3_quad(x.size // 2, E0, N, _dp(x))
+
+
+def grid(xh, E0: float, N: int) -> np.ndarray:
+    x = _f64(xh)
+    u = np.zeros(N)
+    lib.orc_grid(x.size // 2, E0, N, _dp(x), _dp(u))
+    return u
+
+
+def log_ratio(xh, E0, beta_p, c32, alpha, proposal_kind: int, normalise_input=False) -> float:
+    """log f/g (proposal_kind 1) or log f (0), unnormalised, at x^ (or y/|y|)."""
+    x = _f64(xh)
+    fn = lib.orc_log_ratio_unnorm if normalise_input else lib.orc_log_ratio
+    return fn(x.size // 2, E0, beta_p, c32, alpha, proposal_kind, _dp(x))
+
+
+def F_alpha(K: int, beta_p: float, alpha: float) -> float:
+    return lib.orc_F_alpha(K, beta_p, alpha)
+
+
+def _point(K, N, proposal_kind, point_id, E0, beta_p, c32, alpha_star, log_M, seed) -> _Point:
+    return _Point(K, N, proposal_kind, point_id, E0, beta_p, c32, alpha_star, log_M, seed)
+
+
+def proposal(K, E0, beta_p, c32, proposal_kind, alpha_star, log_M, seed, point_id, i, N=None):
+    """(x^, log a, log U) of proposal i."""
+    p = _point(K, N or 4 * K, proposal_kind, point_id, E0, beta_p, c32, alpha_star, log_M, seed)
+    xh = np.zeros(2 * K)
+    lu = C.c_double()
+    la = lib.orc_proposal(C.byref(p), i, _dp(xh), C.byref(lu))
+    return xh, la, lu.value
+
+
+def sample(K, E0, beta_p, c32, proposal_kind, alpha_star, log_M, seed, point_id, n,
+           N, i0=0, cap=0, want_log=False, nthreads=0):
+    """Run the sampler over proposal indices [i0, i0+n).
+
+    Returns dict with accept (uint8[n]), optional log_a/log_u, xhat [min(cap,
+    n_acc), 2K], index, stats.
+    """
+    p = _point(K, N, proposal_kind, point_id, E0, beta_p, c32, alpha_star, log_M, seed)
+    acc = np.zeros(n, dtype=np.uint8)
+    la = np.zeros(n) if want_log else None
+    lu = np.zeros(n) if want_log else None
+    xo = np.zeros((max(cap, 1), 2 * K))
+    io = np.zeros(max(cap, 1), dtype=np.uint64)
+    st = _Stats()
+    lib.orc_sample(C.byref(p), i0, n, acc.ctypes.data_as(C.POINTER(C.c_uint8)),
+                   _dp(la) if la is not None else None, _dp(lu) if lu is not None else None,
+                   _dp(xo), io.ctypes.data_as(C.POINTER(C.c_uint64)), cap, C.byref(st), nthreads)
+    s = OracleStats._from(st)
+    nw = s.n_written
+    return {"accept": acc, "log_a": la, "log_u": lu, "xhat": xo[:nw], "index": io[:nw], "stats": s}
+
+
+def sample_until(K, E0, beta_p, c32, proposal_kind, alpha_star, log_M, seed, point_id,
+                 n_target, max_proposals, N, cap=None, nthreads=0):
+    """Accepted-count mode: the first n_target accepted samples by index."""
+    cap = n_target if cap is None else cap
+    p = _point(K, N, proposal_kind, point_id, E0, beta_p, c32, alpha_star, log_M, seed)
+    xo = np.zeros((max(cap, 1), 2 * K))
+    io = np.zeros(max(cap, 1), dtype=np.uint64)
+    st = _Stats()
+    lib.orc_sample_until(C.byref(p), n_target, max_proposals, _dp(xo),
+                         io.ctypes.data_as(C.POINTER(C.c_uint64)), cap, C.byref(st), nthreads)
+    s = OracleStats._from(st)
+    return {"xhat": xo[:s.n_written], "index": io[:s.n_written], "stats": s}
+
+
+def stats_of(xhat, E0: float, N: int) -> OracleStats:
+    x = _f64(xhat)
+    if x.ndim == 1:
+        x = x[None, :]
+    K = x.shape[1] // 2
+    st = _Stats()
+    lib.orc_stats_of(K, N, E0, _dp(x), x.shape[0], C.byref(st))
+    return OracleStats._from(st)
+
+
+def hist_bin(u0: float, u_max: float) -> int:
+    return lib.orc_hist_bin(u0, u_max)
+
+
+def max_threads() -> int:
+    return lib.orc_max_threads()

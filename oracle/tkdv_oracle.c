@@ -1,0 +1,505 @@
+/*
+ * tkdv_oracle.c -- plain CPU FP64 oracle for rejection sampling of the
+ * truncated-KdV (TKdV) Gibbs measure on the energy sphere S^{2K-1}
+ * (N. J. Moore & B. Foerster, "In search of rogue waves: a novel proposal
+ * distribution for parallelized rejection sampling of the truncated KdV Gibbs
+ * measure", arXiv 2411.16952).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file: only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark use it.  It shares no code with the HIP library; both sides
+ * implement the same counter-based generator (Philox4x32-10) from its
+ * published definition, so that individual proposals can be compared.
+ *
+ * Everything is computed in IEEE double precision, one proposal at a time, in
+ * the order the paper's algorithm (Sec. IV.B, steps 2-4) states it:
+ *   draw X ~ gamma_Sigma (or the standard Gaussian for the uniform proposal),
+ *   project X^ = X/|X|, evaluate H2 by Parseval and H3 by the O(K^2) double
+ *   sum, form f/(M g) and accept with that probability.
+ * There is no blocking, fusion or reordering of the per-proposal arithmetic.
+ * Proposals are independent (Sec. IV.B, closing paragraph); the only
+ * parallelism here is an OpenMP loop over proposal indices whose results are
+ * written to per-index slots, so the output does not depend on the thread
+ * count.  Statistics are accumulated afterwards in increasing proposal index.
+ *
+ * Conventions fixed by this implementation (the paper is silent on them):
+ *   - coordinate layout x^ = [x^_1..x^_K | x^_{K+1}..x^_{2K}] (cos | sin
+ *     block), so that u^_k = sqrt(E0/2pi)(x^_k - i x^_{K+k}) (Sec. II.C);
+ *   - random numbers: Philox4x32-10, key = (seed_lo, seed_hi), counter =
+ *     (i_lo, i_hi, point_id, block | tag<<16); proposal i consumes words
+ *     0..2K+1 of blocks 0..ceil((2K+2)/4)-1; word w -> U = (w + 1/2) 2^-32;
+ *     words (2m, 2m+1) -> Box-Muller pair (z_2m, z_2m+1); word 2K is the
+ *     acceptance uniform, word 2K+1 is reserved for a mixture component draw;
+ *   - accept iff log U < log a (strict).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+#define ORC_KMAX 128
+#define ORC_NBINS 64
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as  */
+/* easy as 1, 2, 3", SC'11).  Two 32x32->64 multiplications per round with  */
+/* the multipliers below, the key bumped by the two Weyl constants between  */
+/* rounds, ten rounds.                                                      */
+/* ------------------------------------------------------------------------ */
+static const uint32_t PHILOX_MUL_A = 0xD2511F53u;
+static const uint32_t PHILOX_MUL_B = 0xCD9E8D57u;
+static const uint32_t PHILOX_WEYL_A = 0x9E3779B9u;
+static const uint32_t PHILOX_WEYL_B = 0xBB67AE85u;
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t prod_a = (uint64_t)PHILOX_MUL_A * (uint64_t)x0;
+        uint64_t prod_b = (uint64_t)PHILOX_MUL_B * (uint64_t)x2;
+        uint32_t hi_a = (uint32_t)(prod_a >> 32), lo_a = (uint32_t)prod_a;
+        uint32_t hi_b = (uint32_t)(prod_b >> 32), lo_b = (uint32_t)prod_b;
+        uint32_t y0 = hi_b ^ x1 ^ k0;
+        uint32_t y1 = lo_b;
+        uint32_t y2 = hi_a ^ x3 ^ k1;
+        uint32_t y3 = lo_a;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+        k0 += PHILOX_WEYL_A;
+        k1 += PHILOX_WEYL_B;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Words 0..nwords-1 of proposal i of point point_id under the given tag. */
+void orc_proposal_words(uint64_t seed, uint64_t i, uint32_t point_id, uint32_t tag,
+                        int nwords, uint32_t *words)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    int nblocks = (nwords + 3) / 4;
+    for (int b = 0; b < nblocks; ++b) {
+        uint32_t ctr[4] = {(uint32_t)i, (uint32_t)(i >> 32), point_id,
+                           (uint32_t)b | (tag << 16)};
+        uint32_t out[4];
+        orc_philox4x32_10(ctr, key, out);
+        for (int w = 0; w < 4 && 4 * b + w < nwords; ++w) words[4 * b + w] = out[w];
+    }
+}
+
+/* Open-interval uniform from one 32-bit word: (w + 1/2) 2^-32, never 0 or 1. */
+double orc_uniform(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
+
+/*
+ * The 2K standard normals z and the two extra uniforms of proposal i.
+ * Box-Muller on word pairs: r = sqrt(-2 ln U1), z_2m = r cos(2 pi U2),
+ * z_2m+1 = r sin(2 pi U2).  u_accept = U(word 2K), u_mix = U(word 2K+1).
+ */
+void orc_normals(uint64_t seed, uint64_t i, uint32_t point_id, int K, double *z,
+                 double *u_accept, double *u_mix)
+{
+    uint32_t words[2 * ORC_KMAX + 4];
+    int nw = 2 * K + 2;
+    orc_proposal_words(seed, i, point_id, 0u, nw, words);
+    for (int m = 0; m < K; ++m) {
+        double u1 = orc_uniform(words[2 * m]);
+        double u2 = orc_uniform(words[2 * m + 1]);
+        double r = sqrt(-2.0 * log(u1));
+        double th = 2.0 * M_PI * u2;
+        z[2 * m] = r * cos(th);
+        z[2 * m + 1] = r * sin(th);
+    }
+    if (u_accept) *u_accept = orc_uniform(words[2 * K]);
+    if (u_mix) *u_mix = orc_uniform(words[2 * K + 1]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Proposal parameters (Sec. III.A): sigma_k^2 = 1/(1 + alpha beta' k^2/K^3) */
+/* for the anisotropic Gaussian gamma_Sigma, Sigma = diag(s^2, s^2).         */
+/* ------------------------------------------------------------------------ */
+double orc_sigma2(int K, double beta_p, double alpha, int k)
+{
+    double K3 = (double)K * K * K;
+    return 1.0 / (1.0 + alpha * beta_p * (double)k * k / K3);
+}
+
+/* F(alpha) = 1 - (alpha/K) sum_k 1/(1 + alpha beta' k^2/K^3)  (Sec. III.A). */
+double orc_F_alpha(int K, double beta_p, double alpha)
+{
+    double s = 0.0;
+    for (int k = 1; k <= K; ++k) s += orc_sigma2(K, beta_p, alpha, k);
+    return 1.0 - alpha / K * s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hamiltonian pieces on the sphere.                                        */
+/* ------------------------------------------------------------------------ */
+
+/* t = sum_k k^2 (x^_k^2 + x^_{K+k}^2); H2 = E0 t  (Sec. III.A, Parseval). */
+double orc_t(int K, const double *xh)
+{
+    double t = 0.0;
+    for (int k = 1; k <= K; ++k) {
+        double s = xh[k - 1] * xh[k - 1] + xh[K + k - 1] * xh[K + k - 1];
+        t += (double)k * k * s;
+    }
+    return t;
+}
+
+double orc_H2(int K, double E0, const double *xh) { return E0 * orc_t(K, xh); }
+
+/*
+ * H3 by the double sum of Sec. IV.A:
+ *   H3 = 2 pi sum_{n=1..K} Re( conj(u^_n) sum_{k=1..n-1} u^_k u^_{n-k} ),
+ * with u^_k = sqrt(E0/2pi)(x^_k - i x^_{K+k}) (Sec. II.C).
+ */
+double orc_H3_triad(int K, double E0, const double *xh)
+{
+    double a = sqrt(E0 / (2.0 * M_PI));
+    double total = 0.0;
+    for (int n = 1; n <= K; ++n) {
+        double in_re = 0.0, in_im = 0.0;
+        for (int k = 1; k <= n - 1; ++k) {
+            double p_re = a * xh[k - 1], p_im = -a * xh[K + k - 1];
+            double q_re = a * xh[n - k - 1], q_im = -a * xh[K + n - k - 1];
+            in_re += p_re * q_re - p_im * q_im;
+            in_im += p_re * q_im + p_im * q_re;
+        }
+        double n_re = a * xh[n - 1], n_im = -a * xh[K + n - 1];
+        /* Re(conj(u_n) * inner) */
+        total += n_re * in_re + n_im * in_im;
+    }
+    return 2.0 * M_PI * total;
+}
+
+/*
+ * Surface displacement on the grid xi_j = -pi + 2 pi j/N, j = 0..N-1:
+ *   u(xi) = sum_k a_k cos(k xi) + b_k sin(k xi), a_k = 2 Re u^_k, b_k = -2 Im u^_k
+ * (Sec. II.B), i.e. u = sqrt(2 E0/pi) sum_k (x^_k cos k xi + x^_{K+k} sin k xi).
+ */
+void orc_grid(int K, double E0, int N, const double *xh, double *u)
+{
+    double amp = sqrt(2.0 * E0 / M_PI);
+    for (int j = 0; j < N; ++j) {
+        double xi = -M_PI + 2.0 * M_PI * (double)j / (double)N;
+        double s = 0.0;
+        for (int k = 1; k <= K; ++k)
+            s += xh[k - 1] * cos(k * xi) + xh[K + k - 1] * sin(k * xi);
+        u[j] = amp * s;
+    }
+}
+
+/*
+ * H3 = (1/6) int u^3 dxi by the N-point trapezoid rule on the periodic grid
+ * (definition of H3, Sec. II.A).  Exact when N >= 3K+1 because u^3 is a
+ * trigonometric polynomial of degree 3K.
+ */
+double orc_H3_quad(int K, double E0, int N, const double *xh)
+{
+    double *u = (double *)malloc(sizeof(double) * (size_t)N);
+    orc_grid(K, E0, N, xh, u);
+    double s = 0.0;
+    for (int j = 0; j < N; ++j) s += u[j] * u[j] * u[j];
+    free(u);
+    return (1.0 / 6.0) * (2.0 * M_PI / N) * s;
+}
+
+/* beta H_K = beta'/(E0 K^2) (H2 - (C3/C2) H3)   (Sec. IV.A). */
+double orc_beta_H(int K, double E0, double beta_p, double c32, const double *xh)
+{
+    double H2 = orc_H2(K, E0, xh);
+    double H3 = orc_H3_triad(K, E0, xh);
+    return beta_p / (E0 * (double)K * K) * (H2 - c32 * H3);
+}
+
+/*
+ * log of the unnormalised ratio target/proposal on the sphere.
+ *   proposal 0 (uniform mu0):  log f = -beta H_K
+ *   proposal 1 (Sigma):        log f/g = -beta H_K + K log(1 + alpha* beta' t/K^3)
+ * (Sec. IV.A, ratio f/g with Const = 1/Z).
+ */
+double orc_log_ratio(int K, double E0, double beta_p, double c32, double alpha,
+                     int proposal, const double *xh)
+{
+    double lr = -orc_beta_H(K, E0, beta_p, c32, xh);
+    if (proposal == 1) {
+        double K3 = (double)K * K * K;
+        lr += K * log1p(alpha * beta_p * orc_t(K, xh) / K3);
+    }
+    return lr;
+}
+
+/* Same, for an arbitrary non-zero y in R^{2K} projected to the sphere. */
+double orc_log_ratio_unnorm(int K, double E0, double beta_p, double c32, double alpha,
+                            int proposal, const double *y)
+{
+    double xh[2 * ORC_KMAX];
+    double r2 = 0.0;
+    for (int m = 0; m < 2 * K; ++m) r2 += y[m] * y[m];
+    double r = sqrt(r2);
+    for (int m = 0; m < 2 * K; ++m) xh[m] = y[m] / r;
+    return orc_log_ratio(K, E0, beta_p, c32, alpha, proposal, xh);
+}
+
+/* ------------------------------------------------------------------------ */
+/* One proposal: draw, project, evaluate (Sec. IV.B steps 2-4).             */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t K;
+    int32_t N;          /* grid points for the statistics                   */
+    int32_t proposal;   /* 0 uniform, 1 Sigma                                */
+    uint32_t point_id;  /* third counter word                                */
+    double E0, beta_p, c32;
+    double alpha_star;  /* root of F (Sigma proposal only)                   */
+    double log_M;       /* log of the rejection constant                     */
+    uint64_t seed;
+} orc_point;
+
+/* x^ of proposal i; returns log a = log f/(M g) and the acceptance log U. */
+double orc_proposal(const orc_point *p, uint64_t i, double *xh, double *log_u)
+{
+    int K = p->K;
+    double z[2 * ORC_KMAX];
+    double x[2 * ORC_KMAX];
+    double u_acc;
+    orc_normals(p->seed, i, p->point_id, K, z, &u_acc, NULL);
+    for (int m = 0; m < 2 * K; ++m) {
+        double scale = 1.0;
+        if (p->proposal == 1) scale = sqrt(orc_sigma2(K, p->beta_p, p->alpha_star, m % K + 1));
+        x[m] = scale * z[m];
+    }
+    double r2 = 0.0;
+    for (int m = 0; m < 2 * K; ++m) r2 += x[m] * x[m];
+    double r = sqrt(r2);
+    for (int m = 0; m < 2 * K; ++m) xh[m] = x[m] / r;
+    if (log_u) *log_u = log(u_acc);
+    return orc_log_ratio(K, p->E0, p->beta_p, p->c32, p->alpha_star, p->proposal, xh) - p->log_M;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Statistics of the accepted ensemble (moments of u pooled over samples x  */
+/* grid points, exceedance of 2 sigma with sigma = sqrt(E0/pi), histogram of */
+/* u(0) on [-u_max, u_max], u_max = sqrt(2 K E0/pi)).                       */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint64_t n_proposed, n_accepted, n_written, n_violations, n_exceed, n_grid;
+    double max_log_a;
+    double S1, S2, S3, S4;
+    double skewness, kurtosis, p_exceed;
+    double hist_lo, hist_hi;
+    uint64_t hist[ORC_NBINS];
+} orc_stats;
+
+typedef struct {
+    int K, N;
+    double E0, amp, two_sigma, u_max;
+    double *cosv, *sinv; /* [N][K] */
+} orc_grid_table;
+
+static void grid_table_init(orc_grid_table *g, int K, int N, double E0)
+{
+    g->K = K; g->N = N; g->E0 = E0;
+    g->amp = sqrt(2.0 * E0 / M_PI);
+    g->two_sigma = 2.0 * sqrt(E0 / M_PI);
+    g->u_max = sqrt(2.0 * K * E0 / M_PI);
+    g->cosv = (double *)malloc(sizeof(double) * (size_t)N * K);
+    g->sinv = (double *)malloc(sizeof(double) * (size_t)N * K);
+    for (int j = 0; j < N; ++j) {
+        double xi = -M_PI + 2.0 * M_PI * (double)j / (double)N;
+        for (int k = 1; k <= K; ++k) {
+            g->cosv[(size_t)j * K + k - 1] = cos(k * xi);
+            g->sinv[(size_t)j * K + k - 1] = sin(k * xi);
+        }
+    }
+}
+
+static void grid_table_free(orc_grid_table *g) { free(g->cosv); free(g->sinv); }
+
+int orc_hist_bin(double u0, double u_max)
+{
+    double pos = (u0 + u_max) / (2.0 * u_max) * ORC_NBINS;
+    int b = (int)floor(pos);
+    if (b < 0) b = 0;
+    if (b > ORC_NBINS - 1) b = ORC_NBINS - 1;
+    return b;
+}
+
+static void stats_add_sample(orc_stats *st, const orc_grid_table *g, const double *xh)
+{
+    int K = g->K;
+    for (int j = 0; j < g->N; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < K; ++k)
+            s += xh[k] * g->cosv[(size_t)j * K + k] + xh[K + k] * g->sinv[(size_t)j * K + k];
+        double u = g->amp * s;
+        double u2 = u * u;
+        st->S1 += u;
+        st->S2 += u2;
+        st->S3 += u2 * u;
+        st->S4 += u2 * u2;
+        if (u > g->two_sigma) st->n_exceed++;
+    }
+    st->n_grid += (uint64_t)g->N;
+    /* u(0): xi = 0 is a grid point when N is even; evaluated spectrally. */
+    double s0 = 0.0;
+    for (int k = 0; k < K; ++k) s0 += xh[k];
+    st->hist[orc_hist_bin(g->amp * s0, g->u_max)]++;
+}
+
+static void stats_finish(orc_stats *st)
+{
+    if (st->n_grid > 0) {
+        double n = (double)st->n_grid;
+        double m2 = st->S2 / n, m3 = st->S3 / n, m4 = st->S4 / n;
+        st->skewness = m3 / pow(m2, 1.5);
+        st->kurtosis = m4 / (m2 * m2);
+        st->p_exceed = (double)st->n_exceed / n;
+    }
+}
+
+/*
+ * The rejection sampler over proposal indices [i0, i0+n).  For every index:
+ * accept[i-i0] (0/1), and optionally log_a / log_u.  Accepted samples are
+ * written in increasing index, up to cap rows of x^ (2K doubles) and index.
+ * Statistics cover every accepted sample, written or not.
+ * Returns the number accepted.
+ */
+uint64_t orc_sample(const orc_point *p, uint64_t i0, uint64_t n, uint8_t *accept,
+                    double *log_a_out, double *log_u_out, double *xhat_out,
+                    uint64_t *index_out, uint64_t cap, orc_stats *st, int nthreads)
+{
+    int K = p->K;
+    uint8_t *acc = accept ? accept : (uint8_t *)malloc(n ? n : 1);
+    double max_la = -INFINITY;
+    uint64_t nviol = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(static) reduction(max : max_la) reduction(+ : nviol)
+    for (int64_t q = 0; q < (int64_t)n; ++q) {
+        double xh[2 * ORC_KMAX];
+        double lu;
+        double la = orc_proposal(p, i0 + (uint64_t)q, xh, &lu);
+        acc[q] = (uint8_t)(lu < la);
+        if (la > max_la) max_la = la;
+        if (la > 0.0) nviol++;
+        if (log_a_out) log_a_out[q] = la;
+        if (log_u_out) log_u_out[q] = lu;
+    }
+    orc_stats local;
+    memset(&local, 0, sizeof(local));
+    orc_grid_table g;
+    grid_table_init(&g, K, p->N, p->E0);
+    local.hist_lo = -g.u_max;
+    local.hist_hi = g.u_max;
+    uint64_t nacc = 0;
+    double xh[2 * ORC_KMAX];
+    for (uint64_t q = 0; q < n; ++q) {
+        if (!acc[q]) continue;
+        orc_proposal(p, i0 + q, xh, NULL);
+        if (nacc < cap) {
+            if (xhat_out)
+                for (int m = 0; m < 2 * K; ++m) xhat_out[nacc * 2 * K + m] = xh[m];
+            if (index_out) index_out[nacc] = i0 + q;
+            local.n_written++;
+        }
+        stats_add_sample(&local, &g, xh);
+        nacc++;
+    }
+    grid_table_free(&g);
+    local.n_proposed = n;
+    local.n_accepted = nacc;
+    local.n_violations = nviol;
+    local.max_log_a = max_la;
+    stats_finish(&local);
+    if (st) *st = local;
+    if (!accept) free(acc);
+    return nacc;
+}
+
+/*
+ * Accepted-count mode: scan proposal indices from 0 in blocks of `block`
+ * until n_target samples are accepted or max_proposals are used.  The result
+ * is the first n_target accepted samples by index; n_proposed is the index of
+ * the last one plus one.
+ */
+uint64_t orc_sample_until(const orc_point *p, uint64_t n_target, uint64_t max_proposals,
+                          double *xhat_out, uint64_t *index_out, uint64_t cap,
+                          orc_stats *st, int nthreads)
+{
+    int K = p->K;
+    const uint64_t block = 1u << 16;
+    uint8_t *acc = (uint8_t *)malloc(block);
+    orc_stats local;
+    memset(&local, 0, sizeof(local));
+    orc_grid_table g;
+    grid_table_init(&g, K, p->N, p->E0);
+    local.hist_lo = -g.u_max;
+    local.hist_hi = g.u_max;
+    double max_la = -INFINITY;
+    uint64_t nacc = 0, last = 0, nviol = 0;
+    double xh[2 * ORC_KMAX];
+    for (uint64_t base = 0; base < max_proposals && nacc < n_target; base += block) {
+        uint64_t nb = max_proposals - base < block ? max_proposals - base : block;
+        double *la = (double *)malloc(sizeof(double) * nb);
+        orc_sample(p, base, nb, acc, la, NULL, NULL, NULL, 0, NULL, nthreads);
+        for (uint64_t q = 0; q < nb && nacc < n_target; ++q) {
+            if (la[q] > max_la) max_la = la[q];
+            if (la[q] > 0.0) nviol++;
+            last = base + q;
+            if (!acc[q]) continue;
+            orc_proposal(p, base + q, xh, NULL);
+            if (nacc < cap) {
+                if (xhat_out)
+                    for (int m = 0; m < 2 * K; ++m) xhat_out[nacc * 2 * K + m] = xh[m];
+                if (index_out) index_out[nacc] = base + q;
+                local.n_written++;
+            }
+            stats_add_sample(&local, &g, xh);
+            nacc++;
+        }
+        free(la);
+    }
+    grid_table_free(&g);
+    free(acc);
+    local.n_proposed = max_proposals ? last + 1 : 0;
+    local.n_accepted = nacc;
+    local.n_violations = nviol;
+    local.max_log_a = max_la;
+    stats_finish(&local);
+    if (st) *st = local;
+    return nacc;
+}
+
+/* Statistics of an externally supplied set of samples (rows of x^). */
+void orc_stats_of(int K, int N, double E0, const double *xhat, uint64_t n, orc_stats *st)
+{
+    orc_stats local;
+    memset(&local, 0, sizeof(local));
+    orc_grid_table g;
+    grid_table_init(&g, K, N, E0);
+    local.hist_lo = -g.u_max;
+    local.hist_hi = g.u_max;
+    for (uint64_t s = 0; s < n; ++s) stats_add_sample(&local, &g, xhat + s * 2 * K);
+    grid_table_free(&g);
+    local.n_accepted = n;
+    stats_finish(&local);
+    *st = local;
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,71 @@
+"""Planted mistakes in a copy of the oracle must each fail a pin.
+
+Each case edits one line of a temporary copy of ``oracle/tkdv_oracle.c`` (a
+sign, an index, a dropped factor, a swapped function), builds it, and runs the
+fast subset of ``test_oracle_pins.py`` against that build in a subprocess.  The
+pins pass on the real oracle (that is ``test_oracle_pins.py`` itself); here
+every mutant must make at least one of them fail.  Mistakes in the Philox
+constants are not in this list: no closed form fixes them, and they are
+caught by bit-exact comparison with the independent HIP implementation.
+"""
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "tkdv_oracle.c")
+
+FAST_PINS = " or ".join([
+    "appendix_A", "dirichlet_kernel", "double_sum_equals", "parseval", "H3_odd",
+    "box_muller", "uniform_sphere_law", "K2_brute_force", "uniform_proposal_linear",
+    "paper_linear_rows and 16-", "positive_nonlinearity",
+])
+
+MUTATIONS = {
+    "triad_product_sign": ("in_re += p_re * q_re - p_im * q_im;", "in_re += p_re * q_re + p_im * q_im;"),
+    "triad_index": ("double q_re = a * xh[n - k - 1], q_im = -a * xh[K + n - k - 1];",
+                    "double q_re = a * xh[n - k - 1], q_im = -a * xh[K + n - k];"),
+    "triad_no_conjugate": ("total += n_re * in_re + n_im * in_im;", "total += n_re * in_re - n_im * in_im;"),
+    "triad_prefactor": ("return 2.0 * M_PI * total;", "return M_PI * total;"),
+    "t_dropped_square": ("t += (double)k * k * s;", "t += (double)k * s;"),
+    "g_sign": ("lr += K * log1p(alpha * beta_p * orc_t(K, xh) / K3);",
+               "lr -= K * log1p(alpha * beta_p * orc_t(K, xh) / K3);"),
+    "sigma_power": ("return 1.0 / (1.0 + alpha * beta_p * (double)k * k / K3);",
+                    "return 1.0 / (1.0 + alpha * beta_p * (double)k / K3);"),
+    "sigma_index": ("scale = sqrt(orc_sigma2(K, p->beta_p, p->alpha_star, m % K + 1));",
+                    "scale = sqrt(orc_sigma2(K, p->beta_p, p->alpha_star, m / 2 + 1));"),
+    "grid_sin_as_cos": ("s += xh[k - 1] * cos(k * xi) + xh[K + k - 1] * sin(k * xi);",
+                        "s += xh[k - 1] * cos(k * xi) + xh[K + k - 1] * cos(k * xi);"),
+    "box_muller_pair": ("z[2 * m + 1] = r * sin(th);", "z[2 * m + 1] = r * cos(th);"),
+    "box_muller_radius": ("double r = sqrt(-2.0 * log(u1));", "double r = sqrt(-log(u1));"),
+    "hamiltonian_sign": ("return beta_p / (E0 * (double)K * K) * (H2 - c32 * H3);",
+                         "return beta_p / (E0 * (double)K * K) * (H2 + c32 * H3);"),
+    "hamiltonian_scale": ("return beta_p / (E0 * (double)K * K) * (H2 - c32 * H3);",
+                          "return beta_p / (E0 * (double)K) * (H2 - c32 * H3);"),
+    "stats_cube": ("st->S3 += u2 * u;", "st->S3 += u2 * u2;"),
+    "hist_bins": ("double pos = (u0 + u_max) / (2.0 * u_max) * ORC_NBINS;",
+                  "double pos = (u0 + u_max) / (2.0 * u_max) * (ORC_NBINS - 1);"),
+    "accept_rule": ("acc[q] = (uint8_t)(lu < la);", "acc[q] = (uint8_t)(lu < la + 0.05);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_is_caught(name):
+    old, new = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not found exactly once"
+    with tempfile.TemporaryDirectory() as d:
+        c_path = os.path.join(d, "mut.c")
+        so_path = os.path.join(d, "libmut.so")
+        with open(c_path, "w") as f:
+            f.write(src.replace(old, new))
+        subprocess.run(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", "-o", so_path,
+                        c_path, "-lm"], check=True)
+        env = dict(os.environ, TKDV_ORACLE_LIB=so_path, OMP_NUM_THREADS="4")
+        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                            os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-k", FAST_PINS],
+                           cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
