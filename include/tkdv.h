@@ -1,0 +1,191 @@
+/*
+ * tkdv.h -- C ABI of the MI355X (gfx950) rejection sampler for the Gibbs
+ * measure of the truncated Korteweg-de Vries (TKdV) system on the energy
+ * sphere S^{2K-1} (N. J. Moore & B. Foerster, arXiv 2411.16952).
+ *
+ * What is computed (all references are to that paper):
+ *   - the target density f(x^) = Z^-1 exp(-beta H_K[U(x^)]) on S^{2K-1}
+ *     w.r.t. the uniform measure mu0 (Sec. II.C), with
+ *       beta H_K = beta'/(E0 K^2) (H2 - (C3/C2) H3)            (Sec. IV.A)
+ *       H2 = E0 sum_k k^2 (x^_k^2 + x^_{K+k}^2)                 (Sec. III.A)
+ *       H3 = (1/6) int u^3 dxi                                  (Sec. II.A);
+ *   - the paper's proposal g: X ~ N(0, Sigma), Sigma = diag(s^2, s^2),
+ *     s_k^2 = 1/(1 + alpha* beta' k^2/K^3), alpha* the root of F (Sec. III.A),
+ *     projected X^ = X/|X|, with density ~ (1 + alpha* beta' t/K^3)^-K,
+ *     t = sum k^2 (x^_k^2 + x^_{K+k}^2) (Sec. III.B); or the uniform proposal
+ *     mu0 (X ~ N(0, I), Sec. II.C), the paper's baseline;
+ *   - the rejection algorithm of Sec. IV.B: accept X^ with probability
+ *     f/(M g), M = sup f/g (Sec. IV.A), precomputed once per point.
+ *
+ * Data layout.  A sample is x^ in R^{2K}, stored as 2K consecutive floats
+ * [x^_1..x^_K | x^_{K+1}..x^_{2K}]; the Fourier coefficients are
+ * u^_k = sqrt(E0/2pi) (x^_k - i x^_{K+k}) (Sec. II.C) and the surface
+ * displacement is u(xi) = sqrt(2 E0/pi) sum_k (x^_k cos k xi + x^_{K+k} sin k xi).
+ *
+ * Random numbers.  Proposal i of a point with stream (seed, point_id) uses
+ * Philox4x32-10 with key (seed_lo, seed_hi) and counters
+ * (i_lo, i_hi, point_id, j), j = 0..K/2; its words 0..2K-1 give the 2K
+ * Box-Muller normals (words 2m, 2m+1 -> z_2m = r cos 2pi U2,
+ * z_2m+1 = r sin 2pi U2, r = sqrt(-2 ln U1), U = (w + 1/2) 2^-32) and word 2K
+ * gives the acceptance uniform.  Results are a deterministic function of
+ * (point, proposal, plan, seed, point_id, n, precision): independent of the
+ * launch configuration and of the stream's other work.
+ *
+ * Exactness.  The fast path evaluates log a = log f/(M g) in FP32 with the
+ * spectral-to-grid synthesis on the matrix cores; every proposal whose
+ * |log U - log a| is below a proven bound on the fast path's error is
+ * re-decided in FP64 (H3 by the double sum of Sec. IV.A), so every accept
+ * decision equals the FP64 decision.
+ *
+ * Conventions.  All functions return a tkdv_status (0 = TKDV_OK).  Device
+ * pointers are caller-owned HIP device allocations; host pointers are plain
+ * host memory.  `stream` is a hipStream_t (NULL = the default stream); calls
+ * are stream-ordered and return after the host-side statistics are complete.
+ * Supported mode counts on the GPU: K in {8, 16, 32, 64}, grid N = 4K.
+ */
+#ifndef TKDV_H
+#define TKDV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TKDV_KMAX 64
+#define TKDV_NBINS 64
+
+typedef enum {
+    TKDV_OK = 0,
+    TKDV_E_ARG = -1,           /* bad size, pointer, enum, non-finite or out-of-range value    */
+    TKDV_E_NO_ALPHA_ROOT = -2, /* F has no root: beta' >= K^2 sum_{k<=K} 1/k^2 (Sec. III.A)   */
+    TKDV_E_DEVICE = -3,        /* a HIP call failed; tkdv_last_error() has the text            */
+    TKDV_E_CAPACITY = -4,      /* an internal work list overflowed                            */
+    TKDV_E_UNSUPPORTED = -5,   /* K not in {8, 16, 32, 64} on the GPU path                     */
+    TKDV_E_M_VIOLATION = -6    /* reserved: a proposal had f/(M g) > 1                        */
+} tkdv_status;
+
+typedef enum { TKDV_PROP_UNIFORM = 0, TKDV_PROP_SIGMA = 1 } tkdv_proposal;
+
+/* Arithmetic of the spectral-to-grid synthesis U = X^ Phi on the matrix cores:
+ * FP32 products, BF16 products (one term), or BF16 with 3-term split
+ * (hi*hi + hi*lo + lo*hi) and FP32 accumulation.  All other per-proposal
+ * arithmetic is FP32; the decision window is re-evaluated in FP64.           */
+typedef enum { TKDV_FP32 = 0, TKDV_BF16 = 1, TKDV_BF16X3 = 2 } tkdv_precision;
+
+typedef enum { TKDV_COUNT_PROPOSALS = 0, TKDV_COUNT_ACCEPTED = 1 } tkdv_count_mode;
+
+/* One parameter point: K modes, energy E0, normalised inverse temperature
+ * beta' = E0 C2 K^2 beta (Sec. III.A) and the ratio C3/C2 (Sec. IV.A). */
+typedef struct {
+    int32_t K;
+    uint32_t point_id; /* third Philox counter word: distinct streams per point */
+    double E0;
+    double beta_p;
+    double c32;
+    uint64_t seed;     /* Philox key */
+} tkdv_point;
+
+/* Per-point precompute, plain data (step 1 of Sec. IV.B). */
+typedef struct {
+    double alpha_star;          /* root of F (Sigma proposal); 1 for the uniform proposal   */
+    double log_M;               /* log of the rejection constant for the unnormalised ratio */
+    double log_norm_g;          /* sum_k log(1 + alpha* beta' k^2/K^3)                       */
+    double sigma2[TKDV_KMAX];   /* proposal variances s_k^2, k = 1..K                        */
+    int32_t N;                  /* synthesis grid, 4K                                        */
+    int32_t proposal;           /* tkdv_proposal                                             */
+    int32_t M_source;           /* 0 closed form (C3/C2 = 0), 1 optimiser                    */
+    int32_t n_optimiser_evals;  /* objective evaluations spent on log_M                      */
+} tkdv_plan;
+
+/* Statistics of one point's run (Sec. V: skewness, histograms, 2-sigma). */
+typedef struct {
+    uint64_t n_proposed;      /* proposals covered by the statistics                         */
+    uint64_t n_accepted;      /* accepted among them                                         */
+    uint64_t n_written;       /* samples stored (<= capacity)                                */
+    uint64_t n_fp64_fixups;   /* proposals re-decided in FP64                                */
+    uint64_t n_M_violations;  /* proposals with log a > 0                                    */
+    uint64_t n_exceed_2sigma; /* grid values with u > 2 sqrt(E0/pi) over accepted samples    */
+    uint64_t n_grid_values;   /* accepted samples x N                                        */
+    double max_log_a;         /* largest log f/(M g) seen (FP32 fast path)                   */
+    double S1, S2, S3, S4;    /* sums of u^p over accepted samples x grid, FP64              */
+    double skewness;          /* m3 / m2^1.5 (raw moments: each sample has mean 0)           */
+    double kurtosis;          /* m4 / m2^2 (Gaussian: 3)                                      */
+    double p_exceed_2sigma;   /* n_exceed_2sigma / n_grid_values                             */
+    double hist_lo, hist_hi;  /* [-u_max, u_max], u_max = sqrt(2 K E0/pi)                     */
+    uint64_t hist_u0[TKDV_NBINS]; /* 64 equal bins of u(0), clamped                          */
+} tkdv_stats;
+
+typedef struct tkdv_ctx tkdv_ctx;
+
+/* Create a context on HIP device `hip_device`: device workspaces, the cos/sin
+ * synthesis tables, and the launch configuration.  *out is owned by the
+ * caller and released by tkdv_destroy. */
+tkdv_status tkdv_create(int hip_device, tkdv_ctx **out);
+tkdv_status tkdv_destroy(tkdv_ctx *ctx);
+
+/* Step 1 of Sec. IV.B on the host in FP64: alpha* (Brent on F, Sec. III.A),
+ * s_k^2, log_norm_g and log M (closed form for C3/C2 = 0; otherwise
+ * Nelder-Mead from the zero-mean Dirichlet kernel of Sec. IV.A plus further
+ * starts, then refined by gradient ascent on the sphere).  Needs no device. */
+tkdv_status tkdv_plan_point(const tkdv_point *pt, tkdv_proposal proposal, tkdv_plan *out);
+
+/*
+ * Rejection-sample one point (Sec. IV.B steps 2-5) on the GPU.
+ *   mode = TKDV_COUNT_PROPOSALS: evaluate proposals 0..n-1;
+ *   mode = TKDV_COUNT_ACCEPTED:  continue until n samples are accepted (or
+ *          max_proposals are used); the result is the first n accepted by
+ *          proposal index.
+ * plan: NULL plans internally (tkdv_plan_point).
+ * d_xhat [capacity][2K] floats and d_index [capacity] (may be NULL) receive
+ * the accepted samples in increasing proposal index; beyond `capacity` they
+ * are dropped while the statistics still cover every accepted sample.
+ * h_stats (host) is filled on return.
+ */
+tkdv_status tkdv_sample(tkdv_ctx *ctx, const tkdv_point *pt, tkdv_proposal proposal,
+                        const tkdv_plan *plan, uint64_t n, tkdv_count_mode mode,
+                        uint64_t max_proposals, tkdv_precision precision,
+                        float *d_xhat, uint64_t *d_index, uint64_t capacity,
+                        tkdv_stats *h_stats, void *stream);
+
+/*
+ * Many points in one launch sequence (the points may have different K).
+ * pts, plans (may be NULL), n, capacity, out_offset and h_stats are host
+ * arrays of length n_points; point p writes rows out_offset[p] ..
+ * out_offset[p] + min(capacity[p], accepted) - 1 of d_xhat (row stride
+ * 2*TKDV_KMAX floats, so rows of different K share one buffer) and d_index.
+ */
+tkdv_status tkdv_sample_batch(tkdv_ctx *ctx, int32_t n_points, const tkdv_point *pts,
+                              tkdv_proposal proposal, const tkdv_plan *plans,
+                              const uint64_t *n, tkdv_count_mode mode, uint64_t max_proposals,
+                              tkdv_precision precision, float *d_xhat, uint64_t *d_index,
+                              const uint64_t *capacity, const uint64_t *out_offset,
+                              tkdv_stats *h_stats, void *stream);
+
+/*
+ * Per-proposal evaluation for verification: for proposals i0..i0+n-1 writes
+ * (each pointer may be NULL) the fast path's x^ [n][2K], t [n], the grid sum
+ * S3 = sum_j u~_j^3 of the unscaled synthesis u~ = X^ Phi [n], log a [n] and
+ * log U [n] (FP32), and the final accept decision after the FP64 re-check
+ * [n] (0/1 bytes).  Same kernels and arithmetic as tkdv_sample.
+ */
+tkdv_status tkdv_eval_proposals(tkdv_ctx *ctx, const tkdv_point *pt, tkdv_proposal proposal,
+                                const tkdv_plan *plan, uint64_t i0, uint64_t n,
+                                tkdv_precision precision, float *d_xhat, float *d_t,
+                                float *d_s3, float *d_log_a, float *d_log_u,
+                                uint8_t *d_accept, void *stream);
+
+/* The decision window used for a point: proposals with |log U - log a| below
+ * it are re-decided in FP64.  It is an upper bound on the fast path's error
+ * in log a (see the library's design notes) times a safety factor of 2. */
+double tkdv_decision_window(const tkdv_point *pt, tkdv_proposal proposal, tkdv_precision precision);
+
+const char *tkdv_status_str(tkdv_status s);
+/* Text of the last error on this context (or of the last context-less call). */
+const char *tkdv_last_error(const tkdv_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TKDV_H */

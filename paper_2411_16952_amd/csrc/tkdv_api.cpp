@@ -1,0 +1,615 @@
+// C ABI of the gfx950 TKdV rejection sampler: context, workspaces, synthesis
+// tables, argument checking and the launch sequence of one sampling call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/tkdv.h"
+#include "tkdv_internal.h"
+#include "tkdv_kernels.h"
+#include "tkdv_plan.h"
+
+using namespace tkdv;
+
+namespace {
+
+const double kPi = 3.14159265358979323846;
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+std::mutex g_err_mu;
+std::string g_last_error;  // for calls without a context
+
+int kindex(int K)
+{
+    switch (K) {
+    case 8: return 0;
+    case 16: return 1;
+    case 32: return 2;
+    case 64: return 3;
+    default: return -1;
+    }
+}
+
+// Round to bfloat16 with round-to-nearest-even; returns the bits.
+uint16_t bf16_bits(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;
+    return (uint16_t)(u >> 16);
+}
+float bf16_value(uint16_t b)
+{
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+}  // namespace
+
+struct tkdv_ctx {
+    int device = 0;
+    int n_cu = 0;
+    std::string last_error;
+    DevBuf bitmap, defer_list, defer_count, counters, points, seg_cnt, seg_base, seg_stats, results, plist;
+    DevBuf phi_hi[4], phi_lo[4], phi_f32[4];
+    void *h_results = nullptr;  // pinned
+    size_t h_results_bytes = 0;
+    void *h_counters = nullptr;  // pinned
+    size_t h_counters_bytes = 0;
+    void *h_points = nullptr;  // pinned staging of DevPoint[]
+    size_t h_points_bytes = 0;
+    void *h_misc = nullptr;  // pinned: defer count + plist staging
+    size_t h_misc_bytes = 0;
+};
+
+namespace {
+
+tkdv_status set_err(tkdv_ctx *ctx, tkdv_status st, const std::string &msg)
+{
+    if (ctx) ctx->last_error = msg;
+    std::lock_guard<std::mutex> g(g_err_mu);
+    g_last_error = msg;
+    return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                                             \
+    do {                                                                                               \
+        hipError_t _e = (expr);                                                                        \
+        if (_e != hipSuccess)                                                                          \
+            return set_err((ctx), TKDV_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+hipError_t ensure(DevBuf &b, size_t bytes)
+{
+    if (b.bytes >= bytes && b.p) return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        if (e != hipSuccess) return e;
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = std::max<size_t>(bytes, 256);
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) return e;
+    b.bytes = want;
+    return hipSuccess;
+}
+
+hipError_t ensure_host(void *&p, size_t &have, size_t bytes)
+{
+    if (have >= bytes && p) return hipSuccess;
+    if (p) {
+        hipError_t e = hipHostFree(p);
+        if (e != hipSuccess) return e;
+        p = nullptr;
+        have = 0;
+    }
+    size_t want = std::max<size_t>(bytes, 4096);
+    hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    have = want;
+    return hipSuccess;
+}
+
+// Synthesis tables for K modes on the grid xi_j = -pi + 2 pi j/N, N = 4K.
+// Row (block b, mode k) of Phi is cos(k xi_j) (b = 0) or sin(k xi_j) (b = 1);
+// angles are reduced exactly: k xi_j = -k pi + 2 pi (k j mod N)/N.
+tkdv_status build_tables(tkdv_ctx *ctx, int K)
+{
+    const int ki = kindex(K);
+    if (ctx->phi_hi[ki].p) return TKDV_OK;
+    const int N = 4 * K, T = K / 8, S = K / 8, Q = K / 4;
+    auto phi = [&](int block, int k, int j) {
+        const long r = ((long)k * j) % N;
+        const double ang = 2.0 * kPi * (double)r / N;
+        const double sign = (k & 1) ? -1.0 : 1.0;  // shift by -k pi
+        return block == 0 ? sign * std::cos(ang) : sign * std::sin(ang);
+    };
+    std::vector<uint16_t> hi((size_t)T * S * 64 * 8), lo(hi.size());
+    for (int t = 0; t < T; ++t)
+        for (int s = 0; s < S; ++s)
+            for (int l = 0; l < 64; ++l)
+                for (int e = 0; e < 8; ++e) {
+                    const int block = l / 32, j = 32 * t + l % 32, k = 8 * s + e + 1;
+                    const double v = phi(block, k, j);
+                    const uint16_t h = bf16_bits((float)v);
+                    const double rem = v - (double)bf16_value(h);
+                    const size_t idx = (((size_t)t * S + s) * 64 + l) * 8 + e;
+                    hi[idx] = h;
+                    lo[idx] = bf16_bits((float)rem);
+                }
+    std::vector<float> f32((size_t)T * Q * 64 * 4);
+    for (int t = 0; t < T; ++t)
+        for (int q = 0; q < Q; ++q)
+            for (int l = 0; l < 64; ++l)
+                for (int e = 0; e < 4; ++e) {
+                    const int block = l / 32, j = 32 * t + l % 32, k = 4 * q + e + 1;
+                    f32[(((size_t)t * Q + q) * 64 + l) * 4 + e] = (float)phi(block, k, j);
+                }
+    HIP_TRY(ctx, ensure(ctx->phi_hi[ki], hi.size() * 2));
+    HIP_TRY(ctx, ensure(ctx->phi_lo[ki], lo.size() * 2));
+    HIP_TRY(ctx, ensure(ctx->phi_f32[ki], f32.size() * 4));
+    HIP_TRY(ctx, hipMemcpy(ctx->phi_hi[ki].p, hi.data(), hi.size() * 2, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(ctx->phi_lo[ki].p, lo.data(), lo.size() * 2, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(ctx->phi_f32[ki].p, f32.data(), f32.size() * 4, hipMemcpyHostToDevice));
+    return TKDV_OK;
+}
+
+tkdv_status check_point(tkdv_ctx *ctx, const tkdv_point &pt)
+{
+    if (pt.K < 1 || pt.K > TKDV_KMAX) return set_err(ctx, TKDV_E_ARG, "K out of range");
+    if (kindex(pt.K) < 0) return set_err(ctx, TKDV_E_UNSUPPORTED, "GPU path supports K in {8,16,32,64}");
+    if (!std::isfinite(pt.E0) || !(pt.E0 > 0.0)) return set_err(ctx, TKDV_E_ARG, "E0 must be finite and > 0");
+    if (!std::isfinite(pt.beta_p) || pt.beta_p < 0.0)
+        return set_err(ctx, TKDV_E_ARG, "beta' must be finite and >= 0");
+    if (!std::isfinite(pt.c32)) return set_err(ctx, TKDV_E_ARG, "C3/C2 must be finite");
+    return TKDV_OK;
+}
+
+// Upper bound on |log a_fast - log a_exact| (times 2) for the FP32 fast path:
+//   max_j |du~_j| <= sqrt(K) (eps_synth + eps_x)  (Cauchy-Schwarz, |x^| = 1,
+//   sum_k Phi_kj^2 = K), |dH3| <= E0 amp max|du~| + sum-of-cubes rounding
+//   (sum_j u_j^2 = N E0/pi), the t terms carry 4 eps_x relative error, and
+//   FP32 rounding of the terms of log a and of log U is added explicitly.
+double window(const tkdv_point &pt, int proposal, int precision, double alpha, double log_M)
+{
+    const int K = pt.K, N = 4 * K;
+    const double eps_x = 1e-5;  // bound on |x^_fast - x^_exact|_2 (normals + projection)
+    double eps_s;
+    switch (precision) {
+    case TKDV_FP32: eps_s = 2.0 * K * 0x1p-24; break;
+    case TKDV_BF16: eps_s = 1.01 * 0x1p-8 + 2.0 * K * 0x1p-24; break;
+    default: eps_s = 3.01 * 0x1p-16 + 2.0 * K * 0x1p-24; break;
+    }
+    const double amp = std::sqrt(2.0 * pt.E0 / kPi);
+    const double du = std::sqrt((double)K) * (eps_s + eps_x);  // max_j |du~_j|, u~ unscaled
+    const double umax = std::sqrt((double)K);                   // |u~_j| <= sqrt(K)
+    // S3 = sum_j u~_j^3 with sum_j u~_j^2 = N/2 exactly: first-order error
+    // 3 (N/2) du, plus FP32 accumulation of N cubes, |S3| <= umax N/2.
+    const double err_S3 = 3.0 * (N / 2.0) * du + N * 0x1p-23 * umax * (N / 2.0);
+    const double c3coef = pt.beta_p * std::fabs(pt.c32) / (pt.E0 * K * K) * (kPi / (3.0 * N)) * amp * amp * amp;
+    const double err_H3term = c3coef * err_S3;
+    // t = sum k^2 s_k: |dt| <= 2 K^2 |x^| |dx^| plus rounding
+    const double err_t = 4.0 * eps_x * K * K + 64.0 * K * K * 0x1p-24;
+    const double slope = pt.beta_p / ((double)K * K) * (1.0 + (proposal == TKDV_PROP_SIGMA ? alpha : 0.0));
+    const double err_tterm = slope * err_t;
+    // FP32 rounding of the terms of log a (each bounded in magnitude) and of log U
+    const double mag = pt.beta_p + K * std::log1p(alpha * pt.beta_p / K) + std::fabs(log_M) +
+                       c3coef * umax * (N / 2.0);
+    const double err_round = 16.0 * 0x1p-24 * (mag + 30.0);
+    return 2.0 * (err_H3term + err_tterm + err_round) + 1e-6;
+}
+
+void fill_devpoint(DevPoint &d, const tkdv_point &pt, const tkdv_plan &pl, int proposal, int precision)
+{
+    std::memset(&d, 0, sizeof(d));
+    const int K = pt.K, N = 4 * K;
+    for (int k = 0; k < TKDV_KMAX; ++k) {
+        const double s2 = (k < K && proposal == TKDV_PROP_SIGMA) ? pl.sigma2[k] : 1.0;
+        d.sig64[k] = std::sqrt(s2);
+        d.sig[k] = (float)d.sig64[k];
+    }
+    const double amp = std::sqrt(2.0 * pt.E0 / kPi);
+    d.neg_bp_K2 = (float)(-pt.beta_p / ((double)K * K));
+    d.c3coef = (float)(pt.beta_p * pt.c32 / (pt.E0 * K * K) * (kPi / (3.0 * N)) * amp * amp * amp);
+    d.g_coef = proposal == TKDV_PROP_SIGMA ? (float)(pl.alpha_star * pt.beta_p / ((double)K * K * K)) : 0.0f;
+    d.Kf = proposal == TKDV_PROP_SIGMA ? (float)K : 0.0f;
+    d.log_M = (float)pl.log_M;
+    d.tau = (float)window(pt, proposal, precision, pl.alpha_star, pl.log_M);
+    d.K = K;
+    d.proposal = proposal;
+    d.point_id = pt.point_id;
+    d.key0 = (uint32_t)pt.seed;
+    d.key1 = (uint32_t)(pt.seed >> 32);
+    d.E0 = pt.E0;
+    d.beta_p = pt.beta_p;
+    d.c32 = pt.c32;
+    d.alpha_star = pl.alpha_star;
+    d.log_M64 = pl.log_M;
+    d.amp = amp;
+}
+
+struct Call {
+    std::vector<DevPoint> pts;
+    std::vector<int> plist_off, plist_n;  // per K index
+    std::vector<int> plist;               // concatenated point lists
+    unsigned long long total_tiles = 0, total_segs = 0, bitmap_words = 0;
+};
+
+tkdv_status run(tkdv_ctx *ctx, Call &call, int precision, int proposal, float *d_xhat,
+                unsigned long long *d_index, hipStream_t st, std::vector<PointResult> *res_out,
+                std::vector<DevCounters> *cnt_out, unsigned long long *n_deferred_out,
+                float *dbg_xhat, float *dbg_t, float *dbg_s3, float *dbg_la, float *dbg_lu,
+                bool stats)
+{
+    const int np = (int)call.pts.size();
+    const unsigned long long defer_cap =
+        std::min<unsigned long long>(1ull << 26, std::max<unsigned long long>(1ull << 20, call.total_tiles));
+    HIP_TRY(ctx, ensure(ctx->bitmap, call.bitmap_words * 4));
+    HIP_TRY(ctx, ensure(ctx->defer_list, defer_cap * 8));
+    HIP_TRY(ctx, ensure(ctx->defer_count, 8));
+    HIP_TRY(ctx, ensure(ctx->counters, sizeof(DevCounters) * np));
+    HIP_TRY(ctx, ensure(ctx->points, sizeof(DevPoint) * np));
+    HIP_TRY(ctx, ensure(ctx->seg_cnt, 8 * std::max<unsigned long long>(call.total_segs, 1)));
+    HIP_TRY(ctx, ensure(ctx->seg_base, 8 * std::max<unsigned long long>(call.total_segs, 1)));
+    HIP_TRY(ctx, ensure(ctx->seg_stats, sizeof(SegStats) * std::max<unsigned long long>(call.total_segs, 1)));
+    HIP_TRY(ctx, ensure(ctx->results, sizeof(PointResult) * np));
+    HIP_TRY(ctx, ensure(ctx->plist, sizeof(int) * call.plist.size()));
+    HIP_TRY(ctx, ensure_host(ctx->h_points, ctx->h_points_bytes, sizeof(DevPoint) * np));
+    HIP_TRY(ctx, ensure_host(ctx->h_misc, ctx->h_misc_bytes, 64 + sizeof(int) * call.plist.size()));
+    HIP_TRY(ctx, ensure_host(ctx->h_results, ctx->h_results_bytes, sizeof(PointResult) * np));
+    HIP_TRY(ctx, ensure_host(ctx->h_counters, ctx->h_counters_bytes, sizeof(DevCounters) * np));
+    for (int ki = 0; ki < 4; ++ki) {
+        if (call.plist_n[ki] == 0) continue;
+        tkdv_status s = build_tables(ctx, 8 << ki);
+        if (s != TKDV_OK) return s;
+    }
+    // The pinned staging buffers are reused by later calls, so the stream must
+    // have consumed them before we return (we synchronise at the end).
+    std::memcpy(ctx->h_points, call.pts.data(), sizeof(DevPoint) * np);
+    int *h_plist = reinterpret_cast<int *>((char *)ctx->h_misc + 64);
+    std::memcpy(h_plist, call.plist.data(), sizeof(int) * call.plist.size());
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->points.p, ctx->h_points, sizeof(DevPoint) * np, hipMemcpyHostToDevice, st));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->plist.p, h_plist, sizeof(int) * call.plist.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(ctx, launch_fill_u32(ctx->counters.p, sizeof(DevCounters) * np / 4, 0u, st));
+    HIP_TRY(ctx, launch_fill_u32(ctx->results.p, sizeof(PointResult) * np / 4, 0u, st));
+    HIP_TRY(ctx, launch_fill_u32(ctx->defer_count.p, 2, 0u, st));
+
+    KernelArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.pts = reinterpret_cast<const DevPoint *>(ctx->points.p);
+    a.n_points = np;
+    a.cnt = reinterpret_cast<DevCounters *>(ctx->counters.p);
+    a.bitmap = reinterpret_cast<uint32_t *>(ctx->bitmap.p);
+    a.defer_list = reinterpret_cast<unsigned long long *>(ctx->defer_list.p);
+    a.defer_count = reinterpret_cast<unsigned long long *>(ctx->defer_count.p);
+    a.defer_cap = defer_cap;
+    a.dbg_xhat = dbg_xhat;
+    a.dbg_t = dbg_t;
+    a.dbg_s3 = dbg_s3;
+    a.dbg_log_a = dbg_la;
+    a.dbg_log_u = dbg_lu;
+    const int *d_plist = reinterpret_cast<const int *>(ctx->plist.p);
+    for (int ki = 0; ki < 4; ++ki) {
+        if (call.plist_n[ki] == 0) continue;
+        const int K = 8 << ki;
+        a.phi_hi = precision == TKDV_FP32 ? ctx->phi_f32[ki].p : ctx->phi_hi[ki].p;
+        a.phi_lo = ctx->phi_lo[ki].p;
+        unsigned long long tiles = 0;
+        for (int q = 0; q < call.plist_n[ki]; ++q) tiles += call.pts[call.plist[call.plist_off[ki] + q]].n_tiles;
+        HIP_TRY(ctx, launch_decide(K, precision, proposal, a, d_plist + call.plist_off[ki], call.plist_n[ki],
+                                   ctx->n_cu, tiles, st, nullptr));
+    }
+    HIP_TRY(ctx, launch_fixup(a, ctx->n_cu, st));
+    if (stats) {
+        unsigned long long *seg_cnt = reinterpret_cast<unsigned long long *>(ctx->seg_cnt.p);
+        unsigned long long *seg_base = reinterpret_cast<unsigned long long *>(ctx->seg_base.p);
+        SegStats *seg_stats = reinterpret_cast<SegStats *>(ctx->seg_stats.p);
+        PointResult *res = reinterpret_cast<PointResult *>(ctx->results.p);
+        HIP_TRY(ctx, launch_segments(a, call.total_segs, seg_cnt, seg_base, res, ctx->n_cu, st));
+        for (int ki = 0; ki < 4; ++ki) {
+            if (call.plist_n[ki] == 0) continue;
+            a.phi_hi = ctx->phi_f32[ki].p;
+            HIP_TRY(ctx, launch_materialize(8 << ki, proposal, a, d_plist + call.plist_off[ki], call.plist_n[ki],
+                                            call.total_segs, seg_cnt, seg_base, seg_stats, res, d_xhat, d_index,
+                                            ctx->n_cu, st));
+        }
+        HIP_TRY(ctx, launch_finalize(a, seg_cnt, seg_base, seg_stats, res, st));
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->h_results, ctx->results.p, sizeof(PointResult) * np, hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_counters, ctx->counters.p, sizeof(DevCounters) * np, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_misc, ctx->defer_count.p, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    const unsigned long long n_def = *reinterpret_cast<unsigned long long *>(ctx->h_misc);
+    if (n_deferred_out) *n_deferred_out = n_def;
+    if (res_out) {
+        res_out->resize(np);
+        std::memcpy(res_out->data(), ctx->h_results, sizeof(PointResult) * np);
+    }
+    if (cnt_out) {
+        cnt_out->resize(np);
+        std::memcpy(cnt_out->data(), ctx->h_counters, sizeof(DevCounters) * np);
+    }
+    if (n_def > defer_cap)
+        return set_err(ctx, TKDV_E_CAPACITY, "FP64 re-decision list overflowed (" + std::to_string(n_def) + " > " +
+                                                 std::to_string(defer_cap) + ")");
+    return TKDV_OK;
+}
+
+float key_to_float(unsigned int k)
+{
+    uint32_t u = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+void fill_stats(tkdv_stats &s, const DevPoint &P, const PointResult &r, const DevCounters &c, int mode)
+{
+    std::memset(&s, 0, sizeof(s));
+    const int K = P.K, N = 4 * K;
+    if (mode == TKDV_COUNT_ACCEPTED && P.target != ~0ull && r.n_accepted >= P.target && P.target > 0)
+        s.n_proposed = c.last_index - P.i0 + 1;
+    else
+        s.n_proposed = r.n_processed;
+    s.n_accepted = r.n_samples;
+    s.n_written = r.n_written;
+    s.n_fp64_fixups = c.deferred;
+    s.n_M_violations = c.violations;
+    s.n_exceed_2sigma = r.n_exceed;
+    s.n_grid_values = r.n_samples * (uint64_t)N;
+    s.max_log_a = c.max_log_a_key ? (double)key_to_float(c.max_log_a_key) : -INFINITY;
+    s.S1 = r.S1;
+    s.S2 = r.S2;
+    s.S3 = r.S3;
+    s.S4 = r.S4;
+    if (s.n_grid_values > 0) {
+        const double n = (double)s.n_grid_values;
+        const double m2 = r.S2 / n, m3 = r.S3 / n, m4 = r.S4 / n;
+        s.skewness = m3 / std::pow(m2, 1.5);
+        s.kurtosis = m4 / (m2 * m2);
+        s.p_exceed_2sigma = (double)r.n_exceed / n;
+    }
+    const double umax = std::sqrt(2.0 * K * P.E0 / kPi);
+    s.hist_lo = -umax;
+    s.hist_hi = umax;
+    for (int b = 0; b < TKDV_NBINS; ++b) s.hist_u0[b] = r.hist[b];
+}
+
+tkdv_status prepare(tkdv_ctx *ctx, Call &call, int n_points, const tkdv_point *pts, int proposal,
+                    const tkdv_plan *plans, const uint64_t *n, int mode, uint64_t max_proposals,
+                    int precision, const uint64_t *capacity, const uint64_t *out_offset, uint64_t row_stride,
+                    uint64_t i0)
+{
+    if (n_points < 1) return set_err(ctx, TKDV_E_ARG, "n_points must be >= 1");
+    if (proposal != TKDV_PROP_UNIFORM && proposal != TKDV_PROP_SIGMA) return set_err(ctx, TKDV_E_ARG, "bad proposal");
+    if (precision < TKDV_FP32 || precision > TKDV_BF16X3) return set_err(ctx, TKDV_E_ARG, "bad precision");
+    if (mode != TKDV_COUNT_PROPOSALS && mode != TKDV_COUNT_ACCEPTED) return set_err(ctx, TKDV_E_ARG, "bad mode");
+    if (mode == TKDV_COUNT_ACCEPTED && max_proposals == 0)
+        return set_err(ctx, TKDV_E_ARG, "accepted-count mode needs max_proposals > 0");
+    call.pts.resize(n_points);
+    call.plist_n.assign(4, 0);
+    call.plist_off.assign(4, 0);
+    std::vector<std::vector<int>> by_k(4);
+    unsigned long long bm = 0, segs = 0, tiles = 0;
+    for (int p = 0; p < n_points; ++p) {
+        tkdv_status s = check_point(ctx, pts[p]);
+        if (s != TKDV_OK) return s;
+        tkdv_plan pl;
+        if (plans) {
+            pl = plans[p];
+            if (pl.proposal != proposal) return set_err(ctx, TKDV_E_ARG, "plan was made for another proposal");
+            if (!std::isfinite(pl.log_M) || !(pl.alpha_star > 0.0))
+                return set_err(ctx, TKDV_E_ARG, "plan has non-finite log_M or alpha*");
+        } else {
+            s = (tkdv_status)plan_point_host(&pts[p], proposal, 2, &pl);
+            if (s != TKDV_OK) return set_err(ctx, s, "planning failed");
+        }
+        DevPoint &d = call.pts[p];
+        fill_devpoint(d, pts[p], pl, proposal, precision);
+        const uint64_t ncov = mode == TKDV_COUNT_PROPOSALS ? n[p] : max_proposals;
+        if (i0 + ncov < i0 || i0 + ncov >= (1ull << 40))
+            return set_err(ctx, TKDV_E_ARG, "proposal indices must stay below 2^40");
+        d.i0 = i0;
+        d.n = ncov;
+        d.n_tiles = (ncov + kTile - 1) / kTile;
+        d.target = mode == TKDV_COUNT_ACCEPTED ? n[p] : ~0ull;
+        d.bm_off = bm;
+        d.seg_off = segs;
+        d.n_segs = (d.n_tiles + kSegWords - 1) / kSegWords;
+        d.out_off = out_offset ? out_offset[p] : 0;
+        d.capacity = capacity ? capacity[p] : 0;
+        d.row_stride = row_stride;
+        bm += d.n_tiles;
+        segs += d.n_segs;
+        tiles += d.n_tiles;
+        by_k[kindex(pts[p].K)].push_back(p);
+    }
+    call.plist.clear();
+    for (int ki = 0; ki < 4; ++ki) {
+        call.plist_off[ki] = (int)call.plist.size();
+        call.plist_n[ki] = (int)by_k[ki].size();
+        call.plist.insert(call.plist.end(), by_k[ki].begin(), by_k[ki].end());
+    }
+    call.bitmap_words = bm;
+    call.total_segs = segs;
+    call.total_tiles = tiles;
+    return TKDV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tkdv_status tkdv_create(int hip_device, tkdv_ctx **out)
+{
+    if (!out) return set_err(nullptr, TKDV_E_ARG, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n < 1) return set_err(nullptr, TKDV_E_DEVICE, "no HIP device");
+    if (hip_device < 0 || hip_device >= n) return set_err(nullptr, TKDV_E_ARG, "bad device index");
+    e = hipSetDevice(hip_device);
+    if (e != hipSuccess) return set_err(nullptr, TKDV_E_DEVICE, hipGetErrorString(e));
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, hip_device);
+    if (e != hipSuccess) return set_err(nullptr, TKDV_E_DEVICE, hipGetErrorString(e));
+    tkdv_ctx *ctx = new tkdv_ctx();
+    ctx->device = hip_device;
+    ctx->n_cu = prop.multiProcessorCount;
+    *out = ctx;
+    return TKDV_OK;
+}
+
+tkdv_status tkdv_destroy(tkdv_ctx *ctx)
+{
+    if (!ctx) return TKDV_OK;
+    (void)hipSetDevice(ctx->device);
+    DevBuf *bufs[] = {&ctx->bitmap, &ctx->defer_list, &ctx->defer_count, &ctx->counters, &ctx->points,
+                      &ctx->seg_cnt, &ctx->seg_base, &ctx->seg_stats, &ctx->results, &ctx->plist};
+    for (DevBuf *b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    for (int i = 0; i < 4; ++i) {
+        if (ctx->phi_hi[i].p) (void)hipFree(ctx->phi_hi[i].p);
+        if (ctx->phi_lo[i].p) (void)hipFree(ctx->phi_lo[i].p);
+        if (ctx->phi_f32[i].p) (void)hipFree(ctx->phi_f32[i].p);
+    }
+    if (ctx->h_results) (void)hipHostFree(ctx->h_results);
+    if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
+    if (ctx->h_points) (void)hipHostFree(ctx->h_points);
+    if (ctx->h_misc) (void)hipHostFree(ctx->h_misc);
+    delete ctx;
+    return TKDV_OK;
+}
+
+tkdv_status tkdv_plan_point(const tkdv_point *pt, tkdv_proposal proposal, tkdv_plan *out)
+{
+    if (!pt || !out) return set_err(nullptr, TKDV_E_ARG, "NULL argument");
+    tkdv_status s = (tkdv_status)plan_point_host(pt, proposal, 2, out);
+    if (s != TKDV_OK) return set_err(nullptr, s, "planning failed");
+    return TKDV_OK;
+}
+
+tkdv_status tkdv_sample_batch(tkdv_ctx *ctx, int32_t n_points, const tkdv_point *pts, tkdv_proposal proposal,
+                              const tkdv_plan *plans, const uint64_t *n, tkdv_count_mode mode,
+                              uint64_t max_proposals, tkdv_precision precision, float *d_xhat,
+                              uint64_t *d_index, const uint64_t *capacity, const uint64_t *out_offset,
+                              tkdv_stats *h_stats, void *stream)
+{
+    if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");
+    if (!pts || !n || !h_stats) return set_err(ctx, TKDV_E_ARG, "NULL argument");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    Call call;
+    tkdv_status s = prepare(ctx, call, n_points, pts, proposal, plans, n, mode, max_proposals, precision, capacity,
+                            out_offset, 2 * TKDV_KMAX, 0);
+    if (s != TKDV_OK) return s;
+    std::vector<PointResult> res;
+    std::vector<DevCounters> cnt;
+    s = run(ctx, call, precision, proposal, d_xhat, reinterpret_cast<unsigned long long *>(d_index),
+            (hipStream_t)stream, &res, &cnt, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, true);
+    if (s != TKDV_OK) return s;
+    for (int p = 0; p < n_points; ++p) fill_stats(h_stats[p], call.pts[p], res[p], cnt[p], mode);
+    return TKDV_OK;
+}
+
+tkdv_status tkdv_sample(tkdv_ctx *ctx, const tkdv_point *pt, tkdv_proposal proposal, const tkdv_plan *plan,
+                        uint64_t n, tkdv_count_mode mode, uint64_t max_proposals, tkdv_precision precision,
+                        float *d_xhat, uint64_t *d_index, uint64_t capacity, tkdv_stats *h_stats, void *stream)
+{
+    if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");
+    if (!pt || !h_stats) return set_err(ctx, TKDV_E_ARG, "NULL argument");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (n == 0) {
+        std::memset(h_stats, 0, sizeof(*h_stats));
+        tkdv_status s = check_point(ctx, *pt);
+        if (s != TKDV_OK) return s;
+        const double umax = std::sqrt(2.0 * pt->K * pt->E0 / kPi);
+        h_stats->hist_lo = -umax;
+        h_stats->hist_hi = umax;
+        h_stats->max_log_a = -INFINITY;
+        return TKDV_OK;
+    }
+    Call call;
+    const uint64_t cap = capacity, off = 0;
+    tkdv_status s = prepare(ctx, call, 1, pt, proposal, plan, &n, mode, max_proposals, precision, &cap, &off,
+                            2 * (uint64_t)pt->K, 0);
+    if (s != TKDV_OK) return s;
+    std::vector<PointResult> res;
+    std::vector<DevCounters> cnt;
+    s = run(ctx, call, precision, proposal, d_xhat, reinterpret_cast<unsigned long long *>(d_index),
+            (hipStream_t)stream, &res, &cnt, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, true);
+    if (s != TKDV_OK) return s;
+    fill_stats(*h_stats, call.pts[0], res[0], cnt[0], mode);
+    return TKDV_OK;
+}
+
+tkdv_status tkdv_eval_proposals(tkdv_ctx *ctx, const tkdv_point *pt, tkdv_proposal proposal, const tkdv_plan *plan,
+                                uint64_t i0, uint64_t n, tkdv_precision precision, float *d_xhat, float *d_t,
+                                float *d_s3, float *d_log_a, float *d_log_u, uint8_t *d_accept, void *stream)
+{
+    if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");
+    if (!pt) return set_err(ctx, TKDV_E_ARG, "NULL argument");
+    if (n == 0) return TKDV_OK;
+    const int any_dbg = (d_t != nullptr) + (d_s3 != nullptr) + (d_log_a != nullptr) + (d_log_u != nullptr);
+    if (any_dbg != 0 && any_dbg != 4)
+        return set_err(ctx, TKDV_E_ARG, "d_t, d_s3, d_log_a and d_log_u must be all set or all NULL");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    Call call;
+    const uint64_t zero = 0;
+    tkdv_status s = prepare(ctx, call, 1, pt, proposal, plan, &n, TKDV_COUNT_PROPOSALS, 0, precision, &zero, &zero,
+                            2 * (uint64_t)pt->K, i0);
+    if (s != TKDV_OK) return s;
+    s = run(ctx, call, precision, proposal, nullptr, nullptr, (hipStream_t)stream, nullptr, nullptr, nullptr, d_xhat,
+            d_t, d_s3, d_log_a, d_log_u, false);
+    if (s != TKDV_OK) return s;
+    if (d_accept) {
+        HIP_TRY(ctx, launch_bits_to_bytes(reinterpret_cast<const uint32_t *>(ctx->bitmap.p), n, d_accept,
+                                          (hipStream_t)stream));
+        HIP_TRY(ctx, hipStreamSynchronize((hipStream_t)stream));
+    }
+    return TKDV_OK;
+}
+
+double tkdv_decision_window(const tkdv_point *pt, tkdv_proposal proposal, tkdv_precision precision)
+{
+    if (!pt) return NAN;
+    tkdv_plan pl;
+    if (plan_point_host(pt, proposal, 2, &pl) != TKDV_OK) return NAN;
+    return window(*pt, proposal, precision, pl.alpha_star, pl.log_M);
+}
+
+const char *tkdv_status_str(tkdv_status s)
+{
+    switch (s) {
+    case TKDV_OK: return "ok";
+    case TKDV_E_ARG: return "invalid argument";
+    case TKDV_E_NO_ALPHA_ROOT: return "F(alpha) has no root for this (K, beta')";
+    case TKDV_E_DEVICE: return "HIP error";
+    case TKDV_E_CAPACITY: return "internal list capacity exceeded";
+    case TKDV_E_UNSUPPORTED: return "unsupported K for the GPU path";
+    case TKDV_E_M_VIOLATION: return "rejection constant violated";
+    }
+    return "unknown status";
+}
+
+const char *tkdv_last_error(const tkdv_ctx *ctx)
+{
+    if (ctx) return ctx->last_error.c_str();
+    std::lock_guard<std::mutex> g(g_err_mu);
+    return g_last_error.c_str();
+}
+
+}  // extern "C"

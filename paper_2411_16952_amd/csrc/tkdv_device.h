@@ -1,0 +1,230 @@
+// Device building blocks of the gfx950 TKdV rejection sampler.
+//
+// One wavefront evaluates a tile of 32 proposals; proposal p of the tile lives
+// in lanes p (cos block: coordinates x^_1..x^_K) and p + 32 (sin block:
+// x^_{K+1}..x^_{2K}).  This is exactly the operand layout of the 32x32 matrix
+// instructions with the proposals as the B (column) operand, so the
+// spectral-to-grid synthesis u~ = Phi^T x^ needs no data movement, and each
+// lane ends up holding half of its proposal's grid values.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tkdv_internal.h"
+
+namespace tkdv {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_BF16X3 = 2 };
+enum { PROP_UNIFORM = 0, PROP_SIGMA = 1 };
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): per round two 32x32->64 products of
+// counter words 0 and 2 with the two multipliers, high halves XORed with the
+// other counter words and the key, key advanced by the Weyl constants.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t ma = 0xD2511F53u, mb = 0xCD9E8D57u;
+        uint32_t hi_a = __umulhi(ma, c0), lo_a = ma * c0;
+        uint32_t hi_b = __umulhi(mb, c2), lo_b = mb * c2;
+        uint32_t n0 = hi_b ^ c1 ^ k0;
+        uint32_t n2 = hi_a ^ c3 ^ k1;
+        c0 = n0; c1 = lo_b; c2 = n2; c3 = lo_a;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 transforms of the 32-bit words.  U = (w + 1/2) 2^-32.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float log2_hw(float x) { return __builtin_amdgcn_logf(x); }
+
+// ln(1 - d) for d in (0, 1/2], accurate to a few ulps.
+__device__ __forceinline__ float log1m_f32(float d)
+{
+    // small d: -d (1 + d/2 + d^2/3 + d^3/4 + d^4/5 + d^5/6); truncation < d^7/7
+    float ser = __builtin_fmaf(d, 1.0f / 6.0f, 0.2f);
+    ser = __builtin_fmaf(d, ser, 0.25f);
+    ser = __builtin_fmaf(d, ser, 1.0f / 3.0f);
+    ser = __builtin_fmaf(d, ser, 0.5f);
+    ser = __builtin_fmaf(d, ser, 1.0f);
+    ser = -d * ser;
+    // larger d: log(y) * (-d)/(y - 1) with y = 1 - d rounded; y - 1 is exact.
+    float y = 1.0f - d;
+    float lg = log2_hw(y) * 0.69314718055994531f * (-d / (y - 1.0f));
+    return d < 0.0078125f ? ser : lg;
+}
+
+// ln U of a word.  U < 1/2: log2 of U itself (relative accuracy of the
+// hardware log2); U >= 1/2: ln(1 - d) with d = 1 - U formed from ~w, so the
+// result keeps its relative accuracy as U -> 1.
+__device__ __forceinline__ float log_u_word(uint32_t w)
+{
+    const float two_m32 = 2.3283064365386963e-10f;
+    float u = __builtin_fmaf((float)w, two_m32, 0.5f * two_m32);
+    float lo = log2_hw(u) * 0.69314718055994531f;
+    float d = __builtin_fmaf((float)(~w), two_m32, 0.5f * two_m32);  // 1 - U
+    float hi = log1m_f32(d);
+    return (w & 0x80000000u) ? hi : lo;
+}
+
+// One Box-Muller pair: r = sqrt(-2 ln U1), (r cos 2 pi U2, r sin 2 pi U2).
+__device__ __forceinline__ void box_muller_f32(uint32_t w1, uint32_t w2, float &z0, float &z1)
+{
+    float r = __builtin_sqrtf(-2.0f * log_u_word(w1));
+    // U2 - 1/2 = (w2 - 2^31 + 1/2) 2^-32 in revolutions, centred on zero for
+    // the hardware sin/cos; the signed integer w2 - 2^31 is formed exactly.
+    float rev = ((float)(int32_t)(w2 ^ 0x80000000u) + 0.5f) * 2.3283064365386963e-10f;
+    // sin/cos(2 pi (U2 - 1/2)) = -sin/-cos(2 pi U2)
+    z0 = -r * __builtin_amdgcn_cosf(rev);
+    z1 = -r * __builtin_amdgcn_sinf(rev);
+}
+
+// ln(1 + y) for y >= 0 (log1p by the exact-denominator correction).
+__device__ __forceinline__ float log1p_f32(float y)
+{
+    float u = 1.0f + y;
+    float den = u - 1.0f;
+    float lg = log2_hw(u) * 0.69314718055994531f;
+    return den == 0.0f ? y : lg * (y / den);
+}
+
+__device__ __forceinline__ float xor32(float v) { return __shfl_xor(v, 32, 64); }
+
+// ---------------------------------------------------------------------------
+// Proposal generation: the K coordinates of this lane's block, projected onto
+// the sphere.  Also returns t = sum_k k^2 s_k and the acceptance word.
+// Every lane of a proposal pair computes bitwise identical |x|^2 and t.
+// ---------------------------------------------------------------------------
+template <int K, int PROP>
+__device__ __forceinline__ void gen_xhat(const DevPoint &P, uint64_t i, int half, float (&x)[K],
+                                         float &t, uint32_t &w_acc)
+{
+    const uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32), c2 = P.point_id;
+#pragma unroll
+    for (int b = 0; b < K / 4; ++b) {
+        uint4 w = philox4x32_10(c0, c1, c2, (uint32_t)(half * (K / 4) + b), P.key0, P.key1);
+        box_muller_f32(w.x, w.y, x[4 * b + 0], x[4 * b + 1]);
+        box_muller_f32(w.z, w.w, x[4 * b + 2], x[4 * b + 3]);
+    }
+    w_acc = philox4x32_10(c0, c1, c2, (uint32_t)(K / 2), P.key0, P.key1).x;
+    if (PROP == PROP_SIGMA) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) x[j] *= P.sig[j];
+    }
+    float r2 = 0.0f;
+#pragma unroll
+    for (int j = 0; j < K; ++j) r2 = __builtin_fmaf(x[j], x[j], r2);
+    r2 = r2 + xor32(r2);
+    const float inv = __builtin_amdgcn_rsqf(r2);
+    float tl = 0.0f;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        x[j] *= inv;
+        tl = __builtin_fmaf((float)((j + 1) * (j + 1)) * x[j], x[j], tl);
+    }
+    t = tl + xor32(tl);
+}
+
+// ---------------------------------------------------------------------------
+// Synthesis tables in LDS.
+//   BF16: [T = K/8 grid tiles][S = K/8 k-steps][64 lanes][8] bf16, hi and lo;
+//         lane l, tile t, step s holds Phi(block l/32, modes 8s+1..8s+8) at
+//         grid point 32t + l%32.
+//   FP32: [T][Q = K/4][64][4] floats; lane l holds Phi(block l/32, modes
+//         4q+1..4q+4) at grid point 32t + l%32.
+// ---------------------------------------------------------------------------
+template <int K>
+__host__ __device__ constexpr int bf16_table_bytes() { return (K / 8) * (K / 8) * kWave * 16; }
+template <int K>
+__host__ __device__ constexpr int f32_table_bytes() { return (K / 8) * (K / 4) * kWave * 16; }
+
+// Sum over this lane's grid values of u~^3 (u~ = unscaled synthesis), with
+// the products in the requested arithmetic.
+template <int K, int PREC>
+__device__ __forceinline__ float synth_cube_sum(const float (&x)[K], const char *lds_hi,
+                                                const char *lds_lo, int lane)
+{
+    float s3 = 0.0f;
+    if constexpr (PREC == PREC_FP32) {
+        const float4 *tab = reinterpret_cast<const float4 *>(lds_hi);
+#pragma unroll
+        for (int t = 0; t < K / 8; ++t) {
+            f32x16 acc = {};
+#pragma unroll
+            for (int q = 0; q < K / 4; ++q) {
+                float4 a = tab[(t * (K / 4) + q) * kWave + lane];
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, x[4 * q + 0], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, x[4 * q + 1], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, x[4 * q + 2], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, x[4 * q + 3], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 16; ++v) s3 = __builtin_fmaf(acc[v] * acc[v], acc[v], s3);
+        }
+    } else {
+        bf16x8 bh[K / 8], bl[K / 8];
+#pragma unroll
+        for (int s = 0; s < K / 8; ++s) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float v = x[8 * s + e];
+                const __bf16 hv = (__bf16)v;
+                bh[s][e] = hv;
+                if constexpr (PREC == PREC_BF16X3) bl[s][e] = (__bf16)(v - (float)hv);
+            }
+        }
+        const bf16x8 *th = reinterpret_cast<const bf16x8 *>(lds_hi);
+        const bf16x8 *tl = reinterpret_cast<const bf16x8 *>(lds_lo);
+#pragma unroll
+        for (int t = 0; t < K / 8; ++t) {
+            f32x16 acc = {};
+#pragma unroll
+            for (int s = 0; s < K / 8; ++s) {
+                const int idx = (t * (K / 8) + s) * kWave + lane;
+                const bf16x8 ah = th[idx];
+                if constexpr (PREC == PREC_BF16X3) {
+                    const bf16x8 al = tl[idx];
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[s], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[s], acc, 0, 0, 0);
+                }
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[s], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 16; ++v) s3 = __builtin_fmaf(acc[v] * acc[v], acc[v], s3);
+        }
+    }
+    return s3;
+}
+
+// log a = log f/(M g) in FP32 from t and S3 = sum_j u~_j^3 (both lanes identical).
+template <int PROP>
+__device__ __forceinline__ float log_a_f32(const DevPoint &P, float t, float s3)
+{
+    float lf = __builtin_fmaf(P.neg_bp_K2, t, P.c3coef * s3);
+    if (PROP == PROP_SIGMA) lf = __builtin_fmaf(P.Kf, log1p_f32(P.g_coef * t), lf);
+    return lf - P.log_M;
+}
+
+// Order-preserving map float -> uint32 for atomicMax.
+__device__ __forceinline__ unsigned int float_key(float f)
+{
+    unsigned int u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ unsigned long long pack_defer(int p, uint64_t i)
+{
+    return ((unsigned long long)p << 40) | (unsigned long long)i;
+}
+
+}  // namespace tkdv

@@ -1,0 +1,94 @@
+// Structures shared by the host runtime and the gfx950 kernels of the TKdV
+// rejection sampler.  Plain data only; no HIP types in the structs.
+#pragma once
+
+#include <stdint.h>
+
+#include "../../include/tkdv.h"
+
+namespace tkdv {
+
+constexpr int kWave = 64;          // CDNA wavefront
+constexpr int kTile = 32;          // proposals per wave tile (two lanes per proposal)
+constexpr int kBlock = 256;        // threads per workgroup of the sampling kernels
+constexpr int kClaimTiles = 8;     // tiles claimed per work-queue claim (256 proposals)
+constexpr int kSegWords = 2048;    // bitmap words per statistics segment (65536 proposals)
+constexpr int kNBins = TKDV_NBINS;
+
+// Per-point constants, laid out for wave-uniform (scalar) loads.
+struct DevPoint {
+    float sig[TKDV_KMAX];    // proposal standard deviations s_k (1 for the uniform proposal)
+    double sig64[TKDV_KMAX]; // the same in FP64 (sqrt of the plan's s_k^2)
+    // FP32 fast path: log a = neg_bp_K2 * t + c3coef * S3 + Kf * log1p(g_coef * t) - log_M
+    float neg_bp_K2;         // -beta'/K^2
+    float c3coef;            // beta' c/(E0 K^2) * (pi/(3N)) * (2 E0/pi)^{3/2}
+    float g_coef;            // alpha* beta'/K^3   (Sigma proposal; 0 for uniform)
+    float Kf;                // K                  (Sigma proposal; 0 for uniform)
+    float log_M;             // log M rounded to FP32
+    float tau;               // decision window: |log U - log a| < tau -> FP64 re-decision
+    int32_t K;
+    int32_t proposal;
+    uint32_t point_id;
+    uint32_t key0, key1;     // Philox key = seed
+    uint32_t pad0;
+    // FP64 re-decision
+    double E0, beta_p, c32, alpha_star, log_M64;
+    double amp;              // sqrt(2 E0/pi)
+    // work description
+    uint64_t i0;             // first proposal index
+    uint64_t n;              // proposals to cover (upper bound in accepted-count mode)
+    uint64_t n_tiles;        // ceil(n / 32)
+    uint64_t target;         // accepted-sample target (UINT64_MAX in proposal-count mode)
+    uint64_t bm_off;         // first bitmap word of this point
+    uint64_t seg_off;        // first statistics segment of this point
+    uint64_t n_segs;         // statistics segments of this point
+    uint64_t out_off;        // first output row of this point
+    uint64_t capacity;       // output rows available to this point
+    uint64_t row_stride;     // floats between consecutive output rows
+};
+
+// Device-side counters per point (zeroed before every launch sequence).
+struct DevCounters {
+    unsigned long long next_tile;     // work-queue head (tiles)
+    unsigned long long accepted;      // decisions that were definite accepts
+    unsigned long long violations;    // proposals with log a > 0
+    unsigned long long deferred;      // proposals sent to the FP64 re-decision
+    unsigned long long fix_accepted;  // of those, accepted
+    unsigned long long last_index;    // accepted-count mode: index of the target-th sample
+    unsigned int max_log_a_key;       // order-preserving encoding of the largest log a
+    unsigned int pad;
+};
+
+// Per-segment partial statistics (FP64 sums in a fixed order).
+struct SegStats {
+    double S1, S2, S3, S4;
+    unsigned long long n_exceed;
+    unsigned long long n_samples;
+};
+
+// Per-point result of the finalisation kernel.
+struct PointResult {
+    double S1, S2, S3, S4;
+    unsigned long long n_exceed;
+    unsigned long long n_samples;      // accepted samples covered by the statistics
+    unsigned long long n_accepted;     // all accepted in the processed range
+    unsigned long long n_written;
+    unsigned long long n_processed;    // proposals whose decision exists
+    unsigned long long hist[kNBins];
+};
+
+struct KernelArgs {
+    const DevPoint *pts;
+    int n_points;
+    DevCounters *cnt;
+    uint32_t *bitmap;
+    unsigned long long *defer_list;
+    unsigned long long *defer_count;
+    unsigned long long defer_cap;
+    const void *phi_hi;    // BF16 fragment table (hi), or FP32 fragment table
+    const void *phi_lo;    // BF16 fragment table (lo)
+    // optional per-proposal outputs of the evaluation entry point (point 0 only)
+    float *dbg_xhat, *dbg_t, *dbg_s3, *dbg_log_a, *dbg_log_u;
+};
+
+}  // namespace tkdv

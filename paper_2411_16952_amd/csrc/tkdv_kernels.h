@@ -1,0 +1,25 @@
+// Host-side launchers of the gfx950 kernels (defined in tkdv_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "tkdv_internal.h"
+
+namespace tkdv {
+
+hipError_t launch_decide(int K, int prec, int prop, const KernelArgs &a, const int *plist, int n_plist,
+                         int n_cu, unsigned long long total_tiles, hipStream_t st, int *grid_out);
+hipError_t launch_fixup(const KernelArgs &a, int n_cu, hipStream_t st);
+hipError_t launch_segments(const KernelArgs &a, unsigned long long total_segs, unsigned long long *seg_cnt,
+                           unsigned long long *seg_base, PointResult *res, int n_cu, hipStream_t st);
+hipError_t launch_materialize(int K, int prop, const KernelArgs &a, const int *plist, int n_plist,
+                              unsigned long long total_segs, const unsigned long long *seg_cnt,
+                              const unsigned long long *seg_base, SegStats *seg_stats, PointResult *res,
+                              float *out_xhat, unsigned long long *out_index, int n_cu, hipStream_t st);
+hipError_t launch_finalize(const KernelArgs &a, const unsigned long long *seg_cnt,
+                           const unsigned long long *seg_base, const SegStats *seg_stats, PointResult *res,
+                           hipStream_t st);
+hipError_t launch_fill_u32(void *p, unsigned long long n_words, uint32_t v, hipStream_t st);
+hipError_t launch_bits_to_bytes(const uint32_t *bitmap, unsigned long long n, uint8_t *out, hipStream_t st);
+
+}  // namespace tkdv

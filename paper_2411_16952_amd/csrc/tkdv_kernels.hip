@@ -1,0 +1,670 @@
+// gfx950 kernels of the TKdV rejection sampler.
+//
+// Pipeline of one sampling call (all on one stream, no host round trip):
+//   k_decide       persistent: per wave, tiles of 32 proposals claimed from a
+//                  per-point queue; Philox -> Box-Muller -> scale -> project
+//                  -> t, matrix-core synthesis -> sum u^3 -> log a -> decision.
+//                  Writes one accept-bit word per tile; proposals within the
+//                  decision window go to the FP64 list.
+//   k_fixup        FP64 re-decision of the listed proposals (H3 by the double
+//                  sum of Sec. IV.A), OR-ed into the accept bitmap.
+//   k_seg_count    accepted count per 65536-proposal segment.
+//   k_seg_scan     exclusive scan of the segment counts, per point.
+//   k_materialize  LDS-staged stream compaction of the accepted bits in
+//                  proposal order; regenerates each accepted x^ (same
+//                  arithmetic as k_decide), writes it at its rank, and
+//                  accumulates FP64 moments, 2-sigma exceedances and the u(0)
+//                  histogram from an FP32 matrix-core synthesis.
+//   k_finalize     per point, segment partials summed in segment order.
+#include <hip/hip_runtime.h>
+
+#include "tkdv_device.h"
+#include "tkdv_kernels.h"
+
+namespace tkdv {
+
+// ---------------------------------------------------------------------------
+// Wave reductions (fixed butterfly order: deterministic)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ float wave_max_f32(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long load_relaxed(const unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int K, int PREC>
+__host__ __device__ constexpr int decide_lds_bytes()
+{
+    return PREC == PREC_FP32 ? f32_table_bytes<K>()
+                             : (PREC == PREC_BF16X3 ? 2 : 1) * bf16_table_bytes<K>();
+}
+
+// ---------------------------------------------------------------------------
+// k_decide
+// ---------------------------------------------------------------------------
+template <int K, int PREC, int PROP>
+__global__ void __launch_bounds__(kBlock) k_decide(KernelArgs a, const int *plist, int n_plist)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    constexpr int tab = PREC == PREC_FP32 ? f32_table_bytes<K>() : bf16_table_bytes<K>();
+    {
+        const uint4 *s0 = reinterpret_cast<const uint4 *>(a.phi_hi);
+        uint4 *d = reinterpret_cast<uint4 *>(lds);
+        for (int v = threadIdx.x; v < tab / 16; v += kBlock) d[v] = s0[v];
+        if constexpr (PREC == PREC_BF16X3) {
+            const uint4 *s1 = reinterpret_cast<const uint4 *>(a.phi_lo);
+            for (int v = threadIdx.x; v < tab / 16; v += kBlock) d[tab / 16 + v] = s1[v];
+        }
+    }
+    __syncthreads();
+    const char *lds_hi = lds;
+    const char *lds_lo = lds + tab;
+    const int lane = threadIdx.x & 63, half = lane >> 5, pl = lane & 31;
+    const int gwave = blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6);
+    int cursor = gwave % n_plist;
+    int misses = 0;
+    while (misses < n_plist) {
+        const int p = __builtin_amdgcn_readfirstlane(plist[cursor]);
+        const DevPoint &P = a.pts[p];
+        DevCounters *C = a.cnt + p;
+        unsigned long long base = ~0ull;
+        if (lane == 0) {
+            if (load_relaxed(&C->accepted) < P.target && load_relaxed(&C->next_tile) < P.n_tiles)
+                base = atomicAdd(&C->next_tile, (unsigned long long)kClaimTiles);
+        }
+        base = __shfl(base, 0, 64);
+        if (base >= P.n_tiles) {
+            cursor = (cursor + 1 == n_plist) ? 0 : cursor + 1;
+            ++misses;
+            continue;
+        }
+        misses = 0;
+        unsigned long long n_acc = 0, n_def = 0;
+        unsigned int n_viol = 0;
+        float max_la = -INFINITY;
+        for (int c = 0; c < kClaimTiles; ++c) {
+            const unsigned long long tile = base + c;
+            if (tile >= P.n_tiles) break;
+            const unsigned long long local = tile * kTile + pl;
+            const bool valid = local < P.n;
+            const uint64_t i = P.i0 + local;
+            float x[K];
+            float t;
+            uint32_t w_acc;
+            gen_xhat<K, PROP>(P, i, half, x, t, w_acc);
+            if (a.dbg_xhat && valid) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) a.dbg_xhat[local * (2 * K) + half * K + j] = x[j];
+            }
+            const float s3l = synth_cube_sum<K, PREC>(x, lds_hi, lds_lo, lane);
+            const float s3 = s3l + xor32(s3l);
+            const float la = log_a_f32<PROP>(P, t, s3);
+            const float lu = log_u_word(w_acc);
+            const float d = lu - la;
+            const bool mine = valid && half == 0;
+            const bool defer = mine && fabsf(d) < P.tau;
+            const bool accept = mine && !defer && d < 0.0f;
+            const unsigned long long bacc = __ballot(accept);
+            const unsigned long long bdef = __ballot(defer);
+            if (lane == 0) a.bitmap[P.bm_off + tile] = (uint32_t)bacc;
+            n_acc += __popcll(bacc);
+            if (mine) {
+                n_viol += la > 0.0f ? 1u : 0u;
+                max_la = fmaxf(max_la, la);
+                if (a.dbg_t) {
+                    a.dbg_t[local] = t;
+                    a.dbg_s3[local] = s3;
+                    a.dbg_log_a[local] = la;
+                    a.dbg_log_u[local] = lu;
+                }
+            }
+            if (bdef) {
+                const unsigned long long nd = __popcll(bdef);
+                unsigned long long slot = 0;
+                if (lane == 0) slot = atomicAdd(a.defer_count, nd);
+                slot = __shfl(slot, 0, 64);
+                if (defer) {
+                    const unsigned long long pos = slot + __popcll(bdef & ((1ull << lane) - 1ull));
+                    if (pos < a.defer_cap) a.defer_list[pos] = pack_defer(p, i);
+                }
+                n_def += nd;
+            }
+        }
+        const unsigned long long viol = wave_sum_u64(n_viol);
+        max_la = wave_max_f32(max_la);
+        if (lane == 0) {
+            atomicAdd(&C->accepted, n_acc);
+            if (viol) atomicAdd(&C->violations, viol);
+            if (n_def) atomicAdd(&C->deferred, n_def);
+            atomicMax(&C->max_log_a_key, float_key(max_la));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_fixup: FP64 evaluation of listed proposals, as the paper states it:
+// normals from the same words, X = Sigma^{1/2} z, X^ = X/|X|, H2 by Parseval,
+// H3 by the double sum, log f/(M g) = -beta H + K log(1 + alpha beta' t/K^3) - log M.
+// ---------------------------------------------------------------------------
+__device__ void fp64_eval(const DevPoint &P, uint64_t i, double &log_a, double &log_u)
+{
+    const int K = P.K;
+    double x[2 * TKDV_KMAX];
+    const uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32);
+    const double pi = 3.14159265358979323846;
+    for (int b = 0; b < K / 2; ++b) {
+        uint4 w = philox4x32_10(c0, c1, P.point_id, (uint32_t)b, P.key0, P.key1);
+        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+        for (int q = 0; q < 4; q += 2) {
+            const double u1 = ((double)ws[q] + 0.5) * 0x1p-32;
+            const double u2 = ((double)ws[q + 1] + 0.5) * 0x1p-32;
+            const double r = sqrt(-2.0 * log(u1));
+            const double th = 2.0 * pi * u2;
+            x[4 * b + q] = r * cos(th);
+            x[4 * b + q + 1] = r * sin(th);
+        }
+    }
+    const uint32_t wa = philox4x32_10(c0, c1, P.point_id, (uint32_t)(K / 2), P.key0, P.key1).x;
+    log_u = log(((double)wa + 0.5) * 0x1p-32);
+    double r2 = 0.0;
+    for (int m = 0; m < 2 * K; ++m) {
+        x[m] *= P.sig64[m % K];
+        r2 += x[m] * x[m];
+    }
+    const double r = sqrt(r2);
+    for (int m = 0; m < 2 * K; ++m) x[m] /= r;
+    double t = 0.0;
+    for (int k = 1; k <= K; ++k) t += (double)k * k * (x[k - 1] * x[k - 1] + x[K + k - 1] * x[K + k - 1]);
+    const double s = sqrt(P.E0 / (2.0 * pi));
+    double tri = 0.0;
+    for (int n = 2; n <= K; ++n) {
+        double in_re = 0.0, in_im = 0.0;
+        for (int k = 1; k < n; ++k) {
+            const double pr = s * x[k - 1], pi_ = -s * x[K + k - 1];
+            const double qr = s * x[n - k - 1], qi = -s * x[K + n - k - 1];
+            in_re += pr * qr - pi_ * qi;
+            in_im += pr * qi + pi_ * qr;
+        }
+        tri += (s * x[n - 1]) * in_re + (-s * x[K + n - 1]) * in_im;
+    }
+    const double H3 = 2.0 * pi * tri;
+    const double H2 = P.E0 * t;
+    double lr = -(P.beta_p / (P.E0 * (double)K * K) * (H2 - P.c32 * H3));
+    if (P.proposal == PROP_SIGMA) lr += K * log1p(P.alpha_star * P.beta_p * t / ((double)K * K * K));
+    log_a = lr - P.log_M64;
+}
+
+__global__ void __launch_bounds__(kBlock) k_fixup(KernelArgs a)
+{
+    const unsigned long long cnt = *a.defer_count;
+    const unsigned long long n = cnt < a.defer_cap ? cnt : a.defer_cap;
+    for (unsigned long long e = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (unsigned long long)gridDim.x * blockDim.x) {
+        const unsigned long long v = a.defer_list[e];
+        const int p = (int)(v >> 40);
+        const uint64_t i = v & ((1ull << 40) - 1ull);
+        const DevPoint &P = a.pts[p];
+        double la, lu;
+        fp64_eval(P, i, la, lu);
+        if (lu < la) {
+            const uint64_t local = i - P.i0;
+            atomicOr(&a.bitmap[P.bm_off + local / 32], 1u << (local % 32));
+            atomicAdd(&a.cnt[p].fix_accepted, 1ull);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Segments
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int point_of_segment(const DevPoint *pts, int n_points, unsigned long long gs)
+{
+    int lo = 0, hi = n_points - 1;
+    while (lo < hi) {  // last p with seg_off <= gs
+        const int mid = (lo + hi + 1) >> 1;
+        if (pts[mid].seg_off <= gs) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ unsigned long long processed_words(const DevPoint &P, const DevCounters &C)
+{
+    const unsigned long long nt = C.next_tile;
+    return nt < P.n_tiles ? nt : P.n_tiles;
+}
+
+__global__ void __launch_bounds__(kBlock) k_seg_count(KernelArgs a, unsigned long long total_segs,
+                                                      unsigned long long *seg_cnt)
+{
+    __shared__ unsigned long long red[kBlock / kWave];
+    for (unsigned long long gs = blockIdx.x; gs < total_segs; gs += gridDim.x) {
+        const int p = point_of_segment(a.pts, a.n_points, gs);
+        const DevPoint &P = a.pts[p];
+        const unsigned long long nw = processed_words(P, a.cnt[p]);
+        const unsigned long long w0 = (gs - P.seg_off) * kSegWords;
+        unsigned long long c = 0;
+        for (int k = threadIdx.x; k < kSegWords; k += kBlock) {
+            const unsigned long long w = w0 + k;
+            if (w < nw) c += __popc(a.bitmap[P.bm_off + w]);
+        }
+        c = wave_sum_u64(c);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long s = 0;
+            for (int w = 0; w < kBlock / kWave; ++w) s += red[w];
+            seg_cnt[gs] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// One block: per point, exclusive scan of its segment counts.
+__global__ void __launch_bounds__(1024) k_seg_scan(KernelArgs a, const unsigned long long *seg_cnt,
+                                                   unsigned long long *seg_base, PointResult *res)
+{
+    __shared__ unsigned long long buf[1024];
+    for (int p = 0; p < a.n_points; ++p) {
+        const DevPoint &P = a.pts[p];
+        unsigned long long run = 0;
+        for (unsigned long long s0 = 0; s0 < P.n_segs; s0 += 1024) {
+            const unsigned long long s = s0 + threadIdx.x;
+            const unsigned long long v = s < P.n_segs ? seg_cnt[P.seg_off + s] : 0ull;
+            buf[threadIdx.x] = v;
+            __syncthreads();
+            for (int o = 1; o < 1024; o <<= 1) {  // Hillis-Steele inclusive scan
+                const unsigned long long add = threadIdx.x >= (unsigned)o ? buf[threadIdx.x - o] : 0ull;
+                __syncthreads();
+                buf[threadIdx.x] += add;
+                __syncthreads();
+            }
+            if (s < P.n_segs) seg_base[P.seg_off + s] = run + buf[threadIdx.x] - v;
+            run += buf[1023];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            res[p].n_accepted = run;
+            res[p].n_processed = processed_words(P, a.cnt[p]) * kTile < P.n
+                                     ? processed_words(P, a.cnt[p]) * kTile
+                                     : P.n;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_materialize: one block per segment, one wave per quarter segment.
+// ---------------------------------------------------------------------------
+constexpr int kWaveWords = kSegWords / (kBlock / kWave);  // 512 words per wave
+constexpr int kGroupWords = kWave;                         // one word per lane per group
+
+template <int K>
+__host__ __device__ constexpr int materialize_lds_bytes()
+{
+    return f32_table_bytes<K>() + (kBlock / kWave) * kGroupWords * 32 * 2 + 1024;
+}
+
+template <int K, int PROP>
+__global__ void __launch_bounds__(kBlock) k_materialize(KernelArgs a, const int *plist, int n_plist,
+                                                        unsigned long long total_segs,
+                                                        const unsigned long long *seg_cnt,
+                                                        const unsigned long long *seg_base,
+                                                        SegStats *seg_stats, PointResult *res,
+                                                        float *out_xhat, unsigned long long *out_index)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    constexpr int tab = f32_table_bytes<K>();
+    uint16_t *lists = reinterpret_cast<uint16_t *>(lds + tab);
+    unsigned int *hist = reinterpret_cast<unsigned int *>(lds + tab + (kBlock / kWave) * kGroupWords * 32 * 2);
+    __shared__ unsigned long long wave_cnt[kBlock / kWave];
+    __shared__ double wave_S[kBlock / kWave][4];
+    __shared__ unsigned long long wave_ex[kBlock / kWave];
+    {
+        const uint4 *s0 = reinterpret_cast<const uint4 *>(a.phi_hi);
+        uint4 *d = reinterpret_cast<uint4 *>(lds);
+        for (int v = threadIdx.x; v < tab / 16; v += kBlock) d[v] = s0[v];
+    }
+    const int lane = threadIdx.x & 63, half = lane >> 5, pl = lane & 31, wv = threadIdx.x >> 6;
+    uint16_t *mylist = lists + wv * (kGroupWords * 32);
+    __syncthreads();
+    for (unsigned long long gs = blockIdx.x; gs < total_segs; gs += gridDim.x) {
+        const int p = point_of_segment(a.pts, a.n_points, gs);
+        const DevPoint &P = a.pts[p];
+        bool mine_k = P.K == K && P.proposal == PROP;
+        const unsigned long long limit = P.target;  // ranks >= target are not part of the result
+        if (!mine_k || seg_cnt[gs] == 0 || seg_base[gs] >= limit) continue;  // block-uniform
+        for (int b = threadIdx.x; b < kNBins; b += kBlock) hist[b] = 0u;
+        const unsigned long long nw = processed_words(P, a.cnt[p]);
+        const unsigned long long seg_w0 = (gs - P.seg_off) * kSegWords;
+        const unsigned long long w_first = seg_w0 + (unsigned long long)wv * kWaveWords;
+        // this wave's accepted count -> rank base
+        unsigned long long c = 0;
+        for (int k = lane; k < kWaveWords; k += kWave) {
+            const unsigned long long w = w_first + k;
+            if (w < nw) c += __popc(a.bitmap[P.bm_off + w]);
+        }
+        c = wave_sum_u64(c);
+        if (lane == 0) wave_cnt[wv] = c;
+        __syncthreads();
+        unsigned long long rank = seg_base[gs];
+        for (int w = 0; w < wv; ++w) rank += wave_cnt[w];
+        double S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0;
+        unsigned long long n_ex = 0;
+        for (int g = 0; g < kWaveWords / kGroupWords; ++g) {
+            const unsigned long long w = w_first + (unsigned long long)g * kGroupWords + lane;
+            const uint32_t word = w < nw ? a.bitmap[P.bm_off + w] : 0u;
+            const int cntw = __popc(word);
+            // inclusive prefix over lanes
+            int incl = cntw;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int up = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += up;
+            }
+            const int total = __shfl(incl, 63, 64);
+            if (total == 0) continue;
+            int pos = incl - cntw;
+            uint32_t m = word;
+            while (m) {
+                const int bit = __ffs(m) - 1;
+                m &= m - 1;
+                mylist[pos++] = (uint16_t)(lane * 32 + bit);
+            }
+            // the list is written and read by lanes of this wave only
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            for (int c0 = 0; c0 < total; c0 += kTile) {
+                const bool in_chunk = c0 + pl < total;
+                const int off = in_chunk ? (int)mylist[c0 + pl] : 0;
+                const unsigned long long local =
+                    (w_first + (unsigned long long)g * kGroupWords) * kTile + (unsigned long long)off;
+                const uint64_t i = P.i0 + local;
+                const unsigned long long r = rank + c0 + pl;
+                const bool valid = in_chunk && r < limit;
+                float x[K];
+                float t;
+                uint32_t w_acc;
+                gen_xhat<K, PROP>(P, i, half, x, t, w_acc);
+                if (valid && r < P.capacity) {
+                    if (out_xhat) {
+                        float *row = out_xhat + (P.out_off + r) * P.row_stride + half * K;
+#pragma unroll
+                        for (int j = 0; j < K; ++j) row[j] = x[j];
+                    }
+                    if (out_index && half == 0) out_index[P.out_off + r] = i;
+                }
+                if (valid && half == 0 && r + 1 == limit) a.cnt[p].last_index = i;
+                // statistics on the grid: u = sqrt(2 E0/pi) u~, u~ from FP32 products
+                const float4 *ftab = reinterpret_cast<const float4 *>(lds);
+#pragma unroll
+                for (int tt = 0; tt < K / 8; ++tt) {
+                    f32x16 acc = {};
+#pragma unroll
+                    for (int q = 0; q < K / 4; ++q) {
+                        const float4 av = ftab[(tt * (K / 4) + q) * kWave + lane];
+                        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, x[4 * q + 0], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, x[4 * q + 1], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, x[4 * q + 2], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, x[4 * q + 3], acc, 0, 0, 0);
+                    }
+                    if (valid) {
+#pragma unroll
+                        for (int v = 0; v < 16; ++v) {
+                            const double u = P.amp * (double)acc[v];
+                            const double u2 = u * u;
+                            S1 += u;
+                            S2 += u2;
+                            S3 += u2 * u;
+                            S4 += u2 * u2;
+                            n_ex += acc[v] > 1.41421356237309515f ? 1ull : 0ull;  // u > 2 sqrt(E0/pi)
+                        }
+                    }
+                }
+                if (valid && half == 0) {
+                    // u(0) = sqrt(2 E0/pi) sum_k x^_k; bin of u(0)/u_max = sum_k x^_k / sqrt(K)
+                    double s0 = 0.0;
+#pragma unroll
+                    for (int j = 0; j < K; ++j) s0 += (double)x[j];
+                    double posb = (s0 / sqrt((double)K) + 1.0) * (0.5 * kNBins);
+                    int bin = (int)floor(posb);
+                    bin = bin < 0 ? 0 : (bin > kNBins - 1 ? kNBins - 1 : bin);
+                    atomicAdd(&hist[bin], 1u);
+                }
+            }
+            rank += total;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        S1 = wave_sum_f64(S1);
+        S2 = wave_sum_f64(S2);
+        S3 = wave_sum_f64(S3);
+        S4 = wave_sum_f64(S4);
+        n_ex = wave_sum_u64(n_ex);
+        if (lane == 0) {
+            wave_S[wv][0] = S1;
+            wave_S[wv][1] = S2;
+            wave_S[wv][2] = S3;
+            wave_S[wv][3] = S4;
+            wave_ex[wv] = n_ex;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            SegStats st = {0.0, 0.0, 0.0, 0.0, 0ull, 0ull};
+            for (int w = 0; w < kBlock / kWave; ++w) {
+                st.S1 += wave_S[w][0];
+                st.S2 += wave_S[w][1];
+                st.S3 += wave_S[w][2];
+                st.S4 += wave_S[w][3];
+                st.n_exceed += wave_ex[w];
+            }
+            const unsigned long long sb = seg_base[gs];
+            const unsigned long long se = sb + seg_cnt[gs];
+            st.n_samples = (se < limit ? se : limit) - sb;
+            seg_stats[gs] = st;
+        }
+        for (int b = threadIdx.x; b < kNBins; b += kBlock)
+            if (hist[b]) atomicAdd(&res[p].hist[b], (unsigned long long)hist[b]);
+        __syncthreads();
+    }
+}
+
+// Per point: segment partials in segment order.
+__global__ void k_finalize(KernelArgs a, const unsigned long long *seg_cnt,
+                           const unsigned long long *seg_base, const SegStats *seg_stats,
+                           PointResult *res)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n_points) return;
+    const DevPoint &P = a.pts[p];
+    double S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0;
+    unsigned long long ex = 0, ns = 0;
+    for (unsigned long long s = 0; s < P.n_segs; ++s) {
+        const unsigned long long gs = P.seg_off + s;
+        if (seg_cnt[gs] == 0 || seg_base[gs] >= P.target) continue;
+        const SegStats &st = seg_stats[gs];
+        S1 += st.S1;
+        S2 += st.S2;
+        S3 += st.S3;
+        S4 += st.S4;
+        ex += st.n_exceed;
+        ns += st.n_samples;
+    }
+    res[p].S1 = S1;
+    res[p].S2 = S2;
+    res[p].S3 = S3;
+    res[p].S4 = S4;
+    res[p].n_exceed = ex;
+    res[p].n_samples = ns;
+    res[p].n_written = ns < P.capacity ? ns : P.capacity;
+}
+
+__global__ void k_fill_u32(uint32_t *p, unsigned long long n, uint32_t v)
+{
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (unsigned long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_bits_to_bytes(const uint32_t *bitmap, unsigned long long n, uint8_t *out)
+{
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (unsigned long long)gridDim.x * blockDim.x)
+        out[i] = (uint8_t)((bitmap[i / 32] >> (i % 32)) & 1u);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------
+template <int K, int PREC, int PROP>
+static hipError_t launch_decide_t(const KernelArgs &a, const int *plist, int n_plist, int n_cu,
+                                  unsigned long long total_tiles, hipStream_t st, int *grid_out)
+{
+    constexpr int lds = decide_lds_bytes<K, PREC>();
+    auto kern = k_decide<K, PREC, PROP>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    unsigned long long want = (total_tiles + (unsigned long long)(kBlock / kWave) * kClaimTiles - 1) /
+                              ((unsigned long long)(kBlock / kWave) * kClaimTiles);
+    unsigned long long grid = (unsigned long long)per_cu * n_cu;
+    if (want < grid) grid = want;
+    if (grid < 1) grid = 1;
+    if (grid_out) *grid_out = (int)grid;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kBlock), lds, st, a, plist, n_plist);
+    return hipGetLastError();
+}
+
+template <int K>
+static hipError_t launch_decide_k(int prec, int prop, const KernelArgs &a, const int *plist, int n_plist,
+                                  int n_cu, unsigned long long tiles, hipStream_t st, int *g)
+{
+#define TKDV_DISPATCH_P(PR, PP) \
+    if (prec == PR && prop == PP) return launch_decide_t<K, PR, PP>(a, plist, n_plist, n_cu, tiles, st, g);
+    TKDV_DISPATCH_P(PREC_FP32, PROP_UNIFORM)
+    TKDV_DISPATCH_P(PREC_FP32, PROP_SIGMA)
+    TKDV_DISPATCH_P(PREC_BF16, PROP_UNIFORM)
+    TKDV_DISPATCH_P(PREC_BF16, PROP_SIGMA)
+    TKDV_DISPATCH_P(PREC_BF16X3, PROP_UNIFORM)
+    TKDV_DISPATCH_P(PREC_BF16X3, PROP_SIGMA)
+#undef TKDV_DISPATCH_P
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_decide(int K, int prec, int prop, const KernelArgs &a, const int *plist, int n_plist,
+                         int n_cu, unsigned long long tiles, hipStream_t st, int *grid_out)
+{
+    switch (K) {
+    case 8: return launch_decide_k<8>(prec, prop, a, plist, n_plist, n_cu, tiles, st, grid_out);
+    case 16: return launch_decide_k<16>(prec, prop, a, plist, n_plist, n_cu, tiles, st, grid_out);
+    case 32: return launch_decide_k<32>(prec, prop, a, plist, n_plist, n_cu, tiles, st, grid_out);
+    case 64: return launch_decide_k<64>(prec, prop, a, plist, n_plist, n_cu, tiles, st, grid_out);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fixup(const KernelArgs &a, int n_cu, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fixup, dim3(4 * n_cu), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_segments(const KernelArgs &a, unsigned long long total_segs, unsigned long long *seg_cnt,
+                           unsigned long long *seg_base, PointResult *res, int n_cu, hipStream_t st)
+{
+    unsigned long long g = total_segs < (unsigned long long)(32 * n_cu) ? total_segs : 32ull * n_cu;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_seg_count, dim3((unsigned)g), dim3(kBlock), 0, st, a, total_segs, seg_cnt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(1024), 0, st, a, seg_cnt, seg_base, res);
+    return hipGetLastError();
+}
+
+template <int K, int PROP>
+static hipError_t launch_materialize_t(const KernelArgs &a, const int *plist, int n_plist,
+                                       unsigned long long total_segs, const unsigned long long *seg_cnt,
+                                       const unsigned long long *seg_base, SegStats *seg_stats,
+                                       PointResult *res, float *out_xhat, unsigned long long *out_index,
+                                       int n_cu, hipStream_t st)
+{
+    constexpr int lds = materialize_lds_bytes<K>();
+    auto kern = k_materialize<K, PROP>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    unsigned long long g = total_segs < (unsigned long long)(8 * n_cu) ? total_segs : 8ull * n_cu;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(kern, dim3((unsigned)g), dim3(kBlock), lds, st, a, plist, n_plist, total_segs,
+                       seg_cnt, seg_base, seg_stats, res, out_xhat, out_index);
+    return hipGetLastError();
+}
+
+hipError_t launch_materialize(int K, int prop, const KernelArgs &a, const int *plist, int n_plist,
+                              unsigned long long total_segs, const unsigned long long *seg_cnt,
+                              const unsigned long long *seg_base, SegStats *seg_stats, PointResult *res,
+                              float *out_xhat, unsigned long long *out_index, int n_cu, hipStream_t st)
+{
+#define TKDV_DISPATCH_M(KK, PP)                                                                          \
+    if (K == KK && prop == PP)                                                                           \
+        return launch_materialize_t<KK, PP>(a, plist, n_plist, total_segs, seg_cnt, seg_base, seg_stats, \
+                                            res, out_xhat, out_index, n_cu, st);
+    TKDV_DISPATCH_M(8, PROP_UNIFORM)
+    TKDV_DISPATCH_M(8, PROP_SIGMA)
+    TKDV_DISPATCH_M(16, PROP_UNIFORM)
+    TKDV_DISPATCH_M(16, PROP_SIGMA)
+    TKDV_DISPATCH_M(32, PROP_UNIFORM)
+    TKDV_DISPATCH_M(32, PROP_SIGMA)
+    TKDV_DISPATCH_M(64, PROP_UNIFORM)
+    TKDV_DISPATCH_M(64, PROP_SIGMA)
+#undef TKDV_DISPATCH_M
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_finalize(const KernelArgs &a, const unsigned long long *seg_cnt,
+                           const unsigned long long *seg_base, const SegStats *seg_stats, PointResult *res,
+                           hipStream_t st)
+{
+    const int nb = (a.n_points + 63) / 64;
+    hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(64), 0, st, a, seg_cnt, seg_base, seg_stats, res);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(void *p, unsigned long long n_words, uint32_t v, hipStream_t st)
+{
+    if (n_words == 0) return hipSuccess;
+    unsigned long long g = (n_words + kBlock - 1) / kBlock;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)g), dim3(kBlock), 0, st, (uint32_t *)p, n_words, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_bits_to_bytes(const uint32_t *bitmap, unsigned long long n, uint8_t *out, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    unsigned long long g = (n + kBlock - 1) / kBlock;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_bits_to_bytes, dim3((unsigned)g), dim3(kBlock), 0, st, bitmap, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace tkdv

@@ -1,0 +1,219 @@
+"""Python binding of the C ABI in ``include/tkdv.h`` (ctypes; argument marshalling only).
+
+Every step of the sampler runs in the HIP library ``libtkdv.so``; PyTorch is
+used here only to allocate device memory and to pass the current HIP stream.
+Importing this module fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtkdv.so")
+
+KMAX = 64
+NBINS = 64
+
+UNIFORM, SIGMA = 0, 1
+FP32, BF16, BF16X3 = 0, 1, 2
+COUNT_PROPOSALS, COUNT_ACCEPTED = 0, 1
+
+PRECISIONS = {"fp32": FP32, "bf16": BF16, "bf16x3": BF16X3}
+PROPOSALS = {"uniform": UNIFORM, "sigma": SIGMA}
+
+STATUS = {0: "ok", -1: "invalid argument", -2: "no alpha root", -3: "HIP error",
+          -4: "capacity exceeded", -5: "unsupported K", -6: "M violation"}
+
+
+class TkdvError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"tkdv status {status} ({STATUS.get(status, '?')}): {msg}")
+        self.status = status
+
+
+class Point(C.Structure):
+    _fields_ = [("K", C.c_int32), ("point_id", C.c_uint32), ("E0", C.c_double),
+                ("beta_p", C.c_double), ("c32", C.c_double), ("seed", C.c_uint64)]
+
+
+class Plan(C.Structure):
+    _fields_ = [("alpha_star", C.c_double), ("log_M", C.c_double), ("log_norm_g", C.c_double),
+                ("sigma2", C.c_double * KMAX), ("N", C.c_int32), ("proposal", C.c_int32),
+                ("M_source", C.c_int32), ("n_optimiser_evals", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_proposed", C.c_uint64), ("n_accepted", C.c_uint64), ("n_written", C.c_uint64),
+                ("n_fp64_fixups", C.c_uint64), ("n_M_violations", C.c_uint64),
+                ("n_exceed_2sigma", C.c_uint64), ("n_grid_values", C.c_uint64),
+                ("max_log_a", C.c_double), ("S1", C.c_double), ("S2", C.c_double),
+                ("S3", C.c_double), ("S4", C.c_double), ("skewness", C.c_double),
+                ("kurtosis", C.c_double), ("p_exceed_2sigma", C.c_double),
+                ("hist_lo", C.c_double), ("hist_hi", C.c_double),
+                ("hist_u0", C.c_uint64 * NBINS)]
+
+    def to_dict(self) -> dict:
+        d = {name: getattr(self, name) for name, _ in self._fields_ if name != "hist_u0"}
+        d["hist_u0"] = np.array(self.hist_u0[:], dtype=np.uint64)
+        d["acceptance"] = self.n_accepted / self.n_proposed if self.n_proposed else float("nan")
+        return d
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2411_16952_amd.build` "
+                          "(or __graft_entry__.build()) before using the GPU sampler")
+    return C.CDLL(LIB_PATH)
+
+
+lib = _load()
+
+EXPORTS = ["tkdv_create", "tkdv_destroy", "tkdv_plan_point", "tkdv_sample", "tkdv_sample_batch",
+           "tkdv_eval_proposals", "tkdv_decision_window", "tkdv_status_str", "tkdv_last_error"]
+
+_P = C.c_void_p
+lib.tkdv_create.argtypes = [C.c_int, C.POINTER(_P)]
+lib.tkdv_destroy.argtypes = [_P]
+lib.tkdv_plan_point.argtypes = [C.POINTER(Point), C.c_int, C.POINTER(Plan)]
+lib.tkdv_sample.argtypes = [_P, C.POINTER(Point), C.c_int, C.POINTER(Plan), C.c_uint64, C.c_int,
+                            C.c_uint64, C.c_int, _P, _P, C.c_uint64, C.POINTER(Stats), _P]
+lib.tkdv_sample_batch.argtypes = [_P, C.c_int32, C.POINTER(Point), C.c_int, C.POINTER(Plan),
+                                  C.POINTER(C.c_uint64), C.c_int, C.c_uint64, C.c_int, _P, _P,
+                                  C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(Stats), _P]
+lib.tkdv_eval_proposals.argtypes = [_P, C.POINTER(Point), C.c_int, C.POINTER(Plan), C.c_uint64,
+                                    C.c_uint64, C.c_int, _P, _P, _P, _P, _P, _P, _P]
+lib.tkdv_decision_window.argtypes = [C.POINTER(Point), C.c_int, C.c_int]
+lib.tkdv_decision_window.restype = C.c_double
+lib.tkdv_status_str.argtypes = [C.c_int]
+lib.tkdv_status_str.restype = C.c_char_p
+lib.tkdv_last_error.argtypes = [_P]
+lib.tkdv_last_error.restype = C.c_char_p
+for _f in EXPORTS:
+    if _f not in ("tkdv_decision_window", "tkdv_status_str", "tkdv_last_error"):
+        getattr(lib, _f).restype = C.c_int
+
+
+def _check(st: int, ctx=None):
+    if st != 0:
+        msg = lib.tkdv_last_error(ctx)
+        raise TkdvError(st, msg.decode() if msg else "")
+
+
+def make_point(K: int, E0: float, beta_p: float, c32: float, seed: int = 0, point_id: int = 0) -> Point:
+    return Point(int(K), int(point_id), float(E0), float(beta_p), float(c32), int(seed))
+
+
+def plan_point(point: Point, proposal: int = SIGMA) -> Plan:
+    pl = Plan()
+    _check(lib.tkdv_plan_point(C.byref(point), int(proposal), C.byref(pl)))
+    return pl
+
+
+def decision_window(point: Point, proposal: int, precision: int) -> float:
+    return lib.tkdv_decision_window(C.byref(point), int(proposal), int(precision))
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """A sampler context on one HIP device (workspaces and synthesis tables)."""
+
+    def __init__(self, device: int = 0):
+        self._h = C.c_void_p()
+        _check(lib.tkdv_create(int(device), C.byref(self._h)))
+        self.device = device
+
+    def close(self):
+        if self._h:
+            lib.tkdv_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sample(self, point: Point, n: int, proposal: int = SIGMA, plan: Plan | None = None,
+               mode: int = COUNT_PROPOSALS, max_proposals: int = 0, precision: int = BF16X3,
+               capacity: int = 0, xhat=None, index=None, stream=None) -> dict:
+        """Rejection-sample one point; returns stats (dict) plus the output tensors."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        if capacity and xhat is None:
+            xhat = torch.empty((capacity, 2 * point.K), dtype=torch.float32, device=dev)
+        if capacity and index is None:
+            index = torch.empty((capacity,), dtype=torch.int64, device=dev)
+        st = Stats()
+        _check(lib.tkdv_sample(self._h, C.byref(point), int(proposal),
+                               C.byref(plan) if plan is not None else None, int(n), int(mode),
+                               int(max_proposals), int(precision), _ptr(xhat), _ptr(index),
+                               int(capacity), C.byref(st), _stream(stream)), self._h)
+        d = st.to_dict()
+        nw = d["n_written"]
+        d["xhat"] = xhat[:nw] if xhat is not None else None
+        d["index"] = index[:nw] if index is not None else None
+        return d
+
+    def sample_batch(self, points: list, n: list, proposal: int = SIGMA, plans: list | None = None,
+                     mode: int = COUNT_PROPOSALS, max_proposals: int = 0, precision: int = BF16X3,
+                     capacity: list | None = None, stream=None) -> tuple[list, object, object]:
+        """Many points in one launch sequence; rows have stride 2*KMAX floats."""
+        import torch
+        npnt = len(points)
+        pts = (Point * npnt)(*points)
+        pls = (Plan * npnt)(*plans) if plans is not None else None
+        nn = (C.c_uint64 * npnt)(*[int(v) for v in n])
+        cap = [int(c) for c in (capacity or [0] * npnt)]
+        offs = np.concatenate([[0], np.cumsum(cap)[:-1]]).astype(np.uint64)
+        total = int(sum(cap))
+        dev = torch.device("cuda", self.device)
+        xhat = torch.empty((max(total, 1), 2 * KMAX), dtype=torch.float32, device=dev)
+        index = torch.empty((max(total, 1),), dtype=torch.int64, device=dev)
+        caps = (C.c_uint64 * npnt)(*cap)
+        offc = (C.c_uint64 * npnt)(*[int(v) for v in offs])
+        sts = (Stats * npnt)()
+        _check(lib.tkdv_sample_batch(self._h, npnt, pts, int(proposal), pls, nn, int(mode),
+                                     int(max_proposals), int(precision), _ptr(xhat), _ptr(index),
+                                     caps, offc, sts, _stream(stream)), self._h)
+        out = []
+        for p in range(npnt):
+            d = sts[p].to_dict()
+            o, nw = int(offs[p]), d["n_written"]
+            d["xhat"] = xhat[o:o + nw, : 2 * points[p].K]
+            d["index"] = index[o:o + nw]
+            out.append(d)
+        return out, xhat, index
+
+    def eval_proposals(self, point: Point, i0: int, n: int, proposal: int = SIGMA,
+                       plan: Plan | None = None, precision: int = BF16X3, stream=None) -> dict:
+        """Per-proposal fast-path values and final decisions for indices i0..i0+n-1."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        K = point.K
+        out = {
+            "xhat": torch.empty((n, 2 * K), dtype=torch.float32, device=dev),
+            "t": torch.empty((n,), dtype=torch.float32, device=dev),
+            "s3": torch.empty((n,), dtype=torch.float32, device=dev),
+            "log_a": torch.empty((n,), dtype=torch.float32, device=dev),
+            "log_u": torch.empty((n,), dtype=torch.float32, device=dev),
+            "accept": torch.empty((n,), dtype=torch.uint8, device=dev),
+        }
+        _check(lib.tkdv_eval_proposals(self._h, C.byref(point), int(proposal),
+                                       C.byref(plan) if plan is not None else None, int(i0), int(n),
+                                       int(precision), _ptr(out["xhat"]), _ptr(out["t"]), _ptr(out["s3"]),
+                                       _ptr(out["log_a"]), _ptr(out["log_u"]), _ptr(out["accept"]),
+                                       _stream(stream)), self._h)
+        return out

@@ -1,0 +1,48 @@
+"""Seeded parameter points of the benchmark and test configurations.
+
+Pure data: no arithmetic of the method.  Both the HIP path and the oracle are
+driven from these definitions.  The paper's workloads are parameter points
+with E0 = 1 (Sec. V); the paper gives no physical depth, so the nonlinearity
+levels are expressed through C3/C2 = P/beta' with the paper's equal-
+(beta' C3/C2) design (Sec. V.B, Tables 1-2).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+
+@dataclass(frozen=True)
+class PointSpec:
+    K: int
+    E0: float
+    beta_p: float
+    c32: float
+    seed: int
+    point_id: int
+
+
+# Plain method, CPU-sized: K = 8 (sphere S^15), beta' = 40, C3/C2 = 20 (strong
+# skewness, about 0.55), 1e6 proposals of each proposal, Philox seed 0.
+CPU_SIZED = dict(points=[PointSpec(8, 1.0, 40.0, 20.0, 0, 0)], n_proposals=10**6, N=32)
+
+# Plain GPU: K = 32, N = 128, eight beta' values, two nonlinearity levels
+# beta' C3/C2 = 6000 and 12000 (Table 2's acceptance ~1e-3 and ~1.4e-6), 1e9
+# proposals per point, seed = point id.
+PLAIN_GPU_BETAS = (20.0, 25.0, 30.0, 35.0, 40.0, 45.0, 50.0, 60.0)
+PLAIN_GPU_LEVELS = (6000.0, 12000.0)
+
+
+def plain_gpu_points() -> list[PointSpec]:
+    pts = []
+    for lvl in PLAIN_GPU_LEVELS:
+        for bp in PLAIN_GPU_BETAS:
+            pid = len(pts)
+            pts.append(PointSpec(32, 1.0, bp, lvl / bp, pid, pid))
+    return pts
+
+
+PLAIN_GPU = dict(n_proposals=10**9, N=128)
+
+# Precision: K = 64, N = 256, beta' = 40, C3/C2 in {0, 300}, batches of 2^20.
+PRECISION_POINTS = [PointSpec(64, 1.0, 40.0, 0.0, 7, 0), PointSpec(64, 1.0, 40.0, 300.0, 7, 1)]
+PRECISION_BATCH = 1 << 20
