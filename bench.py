@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Throughput of the MI355X TKdV rejection sampler (arXiv 2411.16952).
+
+Workload (one step): the plain-GPU configuration -- K = 32 complex modes
+(sphere S^63), grid N = 128, E0 = 1, the paper's Sigma proposal, eight beta'
+values {20, 25, 30, 35, 40, 45, 50, 60} at the two nonlinearity levels
+beta' C3/C2 = 6000 and 12000 (16 points, seed = point id), 1e9 proposals per
+point, all accepted samples stored in HBM and their statistics reduced.
+Per-point plans (alpha*, M) are step 1 of the paper's algorithm and are
+computed once before the timed region; their wall time is reported.
+
+Prints one JSON line: accepted samples/s (value), proposals/s, the roofline of
+the dominant kernel (k_decide, ALU-bound) from HIP events recorded inside the
+library on the kernel's own stream, and the CPU FP64 oracle's throughput on a
+bounded sample of the same workload (the first proposals of every point).
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X vector ALU peak: 256 compute units x 2.4 GHz x 128 lane-operations per
+# clock per CU -- the published FP32 vector rate of 157.3 TFLOP/s counted as
+# operations (an FMA is one operation).
+ALU_OPS_PER_S = 256 * 2.4e9 * 128
+
+
+def alu_ops_per_proposal(K: int, proposal: str = "sigma", precision: str = "bf16x3") -> float:
+    """Algorithmic ALU operations of one proposal (each add, multiply, FMA,
+    compare, conversion, bit operation or transcendental counts 1):
+      Philox4x32-10: K/2 + 1 blocks x 10 rounds x (2 products x 2 halves + 4 xor) = 80 (K/2 + 1)
+      word -> uniform (2K + 1 words, convert + scale)                          = 2 (2K + 1)
+      Box-Muller: K pairs x (ln, x-2, sqrt, sin, cos, 2 products)              = 7 K
+      Sigma scaling (2K products; uniform proposal: none)                      = 2 K
+      |x|^2 (2K FMA), 1/sqrt, projection (2K products), t = sum k^2 s_k (4K)   = 8 K + 1
+      synthesis operand split (BF16x3: round, subtract, round per coordinate;
+        BF16: round; FP32: none)                                               = 6 K / 2 K / 0
+      cube-and-sum over the N = 4K grid values (square, FMA)                   = 8 K
+      log U, log a, comparison                                                 = 12
+    The synthesis products themselves run on the matrix cores."""
+    split = {"bf16x3": 6 * K, "bf16": 2 * K, "fp32": 0}[precision]
+    scale = 2 * K if proposal == "sigma" else 0
+    return 80 * (K / 2 + 1) + 2 * (2 * K + 1) + 7 * K + scale + 8 * K + 1 + split + 8 * K + 12
+
+
+def mfma_flops_per_proposal(K: int, precision: str = "bf16x3") -> float:
+    """Synthesis u~ = Phi^T x^ on the N = 4K grid: 2 x 2K x N flops per product term."""
+    return {"bf16x3": 3, "bf16": 1, "fp32": 1}[precision] * 2 * (2 * K) * (4 * K)
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("tkdv_device.h", "tkdv_kernels.hip"):
+        with open(os.path.join(ROOT, "paper_2411_16952_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(K: int, precision: str, proposals_per_launch: int):
+    """HBM bytes per k_decide launch from the committed rocprofv3 counter summary
+    (bytes per proposal, FETCH_SIZE and WRITE_SIZE scaled by the plain-copy
+    calibration, times the proposals of this launch), or None when the summary
+    is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"k_decide_k{K}_{precision}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_digest") != kernel_source_digest():
+        return None
+    return d["bytes_per_proposal"] * proposals_per_launch
+
+
+def cpu_baseline(points, plans, n_sample: int) -> dict:
+    import oracle
+    cores = oracle.max_threads()
+    t0 = time.perf_counter()
+    n_acc = 0
+    for p, pl in zip(points, plans):
+        r = oracle.sample(p.K, p.E0, p.beta_p, p.c32, 1, pl.alpha_star, pl.log_M, p.seed, p.point_id,
+                          n_sample, 4 * p.K, cap=0, nthreads=cores)
+        n_acc += r["stats"].n_accepted
+    dt = time.perf_counter() - t0
+    n_prop = n_sample * len(points)
+    return {
+        "value": n_acc / dt, "unit": "accepted samples/s", "cores": cores, "kind": "oracle",
+        "proposals_per_s": n_prop / dt, "accepted": n_acc, "seconds": dt,
+        "sample": f"first {n_sample} proposal indices of each of the {len(points)} points "
+                  f"({n_prop} proposals, same Philox counters), FP64 oracle with OpenMP",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--proposals", type=float, default=1e9, help="proposals per point")
+    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16", "bf16x3"])
+    ap.add_argument("--cpu-sample", type=int, default=1 << 22, help="oracle proposals per point (0: skip)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        src = torch.empty(args.calibrate_copy // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": args.calibrate_copy, "copies": 3}))
+        return 0
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sampler's proposals "
+              "are independent, and multi-GPU sharding is a design note, not a measured path.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs an MI355X GPU", file=sys.stderr)
+        return 1
+    from paper_2411_16952_amd import tkdv as T
+    from paper_2411_16952_amd import workloads as W
+
+    specs = W.plain_gpu_points()
+    pts = [T.make_point(s.K, s.E0, s.beta_p, s.c32, seed=s.seed, point_id=s.point_id) for s in specs]
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=min(16, len(pts))) as ex:
+        plans = list(ex.map(lambda p: T.plan_point(p, T.SIGMA), pts))
+    plan_s = time.perf_counter() - t0
+    K = specs[0].K
+    n_per = int(args.proposals)
+    n = [n_per] * len(pts)
+    cap = [1 << 21] * len(pts)  # every accepted sample of the beta' C3/C2 = 6000 points fits
+    prec = T.PRECISIONS[args.precision]
+    ctx = T.Context(0)
+    print(f"bench: {len(pts)} points, K={K}, {n_per:.3g} proposals/point, {args.precision}, "
+          f"plans {plan_s:.2f}s", file=sys.stderr, flush=True)
+
+    def step():
+        out, _, _ = ctx.sample_batch(pts, n, plans=plans, precision=prec, capacity=cap)
+        return out, ctx.timing()
+
+    for w in range(args.warmup):
+        out, tm = step()
+        print(f"warmup {w}: {tm['total_ms']:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    acc, decide_ms, phases = 0, [], []
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        out, tm = step()
+        acc += sum(int(o["n_accepted"]) for o in out)
+        decide_ms.append(tm["decide_ms"] / max(tm["decide_launches"], 1))
+        phases.append(tm)
+        print(f"step {s}: {tm['total_ms']:.1f} ms, decide {tm['decide_ms']:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n_prop = n_per * len(pts) * args.steps
+    fix = sum(int(o["n_fp64_fixups"]) for o in out)
+    viol = sum(int(o["n_M_violations"]) for o in out)
+
+    avg_decide_s = sum(decide_ms) / len(decide_ms) / 1e3
+    per_launch_props = n_per * len(pts)
+    ops = alu_ops_per_proposal(K, "sigma", args.precision)
+    achieved = ops * per_launch_props / avg_decide_s
+    traffic = load_traffic(K, args.precision, per_launch_props)
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_OPS_PER_S / 1e12,
+            "unit": "T ALU ops/s", "frac": achieved / ALU_OPS_PER_S,
+            "traffic": traffic, "kernel": "k_decide",
+            "algorithmic_ops_per_proposal": ops,
+            "avg_launch_ms": avg_decide_s * 1e3,
+            "proposals_per_launch": per_launch_props,
+            "mfma_flops_per_proposal": mfma_flops_per_proposal(K, args.precision),
+            "mfma_frac": mfma_flops_per_proposal(K, args.precision) * per_launch_props / avg_decide_s
+                         / (2.5e15 if args.precision != "fp32" else 157.3e12)}
+
+    cpu = None
+    if args.cpu_sample > 0:
+        print("cpu baseline ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(specs, plans, args.cpu_sample)
+
+    line = {
+        "metric": "accepted samples/sec at K=32 (plain Sigma proposal); proposals/sec",
+        "value": acc / dt,
+        "unit": "accepted samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "plain GPU sweep: K=32, N=128, E0=1, Sigma proposal, beta' in "
+                        "{20,25,30,35,40,45,50,60} x beta'C3/C2 in {6000,12000}, 1e9 proposals/point",
+            "K": K, "N": 4 * K, "points": len(pts), "proposals_per_point": n_per,
+            "synthesis": args.precision, "fp64_redecision": True,
+        },
+        "proposals_per_s": n_prop / dt,
+        "acceptance": acc / n_prop,
+        "fp64_redecisions_last_step": fix,
+        "M_violations_last_step": viol,
+        "plan_seconds": plan_s,
+        "phase_ms_last_step": {k: round(v, 3) for k, v in phases[-1].items() if k.endswith("_ms")},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

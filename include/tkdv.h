@@ -116,6 +116,22 @@ typedef struct {
     uint64_t hist_u0[TKDV_NBINS]; /* 64 equal bins of u(0), clamped                          */
 } tkdv_stats;
 
+/* Device time of the phases of the last tkdv_sample / tkdv_sample_batch /
+ * tkdv_eval_proposals call on a context, from HIP events recorded on the
+ * call's stream around each phase. */
+typedef struct {
+    double decide_ms;       /* proposal evaluation and decisions (k_decide launches) */
+    double fixup_ms;        /* FP64 re-decision of the window proposals             */
+    double segments_ms;     /* accept counts and their scan                         */
+    double materialize_ms;  /* ordered output and statistics                        */
+    double finalize_ms;     /* per-point reduction                                  */
+    double total_ms;        /* first to last event                                  */
+    int32_t decide_launches;
+    int32_t decide_grid;    /* workgroups of the (last) k_decide launch             */
+    int32_t decide_block;   /* threads per workgroup                                */
+    int32_t pad;
+} tkdv_timing;
+
 typedef struct tkdv_ctx tkdv_ctx;
 
 /* Create a context on HIP device `hip_device`: device workspaces, the cos/sin
@@ -179,6 +195,9 @@ tkdv_status tkdv_eval_proposals(tkdv_ctx *ctx, const tkdv_point *pt, tkdv_propos
  * it are re-decided in FP64.  It is an upper bound on the fast path's error
  * in log a (see the library's design notes) times a safety factor of 2. */
 double tkdv_decision_window(const tkdv_point *pt, tkdv_proposal proposal, tkdv_precision precision);
+
+/* Phase timings of the last call on this context (see tkdv_timing). */
+tkdv_status tkdv_get_timing(const tkdv_ctx *ctx, tkdv_timing *out);
 
 const char *tkdv_status_str(tkdv_status s);
 /* Text of the last error on this context (or of the last context-less call). */

@@ -73,6 +73,8 @@ struct tkdv_ctx {
     size_t h_points_bytes = 0;
     void *h_misc = nullptr;  // pinned: defer count + plist staging
     size_t h_misc_bytes = 0;
+    hipEvent_t ev[6] = {};  // phase boundaries of the last call
+    tkdv_timing timing = {};
 };
 
 namespace {
@@ -303,6 +305,9 @@ tkdv_status run(tkdv_ctx *ctx, Call &call, int precision, int proposal, float *d
     a.dbg_log_a = dbg_la;
     a.dbg_log_u = dbg_lu;
     const int *d_plist = reinterpret_cast<const int *>(ctx->plist.p);
+    std::memset(&ctx->timing, 0, sizeof(ctx->timing));
+    ctx->timing.decide_block = kBlock;
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[0], st));
     for (int ki = 0; ki < 4; ++ki) {
         if (call.plist_n[ki] == 0) continue;
         const int K = 8 << ki;
@@ -311,15 +316,19 @@ tkdv_status run(tkdv_ctx *ctx, Call &call, int precision, int proposal, float *d
         unsigned long long tiles = 0;
         for (int q = 0; q < call.plist_n[ki]; ++q) tiles += call.pts[call.plist[call.plist_off[ki] + q]].n_tiles;
         HIP_TRY(ctx, launch_decide(K, precision, proposal, a, d_plist + call.plist_off[ki], call.plist_n[ki],
-                                   ctx->n_cu, tiles, st, nullptr));
+                                   ctx->n_cu, tiles, st, &ctx->timing.decide_grid));
+        ctx->timing.decide_launches++;
     }
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[1], st));
     HIP_TRY(ctx, launch_fixup(a, ctx->n_cu, st));
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[2], st));
     if (stats) {
         unsigned long long *seg_cnt = reinterpret_cast<unsigned long long *>(ctx->seg_cnt.p);
         unsigned long long *seg_base = reinterpret_cast<unsigned long long *>(ctx->seg_base.p);
         SegStats *seg_stats = reinterpret_cast<SegStats *>(ctx->seg_stats.p);
         PointResult *res = reinterpret_cast<PointResult *>(ctx->results.p);
         HIP_TRY(ctx, launch_segments(a, call.total_segs, seg_cnt, seg_base, res, ctx->n_cu, st));
+        HIP_TRY(ctx, hipEventRecord(ctx->ev[3], st));
         for (int ki = 0; ki < 4; ++ki) {
             if (call.plist_n[ki] == 0) continue;
             a.phi_hi = ctx->phi_f32[ki].p;
@@ -327,12 +336,33 @@ tkdv_status run(tkdv_ctx *ctx, Call &call, int precision, int proposal, float *d
                                             call.total_segs, seg_cnt, seg_base, seg_stats, res, d_xhat, d_index,
                                             ctx->n_cu, st));
         }
+        HIP_TRY(ctx, hipEventRecord(ctx->ev[4], st));
         HIP_TRY(ctx, launch_finalize(a, seg_cnt, seg_base, seg_stats, res, st));
+        HIP_TRY(ctx, hipEventRecord(ctx->ev[5], st));
         HIP_TRY(ctx, hipMemcpyAsync(ctx->h_results, ctx->results.p, sizeof(PointResult) * np, hipMemcpyDeviceToHost, st));
     }
     HIP_TRY(ctx, hipMemcpyAsync(ctx->h_counters, ctx->counters.p, sizeof(DevCounters) * np, hipMemcpyDeviceToHost, st));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->h_misc, ctx->defer_count.p, 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(ctx, hipStreamSynchronize(st));
+    {
+        float ms = 0.0f;
+        HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+        ctx->timing.decide_ms = ms;
+        HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
+        ctx->timing.fixup_ms = ms;
+        if (stats) {
+            HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]));
+            ctx->timing.segments_ms = ms;
+            HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev[3], ctx->ev[4]));
+            ctx->timing.materialize_ms = ms;
+            HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev[4], ctx->ev[5]));
+            ctx->timing.finalize_ms = ms;
+            HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[5]));
+        } else {
+            HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[2]));
+        }
+        ctx->timing.total_ms = ms;
+    }
     const unsigned long long n_def = *reinterpret_cast<unsigned long long *>(ctx->h_misc);
     if (n_deferred_out) *n_deferred_out = n_def;
     if (res_out) {
@@ -470,6 +500,13 @@ tkdv_status tkdv_create(int hip_device, tkdv_ctx **out)
     tkdv_ctx *ctx = new tkdv_ctx();
     ctx->device = hip_device;
     ctx->n_cu = prop.multiProcessorCount;
+    for (hipEvent_t &ev : ctx->ev) {
+        e = hipEventCreate(&ev);
+        if (e != hipSuccess) {
+            tkdv_destroy(ctx);
+            return set_err(nullptr, TKDV_E_DEVICE, hipGetErrorString(e));
+        }
+    }
     *out = ctx;
     return TKDV_OK;
 }
@@ -491,6 +528,8 @@ tkdv_status tkdv_destroy(tkdv_ctx *ctx)
     if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
     if (ctx->h_points) (void)hipHostFree(ctx->h_points);
     if (ctx->h_misc) (void)hipHostFree(ctx->h_misc);
+    for (hipEvent_t ev : ctx->ev)
+        if (ev) (void)hipEventDestroy(ev);
     delete ctx;
     return TKDV_OK;
 }
@@ -589,6 +628,13 @@ double tkdv_decision_window(const tkdv_point *pt, tkdv_proposal proposal, tkdv_p
     tkdv_plan pl;
     if (plan_point_host(pt, proposal, 2, &pl) != TKDV_OK) return NAN;
     return window(*pt, proposal, precision, pl.alpha_star, pl.log_M);
+}
+
+tkdv_status tkdv_get_timing(const tkdv_ctx *ctx, tkdv_timing *out)
+{
+    if (!ctx || !out) return set_err(nullptr, TKDV_E_ARG, "NULL argument");
+    *out = ctx->timing;
+    return TKDV_OK;
 }
 
 const char *tkdv_status_str(tkdv_status s)

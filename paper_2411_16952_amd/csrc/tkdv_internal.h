@@ -11,7 +11,8 @@ namespace tkdv {
 constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kTile = 32;          // proposals per wave tile (two lanes per proposal)
 constexpr int kBlock = 256;        // threads per workgroup of the sampling kernels
-constexpr int kClaimTiles = 8;     // tiles claimed per work-queue claim (256 proposals)
+constexpr int kClaimTiles = 64;    // tiles claimed per work-queue claim (2048 proposals);
+                                   // lane c keeps the accept word of tile c
 constexpr int kSegWords = 2048;    // bitmap words per statistics segment (65536 proposals)
 constexpr int kNBins = TKDV_NBINS;
 

@@ -50,6 +50,8 @@ __device__ __forceinline__ unsigned long long load_relaxed(const unsigned long l
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+static_assert(kClaimTiles == kWave, "one accept word per lane per claim");
+
 template <int K, int PREC>
 __host__ __device__ constexpr int decide_lds_bytes()
 {
@@ -87,7 +89,8 @@ __global__ void __launch_bounds__(kBlock) k_decide(KernelArgs a, const int *plis
         DevCounters *C = a.cnt + p;
         unsigned long long base = ~0ull;
         if (lane == 0) {
-            if (load_relaxed(&C->accepted) < P.target && load_relaxed(&C->next_tile) < P.n_tiles)
+            // the accepted-count test only matters in accepted-count mode
+            if (P.target == ~0ull || load_relaxed(&C->accepted) < P.target)
                 base = atomicAdd(&C->next_tile, (unsigned long long)kClaimTiles);
         }
         base = __shfl(base, 0, 64);
@@ -100,6 +103,7 @@ __global__ void __launch_bounds__(kBlock) k_decide(KernelArgs a, const int *plis
         unsigned long long n_acc = 0, n_def = 0;
         unsigned int n_viol = 0;
         float max_la = -INFINITY;
+        uint32_t my_word = 0u;  // accept bits of tile `lane` of this claim
         for (int c = 0; c < kClaimTiles; ++c) {
             const unsigned long long tile = base + c;
             if (tile >= P.n_tiles) break;
@@ -124,7 +128,7 @@ __global__ void __launch_bounds__(kBlock) k_decide(KernelArgs a, const int *plis
             const bool accept = mine && !defer && d < 0.0f;
             const unsigned long long bacc = __ballot(accept);
             const unsigned long long bdef = __ballot(defer);
-            if (lane == 0) a.bitmap[P.bm_off + tile] = (uint32_t)bacc;
+            if (lane == c) my_word = (uint32_t)bacc;
             n_acc += __popcll(bacc);
             if (mine) {
                 n_viol += la > 0.0f ? 1u : 0u;
@@ -148,13 +152,15 @@ __global__ void __launch_bounds__(kBlock) k_decide(KernelArgs a, const int *plis
                 n_def += nd;
             }
         }
+        // one coalesced store of the claim's accept words
+        if (base + lane < P.n_tiles) a.bitmap[P.bm_off + base + lane] = my_word;
         const unsigned long long viol = wave_sum_u64(n_viol);
         max_la = wave_max_f32(max_la);
         if (lane == 0) {
-            atomicAdd(&C->accepted, n_acc);
+            if (n_acc) atomicAdd(&C->accepted, n_acc);
             if (viol) atomicAdd(&C->violations, viol);
             if (n_def) atomicAdd(&C->deferred, n_def);
-            atomicMax(&C->max_log_a_key, float_key(max_la));
+            if (max_la > -INFINITY) atomicMax(&C->max_log_a_key, float_key(max_la));
         }
     }
 }

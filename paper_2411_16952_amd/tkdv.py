@@ -46,6 +46,16 @@ class Plan(C.Structure):
                 ("M_source", C.c_int32), ("n_optimiser_evals", C.c_int32)]
 
 
+class Timing(C.Structure):
+    _fields_ = [("decide_ms", C.c_double), ("fixup_ms", C.c_double), ("segments_ms", C.c_double),
+                ("materialize_ms", C.c_double), ("finalize_ms", C.c_double), ("total_ms", C.c_double),
+                ("decide_launches", C.c_int32), ("decide_grid", C.c_int32), ("decide_block", C.c_int32),
+                ("pad", C.c_int32)]
+
+    def to_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad"}
+
+
 class Stats(C.Structure):
     _fields_ = [("n_proposed", C.c_uint64), ("n_accepted", C.c_uint64), ("n_written", C.c_uint64),
                 ("n_fp64_fixups", C.c_uint64), ("n_M_violations", C.c_uint64),
@@ -73,7 +83,8 @@ def _load() -> C.CDLL:
 lib = _load()
 
 EXPORTS = ["tkdv_create", "tkdv_destroy", "tkdv_plan_point", "tkdv_sample", "tkdv_sample_batch",
-           "tkdv_eval_proposals", "tkdv_decision_window", "tkdv_status_str", "tkdv_last_error"]
+           "tkdv_eval_proposals", "tkdv_decision_window", "tkdv_get_timing", "tkdv_status_str",
+           "tkdv_last_error"]
 
 _P = C.c_void_p
 lib.tkdv_create.argtypes = [C.c_int, C.POINTER(_P)]
@@ -86,6 +97,7 @@ lib.tkdv_sample_batch.argtypes = [_P, C.c_int32, C.POINTER(Point), C.c_int, C.PO
                                   C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(Stats), _P]
 lib.tkdv_eval_proposals.argtypes = [_P, C.POINTER(Point), C.c_int, C.POINTER(Plan), C.c_uint64,
                                     C.c_uint64, C.c_int, _P, _P, _P, _P, _P, _P, _P]
+lib.tkdv_get_timing.argtypes = [_P, C.POINTER(Timing)]
 lib.tkdv_decision_window.argtypes = [C.POINTER(Point), C.c_int, C.c_int]
 lib.tkdv_decision_window.restype = C.c_double
 lib.tkdv_status_str.argtypes = [C.c_int]
@@ -145,6 +157,12 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def timing(self) -> dict:
+        """Device time of the phases of the last call (HIP events on its stream)."""
+        t = Timing()
+        _check(lib.tkdv_get_timing(self._h, C.byref(t)), self._h)
+        return t.to_dict()
 
     def sample(self, point: Point, n: int, proposal: int = SIGMA, plan: Plan | None = None,
                mode: int = COUNT_PROPOSALS, max_proposals: int = 0, precision: int = BF16X3,
