@@ -230,7 +230,11 @@ void fill_devpoint(DevPoint &d, const tkdv_point &pt, const tkdv_plan &pl, int p
     d.g_coef = proposal == TKDV_PROP_SIGMA ? (float)(pl.alpha_star * pt.beta_p / ((double)K * K * K)) : 0.0f;
     d.Kf = proposal == TKDV_PROP_SIGMA ? (float)K : 0.0f;
     d.log_M = (float)pl.log_M;
-    d.tau = (float)window(pt, proposal, precision, pl.alpha_star, pl.log_M);
+    const double tau = window(pt, proposal, precision, pl.alpha_star, pl.log_M);
+    d.tau = (float)tau;
+    // rounded inwards so that the FP32 products stay inside the exact window
+    d.e_lo = (float)std::exp(-tau) * (1.0f - 0x1p-22f);
+    d.e_hi = (float)std::exp(tau) * (1.0f + 0x1p-22f);
     d.K = K;
     d.proposal = proposal;
     d.point_id = pt.point_id;

@@ -31,11 +31,13 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t ma = 0xD2511F53u, mb = 0xCD9E8D57u;
-        uint32_t hi_a = __umulhi(ma, c0), lo_a = ma * c0;
-        uint32_t hi_b = __umulhi(mb, c2), lo_b = mb * c2;
-        uint32_t n0 = hi_b ^ c1 ^ k0;
-        uint32_t n2 = hi_a ^ c3 ^ k1;
+        // one 32x32->64 multiply instruction per product
+        const uint64_t pa = (uint64_t)c0 * 0xD2511F53u;
+        const uint64_t pb = (uint64_t)c2 * 0xCD9E8D57u;
+        const uint32_t hi_a = (uint32_t)(pa >> 32), lo_a = (uint32_t)pa;
+        const uint32_t hi_b = (uint32_t)(pb >> 32), lo_b = (uint32_t)pb;
+        uint32_t n0 = __builtin_amdgcn_bitop3_b32(hi_b, c1, k0, 0x96);  // three-way xor
+        uint32_t n2 = __builtin_amdgcn_bitop3_b32(hi_a, c3, k1, 0x96);
         c0 = n0; c1 = lo_b; c2 = n2; c3 = lo_a;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
@@ -48,66 +50,69 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float log2_hw(float x) { return __builtin_amdgcn_logf(x); }
 
-// ln(1 - d) for d in (0, 1/2], accurate to a few ulps.
-__device__ __forceinline__ float log1m_f32(float d)
-{
-    // small d: -d (1 + d/2 + d^2/3 + d^3/4 + d^4/5 + d^5/6); truncation < d^7/7
-    float ser = __builtin_fmaf(d, 1.0f / 6.0f, 0.2f);
-    ser = __builtin_fmaf(d, ser, 0.25f);
-    ser = __builtin_fmaf(d, ser, 1.0f / 3.0f);
-    ser = __builtin_fmaf(d, ser, 0.5f);
-    ser = __builtin_fmaf(d, ser, 1.0f);
-    ser = -d * ser;
-    // larger d: log(y) * (-d)/(y - 1) with y = 1 - d rounded; y - 1 is exact.
-    float y = 1.0f - d;
-    float lg = log2_hw(y) * 0.69314718055994531f * (-d / (y - 1.0f));
-    return d < 0.0078125f ? ser : lg;
-}
-
-// ln U of a word.  U < 1/2: log2 of U itself (relative accuracy of the
-// hardware log2); U >= 1/2: ln(1 - d) with d = 1 - U formed from ~w, so the
-// result keeps its relative accuracy as U -> 1.
-__device__ __forceinline__ float log_u_word(uint32_t w)
+// -2 ln U of a word, U = (w + 1/2) 2^-32, with one hardware log2:
+//   U < 1/2:  log2(U) (relative accuracy of the hardware log2, |ln U| > ln 2);
+//   U >= 1/2: d = 1 - U is formed exactly from ~w; for d < 1/16 the series
+//             -ln(1 - d) = d (1 + d/2 + ... + d^5/6) (truncation below 1e-8
+//             relative), otherwise log2(1 - d) with 1 - d rounded (absolute
+//             error below 2^-25, |ln(1 - d)| > 0.06).
+__device__ __forceinline__ float neg2_log_u_word(uint32_t w)
 {
     const float two_m32 = 2.3283064365386963e-10f;
-    float u = __builtin_fmaf((float)w, two_m32, 0.5f * two_m32);
-    float lo = log2_hw(u) * 0.69314718055994531f;
-    float d = __builtin_fmaf((float)(~w), two_m32, 0.5f * two_m32);  // 1 - U
-    float hi = log1m_f32(d);
-    return (w & 0x80000000u) ? hi : lo;
+    const bool upper = (w & 0x80000000u) != 0u;
+    // q = U for U < 1/2 and q = d = 1 - U for U >= 1/2 (~w = 2^32 - 1 - w), one conversion
+    const uint32_t v = w ^ (uint32_t)((int32_t)w >> 31);
+    const float q = __builtin_fmaf((float)v, two_m32, 0.5f * two_m32);
+    const float d = q, u = q;
+    float p = __builtin_fmaf(d, 1.0f / 6.0f, 0.2f);
+    p = __builtin_fmaf(d, p, 0.25f);
+    p = __builtin_fmaf(d, p, 0.33333333333333333f);
+    p = __builtin_fmaf(d, p, 0.5f);
+    p = __builtin_fmaf(d, p, 1.0f);
+    const float ser = (2.0f * d) * p;
+    const float lg = log2_hw(upper ? 1.0f - d : u) * -1.3862943611198906f;  // -2 ln 2
+    return (upper && d < 0.0625f) ? ser : lg;
 }
+
+// ln U of a word (the same arithmetic, scaled by -1/2).
+__device__ __forceinline__ float log_u_word(uint32_t w) { return -0.5f * neg2_log_u_word(w); }
 
 // One Box-Muller pair: r = sqrt(-2 ln U1), (r cos 2 pi U2, r sin 2 pi U2).
 __device__ __forceinline__ void box_muller_f32(uint32_t w1, uint32_t w2, float &z0, float &z1)
 {
-    float r = __builtin_sqrtf(-2.0f * log_u_word(w1));
+    const float r = __builtin_amdgcn_sqrtf(neg2_log_u_word(w1));  // argument in [6e-10, 45]
     // U2 - 1/2 = (w2 - 2^31 + 1/2) 2^-32 in revolutions, centred on zero for
     // the hardware sin/cos; the signed integer w2 - 2^31 is formed exactly.
-    float rev = ((float)(int32_t)(w2 ^ 0x80000000u) + 0.5f) * 2.3283064365386963e-10f;
+    const float rev = __builtin_fmaf((float)(int32_t)(w2 ^ 0x80000000u), 2.3283064365386963e-10f,
+                                     1.1641532182693481e-10f);
     // sin/cos(2 pi (U2 - 1/2)) = -sin/-cos(2 pi U2)
     z0 = -r * __builtin_amdgcn_cosf(rev);
     z1 = -r * __builtin_amdgcn_sinf(rev);
 }
 
-// ln(1 + y) for y >= 0 (log1p by the exact-denominator correction).
+// ln(1 + y) for 0 <= y: the rounding of 1 + y is corrected to first order
+// with the exact difference (1 + y) - 1 (an approximate reciprocal suffices).
 __device__ __forceinline__ float log1p_f32(float y)
 {
-    float u = 1.0f + y;
-    float den = u - 1.0f;
-    float lg = log2_hw(u) * 0.69314718055994531f;
-    return den == 0.0f ? y : lg * (y / den);
+    const float u = 1.0f + y;
+    const float den = u - 1.0f;
+    const float lg = log2_hw(u) * 0.69314718055994531f;
+    return den == 0.0f ? y : lg * (y * __builtin_amdgcn_rcpf(den));
 }
 
 __device__ __forceinline__ float xor32(float v) { return __shfl_xor(v, 32, 64); }
 
 // ---------------------------------------------------------------------------
-// Proposal generation: the K coordinates of this lane's block, projected onto
-// the sphere.  Also returns t = sum_k k^2 s_k and the acceptance word.
-// Every lane of a proposal pair computes bitwise identical |x|^2 and t.
+// Proposal generation: the K coordinates x of this lane's block (scaled by the
+// proposal's standard deviations), |x|^-1, t = sum_k k^2 s_k of the projected
+// point, and the acceptance word.  With NORMALIZE the coordinates are
+// projected onto the sphere (x^ = x |x|^-1); otherwise the caller scales
+// whatever it derives from x.  Both lanes of a proposal compute bitwise
+// identical |x|^2 and t.
 // ---------------------------------------------------------------------------
-template <int K, int PROP>
-__device__ __forceinline__ void gen_xhat(const DevPoint &P, uint64_t i, int half, float (&x)[K],
-                                         float &t, uint32_t &w_acc)
+template <int K, int PROP, bool NORMALIZE>
+__device__ __forceinline__ float gen_xhat(const DevPoint &P, uint64_t i, int half, float (&x)[K],
+                                          float &t, uint32_t &w_acc)
 {
     const uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32), c2 = P.point_id;
 #pragma unroll
@@ -121,18 +126,22 @@ __device__ __forceinline__ void gen_xhat(const DevPoint &P, uint64_t i, int half
 #pragma unroll
         for (int j = 0; j < K; ++j) x[j] *= P.sig[j];
     }
-    float r2 = 0.0f;
-#pragma unroll
-    for (int j = 0; j < K; ++j) r2 = __builtin_fmaf(x[j], x[j], r2);
-    r2 = r2 + xor32(r2);
-    const float inv = __builtin_amdgcn_rsqf(r2);
-    float tl = 0.0f;
+    float r2 = 0.0f, tk = 0.0f;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        x[j] *= inv;
-        tl = __builtin_fmaf((float)((j + 1) * (j + 1)) * x[j], x[j], tl);
+        const float sq = x[j] * x[j];
+        r2 += sq;
+        tk = __builtin_fmaf((float)((j + 1) * (j + 1)), sq, tk);
     }
-    t = tl + xor32(tl);
+    r2 = r2 + xor32(r2);
+    tk = tk + xor32(tk);
+    const float inv = __builtin_amdgcn_rsqf(r2);
+    t = tk * (inv * inv);
+    if (NORMALIZE) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) x[j] *= inv;
+    }
+    return inv;
 }
 
 // ---------------------------------------------------------------------------

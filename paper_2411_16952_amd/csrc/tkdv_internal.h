@@ -27,6 +27,7 @@ struct DevPoint {
     float Kf;                // K                  (Sigma proposal; 0 for uniform)
     float log_M;             // log M rounded to FP32
     float tau;               // decision window: |log U - log a| < tau -> FP64 re-decision
+    float e_lo, e_hi;        // exp(-tau), exp(tau): the window in terms of U and a
     int32_t K;
     int32_t proposal;
     uint32_t point_id;

@@ -113,19 +113,23 @@ __global__ void __launch_bounds__(kBlock) k_decide(KernelArgs a, const int *plis
             float x[K];
             float t;
             uint32_t w_acc;
-            gen_xhat<K, PROP>(P, i, half, x, t, w_acc);
+            // x is not projected: the cube sum of u~' = Phi^T x is scaled by |x|^-3
+            const float inv = gen_xhat<K, PROP, false>(P, i, half, x, t, w_acc);
             if (a.dbg_xhat && valid) {
 #pragma unroll
-                for (int j = 0; j < K; ++j) a.dbg_xhat[local * (2 * K) + half * K + j] = x[j];
+                for (int j = 0; j < K; ++j) a.dbg_xhat[local * (2 * K) + half * K + j] = x[j] * inv;
             }
             const float s3l = synth_cube_sum<K, PREC>(x, lds_hi, lds_lo, lane);
-            const float s3 = s3l + xor32(s3l);
+            const float s3 = (s3l + xor32(s3l)) * (inv * inv * inv);
             const float la = log_a_f32<PROP>(P, t, s3);
-            const float lu = log_u_word(w_acc);
-            const float d = lu - la;
+            // ln U < ln a - tau  <=>  U < a e^-tau (accept); within the window: FP64.
+            // U = (w + 1/2) 2^-32; a = 2^(la log2 e) underflows to 0 only where U > a e^tau.
+            const float U = __builtin_fmaf((float)w_acc, 2.3283064365386963e-10f, 1.1641532182693481e-10f);
+            const float alin = __builtin_amdgcn_exp2f(la * 1.4426950408889634f);
+            const float lo_edge = alin * P.e_lo, hi_edge = alin * P.e_hi;
             const bool mine = valid && half == 0;
-            const bool defer = mine && fabsf(d) < P.tau;
-            const bool accept = mine && !defer && d < 0.0f;
+            const bool defer = mine && U >= lo_edge && U < hi_edge;
+            const bool accept = mine && U < lo_edge;
             const unsigned long long bacc = __ballot(accept);
             const unsigned long long bdef = __ballot(defer);
             if (lane == c) my_word = (uint32_t)bacc;
@@ -137,7 +141,7 @@ __global__ void __launch_bounds__(kBlock) k_decide(KernelArgs a, const int *plis
                     a.dbg_t[local] = t;
                     a.dbg_s3[local] = s3;
                     a.dbg_log_a[local] = la;
-                    a.dbg_log_u[local] = lu;
+                    a.dbg_log_u[local] = log_u_word(w_acc);
                 }
             }
             if (bdef) {
@@ -408,7 +412,7 @@ __global__ void __launch_bounds__(kBlock) k_materialize(KernelArgs a, const int 
                 float x[K];
                 float t;
                 uint32_t w_acc;
-                gen_xhat<K, PROP>(P, i, half, x, t, w_acc);
+                gen_xhat<K, PROP, true>(P, i, half, x, t, w_acc);
                 if (valid && r < P.capacity) {
                     if (out_xhat) {
                         float *row = out_xhat + (P.out_off + r) * P.row_stride + half * K;
