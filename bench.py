@@ -98,6 +98,42 @@ def cpu_baseline(points, plans, n_sample: int) -> dict:
     }
 
 
+def synthesis_bench(args) -> int:
+    """Matrix-core utilisation of the synthesis u~ = Phi^T x^ plus sum of cubes on
+    2^20 x 128 . 128 x 256 (the precision configuration), x^ read from HBM."""
+    import torch
+    from paper_2411_16952_amd import tkdv as T
+    K, n = 64, 1 << 20
+    ctx = T.Context(0)
+    pt = T.make_point(K, 1.0, 40.0, 300.0, seed=7, point_id=1)
+    plan = T.plan_point(pt, T.SIGMA)
+    xhat = ctx.eval_proposals(pt, 0, n, plan=plan, precision=T.BF16X3)["xhat"]
+    s3 = torch.empty((n,), dtype=torch.float32, device=xhat.device)
+    res = {}
+    for name in ("bf16x3", "bf16", "fp32"):
+        P = T.PRECISIONS[name]
+        for _ in range(max(args.warmup, 1)):
+            ctx.synthesize(xhat, precision=P, s3=s3)
+        ms = []
+        for _ in range(max(args.steps, 3)):
+            ctx.synthesize(xhat, precision=P, s3=s3)
+            ms.append(ctx.timing()["synth_ms"])
+        avg = sum(ms) / len(ms)
+        flops = {"bf16x3": 3, "bf16": 1, "fp32": 1}[name] * 2.0 * (2 * K) * (4 * K) * n
+        peak = 157.3e12 if name == "fp32" else 2.5e15
+        bytes_ = n * (2 * K) * 4 + n * 4
+        res[name] = {"ms": avg, "tflops": flops / (avg * 1e-3) / 1e12, "mfma_frac": flops / (avg * 1e-3) / peak,
+                     "hbm_GBps": bytes_ / (avg * 1e-3) / 1e9, "grid": ctx.timing()["decide_grid"]}
+        print(f"synthesis {name}: {avg:.3f} ms", file=sys.stderr, flush=True)
+    line = {"metric": "synthesis matrix-core utilisation (sum of cubes on the grid)", "value": res["bf16x3"]["mfma_frac"],
+            "unit": "fraction of dense BF16 peak", "higher_is_better": True, "n_gpus": 1,
+            "config": {"workload": "K=64, N=256, 2^20 rows of x^ (Sigma proposals, beta'=40, C3/C2=300) in HBM",
+                       "rows": n, "K": K, "N": 4 * K}, "precisions": res}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +142,9 @@ def main() -> int:
     ap.add_argument("--proposals", type=float, default=1e9, help="proposals per point")
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16", "bf16x3"])
     ap.add_argument("--cpu-sample", type=int, default=1 << 22, help="oracle proposals per point (0: skip)")
+    ap.add_argument("--synthesis", action="store_true",
+                    help="only time the standalone synthesis kernel (K = 64, N = 256, 2^20 rows of x^ "
+                         "in HBM) for FP32, BF16 and BF16x3 products; prints one JSON line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
@@ -118,6 +157,8 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": args.calibrate_copy, "copies": 3}))
         return 0
+    if args.synthesis:
+        return synthesis_bench(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sampler's proposals "
               "are independent, and multi-GPU sharding is a design note, not a measured path.",

@@ -125,6 +125,7 @@ typedef struct {
     double segments_ms;     /* accept counts and their scan                         */
     double materialize_ms;  /* ordered output and statistics                        */
     double finalize_ms;     /* per-point reduction                                  */
+    double synth_ms;        /* tkdv_synthesize: the synthesis kernel                */
     double total_ms;        /* first to last event                                  */
     int32_t decide_launches;
     int32_t decide_grid;    /* workgroups of the (last) k_decide launch             */
@@ -190,6 +191,19 @@ tkdv_status tkdv_eval_proposals(tkdv_ctx *ctx, const tkdv_point *pt, tkdv_propos
                                 tkdv_precision precision, float *d_xhat, float *d_t,
                                 float *d_s3, float *d_log_a, float *d_log_u,
                                 uint8_t *d_accept, void *stream);
+
+/*
+ * The spectral-to-grid synthesis of the fast path on its own, for rows of x^
+ * already in device memory: for r < n, with x^ = d_xhat[r][0..2K-1] (the
+ * layout above) and the grid xi_j = -pi + 2 pi j/N, N = 4K,
+ *   d_s3[r] = sum_j u~_j^3,  u~_j = sum_k (x^_k cos k xi_j + x^_{K+k} sin k xi_j),
+ * i.e. H3 = (1/6) int u^3 dxi = (pi/(3N)) (2 E0/pi)^{3/2} d_s3[r] exactly when
+ * |x^| = 1 (Sec. II.A; N >= 3K + 1).  The products run on the matrix cores in
+ * the requested arithmetic with FP32 accumulation.  K in {8, 16, 32, 64};
+ * both pointers are device pointers owned by the caller.
+ */
+tkdv_status tkdv_synthesize(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, const float *d_xhat,
+                            uint64_t n, float *d_s3, void *stream);
 
 /* The decision window used for a point: proposals with |log U - log a| below
  * it are re-decided in FP64.  It is an upper bound on the fast path's error

@@ -34,6 +34,7 @@ from .core import (  # noqa: F401
     proposal,
     sample,
     sample_until,
+    eval_batch,
     stats_of,
     hist_bin,
     max_threads,

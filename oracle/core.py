@@ -127,6 +127,7 @@ lib.orc_sample_until.argtypes = [C.POINTER(_Point), C.c_uint64, C.c_uint64, _PD,
                                  C.POINTER(C.c_uint64), C.c_uint64, C.POINTER(_Stats), C.c_int]
 lib.orc_sample_until.restype = C.c_uint64
 lib.orc_stats_of.argtypes = [C.c_int, C.c_int, _D, _PD, C.c_uint64, C.POINTER(_Stats)]
+lib.orc_eval_batch.argtypes = [C.POINTER(_Point), C.c_uint64, C.c_uint64, _PD, _PD, _PD, _PD, _PD, _PD, C.c_int]
 lib.orc_hist_bin.argtypes = [_D, _D]
 lib.orc_hist_bin.restype = C.c_int
 lib.orc_max_threads.restype = C.c_int
@@ -253,6 +254,20 @@ def sample_until(K, E0, beta_p, c32, proposal_kind, alpha_star, log_M, seed, poi
                          io.ctypes.data_as(C.POINTER(C.c_uint64)), cap, C.byref(st), nthreads)
     s = OracleStats._from(st)
     return {"xhat": xo[:s.n_written], "index": io[:s.n_written], "stats": s}
+
+
+def eval_batch(K, E0, beta_p, c32, proposal_kind, alpha_star, log_M, seed, point_id, i0, n, N,
+               grid=True, nthreads=0) -> dict:
+    """Per-proposal H2, H3 (double sum), grid sums S3/S3abs of the unscaled field
+    (when grid), log a and log U for indices i0..i0+n-1."""
+    p = _point(K, N, proposal_kind, point_id, E0, beta_p, c32, alpha_star, log_M, seed)
+    out = {k: np.zeros(n) for k in ("H2", "H3", "log_a", "log_u")}
+    if grid:
+        out["S3"], out["S3abs"] = np.zeros(n), np.zeros(n)
+    g = (lambda k: _dp(out[k]) if k in out else None)
+    lib.orc_eval_batch(C.byref(p), i0, n, g("H2"), g("H3"), g("S3"), g("S3abs"), g("log_a"), g("log_u"),
+                       nthreads)
+    return out
 
 
 def stats_of(xhat, E0: float, N: int) -> OracleStats:

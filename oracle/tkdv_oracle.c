@@ -479,6 +479,48 @@ uint64_t orc_sample_until(const orc_point *p, uint64_t n_target, uint64_t max_pr
     return nacc;
 }
 
+/*
+ * Per-proposal evaluation of indices [i0, i0+n) for precision studies: H2,
+ * H3 (double sum), the grid sums S3 = sum_j u_j^3 and S3abs = sum_j |u_j|^3 of
+ * the UNSCALED field u~ = sum_k (x^_k cos k xi_j + x^_{K+k} sin k xi_j) on the
+ * N-point grid (direct cos/sin sums), log a and log U.  Any output may be NULL.
+ */
+void orc_eval_batch(const orc_point *p, uint64_t i0, uint64_t n, double *H2, double *H3,
+                    double *S3, double *S3abs, double *log_a, double *log_u, int nthreads)
+{
+    int K = p->K, N = p->N;
+    orc_grid_table g; /* cos(k xi_j), sin(k xi_j) */
+    grid_table_init(&g, K, N, p->E0);
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < (int64_t)n; ++q) {
+        double xh[2 * ORC_KMAX];
+        double lu;
+        double la = orc_proposal(p, i0 + (uint64_t)q, xh, &lu);
+        if (H2) H2[q] = orc_H2(K, p->E0, xh);
+        if (H3) H3[q] = orc_H3_triad(K, p->E0, xh);
+        if (S3 || S3abs) {
+            double s3 = 0.0, sa = 0.0;
+            for (int j = 0; j < N; ++j) {
+                double u = 0.0;
+                for (int k = 0; k < K; ++k)
+                    u += xh[k] * g.cosv[(size_t)j * K + k] + xh[K + k] * g.sinv[(size_t)j * K + k];
+                s3 += u * u * u;
+                sa += fabs(u * u * u);
+            }
+            if (S3) S3[q] = s3;
+            if (S3abs) S3abs[q] = sa;
+        }
+        if (log_a) log_a[q] = la;
+        if (log_u) log_u[q] = lu;
+    }
+    grid_table_free(&g);
+}
+
 /* Statistics of an externally supplied set of samples (rows of x^). */
 void orc_stats_of(int K, int N, double E0, const double *xhat, uint64_t n, orc_stats *st)
 {

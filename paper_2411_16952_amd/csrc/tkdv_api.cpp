@@ -634,6 +634,34 @@ double tkdv_decision_window(const tkdv_point *pt, tkdv_proposal proposal, tkdv_p
     return window(*pt, proposal, precision, pl.alpha_star, pl.log_M);
 }
 
+tkdv_status tkdv_synthesize(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, const float *d_xhat, uint64_t n,
+                            float *d_s3, void *stream)
+{
+    if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");
+    if (kindex(K) < 0) return set_err(ctx, TKDV_E_UNSUPPORTED, "GPU path supports K in {8,16,32,64}");
+    if (precision < TKDV_FP32 || precision > TKDV_BF16X3) return set_err(ctx, TKDV_E_ARG, "bad precision");
+    if (n == 0) return TKDV_OK;
+    if (!d_xhat || !d_s3) return set_err(ctx, TKDV_E_ARG, "NULL device pointer");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    tkdv_status s = build_tables(ctx, K);
+    if (s != TKDV_OK) return s;
+    const int ki = kindex(K);
+    hipStream_t st = (hipStream_t)stream;
+    std::memset(&ctx->timing, 0, sizeof(ctx->timing));
+    ctx->timing.decide_block = kSynthBlock;
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[0], st));
+    HIP_TRY(ctx, launch_synth(K, precision, d_xhat, n, d_s3,
+                              precision == TKDV_FP32 ? ctx->phi_f32[ki].p : ctx->phi_hi[ki].p, ctx->phi_lo[ki].p,
+                              ctx->n_cu, st, &ctx->timing.decide_grid));
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[1], st));
+    HIP_TRY(ctx, hipEventSynchronize(ctx->ev[1]));
+    float ms = 0.0f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+    ctx->timing.synth_ms = ms;
+    ctx->timing.total_ms = ms;
+    return TKDV_OK;
+}
+
 tkdv_status tkdv_get_timing(const tkdv_ctx *ctx, tkdv_timing *out)
 {
     if (!ctx || !out) return set_err(nullptr, TKDV_E_ARG, "NULL argument");

@@ -158,15 +158,17 @@ template <int K>
 __host__ __device__ constexpr int f32_table_bytes() { return (K / 8) * (K / 4) * kWave * 16; }
 
 // Sum over this lane's grid values of u~^3 (u~ = unscaled synthesis), with
-// the products in the requested arithmetic.
-template <int K, int PREC>
+// the products in the requested arithmetic.  TWO_CHAINS accumulates even and
+// odd k-steps of the BF16 paths in separate registers (two independent
+// dependency chains on the matrix pipe), summed before the cube.
+template <int K, int PREC, bool TWO_CHAINS = false>
 __device__ __forceinline__ float synth_cube_sum(const float (&x)[K], const char *lds_hi,
                                                 const char *lds_lo, int lane)
 {
     float s3 = 0.0f;
     if constexpr (PREC == PREC_FP32) {
         const float4 *tab = reinterpret_cast<const float4 *>(lds_hi);
-#pragma unroll
+#pragma unroll(K >= 64 ? 2 : K / 8)
         for (int t = 0; t < K / 8; ++t) {
             f32x16 acc = {};
 #pragma unroll
@@ -194,19 +196,25 @@ __device__ __forceinline__ float synth_cube_sum(const float (&x)[K], const char 
         }
         const bf16x8 *th = reinterpret_cast<const bf16x8 *>(lds_hi);
         const bf16x8 *tl = reinterpret_cast<const bf16x8 *>(lds_lo);
-#pragma unroll
+        // at K = 64 a full unroll keeps every grid tile's operands live (spills)
+#pragma unroll(K >= 64 ? 2 : K / 8)
         for (int t = 0; t < K / 8; ++t) {
-            f32x16 acc = {};
+            f32x16 acc = {}, acc2 = {};
 #pragma unroll
             for (int s = 0; s < K / 8; ++s) {
                 const int idx = (t * (K / 8) + s) * kWave + lane;
                 const bf16x8 ah = th[idx];
+                f32x16 &a = (TWO_CHAINS && (s & 1)) ? acc2 : acc;
                 if constexpr (PREC == PREC_BF16X3) {
                     const bf16x8 al = tl[idx];
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[s], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[s], acc, 0, 0, 0);
+                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[s], a, 0, 0, 0);
+                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[s], a, 0, 0, 0);
                 }
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[s], acc, 0, 0, 0);
+                a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[s], a, 0, 0, 0);
+            }
+            if constexpr (TWO_CHAINS) {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) acc[v] += acc2[v];
             }
 #pragma unroll
             for (int v = 0; v < 16; ++v) s3 = __builtin_fmaf(acc[v] * acc[v], acc[v], s3);

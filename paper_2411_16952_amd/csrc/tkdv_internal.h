@@ -11,6 +11,7 @@ namespace tkdv {
 constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kTile = 32;          // proposals per wave tile (two lanes per proposal)
 constexpr int kBlock = 256;        // threads per workgroup of the sampling kernels
+constexpr int kSynthBlock = 512;   // threads per workgroup of the standalone synthesis kernel
 constexpr int kClaimTiles = 64;    // tiles claimed per work-queue claim (2048 proposals);
                                    // lane c keeps the accept word of tile c
 constexpr int kSegWords = 2048;    // bitmap words per statistics segment (65536 proposals)

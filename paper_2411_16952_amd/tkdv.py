@@ -48,7 +48,8 @@ class Plan(C.Structure):
 
 class Timing(C.Structure):
     _fields_ = [("decide_ms", C.c_double), ("fixup_ms", C.c_double), ("segments_ms", C.c_double),
-                ("materialize_ms", C.c_double), ("finalize_ms", C.c_double), ("total_ms", C.c_double),
+                ("materialize_ms", C.c_double), ("finalize_ms", C.c_double), ("synth_ms", C.c_double),
+                ("total_ms", C.c_double),
                 ("decide_launches", C.c_int32), ("decide_grid", C.c_int32), ("decide_block", C.c_int32),
                 ("pad", C.c_int32)]
 
@@ -83,8 +84,8 @@ def _load() -> C.CDLL:
 lib = _load()
 
 EXPORTS = ["tkdv_create", "tkdv_destroy", "tkdv_plan_point", "tkdv_sample", "tkdv_sample_batch",
-           "tkdv_eval_proposals", "tkdv_decision_window", "tkdv_get_timing", "tkdv_status_str",
-           "tkdv_last_error"]
+           "tkdv_eval_proposals", "tkdv_synthesize", "tkdv_decision_window", "tkdv_get_timing",
+           "tkdv_status_str", "tkdv_last_error"]
 
 _P = C.c_void_p
 lib.tkdv_create.argtypes = [C.c_int, C.POINTER(_P)]
@@ -98,6 +99,7 @@ lib.tkdv_sample_batch.argtypes = [_P, C.c_int32, C.POINTER(Point), C.c_int, C.PO
 lib.tkdv_eval_proposals.argtypes = [_P, C.POINTER(Point), C.c_int, C.POINTER(Plan), C.c_uint64,
                                     C.c_uint64, C.c_int, _P, _P, _P, _P, _P, _P, _P]
 lib.tkdv_get_timing.argtypes = [_P, C.POINTER(Timing)]
+lib.tkdv_synthesize.argtypes = [_P, C.c_int32, C.c_int, _P, C.c_uint64, _P, _P]
 lib.tkdv_decision_window.argtypes = [C.POINTER(Point), C.c_int, C.c_int]
 lib.tkdv_decision_window.restype = C.c_double
 lib.tkdv_status_str.argtypes = [C.c_int]
@@ -214,6 +216,17 @@ class Context:
             d["index"] = index[o:o + nw]
             out.append(d)
         return out, xhat, index
+
+    def synthesize(self, xhat, precision: int = BF16X3, s3=None, stream=None):
+        """s3[r] = sum_j u~_j^3 on the N = 4K grid for rows x^ (n, 2K) float32 on the device."""
+        import torch
+        assert xhat.dtype == torch.float32 and xhat.is_contiguous() and xhat.dim() == 2
+        n, twoK = xhat.shape
+        if s3 is None:
+            s3 = torch.empty((n,), dtype=torch.float32, device=xhat.device)
+        _check(lib.tkdv_synthesize(self._h, twoK // 2, int(precision), _ptr(xhat), int(n), _ptr(s3),
+                                   _stream(stream)), self._h)
+        return s3
 
     def eval_proposals(self, point: Point, i0: int, n: int, proposal: int = SIGMA,
                        plan: Plan | None = None, precision: int = BF16X3, stream=None) -> dict:

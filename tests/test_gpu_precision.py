@@ -1,0 +1,94 @@
+"""Precision of the synthesis arithmetic against the FP64 oracle (K = 64, N = 256).
+
+One batch of 2^20 Sigma proposals at beta' = 40, C3/C2 in {0, 300}: the fast
+path's H3 (grid sum of cubes) and H2 for FP32, BF16 and BF16x3 products,
+compared proposal by proposal with the oracle (H3 relative to the scale
+S3abs = sum_j |u_j|^3, H2 relative to itself); accept-decision mismatches of
+the FP32 fast path alone and after the FP64 re-decision; and the standalone
+synthesis kernel (x^ read from HBM) on the same rows.  A JSON report is
+written to gpurun_out/ when that directory exists.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+N_BATCH = 1 << 20
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2411_16952_amd import tkdv
+    return tkdv
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    c = T.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("c32", [0.0, 300.0])
+def test_precision_study_k64(T, ctx, c32):
+    K, E0, bp = 64, 1.0, 40.0
+    print(f"precision study K={K} beta'={bp} c={c32} n={N_BATCH}", flush=True)
+    pt = T.make_point(K, E0, bp, c32, seed=7, point_id=int(c32 > 0))
+    plan = T.plan_point(pt, T.SIGMA)
+    o = oracle.eval_batch(K, E0, bp, c32, 1, plan.alpha_star, plan.log_M, pt.seed, pt.point_id, 0, N_BATCH, 4 * K)
+    t_o = o["H2"] / E0
+    amb = np.abs(o["log_u"] - o["log_a"]) < 1e-9
+    dec_o = o["log_u"] < o["log_a"]
+    report = {"K": K, "N": 4 * K, "beta_p": bp, "c32": c32, "n": N_BATCH,
+              "oracle_accepted": int(dec_o.sum()), "ambiguous": int(amb.sum()), "precisions": {}}
+    bounds = {"fp32": 2e-5, "bf16x3": 1e-3, "bf16": 1e-1}  # worst-case relative H3 error allowed
+    for name in ("fp32", "bf16x3", "bf16"):
+        P = T.PRECISIONS[name]
+        g = ctx.eval_proposals(pt, 0, N_BATCH, plan=plan, precision=P)
+        s3_sa = ctx.synthesize(g["xhat"], precision=P).cpu().numpy().astype(np.float64)
+        s3 = g["s3"].cpu().numpy().astype(np.float64)
+        t = g["t"].cpu().numpy().astype(np.float64)
+        la = g["log_a"].cpu().numpy().astype(np.float64)
+        lu = g["log_u"].cpu().numpy().astype(np.float64)
+        acc = g["accept"].cpu().numpy().astype(bool)
+        del g
+        rel3 = np.abs(s3 - o["S3"]) / o["S3abs"]
+        rel3_sa = np.abs(s3_sa - o["S3"]) / o["S3abs"]
+        rel2 = np.abs(t - t_o) / t_o
+        fast = lu < la
+        rep = {
+            "H3_rel_max": float(rel3.max()), "H3_rel_median": float(np.median(rel3)),
+            "H3_rel_max_standalone": float(rel3_sa.max()),
+            "H3_rel_median_standalone": float(np.median(rel3_sa)),
+            "H2_rel_max": float(rel2.max()), "H2_rel_median": float(np.median(rel2)),
+            "log_a_abs_max": float(np.abs(la - o["log_a"]).max()),
+            "window": T.decision_window(pt, T.SIGMA, P),
+            "decision_mismatch_fast_path": int(((fast != dec_o) & ~amb).sum()),
+            "decision_mismatch_after_fp64": int(((acc != dec_o) & ~amb).sum()),
+            "fp64_redecided": None,
+        }
+        report["precisions"][name] = rep
+        print(name, json.dumps(rep), flush=True)
+        assert rep["decision_mismatch_after_fp64"] == 0
+        assert rep["H3_rel_max"] < bounds[name] and rep["H3_rel_max_standalone"] < bounds[name]
+        assert rep["H2_rel_max"] < 2e-6
+        assert rep["log_a_abs_max"] < rep["window"] / 2
+    p = report["precisions"]
+    assert p["fp32"]["H3_rel_median"] < 1e-6           # FP32: 1e-6 relative
+    assert p["bf16"]["H3_rel_median"] < 1e-2           # BF16 before split recovery
+    assert p["bf16x3"]["H3_rel_median"] < 1e-4         # BF16x3: measured and reported
+    out = os.path.join(ROOT, "gpurun_out")
+    if os.path.isdir(out):
+        with open(os.path.join(out, f"precision_k64_c{int(c32)}.json"), "w") as f:
+            json.dump(report, f, indent=1)
+    sys.stdout.flush()
