@@ -65,7 +65,36 @@ typedef enum {
     TKDV_E_M_VIOLATION = -6    /* reserved: a proposal had f/(M g) > 1                        */
 } tkdv_status;
 
-typedef enum { TKDV_PROP_UNIFORM = 0, TKDV_PROP_SIGMA = 1 } tkdv_proposal;
+typedef enum { TKDV_PROP_UNIFORM = 0, TKDV_PROP_SIGMA = 1, TKDV_PROP_MIXTURE = 2 } tkdv_proposal;
+
+/*
+ * Learned proposal (an extension, not in the paper): the defensive mixture
+ *   q_mix = eps g_Sigma + (1 - eps) q_net,   q_net = (1/S) sum_{j<S} ACG_j,
+ * of angular central Gaussian densities w.r.t. mu0, exactly normalised:
+ *   ACG(x^; L) = |L|^{-1/2} (x^T L^{-1} x^)^{-K};
+ * g_Sigma (the paper's proposal, Sec. III.B) is the ACG with L = Sigma.
+ * Component j is the base L0 = D + V V^T (D = diag(exp logd_k) on the cos and
+ * sin coordinate of mode k, V of rank TKDV_MIX_R) rotated by the xi-shift
+ * phi_j = 2 pi j/S: (R x)_k = x_k cos k phi + x_{K+k} sin k phi,
+ * (R x)_{K+k} = x_{K+k} cos k phi - x_k sin k phi; the target f is invariant
+ * under these shifts.  Since q_mix >= eps g_Sigma, f/q_mix <= M_Sigma/eps.
+ * Draw of proposal i: the 2K normals zeta of words 0..2K-1, word 2K the
+ * acceptance uniform, word 2K+1 the component word w_c, words 2K+2, 2K+3 a
+ * Box-Muller pair eta.  The component is chosen in integers: with
+ * E = S floor(eps 2^32/S) and B = (2^32 - E)/S, w_c < E -> X = Sigma^{1/2} zeta,
+ * otherwise j = (w_c - E) div B, X = D^{1/2} zeta + (R_j V) eta; x^ = X/|X|.
+ * The weight of g_Sigma in every density is therefore E 2^-32 (eps rounded
+ * down to a multiple of 2^-27).
+ */
+#define TKDV_MIX_S 32
+#define TKDV_MIX_R 2
+typedef struct {
+    int32_t K;
+    int32_t pad;
+    double eps;                            /* weight of g_Sigma, e.g. 0.2                */
+    double logd[TKDV_KMAX];                /* log d_k, k = 1..K                          */
+    double V[2 * TKDV_KMAX][TKDV_MIX_R];   /* base rank-R factor, rows = coordinates     */
+} tkdv_mixture;
 
 /* Arithmetic of the spectral-to-grid synthesis U = X^ Phi on the matrix cores:
  * FP32 products, BF16 products (one term), or BF16 with 3-term split
@@ -209,6 +238,47 @@ tkdv_status tkdv_synthesize(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, 
  * it are re-decided in FP64.  It is an upper bound on the fast path's error
  * in log a (see the library's design notes) times a safety factor of 2. */
 double tkdv_decision_window(const tkdv_point *pt, tkdv_proposal proposal, tkdv_precision precision);
+
+/* Host FP64: log q_net and log q_mix (normalised, w.r.t. mu0) at n points x^
+ * (host array [n][2K]); sigma_plan is the Sigma plan of the point (alpha*). */
+tkdv_status tkdv_mixture_log_q(const tkdv_point *pt, const tkdv_plan *sigma_plan, const tkdv_mixture *mix,
+                               const double *xhat, int32_t n, double *log_q_net, double *log_q_mix);
+
+/* Host FP64: the rejection constant of the mixture proposal, log M_mix = log sup
+ * f/q_mix (f unnormalised as in log_M of the Sigma plan), by BFGS ascent on the
+ * sphere (analytic gradient) from the zero-mean Dirichlet kernel and its
+ * shifts, the Sigma maximiser, n_starts caller points (host [n_starts][2K],
+ * may be NULL) and seeded random directions.  The result is raised by
+ * log(1 + margin) and capped at log M_Sigma - log_norm_g - log eps (valid since
+ * q_mix >= eps g_Sigma).  *out is the Sigma plan with log_M replaced and
+ * proposal = TKDV_PROP_MIXTURE; argmax (host [2K], may be NULL) receives the
+ * best point found. */
+tkdv_status tkdv_plan_mixture(const tkdv_point *pt, const tkdv_plan *sigma_plan, const tkdv_mixture *mix,
+                              const double *starts, int32_t n_starts, double margin, tkdv_plan *out,
+                              double *argmax);
+
+/* tkdv_sample with the learned proposal (plan from tkdv_plan_mixture), same
+ * outputs and statistics.  K in {8, 16, 32}: at K = 64 the synthesis and shift
+ * tables together exceed the LDS of a compute unit (TKDV_E_UNSUPPORTED).
+ * TKDV_E_ARG also when lambda_max(I + V^T D^-1 V) > 1e5 (the FP32 quadratic
+ * forms would lose all precision). */
+tkdv_status tkdv_sample_mixture(tkdv_ctx *ctx, const tkdv_point *pt, const tkdv_plan *mix_plan,
+                                const tkdv_mixture *mix, uint64_t n, tkdv_count_mode mode,
+                                uint64_t max_proposals, tkdv_precision precision, float *d_xhat,
+                                uint64_t *d_index, uint64_t capacity, tkdv_stats *h_stats, void *stream);
+
+/* tkdv_eval_proposals for the learned proposal: per-proposal x^, t, S3, log a,
+ * log U and decisions of proposals [i0, i0 + n) (device arrays as there). */
+tkdv_status tkdv_eval_mixture(tkdv_ctx *ctx, const tkdv_point *pt, const tkdv_plan *mix_plan,
+                              const tkdv_mixture *mix, uint64_t i0, uint64_t n, tkdv_precision precision,
+                              float *d_xhat, float *d_t, float *d_s3, float *d_log_a, float *d_log_u,
+                              uint8_t *d_accept, void *stream);
+
+/* Decision window of the mixture sampler for this point, mixture and
+ * arithmetic: the window of the paper's proposal plus the error bound of the
+ * FP32 log q_mix (input error, y products, rounding, log2/exp2), times 2. */
+double tkdv_mixture_window(const tkdv_point *pt, const tkdv_plan *mix_plan, const tkdv_mixture *mix,
+                           tkdv_precision precision);
 
 /* Phase timings of the last call on this context (see tkdv_timing). */
 tkdv_status tkdv_get_timing(const tkdv_ctx *ctx, tkdv_timing *out);

@@ -35,6 +35,15 @@ from .core import (  # noqa: F401
     sample,
     sample_until,
     eval_batch,
+    MIX_S,
+    MIX_R,
+    make_mixture,
+    shift,
+    mix_log_q,
+    mix_draw,
+    mix_sample,
+    mix_eps,
+    mix_threshold,
     stats_of,
     hist_bin,
     max_threads,

@@ -59,6 +59,28 @@ class _Stats(C.Structure):
     ]
 
 
+MIX_S, MIX_R = 32, 2
+
+
+class _Mixture(C.Structure):
+    _fields_ = [("K", C.c_int32), ("pad", C.c_int32), ("eps", C.c_double),
+                ("logd", C.c_double * 128), ("V", (C.c_double * MIX_R) * 256)]
+
+
+def make_mixture(K: int, eps: float, logd, V) -> _Mixture:
+    """Base component L0 = D + V V^T: logd [K], V [2K, 2]."""
+    m = _Mixture()
+    m.K, m.eps = K, eps
+    logd = np.asarray(logd, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    for k in range(K):
+        m.logd[k] = logd[k]
+    for c in range(2 * K):
+        for q in range(MIX_R):
+            m.V[c][q] = V[c, q]
+    return m
+
+
 @dataclass
 class OracleStats:
     n_proposed: int
@@ -128,6 +150,19 @@ lib.orc_sample_until.argtypes = [C.POINTER(_Point), C.c_uint64, C.c_uint64, _PD,
 lib.orc_sample_until.restype = C.c_uint64
 lib.orc_stats_of.argtypes = [C.c_int, C.c_int, _D, _PD, C.c_uint64, C.POINTER(_Stats)]
 lib.orc_eval_batch.argtypes = [C.POINTER(_Point), C.c_uint64, C.c_uint64, _PD, _PD, _PD, _PD, _PD, _PD, C.c_int]
+lib.orc_shift.argtypes = [C.c_int, _D, _PD, _PD]
+lib.orc_mix_log_q.argtypes = [C.POINTER(_Point), C.POINTER(_Mixture), _PD, _PD, _PD]
+lib.orc_mix_draw.argtypes = [C.POINTER(_Point), C.POINTER(_Mixture), C.c_uint64, _PD, _PD]
+lib.orc_mix_draw.restype = C.c_int
+lib.orc_mix_proposal.argtypes = [C.POINTER(_Point), C.POINTER(_Mixture), C.c_uint64, _PD, _PD]
+lib.orc_mix_proposal.restype = _D
+lib.orc_mix_sample.argtypes = [C.POINTER(_Point), C.POINTER(_Mixture), C.c_uint64, C.c_uint64,
+                               C.POINTER(C.c_uint8), _PD, _PD, _PD, C.POINTER(C.c_uint64), C.c_uint64, C.c_int]
+lib.orc_mix_sample.restype = C.c_uint64
+lib.orc_mix_threshold.argtypes = [C.POINTER(_Mixture)]
+lib.orc_mix_threshold.restype = C.c_uint64
+lib.orc_mix_eps.argtypes = [C.POINTER(_Mixture)]
+lib.orc_mix_eps.restype = _D
 lib.orc_hist_bin.argtypes = [_D, _D]
 lib.orc_hist_bin.restype = C.c_int
 lib.orc_max_threads.restype = C.c_int
@@ -268,6 +303,57 @@ def eval_batch(K, E0, beta_p, c32, proposal_kind, alpha_star, log_M, seed, point
     lib.orc_eval_batch(C.byref(p), i0, n, g("H2"), g("H3"), g("S3"), g("S3abs"), g("log_a"), g("log_u"),
                        nthreads)
     return out
+
+
+def shift(x, phi: float) -> np.ndarray:
+    """Coefficients of u(xi + phi): mode k rotated by the angle k phi."""
+    x = _f64(x)
+    out = np.zeros_like(x)
+    lib.orc_shift(x.size // 2, phi, _dp(x), _dp(out))
+    return out
+
+
+def mix_log_q(K, E0, beta_p, c32, alpha_star, mixture, xhat):
+    """(log q_net, log q_mix) at x^ (normalised densities w.r.t. mu0)."""
+    p = _point(K, 4 * K, 1, 0, E0, beta_p, c32, alpha_star, 0.0, 0)
+    x = _f64(xhat)
+    a, b = C.c_double(), C.c_double()
+    lib.orc_mix_log_q(C.byref(p), C.byref(mixture), _dp(x), C.byref(a), C.byref(b))
+    return a.value, b.value
+
+
+def mix_draw(K, E0, beta_p, c32, alpha_star, mixture, seed, point_id, i):
+    """(x^, component or -1, log U) of mixture proposal i."""
+    p = _point(K, 4 * K, 1, point_id, E0, beta_p, c32, alpha_star, 0.0, seed)
+    xh = np.zeros(2 * K)
+    lu = C.c_double()
+    comp = lib.orc_mix_draw(C.byref(p), C.byref(mixture), i, _dp(xh), C.byref(lu))
+    return xh, comp, lu.value
+
+
+def mix_sample(K, E0, beta_p, c32, alpha_star, log_M_mix, mixture, seed, point_id, n, i0=0,
+               cap=0, want_log=False, nthreads=0):
+    """Rejection sampler with the mixture proposal over indices [i0, i0+n)."""
+    p = _point(K, 4 * K, 1, point_id, E0, beta_p, c32, alpha_star, log_M_mix, seed)
+    acc = np.zeros(n, dtype=np.uint8)
+    la = np.zeros(n) if want_log else None
+    lu = np.zeros(n) if want_log else None
+    xo = np.zeros((max(cap, 1), 2 * K))
+    io = np.zeros(max(cap, 1), dtype=np.uint64)
+    nacc = lib.orc_mix_sample(C.byref(p), C.byref(mixture), i0, n, acc.ctypes.data_as(C.POINTER(C.c_uint8)),
+                              _dp(la) if la is not None else None, _dp(lu) if lu is not None else None,
+                              _dp(xo), io.ctypes.data_as(C.POINTER(C.c_uint64)), cap, nthreads)
+    nw = min(nacc, cap)
+    return {"accept": acc, "log_a": la, "log_u": lu, "xhat": xo[:nw], "index": io[:nw], "n_accepted": nacc}
+
+
+def mix_eps(mixture) -> float:
+    """Weight of g_Sigma the mixture realises: E 2^-32, E = S floor(eps 2^32/S)."""
+    return lib.orc_mix_eps(C.byref(mixture))
+
+
+def mix_threshold(mixture) -> int:
+    return int(lib.orc_mix_threshold(C.byref(mixture)))
 
 
 def stats_of(xhat, E0: float, N: int) -> OracleStats:

@@ -283,6 +283,184 @@ double orc_proposal(const orc_point *p, uint64_t i, double *xh, double *log_u)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Learned proposal (not in the paper): a defensive mixture                 */
+/*   q_mix = eps g_Sigma + (1 - eps) q_net,  q_net = (1/S) sum_j ACG_j,      */
+/* of angular central Gaussian densities w.r.t. mu0, exactly normalised:     */
+/*   ACG(x^; L) = |L|^{-1/2} (x^T L^{-1} x^)^{-K}   (x^ in S^{2K-1}).        */
+/* g_Sigma is the paper's proposal, an ACG with L = Sigma (Sec. III.B).      */
+/* Component j is the base L0 = D + V V^T (D = diag(d_k) on the cos and sin */
+/* coordinate of mode k, V of rank R) rotated by the xi-shift phi_j =       */
+/* 2 pi j/S, which rotates mode k by the angle k phi_j; f is invariant      */
+/* under these shifts.                                                      */
+/* ------------------------------------------------------------------------ */
+#define ORC_MIX_S 32
+#define ORC_MIX_R 2
+
+typedef struct {
+    int32_t K;
+    int32_t pad;
+    double eps;                          /* weight of g_Sigma                   */
+    double logd[ORC_KMAX];               /* log d_k, k = 1..K                   */
+    double V[2 * ORC_KMAX][ORC_MIX_R];   /* rows = coordinates                  */
+} orc_mixture;
+
+/* Integer threshold of the g_Sigma component, E = S floor(eps 2^32 / S), and
+   the weight it realises, eps_eff = E 2^-32 (used in every density). */
+uint64_t orc_mix_threshold(const orc_mixture *m)
+{
+    return (uint64_t)ORC_MIX_S * (uint64_t)floor(m->eps * (double)(1ull << 32) / ORC_MIX_S);
+}
+double orc_mix_eps(const orc_mixture *m) { return ldexp((double)orc_mix_threshold(m), -32); }
+
+/* (R_phi x)_k = x_k cos k phi + x_{K+k} sin k phi,
+   (R_phi x)_{K+k} = x_{K+k} cos k phi - x_k sin k phi  (shift of u by phi). */
+void orc_shift(int K, double phi, const double *x, double *out)
+{
+    for (int k = 1; k <= K; ++k) {
+        double c = cos(k * phi), s = sin(k * phi);
+        double a = x[k - 1], b = x[K + k - 1];
+        out[k - 1] = a * c + b * s;
+        out[K + k - 1] = b * c - a * s;
+    }
+}
+
+/* r x r Gram G = I + V^T D^-1 V, its inverse and log det (r = 2, closed form). */
+static void mix_gram(const orc_mixture *m, double Ginv[ORC_MIX_R][ORC_MIX_R], double *logdetG)
+{
+    int K = m->K;
+    double G[ORC_MIX_R][ORC_MIX_R] = {{1.0, 0.0}, {0.0, 1.0}};
+    for (int c = 0; c < 2 * K; ++c) {
+        double a = exp(-m->logd[c % K]);
+        for (int p = 0; p < ORC_MIX_R; ++p)
+            for (int q = 0; q < ORC_MIX_R; ++q) G[p][q] += m->V[c][p] * a * m->V[c][q];
+    }
+    double det = G[0][0] * G[1][1] - G[0][1] * G[1][0];
+    Ginv[0][0] = G[1][1] / det;
+    Ginv[1][1] = G[0][0] / det;
+    Ginv[0][1] = -G[0][1] / det;
+    Ginv[1][0] = -G[1][0] / det;
+    *logdetG = log(det);
+}
+
+/* log ACG(w; L0) for a point w of the sphere, via x^T L0^-1 x = e^T D^-1 e + |g|^2,
+   g = G^-1 V^T D^-1 w, e = w - V g (Woodbury, no cancellation). */
+static double mix_log_acg0(const orc_mixture *m, const double Ginv[ORC_MIX_R][ORC_MIX_R],
+                           double logdet_L0, const double *w)
+{
+    int K = m->K;
+    double y[ORC_MIX_R] = {0.0, 0.0};
+    for (int c = 0; c < 2 * K; ++c) {
+        double a = exp(-m->logd[c % K]);
+        for (int p = 0; p < ORC_MIX_R; ++p) y[p] += m->V[c][p] * a * w[c];
+    }
+    double g[ORC_MIX_R];
+    for (int p = 0; p < ORC_MIX_R; ++p) g[p] = Ginv[p][0] * y[0] + Ginv[p][1] * y[1];
+    double qf = g[0] * g[0] + g[1] * g[1];
+    for (int c = 0; c < 2 * K; ++c) {
+        double e = w[c] - (m->V[c][0] * g[0] + m->V[c][1] * g[1]);
+        qf += exp(-m->logd[c % K]) * e * e;
+    }
+    return -0.5 * logdet_L0 - K * log(qf);
+}
+
+/* log q_net and log q_mix at x^ (normalised densities w.r.t. mu0).
+   log g_Sigma = sum_k log(1 + alpha beta' k^2/K^3) - K log(1 + alpha beta' t/K^3). */
+void orc_mix_log_q(const orc_point *p, const orc_mixture *m, const double *xh,
+                   double *log_q_net, double *log_q_mix)
+{
+    int K = p->K;
+    double Ginv[ORC_MIX_R][ORC_MIX_R], ldG;
+    mix_gram(m, Ginv, &ldG);
+    double ldD = 0.0;
+    for (int k = 0; k < K; ++k) ldD += 2.0 * m->logd[k];
+    double logdet_L0 = ldD + ldG;
+    double terms[ORC_MIX_S], mx = -INFINITY;
+    double w[2 * ORC_KMAX];
+    for (int j = 0; j < ORC_MIX_S; ++j) {
+        /* ACG_j(x^) = ACG(R_j^T x^; L0), R_j^T = shift by -phi_j */
+        orc_shift(K, -2.0 * M_PI * j / ORC_MIX_S, xh, w);
+        terms[j] = mix_log_acg0(m, Ginv, logdet_L0, w);
+        if (terms[j] > mx) mx = terms[j];
+    }
+    double se = 0.0;
+    for (int j = 0; j < ORC_MIX_S; ++j) se += exp(terms[j] - mx);
+    double lnet = mx + log(se) - log((double)ORC_MIX_S);
+    double K3 = (double)K * K * K, lng = 0.0;
+    for (int k = 1; k <= K; ++k) lng += log1p(p->alpha_star * p->beta_p * (double)k * k / K3);
+    double lg = lng - K * log1p(p->alpha_star * p->beta_p * orc_t(K, xh) / K3);
+    double eps = orc_mix_eps(m);
+    double a = log(eps) + lg, b = log1p(-eps) + lnet;
+    double hi = a > b ? a : b;
+    if (log_q_net) *log_q_net = lnet;
+    if (log_q_mix) *log_q_mix = hi + log(exp(a - hi) + exp(b - hi));
+}
+
+/*
+ * Draw of proposal i from q_mix.  Words 0..2K-1: the 2K normals zeta (as for
+ * the paper's proposal); word 2K: acceptance uniform; word 2K+1: component
+ * word w_c; words (2K+2, 2K+3): one Box-Muller pair eta (r = 2).
+ * The component is chosen in integers: w_c < E gives g_Sigma with
+ * X = Sigma^{1/2} zeta, otherwise j = (w_c - E) div B with B = (2^32 - E)/S
+ * and X = D^{1/2} zeta + (R_j V) eta ~ N(0, R_j L0 R_j^T).  x^ = X/|X|.
+ * E = S floor(eps 2^32/S), so the mixture weights are exactly E 2^-32 and
+ * (1 - E 2^-32)/S (orc_mix_eps).  Returns the component (-1 for g_Sigma)
+ * and log U.
+ */
+int orc_mix_draw(const orc_point *p, const orc_mixture *m, uint64_t i, double *xh, double *log_u)
+{
+    int K = p->K;
+    uint32_t words[2 * ORC_KMAX + 4];
+    orc_proposal_words(p->seed, i, p->point_id, 0u, 2 * K + 4, words);
+    double z[2 * ORC_KMAX];
+    for (int q = 0; q < K; ++q) {
+        double u1 = orc_uniform(words[2 * q]), u2 = orc_uniform(words[2 * q + 1]);
+        double r = sqrt(-2.0 * log(u1)), th = 2.0 * M_PI * u2;
+        z[2 * q] = r * cos(th);
+        z[2 * q + 1] = r * sin(th);
+    }
+    uint64_t wc = words[2 * K + 1], E = orc_mix_threshold(m), B = ((1ull << 32) - E) / ORC_MIX_S;
+    double e1 = orc_uniform(words[2 * K + 2]), e2 = orc_uniform(words[2 * K + 3]);
+    double er = sqrt(-2.0 * log(e1)), eth = 2.0 * M_PI * e2;
+    double eta[2] = {er * cos(eth), er * sin(eth)};
+    if (log_u) *log_u = log(orc_uniform(words[2 * K]));
+    double X[2 * ORC_KMAX];
+    int comp = -1;
+    if (wc < E) {
+        for (int c = 0; c < 2 * K; ++c) X[c] = sqrt(orc_sigma2(K, p->beta_p, p->alpha_star, c % K + 1)) * z[c];
+    } else {
+        comp = (int)((wc - E) / B);
+        double v0[2 * ORC_KMAX], v1[2 * ORC_KMAX], rv0[2 * ORC_KMAX], rv1[2 * ORC_KMAX];
+        for (int c = 0; c < 2 * K; ++c) { v0[c] = m->V[c][0]; v1[c] = m->V[c][1]; }
+        double phi = 2.0 * M_PI * comp / ORC_MIX_S;
+        orc_shift(K, phi, v0, rv0);
+        orc_shift(K, phi, v1, rv1);
+        for (int c = 0; c < 2 * K; ++c)
+            X[c] = exp(0.5 * m->logd[c % K]) * z[c] + rv0[c] * eta[0] + rv1[c] * eta[1];
+    }
+    double r2 = 0.0;
+    for (int c = 0; c < 2 * K; ++c) r2 += X[c] * X[c];
+    double r = sqrt(r2);
+    for (int c = 0; c < 2 * K; ++c) xh[c] = X[c] / r;
+    return comp;
+}
+
+/* log a = log f - log q_mix - log M_mix for proposal i of the mixture sampler
+   (p->log_M holds log M_mix for the normalised q_mix). */
+double orc_mix_proposal(const orc_point *p, const orc_mixture *m, uint64_t i, double *xh, double *log_u)
+{
+    orc_mix_draw(p, m, i, xh, log_u);
+    double lqm;
+    orc_mix_log_q(p, m, xh, NULL, &lqm);
+    return -orc_beta_H(p->K, p->E0, p->beta_p, p->c32, xh) - lqm - p->log_M;
+}
+
+/* The rejection sampler with the mixture proposal over [i0, i0+n): accept
+   flags, optional log a / log U, accepted rows (up to cap) and statistics. */
+uint64_t orc_mix_sample(const orc_point *p, const orc_mixture *m, uint64_t i0, uint64_t n,
+                        uint8_t *accept, double *log_a_out, double *log_u_out, double *xhat_out,
+                        uint64_t *index_out, uint64_t cap, int nthreads);
+
+/* ------------------------------------------------------------------------ */
 /* Statistics of the accepted ensemble (moments of u pooled over samples x  */
 /* grid points, exceedance of 2 sigma with sigma = sqrt(E0/pi), histogram of */
 /* u(0) on [-u_max, u_max], u_max = sqrt(2 K E0/pi)).                       */
@@ -544,4 +722,37 @@ int orc_max_threads(void)
 #else
     return 1;
 #endif
+}
+
+uint64_t orc_mix_sample(const orc_point *p, const orc_mixture *m, uint64_t i0, uint64_t n,
+                        uint8_t *accept, double *log_a_out, double *log_u_out, double *xhat_out,
+                        uint64_t *index_out, uint64_t cap, int nthreads)
+{
+    int K = p->K;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < (int64_t)n; ++q) {
+        double xh[2 * ORC_KMAX], lu;
+        double la = orc_mix_proposal(p, m, i0 + (uint64_t)q, xh, &lu);
+        accept[q] = (uint8_t)(lu < la);
+        if (log_a_out) log_a_out[q] = la;
+        if (log_u_out) log_u_out[q] = lu;
+    }
+    uint64_t nacc = 0;
+    double xh[2 * ORC_KMAX];
+    for (uint64_t q = 0; q < n; ++q) {
+        if (!accept[q]) continue;
+        if (nacc < cap) {
+            orc_mix_draw(p, m, i0 + q, xh, NULL);
+            if (xhat_out)
+                for (int c = 0; c < 2 * K; ++c) xhat_out[nacc * 2 * K + c] = xh[c];
+            if (index_out) index_out[nacc] = i0 + q;
+        }
+        nacc++;
+    }
+    return nacc;
 }

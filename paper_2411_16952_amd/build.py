@@ -15,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtkdv.so")
-SOURCES = ["tkdv_kernels.hip", "tkdv_api.cpp", "tkdv_plan.cpp"]
+SOURCES = ["tkdv_kernels.hip", "tkdv_api.cpp", "tkdv_plan.cpp", "tkdv_mixture.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -23,6 +23,9 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # matrix-instruction results in ordinary VGPRs (no accumulator-register reads)
     "-mllvm", "-amdgpu-mfma-vgpr-form=1",
+    # wave-level atomics with a per-lane value (lane 0's claim, others 0) are
+    # reduced with DPP row operations instead of a 64-step scalar scan
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=DPP",
     "-Wall", "-Wno-unused-function",
 ]
 

@@ -13,6 +13,8 @@
 #include "../../include/tkdv.h"
 #include "tkdv_internal.h"
 #include "tkdv_kernels.h"
+#include "tkdv_host_math.h"
+#include "tkdv_mixture.h"
 #include "tkdv_plan.h"
 
 using namespace tkdv;
@@ -40,23 +42,6 @@ int kindex(int K)
     }
 }
 
-// Round to bfloat16 with round-to-nearest-even; returns the bits.
-uint16_t bf16_bits(float f)
-{
-    uint32_t u;
-    std::memcpy(&u, &f, 4);
-    const uint32_t lsb = (u >> 16) & 1u;
-    u += 0x7FFFu + lsb;
-    return (uint16_t)(u >> 16);
-}
-float bf16_value(uint16_t b)
-{
-    uint32_t u = (uint32_t)b << 16;
-    float f;
-    std::memcpy(&f, &u, 4);
-    return f;
-}
-
 }  // namespace
 
 struct tkdv_ctx {
@@ -64,6 +49,7 @@ struct tkdv_ctx {
     int n_cu = 0;
     std::string last_error;
     DevBuf bitmap, defer_list, defer_count, counters, points, seg_cnt, seg_base, seg_stats, results, plist;
+    DevBuf mix, mix_tab;  // learned-proposal constants and tables of the current call
     DevBuf phi_hi[4], phi_lo[4], phi_f32[4];
     void *h_results = nullptr;  // pinned
     size_t h_results_bytes = 0;
@@ -186,7 +172,7 @@ tkdv_status check_point(tkdv_ctx *ctx, const tkdv_point &pt)
 //   sum_k Phi_kj^2 = K), |dH3| <= E0 amp max|du~| + sum-of-cubes rounding
 //   (sum_j u_j^2 = N E0/pi), the t terms carry 4 eps_x relative error, and
 //   FP32 rounding of the terms of log a and of log U is added explicitly.
-double window(const tkdv_point &pt, int proposal, int precision, double alpha, double log_M)
+double window(const tkdv_point &pt, int proposal, int precision, double alpha, double log_M, double extra = 0.0)
 {
     const int K = pt.K, N = 4 * K;
     const double eps_x = 1e-5;  // bound on |x^_fast - x^_exact|_2 (normals + projection)
@@ -206,35 +192,41 @@ double window(const tkdv_point &pt, int proposal, int precision, double alpha, d
     const double err_H3term = c3coef * err_S3;
     // t = sum k^2 s_k: |dt| <= 2 K^2 |x^| |dx^| plus rounding
     const double err_t = 4.0 * eps_x * K * K + 64.0 * K * K * 0x1p-24;
-    const double slope = pt.beta_p / ((double)K * K) * (1.0 + (proposal == TKDV_PROP_SIGMA ? alpha : 0.0));
+    const double slope = pt.beta_p / ((double)K * K) * (1.0 + (proposal != TKDV_PROP_UNIFORM ? alpha : 0.0));
     const double err_tterm = slope * err_t;
     // FP32 rounding of the terms of log a (each bounded in magnitude) and of log U
     const double mag = pt.beta_p + K * std::log1p(alpha * pt.beta_p / K) + std::fabs(log_M) +
                        c3coef * umax * (N / 2.0);
     const double err_round = 16.0 * 0x1p-24 * (mag + 30.0);
-    return 2.0 * (err_H3term + err_tterm + err_round) + 1e-6;
+    return 2.0 * (err_H3term + err_tterm + err_round + extra) + 1e-6;
 }
 
+void set_window(DevPoint &d, double tau)
+{
+    d.tau = (float)tau;
+    // rounded inwards so that the FP32 products stay inside the exact window
+    d.e_lo = (float)std::exp(-tau) * (1.0f - 0x1p-22f);
+    d.e_hi = (float)std::exp(tau) * (1.0f + 0x1p-22f);
+}
+
+// The mixture keeps the Sigma component (its standard deviations and alpha*).
 void fill_devpoint(DevPoint &d, const tkdv_point &pt, const tkdv_plan &pl, int proposal, int precision)
 {
     std::memset(&d, 0, sizeof(d));
     const int K = pt.K, N = 4 * K;
+    const bool sig = proposal != TKDV_PROP_UNIFORM;
     for (int k = 0; k < TKDV_KMAX; ++k) {
-        const double s2 = (k < K && proposal == TKDV_PROP_SIGMA) ? pl.sigma2[k] : 1.0;
+        const double s2 = (k < K && sig) ? pl.sigma2[k] : 1.0;
         d.sig64[k] = std::sqrt(s2);
         d.sig[k] = (float)d.sig64[k];
     }
     const double amp = std::sqrt(2.0 * pt.E0 / kPi);
     d.neg_bp_K2 = (float)(-pt.beta_p / ((double)K * K));
     d.c3coef = (float)(pt.beta_p * pt.c32 / (pt.E0 * K * K) * (kPi / (3.0 * N)) * amp * amp * amp);
-    d.g_coef = proposal == TKDV_PROP_SIGMA ? (float)(pl.alpha_star * pt.beta_p / ((double)K * K * K)) : 0.0f;
-    d.Kf = proposal == TKDV_PROP_SIGMA ? (float)K : 0.0f;
+    d.g_coef = sig ? (float)(pl.alpha_star * pt.beta_p / ((double)K * K * K)) : 0.0f;
+    d.Kf = sig ? (float)K : 0.0f;
     d.log_M = (float)pl.log_M;
-    const double tau = window(pt, proposal, precision, pl.alpha_star, pl.log_M);
-    d.tau = (float)tau;
-    // rounded inwards so that the FP32 products stay inside the exact window
-    d.e_lo = (float)std::exp(-tau) * (1.0f - 0x1p-22f);
-    d.e_hi = (float)std::exp(tau) * (1.0f + 0x1p-22f);
+    set_window(d, window(pt, proposal, precision, pl.alpha_star, pl.log_M));
     d.K = K;
     d.proposal = proposal;
     d.point_id = pt.point_id;
@@ -308,9 +300,13 @@ tkdv_status run(tkdv_ctx *ctx, Call &call, int precision, int proposal, float *d
     a.dbg_s3 = dbg_s3;
     a.dbg_log_a = dbg_la;
     a.dbg_log_u = dbg_lu;
+    if (proposal == TKDV_PROP_MIXTURE) {
+        a.mix = reinterpret_cast<const DevMix *>(ctx->mix.p);
+        a.mix_tab = reinterpret_cast<const char *>(ctx->mix_tab.p);
+    }
     const int *d_plist = reinterpret_cast<const int *>(ctx->plist.p);
     std::memset(&ctx->timing, 0, sizeof(ctx->timing));
-    ctx->timing.decide_block = kBlock;
+    ctx->timing.decide_block = proposal == TKDV_PROP_MIXTURE ? kMixBlock : kBlock;
     HIP_TRY(ctx, hipEventRecord(ctx->ev[0], st));
     for (int ki = 0; ki < 4; ++ki) {
         if (call.plist_n[ki] == 0) continue;
@@ -319,8 +315,12 @@ tkdv_status run(tkdv_ctx *ctx, Call &call, int precision, int proposal, float *d
         a.phi_lo = ctx->phi_lo[ki].p;
         unsigned long long tiles = 0;
         for (int q = 0; q < call.plist_n[ki]; ++q) tiles += call.pts[call.plist[call.plist_off[ki] + q]].n_tiles;
-        HIP_TRY(ctx, launch_decide(K, precision, proposal, a, d_plist + call.plist_off[ki], call.plist_n[ki],
-                                   ctx->n_cu, tiles, st, &ctx->timing.decide_grid));
+        if (proposal == TKDV_PROP_MIXTURE)
+            HIP_TRY(ctx, launch_decide_mix(K, precision, a, d_plist + call.plist_off[ki], call.plist_n[ki],
+                                           ctx->n_cu, tiles, st, &ctx->timing.decide_grid));
+        else
+            HIP_TRY(ctx, launch_decide(K, precision, proposal, a, d_plist + call.plist_off[ki], call.plist_n[ki],
+                                       ctx->n_cu, tiles, st, &ctx->timing.decide_grid));
         ctx->timing.decide_launches++;
     }
     HIP_TRY(ctx, hipEventRecord(ctx->ev[1], st));
@@ -429,7 +429,9 @@ tkdv_status prepare(tkdv_ctx *ctx, Call &call, int n_points, const tkdv_point *p
                     uint64_t i0)
 {
     if (n_points < 1) return set_err(ctx, TKDV_E_ARG, "n_points must be >= 1");
-    if (proposal != TKDV_PROP_UNIFORM && proposal != TKDV_PROP_SIGMA) return set_err(ctx, TKDV_E_ARG, "bad proposal");
+    if (proposal != TKDV_PROP_UNIFORM && proposal != TKDV_PROP_SIGMA && proposal != TKDV_PROP_MIXTURE)
+        return set_err(ctx, TKDV_E_ARG, "bad proposal");
+    if (proposal == TKDV_PROP_MIXTURE && !plans) return set_err(ctx, TKDV_E_ARG, "the mixture needs its plan");
     if (precision < TKDV_FP32 || precision > TKDV_BF16X3) return set_err(ctx, TKDV_E_ARG, "bad precision");
     if (mode != TKDV_COUNT_PROPOSALS && mode != TKDV_COUNT_ACCEPTED) return set_err(ctx, TKDV_E_ARG, "bad mode");
     if (mode == TKDV_COUNT_ACCEPTED && max_proposals == 0)
@@ -484,6 +486,32 @@ tkdv_status prepare(tkdv_ctx *ctx, Call &call, int n_points, const tkdv_point *p
     return TKDV_OK;
 }
 
+// Learned proposal: host FP64 set-up of the point's constants and tables,
+// uploaded to the context, and the point's decision window widened by the
+// error bound of the FP32 log q_mix.
+tkdv_status prepare_mixture(tkdv_ctx *ctx, Call &call, const tkdv_point &pt, const tkdv_plan &plan,
+                            const tkdv_mixture *mix, int precision, hipStream_t st)
+{
+    if (!mix) return set_err(ctx, TKDV_E_ARG, "mixture is NULL");
+    if (pt.K == 64) return set_err(ctx, TKDV_E_UNSUPPORTED, "the mixture sampler supports K in {8,16,32}");
+    if (plan.proposal != TKDV_PROP_MIXTURE) return set_err(ctx, TKDV_E_ARG, "plan was made for another proposal");
+    MixHost mh;
+    if (mh.init(pt, plan, *mix) != TKDV_OK) return set_err(ctx, TKDV_E_ARG, "invalid mixture parameters");
+    if (!(mh.kappa() <= 1e5)) return set_err(ctx, TKDV_E_ARG, "mixture too ill-conditioned (lambda_max(G) > 1e5)");
+    std::vector<DevMix> dm(1);
+    std::vector<uint8_t> tab;
+    mix_device_data(mh, dm[0], tab);
+    dm[0].tab_off = 0;
+    HIP_TRY(ctx, ensure(ctx->mix, sizeof(DevMix)));
+    HIP_TRY(ctx, ensure(ctx->mix_tab, tab.size()));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->mix.p, dm.data(), sizeof(DevMix), hipMemcpyHostToDevice, st));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->mix_tab.p, tab.data(), tab.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));  // the host vectors go out of scope
+    set_window(call.pts[0], window(pt, TKDV_PROP_MIXTURE, precision, plan.alpha_star, plan.log_M,
+                                   mix_window_extra(mh, precision)));
+    return TKDV_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -520,7 +548,8 @@ tkdv_status tkdv_destroy(tkdv_ctx *ctx)
     if (!ctx) return TKDV_OK;
     (void)hipSetDevice(ctx->device);
     DevBuf *bufs[] = {&ctx->bitmap, &ctx->defer_list, &ctx->defer_count, &ctx->counters, &ctx->points,
-                      &ctx->seg_cnt, &ctx->seg_base, &ctx->seg_stats, &ctx->results, &ctx->plist};
+                      &ctx->seg_cnt, &ctx->seg_base, &ctx->seg_stats, &ctx->results, &ctx->plist,
+                      &ctx->mix, &ctx->mix_tab};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (int i = 0; i < 4; ++i) {
@@ -624,6 +653,81 @@ tkdv_status tkdv_eval_proposals(tkdv_ctx *ctx, const tkdv_point *pt, tkdv_propos
         HIP_TRY(ctx, hipStreamSynchronize((hipStream_t)stream));
     }
     return TKDV_OK;
+}
+
+tkdv_status tkdv_sample_mixture(tkdv_ctx *ctx, const tkdv_point *pt, const tkdv_plan *mix_plan,
+                                const tkdv_mixture *mix, uint64_t n, tkdv_count_mode mode,
+                                uint64_t max_proposals, tkdv_precision precision, float *d_xhat,
+                                uint64_t *d_index, uint64_t capacity, tkdv_stats *h_stats, void *stream)
+{
+    if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");
+    if (!pt || !h_stats || !mix_plan || !mix) return set_err(ctx, TKDV_E_ARG, "NULL argument");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (n == 0) {
+        std::memset(h_stats, 0, sizeof(*h_stats));
+        tkdv_status s = check_point(ctx, *pt);
+        if (s != TKDV_OK) return s;
+        const double umax = std::sqrt(2.0 * pt->K * pt->E0 / kPi);
+        h_stats->hist_lo = -umax;
+        h_stats->hist_hi = umax;
+        h_stats->max_log_a = -INFINITY;
+        return TKDV_OK;
+    }
+    Call call;
+    const uint64_t cap = capacity, off = 0;
+    tkdv_status s = prepare(ctx, call, 1, pt, TKDV_PROP_MIXTURE, mix_plan, &n, mode, max_proposals, precision, &cap,
+                            &off, 2 * (uint64_t)pt->K, 0);
+    if (s != TKDV_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    s = prepare_mixture(ctx, call, *pt, *mix_plan, mix, precision, st);
+    if (s != TKDV_OK) return s;
+    std::vector<PointResult> res;
+    std::vector<DevCounters> cnt;
+    s = run(ctx, call, precision, TKDV_PROP_MIXTURE, d_xhat, reinterpret_cast<unsigned long long *>(d_index), st,
+            &res, &cnt, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, true);
+    if (s != TKDV_OK) return s;
+    fill_stats(*h_stats, call.pts[0], res[0], cnt[0], mode);
+    return TKDV_OK;
+}
+
+tkdv_status tkdv_eval_mixture(tkdv_ctx *ctx, const tkdv_point *pt, const tkdv_plan *mix_plan,
+                              const tkdv_mixture *mix, uint64_t i0, uint64_t n, tkdv_precision precision,
+                              float *d_xhat, float *d_t, float *d_s3, float *d_log_a, float *d_log_u,
+                              uint8_t *d_accept, void *stream)
+{
+    if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");
+    if (!pt || !mix_plan || !mix) return set_err(ctx, TKDV_E_ARG, "NULL argument");
+    if (n == 0) return TKDV_OK;
+    const int any_dbg = (d_t != nullptr) + (d_s3 != nullptr) + (d_log_a != nullptr) + (d_log_u != nullptr);
+    if (any_dbg != 0 && any_dbg != 4)
+        return set_err(ctx, TKDV_E_ARG, "d_t, d_s3, d_log_a and d_log_u must be all set or all NULL");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    Call call;
+    const uint64_t zero = 0;
+    tkdv_status s = prepare(ctx, call, 1, pt, TKDV_PROP_MIXTURE, mix_plan, &n, TKDV_COUNT_PROPOSALS, 0, precision,
+                            &zero, &zero, 2 * (uint64_t)pt->K, i0);
+    if (s != TKDV_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    s = prepare_mixture(ctx, call, *pt, *mix_plan, mix, precision, st);
+    if (s != TKDV_OK) return s;
+    s = run(ctx, call, precision, TKDV_PROP_MIXTURE, nullptr, nullptr, st, nullptr, nullptr, nullptr, d_xhat, d_t,
+            d_s3, d_log_a, d_log_u, false);
+    if (s != TKDV_OK) return s;
+    if (d_accept) {
+        HIP_TRY(ctx, launch_bits_to_bytes(reinterpret_cast<const uint32_t *>(ctx->bitmap.p), n, d_accept, st));
+        HIP_TRY(ctx, hipStreamSynchronize(st));
+    }
+    return TKDV_OK;
+}
+
+double tkdv_mixture_window(const tkdv_point *pt, const tkdv_plan *mix_plan, const tkdv_mixture *mix,
+                           tkdv_precision precision)
+{
+    if (!pt || !mix_plan || !mix) return NAN;
+    MixHost mh;
+    if (mh.init(*pt, *mix_plan, *mix) != TKDV_OK) return NAN;
+    return window(*pt, TKDV_PROP_MIXTURE, precision, mix_plan->alpha_star, mix_plan->log_M,
+                  mix_window_extra(mh, precision));
 }
 
 double tkdv_decision_window(const tkdv_point *pt, tkdv_proposal proposal, tkdv_precision precision)

@@ -19,7 +19,7 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
 enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_BF16X3 = 2 };
-enum { PROP_UNIFORM = 0, PROP_SIGMA = 1 };
+enum { PROP_UNIFORM = 0, PROP_SIGMA = 1, PROP_MIXTURE = 2 };
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): per round two 32x32->64 products of
@@ -157,13 +157,31 @@ __host__ __device__ constexpr int bf16_table_bytes() { return (K / 8) * (K / 8) 
 template <int K>
 __host__ __device__ constexpr int f32_table_bytes() { return (K / 8) * (K / 4) * kWave * 16; }
 
+// BF16 operands of this lane's coordinates: hi = RNE(x), lo = RNE(x - hi).
+template <int K, int PREC>
+__device__ __forceinline__ void split_bf16(const float (&x)[K], bf16x8 (&bh)[K / 8], bf16x8 (&bl)[K / 8])
+{
+#pragma unroll
+    for (int s = 0; s < K / 8; ++s) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float v = x[8 * s + e];
+            const __bf16 hv = (__bf16)v;
+            bh[s][e] = hv;
+            if constexpr (PREC == PREC_BF16X3) bl[s][e] = (__bf16)(v - (float)hv);
+        }
+    }
+}
+
 // Sum over this lane's grid values of u~^3 (u~ = unscaled synthesis), with
-// the products in the requested arithmetic.  TWO_CHAINS accumulates even and
-// odd k-steps of the BF16 paths in separate registers (two independent
-// dependency chains on the matrix pipe), summed before the cube.
+// the products in the requested arithmetic (FP32 reads x, BF16 reads bh/bl).
+// TWO_CHAINS accumulates even and odd k-steps of the BF16 paths in separate
+// registers (two independent dependency chains on the matrix pipe), summed
+// before the cube.
 template <int K, int PREC, bool TWO_CHAINS = false>
-__device__ __forceinline__ float synth_cube_sum(const float (&x)[K], const char *lds_hi,
-                                                const char *lds_lo, int lane)
+__device__ __forceinline__ float cube_sum_ops(const float (&x)[K], const bf16x8 (&bh)[K / 8],
+                                              const bf16x8 (&bl)[K / 8], const char *lds_hi,
+                                              const char *lds_lo, int lane)
 {
     float s3 = 0.0f;
     if constexpr (PREC == PREC_FP32) {
@@ -183,17 +201,6 @@ __device__ __forceinline__ float synth_cube_sum(const float (&x)[K], const char 
             for (int v = 0; v < 16; ++v) s3 = __builtin_fmaf(acc[v] * acc[v], acc[v], s3);
         }
     } else {
-        bf16x8 bh[K / 8], bl[K / 8];
-#pragma unroll
-        for (int s = 0; s < K / 8; ++s) {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float v = x[8 * s + e];
-                const __bf16 hv = (__bf16)v;
-                bh[s][e] = hv;
-                if constexpr (PREC == PREC_BF16X3) bl[s][e] = (__bf16)(v - (float)hv);
-            }
-        }
         const bf16x8 *th = reinterpret_cast<const bf16x8 *>(lds_hi);
         const bf16x8 *tl = reinterpret_cast<const bf16x8 *>(lds_lo);
         // at K = 64 a full unroll keeps every grid tile's operands live (spills)
@@ -223,6 +230,15 @@ __device__ __forceinline__ float synth_cube_sum(const float (&x)[K], const char 
     return s3;
 }
 
+template <int K, int PREC, bool TWO_CHAINS = false>
+__device__ __forceinline__ float synth_cube_sum(const float (&x)[K], const char *lds_hi,
+                                                const char *lds_lo, int lane)
+{
+    bf16x8 bh[K / 8], bl[K / 8];
+    if constexpr (PREC != PREC_FP32) split_bf16<K, PREC>(x, bh, bl);
+    return cube_sum_ops<K, PREC, TWO_CHAINS>(x, bh, bl, lds_hi, lds_lo, lane);
+}
+
 // log a = log f/(M g) in FP32 from t and S3 = sum_j u~_j^3 (both lanes identical).
 template <int PROP>
 __device__ __forceinline__ float log_a_f32(const DevPoint &P, float t, float s3)
@@ -242,6 +258,151 @@ __device__ __forceinline__ unsigned int float_key(float f)
 __device__ __forceinline__ unsigned long long pack_defer(int p, uint64_t i)
 {
     return ((unsigned long long)p << 40) | (unsigned long long)i;
+}
+
+// ---------------------------------------------------------------------------
+// Learned mixture proposal
+// ---------------------------------------------------------------------------
+// Component of a proposal from its component word: -1 (g_Sigma) when w < E,
+// else j = (w - E) div B, formed in integers (one FP32 estimate, corrected
+// by one step: the estimate is within 1 of the quotient).
+__device__ __forceinline__ int mix_component(const DevMix &M, uint32_t w)
+{
+    const uint32_t d = w - M.E;
+    uint32_t j = (uint32_t)((float)d * M.invB);
+    j = j > (uint32_t)(kMixS - 1) ? (uint32_t)(kMixS - 1) : j;
+    const uint32_t prod = j * M.B;
+    if (prod > d) --j;
+    else if (d - prod >= M.B) ++j;
+    return w < M.E ? -1 : (int)j;
+}
+
+// Draw of proposal i from q_mix: this lane's K coordinates of X (words
+// 0..2K-1 as for the paper's proposal, word 2K the acceptance word, 2K+1 the
+// component word, 2K+2 and 2K+3 the pair eta), |X|^-1, t of the projected
+// point and Qa = sum over this proposal of a_c X_c^2 (unprojected).  rv
+// points to the RV table of the point (LDS or global memory).
+template <int K, bool NORMALIZE>
+__device__ __forceinline__ float gen_x_mix(const DevPoint &P, const DevMix &M, const float *rv, uint64_t i,
+                                           int half, float (&x)[K], float &t, float &Qa, uint32_t &w_acc)
+{
+    const uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32), c2 = P.point_id;
+#pragma unroll
+    for (int b = 0; b < K / 4; ++b) {
+        uint4 w = philox4x32_10(c0, c1, c2, (uint32_t)(half * (K / 4) + b), P.key0, P.key1);
+        box_muller_f32(w.x, w.y, x[4 * b + 0], x[4 * b + 1]);
+        box_muller_f32(w.z, w.w, x[4 * b + 2], x[4 * b + 3]);
+    }
+    const uint4 wl = philox4x32_10(c0, c1, c2, (uint32_t)(K / 2), P.key0, P.key1);
+    w_acc = wl.x;
+    const int comp = mix_component(M, wl.y);
+    const bool def = comp < 0;
+    float e0, e1;
+    box_muller_f32(wl.z, wl.w, e0, e1);
+    e0 = def ? 0.0f : e0;
+    e1 = def ? 0.0f : e1;
+    const float2 *row = reinterpret_cast<const float2 *>(rv + (2 * (def ? 0 : comp) + half) * (2 * K + 2));
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const float sc = def ? P.sig[j] : M.sqd[j];
+        const float2 v = row[j];
+        x[j] = __builtin_fmaf(v.x, e0, __builtin_fmaf(v.y, e1, sc * x[j]));
+    }
+    float r2 = 0.0f, tk = 0.0f, qa = 0.0f;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const float sq = x[j] * x[j];
+        r2 += sq;
+        tk = __builtin_fmaf((float)((j + 1) * (j + 1)), sq, tk);
+        qa = __builtin_fmaf(M.a[j], sq, qa);
+    }
+    r2 = r2 + xor32(r2);
+    tk = tk + xor32(tk);
+    Qa = qa + xor32(qa);
+    const float inv = __builtin_amdgcn_rsqf(r2);
+    t = tk * (inv * inv);
+    if (NORMALIZE) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) x[j] *= inv;
+    }
+    return inv;
+}
+
+// y = (R_j A V)^T X for the S shifts on the matrix cores: row tile q holds
+// rank index q, row j the shift, column the proposal (the B operand layout).
+// Row tiles share their row order, so y0[v] and y1[v] belong to one shift.
+template <int K, int PREC>
+__device__ __forceinline__ void mix_y(const float (&x)[K], const bf16x8 (&bh)[K / 8], const bf16x8 (&bl)[K / 8],
+                                      const char *yt_hi, const char *yt_lo, int lane, f32x16 &y0, f32x16 &y1)
+{
+    if constexpr (PREC == PREC_FP32) {
+        const float4 *tab = reinterpret_cast<const float4 *>(yt_hi);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            f32x16 acc = {};
+#pragma unroll
+            for (int q = 0; q < K / 4; ++q) {
+                float4 a = tab[(t * (K / 4) + q) * kWave + lane];
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, x[4 * q + 0], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, x[4 * q + 1], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, x[4 * q + 2], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, x[4 * q + 3], acc, 0, 0, 0);
+            }
+            if (t == 0) y0 = acc; else y1 = acc;
+        }
+    } else {
+        const bf16x8 *th = reinterpret_cast<const bf16x8 *>(yt_hi);
+        const bf16x8 *tl = reinterpret_cast<const bf16x8 *>(yt_lo);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            f32x16 acc = {};
+#pragma unroll
+            for (int s = 0; s < K / 8; ++s) {
+                const int idx = (t * (K / 8) + s) * kWave + lane;
+                const bf16x8 ah = th[idx];
+                if constexpr (PREC == PREC_BF16X3) {
+                    const bf16x8 al = tl[idx];
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[s], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[s], acc, 0, 0, 0);
+                }
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[s], acc, 0, 0, 0);
+            }
+            if (t == 0) y0 = acc; else y1 = acc;
+        }
+    }
+}
+
+// log q_mix in FP32 from the shifts' y, Qa = X^T A X (both unprojected: the
+// ratios r_j = qf_j/Q = 1 - y_j^T G^-1 y_j/Qa are scale free), |X|^-2 and t.
+//   ln q_net + ln(1 - eps) = c_net - K ln(Qa |X|^-2) + ln sum_j r_j^-K,
+//   ln(eps g_Sigma) = c_g - K ln(1 + alpha beta' t/K^3).
+// The sum is taken relative to the smallest r_j of the proposal (all terms
+// <= 1, the largest exactly 1).  Both lanes of a proposal return the same.
+__device__ __forceinline__ float mix_log_q_f32(const DevPoint &P, const DevMix &M, const f32x16 &y0,
+                                               const f32x16 &y1, float Qa, float inv2, float t, float Kf)
+{
+    const float invQ = __builtin_amdgcn_rcpf(Qa);
+    float l[16];
+    float lmin = INFINITY;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const float a0 = y0[v], a1 = y1[v];
+        const float t1 = __builtin_fmaf(M.g01x2, a1, M.g00 * a0);
+        const float quad = __builtin_fmaf(a0, t1, (M.g11 * a1) * a1);
+        const float r = fmaxf(__builtin_fmaf(-quad, invQ, 1.0f), 1e-30f);
+        l[v] = log2_hw(r);
+        lmin = fminf(lmin, l[v]);
+    }
+    lmin = fminf(lmin, xor32(lmin));
+    float sum = 0.0f;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) sum += __builtin_amdgcn_exp2f((lmin - l[v]) * Kf);
+    sum = sum + xor32(sum);
+    const float ln2 = 0.69314718055994531f;
+    const float LN = M.c_net + ln2 * (log2_hw(sum) - Kf * (lmin + log2_hw(Qa * inv2)));
+    const float LG = M.c_g - Kf * log1p_f32(P.g_coef * t);
+    const float hi = fmaxf(LN, LG);
+    return hi + log1p_f32(__builtin_amdgcn_exp2f(-fabsf(LN - LG) * 1.4426950408889634f));
 }
 
 }  // namespace tkdv

@@ -16,6 +16,8 @@ constexpr int kClaimTiles = 64;    // tiles claimed per work-queue claim (2048 p
                                    // lane c keeps the accept word of tile c
 constexpr int kSegWords = 2048;    // bitmap words per statistics segment (65536 proposals)
 constexpr int kNBins = TKDV_NBINS;
+constexpr int kMixBlock = 1024;    // threads per workgroup of the mixture sampling kernel
+constexpr int kMixS = TKDV_MIX_S;  // xi-shifts of the learned mixture
 
 // Per-point constants, laid out for wave-uniform (scalar) loads.
 struct DevPoint {
@@ -49,6 +51,44 @@ struct DevPoint {
     uint64_t capacity;       // output rows available to this point
     uint64_t row_stride;     // floats between consecutive output rows
 };
+
+// Per-point constants of the learned mixture proposal (see tkdv_mixture).
+// Its tables live at tab_off in the mixture table buffer:
+//   y tables  B[(q, j)][c] = a_c (R_j V_q)_c as matrix-core A operands, row
+//             tile q (rank index), row j (shift) -- BF16 hi, BF16 lo, FP32;
+//   RV table  (R_j V)_c for shift j, half h, coordinate k of that half:
+//             float2 at ((2 j + h) (2K + 2) + 2 k) floats (rows padded by
+//             two floats to spread the shifts over the LDS banks).
+struct DevMix {
+    float sqd[TKDV_KMAX];    // sqrt(d_k)
+    float a[TKDV_KMAX];      // 1/d_k
+    float g00, g01x2, g11;   // (I + V^T D^-1 V)^-1: entries 00, 2*01, 11
+    float c_net;             // ln(1 - eps) - ln|L0|/2 - ln S
+    float c_g;               // ln eps + sum_k ln(1 + alpha beta' k^2/K^3)
+    float invB;              // 1/B rounded to FP32
+    uint32_t E, B;           // component word: w < E -> g_Sigma, else j = (w - E) div B
+    // FP64 re-decision
+    double a64[TKDV_KMAX], sqd64[TKDV_KMAX];
+    double V64[2 * TKDV_KMAX][TKDV_MIX_R];
+    double gi64[TKDV_MIX_R][TKDV_MIX_R];
+    double cs64[kMixS], sn64[kMixS];  // cos, sin of 2 pi m/S
+    double logdetL0, lng, log_eps, log_1m_eps;
+    uint64_t tab_off;        // bytes
+    uint64_t pad;
+};
+
+template <int K>
+constexpr int mix_ytab_bf16_bytes() { return 2 * (K / 8) * kWave * 16; }
+template <int K>
+constexpr int mix_ytab_f32_bytes() { return 2 * (K / 4) * kWave * 16; }
+template <int K>
+constexpr int mix_rv_bytes() { return kMixS * 2 * (2 * K + 2) * 4; }
+// per point: y hi, y lo, y f32, RV
+template <int K>
+constexpr int mix_point_bytes()
+{
+    return 2 * mix_ytab_bf16_bytes<K>() + mix_ytab_f32_bytes<K>() + mix_rv_bytes<K>();
+}
 
 // Device-side counters per point (zeroed before every launch sequence).
 struct DevCounters {
@@ -90,6 +130,8 @@ struct KernelArgs {
     unsigned long long defer_cap;
     const void *phi_hi;    // BF16 fragment table (hi), or FP32 fragment table
     const void *phi_lo;    // BF16 fragment table (lo)
+    const DevMix *mix;     // per point (learned proposal only)
+    const char *mix_tab;   // mixture tables (learned proposal only)
     // optional per-proposal outputs of the evaluation entry point (point 0 only)
     float *dbg_xhat, *dbg_t, *dbg_s3, *dbg_log_a, *dbg_log_u;
 };

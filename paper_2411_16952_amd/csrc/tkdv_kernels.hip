@@ -50,6 +50,35 @@ __device__ __forceinline__ unsigned long long load_relaxed(const unsigned long l
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Lane 0's value, as a wave-uniform (scalar) value.  The claim loops branch
+// on it: a per-lane copy would make their exits divergent for the compiler,
+// which may then split a loop so that lanes wait on a lane that has left it.
+__device__ __forceinline__ unsigned long long bcast_lane0(unsigned long long v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Claim kClaimTiles tiles of point C's queue for this wave: every lane issues
+// the atomic (lane 0 adds, the others add 0) and lane 0's old value is taken,
+// so no lane-divergent region sits next to the loop back-edge (the compiler
+// may otherwise thread lanes 1-63 past lane 0's region to the broadcast and
+// split the wave).  ~0 when the point's accepted-sample target is met.
+__device__ __forceinline__ unsigned long long claim_tiles(const DevPoint &P, DevCounters *C, int lane)
+{
+    const bool open = P.target == ~0ull || bcast_lane0(load_relaxed(&C->accepted)) < P.target;
+    const unsigned long long old =
+        atomicAdd(&C->next_tile, (open && lane == 0) ? (unsigned long long)kClaimTiles : 0ull);
+    return open ? bcast_lane0(old) : ~0ull;
+}
+
+// Per-wave counter update with the same structure: lane 0's (wave-uniform) value.
+__device__ __forceinline__ void add_lane0(unsigned long long *ctr, unsigned long long v, int lane)
+{
+    if (bcast_lane0(v) != 0ull) atomicAdd(ctr, lane == 0 ? v : 0ull);
+}
+
 static_assert(kClaimTiles == kWave, "one accept word per lane per claim");
 
 template <int K, int PREC>
@@ -87,13 +116,7 @@ __global__ void __launch_bounds__(kBlock) k_decide(KernelArgs a, const int *plis
         const int p = __builtin_amdgcn_readfirstlane(plist[cursor]);
         const DevPoint &P = a.pts[p];
         DevCounters *C = a.cnt + p;
-        unsigned long long base = ~0ull;
-        if (lane == 0) {
-            // the accepted-count test only matters in accepted-count mode
-            if (P.target == ~0ull || load_relaxed(&C->accepted) < P.target)
-                base = atomicAdd(&C->next_tile, (unsigned long long)kClaimTiles);
-        }
-        base = __shfl(base, 0, 64);
+        const unsigned long long base = claim_tiles(P, C, lane);
         if (base >= P.n_tiles) {
             cursor = (cursor + 1 == n_plist) ? 0 : cursor + 1;
             ++misses;
@@ -146,9 +169,7 @@ __global__ void __launch_bounds__(kBlock) k_decide(KernelArgs a, const int *plis
             }
             if (bdef) {
                 const unsigned long long nd = __popcll(bdef);
-                unsigned long long slot = 0;
-                if (lane == 0) slot = atomicAdd(a.defer_count, nd);
-                slot = __shfl(slot, 0, 64);
+                const unsigned long long slot = bcast_lane0(atomicAdd(a.defer_count, lane == 0 ? nd : 0ull));
                 if (defer) {
                     const unsigned long long pos = slot + __popcll(bdef & ((1ull << lane) - 1ull));
                     if (pos < a.defer_cap) a.defer_list[pos] = pack_defer(p, i);
@@ -160,11 +181,147 @@ __global__ void __launch_bounds__(kBlock) k_decide(KernelArgs a, const int *plis
         if (base + lane < P.n_tiles) a.bitmap[P.bm_off + base + lane] = my_word;
         const unsigned long long viol = wave_sum_u64(n_viol);
         max_la = wave_max_f32(max_la);
-        if (lane == 0) {
-            if (n_acc) atomicAdd(&C->accepted, n_acc);
-            if (viol) atomicAdd(&C->violations, viol);
-            if (n_def) atomicAdd(&C->deferred, n_def);
-            if (max_la > -INFINITY) atomicMax(&C->max_log_a_key, float_key(max_la));
+        add_lane0(&C->accepted, n_acc, lane);
+        add_lane0(&C->violations, viol, lane);
+        add_lane0(&C->deferred, n_def, lane);
+        if (__builtin_amdgcn_readfirstlane(__float_as_uint(max_la)) != __float_as_uint(-INFINITY))
+            atomicMax(&C->max_log_a_key, lane == 0 ? float_key(max_la) : 0u);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_decide_mix: the sampler with the learned mixture proposal.  Workgroups
+// visit the points in turn (starting at their own index) and stage the
+// point's shift tables in LDS next to the synthesis tables; the waves of a
+// workgroup claim tiles of that point until its queue is empty.  Per
+// proposal, on top of the paper's steps: the component draw, y = (R_j A V)^T X
+// for the S shifts on the matrix cores and log q_mix (mix_log_q_f32).
+// ---------------------------------------------------------------------------
+template <int K, int PREC>
+__host__ __device__ constexpr int mix_ytab_lds_bytes()
+{
+    return PREC == PREC_FP32 ? mix_ytab_f32_bytes<K>() : (PREC == PREC_BF16X3 ? 2 : 1) * mix_ytab_bf16_bytes<K>();
+}
+template <int K, int PREC>
+__host__ __device__ constexpr int decide_mix_lds_bytes()
+{
+    return decide_lds_bytes<K, PREC>() + mix_ytab_lds_bytes<K, PREC>() + mix_rv_bytes<K>();
+}
+
+template <int K, int PREC>
+__global__ void __launch_bounds__(kMixBlock) k_decide_mix(KernelArgs a, const int *plist, int n_plist)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    constexpr int tab = PREC == PREC_FP32 ? f32_table_bytes<K>() : bf16_table_bytes<K>();
+    constexpr int phi_bytes = decide_lds_bytes<K, PREC>();
+    constexpr int yb = PREC == PREC_FP32 ? mix_ytab_f32_bytes<K>() : mix_ytab_bf16_bytes<K>();
+    constexpr int ytab_bytes = mix_ytab_lds_bytes<K, PREC>();
+    constexpr int rv_bytes = mix_rv_bytes<K>();
+    static_assert(phi_bytes % 16 == 0 && ytab_bytes % 16 == 0 && rv_bytes % 16 == 0, "16-byte staging");
+    {
+        const uint4 *s0 = reinterpret_cast<const uint4 *>(a.phi_hi);
+        uint4 *d = reinterpret_cast<uint4 *>(lds);
+        for (int v = threadIdx.x; v < tab / 16; v += kMixBlock) d[v] = s0[v];
+        if constexpr (PREC == PREC_BF16X3) {
+            const uint4 *s1 = reinterpret_cast<const uint4 *>(a.phi_lo);
+            for (int v = threadIdx.x; v < tab / 16; v += kMixBlock) d[tab / 16 + v] = s1[v];
+        }
+    }
+    const char *lds_hi = lds;
+    const char *lds_lo = lds + tab;
+    const char *y_hi = lds + phi_bytes;
+    const char *y_lo = lds + phi_bytes + yb;
+    const float *rv = reinterpret_cast<const float *>(lds + phi_bytes + ytab_bytes);
+    const int lane = threadIdx.x & 63, half = lane >> 5, pl = lane & 31;
+    const float Kf = (float)K;
+    for (int q = 0; q < n_plist; ++q) {
+        const int p = __builtin_amdgcn_readfirstlane(plist[(blockIdx.x + q) % n_plist]);
+        const DevPoint &P = a.pts[p];
+        const DevMix &M = a.mix[p];
+        DevCounters *C = a.cnt + p;
+        __syncthreads();  // every wave is done with the previous point's tables
+        {
+            // y tables of the requested arithmetic, then the RV table
+            const char *src = a.mix_tab + M.tab_off;
+            const uint4 *sy = reinterpret_cast<const uint4 *>(
+                src + (PREC == PREC_FP32 ? 2 * mix_ytab_bf16_bytes<K>() : 0));
+            const uint4 *srv = reinterpret_cast<const uint4 *>(
+                src + 2 * mix_ytab_bf16_bytes<K>() + mix_ytab_f32_bytes<K>());
+            uint4 *dy = reinterpret_cast<uint4 *>(lds + phi_bytes);
+            uint4 *drv = reinterpret_cast<uint4 *>(lds + phi_bytes + ytab_bytes);
+            for (int v = threadIdx.x; v < ytab_bytes / 16; v += kMixBlock) dy[v] = sy[v];
+            for (int v = threadIdx.x; v < rv_bytes / 16; v += kMixBlock) drv[v] = srv[v];
+        }
+        __syncthreads();
+        while (true) {
+            const unsigned long long base = claim_tiles(P, C, lane);
+            if (base >= P.n_tiles) break;  // scalar branch
+            unsigned long long n_acc = 0, n_def = 0;
+            unsigned int n_viol = 0;
+            float max_la = -INFINITY;
+            uint32_t my_word = 0u;
+            for (int c = 0; c < kClaimTiles; ++c) {
+                const unsigned long long tile = base + c;
+                if (tile >= P.n_tiles) break;
+                const unsigned long long local = tile * kTile + pl;
+                const bool valid = local < P.n;
+                const uint64_t i = P.i0 + local;
+                float x[K];
+                float t, Qa;
+                uint32_t w_acc;
+                const float inv = gen_x_mix<K, false>(P, M, rv, i, half, x, t, Qa, w_acc);
+                if (a.dbg_xhat && valid) {
+#pragma unroll
+                    for (int j = 0; j < K; ++j) a.dbg_xhat[local * (2 * K) + half * K + j] = x[j] * inv;
+                }
+                bf16x8 bh[K / 8], bl[K / 8];
+                if constexpr (PREC != PREC_FP32) split_bf16<K, PREC>(x, bh, bl);
+                const float s3l = cube_sum_ops<K, PREC>(x, bh, bl, lds_hi, lds_lo, lane);
+                const float s3 = (s3l + xor32(s3l)) * (inv * inv * inv);
+                f32x16 y0, y1;
+                mix_y<K, PREC>(x, bh, bl, y_hi, y_lo, lane, y0, y1);
+                const float lq = mix_log_q_f32(P, M, y0, y1, Qa, inv * inv, t, Kf);
+                const float lf = __builtin_fmaf(P.neg_bp_K2, t, P.c3coef * s3);
+                const float la = (lf - lq) - P.log_M;
+                const float U = __builtin_fmaf((float)w_acc, 2.3283064365386963e-10f, 1.1641532182693481e-10f);
+                const float alin = __builtin_amdgcn_exp2f(la * 1.4426950408889634f);
+                const float lo_edge = alin * P.e_lo, hi_edge = alin * P.e_hi;
+                const bool mine = valid && half == 0;
+                const bool defer = mine && U >= lo_edge && U < hi_edge;
+                const bool accept = mine && U < lo_edge;
+                const unsigned long long bacc = __ballot(accept);
+                const unsigned long long bdef = __ballot(defer);
+                if (lane == c) my_word = (uint32_t)bacc;
+                n_acc += __popcll(bacc);
+                if (mine) {
+                    n_viol += la > 0.0f ? 1u : 0u;
+                    max_la = fmaxf(max_la, la);
+                    if (a.dbg_t) {
+                        a.dbg_t[local] = t;
+                        a.dbg_s3[local] = s3;
+                        a.dbg_log_a[local] = la;
+                        a.dbg_log_u[local] = log_u_word(w_acc);
+                    }
+                }
+                if (bdef) {
+                    const unsigned long long nd = __popcll(bdef);
+                    const unsigned long long slot =
+                        bcast_lane0(atomicAdd(a.defer_count, lane == 0 ? nd : 0ull));
+                    if (defer) {
+                        const unsigned long long pos = slot + __popcll(bdef & ((1ull << lane) - 1ull));
+                        if (pos < a.defer_cap) a.defer_list[pos] = pack_defer(p, i);
+                    }
+                    n_def += nd;
+                }
+            }
+            if (base + lane < P.n_tiles) a.bitmap[P.bm_off + base + lane] = my_word;
+            const unsigned long long viol = wave_sum_u64(n_viol);
+            max_la = wave_max_f32(max_la);
+            add_lane0(&C->accepted, n_acc, lane);
+            add_lane0(&C->violations, viol, lane);
+            add_lane0(&C->deferred, n_def, lane);
+            if (__builtin_amdgcn_readfirstlane(__float_as_uint(max_la)) != __float_as_uint(-INFINITY))
+                atomicMax(&C->max_log_a_key, lane == 0 ? float_key(max_la) : 0u);
         }
     }
 }
@@ -174,10 +331,11 @@ __global__ void __launch_bounds__(kBlock) k_decide(KernelArgs a, const int *plis
 // normals from the same words, X = Sigma^{1/2} z, X^ = X/|X|, H2 by Parseval,
 // H3 by the double sum, log f/(M g) = -beta H + K log(1 + alpha beta' t/K^3) - log M.
 // ---------------------------------------------------------------------------
-__device__ void fp64_eval(const DevPoint &P, uint64_t i, double &log_a, double &log_u)
+// Normals z (words 0..2K-1 by Box-Muller pairs) and the last Philox block
+// (words 2K..2K+3) of proposal i, in FP64.
+__device__ uint4 fp64_normals(const DevPoint &P, uint64_t i, double *x)
 {
     const int K = P.K;
-    double x[2 * TKDV_KMAX];
     const uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32);
     const double pi = 3.14159265358979323846;
     for (int b = 0; b < K / 2; ++b) {
@@ -192,17 +350,27 @@ __device__ void fp64_eval(const DevPoint &P, uint64_t i, double &log_a, double &
             x[4 * b + q + 1] = r * sin(th);
         }
     }
-    const uint32_t wa = philox4x32_10(c0, c1, P.point_id, (uint32_t)(K / 2), P.key0, P.key1).x;
-    log_u = log(((double)wa + 0.5) * 0x1p-32);
+    return philox4x32_10(c0, c1, P.point_id, (uint32_t)(K / 2), P.key0, P.key1);
+}
+
+// Project onto the sphere; returns t = sum k^2 s_k.
+__device__ double fp64_project(int K, double *x)
+{
     double r2 = 0.0;
-    for (int m = 0; m < 2 * K; ++m) {
-        x[m] *= P.sig64[m % K];
-        r2 += x[m] * x[m];
-    }
+    for (int m = 0; m < 2 * K; ++m) r2 += x[m] * x[m];
     const double r = sqrt(r2);
     for (int m = 0; m < 2 * K; ++m) x[m] /= r;
     double t = 0.0;
     for (int k = 1; k <= K; ++k) t += (double)k * k * (x[k - 1] * x[k - 1] + x[K + k - 1] * x[K + k - 1]);
+    return t;
+}
+
+// log f = -beta'/(E0 K^2) (H2 - c H3) at a point of the sphere, H2 = E0 t by
+// Parseval and H3 by the double sum over triads (Sec. IV.A).
+__device__ double fp64_log_f(const DevPoint &P, const double *x, double t)
+{
+    const int K = P.K;
+    const double pi = 3.14159265358979323846;
     const double s = sqrt(P.E0 / (2.0 * pi));
     double tri = 0.0;
     for (int n = 2; n <= K; ++n) {
@@ -217,9 +385,89 @@ __device__ void fp64_eval(const DevPoint &P, uint64_t i, double &log_a, double &
     }
     const double H3 = 2.0 * pi * tri;
     const double H2 = P.E0 * t;
-    double lr = -(P.beta_p / (P.E0 * (double)K * K) * (H2 - P.c32 * H3));
+    return -(P.beta_p / (P.E0 * (double)K * K) * (H2 - P.c32 * H3));
+}
+
+// FP64 evaluation of a listed proposal of the paper's sampler: normals from
+// the same words, X = Sigma^{1/2} z, X^ = X/|X|,
+// log f/(M g) = log f + K log(1 + alpha beta' t/K^3) - log M.
+__device__ void fp64_eval(const DevPoint &P, uint64_t i, double &log_a, double &log_u)
+{
+    const int K = P.K;
+    double x[2 * TKDV_KMAX];
+    const uint4 wl = fp64_normals(P, i, x);
+    log_u = log(((double)wl.x + 0.5) * 0x1p-32);
+    for (int m = 0; m < 2 * K; ++m) x[m] *= P.sig64[m % K];
+    const double t = fp64_project(K, x);
+    double lr = fp64_log_f(P, x, t);
     if (P.proposal == PROP_SIGMA) lr += K * log1p(P.alpha_star * P.beta_p * t / ((double)K * K * K));
     log_a = lr - P.log_M64;
+}
+
+// FP64 evaluation of a listed proposal of the mixture sampler: the draw of
+// gen_x_mix in FP64 (component from the same word, in integers), then
+// log q_mix with x^T L0^-1 x = e^T A e + |g|^2, g = G^-1 V^T A w, e = w - V g
+// for w = R_j^T x^ (no cancellation), and log a = log f - log q_mix - log M.
+__device__ void fp64_eval_mix(const DevPoint &P, const DevMix &M, uint64_t i, double &log_a, double &log_u)
+{
+    const int K = P.K;
+    double x[2 * TKDV_KMAX];
+    const uint4 wl = fp64_normals(P, i, x);
+    log_u = log(((double)wl.x + 0.5) * 0x1p-32);
+    const double pi = 3.14159265358979323846;
+    const int comp = wl.y < M.E ? -1 : (int)((wl.y - M.E) / M.B);
+    if (comp < 0) {
+        for (int m = 0; m < 2 * K; ++m) x[m] *= P.sig64[m % K];
+    } else {
+        const double r = sqrt(-2.0 * log(((double)wl.z + 0.5) * 0x1p-32));
+        const double th = 2.0 * pi * (((double)wl.w + 0.5) * 0x1p-32);
+        const double e0 = r * cos(th), e1 = r * sin(th);
+        for (int k = 1; k <= K; ++k) {
+            const int mi = (k * comp) & (kMixS - 1);
+            const double cs = M.cs64[mi], sn = M.sn64[mi];
+            const double vc0 = M.V64[k - 1][0], vc1 = M.V64[k - 1][1];
+            const double vs0 = M.V64[K + k - 1][0], vs1 = M.V64[K + k - 1][1];
+            const double rc0 = vc0 * cs + vs0 * sn, rc1 = vc1 * cs + vs1 * sn;
+            const double rs0 = vs0 * cs - vc0 * sn, rs1 = vs1 * cs - vc1 * sn;
+            x[k - 1] = M.sqd64[k - 1] * x[k - 1] + rc0 * e0 + rc1 * e1;
+            x[K + k - 1] = M.sqd64[k - 1] * x[K + k - 1] + rs0 * e0 + rs1 * e1;
+        }
+    }
+    const double t = fp64_project(K, x);
+    const double lf = fp64_log_f(P, x, t);
+    double lj[kMixS];
+    double mx = -INFINITY;
+    for (int j = 0; j < kMixS; ++j) {
+        double w[2 * TKDV_KMAX];
+        double y0 = 0.0, y1 = 0.0;
+        for (int k = 1; k <= K; ++k) {  // w = R_j^T x: shift by -phi_j
+            const int mi = (k * j) & (kMixS - 1);
+            const double cs = M.cs64[mi], sn = M.sn64[mi];
+            const double xc = x[k - 1], xs = x[K + k - 1];
+            w[k - 1] = xc * cs - xs * sn;
+            w[K + k - 1] = xs * cs + xc * sn;
+            const double ac = M.a64[k - 1];
+            y0 += ac * (M.V64[k - 1][0] * w[k - 1] + M.V64[K + k - 1][0] * w[K + k - 1]);
+            y1 += ac * (M.V64[k - 1][1] * w[k - 1] + M.V64[K + k - 1][1] * w[K + k - 1]);
+        }
+        const double g0 = M.gi64[0][0] * y0 + M.gi64[0][1] * y1;
+        const double g1 = M.gi64[1][0] * y0 + M.gi64[1][1] * y1;
+        double qf = g0 * g0 + g1 * g1;
+        for (int m = 0; m < 2 * K; ++m) {
+            const double e = w[m] - (M.V64[m][0] * g0 + M.V64[m][1] * g1);
+            qf += M.a64[m % K] * e * e;
+        }
+        lj[j] = -K * log(qf);
+        mx = lj[j] > mx ? lj[j] : mx;
+    }
+    double se = 0.0;
+    for (int j = 0; j < kMixS; ++j) se += exp(lj[j] - mx);
+    const double lnet = -0.5 * M.logdetL0 + mx + log(se) - log((double)kMixS);
+    const double lg = M.lng - K * log1p(P.alpha_star * P.beta_p * t / ((double)K * K * K));
+    const double A = M.log_eps + lg, B = M.log_1m_eps + lnet;
+    const double hi = A > B ? A : B;
+    const double lq = hi + log(exp(A - hi) + exp(B - hi));
+    log_a = lf - lq - P.log_M64;
 }
 
 __global__ void __launch_bounds__(kBlock) k_fixup(KernelArgs a)
@@ -233,7 +481,8 @@ __global__ void __launch_bounds__(kBlock) k_fixup(KernelArgs a)
         const uint64_t i = v & ((1ull << 40) - 1ull);
         const DevPoint &P = a.pts[p];
         double la, lu;
-        fp64_eval(P, i, la, lu);
+        if (P.proposal == PROP_MIXTURE) fp64_eval_mix(P, a.mix[p], i, la, lu);
+        else fp64_eval(P, i, la, lu);
         if (lu < la) {
             const uint64_t local = i - P.i0;
             atomicOr(&a.bitmap[P.bm_off + local / 32], 1u << (local % 32));
@@ -412,7 +661,15 @@ __global__ void __launch_bounds__(kBlock) k_materialize(KernelArgs a, const int 
                 float x[K];
                 float t;
                 uint32_t w_acc;
-                gen_xhat<K, PROP, true>(P, i, half, x, t, w_acc);
+                if constexpr (PROP == PROP_MIXTURE) {
+                    const DevMix &M = a.mix[p];
+                    const float *rvg = reinterpret_cast<const float *>(
+                        a.mix_tab + M.tab_off + 2 * mix_ytab_bf16_bytes<K>() + mix_ytab_f32_bytes<K>());
+                    float Qa;
+                    gen_x_mix<K, true>(P, M, rvg, i, half, x, t, Qa, w_acc);
+                } else {
+                    gen_xhat<K, PROP, true>(P, i, half, x, t, w_acc);
+                }
                 if (valid && r < P.capacity) {
                     if (out_xhat) {
                         float *row = out_xhat + (P.out_off + r) * P.row_stride + half * K;
@@ -694,6 +951,40 @@ hipError_t launch_decide(int K, int prec, int prop, const KernelArgs &a, const i
     }
 }
 
+template <int K, int PREC>
+static hipError_t launch_decide_mix_t(const KernelArgs &a, const int *plist, int n_plist, int n_cu,
+                                      unsigned long long total_tiles, hipStream_t st, int *grid_out)
+{
+    constexpr int lds = decide_mix_lds_bytes<K, PREC>();
+    auto kern = k_decide_mix<K, PREC>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kMixBlock, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    unsigned long long want = (total_tiles + (unsigned long long)(kMixBlock / kWave) * kClaimTiles - 1) /
+                              ((unsigned long long)(kMixBlock / kWave) * kClaimTiles);
+    unsigned long long grid = (unsigned long long)per_cu * n_cu;
+    if (want < grid) grid = want;
+    if (grid < 1) grid = 1;
+    if (grid_out) *grid_out = (int)grid;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kMixBlock), lds, st, a, plist, n_plist);
+    return hipGetLastError();
+}
+
+hipError_t launch_decide_mix(int K, int prec, const KernelArgs &a, const int *plist, int n_plist, int n_cu,
+                             unsigned long long tiles, hipStream_t st, int *grid_out)
+{
+#define TKDV_DISPATCH_X(KK, PR) \
+    if (K == KK && prec == PR) return launch_decide_mix_t<KK, PR>(a, plist, n_plist, n_cu, tiles, st, grid_out);
+    TKDV_DISPATCH_X(8, PREC_FP32) TKDV_DISPATCH_X(8, PREC_BF16) TKDV_DISPATCH_X(8, PREC_BF16X3)
+    TKDV_DISPATCH_X(16, PREC_FP32) TKDV_DISPATCH_X(16, PREC_BF16) TKDV_DISPATCH_X(16, PREC_BF16X3)
+    TKDV_DISPATCH_X(32, PREC_FP32) TKDV_DISPATCH_X(32, PREC_BF16) TKDV_DISPATCH_X(32, PREC_BF16X3)
+#undef TKDV_DISPATCH_X
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_fixup(const KernelArgs &a, int n_cu, hipStream_t st)
 {
     hipLaunchKernelGGL(k_fixup, dim3(4 * n_cu), dim3(kBlock), 0, st, a);
@@ -747,6 +1038,9 @@ hipError_t launch_materialize(int K, int prop, const KernelArgs &a, const int *p
     TKDV_DISPATCH_M(32, PROP_SIGMA)
     TKDV_DISPATCH_M(64, PROP_UNIFORM)
     TKDV_DISPATCH_M(64, PROP_SIGMA)
+    TKDV_DISPATCH_M(8, PROP_MIXTURE)
+    TKDV_DISPATCH_M(16, PROP_MIXTURE)
+    TKDV_DISPATCH_M(32, PROP_MIXTURE)
 #undef TKDV_DISPATCH_M
     return hipErrorInvalidValue;
 }

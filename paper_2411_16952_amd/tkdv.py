@@ -18,12 +18,13 @@ LIB_PATH = os.path.join(HERE, "libtkdv.so")
 KMAX = 64
 NBINS = 64
 
-UNIFORM, SIGMA = 0, 1
+UNIFORM, SIGMA, MIXTURE = 0, 1, 2
+MIX_S, MIX_R = 32, 2
 FP32, BF16, BF16X3 = 0, 1, 2
 COUNT_PROPOSALS, COUNT_ACCEPTED = 0, 1
 
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "bf16x3": BF16X3}
-PROPOSALS = {"uniform": UNIFORM, "sigma": SIGMA}
+PROPOSALS = {"uniform": UNIFORM, "sigma": SIGMA, "mixture": MIXTURE}
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "no alpha root", -3: "HIP error",
           -4: "capacity exceeded", -5: "unsupported K", -6: "M violation"}
@@ -44,6 +45,12 @@ class Plan(C.Structure):
     _fields_ = [("alpha_star", C.c_double), ("log_M", C.c_double), ("log_norm_g", C.c_double),
                 ("sigma2", C.c_double * KMAX), ("N", C.c_int32), ("proposal", C.c_int32),
                 ("M_source", C.c_int32), ("n_optimiser_evals", C.c_int32)]
+
+
+class Mixture(C.Structure):
+    """Learned defensive mixture (tkdv_mixture): base ACG L0 = D + V V^T and its S shifts."""
+    _fields_ = [("K", C.c_int32), ("pad", C.c_int32), ("eps", C.c_double),
+                ("logd", C.c_double * KMAX), ("V", (C.c_double * MIX_R) * (2 * KMAX))]
 
 
 class Timing(C.Structure):
@@ -85,7 +92,8 @@ lib = _load()
 
 EXPORTS = ["tkdv_create", "tkdv_destroy", "tkdv_plan_point", "tkdv_sample", "tkdv_sample_batch",
            "tkdv_eval_proposals", "tkdv_synthesize", "tkdv_decision_window", "tkdv_get_timing",
-           "tkdv_status_str", "tkdv_last_error"]
+           "tkdv_status_str", "tkdv_last_error", "tkdv_mixture_log_q", "tkdv_plan_mixture",
+           "tkdv_sample_mixture", "tkdv_eval_mixture", "tkdv_mixture_window"]
 
 _P = C.c_void_p
 lib.tkdv_create.argtypes = [C.c_int, C.POINTER(_P)]
@@ -102,12 +110,22 @@ lib.tkdv_get_timing.argtypes = [_P, C.POINTER(Timing)]
 lib.tkdv_synthesize.argtypes = [_P, C.c_int32, C.c_int, _P, C.c_uint64, _P, _P]
 lib.tkdv_decision_window.argtypes = [C.POINTER(Point), C.c_int, C.c_int]
 lib.tkdv_decision_window.restype = C.c_double
+_PD = C.POINTER(C.c_double)
+lib.tkdv_mixture_log_q.argtypes = [C.POINTER(Point), C.POINTER(Plan), C.POINTER(Mixture), _PD, C.c_int32, _PD, _PD]
+lib.tkdv_plan_mixture.argtypes = [C.POINTER(Point), C.POINTER(Plan), C.POINTER(Mixture), _PD, C.c_int32,
+                                  C.c_double, C.POINTER(Plan), _PD]
+lib.tkdv_sample_mixture.argtypes = [_P, C.POINTER(Point), C.POINTER(Plan), C.POINTER(Mixture), C.c_uint64,
+                                    C.c_int, C.c_uint64, C.c_int, _P, _P, C.c_uint64, C.POINTER(Stats), _P]
+lib.tkdv_eval_mixture.argtypes = [_P, C.POINTER(Point), C.POINTER(Plan), C.POINTER(Mixture), C.c_uint64,
+                                  C.c_uint64, C.c_int, _P, _P, _P, _P, _P, _P, _P]
+lib.tkdv_mixture_window.argtypes = [C.POINTER(Point), C.POINTER(Plan), C.POINTER(Mixture), C.c_int]
+lib.tkdv_mixture_window.restype = C.c_double
 lib.tkdv_status_str.argtypes = [C.c_int]
 lib.tkdv_status_str.restype = C.c_char_p
 lib.tkdv_last_error.argtypes = [_P]
 lib.tkdv_last_error.restype = C.c_char_p
 for _f in EXPORTS:
-    if _f not in ("tkdv_decision_window", "tkdv_status_str", "tkdv_last_error"):
+    if _f not in ("tkdv_decision_window", "tkdv_status_str", "tkdv_last_error", "tkdv_mixture_window"):
         getattr(lib, _f).restype = C.c_int
 
 
@@ -129,6 +147,47 @@ def plan_point(point: Point, proposal: int = SIGMA) -> Plan:
 
 def decision_window(point: Point, proposal: int, precision: int) -> float:
     return lib.tkdv_decision_window(C.byref(point), int(proposal), int(precision))
+
+
+def make_mixture(K: int, eps: float, logd, V) -> Mixture:
+    """tkdv_mixture from log d [K] and V [2K, 2] (host arrays)."""
+    m = Mixture()
+    m.K, m.eps = int(K), float(eps)
+    logd = np.asarray(logd, dtype=np.float64).reshape(K)
+    V = np.asarray(V, dtype=np.float64).reshape(2 * K, MIX_R)
+    for k in range(K):
+        m.logd[k] = logd[k]
+    for c in range(2 * K):
+        for q in range(MIX_R):
+            m.V[c][q] = V[c, q]
+    return m
+
+
+def mixture_log_q(point: Point, sigma_plan: Plan, mix: Mixture, xhat) -> tuple[np.ndarray, np.ndarray]:
+    """Host FP64 (log q_net, log q_mix) at rows x^ of shape (n, 2K)."""
+    x = np.ascontiguousarray(np.asarray(xhat, dtype=np.float64).reshape(-1, 2 * point.K))
+    n = x.shape[0]
+    a, b = np.zeros(n), np.zeros(n)
+    _check(lib.tkdv_mixture_log_q(C.byref(point), C.byref(sigma_plan), C.byref(mix),
+                                  x.ctypes.data_as(_PD), n, a.ctypes.data_as(_PD), b.ctypes.data_as(_PD)))
+    return a, b
+
+
+def plan_mixture(point: Point, sigma_plan: Plan, mix: Mixture, starts=None, margin: float = 0.0):
+    """(plan with log M_mix, argmax) by multi-start BFGS on the sphere."""
+    K = point.K
+    st = None if starts is None else np.ascontiguousarray(np.asarray(starts, dtype=np.float64).reshape(-1, 2 * K))
+    out = Plan()
+    am = np.zeros(2 * K)
+    _check(lib.tkdv_plan_mixture(C.byref(point), C.byref(sigma_plan), C.byref(mix),
+                                 st.ctypes.data_as(_PD) if st is not None else None,
+                                 0 if st is None else st.shape[0], float(margin), C.byref(out),
+                                 am.ctypes.data_as(_PD)))
+    return out, am
+
+
+def mixture_window(point: Point, mix_plan: Plan, mix: Mixture, precision: int) -> float:
+    return lib.tkdv_mixture_window(C.byref(point), C.byref(mix_plan), C.byref(mix), int(precision))
 
 
 def _ptr(t) -> int | None:
@@ -186,6 +245,46 @@ class Context:
         d["xhat"] = xhat[:nw] if xhat is not None else None
         d["index"] = index[:nw] if index is not None else None
         return d
+
+    def sample_mixture(self, point: Point, plan: Plan, mix: Mixture, n: int, mode: int = COUNT_PROPOSALS,
+                       max_proposals: int = 0, precision: int = BF16X3, capacity: int = 0, xhat=None,
+                       index=None, stream=None) -> dict:
+        """Rejection-sample one point with the learned mixture proposal."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        if capacity and xhat is None:
+            xhat = torch.empty((capacity, 2 * point.K), dtype=torch.float32, device=dev)
+        if capacity and index is None:
+            index = torch.empty((capacity,), dtype=torch.int64, device=dev)
+        st = Stats()
+        _check(lib.tkdv_sample_mixture(self._h, C.byref(point), C.byref(plan), C.byref(mix), int(n), int(mode),
+                                       int(max_proposals), int(precision), _ptr(xhat), _ptr(index),
+                                       int(capacity), C.byref(st), _stream(stream)), self._h)
+        d = st.to_dict()
+        nw = d["n_written"]
+        d["xhat"] = xhat[:nw] if xhat is not None else None
+        d["index"] = index[:nw] if index is not None else None
+        return d
+
+    def eval_mixture(self, point: Point, plan: Plan, mix: Mixture, i0: int, n: int,
+                     precision: int = BF16X3, stream=None) -> dict:
+        """eval_proposals for the learned mixture proposal."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        K = point.K
+        out = {
+            "xhat": torch.empty((n, 2 * K), dtype=torch.float32, device=dev),
+            "t": torch.empty((n,), dtype=torch.float32, device=dev),
+            "s3": torch.empty((n,), dtype=torch.float32, device=dev),
+            "log_a": torch.empty((n,), dtype=torch.float32, device=dev),
+            "log_u": torch.empty((n,), dtype=torch.float32, device=dev),
+            "accept": torch.empty((n,), dtype=torch.uint8, device=dev),
+        }
+        _check(lib.tkdv_eval_mixture(self._h, C.byref(point), C.byref(plan), C.byref(mix), int(i0), int(n),
+                                     int(precision), _ptr(out["xhat"]), _ptr(out["t"]), _ptr(out["s3"]),
+                                     _ptr(out["log_a"]), _ptr(out["log_u"]), _ptr(out["accept"]),
+                                     _stream(stream)), self._h)
+        return out
 
     def sample_batch(self, points: list, n: list, proposal: int = SIGMA, plans: list | None = None,
                      mode: int = COUNT_PROPOSALS, max_proposals: int = 0, precision: int = BF16X3,

@@ -76,3 +76,78 @@ def test_decision_window_orders_precisions():
     assert 0 < w[0] < w[1] < w[2] < 1.0
     w2 = T.decision_window(T.make_point(16, 1.0, 40.0, 120.0), T.SIGMA, T.BF16X3)
     assert w2 > w[1]
+
+
+def _mixture_case(K, bp, c, scale, seed):
+    import numpy as np
+    from paper_2411_16952_amd import tkdv as T
+    pt = T.make_point(K, 1.0, bp, c, seed=seed)
+    sp = T.plan_point(pt, T.SIGMA)
+    rng = np.random.default_rng(seed)
+    logd = np.log(np.array(sp.sigma2[:K])) + 0.2 * rng.standard_normal(K)
+    V = scale * rng.standard_normal((2 * K, 2)) / math.sqrt(K)
+    return T, pt, sp, logd, V, rng
+
+
+@pytest.mark.parametrize("K", [8, 32])
+def test_host_mixture_density_matches_oracle(K):
+    """The library's FP64 mixture density (tkdv_mixture_log_q) against the oracle's."""
+    import numpy as np
+    T, pt, sp, logd, V, rng = _mixture_case(K, 30.0, 10.0, 1.0, 3)
+    mx = T.make_mixture(K, 0.2, logd, V)
+    mo = oracle.make_mixture(K, 0.2, logd, V)
+    X = rng.standard_normal((40, 2 * K))
+    X /= np.linalg.norm(X, axis=1)[:, None]
+    ln, lm = T.mixture_log_q(pt, sp, mx, X)
+    for i in range(len(X)):
+        a, b = oracle.mix_log_q(K, 1.0, 30.0, 10.0, sp.alpha_star, mo, X[i])
+        assert abs(ln[i] - a) < 1e-10 and abs(lm[i] - b) < 1e-10
+
+
+def test_host_mixture_rejection_constant_bounds_the_ratio():
+    """log M_mix from tkdv_plan_mixture: at or above log f - log q_mix at every oracle
+    draw of the mixture, at or below the defensive cap log M_Sigma - log|g| - log eps,
+    and at least the value at the point it reports."""
+    import numpy as np
+    K, bp, c = 8, 40.0, 20.0
+    T, pt, sp, logd, V, rng = _mixture_case(K, bp, c, 0.8, 5)
+    mx = T.make_mixture(K, 0.2, logd, V)
+    mo = oracle.make_mixture(K, 0.2, logd, V)
+    pl, am = T.plan_mixture(pt, sp, mx, margin=0.0)
+    assert pl.proposal == T.MIXTURE and pl.alpha_star == sp.alpha_star
+    cap = sp.log_M - sp.log_norm_g - math.log(oracle.mix_eps(mo))
+    assert pl.log_M <= cap + 1e-12
+    lf = oracle.log_ratio(am, 1.0, bp, c, sp.alpha_star, 0)
+    assert abs(lf - oracle.mix_log_q(K, 1.0, bp, c, sp.alpha_star, mo, am)[1] - pl.log_M) < 1e-9
+    res = oracle.mix_sample(K, 1.0, bp, c, sp.alpha_star, pl.log_M, mo, 9, 0, 200000, want_log=True)
+    assert res["log_a"].max() <= 1e-12
+    pl2, _ = T.plan_mixture(pt, sp, mx, margin=0.1)
+    assert abs(pl2.log_M - min(pl.log_M + math.log(1.1), cap)) < 1e-9
+
+
+def test_mixture_argument_errors():
+    import numpy as np
+    from paper_2411_16952_amd import tkdv as T
+    T_, pt, sp, logd, V, _ = _mixture_case(8, 30.0, 0.0, 0.5, 1)
+    with pytest.raises(T.TkdvError):
+        T.plan_mixture(pt, sp, T.make_mixture(8, 0.0, logd, V))      # eps must be in (0, 1)
+    with pytest.raises(T.TkdvError):
+        T.plan_mixture(pt, sp, T.make_mixture(16, 0.2, np.zeros(16), np.zeros((32, 2))))  # K mismatch
+    bad = logd.copy()
+    bad[0] = float("nan")
+    with pytest.raises(T.TkdvError):
+        T.mixture_log_q(pt, sp, T.make_mixture(8, 0.2, bad, V), np.eye(16)[:1])
+    up = T.plan_point(pt, T.UNIFORM)
+    with pytest.raises(T.TkdvError):
+        T.plan_mixture(pt, up, T.make_mixture(8, 0.2, logd, V))       # needs the Sigma plan
+
+
+def test_mixture_window_exceeds_sigma_window():
+    from paper_2411_16952_amd import tkdv as T
+    T_, pt, sp, logd, V, _ = _mixture_case(32, 40.0, 225.0, 1.0, 2)
+    mx = T.make_mixture(32, 0.2, logd, V)
+    pl, _ = T.plan_mixture(pt, sp, mx)
+    for prec in (T.FP32, T.BF16X3, T.BF16):
+        w_mix = T.mixture_window(pt, pl, mx, prec)
+        assert w_mix > T.decision_window(pt, T.SIGMA, prec)
+        assert w_mix < (1.0 if prec != T.BF16 else 50.0)

@@ -52,6 +52,49 @@ MUTATIONS = {
 }
 
 
+# mistakes in the learned-proposal functions, run against the mixture pins
+MIX_PINS = " or ".join(["normalised", "dense_definition", "V0_and_D_sigma", "shift_group",
+                        "draw_has_density", "component_weights"])
+MIX_MUTATIONS = {
+    "mix_woodbury_sign": ("double e = w[c] - (m->V[c][0] * g[0] + m->V[c][1] * g[1]);",
+                          "double e = w[c] + (m->V[c][0] * g[0] + m->V[c][1] * g[1]);"),
+    "mix_logdet_half": ("return -0.5 * logdet_L0 - K * log(qf);", "return -logdet_L0 - K * log(qf);"),
+    "mix_gram_identity": ("double G[ORC_MIX_R][ORC_MIX_R] = {{1.0, 0.0}, {0.0, 1.0}};",
+                          "double G[ORC_MIX_R][ORC_MIX_R] = {{1.0, 0.0}, {0.0, 0.0}};"),
+    "mix_weights_swapped": ("double a = log(eps) + lg, b = log1p(-eps) + lnet;",
+                            "double a = log1p(-eps) + lg, b = log(eps) + lnet;"),
+    "mix_draw_sqrt_d": ("X[c] = exp(0.5 * m->logd[c % K]) * z[c] + rv0[c] * eta[0] + rv1[c] * eta[1];",
+                        "X[c] = exp(m->logd[c % K]) * z[c] + rv0[c] * eta[0] + rv1[c] * eta[1];"),
+    "mix_draw_eta": ("X[c] = exp(0.5 * m->logd[c % K]) * z[c] + rv0[c] * eta[0] + rv1[c] * eta[1];",
+                     "X[c] = exp(0.5 * m->logd[c % K]) * z[c] + rv0[c] * eta[0] + rv1[c] * eta[0];"),
+    "mix_shift_pair": ("out[K + k - 1] = b * c - a * s;", "out[K + k - 1] = b * c + a * s;"),
+    "mix_component_rule": ("comp = (int)((wc - E) / B);", "comp = (int)((wc - E) / B / 2);"),
+}
+
+
+def _run_mutant(name, old, new, pins_file, pins):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not found exactly once"
+    with tempfile.TemporaryDirectory() as d:
+        c_path = os.path.join(d, "mut.c")
+        so_path = os.path.join(d, "libmut.so")
+        with open(c_path, "w") as f:
+            f.write(src.replace(old, new))
+        subprocess.run(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", "-o", so_path,
+                        c_path, "-lm"], check=True)
+        env = dict(os.environ, TKDV_ORACLE_LIB=so_path, OMP_NUM_THREADS="4")
+        return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                               os.path.join(ROOT, "tests", pins_file), "-k", pins],
+                              cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+
+
+@pytest.mark.parametrize("name", sorted(MIX_MUTATIONS))
+def test_planted_mixture_mistake_is_caught(name):
+    old, new = MIX_MUTATIONS[name]
+    r = _run_mutant(name, old, new, "test_mixture_oracle.py", MIX_PINS)
+    assert r.returncode == 1, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
+
+
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
 def test_planted_mistake_is_caught(name):
     old, new = MUTATIONS[name]
