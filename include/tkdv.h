@@ -280,6 +280,64 @@ tkdv_status tkdv_eval_mixture(tkdv_ctx *ctx, const tkdv_point *pt, const tkdv_pl
 double tkdv_mixture_window(const tkdv_point *pt, const tkdv_plan *mix_plan, const tkdv_mixture *mix,
                            tkdv_precision precision);
 
+/*
+ * Learned proposal, the network (an extension, not in the paper): a
+ * multilayer perceptron conditioned on (beta', E0, C3/C2) whose output is the
+ * tkdv_mixture of a point, evaluated and trained on the GPU in FP64.
+ *   z  = ((beta' - 40)/20, ln E0, (C3/C2) sqrt(E0) beta'/1e4 - 1)
+ *   h1 = tanh(W1^T z + b1),  h2 = tanh(W2^T h1 + b2),  o = W3^T h2 + b3
+ *   log d_k = log s_k^2 + o_{k-1}          (s_k^2 of the point's Sigma plan)
+ *   V = V0 + v_scale * o_{K..5K-1} (row-major [2K][2]), V0 = v_amp/sqrt(K) on
+ *       the cos block of column 0 and on the sin block of column 1.
+ * Weights, one FP64 array, input-major: W1 [3][H], b1 [H], W2 [H][H], b2 [H],
+ * W3 [H][5K], b3 [5K].  Training rows of point p are unit vectors x_s of
+ * two kinds: accepted samples of the point (kind 0) and points where f/q_mix
+ * is large, e.g. the arg max of tkdv_plan_mixture (kind 1).  The loss is
+ *   L = sum_p [ T log sum_{s in p} exp((log f(x_s) - log q_mix(x_s))/T)
+ *               - lambda mean_{s in p, kind 0} log q_net(x_s) ],
+ * a soft maximum of the ratio (whose supremum is log M_mix) plus a
+ * likelihood term; Adam on the weights.  K in {8, 16, 32}.
+ */
+typedef struct {
+    int32_t K;
+    int32_t hidden;       /* H, 1..256                                        */
+    double eps;           /* weight of g_Sigma in the mixture                 */
+    double v_amp;         /* V0 amplitude                                     */
+    double v_scale;       /* output scale of V                                */
+    double temperature;   /* T > 0                                            */
+    double nll_weight;    /* lambda >= 0                                      */
+    double lr, beta1, beta2, adam_eps;
+    uint64_t seed;        /* initial weights: W1, W2 ~ Glorot uniform, the rest 0 */
+} tkdv_learner_cfg;
+
+typedef struct tkdv_learner tkdv_learner;
+
+tkdv_status tkdv_learner_create(tkdv_ctx *ctx, const tkdv_learner_cfg *cfg, tkdv_learner **out);
+tkdv_status tkdv_learner_destroy(tkdv_learner *learner);
+/* The training points; sigma_plans are their Sigma plans.  Clears the rows. */
+tkdv_status tkdv_learner_set_points(tkdv_learner *learner, int32_t n_points, const tkdv_point *pts,
+                                    const tkdv_plan *sigma_plans);
+/* Append n rows to point `point`: device FP32 rows (row_stride floats apart,
+ * first 2K used) or host FP64 rows [n][2K]; rows are normalised in FP64. */
+tkdv_status tkdv_learner_add_rows(tkdv_learner *learner, int32_t point, const float *d_xhat, uint64_t row_stride,
+                                  uint64_t n, int32_t kind, void *stream);
+tkdv_status tkdv_learner_add_rows_host(tkdv_learner *learner, int32_t point, const double *h_xhat, uint64_t n,
+                                       int32_t kind);
+/* n_steps Adam steps; h_loss (host [n_points], may be NULL) receives the
+ * per-point loss at the weights before the last step. */
+tkdv_status tkdv_learner_train(tkdv_learner *learner, int32_t n_steps, double *h_loss, void *stream);
+/* One evaluation without update: per-point loss, dL/d(log d_1..K, V row-major)
+ * per point (host [n_points][5K]) and dL/dweights (host [n_weights]); each
+ * output may be NULL. */
+tkdv_status tkdv_learner_gradients(tkdv_learner *learner, double *h_loss, double *h_grad_mix,
+                                   double *h_grad_weights, void *stream);
+/* The network's mixture at a point (its Sigma plan gives s_k^2). */
+tkdv_status tkdv_learner_mixture(tkdv_learner *learner, const tkdv_point *pt, const tkdv_plan *sigma_plan,
+                                 tkdv_mixture *out);
+int64_t tkdv_learner_n_weights(const tkdv_learner *learner);
+tkdv_status tkdv_learner_get_weights(const tkdv_learner *learner, double *h_out, int64_t n);
+tkdv_status tkdv_learner_set_weights(tkdv_learner *learner, const double *h_in, int64_t n);
+
 /* Phase timings of the last call on this context (see tkdv_timing). */
 tkdv_status tkdv_get_timing(const tkdv_ctx *ctx, tkdv_timing *out);
 

@@ -16,6 +16,7 @@
 #include "tkdv_host_math.h"
 #include "tkdv_mixture.h"
 #include "tkdv_plan.h"
+#include "tkdv_runtime.h"
 
 using namespace tkdv;
 
@@ -513,6 +514,11 @@ tkdv_status prepare_mixture(tkdv_ctx *ctx, Call &call, const tkdv_point &pt, con
 }
 
 }  // namespace
+
+namespace tkdv {
+int ctx_device(const tkdv_ctx *ctx) { return ctx->device; }
+tkdv_status record_error(tkdv_status st, const std::string &msg) { return set_err(nullptr, st, msg); }
+}  // namespace tkdv
 
 extern "C" {
 

@@ -260,6 +260,29 @@ __device__ __forceinline__ unsigned long long pack_defer(int p, uint64_t i)
     return ((unsigned long long)p << 40) | (unsigned long long)i;
 }
 
+// log f = -beta'/(E0 K^2) (H2 - c H3) in FP64 at a point x of the sphere with
+// t = sum k^2 s_k: H2 = E0 t by Parseval and H3 by the double sum over the
+// triads k + (n - k) = n (Sec. IV.A).
+__device__ inline double log_f_fp64(int K, double E0, double beta_p, double c32, const double *x, double t)
+{
+    const double pi = 3.14159265358979323846;
+    const double s = sqrt(E0 / (2.0 * pi));
+    double tri = 0.0;
+    for (int n = 2; n <= K; ++n) {
+        double in_re = 0.0, in_im = 0.0;
+        for (int k = 1; k < n; ++k) {
+            const double pr = s * x[k - 1], pi_ = -s * x[K + k - 1];
+            const double qr = s * x[n - k - 1], qi = -s * x[K + n - k - 1];
+            in_re += pr * qr - pi_ * qi;
+            in_im += pr * qi + pi_ * qr;
+        }
+        tri += (s * x[n - 1]) * in_re + (-s * x[K + n - 1]) * in_im;
+    }
+    const double H3 = 2.0 * pi * tri;
+    const double H2 = E0 * t;
+    return -(beta_p / (E0 * (double)K * K) * (H2 - c32 * H3));
+}
+
 // ---------------------------------------------------------------------------
 // Learned mixture proposal
 // ---------------------------------------------------------------------------

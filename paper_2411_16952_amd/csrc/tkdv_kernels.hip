@@ -365,27 +365,9 @@ __device__ double fp64_project(int K, double *x)
     return t;
 }
 
-// log f = -beta'/(E0 K^2) (H2 - c H3) at a point of the sphere, H2 = E0 t by
-// Parseval and H3 by the double sum over triads (Sec. IV.A).
 __device__ double fp64_log_f(const DevPoint &P, const double *x, double t)
 {
-    const int K = P.K;
-    const double pi = 3.14159265358979323846;
-    const double s = sqrt(P.E0 / (2.0 * pi));
-    double tri = 0.0;
-    for (int n = 2; n <= K; ++n) {
-        double in_re = 0.0, in_im = 0.0;
-        for (int k = 1; k < n; ++k) {
-            const double pr = s * x[k - 1], pi_ = -s * x[K + k - 1];
-            const double qr = s * x[n - k - 1], qi = -s * x[K + n - k - 1];
-            in_re += pr * qr - pi_ * qi;
-            in_im += pr * qi + pi_ * qr;
-        }
-        tri += (s * x[n - 1]) * in_re + (-s * x[K + n - 1]) * in_im;
-    }
-    const double H3 = 2.0 * pi * tri;
-    const double H2 = P.E0 * t;
-    return -(P.beta_p / (P.E0 * (double)K * K) * (H2 - P.c32 * H3));
+    return log_f_fp64(P.K, P.E0, P.beta_p, P.c32, x, t);
 }
 
 // FP64 evaluation of a listed proposal of the paper's sampler: normals from

@@ -1,0 +1,99 @@
+"""Training driver of the learned proposal (the network of ``tkdv_learner``).
+
+Cutting-plane minimax fit of the network's mixtures to a set of training
+points, on the GPU:
+  1. accepted samples of each point from the paper's sampler (kind-0 rows);
+  2. each round: for every point, the network's mixture, its rejection
+     constant M_mix = sup f/q_mix by tkdv_plan_mixture (multi-start BFGS),
+     and the arg max plus copies of it shifted by fractions of 2 pi/S (the
+     target is invariant under every xi-shift, q_mix only under multiples of
+     2 pi/S) added as kind-1 rows; then Adam steps on the loss of
+     ``tkdv_learner`` (soft maximum of log f/q_mix over the rows plus the
+     likelihood term).
+The soft maximum pulls down log f/q_mix where it is largest, which is what
+sets M_mix and hence the acceptance rate Z/M_mix.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import tkdv as T
+
+
+def shift_rows(x: np.ndarray, phis) -> np.ndarray:
+    """Copies of x^ with u shifted by each phi: mode k rotated by the angle k phi."""
+    K = x.size // 2
+    k = np.arange(1, K + 1)
+    out = []
+    for phi in phis:
+        c, s = np.cos(k * phi), np.sin(k * phi)
+        a, b = x[:K], x[K:]
+        out.append(np.concatenate([a * c + b * s, b * c - a * s]))
+    return np.array(out)
+
+
+@dataclass
+class FitResult:
+    learner: T.Learner
+    points: list
+    sigma_plans: list
+    history: list = field(default_factory=list)   # per round: per-point log gain, loss, seconds
+
+    def mixture(self, i: int) -> T.Mixture:
+        return self.learner.mixture(self.points[i], self.sigma_plans[i])
+
+
+def log_M_sigma_normalised(sp: T.Plan) -> float:
+    """log sup f/g_Sigma with g_Sigma normalised w.r.t. mu0 (comparable with M_mix)."""
+    return sp.log_M - sp.log_norm_g
+
+
+def fit(ctx: T.Context, points: list, cfg: T.LearnerCfg, samples_per_point: int = 4096, rounds: int = 8,
+        steps: int = 150, max_proposals: int = 1 << 32, n_shift_copies: int = 7, margin: float = 0.0,
+        precision: int = T.BF16X3, log=None) -> FitResult:
+    sps = [T.plan_point(p, T.SIGMA) for p in points]
+    L = T.Learner(ctx, cfg)
+    L.set_points(points, sps)
+    for i, (pt, sp) in enumerate(zip(points, sps)):
+        r = ctx.sample(pt, samples_per_point, proposal=T.SIGMA, plan=sp, mode=T.COUNT_ACCEPTED,
+                       max_proposals=max_proposals, precision=precision, capacity=samples_per_point)
+        if r["n_written"] == 0:
+            raise RuntimeError(f"point {i}: no accepted sample within {max_proposals} proposals")
+        L.add_rows(i, r["xhat"], kind=0)
+    res = FitResult(L, points, sps)
+    S = T.MIX_S
+    fracs = [2 * math.pi * (q + 1) / ((n_shift_copies + 1) * S) for q in range(n_shift_copies)]
+    starts = [[] for _ in points]
+    for rnd in range(rounds + 1):
+        t0 = time.time()
+        gains = []
+        for i, (pt, sp) in enumerate(zip(points, sps)):
+            mix = L.mixture(pt, sp)
+            st = np.array(starts[i][-8:]) if starts[i] else None
+            pl, am = T.plan_mixture(pt, sp, mix, starts=st, margin=margin)
+            gains.append(log_M_sigma_normalised(sp) - pl.log_M)
+            if rnd < rounds:
+                rows = np.vstack([am[None, :], shift_rows(am, fracs)])
+                L.add_rows(i, rows, kind=1)
+                starts[i].append(am)
+        loss = L.train(steps) if rnd < rounds else None
+        res.history.append({"round": rnd, "log_gain": gains, "loss": None if loss is None else loss.tolist(),
+                            "seconds": time.time() - t0})
+        if log:
+            g = np.exp(np.array(gains))
+            log(f"round {rnd}: M_Sigma/M_mix min {g.min():.2f} median {np.median(g):.2f} max {g.max():.2f}"
+                + ("" if loss is None else f", loss {np.mean(loss):.4f}") + f" ({time.time() - t0:.1f}s)")
+    return res
+
+
+def plan_for(res_or_learner, point: T.Point, margin: float = 0.02, starts=None):
+    """(mixture, mixture plan, Sigma plan) of the trained network at any point."""
+    L = res_or_learner.learner if isinstance(res_or_learner, FitResult) else res_or_learner
+    sp = T.plan_point(point, T.SIGMA)
+    mix = L.mixture(point, sp)
+    pl, _ = T.plan_mixture(point, sp, mix, starts=starts, margin=margin)
+    return mix, pl, sp

@@ -53,6 +53,13 @@ class Mixture(C.Structure):
                 ("logd", C.c_double * KMAX), ("V", (C.c_double * MIX_R) * (2 * KMAX))]
 
 
+class LearnerCfg(C.Structure):
+    _fields_ = [("K", C.c_int32), ("hidden", C.c_int32), ("eps", C.c_double), ("v_amp", C.c_double),
+                ("v_scale", C.c_double), ("temperature", C.c_double), ("nll_weight", C.c_double),
+                ("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("adam_eps", C.c_double),
+                ("seed", C.c_uint64)]
+
+
 class Timing(C.Structure):
     _fields_ = [("decide_ms", C.c_double), ("fixup_ms", C.c_double), ("segments_ms", C.c_double),
                 ("materialize_ms", C.c_double), ("finalize_ms", C.c_double), ("synth_ms", C.c_double),
@@ -93,7 +100,11 @@ lib = _load()
 EXPORTS = ["tkdv_create", "tkdv_destroy", "tkdv_plan_point", "tkdv_sample", "tkdv_sample_batch",
            "tkdv_eval_proposals", "tkdv_synthesize", "tkdv_decision_window", "tkdv_get_timing",
            "tkdv_status_str", "tkdv_last_error", "tkdv_mixture_log_q", "tkdv_plan_mixture",
-           "tkdv_sample_mixture", "tkdv_eval_mixture", "tkdv_mixture_window"]
+           "tkdv_sample_mixture", "tkdv_eval_mixture", "tkdv_mixture_window", "tkdv_learner_create",
+           "tkdv_learner_destroy", "tkdv_learner_set_points", "tkdv_learner_add_rows",
+           "tkdv_learner_add_rows_host", "tkdv_learner_train", "tkdv_learner_gradients",
+           "tkdv_learner_mixture", "tkdv_learner_n_weights", "tkdv_learner_get_weights",
+           "tkdv_learner_set_weights"]
 
 _P = C.c_void_p
 lib.tkdv_create.argtypes = [C.c_int, C.POINTER(_P)]
@@ -120,12 +131,25 @@ lib.tkdv_eval_mixture.argtypes = [_P, C.POINTER(Point), C.POINTER(Plan), C.POINT
                                   C.c_uint64, C.c_int, _P, _P, _P, _P, _P, _P, _P]
 lib.tkdv_mixture_window.argtypes = [C.POINTER(Point), C.POINTER(Plan), C.POINTER(Mixture), C.c_int]
 lib.tkdv_mixture_window.restype = C.c_double
+lib.tkdv_learner_create.argtypes = [_P, C.POINTER(LearnerCfg), C.POINTER(_P)]
+lib.tkdv_learner_destroy.argtypes = [_P]
+lib.tkdv_learner_set_points.argtypes = [_P, C.c_int32, C.POINTER(Point), C.POINTER(Plan)]
+lib.tkdv_learner_add_rows.argtypes = [_P, C.c_int32, _P, C.c_uint64, C.c_uint64, C.c_int32, _P]
+lib.tkdv_learner_add_rows_host.argtypes = [_P, C.c_int32, _PD, C.c_uint64, C.c_int32]
+lib.tkdv_learner_train.argtypes = [_P, C.c_int32, _PD, _P]
+lib.tkdv_learner_gradients.argtypes = [_P, _PD, _PD, _PD, _P]
+lib.tkdv_learner_mixture.argtypes = [_P, C.POINTER(Point), C.POINTER(Plan), C.POINTER(Mixture)]
+lib.tkdv_learner_n_weights.argtypes = [_P]
+lib.tkdv_learner_n_weights.restype = C.c_int64
+lib.tkdv_learner_get_weights.argtypes = [_P, _PD, C.c_int64]
+lib.tkdv_learner_set_weights.argtypes = [_P, _PD, C.c_int64]
 lib.tkdv_status_str.argtypes = [C.c_int]
 lib.tkdv_status_str.restype = C.c_char_p
 lib.tkdv_last_error.argtypes = [_P]
 lib.tkdv_last_error.restype = C.c_char_p
 for _f in EXPORTS:
-    if _f not in ("tkdv_decision_window", "tkdv_status_str", "tkdv_last_error", "tkdv_mixture_window"):
+    if _f not in ("tkdv_decision_window", "tkdv_status_str", "tkdv_last_error", "tkdv_mixture_window",
+                  "tkdv_learner_n_weights"):
         getattr(lib, _f).restype = C.c_int
 
 
@@ -347,3 +371,85 @@ class Context:
                                        _ptr(out["log_a"]), _ptr(out["log_u"]), _ptr(out["accept"]),
                                        _stream(stream)), self._h)
         return out
+
+
+def learner_cfg(K: int, hidden: int = 256, eps: float = 0.2, v_amp: float = 0.5, v_scale: float = 0.1,
+                temperature: float = 0.05, nll_weight: float = 0.1, lr: float = 3e-3, beta1: float = 0.9,
+                beta2: float = 0.999, adam_eps: float = 1e-8, seed: int = 1) -> LearnerCfg:
+    return LearnerCfg(int(K), int(hidden), eps, v_amp, v_scale, temperature, nll_weight, lr, beta1, beta2,
+                      adam_eps, int(seed))
+
+
+class Learner:
+    """The network of the learned proposal and its training (tkdv_learner_*)."""
+
+    def __init__(self, ctx: Context, cfg: LearnerCfg):
+        self._h = C.c_void_p()
+        self.cfg = cfg
+        self.K = cfg.K
+        _check(lib.tkdv_learner_create(ctx._h, C.byref(cfg), C.byref(self._h)))
+        self.n_points = 0
+
+    def close(self):
+        if self._h:
+            lib.tkdv_learner_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n_weights(self) -> int:
+        return int(lib.tkdv_learner_n_weights(self._h))
+
+    def set_points(self, points: list, sigma_plans: list):
+        n = len(points)
+        _check(lib.tkdv_learner_set_points(self._h, n, (Point * n)(*points), (Plan * n)(*sigma_plans)))
+        self.n_points = n
+
+    def add_rows(self, point: int, xhat, kind: int = 0, stream=None):
+        """Rows of one point: a float32 device tensor (n, >= 2K) or a host array (n, 2K)."""
+        try:
+            import torch
+            is_dev = isinstance(xhat, torch.Tensor) and xhat.is_cuda
+        except ImportError:
+            is_dev = False
+        if is_dev:
+            assert xhat.dtype == torch.float32 and xhat.dim() == 2 and xhat.stride(1) == 1
+            _check(lib.tkdv_learner_add_rows(self._h, int(point), _ptr(xhat), int(xhat.stride(0)),
+                                             int(xhat.shape[0]), int(kind), _stream(stream)))
+        else:
+            x = np.ascontiguousarray(np.asarray(xhat, dtype=np.float64).reshape(-1, 2 * self.K))
+            _check(lib.tkdv_learner_add_rows_host(self._h, int(point), x.ctypes.data_as(_PD), x.shape[0],
+                                                  int(kind)))
+
+    def train(self, n_steps: int, stream=None) -> np.ndarray:
+        loss = np.zeros(self.n_points)
+        _check(lib.tkdv_learner_train(self._h, int(n_steps), loss.ctypes.data_as(_PD), _stream(stream)))
+        return loss
+
+    def gradients(self, stream=None):
+        """(loss [P], dL/d(log d, V) [P, 5K], dL/dweights [n_weights]) at the current weights."""
+        loss = np.zeros(self.n_points)
+        gm = np.zeros((self.n_points, 5 * self.K))
+        gw = np.zeros(self.n_weights)
+        _check(lib.tkdv_learner_gradients(self._h, loss.ctypes.data_as(_PD), gm.ctypes.data_as(_PD),
+                                          gw.ctypes.data_as(_PD), _stream(stream)))
+        return loss, gm, gw
+
+    def mixture(self, point: Point, sigma_plan: Plan) -> Mixture:
+        m = Mixture()
+        _check(lib.tkdv_learner_mixture(self._h, C.byref(point), C.byref(sigma_plan), C.byref(m)))
+        return m
+
+    def get_weights(self) -> np.ndarray:
+        w = np.zeros(self.n_weights)
+        _check(lib.tkdv_learner_get_weights(self._h, w.ctypes.data_as(_PD), w.size))
+        return w
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+        _check(lib.tkdv_learner_set_weights(self._h, w.ctypes.data_as(_PD), w.size))

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_functions():
     text = open(os.path.join(ROOT, "include", "tkdv.h")).read()
     # declarations: "<type> [*]tkdv_name(" at the start of a line
-    return sorted(set(re.findall(r"^[a-z_ ]+\**\s*\*?(tkdv_[a-z_]+)\(", text, re.M)))
+    return sorted(set(re.findall(r"^[a-z0-9_ ]+\**\s*\*?(tkdv_[a-z_]+)\(", text, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
