@@ -1,18 +1,27 @@
 #!/usr/bin/env python3
 """Throughput of the MI355X TKdV rejection sampler (arXiv 2411.16952).
 
-Workload (one step): the plain-GPU configuration -- K = 32 complex modes
-(sphere S^63), grid N = 128, E0 = 1, the paper's Sigma proposal, eight beta'
-values {20, 25, 30, 35, 40, 45, 50, 60} at the two nonlinearity levels
-beta' C3/C2 = 6000 and 12000 (16 points, seed = point id), 1e9 proposals per
-point, all accepted samples stored in HBM and their statistics reduced.
-Per-point plans (alpha*, M) are step 1 of the paper's algorithm and are
-computed once before the timed region; their wall time is reported.
+Default workload (--workload learned): accepted samples/s at K = 32 with the
+learned defensive-mixture proposal against the paper's Sigma proposal.
+  * before the timed region: the network (3 -> 256 -> 256 -> 5K, FP64 on the
+    GPU) is fitted on 16 training points (beta' = linspace(20, 60, 16),
+    C3/C2 = 9000/beta') from the paper's sampler's accepted samples, and the
+    plans of the evaluation points are made: alpha*, M_Sigma (the paper's
+    step 1) and M_mix of the network's mixture (multi-start BFGS of f/q_mix);
+  * one step: 32 evaluation points (the 16 beta' at beta' C3/C2 = 9000 and
+    12000, seeds not used in training), 1e9 proposals per point with the
+    mixture sampler, then 1e9 per point with the paper's sampler (one batched
+    call), all statistics reduced and up to 2^20 samples per point stored.
+  value = the mixture sampler's accepted samples/s; the paper's sampler's
+  rate on the same points is reported beside it.  Both samplers are exact,
+  so equal accepted counts give equal statistical (KS) accuracy; two-sample
+  KS p-values of u(0) between the two samplers' outputs are reported.
+--workload plain: the paper's sampler alone on 8 beta' x beta'C3/C2 in
+{6000, 12000}, 1e9 proposals per point (the plain GPU configuration).
 
-Prints one JSON line: accepted samples/s (value), proposals/s, the roofline of
-the dominant kernel (k_decide, ALU-bound) from HIP events recorded inside the
-library on the kernel's own stream, and the CPU FP64 oracle's throughput on a
-bounded sample of the same workload (the first proposals of every point).
+Prints one JSON line with the roofline of the dominant kernel (ALU-bound)
+from HIP events recorded inside the library on the kernel's own stream, and
+the CPU FP64 oracle's throughput on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -45,15 +54,28 @@ def alu_ops_per_proposal(K: int, proposal: str = "sigma", precision: str = "bf16
         BF16: round; FP32: none)                                               = 6 K / 2 K / 0
       cube-and-sum over the N = 4K grid values (square, FMA)                   = 8 K
       log U, log a, comparison                                                 = 12
-    The synthesis products themselves run on the matrix cores."""
+    The synthesis products themselves run on the matrix cores.
+    The learned mixture adds (mixture_extra_ops): component choice from one
+    word (6), the Box-Muller pair eta (2 conversions + 7), the low-rank part
+    of the draw (2 FMA per coordinate: 4K), Q = X^T A X (2K), and per shift
+    j < S = 32: the 2x2 quadratic form of y_j and r_j (6), log2, running
+    minimum, then exp2 of K (l_min - l_j) and its sum (4) = 12 S, plus the
+    final log-sum and the two-term mixture (20)."""
     split = {"bf16x3": 6 * K, "bf16": 2 * K, "fp32": 0}[precision]
-    scale = 2 * K if proposal == "sigma" else 0
-    return 80 * (K / 2 + 1) + 2 * (2 * K + 1) + 7 * K + scale + 8 * K + 1 + split + 8 * K + 12
+    scale = 2 * K if proposal in ("sigma", "mixture") else 0
+    base = 80 * (K / 2 + 1) + 2 * (2 * K + 1) + 7 * K + scale + 8 * K + 1 + split + 8 * K + 12
+    return base + (mixture_extra_ops(K) if proposal == "mixture" else 0)
 
 
-def mfma_flops_per_proposal(K: int, precision: str = "bf16x3") -> float:
-    """Synthesis u~ = Phi^T x^ on the N = 4K grid: 2 x 2K x N flops per product term."""
-    return {"bf16x3": 3, "bf16": 1, "fp32": 1}[precision] * 2 * (2 * K) * (4 * K)
+def mixture_extra_ops(K: int, S: int = 32) -> float:
+    return 6 + 9 + 4 * K + 2 * K + 12 * S + 20
+
+
+def mfma_flops_per_proposal(K: int, precision: str = "bf16x3", proposal: str = "sigma") -> float:
+    """Synthesis u~ = Phi^T x^ on the N = 4K grid: 2 x 2K x N flops per product
+    term; the mixture adds y = (R_j A V)^T x for S = 32 shifts x rank 2 rows."""
+    rows = 4 * K + (64 if proposal == "mixture" else 0)
+    return {"bf16x3": 3, "bf16": 1, "fp32": 1}[precision] * 2 * (2 * K) * rows
 
 
 def kernel_source_digest() -> str:
@@ -64,12 +86,12 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(K: int, precision: str, proposals_per_launch: int):
-    """HBM bytes per k_decide launch from the committed rocprofv3 counter summary
-    (bytes per proposal, FETCH_SIZE and WRITE_SIZE scaled by the plain-copy
-    calibration, times the proposals of this launch), or None when the summary
-    is missing or was taken on different kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"k_decide_k{K}_{precision}_traffic.json")
+def load_traffic(K: int, precision: str, proposals_per_launch: int, kernel: str = "k_decide"):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (bytes per proposal, FETCH_SIZE and WRITE_SIZE scaled by the
+    plain-copy calibration, times the proposals of this launch), or None when
+    the summary is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_k{K}_{precision}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -134,37 +156,7 @@ def synthesis_bench(args) -> int:
     return 0
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--proposals", type=float, default=1e9, help="proposals per point")
-    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16", "bf16x3"])
-    ap.add_argument("--cpu-sample", type=int, default=1 << 22, help="oracle proposals per point (0: skip)")
-    ap.add_argument("--synthesis", action="store_true",
-                    help="only time the standalone synthesis kernel (K = 64, N = 256, 2^20 rows of x^ "
-                         "in HBM) for FP32, BF16 and BF16x3 products; prints one JSON line")
-    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
-                    help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
-    args = ap.parse_args()
-    if args.calibrate_copy:
-        import torch
-        src = torch.empty(args.calibrate_copy // 4, dtype=torch.float32, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"calibrate_copy_bytes": args.calibrate_copy, "copies": 3}))
-        return 0
-    if args.synthesis:
-        return synthesis_bench(args)
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sampler's proposals "
-              "are independent, and multi-GPU sharding is a design note, not a measured path.",
-              file=sys.stderr)
-        return 2
-
+def plain_bench(args) -> int:
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs an MI355X GPU", file=sys.stderr)
@@ -225,9 +217,10 @@ def main() -> int:
                          / (2.5e15 if args.precision != "fp32" else 157.3e12)}
 
     cpu = None
-    if args.cpu_sample > 0:
+    n_cpu = (1 << 22) if args.cpu_sample < 0 else args.cpu_sample
+    if n_cpu > 0:
         print("cpu baseline ...", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(specs, plans, args.cpu_sample)
+        cpu = cpu_baseline(specs, plans, n_cpu)
 
     line = {
         "metric": "accepted samples/sec at K=32 (plain Sigma proposal); proposals/sec",
@@ -260,6 +253,230 @@ def main() -> int:
     print(json.dumps(line), flush=True)
     ctx.close()
     return 0
+
+
+
+def cpu_baseline_mixture(points, mixtures, mix_plans, n_sample: int) -> dict:
+    """The oracle's mixture sampler (same trained mixtures and M_mix, same
+    Philox counters) on the first n_sample proposal indices of every point."""
+    import numpy as np
+    import oracle
+    cores = oracle.max_threads()
+    t0 = time.perf_counter()
+    n_acc = 0
+    for p, mix, pl in zip(points, mixtures, mix_plans):
+        K = p.K
+        mo = oracle.make_mixture(K, mix.eps, np.array(mix.logd[:K]),
+                                 np.array([[mix.V[r][q] for q in range(2)] for r in range(2 * K)]))
+        r = oracle.mix_sample(K, p.E0, p.beta_p, p.c32, pl.alpha_star, pl.log_M, mo, p.seed, p.point_id,
+                              n_sample, nthreads=cores)
+        n_acc += int(r["n_accepted"])
+    dt = time.perf_counter() - t0
+    n_prop = n_sample * len(points)
+    return {
+        "value": n_acc / dt, "unit": "accepted samples/s", "cores": cores, "kind": "oracle",
+        "proposals_per_s": n_prop / dt, "accepted": n_acc, "seconds": dt,
+        "sample": f"first {n_sample} proposal indices of each of the {len(points)} evaluation points "
+                  f"({n_prop} proposals, same Philox counters, trained mixtures and M_mix), FP64 oracle "
+                  f"mixture sampler with OpenMP",
+    }
+
+
+def learned_bench(args) -> int:
+    import math
+
+    import numpy as np
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs an MI355X GPU", file=sys.stderr)
+        return 1
+    from scipy import stats as sst
+
+    from paper_2411_16952_amd import learned
+    from paper_2411_16952_amd import tkdv as T
+    from paper_2411_16952_amd import workloads as W
+
+    prec = T.PRECISIONS[args.precision]
+    ctx = T.Context(0)
+    train = [T.make_point(s.K, s.E0, s.beta_p, s.c32, seed=s.seed, point_id=s.point_id)
+             for s in W.learned_train_points()]
+    K = train[0].K
+    cfg = T.learner_cfg(K, hidden=256, eps=W.LEARNED_EPS, v_amp=0.5, v_scale=1.0, lr=3e-3, seed=7)
+    t0 = time.perf_counter()
+    res = learned.fit(ctx, train, cfg, samples_per_point=4096, rounds=args.train_rounds, steps=args.train_steps,
+                      max_proposals=1 << 36, precision=prec,
+                      log=lambda m: print("train " + m, file=sys.stderr, flush=True))
+    train_s = time.perf_counter() - t0
+
+    specs = W.learned_eval_points()
+    pts = [T.make_point(s.K, s.E0, s.beta_p, s.c32, seed=s.seed, point_id=s.point_id) for s in specs]
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(pts))) as ex:
+        planned = list(ex.map(lambda p: learned.plan_for(res, p, margin=0.02), pts))
+    plan_s = time.perf_counter() - t0
+    mixes = [m for m, _, _ in planned]
+    mplans = [pl for _, pl, _ in planned]
+    splans = [sp for _, _, sp in planned]
+    log_gain = [learned.log_M_sigma_normalised(sp) - pl.log_M for sp, pl in zip(splans, mplans)]
+    n_per = int(args.proposals)
+    cap = 1 << 20
+    print(f"bench: learned vs plain, {len(pts)} points, K={K}, {n_per:.3g} proposals/point/sampler, "
+          f"{args.precision}; training {train_s:.1f}s, plans {plan_s:.1f}s; M_Sigma/M_mix geometric mean "
+          f"{math.exp(sum(log_gain) / len(log_gain)):.1f}", file=sys.stderr, flush=True)
+
+    def mix_step():
+        out, dec_ms, launches = [], 0.0, 0
+        for p, pl, mx in zip(pts, mplans, mixes):
+            out.append(ctx.sample_mixture(p, pl, mx, n_per, precision=prec, capacity=cap))
+            tm = ctx.timing()
+            dec_ms += tm["decide_ms"]
+            launches += tm["decide_launches"]
+        return out, dec_ms, launches
+
+    def plain_step():
+        out, _, _ = ctx.sample_batch(pts, [n_per] * len(pts), plans=splans, precision=prec,
+                                     capacity=[cap] * len(pts))
+        return out, ctx.timing()
+
+    for w in range(args.warmup):
+        mix_step()
+        plain_step()
+        print(f"warmup {w} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    acc_m, dec_ms_m, launches_m, out_m = 0, 0.0, 0, None
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        out_m, dms, nl = mix_step()
+        acc_m += sum(int(o["n_accepted"]) for o in out_m)
+        dec_ms_m += dms
+        launches_m += nl
+        print(f"mixture step {s}: {acc_m} accepted so far", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt_m = time.perf_counter() - t0
+    acc_p, out_p = 0, None
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        out_p, tm = plain_step()
+        acc_p += sum(int(o["n_accepted"]) for o in out_p)
+        print(f"plain step {s}: {tm['total_ms']:.0f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt_p = time.perf_counter() - t0
+    n_prop = n_per * len(pts) * args.steps
+
+    # exactness at equal accuracy: u(0) of the two samplers' stored samples, per level
+    ks = {}
+    for lvl in W.LEARNED_EVAL_LEVELS:
+        idx = [i for i, s in enumerate(specs) if abs(s.beta_p * s.c32 - lvl) < 1e-6 * lvl]
+        pv = []
+        for i in idx:
+            xm = out_m[i]["xhat"][:20000].double().cpu().numpy()
+            xp = out_p[i]["xhat"][:20000].double().cpu().numpy()
+            if len(xm) > 20 and len(xp) > 20:
+                pv.append(float(sst.ks_2samp(xm[:, :K].sum(1), xp[:, :K].sum(1)).pvalue))
+        ks[f"{lvl:g}"] = {"min_p": min(pv) if pv else None, "median_p": float(np.median(pv)) if pv else None,
+                          "points": len(pv)}
+
+    # roofline of the dominant kernel: k_decide_mix, one launch per point
+    avg_launch_s = dec_ms_m / max(launches_m, 1) / 1e3
+    ops = alu_ops_per_proposal(K, "mixture", args.precision)
+    achieved = ops * n_per / avg_launch_s
+    mflops = mfma_flops_per_proposal(K, args.precision, "mixture")
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_OPS_PER_S / 1e12,
+            "unit": "T ALU ops/s", "frac": achieved / ALU_OPS_PER_S,
+            "traffic": load_traffic(K, args.precision, n_per, "k_decide_mix"), "kernel": "k_decide_mix",
+            "algorithmic_ops_per_proposal": ops, "avg_launch_ms": avg_launch_s * 1e3,
+            "proposals_per_launch": n_per, "mfma_flops_per_proposal": mflops,
+            "mfma_frac": mflops * n_per / avg_launch_s / (2.5e15 if args.precision != "fp32" else 157.3e12)}
+
+    n_cpu = (1 << 17) if args.cpu_sample < 0 else args.cpu_sample
+    cpu = cpu_plain = None
+    if n_cpu > 0:
+        print("cpu baseline ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline_mixture(specs, mixes, mplans, n_cpu)
+        cpu_plain = cpu_baseline(specs, splans, n_cpu)
+
+    per_point = [{"beta_p": s.beta_p, "level": s.beta_p * s.c32, "M_gain": math.exp(g),
+                  "acc_mixture": int(om["n_accepted"]) / n_per, "acc_plain": int(op["n_accepted"]) / n_per,
+                  "fp64_redecisions": int(om["n_fp64_fixups"]), "M_violations": int(om["n_M_violations"])}
+                 for s, g, om, op in zip(specs, log_gain, out_m, out_p)]
+    line = {
+        "metric": "accepted samples/sec at K=32 (learned-mixture vs plain proposal); proposals/sec",
+        "value": acc_m / dt_m,
+        "unit": "accepted samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt_m / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "learned mixture vs plain Sigma: K=32, N=128, E0=1, 16 beta' in [20, 60] x "
+                        "beta'C3/C2 in {9000, 12000} (32 points), 1e9 proposals/point per sampler; network "
+                        "3-256-256-160 fitted on beta'C3/C2 = 9000 (other seeds), eps = 0.2",
+            "K": K, "N": 4 * K, "points": len(pts), "proposals_per_point": n_per,
+            "synthesis": args.precision, "fp64_redecision": True,
+        },
+        "plain_value": acc_p / dt_p,
+        "ratio_vs_plain": (acc_m / dt_m) / (acc_p / dt_p) if acc_p else None,
+        "proposals_per_s": n_prop / dt_m,
+        "plain_proposals_per_s": n_prop / dt_p,
+        "acceptance": acc_m / n_prop,
+        "plain_acceptance": acc_p / n_prop,
+        "M_gain_geomean": math.exp(sum(log_gain) / len(log_gain)),
+        "M_violations_last_step": sum(int(o["n_M_violations"]) for o in out_m),
+        "ks_u0_mixture_vs_plain": ks,
+        "train_seconds": train_s,
+        "plan_seconds": plan_s,
+        "per_point": per_point,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "cpu_baseline_plain": cpu_plain,
+    }
+    print(json.dumps(line), flush=True)
+    res.learner.close()
+    ctx.close()
+    return 0
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="learned", choices=["learned", "plain"])
+    ap.add_argument("--proposals", type=float, default=1e9, help="proposals per point (per sampler)")
+    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16", "bf16x3"])
+    ap.add_argument("--cpu-sample", type=int, default=-1,
+                    help="oracle proposals per point (0: skip; default 2^22 plain, 2^17 learned)")
+    ap.add_argument("--train-rounds", type=int, default=6)
+    ap.add_argument("--train-steps", type=int, default=150)
+    ap.add_argument("--synthesis", action="store_true",
+                    help="only time the standalone synthesis kernel (K = 64, N = 256, 2^20 rows of x^ "
+                         "in HBM) for FP32, BF16 and BF16x3 products; prints one JSON line")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        src = torch.empty(args.calibrate_copy // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": args.calibrate_copy, "copies": 3}))
+        return 0
+    if args.synthesis:
+        return synthesis_bench(args)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sampler's proposals "
+              "are independent, and multi-GPU sharding is a design note, not a measured path.",
+              file=sys.stderr)
+        return 2
+
+    return learned_bench(args) if args.workload == "learned" else plain_bench(args)
 
 
 if __name__ == "__main__":

@@ -177,11 +177,16 @@ double window(const tkdv_point &pt, int proposal, int precision, double alpha, d
 {
     const int K = pt.K, N = 4 * K;
     const double eps_x = 1e-5;  // bound on |x^_fast - x^_exact|_2 (normals + projection)
+    // relative error of a synthesis sum of products, per sum of |products|:
+    // FP32 accumulation of 2K terms (2^-23 per addition, allowing truncation);
+    // BF16 products: both operands rounded (2^-9 each); BF16x3: with
+    // x = x_hi + x_lo + d, |d| <= 2^-18 |x| (two roundings to 8 significant
+    // bits), dropping lo*lo and d leaves at most 3 * 2^-18 per product
     double eps_s;
     switch (precision) {
-    case TKDV_FP32: eps_s = 2.0 * K * 0x1p-24; break;
-    case TKDV_BF16: eps_s = 1.01 * 0x1p-8 + 2.0 * K * 0x1p-24; break;
-    default: eps_s = 3.01 * 0x1p-16 + 2.0 * K * 0x1p-24; break;
+    case TKDV_FP32: eps_s = 2.0 * K * 0x1p-23; break;
+    case TKDV_BF16: eps_s = 1.01 * 0x1p-8 + 2.0 * K * 0x1p-23; break;
+    default: eps_s = 3.02 * 0x1p-18 + 2.0 * K * 0x1p-23; break;
     }
     const double amp = std::sqrt(2.0 * pt.E0 / kPi);
     const double du = std::sqrt((double)K) * (eps_s + eps_x);  // max_j |du~_j|, u~ unscaled
@@ -325,7 +330,12 @@ tkdv_status run(tkdv_ctx *ctx, Call &call, int precision, int proposal, float *d
         ctx->timing.decide_launches++;
     }
     HIP_TRY(ctx, hipEventRecord(ctx->ev[1], st));
-    HIP_TRY(ctx, launch_fixup(a, ctx->n_cu, st));
+    if (proposal == TKDV_PROP_MIXTURE) {
+        for (int ki = 0; ki < 4; ++ki)
+            if (call.plist_n[ki]) HIP_TRY(ctx, launch_fixup_mix(8 << ki, a, ctx->n_cu, st));
+    } else {
+        HIP_TRY(ctx, launch_fixup(a, ctx->n_cu, st));
+    }
     HIP_TRY(ctx, hipEventRecord(ctx->ev[2], st));
     if (stats) {
         unsigned long long *seg_cnt = reinterpret_cast<unsigned long long *>(ctx->seg_cnt.p);

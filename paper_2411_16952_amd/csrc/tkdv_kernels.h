@@ -12,6 +12,7 @@ hipError_t launch_decide(int K, int prec, int prop, const KernelArgs &a, const i
 hipError_t launch_decide_mix(int K, int prec, const KernelArgs &a, const int *plist, int n_plist, int n_cu,
                              unsigned long long total_tiles, hipStream_t st, int *grid_out);
 hipError_t launch_fixup(const KernelArgs &a, int n_cu, hipStream_t st);
+hipError_t launch_fixup_mix(int K, const KernelArgs &a, int n_cu, hipStream_t st);
 hipError_t launch_segments(const KernelArgs &a, unsigned long long total_segs, unsigned long long *seg_cnt,
                            unsigned long long *seg_base, PointResult *res, int n_cu, hipStream_t st);
 hipError_t launch_materialize(int K, int prop, const KernelArgs &a, const int *plist, int n_plist,

@@ -15,7 +15,9 @@
 //                  arithmetic as k_decide), writes it at its rank, and
 //                  accumulates FP64 moments, 2-sigma exceedances and the u(0)
 //                  histogram from an FP32 matrix-core synthesis.
-//   k_finalize     per point, segment partials summed in segment order.
+//   k_finalize     per point, segment partials summed in a fixed order.
+//   (mixture)      k_decide_mix and k_fixup_mix take the places of k_decide
+//                  and k_fixup for the learned proposal.
 #include <hip/hip_runtime.h>
 
 #include "tkdv_device.h"
@@ -386,72 +388,6 @@ __device__ void fp64_eval(const DevPoint &P, uint64_t i, double &log_a, double &
     log_a = lr - P.log_M64;
 }
 
-// FP64 evaluation of a listed proposal of the mixture sampler: the draw of
-// gen_x_mix in FP64 (component from the same word, in integers), then
-// log q_mix with x^T L0^-1 x = e^T A e + |g|^2, g = G^-1 V^T A w, e = w - V g
-// for w = R_j^T x^ (no cancellation), and log a = log f - log q_mix - log M.
-__device__ void fp64_eval_mix(const DevPoint &P, const DevMix &M, uint64_t i, double &log_a, double &log_u)
-{
-    const int K = P.K;
-    double x[2 * TKDV_KMAX];
-    const uint4 wl = fp64_normals(P, i, x);
-    log_u = log(((double)wl.x + 0.5) * 0x1p-32);
-    const double pi = 3.14159265358979323846;
-    const int comp = wl.y < M.E ? -1 : (int)((wl.y - M.E) / M.B);
-    if (comp < 0) {
-        for (int m = 0; m < 2 * K; ++m) x[m] *= P.sig64[m % K];
-    } else {
-        const double r = sqrt(-2.0 * log(((double)wl.z + 0.5) * 0x1p-32));
-        const double th = 2.0 * pi * (((double)wl.w + 0.5) * 0x1p-32);
-        const double e0 = r * cos(th), e1 = r * sin(th);
-        for (int k = 1; k <= K; ++k) {
-            const int mi = (k * comp) & (kMixS - 1);
-            const double cs = M.cs64[mi], sn = M.sn64[mi];
-            const double vc0 = M.V64[k - 1][0], vc1 = M.V64[k - 1][1];
-            const double vs0 = M.V64[K + k - 1][0], vs1 = M.V64[K + k - 1][1];
-            const double rc0 = vc0 * cs + vs0 * sn, rc1 = vc1 * cs + vs1 * sn;
-            const double rs0 = vs0 * cs - vc0 * sn, rs1 = vs1 * cs - vc1 * sn;
-            x[k - 1] = M.sqd64[k - 1] * x[k - 1] + rc0 * e0 + rc1 * e1;
-            x[K + k - 1] = M.sqd64[k - 1] * x[K + k - 1] + rs0 * e0 + rs1 * e1;
-        }
-    }
-    const double t = fp64_project(K, x);
-    const double lf = fp64_log_f(P, x, t);
-    double lj[kMixS];
-    double mx = -INFINITY;
-    for (int j = 0; j < kMixS; ++j) {
-        double w[2 * TKDV_KMAX];
-        double y0 = 0.0, y1 = 0.0;
-        for (int k = 1; k <= K; ++k) {  // w = R_j^T x: shift by -phi_j
-            const int mi = (k * j) & (kMixS - 1);
-            const double cs = M.cs64[mi], sn = M.sn64[mi];
-            const double xc = x[k - 1], xs = x[K + k - 1];
-            w[k - 1] = xc * cs - xs * sn;
-            w[K + k - 1] = xs * cs + xc * sn;
-            const double ac = M.a64[k - 1];
-            y0 += ac * (M.V64[k - 1][0] * w[k - 1] + M.V64[K + k - 1][0] * w[K + k - 1]);
-            y1 += ac * (M.V64[k - 1][1] * w[k - 1] + M.V64[K + k - 1][1] * w[K + k - 1]);
-        }
-        const double g0 = M.gi64[0][0] * y0 + M.gi64[0][1] * y1;
-        const double g1 = M.gi64[1][0] * y0 + M.gi64[1][1] * y1;
-        double qf = g0 * g0 + g1 * g1;
-        for (int m = 0; m < 2 * K; ++m) {
-            const double e = w[m] - (M.V64[m][0] * g0 + M.V64[m][1] * g1);
-            qf += M.a64[m % K] * e * e;
-        }
-        lj[j] = -K * log(qf);
-        mx = lj[j] > mx ? lj[j] : mx;
-    }
-    double se = 0.0;
-    for (int j = 0; j < kMixS; ++j) se += exp(lj[j] - mx);
-    const double lnet = -0.5 * M.logdetL0 + mx + log(se) - log((double)kMixS);
-    const double lg = M.lng - K * log1p(P.alpha_star * P.beta_p * t / ((double)K * K * K));
-    const double A = M.log_eps + lg, B = M.log_1m_eps + lnet;
-    const double hi = A > B ? A : B;
-    const double lq = hi + log(exp(A - hi) + exp(B - hi));
-    log_a = lf - lq - P.log_M64;
-}
-
 __global__ void __launch_bounds__(kBlock) k_fixup(KernelArgs a)
 {
     const unsigned long long cnt = *a.defer_count;
@@ -463,13 +399,135 @@ __global__ void __launch_bounds__(kBlock) k_fixup(KernelArgs a)
         const uint64_t i = v & ((1ull << 40) - 1ull);
         const DevPoint &P = a.pts[p];
         double la, lu;
-        if (P.proposal == PROP_MIXTURE) fp64_eval_mix(P, a.mix[p], i, la, lu);
-        else fp64_eval(P, i, la, lu);
+        fp64_eval(P, i, la, lu);
         if (lu < la) {
             const uint64_t local = i - P.i0;
             atomicOr(&a.bitmap[P.bm_off + local / 32], 1u << (local % 32));
             atomicAdd(&a.cnt[p].fix_accepted, 1ull);
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_fixup_mix: FP64 re-decision of listed proposals of the mixture sampler,
+// one wave per proposal, lane m = coordinate m (2K <= 64): the draw of
+// gen_x_mix in FP64 (component from the same word, in integers), log f with
+// H3 by the double sum over triads (lane n - 2 takes the inner sum of n),
+// and log q_mix with x^T L0^-1 x = e^T A e + |g|^2, g = G^-1 V^T A w,
+// e = w - V g for w = R_j^T x^ (no cancellation), summed over the shifts
+// with a running log-sum-exp.  log a = log f - log q_mix - log M.
+// ---------------------------------------------------------------------------
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_fixup_mix(KernelArgs a)
+{
+    __shared__ double xs[kBlock / kWave][2 * K];
+    const int m = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double *x = xs[wv];
+    const bool act = m < 2 * K;
+    const bool sinb = m >= K;
+    const int k = m % K + 1;  // mode of this lane's coordinate
+    const double pi = 3.14159265358979323846;
+    const unsigned long long cnt = *a.defer_count;
+    const unsigned long long n = cnt < a.defer_cap ? cnt : a.defer_cap;
+    const unsigned long long nw = (unsigned long long)gridDim.x * (kBlock / kWave);
+    for (unsigned long long e = (unsigned long long)blockIdx.x * (kBlock / kWave) + wv; e < n; e += nw) {
+        const unsigned long long v = bcast_lane0(a.defer_list[e]);
+        const int p = (int)(v >> 40);
+        const uint64_t i = v & ((1ull << 40) - 1ull);
+        const DevPoint &P = a.pts[p];
+        const DevMix &M = a.mix[p];
+        const uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32);
+        // normal of coordinate m: Box-Muller pair (words 2q, 2q+1) of block m/4
+        double z = 0.0;
+        if (act) {
+            const uint4 w = philox4x32_10(c0, c1, P.point_id, (uint32_t)(m / 4), P.key0, P.key1);
+            const int q = (m % 4) & ~1;
+            const uint32_t w1 = q == 0 ? w.x : w.z, w2 = q == 0 ? w.y : w.w;
+            const double r = sqrt(-2.0 * log(((double)w1 + 0.5) * 0x1p-32));
+            const double th = 2.0 * pi * (((double)w2 + 0.5) * 0x1p-32);
+            z = (m & 1) ? r * sin(th) : r * cos(th);
+        }
+        const uint4 wl = philox4x32_10(c0, c1, P.point_id, (uint32_t)(K / 2), P.key0, P.key1);
+        const double log_u = log(((double)wl.x + 0.5) * 0x1p-32);
+        const int comp = wl.y < M.E ? -1 : (int)((wl.y - M.E) / M.B);
+        double X = 0.0;
+        if (act) {
+            if (comp < 0) {
+                X = P.sig64[k - 1] * z;
+            } else {
+                const double r = sqrt(-2.0 * log(((double)wl.z + 0.5) * 0x1p-32));
+                const double th = 2.0 * pi * (((double)wl.w + 0.5) * 0x1p-32);
+                const double e0 = r * cos(th), e1 = r * sin(th);
+                const int mi = (k * comp) & (kMixS - 1);
+                const double cs = M.cs64[mi], sn = M.sn64[mi];
+                const double *vc = M.V64[k - 1], *vs = M.V64[K + k - 1];
+                const double r0 = sinb ? vs[0] * cs - vc[0] * sn : vc[0] * cs + vs[0] * sn;
+                const double r1 = sinb ? vs[1] * cs - vc[1] * sn : vc[1] * cs + vs[1] * sn;
+                X = M.sqd64[k - 1] * z + r0 * e0 + r1 * e1;
+            }
+        }
+        const double xm = X / sqrt(wave_sum_f64(X * X));
+        if (act) x[m] = xm;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const double t = wave_sum_f64(act ? (double)k * k * xm * xm : 0.0);
+        // H3 by the double sum: lane l takes n = l + 2
+        double tri = 0.0;
+        {
+            const int nn = m + 2;
+            if (nn <= K) {
+                const double s = sqrt(P.E0 / (2.0 * pi));
+                double in_re = 0.0, in_im = 0.0;
+                for (int kk = 1; kk < nn; ++kk) {
+                    const double pr = s * x[kk - 1], pi_ = -s * x[K + kk - 1];
+                    const double qr = s * x[nn - kk - 1], qi = -s * x[K + nn - kk - 1];
+                    in_re += pr * qr - pi_ * qi;
+                    in_im += pr * qi + pi_ * qr;
+                }
+                tri = (s * x[nn - 1]) * in_re + (-s * x[K + nn - 1]) * in_im;
+            }
+        }
+        const double H3 = 2.0 * pi * wave_sum_f64(tri);
+        const double lf = -(P.beta_p / (P.E0 * (double)K * K) * (P.E0 * t - P.c32 * H3));
+        // q_net over the shifts
+        const double xp = act ? x[sinb ? m - K : m + K] : 0.0;
+        const double am = act ? M.a64[k - 1] : 0.0;
+        const double v0 = act ? M.V64[m][0] : 0.0, v1 = act ? M.V64[m][1] : 0.0;
+        double mx = -INFINITY, se = 0.0;
+        for (int j = 0; j < kMixS; ++j) {
+            const int mi = (k * j) & (kMixS - 1);
+            const double cs = M.cs64[mi], sn = M.sn64[mi];
+            const double w = act ? (sinb ? xm * cs + xp * sn : xm * cs - xp * sn) : 0.0;
+            const double y0 = wave_sum_f64(v0 * am * w), y1 = wave_sum_f64(v1 * am * w);
+            const double g0 = M.gi64[0][0] * y0 + M.gi64[0][1] * y1;
+            const double g1 = M.gi64[1][0] * y0 + M.gi64[1][1] * y1;
+            const double ee = w - (v0 * g0 + v1 * g1);
+            const double qf = wave_sum_f64(am * ee * ee) + g0 * g0 + g1 * g1;
+            const double l = -K * log(qf);
+            if (l > mx) {
+                se = se * exp(mx - l) + 1.0;
+                mx = l;
+            } else {
+                se += exp(l - mx);
+            }
+        }
+        const double lnet = -0.5 * M.logdetL0 + mx + log(se) - log((double)kMixS);
+        const double lg = M.lng - K * log1p(P.alpha_star * P.beta_p * t / ((double)K * K * K));
+        const double A = M.log_eps + lg, B = M.log_1m_eps + lnet;
+        const double hi = A > B ? A : B;
+        const double lq = hi + log(exp(A - hi) + exp(B - hi));
+        const double log_a = lf - lq - P.log_M64;
+        // every lane issues the updates (lane 0 carries them): no lane-0-only
+        // region next to the wave reductions of the next iteration
+        const bool acc = __builtin_amdgcn_readfirstlane((int)(log_u < log_a)) != 0;
+        if (acc) {
+            const uint64_t local = i - P.i0;
+            atomicOr(&a.bitmap[P.bm_off + local / 32], m == 0 ? 1u << (local % 32) : 0u);
+            atomicAdd(&a.cnt[p].fix_accepted, m == 0 ? 1ull : 0ull);
+        }
+        // the next proposal overwrites this wave's copy of x^
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -735,17 +793,23 @@ __global__ void __launch_bounds__(kBlock) k_materialize(KernelArgs a, const int 
     }
 }
 
-// Per point: segment partials in segment order.
-__global__ void k_finalize(KernelArgs a, const unsigned long long *seg_cnt,
-                           const unsigned long long *seg_base, const SegStats *seg_stats,
-                           PointResult *res)
+// Per point (one workgroup): segment partials summed in a fixed order --
+// each thread takes a contiguous run of segments in order, then a fixed
+// pairwise tree over the threads -- so the result does not depend on
+// scheduling.
+__global__ void __launch_bounds__(kBlock) k_finalize(KernelArgs a, const unsigned long long *seg_cnt,
+                                                     const unsigned long long *seg_base,
+                                                     const SegStats *seg_stats, PointResult *res)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.n_points) return;
+    __shared__ double sS[4][kBlock];
+    __shared__ unsigned long long sE[kBlock], sN[kBlock];
+    const int p = blockIdx.x, tid = threadIdx.x;
     const DevPoint &P = a.pts[p];
+    const unsigned long long per = (P.n_segs + kBlock - 1) / kBlock;
+    const unsigned long long s0 = per * tid, s1 = s0 + per < P.n_segs ? s0 + per : P.n_segs;
     double S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0;
     unsigned long long ex = 0, ns = 0;
-    for (unsigned long long s = 0; s < P.n_segs; ++s) {
+    for (unsigned long long s = s0; s < s1; ++s) {
         const unsigned long long gs = P.seg_off + s;
         if (seg_cnt[gs] == 0 || seg_base[gs] >= P.target) continue;
         const SegStats &st = seg_stats[gs];
@@ -756,13 +820,30 @@ __global__ void k_finalize(KernelArgs a, const unsigned long long *seg_cnt,
         ex += st.n_exceed;
         ns += st.n_samples;
     }
-    res[p].S1 = S1;
-    res[p].S2 = S2;
-    res[p].S3 = S3;
-    res[p].S4 = S4;
-    res[p].n_exceed = ex;
-    res[p].n_samples = ns;
-    res[p].n_written = ns < P.capacity ? ns : P.capacity;
+    sS[0][tid] = S1;
+    sS[1][tid] = S2;
+    sS[2][tid] = S3;
+    sS[3][tid] = S4;
+    sE[tid] = ex;
+    sN[tid] = ns;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+            for (int q = 0; q < 4; ++q) sS[q][tid] += sS[q][tid + w];
+            sE[tid] += sE[tid + w];
+            sN[tid] += sN[tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        res[p].S1 = sS[0][0];
+        res[p].S2 = sS[1][0];
+        res[p].S3 = sS[2][0];
+        res[p].S4 = sS[3][0];
+        res[p].n_exceed = sE[0];
+        res[p].n_samples = sN[0];
+        res[p].n_written = sN[0] < P.capacity ? sN[0] : P.capacity;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -967,6 +1048,18 @@ hipError_t launch_decide_mix(int K, int prec, const KernelArgs &a, const int *pl
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_fixup_mix(int K, const KernelArgs &a, int n_cu, hipStream_t st)
+{
+    const dim3 g(8 * n_cu), b(kBlock);
+    switch (K) {
+    case 8: hipLaunchKernelGGL(k_fixup_mix<8>, g, b, 0, st, a); break;
+    case 16: hipLaunchKernelGGL(k_fixup_mix<16>, g, b, 0, st, a); break;
+    case 32: hipLaunchKernelGGL(k_fixup_mix<32>, g, b, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_fixup(const KernelArgs &a, int n_cu, hipStream_t st)
 {
     hipLaunchKernelGGL(k_fixup, dim3(4 * n_cu), dim3(kBlock), 0, st, a);
@@ -1031,8 +1124,7 @@ hipError_t launch_finalize(const KernelArgs &a, const unsigned long long *seg_cn
                            const unsigned long long *seg_base, const SegStats *seg_stats, PointResult *res,
                            hipStream_t st)
 {
-    const int nb = (a.n_points + 63) / 64;
-    hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(64), 0, st, a, seg_cnt, seg_base, seg_stats, res);
+    hipLaunchKernelGGL(k_finalize, dim3(a.n_points), dim3(kBlock), 0, st, a, seg_cnt, seg_base, seg_stats, res);
     return hipGetLastError();
 }
 

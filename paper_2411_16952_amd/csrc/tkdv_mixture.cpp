@@ -243,9 +243,9 @@ double mix_window_extra(const MixHost &mh, int precision)
     const double eps_x = 1e-5;  // bound on |x^_fast - x^_exact|_2 of the draw
     double eps_p;               // relative error of the y products (per sum of |terms|)
     switch (precision) {
-    case TKDV_FP32: eps_p = 2.0 * K * 0x1p-24; break;
-    case TKDV_BF16: eps_p = 1.01 * 0x1p-8 + 2.0 * K * 0x1p-24; break;
-    default: eps_p = 3.01 * 0x1p-16 + 2.0 * K * 0x1p-24; break;
+    case TKDV_FP32: eps_p = 2.0 * K * 0x1p-23; break;
+    case TKDV_BF16: eps_p = 1.01 * 0x1p-8 + 2.0 * K * 0x1p-23; break;
+    default: eps_p = 3.02 * 0x1p-18 + 2.0 * K * 0x1p-23; break;
     }
     double dmin = INFINITY, dmax = 0.0, vf2 = 0.0, avf2 = 0.0;
     for (int k = 0; k < K; ++k) {

@@ -46,3 +46,25 @@ PLAIN_GPU = dict(n_proposals=10**9, N=128)
 # Precision: K = 64, N = 256, beta' = 40, C3/C2 in {0, 300}, batches of 2^20.
 PRECISION_POINTS = [PointSpec(64, 1.0, 40.0, 0.0, 7, 0), PointSpec(64, 1.0, 40.0, 300.0, 7, 1)]
 PRECISION_BATCH = 1 << 20
+
+# Learned proposal: K = 32, training points beta' = linspace(20, 60, 16) at
+# beta' C3/C2 = 9000 (acceptance of the paper's proposal ~4e-5); evaluation
+# on the same 16 beta' at beta' C3/C2 = 9000 and 12000 with other seeds and
+# point ids.  Defensive weight eps = 0.2.
+LEARNED_BETAS = tuple(20.0 + 40.0 * i / 15.0 for i in range(16))
+LEARNED_TRAIN_LEVEL = 9000.0
+LEARNED_EVAL_LEVELS = (9000.0, 12000.0)
+LEARNED_EPS = 0.2
+
+
+def learned_train_points() -> list[PointSpec]:
+    return [PointSpec(32, 1.0, bp, LEARNED_TRAIN_LEVEL / bp, 100 + i, i) for i, bp in enumerate(LEARNED_BETAS)]
+
+
+def learned_eval_points() -> list[PointSpec]:
+    pts = []
+    for lvl in LEARNED_EVAL_LEVELS:
+        for bp in LEARNED_BETAS:
+            pid = 1000 + len(pts)
+            pts.append(PointSpec(32, 1.0, bp, lvl / bp, pid, pid))
+    return pts

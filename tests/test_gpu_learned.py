@@ -166,3 +166,44 @@ def test_training_gains_over_the_paper_proposal(T, ctx):
     h3s = np.array([oracle.H3_triad(x / np.linalg.norm(x), 1.0) for x in xs[:3000]])
     assert stats.ks_2samp(h3m, h3s).pvalue > 0.01
     res.learner.close()
+
+
+def test_k32_learned_mixture_is_exact(T, ctx):
+    """The K = 32 configuration: a network fitted on 16 beta' in [20, 60] at
+    C3/C2 = 9000/beta'; at held-out seeds and at C3/C2 = 12000/beta' the
+    rejection bound must hold on exact samples of f (the paper's sampler's
+    accepted samples: log f - log q_mix - log M_mix <= 0 at every one of them),
+    and the mixture sampler's samples must follow the same law (KS on u(0) and
+    H3)."""
+    from scipy import stats
+    from paper_2411_16952_amd import learned
+    K = 32
+    bps = np.linspace(20, 60, 16)
+    pts = [T.make_point(K, 1.0, float(b), 9000.0 / float(b), seed=100 + i, point_id=i) for i, b in enumerate(bps)]
+    cfg = T.learner_cfg(K, hidden=256, v_amp=0.5, v_scale=1.0, lr=3e-3, seed=7)
+    res = learned.fit(ctx, pts, cfg, samples_per_point=4096, rounds=6, steps=150, max_proposals=1 << 36, log=say)
+    for bp, P in [(40.0, 9000.0), (20.0, 12000.0)]:
+        pt = T.make_point(K, 1.0, bp, P / bp, seed=4242, point_id=9)
+        mix, pl, sp = learned.plan_for(res, pt, margin=0.02)
+        gain = math.exp(learned.log_M_sigma_normalised(sp) - pl.log_M)
+        rs = ctx.sample(pt, 1 << 31, proposal=T.SIGMA, plan=sp, precision=T.BF16X3, capacity=40000)
+        xs = rs["xhat"].cpu().numpy().astype(np.float64)
+        xs /= np.linalg.norm(xs, axis=1)[:, None]
+        mo = oracle.make_mixture(K, mix.eps, np.array(mix.logd[:K]),
+                                 np.array([[mix.V[r][q] for q in range(2)] for r in range(2 * K)]))
+        la = np.array([oracle.log_ratio(x, 1.0, bp, P / bp, sp.alpha_star, 0)
+                       - oracle.mix_log_q(K, 1.0, bp, P / bp, sp.alpha_star, mo, x)[1] for x in xs]) - pl.log_M
+        rm = ctx.sample_mixture(pt, pl, mix, 1 << 28, precision=T.BF16X3, capacity=40000)
+        say(f"beta'={bp} P={P}: M gain {gain:.1f}; {len(xs)} exact samples, max log a_mix {la.max():.4f}; "
+            f"mixture acc {rm['acceptance']:.3e} (sigma {rs['acceptance']:.3e}), violations {rm['n_M_violations']}")
+        assert la.max() <= 0.0, "the rejection bound fails on an exact sample of f"
+        assert rm["n_M_violations"] == 0
+        xm = rm["xhat"].cpu().numpy().astype(np.float64)
+        xm /= np.linalg.norm(xm, axis=1)[:, None]
+        p_u0 = stats.ks_2samp(xm[:, :K].sum(1), xs[:, :K].sum(1)).pvalue
+        h3m = np.array([oracle.H3_triad(x, 1.0) for x in xm[:len(xs)]])
+        h3s = np.array([oracle.H3_triad(x, 1.0) for x in xs])
+        p_h3 = stats.ks_2samp(h3m, h3s).pvalue
+        say(f"   KS p-values: u(0) {p_u0:.3f}, H3 {p_h3:.3f}")
+        assert p_u0 > 0.01 and p_h3 > 0.01
+    res.learner.close()
