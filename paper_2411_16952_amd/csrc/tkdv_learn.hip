@@ -7,12 +7,18 @@
 //                   the gradient of log|L0|
 //   k_mix_fwd       per row (one wave, a lane per coordinate): log q_net and
 //                   log q_mix over the S shifts (online log-sum-exp)
-//   k_loss_max/sum  per point soft maximum of r_s = log f - log q_mix
-//   k_mix_bwd       per row: dL/d(log d, V) of the point, accumulated over
-//                   the row's shifts and summed over a wave's rows
-//   k_param_grad    per point: adds the log|L0| term, maps to dL/do
+//   k_loss_max      per point maximum of r_s = log f - log q_mix
+//   k_loss_chunk    per chunk of a point's rows: sum of exp(r_s/T - max), NLL
+//   k_loss_final    per point: chunk partials in order -> soft maximum, loss
+//   k_mix_bwd       per chunk: dL/d(log d, V) of the point, accumulated over
+//                   the rows' shifts in row order
+//   k_param_grad    per point: chunk partials in order, the log|L0| term,
+//                   dL/do
 //   k_mlp_bwd_*     back through the layers; dL/dweights summed over points
 //   k_adam          the update
+// Rows are grouped by point (an index order) and cut into chunks of at most
+// kChunk rows of one point; every sum runs in a fixed order, so a step is
+// deterministic.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,6 +38,7 @@ namespace tkdv {
 
 constexpr int kLKMax = 32;        // largest K of the learned proposal
 constexpr int kMaxHidden = 256;
+constexpr int kChunk = 32;        // rows per chunk of the reductions
 
 struct LearnPoint {
     double z[3];
@@ -39,6 +46,7 @@ struct LearnPoint {
     double E0, beta_p, c32;
     double lng, gc;        // sum_k ln(1 + gc k^2), gc = alpha beta'/K^3
     double inv_n_acc;      // 1 / (accepted rows of the point), 0 if none
+    uint32_t chunk0, chunk1;  // the point's chunks [chunk0, chunk1)
 };
 
 struct LearnParam {
@@ -54,11 +62,13 @@ struct LearnStats {
     unsigned long long maxkey;  // order-preserving key of max_s r_s/T
     double sum;                 // sum_s exp(r_s/T - max)
     double nll;                 // sum over accepted rows of -log q_net
-    double csum;                // sum_s c_s (c_s = dL/d log q_net(x_s))
     double loss;
-    double gd[kLKMax];          // sum_s c_s d log q_net/d log d_k (without the log|L0| term)
-    double gv[2 * kLKMax][2];
 };
+
+// Partials of one chunk: [sum, nll, csum, gd (K), gv (2K x 2)], csum = sum of
+// c_s = dL/d log q_net(x_s), gd/gv = sum of c_s d log q_net/d(log d, V)
+// without the log|L0| term.
+constexpr int chunk_part_len(int K) { return 3 + 5 * K; }
 
 struct LearnArgs {
     const double *X;         // rows [n][2K]
@@ -70,6 +80,12 @@ struct LearnArgs {
     const LearnPoint *pts;
     const LearnParam *par;
     LearnStats *st;
+    const uint32_t *order;        // row indices grouped by point
+    const uint32_t *chunk_start;  // [n_chunks + 1] offsets into order
+    const int *chunk_point;       // [n_chunks]
+    unsigned n_chunks;
+    double *part;                 // [n_chunks][pt_len]
+    int pt_len;                   // 3 + 5K
     double T, lambda, log_eps, log_1m_eps;
 };
 
@@ -366,64 +382,71 @@ __global__ void k_loss_max(LearnArgs A)
         atomicMax(&A.st[A.row_point[r]].maxkey, dkey((A.lf[r] - A.lmix[r]) / A.T));
 }
 
-__global__ void k_loss_sum(LearnArgs A)
+// Sum of exp(r_s/T - max) and of -log q_net over the accepted rows, per chunk
+// (one wave; lane-strided then a fixed butterfly).
+__global__ void __launch_bounds__(256) k_loss_chunk(LearnArgs A)
 {
-    for (unsigned long long r = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; r < A.n;
-         r += (unsigned long long)gridDim.x * blockDim.x) {
-        LearnStats &S = A.st[A.row_point[r]];
-        atomicAdd(&S.sum, exp((A.lf[r] - A.lmix[r]) / A.T - dkey_inv(S.maxkey)));
-        if (A.kind[r] == 0) atomicAdd(&S.nll, -A.lnet[r]);
+    const int m = threadIdx.x & 63;
+    const unsigned c = __builtin_amdgcn_readfirstlane((blockIdx.x * 256 + threadIdx.x) >> 6);
+    if (c >= A.n_chunks) return;
+    const int p = A.chunk_point[c];
+    const double mx = dkey_inv(A.st[p].maxkey);
+    double se = 0.0, nll = 0.0;
+    for (unsigned q = A.chunk_start[c] + m; q < A.chunk_start[c + 1]; q += 64) {
+        const unsigned r = A.order[q];
+        se += exp((A.lf[r] - A.lmix[r]) / A.T - mx);
+        nll += A.kind[r] == 0 ? -A.lnet[r] : 0.0;
+    }
+    se = wsum(se);
+    nll = wsum(nll);
+    if (m == 0) {
+        A.part[(size_t)c * A.pt_len + 0] = se;
+        A.part[(size_t)c * A.pt_len + 1] = nll;
     }
 }
 
+// Per point: chunk partials in chunk order -> soft maximum and loss.
 __global__ void k_loss_final(LearnArgs A, int n_points)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n_points) return;
     LearnStats &S = A.st[p];
-    S.loss = S.sum > 0.0 ? A.T * (dkey_inv(S.maxkey) + log(S.sum)) + A.lambda * S.nll * A.pts[p].inv_n_acc
-                         : A.lambda * S.nll * A.pts[p].inv_n_acc;
+    const LearnPoint &L = A.pts[p];
+    double se = 0.0, nll = 0.0;
+    for (unsigned c = L.chunk0; c < L.chunk1; ++c) {
+        se += A.part[(size_t)c * A.pt_len + 0];
+        nll += A.part[(size_t)c * A.pt_len + 1];
+    }
+    S.sum = se;
+    S.nll = nll;
+    S.loss = se > 0.0 ? A.T * (dkey_inv(S.maxkey) + log(se)) + A.lambda * nll * L.inv_n_acc
+                      : A.lambda * nll * L.inv_n_acc;
 }
 
-// dL/d(log d, V) of each row's point.  c_s = dL/d log q_net(x_s):
+// dL/d(log d, V) per chunk (one wave, rows in order).  c_s = dL/d log q_net(x_s):
 //   -w_s rho_s - lambda/n_acc [kind 0],  w_s = softmax_s(r_s/T),
 //   rho_s = (1 - eps) q_net/q_mix.
 // d log q_net/dV_mq = sum_j pi_j (2K/qf_j) (A e_j)_m g_jq,
 // d log q_net/d log d_k = sum_j pi_j (K/qf_j) sum_{m in k} a_m e_jm^2
 // (pi_j = softmax_j l_j), without the -log|L0|/2 term (added per point).
 template <int K>
-__global__ void __launch_bounds__(256) k_mix_bwd(LearnArgs A, unsigned long long rows_per_wave)
+__global__ void __launch_bounds__(256) k_mix_bwd(LearnArgs A)
 {
     const int m = threadIdx.x & 63;
-    const unsigned long long wave = ((unsigned long long)blockIdx.x * 256 + threadIdx.x) >> 6;
-    const unsigned long long r0 = wave * rows_per_wave;
-    const unsigned long long r1 = r0 + rows_per_wave < A.n ? r0 + rows_per_wave : A.n;
-    int cur = -1;
+    const unsigned c = __builtin_amdgcn_readfirstlane((blockIdx.x * 256 + threadIdx.x) >> 6);
+    if (c >= A.n_chunks) return;
+    const int p = A.chunk_point[c];
+    const LearnPoint &L = A.pts[p];
+    const LearnParam &Q = A.par[p];
+    const LearnStats &S = A.st[p];
+    const double mx = dkey_inv(S.maxkey);
     double gv0 = 0.0, gv1 = 0.0, gd = 0.0, cs_acc = 0.0;
-    auto flush = [&](int p) {
-        if (p < 0) return;
-        LearnStats &S = A.st[p];
-        if (m < 2 * K) {
-            atomicAdd(&S.gv[m][0], gv0);
-            atomicAdd(&S.gv[m][1], gv1);
-            atomicAdd(&S.gd[m % K], gd);
-        }
-        if (m == 0) atomicAdd(&S.csum, cs_acc);
-        gv0 = gv1 = gd = cs_acc = 0.0;
-    };
-    for (unsigned long long r = r0; r < r1; ++r) {
-        const int p = __builtin_amdgcn_readfirstlane(A.row_point[r]);
-        if (p != cur) {
-            flush(cur);
-            cur = p;
-        }
-        const LearnPoint &L = A.pts[p];
-        const LearnParam &Q = A.par[p];
-        const LearnStats &S = A.st[p];
-        const double ws = exp((A.lf[r] - A.lmix[r]) / A.T - dkey_inv(S.maxkey)) / S.sum;
+    for (unsigned q = A.chunk_start[c]; q < A.chunk_start[c + 1]; ++q) {
+        const unsigned r = A.order[q];
+        const double ws = exp((A.lf[r] - A.lmix[r]) / A.T - mx) / S.sum;
         const double rho = exp(A.log_1m_eps + A.lnet[r] - A.lmix[r]);
-        const double c = -ws * rho - (A.kind[r] == 0 ? A.lambda * L.inv_n_acc : 0.0);
-        cs_acc += c;
+        const double cf = -ws * rho - (A.kind[r] == 0 ? A.lambda * L.inv_n_acc : 0.0);
+        cs_acc += cf;
         RowMix<K> R;
         R.load(A, Q, r, m);
         // log-sum-exp of l_j: ln(sum_j qf_j^-K) relative to the row's q_net
@@ -432,37 +455,55 @@ __global__ void __launch_bounds__(256) k_mix_bwd(LearnArgs A, unsigned long long
             double w, e, qf, g0, g1;
             R.shift(Q, c_cs, c_sn, j, w, e, qf, g0, g1);
             const double pi = exp(-K * log(qf) - lse);
-            const double f = c * pi * K / qf;
+            const double f = cf * pi * K / qf;
             const double ae = R.am * e;
             gv0 += 2.0 * f * ae * g0;
             gv1 += 2.0 * f * ae * g1;
             gd += f * ae * e;
         }
     }
-    flush(cur);
+    // the two coordinates of mode m + 1
+    const double gd_pair = gd + __shfl(gd, (m + K) & 63, 64);
+    double *o = A.part + (size_t)c * A.pt_len;
+    if (m == 0) o[2] = cs_acc;
+    if (m < K) o[3 + m] = gd_pair;
+    if (m < 2 * K) {
+        o[3 + K + 2 * m] = gv0;
+        o[3 + K + 2 * m + 1] = gv1;
+    }
 }
 
-// Per point: dL/dtheta = sample sums - (1/2) csum d log|L0|/dtheta; dL/do.
+// Per point: dL/dtheta = chunk sums (in order) - (1/2) csum d log|L0|/dtheta; dL/do.
 template <int K>
-__global__ void __launch_bounds__(64) k_param_grad(const LearnParam *par, const LearnStats *st, int n_out,
-                                                   double v_scale, double *dout, double *gmix)
+__global__ void __launch_bounds__(64) k_param_grad(const LearnArgs A, int n_out, double v_scale, double *dout,
+                                                   double *gmix)
 {
     const int p = blockIdx.x, m = threadIdx.x;
-    const LearnParam &Q = par[p];
-    const LearnStats &S = st[p];
+    const LearnParam &Q = A.par[p];
+    const LearnPoint &L = A.pts[p];
+    double cs = 0.0, gd = 0.0, g0 = 0.0, g1 = 0.0;
+    for (unsigned c = L.chunk0; c < L.chunk1; ++c) {
+        const double *o = A.part + (size_t)c * A.pt_len;
+        cs += o[2];
+        if (m < K) gd += o[3 + m];
+        if (m < 2 * K) {
+            g0 += o[3 + K + 2 * m];
+            g1 += o[3 + K + 2 * m + 1];
+        }
+    }
     double *d = dout + (size_t)p * n_out;
     double *g = gmix + (size_t)p * 5 * K;
     if (m < K) {
-        const double v = S.gd[m] - 0.5 * S.csum * Q.dld_logd[m];
+        const double v = gd - 0.5 * cs * Q.dld_logd[m];
         d[m] = v;
         g[m] = v;
     }
     if (m < 2 * K) {
-        for (int q = 0; q < 2; ++q) {
-            const double v = S.gv[m][q] - 0.5 * S.csum * Q.dld_V[m][q];
-            g[K + 2 * m + q] = v;
-            d[K + 2 * m + q] = v_scale * v;
-        }
+        const double v0 = g0 - 0.5 * cs * Q.dld_V[m][0], v1 = g1 - 0.5 * cs * Q.dld_V[m][1];
+        g[K + 2 * m] = v0;
+        g[K + 2 * m + 1] = v1;
+        d[K + 2 * m] = v_scale * v0;
+        d[K + 2 * m + 1] = v_scale * v1;
     }
 }
 
@@ -510,6 +551,9 @@ struct tkdv_learner {
     std::vector<uint64_t> n_acc;
     Buf W, gW, m1, m2, z, h1, h2, out, dh1, dh2, dout, gmix, par, pts, st;
     Buf X, row_point, kind, lf, lnet, lmix;
+    Buf order, chunk_start, chunk_point, part;  // rows grouped by point, chunks, chunk partials
+    std::vector<int> h_row_point;
+    unsigned n_chunks = 0;
     unsigned long long n_rows = 0, cap_rows = 0;
     long long step = 0;
     int n_cu = 256;
@@ -583,6 +627,12 @@ LearnArgs args(tkdv_learner *L)
     A.pts = L->pts.as<LearnPoint>();
     A.par = L->par.as<LearnParam>();
     A.st = L->st.as<LearnStats>();
+    A.order = L->order.as<uint32_t>();
+    A.chunk_start = L->chunk_start.as<uint32_t>();
+    A.chunk_point = L->chunk_point.as<int>();
+    A.n_chunks = L->n_chunks;
+    A.part = L->part.as<double>();
+    A.pt_len = chunk_part_len(L->K);
     A.T = L->cfg.temperature;
     A.lambda = L->cfg.nll_weight;
     const uint64_t E = (uint64_t)TKDV_MIX_S * (uint64_t)std::floor(L->cfg.eps * 4294967296.0 / TKDV_MIX_S);
@@ -602,10 +652,7 @@ hipError_t launch_rows(tkdv_learner *L, const LearnArgs &A, hipStream_t st, bool
         g = std::min<unsigned long long>(g, 64ull * L->n_cu);
         hipLaunchKernelGGL(k_mix_fwd<K>, dim3((unsigned)g), dim3(256), 0, st, A);
     } else {
-        const unsigned long long waves = std::min<unsigned long long>(n, 16ull * L->n_cu);
-        const unsigned long long per = (n + waves - 1) / waves;
-        const unsigned long long g = ((n + per - 1) / per + 3) / 4;
-        hipLaunchKernelGGL(k_mix_bwd<K>, dim3((unsigned)g), dim3(256), 0, st, A, per);
+        hipLaunchKernelGGL(k_mix_bwd<K>, dim3((A.n_chunks + 3) / 4), dim3(256), 0, st, A);
     }
     return hipGetLastError();
 }
@@ -622,8 +669,8 @@ hipError_t rows_pass(tkdv_learner *L, const LearnArgs &A, hipStream_t st, bool b
 template <int K>
 hipError_t launch_pgrad(tkdv_learner *L, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_param_grad<K>, dim3(L->n_points), dim3(64), 0, st, L->par.as<LearnParam>(),
-                       L->st.as<LearnStats>(), L->n_out, L->cfg.v_scale, L->dout.as<double>(), L->gmix.as<double>());
+    hipLaunchKernelGGL(k_param_grad<K>, dim3(L->n_points), dim3(64), 0, st, args(L), L->n_out, L->cfg.v_scale,
+                       L->dout.as<double>(), L->gmix.as<double>());
     return hipGetLastError();
 }
 
@@ -641,7 +688,7 @@ tkdv_status evaluate(tkdv_learner *L, hipStream_t st)
     const unsigned long long g = std::min<unsigned long long>((L->n_rows + 255) / 256 + 1, 4096);
     hipLaunchKernelGGL(k_loss_max, dim3((unsigned)g), dim3(256), 0, st, A);
     LTRY(hipGetLastError());
-    hipLaunchKernelGGL(k_loss_sum, dim3((unsigned)g), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_loss_chunk, dim3((A.n_chunks + 3) / 4), dim3(256), 0, st, A);
     LTRY(hipGetLastError());
     hipLaunchKernelGGL(k_loss_final, dim3((np + 63) / 64), dim3(64), 0, st, A, np);
     LTRY(hipGetLastError());
@@ -705,8 +752,46 @@ tkdv_status grow_rows(tkdv_learner *L, unsigned long long need, hipStream_t st)
     return TKDV_OK;
 }
 
+// Rows grouped by point in insertion order, cut into chunks of at most kChunk
+// rows of one point; uploads the index order, the chunk table and the
+// points' chunk ranges.
+tkdv_status build_chunks(tkdv_learner *L, hipStream_t st)
+{
+    const int np = L->n_points;
+    std::vector<std::vector<uint32_t>> by(np);
+    for (uint32_t r = 0; r < (uint32_t)L->h_row_point.size(); ++r) by[L->h_row_point[r]].push_back(r);
+    std::vector<uint32_t> order, cstart;
+    std::vector<int> cpoint;
+    for (int p = 0; p < np; ++p) {
+        L->hpts[p].chunk0 = (uint32_t)cpoint.size();
+        for (size_t q = 0; q < by[p].size(); q += kChunk) {
+            cstart.push_back((uint32_t)(order.size() + q));
+            cpoint.push_back(p);
+        }
+        order.insert(order.end(), by[p].begin(), by[p].end());
+        L->hpts[p].chunk1 = (uint32_t)cpoint.size();
+    }
+    cstart.push_back((uint32_t)order.size());
+    L->n_chunks = (unsigned)cpoint.size();
+    LTRY(L->order.ensure(std::max<size_t>(order.size(), 1) * 4));
+    LTRY(L->chunk_start.ensure(cstart.size() * 4));
+    LTRY(L->chunk_point.ensure(std::max<size_t>(cpoint.size(), 1) * 4));
+    LTRY(L->part.ensure(std::max<size_t>(cpoint.size(), 1) * chunk_part_len(L->K) * 8));
+    if (!order.empty())
+        LTRY(hipMemcpyAsync(L->order.p, order.data(), order.size() * 4, hipMemcpyHostToDevice, st));
+    LTRY(hipMemcpyAsync(L->chunk_start.p, cstart.data(), cstart.size() * 4, hipMemcpyHostToDevice, st));
+    if (!cpoint.empty())
+        LTRY(hipMemcpyAsync(L->chunk_point.p, cpoint.data(), cpoint.size() * 4, hipMemcpyHostToDevice, st));
+    LTRY(hipStreamSynchronize(st));
+    return TKDV_OK;
+}
+
 tkdv_status upload_points(tkdv_learner *L, hipStream_t st)
 {
+    {
+        tkdv_status s = build_chunks(L, st);
+        if (s != TKDV_OK) return s;
+    }
     for (int p = 0; p < L->n_points; ++p) L->hpts[p].inv_n_acc = L->n_acc[p] ? 1.0 / (double)L->n_acc[p] : 0.0;
     LTRY(hipMemcpyAsync(L->pts.p, L->hpts.data(), sizeof(LearnPoint) * L->n_points, hipMemcpyHostToDevice, st));
     LTRY(hipStreamSynchronize(st));
@@ -797,7 +882,8 @@ tkdv_status tkdv_learner_destroy(tkdv_learner *L)
     if (!L) return TKDV_OK;
     (void)hipSetDevice(L->device);
     Buf *bs[] = {&L->W, &L->gW, &L->m1, &L->m2, &L->z, &L->h1, &L->h2, &L->out, &L->dh1, &L->dh2, &L->dout,
-                 &L->gmix, &L->par, &L->pts, &L->st, &L->X, &L->row_point, &L->kind, &L->lf, &L->lnet, &L->lmix};
+                 &L->gmix, &L->par, &L->pts, &L->st, &L->X, &L->row_point, &L->kind, &L->lf, &L->lnet, &L->lmix,
+                 &L->order, &L->chunk_start, &L->chunk_point, &L->part};
     for (Buf *b : bs) b->release();
     delete L;
     return TKDV_OK;
@@ -817,6 +903,7 @@ tkdv_status tkdv_learner_set_points(tkdv_learner *L, int32_t n_points, const tkd
     L->hpts = hp;
     L->n_acc.assign(n_points, 0);
     L->n_rows = 0;
+    L->h_row_point.clear();
     const size_t np = n_points, H = L->H, no = L->n_out;
     LTRY(L->z.ensure(np * 3 * 8));
     LTRY(L->h1.ensure(np * H * 8));
@@ -863,6 +950,7 @@ tkdv_status tkdv_learner_add_rows(tkdv_learner *L, int32_t point, const float *d
     LTRY(e);
     LTRY(hipStreamSynchronize(st));
     L->n_rows += n;
+    L->h_row_point.insert(L->h_row_point.end(), n, point);
     if (kind == 0) L->n_acc[point] += n;
     return upload_points(L, st);
 }
@@ -899,6 +987,7 @@ tkdv_status tkdv_learner_add_rows_host(tkdv_learner *L, int32_t point, const dou
     LTRY(e);
     LTRY(hipDeviceSynchronize());
     L->n_rows += n;
+    L->h_row_point.insert(L->h_row_point.end(), n, point);
     if (kind == 0) L->n_acc[point] += n;
     return upload_points(L, nullptr);
 }

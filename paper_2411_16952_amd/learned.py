@@ -42,6 +42,7 @@ class FitResult:
     points: list
     sigma_plans: list
     history: list = field(default_factory=list)   # per round: per-point log gain, loss, seconds
+    best_round: int = -1                           # the round whose weights were kept
 
     def mixture(self, i: int) -> T.Mixture:
         return self.learner.mixture(self.points[i], self.sigma_plans[i])
@@ -68,6 +69,7 @@ def fit(ctx: T.Context, points: list, cfg: T.LearnerCfg, samples_per_point: int 
     S = T.MIX_S
     fracs = [2 * math.pi * (q + 1) / ((n_shift_copies + 1) * S) for q in range(n_shift_copies)]
     starts = [[] for _ in points]
+    best = (-np.inf, None, -1)
     for rnd in range(rounds + 1):
         t0 = time.time()
         gains = []
@@ -80,6 +82,10 @@ def fit(ctx: T.Context, points: list, cfg: T.LearnerCfg, samples_per_point: int 
                 rows = np.vstack([am[None, :], shift_rows(am, fracs)])
                 L.add_rows(i, rows, kind=1)
                 starts[i].append(am)
+        # the weights of the round with the best mean log M_Sigma/M_mix over the
+        # training points (the fit is not monotone in this measure)
+        if np.mean(gains) > best[0]:
+            best = (float(np.mean(gains)), L.get_weights(), rnd)
         loss = L.train(steps) if rnd < rounds else None
         res.history.append({"round": rnd, "log_gain": gains, "loss": None if loss is None else loss.tolist(),
                             "seconds": time.time() - t0})
@@ -87,6 +93,10 @@ def fit(ctx: T.Context, points: list, cfg: T.LearnerCfg, samples_per_point: int 
             g = np.exp(np.array(gains))
             log(f"round {rnd}: M_Sigma/M_mix min {g.min():.2f} median {np.median(g):.2f} max {g.max():.2f}"
                 + ("" if loss is None else f", loss {np.mean(loss):.4f}") + f" ({time.time() - t0:.1f}s)")
+    L.set_weights(best[1])
+    res.best_round = best[2]
+    if log:
+        log(f"kept the weights of round {best[2]} (mean M_Sigma/M_mix {math.exp(best[0]):.2f})")
     return res
 
 
