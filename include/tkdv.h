@@ -159,7 +159,7 @@ typedef struct {
     int32_t decide_launches;
     int32_t decide_grid;    /* workgroups of the (last) k_decide launch             */
     int32_t decide_block;   /* threads per workgroup                                */
-    int32_t pad;
+    int32_t windows;        /* tkdv_sample_sweep: windows run (graph replays)        */
 } tkdv_timing;
 
 typedef struct tkdv_ctx tkdv_ctx;
@@ -337,6 +337,50 @@ tkdv_status tkdv_learner_mixture(tkdv_learner *learner, const tkdv_point *pt, co
 int64_t tkdv_learner_n_weights(const tkdv_learner *learner);
 tkdv_status tkdv_learner_get_weights(const tkdv_learner *learner, double *h_out, int64_t n);
 tkdv_status tkdv_learner_set_weights(tkdv_learner *learner, const double *h_in, int64_t n);
+
+/*
+ * Batched sweep (the paper's Sigma proposal): accepted-count sampling of many
+ * points of mixed K in windows of proposals.  Launch configuration per
+ * (K, arithmetic):
+ */
+typedef struct {
+    int32_t blocks_per_cu;  /* decide workgroups per compute unit, 0: as many as fit  */
+    int32_t use_graph;      /* 1: one window captured in a hipGraph and replayed       */
+    uint64_t window;        /* proposals per point per window, a multiple of 65536     */
+} tkdv_launch_cfg;
+
+/* Point p draws proposals i = 0, 1, ... until targets[p] (>= 1) samples are
+ * accepted or max_proposals[p] proposals are used (Sec. IV.B's loop, in
+ * windows).  One window is one launch sequence over every unfinished point:
+ * decisions per K, FP64 re-decision, ordered compaction and statistics, and
+ * a device-side advance of every point to its next window; it is captured
+ * once as a hipGraph and replayed until no point is left, the host reading
+ * one counter per window.  Output as in tkdv_sample_batch: the first
+ * targets[p] accepted samples by index in rows (out_offset[p] + r) of d_xhat
+ * (stride 2 * TKDV_KMAX floats) and d_index, at most capacity[p] rows; stats
+ * cover the same samples; n_proposed counts the proposals up to the last of
+ * them (or max_proposals[p]).  cfg NULL: the context's configuration of each
+ * K (tkdv_set_launch_cfg / tkdv_autotune), by default all workgroups that
+ * fit and windows of 2^26 proposals; otherwise cfg for every K.  Plans must
+ * be Sigma plans (or NULL: planned here). */
+tkdv_status tkdv_sample_sweep(tkdv_ctx *ctx, int32_t n_points, const tkdv_point *pts, const tkdv_plan *plans,
+                              const uint64_t *targets, const uint64_t *max_proposals, tkdv_precision precision,
+                              const tkdv_launch_cfg *cfg, float *d_xhat, uint64_t *d_index,
+                              const uint64_t *capacity, const uint64_t *out_offset, tkdv_stats *h_stats,
+                              void *stream);
+
+/* The context's launch configuration of the sweep for (K, precision). */
+tkdv_status tkdv_set_launch_cfg(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, const tkdv_launch_cfg *cfg);
+tkdv_status tkdv_get_launch_cfg(const tkdv_ctx *ctx, int32_t K, tkdv_precision precision, tkdv_launch_cfg *out);
+
+/* Autotuner: times a probe sweep (16 points of this K, beta' in [20, 60],
+ * accepted targets of about 2^14) for every blocks_per_cu that fits and
+ * windows of 2^24, 2^25 and 2^26 proposals, keeps the fastest (proposals/s),
+ * stores it in the context and, when cache_path is not NULL, in a text cache
+ * keyed by device, K and precision (a cached entry is used without timing).
+ * *out (may be NULL) receives the choice. */
+tkdv_status tkdv_autotune(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, const char *cache_path,
+                          tkdv_launch_cfg *out);
 
 /* Phase timings of the last call on this context (see tkdv_timing). */
 tkdv_status tkdv_get_timing(const tkdv_ctx *ctx, tkdv_timing *out);

@@ -62,6 +62,14 @@ struct tkdv_ctx {
     size_t h_misc_bytes = 0;
     hipEvent_t ev[6] = {};  // phase boundaries of the last call
     tkdv_timing timing = {};
+    // sweep: launch configuration per (K index, precision), its own stream
+    // (captured into graphs) joined to the caller's stream by events
+    tkdv_launch_cfg lcfg[4][3];
+    hipStream_t sweep_stream = nullptr;
+    hipEvent_t join[2] = {};
+    DevBuf sweep, active;
+    void *h_poll = nullptr;  // pinned: active count, FP64 list count
+    std::string arch;
 };
 
 namespace {
@@ -523,6 +531,246 @@ tkdv_status prepare_mixture(tkdv_ctx *ctx, Call &call, const tkdv_point &pt, con
     return TKDV_OK;
 }
 
+// Stats of a finished sweep point.
+void fill_stats_sweep(tkdv_stats &s, const DevPoint &P, const SweepState &w)
+{
+    std::memset(&s, 0, sizeof(s));
+    const int K = P.K, N = 4 * K;
+    s.n_proposed = w.n_proposed;
+    s.n_accepted = w.accepted;
+    s.n_written = w.written;
+    s.n_fp64_fixups = w.n_fixups;
+    s.n_M_violations = w.n_violations;
+    s.n_exceed_2sigma = w.total.n_exceed;
+    s.n_grid_values = w.accepted * (uint64_t)N;
+    s.max_log_a = w.max_log_a_key ? (double)key_to_float(w.max_log_a_key) : -INFINITY;
+    s.S1 = w.total.S1;
+    s.S2 = w.total.S2;
+    s.S3 = w.total.S3;
+    s.S4 = w.total.S4;
+    if (s.n_grid_values > 0) {
+        const double n = (double)s.n_grid_values;
+        const double m2 = s.S2 / n, m3 = s.S3 / n, m4 = s.S4 / n;
+        s.skewness = m3 / std::pow(m2, 1.5);
+        s.kurtosis = m4 / (m2 * m2);
+        s.p_exceed_2sigma = (double)w.total.n_exceed / n;
+    }
+    const double umax = std::sqrt(2.0 * K * P.E0 / kPi);
+    s.hist_lo = -umax;
+    s.hist_hi = umax;
+    for (int b = 0; b < TKDV_NBINS; ++b) s.hist_u0[b] = w.total.hist[b];
+}
+
+int prec_index(int precision) { return precision < 0 || precision > 2 ? 0 : precision; }
+
+tkdv_status sweep(tkdv_ctx *ctx, int np, const tkdv_point *pts, const tkdv_plan *plans, const uint64_t *targets,
+                  const uint64_t *maxp, int precision, const tkdv_launch_cfg *cfg, float *d_xhat,
+                  uint64_t *d_index, const uint64_t *capacity, const uint64_t *out_offset, tkdv_stats *h_stats,
+                  hipStream_t user_st)
+{
+    if (np < 1) return set_err(ctx, TKDV_E_ARG, "n_points must be >= 1");
+    if (!pts || !targets || !maxp || !h_stats) return set_err(ctx, TKDV_E_ARG, "NULL argument");
+    if (precision < TKDV_FP32 || precision > TKDV_BF16X3) return set_err(ctx, TKDV_E_ARG, "bad precision");
+    Call call;
+    call.pts.resize(np);
+    call.plist_n.assign(4, 0);
+    call.plist_off.assign(4, 0);
+    std::vector<std::vector<int>> by_k(4);
+    std::vector<SweepState> sw(np);
+    tkdv_launch_cfg kcfg[4];
+    bool use_graph = true;
+    unsigned long long bm = 0, segs = 0, max_windows = 0;
+    for (int ki = 0; ki < 4; ++ki) kcfg[ki] = cfg ? *cfg : ctx->lcfg[ki][prec_index(precision)];
+    for (int p = 0; p < np; ++p) {
+        tkdv_status s = check_point(ctx, pts[p]);
+        if (s != TKDV_OK) return s;
+        if (targets[p] < 1 || maxp[p] < 1 || maxp[p] >= (1ull << 40))
+            return set_err(ctx, TKDV_E_ARG, "targets must be >= 1 and max_proposals in [1, 2^40)");
+        tkdv_plan pl;
+        if (plans) {
+            pl = plans[p];
+            if (pl.proposal != TKDV_PROP_SIGMA) return set_err(ctx, TKDV_E_ARG, "the sweep takes Sigma plans");
+        } else {
+            s = (tkdv_status)plan_point_host(&pts[p], TKDV_PROP_SIGMA, 2, &pl);
+            if (s != TKDV_OK) return set_err(ctx, s, "planning failed");
+        }
+        const int ki = kindex(pts[p].K);
+        const tkdv_launch_cfg &lc = kcfg[ki];
+        if (lc.window < 65536 || lc.window % 65536 != 0 || lc.window > (1ull << 34) || lc.blocks_per_cu < 0)
+            return set_err(ctx, TKDV_E_ARG, "window must be a multiple of 65536 in [65536, 2^34]");
+        use_graph = use_graph && lc.use_graph;
+        DevPoint &d = call.pts[p];
+        fill_devpoint(d, pts[p], pl, TKDV_PROP_SIGMA, precision);
+        const uint64_t W = lc.window, words = W / kTile;
+        d.i0 = 0;
+        d.n = std::min<uint64_t>(W, maxp[p]);
+        d.n_tiles = (d.n + kTile - 1) / kTile;
+        d.target = targets[p];
+        d.bm_off = bm;
+        d.seg_off = segs;
+        d.n_segs = (words + kSegWords - 1) / kSegWords;
+        d.out_off = out_offset ? out_offset[p] : 0;
+        d.capacity = capacity ? capacity[p] : 0;
+        d.row_stride = 2 * TKDV_KMAX;
+        bm += words;
+        segs += d.n_segs;
+        std::memset(&sw[p], 0, sizeof(SweepState));
+        sw[p].i_start = 0;
+        sw[p].i_end = maxp[p];
+        sw[p].window = W;
+        sw[p].target = targets[p];
+        sw[p].capacity = d.capacity;
+        sw[p].out_off = d.out_off;
+        max_windows = std::max<unsigned long long>(max_windows, (maxp[p] + W - 1) / W);
+        by_k[ki].push_back(p);
+    }
+    call.plist.clear();
+    for (int ki = 0; ki < 4; ++ki) {
+        call.plist_off[ki] = (int)call.plist.size();
+        call.plist_n[ki] = (int)by_k[ki].size();
+        call.plist.insert(call.plist.end(), by_k[ki].begin(), by_k[ki].end());
+    }
+    call.bitmap_words = bm;
+    call.total_segs = segs;
+    hipStream_t sst = ctx->sweep_stream;
+    const unsigned long long defer_cap = std::min<unsigned long long>(1ull << 26, std::max<unsigned long long>(1ull << 20, bm));
+    HIP_TRY(ctx, ensure(ctx->bitmap, bm * 4));
+    HIP_TRY(ctx, ensure(ctx->defer_list, defer_cap * 8));
+    HIP_TRY(ctx, ensure(ctx->defer_count, 8));
+    HIP_TRY(ctx, ensure(ctx->counters, sizeof(DevCounters) * np));
+    HIP_TRY(ctx, ensure(ctx->points, sizeof(DevPoint) * np));
+    HIP_TRY(ctx, ensure(ctx->seg_cnt, 8 * segs));
+    HIP_TRY(ctx, ensure(ctx->seg_base, 8 * segs));
+    HIP_TRY(ctx, ensure(ctx->seg_stats, sizeof(SegStats) * segs));
+    HIP_TRY(ctx, ensure(ctx->results, sizeof(PointResult) * np));
+    HIP_TRY(ctx, ensure(ctx->plist, sizeof(int) * call.plist.size()));
+    HIP_TRY(ctx, ensure(ctx->sweep, sizeof(SweepState) * np));
+    HIP_TRY(ctx, ensure(ctx->active, 8));
+    for (int ki = 0; ki < 4; ++ki)
+        if (call.plist_n[ki]) {
+            tkdv_status s = build_tables(ctx, 8 << ki);
+            if (s != TKDV_OK) return s;
+        }
+    // the caller's stream has finished its earlier work before the sweep reads
+    // or writes the caller's buffers
+    HIP_TRY(ctx, hipEventRecord(ctx->join[0], user_st));
+    HIP_TRY(ctx, hipStreamWaitEvent(sst, ctx->join[0], 0));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->points.p, call.pts.data(), sizeof(DevPoint) * np, hipMemcpyHostToDevice, sst));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->plist.p, call.plist.data(), sizeof(int) * call.plist.size(),
+                                hipMemcpyHostToDevice, sst));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->sweep.p, sw.data(), sizeof(SweepState) * np, hipMemcpyHostToDevice, sst));
+    HIP_TRY(ctx, hipStreamSynchronize(sst));  // host vectors are pageable and go out of scope
+
+    KernelArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.pts = reinterpret_cast<const DevPoint *>(ctx->points.p);
+    a.n_points = np;
+    a.cnt = reinterpret_cast<DevCounters *>(ctx->counters.p);
+    a.bitmap = reinterpret_cast<uint32_t *>(ctx->bitmap.p);
+    a.defer_list = reinterpret_cast<unsigned long long *>(ctx->defer_list.p);
+    a.defer_count = reinterpret_cast<unsigned long long *>(ctx->defer_count.p);
+    a.defer_cap = defer_cap;
+    const int *d_plist = reinterpret_cast<const int *>(ctx->plist.p);
+    unsigned long long *seg_cnt = reinterpret_cast<unsigned long long *>(ctx->seg_cnt.p);
+    unsigned long long *seg_base = reinterpret_cast<unsigned long long *>(ctx->seg_base.p);
+    SegStats *seg_stats = reinterpret_cast<SegStats *>(ctx->seg_stats.p);
+    PointResult *res = reinterpret_cast<PointResult *>(ctx->results.p);
+    unsigned long long *active = reinterpret_cast<unsigned long long *>(ctx->active.p);
+    auto window = [&]() -> tkdv_status {
+        HIP_TRY(ctx, launch_fill_u32(ctx->counters.p, sizeof(DevCounters) * np / 4, 0u, sst));
+        HIP_TRY(ctx, launch_fill_u32(ctx->results.p, sizeof(PointResult) * np / 4, 0u, sst));
+        HIP_TRY(ctx, launch_fill_u32(ctx->defer_count.p, 2, 0u, sst));
+        for (int ki = 0; ki < 4; ++ki) {
+            if (call.plist_n[ki] == 0) continue;
+            const int K = 8 << ki;
+            a.blocks_per_cu = kcfg[ki].blocks_per_cu;
+            a.phi_hi = precision == TKDV_FP32 ? ctx->phi_f32[ki].p : ctx->phi_hi[ki].p;
+            a.phi_lo = ctx->phi_lo[ki].p;
+            const unsigned long long tiles = (unsigned long long)call.plist_n[ki] * (kcfg[ki].window / kTile);
+            HIP_TRY(ctx, launch_decide(K, precision, TKDV_PROP_SIGMA, a, d_plist + call.plist_off[ki],
+                                       call.plist_n[ki], ctx->n_cu, tiles, sst, nullptr));
+        }
+        HIP_TRY(ctx, launch_fixup(a, ctx->n_cu, sst));
+        HIP_TRY(ctx, launch_segments(a, segs, seg_cnt, seg_base, res, ctx->n_cu, sst));
+        for (int ki = 0; ki < 4; ++ki) {
+            if (call.plist_n[ki] == 0) continue;
+            a.phi_hi = ctx->phi_f32[ki].p;
+            HIP_TRY(ctx, launch_materialize(8 << ki, TKDV_PROP_SIGMA, a, d_plist + call.plist_off[ki],
+                                            call.plist_n[ki], segs, seg_cnt, seg_base, seg_stats, res, d_xhat,
+                                            reinterpret_cast<unsigned long long *>(d_index), ctx->n_cu, sst));
+        }
+        HIP_TRY(ctx, launch_finalize(a, seg_cnt, seg_base, seg_stats, res, sst));
+        HIP_TRY(ctx, launch_fill_u32(ctx->active.p, 2, 0u, sst));
+        HIP_TRY(ctx, launch_window_advance(reinterpret_cast<DevPoint *>(ctx->points.p), a.cnt, res,
+                                           reinterpret_cast<SweepState *>(ctx->sweep.p), np, active, sst));
+        return TKDV_OK;
+    };
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    auto release = [&]() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    };
+    if (use_graph) {
+        HIP_TRY(ctx, hipStreamBeginCapture(sst, hipStreamCaptureModeThreadLocal));
+        tkdv_status s = window();
+        hipError_t e = hipStreamEndCapture(sst, &graph);
+        if (s != TKDV_OK) {
+            release();
+            return s;
+        }
+        if (e != hipSuccess) {
+            release();
+            return set_err(ctx, TKDV_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        }
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            release();
+            return set_err(ctx, TKDV_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+        }
+    }
+    std::memset(&ctx->timing, 0, sizeof(ctx->timing));
+    ctx->timing.decide_block = kBlock;
+    unsigned long long *poll = reinterpret_cast<unsigned long long *>(ctx->h_poll);
+    tkdv_status st_out = TKDV_OK;
+    int windows = 0;
+    hipError_t e = hipEventRecord(ctx->ev[0], sst);
+    for (unsigned long long w = 0; w < max_windows && e == hipSuccess && st_out == TKDV_OK; ++w) {
+        if (use_graph) e = hipGraphLaunch(exec, sst);
+        else st_out = window();
+        if (e != hipSuccess || st_out != TKDV_OK) break;
+        ++windows;
+        if ((e = hipMemcpyAsync(poll, active, 8, hipMemcpyDeviceToHost, sst)) != hipSuccess) break;
+        if ((e = hipMemcpyAsync(poll + 1, ctx->defer_count.p, 8, hipMemcpyDeviceToHost, sst)) != hipSuccess) break;
+        if ((e = hipStreamSynchronize(sst)) != hipSuccess) break;
+        if (poll[1] > defer_cap) {
+            st_out = set_err(ctx, TKDV_E_CAPACITY, "FP64 re-decision list overflowed in a sweep window");
+            break;
+        }
+        if (poll[0] == 0) break;
+    }
+    if (e == hipSuccess) e = hipEventRecord(ctx->ev[1], sst);
+    if (e == hipSuccess) e = hipEventSynchronize(ctx->ev[1]);
+    release();
+    if (e != hipSuccess) return set_err(ctx, TKDV_E_DEVICE, std::string("sweep: ") + hipGetErrorString(e));
+    if (st_out != TKDV_OK) return st_out;
+    float ms = 0.0f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+    ctx->timing.total_ms = ms;
+    ctx->timing.windows = windows;
+    int nk = 0;
+    for (int ki = 0; ki < 4; ++ki) nk += call.plist_n[ki] ? 1 : 0;
+    ctx->timing.decide_launches = windows * nk;
+    HIP_TRY(ctx, hipMemcpy(sw.data(), ctx->sweep.p, sizeof(SweepState) * np, hipMemcpyDeviceToHost));
+    for (int p = 0; p < np; ++p) fill_stats_sweep(h_stats[p], call.pts[p], sw[p]);
+    // later work on the caller's stream sees the sweep's outputs
+    HIP_TRY(ctx, hipEventRecord(ctx->join[1], sst));
+    HIP_TRY(ctx, hipStreamWaitEvent(user_st, ctx->join[1], 0));
+    return TKDV_OK;
+}
+
 }  // namespace
 
 namespace tkdv {
@@ -548,6 +796,17 @@ tkdv_status tkdv_create(int hip_device, tkdv_ctx **out)
     tkdv_ctx *ctx = new tkdv_ctx();
     ctx->device = hip_device;
     ctx->n_cu = prop.multiProcessorCount;
+    ctx->arch = prop.gcnArchName;
+    for (auto &row : ctx->lcfg)
+        for (auto &c : row) c = tkdv_launch_cfg{0, 1, 1ull << 26};
+    e = hipStreamCreateWithFlags(&ctx->sweep_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join[0], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join[1], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc(&ctx->h_poll, 64, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        tkdv_destroy(ctx);
+        return set_err(nullptr, TKDV_E_DEVICE, hipGetErrorString(e));
+    }
     for (hipEvent_t &ev : ctx->ev) {
         e = hipEventCreate(&ev);
         if (e != hipSuccess) {
@@ -565,7 +824,7 @@ tkdv_status tkdv_destroy(tkdv_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     DevBuf *bufs[] = {&ctx->bitmap, &ctx->defer_list, &ctx->defer_count, &ctx->counters, &ctx->points,
                       &ctx->seg_cnt, &ctx->seg_base, &ctx->seg_stats, &ctx->results, &ctx->plist,
-                      &ctx->mix, &ctx->mix_tab};
+                      &ctx->mix, &ctx->mix_tab, &ctx->sweep, &ctx->active};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (int i = 0; i < 4; ++i) {
@@ -579,6 +838,10 @@ tkdv_status tkdv_destroy(tkdv_ctx *ctx)
     if (ctx->h_misc) (void)hipHostFree(ctx->h_misc);
     for (hipEvent_t ev : ctx->ev)
         if (ev) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : ctx->join)
+        if (ev) (void)hipEventDestroy(ev);
+    if (ctx->sweep_stream) (void)hipStreamDestroy(ctx->sweep_stream);
+    if (ctx->h_poll) (void)hipHostFree(ctx->h_poll);
     delete ctx;
     return TKDV_OK;
 }
@@ -779,6 +1042,109 @@ tkdv_status tkdv_synthesize(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, 
     HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
     ctx->timing.synth_ms = ms;
     ctx->timing.total_ms = ms;
+    return TKDV_OK;
+}
+
+tkdv_status tkdv_sample_sweep(tkdv_ctx *ctx, int32_t n_points, const tkdv_point *pts, const tkdv_plan *plans,
+                              const uint64_t *targets, const uint64_t *max_proposals, tkdv_precision precision,
+                              const tkdv_launch_cfg *cfg, float *d_xhat, uint64_t *d_index,
+                              const uint64_t *capacity, const uint64_t *out_offset, tkdv_stats *h_stats,
+                              void *stream)
+{
+    if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    return sweep(ctx, n_points, pts, plans, targets, max_proposals, precision, cfg, d_xhat, d_index, capacity,
+                 out_offset, h_stats, (hipStream_t)stream);
+}
+
+tkdv_status tkdv_set_launch_cfg(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, const tkdv_launch_cfg *cfg)
+{
+    if (!ctx || !cfg) return set_err(nullptr, TKDV_E_ARG, "NULL argument");
+    if (kindex(K) < 0 || precision < TKDV_FP32 || precision > TKDV_BF16X3)
+        return set_err(ctx, TKDV_E_ARG, "bad K or precision");
+    if (cfg->window < 65536 || cfg->window % 65536 != 0 || cfg->window > (1ull << 34) || cfg->blocks_per_cu < 0)
+        return set_err(ctx, TKDV_E_ARG, "window must be a multiple of 65536 in [65536, 2^34]");
+    ctx->lcfg[kindex(K)][precision] = *cfg;
+    return TKDV_OK;
+}
+
+tkdv_status tkdv_get_launch_cfg(const tkdv_ctx *ctx, int32_t K, tkdv_precision precision, tkdv_launch_cfg *out)
+{
+    if (!ctx || !out) return set_err(nullptr, TKDV_E_ARG, "NULL argument");
+    if (kindex(K) < 0 || precision < TKDV_FP32 || precision > TKDV_BF16X3)
+        return set_err(nullptr, TKDV_E_ARG, "bad K or precision");
+    *out = ctx->lcfg[kindex(K)][precision];
+    return TKDV_OK;
+}
+
+tkdv_status tkdv_autotune(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, const char *cache_path,
+                          tkdv_launch_cfg *out)
+{
+    if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");
+    if (kindex(K) < 0 || precision < TKDV_FP32 || precision > TKDV_BF16X3)
+        return set_err(ctx, TKDV_E_ARG, "bad K or precision");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    char key[160];
+    std::snprintf(key, sizeof(key), "%s:%d K=%d prec=%d", ctx->arch.c_str(), ctx->n_cu, K, (int)precision);
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "r")) {
+            char line[512];
+            while (std::fgets(line, sizeof(line), f)) {
+                const size_t kl = std::strlen(key);
+                if (std::strncmp(line, key, kl) != 0 || line[kl] != ' ') continue;
+                int bpc = 0, graph = 1;
+                unsigned long long win = 0;
+                if (std::sscanf(line + kl, " bpc=%d window=%llu graph=%d", &bpc, &win, &graph) == 3 &&
+                    win >= 65536 && win % 65536 == 0 && bpc >= 0) {
+                    std::fclose(f);
+                    tkdv_launch_cfg c{bpc, graph, win};
+                    ctx->lcfg[kindex(K)][precision] = c;
+                    if (out) *out = c;
+                    return TKDV_OK;
+                }
+            }
+            std::fclose(f);
+        }
+    }
+    // probe: 16 points of this K, beta' in [20, 60], beta'C3/C2 = 6000 (K/32)^2,
+    // a fixed number of proposals each (the targets are never met)
+    const int np = 16;
+    const uint64_t per_point = K >= 64 ? (1ull << 26) : (1ull << 27);
+    std::vector<tkdv_point> pts(np);
+    std::vector<tkdv_plan> plans(np);
+    std::vector<uint64_t> tgt(np, ~0ull >> 24), maxp(np, per_point), cap(np, 0), off(np, 0);
+    for (int p = 0; p < np; ++p) {
+        const double bp = 20.0 + 40.0 * p / (np - 1);
+        pts[p] = tkdv_point{K, (uint32_t)p, 1.0, bp, 6000.0 * (K / 32.0) * (K / 32.0) / bp, 1234567ull + p};
+        tkdv_status s = (tkdv_status)plan_point_host(&pts[p], TKDV_PROP_SIGMA, 0, &plans[p]);
+        if (s != TKDV_OK) return set_err(ctx, s, "autotune planning failed");
+    }
+    std::vector<tkdv_stats> st(np);
+    const int max_bpc = decide_max_blocks_per_cu(K, precision);
+    tkdv_launch_cfg best{0, 1, 1ull << 26};
+    double best_rate = -1.0;
+    const uint64_t windows[3] = {1ull << 24, 1ull << 25, 1ull << 26};
+    for (int bpc = 1; bpc <= max_bpc; ++bpc)
+        for (uint64_t w : windows) {
+            tkdv_launch_cfg c{bpc, 1, w};
+            tkdv_status s = sweep(ctx, np, pts.data(), plans.data(), tgt.data(), maxp.data(), precision, &c, nullptr,
+                                  nullptr, cap.data(), off.data(), st.data(), nullptr);
+            if (s != TKDV_OK) return s;
+            const double rate = (double)per_point * np / (ctx->timing.total_ms * 1e-3);
+            if (rate > best_rate) {
+                best_rate = rate;
+                best = c;
+            }
+        }
+    ctx->lcfg[kindex(K)][precision] = best;
+    if (out) *out = best;
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "a")) {
+            std::fprintf(f, "%s bpc=%d window=%llu graph=%d rate=%.6e\n", key, best.blocks_per_cu,
+                         (unsigned long long)best.window, best.use_graph, best_rate);
+            std::fclose(f);
+        }
+    }
     return TKDV_OK;
 }
 

@@ -120,9 +120,25 @@ struct PointResult {
     unsigned long long hist[kNBins];
 };
 
+// Per-point state of a windowed sweep (accepted-count sampling in windows of
+// proposals; the device advances it after every window).
+struct SweepState {
+    uint64_t i_start, i_end;      // proposal indices [i_start, i_end) of the point
+    uint64_t window;              // proposals per window
+    uint64_t target;              // accepted samples wanted
+    uint64_t capacity, out_off;   // output rows of the point
+    uint64_t accepted;            // accepted samples so far (at most target)
+    uint64_t written;             // rows written so far
+    uint64_t n_proposed;          // proposals consumed (up to the target-th sample)
+    uint64_t n_fixups, n_violations;
+    uint32_t done, max_log_a_key;
+    PointResult total;            // statistics of the accepted samples so far
+};
+
 struct KernelArgs {
     const DevPoint *pts;
     int n_points;
+    int blocks_per_cu;     // decide-kernel workgroups per compute unit (0: as many as fit)
     DevCounters *cnt;
     uint32_t *bitmap;
     unsigned long long *defer_list;

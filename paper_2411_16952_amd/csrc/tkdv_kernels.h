@@ -11,6 +11,8 @@ hipError_t launch_decide(int K, int prec, int prop, const KernelArgs &a, const i
                          int n_cu, unsigned long long total_tiles, hipStream_t st, int *grid_out);
 hipError_t launch_decide_mix(int K, int prec, const KernelArgs &a, const int *plist, int n_plist, int n_cu,
                              unsigned long long total_tiles, hipStream_t st, int *grid_out);
+// largest number of decide workgroups (paper's proposal) resident per compute unit
+int decide_max_blocks_per_cu(int K, int prec);
 hipError_t launch_fixup(const KernelArgs &a, int n_cu, hipStream_t st);
 hipError_t launch_fixup_mix(int K, const KernelArgs &a, int n_cu, hipStream_t st);
 hipError_t launch_segments(const KernelArgs &a, unsigned long long total_segs, unsigned long long *seg_cnt,
@@ -24,6 +26,8 @@ hipError_t launch_finalize(const KernelArgs &a, const unsigned long long *seg_cn
                            hipStream_t st);
 hipError_t launch_synth(int K, int prec, const float *xhat, unsigned long long n, float *s3, const void *phi_hi,
                         const void *phi_lo, int n_cu, hipStream_t st, int *grid_out);
+hipError_t launch_window_advance(DevPoint *pts, const DevCounters *cnt, const PointResult *res, SweepState *sw,
+                                 int n_points, unsigned long long *active, hipStream_t st);
 hipError_t launch_fill_u32(void *p, unsigned long long n_words, uint32_t v, hipStream_t st);
 hipError_t launch_bits_to_bytes(const uint32_t *bitmap, unsigned long long n, uint8_t *out, hipStream_t st);
 

@@ -847,6 +847,65 @@ __global__ void __launch_bounds__(kBlock) k_finalize(KernelArgs a, const unsigne
 }
 
 // ---------------------------------------------------------------------------
+// k_window_advance: after one window of a sweep, per point (one thread):
+// fold the window's statistics into the running totals, count the accepted
+// samples (the window's target is what was still missing), and set up the
+// next window -- its first index, size, remaining target and capacity, and
+// output offset -- or mark the point done (target met or index range used
+// up; a done point gets no tiles).  *active counts the points not done.
+// ---------------------------------------------------------------------------
+__global__ void k_window_advance(DevPoint *pts, const DevCounters *cnt, const PointResult *res,
+                                 SweepState *sw, int n_points, unsigned long long *active)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_points) return;
+    SweepState &S = sw[p];
+    DevPoint &P = pts[p];
+    if (S.done) return;
+    const PointResult &r = res[p];
+    const DevCounters &c = cnt[p];
+    S.total.S1 += r.S1;
+    S.total.S2 += r.S2;
+    S.total.S3 += r.S3;
+    S.total.S4 += r.S4;
+    S.total.n_exceed += r.n_exceed;
+    for (int b = 0; b < kNBins; ++b) S.total.hist[b] += r.hist[b];
+    S.accepted += r.n_samples;
+    S.written += r.n_written;
+    S.n_fixups += c.deferred;
+    S.n_violations += c.violations;
+    if (c.max_log_a_key > S.max_log_a_key) S.max_log_a_key = c.max_log_a_key;
+    if (S.accepted >= S.target) {
+        S.n_proposed = c.last_index - S.i_start + 1;
+        S.done = 1;
+    } else {
+        S.n_proposed += P.n;
+        if (P.i0 + P.n >= S.i_end) S.done = 1;
+    }
+    if (S.done) {
+        P.n = 0;
+        P.n_tiles = 0;
+        return;
+    }
+    P.i0 += P.n;
+    const unsigned long long left = S.i_end - P.i0;
+    P.n = left < S.window ? left : S.window;
+    P.n_tiles = (P.n + kTile - 1) / kTile;
+    P.target = S.target - S.accepted;
+    P.capacity = S.capacity > S.written ? S.capacity - S.written : 0;
+    P.out_off = S.out_off + S.written;
+    atomicAdd(active, 1ull);
+}
+
+hipError_t launch_window_advance(DevPoint *pts, const DevCounters *cnt, const PointResult *res, SweepState *sw,
+                                 int n_points, unsigned long long *active, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_window_advance, dim3((n_points + 63) / 64), dim3(64), 0, st, pts, cnt, res, sw, n_points,
+                       active);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // k_synth: the spectral-to-grid synthesis on its own, with x^ read from HBM.
 // Row r of x^ (2K floats) -> S3[r] = sum_j u~_j^3 over the N = 4K grid,
 // u~ = Phi^T x^ (unscaled), products in the requested arithmetic.  Persistent
@@ -975,6 +1034,7 @@ static hipError_t launch_decide_t(const KernelArgs &a, const int *plist, int n_p
     int per_cu = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, lds);
     if (e != hipSuccess) return e;
+    if (a.blocks_per_cu > 0 && a.blocks_per_cu < per_cu) per_cu = a.blocks_per_cu;
     if (per_cu < 1) per_cu = 1;
     unsigned long long want = (total_tiles + (unsigned long long)(kBlock / kWave) * kClaimTiles - 1) /
                               ((unsigned long long)(kBlock / kWave) * kClaimTiles);
@@ -1002,6 +1062,30 @@ static hipError_t launch_decide_k(int prec, int prop, const KernelArgs &a, const
     return hipErrorInvalidValue;
 }
 
+template <int K, int PREC, int PROP>
+static int decide_blocks_per_cu_t()
+{
+    constexpr int lds = decide_lds_bytes<K, PREC>();
+    auto kern = k_decide<K, PREC, PROP>;
+    if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
+        return 1;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, lds) != hipSuccess) return 1;
+    return per_cu < 1 ? 1 : per_cu;
+}
+
+int decide_max_blocks_per_cu(int K, int prec)
+{
+#define TKDV_DISPATCH_O(KK, PR) \
+    if (K == KK && prec == PR) return decide_blocks_per_cu_t<KK, PR, PROP_SIGMA>();
+    TKDV_DISPATCH_O(8, PREC_FP32) TKDV_DISPATCH_O(8, PREC_BF16) TKDV_DISPATCH_O(8, PREC_BF16X3)
+    TKDV_DISPATCH_O(16, PREC_FP32) TKDV_DISPATCH_O(16, PREC_BF16) TKDV_DISPATCH_O(16, PREC_BF16X3)
+    TKDV_DISPATCH_O(32, PREC_FP32) TKDV_DISPATCH_O(32, PREC_BF16) TKDV_DISPATCH_O(32, PREC_BF16X3)
+    TKDV_DISPATCH_O(64, PREC_FP32) TKDV_DISPATCH_O(64, PREC_BF16) TKDV_DISPATCH_O(64, PREC_BF16X3)
+#undef TKDV_DISPATCH_O
+    return 1;
+}
+
 hipError_t launch_decide(int K, int prec, int prop, const KernelArgs &a, const int *plist, int n_plist,
                          int n_cu, unsigned long long tiles, hipStream_t st, int *grid_out)
 {
@@ -1025,6 +1109,7 @@ static hipError_t launch_decide_mix_t(const KernelArgs &a, const int *plist, int
     int per_cu = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kMixBlock, lds);
     if (e != hipSuccess) return e;
+    if (a.blocks_per_cu > 0 && a.blocks_per_cu < per_cu) per_cu = a.blocks_per_cu;
     if (per_cu < 1) per_cu = 1;
     unsigned long long want = (total_tiles + (unsigned long long)(kMixBlock / kWave) * kClaimTiles - 1) /
                               ((unsigned long long)(kMixBlock / kWave) * kClaimTiles);

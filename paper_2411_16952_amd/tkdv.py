@@ -53,6 +53,14 @@ class Mixture(C.Structure):
                 ("logd", C.c_double * KMAX), ("V", (C.c_double * MIX_R) * (2 * KMAX))]
 
 
+class LaunchCfg(C.Structure):
+    """Launch configuration of the sweep (tkdv_launch_cfg)."""
+    _fields_ = [("blocks_per_cu", C.c_int32), ("use_graph", C.c_int32), ("window", C.c_uint64)]
+
+    def to_dict(self) -> dict:
+        return {"blocks_per_cu": self.blocks_per_cu, "use_graph": self.use_graph, "window": self.window}
+
+
 class LearnerCfg(C.Structure):
     _fields_ = [("K", C.c_int32), ("hidden", C.c_int32), ("eps", C.c_double), ("v_amp", C.c_double),
                 ("v_scale", C.c_double), ("temperature", C.c_double), ("nll_weight", C.c_double),
@@ -65,10 +73,10 @@ class Timing(C.Structure):
                 ("materialize_ms", C.c_double), ("finalize_ms", C.c_double), ("synth_ms", C.c_double),
                 ("total_ms", C.c_double),
                 ("decide_launches", C.c_int32), ("decide_grid", C.c_int32), ("decide_block", C.c_int32),
-                ("pad", C.c_int32)]
+                ("windows", C.c_int32)]
 
     def to_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class Stats(C.Structure):
@@ -104,7 +112,8 @@ EXPORTS = ["tkdv_create", "tkdv_destroy", "tkdv_plan_point", "tkdv_sample", "tkd
            "tkdv_learner_destroy", "tkdv_learner_set_points", "tkdv_learner_add_rows",
            "tkdv_learner_add_rows_host", "tkdv_learner_train", "tkdv_learner_gradients",
            "tkdv_learner_mixture", "tkdv_learner_n_weights", "tkdv_learner_get_weights",
-           "tkdv_learner_set_weights"]
+           "tkdv_learner_set_weights", "tkdv_sample_sweep", "tkdv_set_launch_cfg", "tkdv_get_launch_cfg",
+           "tkdv_autotune"]
 
 _P = C.c_void_p
 lib.tkdv_create.argtypes = [C.c_int, C.POINTER(_P)]
@@ -143,6 +152,12 @@ lib.tkdv_learner_n_weights.argtypes = [_P]
 lib.tkdv_learner_n_weights.restype = C.c_int64
 lib.tkdv_learner_get_weights.argtypes = [_P, _PD, C.c_int64]
 lib.tkdv_learner_set_weights.argtypes = [_P, _PD, C.c_int64]
+lib.tkdv_sample_sweep.argtypes = [_P, C.c_int32, C.POINTER(Point), C.POINTER(Plan), C.POINTER(C.c_uint64),
+                                  C.POINTER(C.c_uint64), C.c_int, C.POINTER(LaunchCfg), _P, _P,
+                                  C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(Stats), _P]
+lib.tkdv_set_launch_cfg.argtypes = [_P, C.c_int32, C.c_int, C.POINTER(LaunchCfg)]
+lib.tkdv_get_launch_cfg.argtypes = [_P, C.c_int32, C.c_int, C.POINTER(LaunchCfg)]
+lib.tkdv_autotune.argtypes = [_P, C.c_int32, C.c_int, C.c_char_p, C.POINTER(LaunchCfg)]
 lib.tkdv_status_str.argtypes = [C.c_int]
 lib.tkdv_status_str.restype = C.c_char_p
 lib.tkdv_last_error.argtypes = [_P]
@@ -339,6 +354,52 @@ class Context:
             d["index"] = index[o:o + nw]
             out.append(d)
         return out, xhat, index
+
+    def sample_sweep(self, points: list, targets: list, max_proposals: list, plans: list | None = None,
+                     precision: int = BF16X3, cfg: LaunchCfg | None = None, capacity: list | None = None,
+                     stream=None) -> tuple[list, object, object]:
+        """Accepted-count sweep of many points (windows replayed as a hipGraph);
+        rows have stride 2*KMAX floats."""
+        import torch
+        npnt = len(points)
+        pts = (Point * npnt)(*points)
+        pls = (Plan * npnt)(*plans) if plans is not None else None
+        tg = (C.c_uint64 * npnt)(*[int(v) for v in targets])
+        mp = (C.c_uint64 * npnt)(*[int(v) for v in max_proposals])
+        cap = [int(c) for c in (capacity or [0] * npnt)]
+        offs = np.concatenate([[0], np.cumsum(cap)[:-1]]).astype(np.uint64)
+        total = int(sum(cap))
+        dev = torch.device("cuda", self.device)
+        xhat = torch.empty((max(total, 1), 2 * KMAX), dtype=torch.float32, device=dev)
+        index = torch.empty((max(total, 1),), dtype=torch.int64, device=dev)
+        caps = (C.c_uint64 * npnt)(*cap)
+        offc = (C.c_uint64 * npnt)(*[int(v) for v in offs])
+        sts = (Stats * npnt)()
+        _check(lib.tkdv_sample_sweep(self._h, npnt, pts, pls, tg, mp, int(precision),
+                                     C.byref(cfg) if cfg is not None else None, _ptr(xhat), _ptr(index),
+                                     caps, offc, sts, _stream(stream)), self._h)
+        out = []
+        for p in range(npnt):
+            d = sts[p].to_dict()
+            o, nw = int(offs[p]), d["n_written"]
+            d["xhat"] = xhat[o:o + nw, : 2 * points[p].K]
+            d["index"] = index[o:o + nw]
+            out.append(d)
+        return out, xhat, index
+
+    def set_launch_cfg(self, K: int, precision: int, cfg: LaunchCfg):
+        _check(lib.tkdv_set_launch_cfg(self._h, int(K), int(precision), C.byref(cfg)), self._h)
+
+    def get_launch_cfg(self, K: int, precision: int) -> LaunchCfg:
+        c = LaunchCfg()
+        _check(lib.tkdv_get_launch_cfg(self._h, int(K), int(precision), C.byref(c)), self._h)
+        return c
+
+    def autotune(self, K: int, precision: int = BF16X3, cache_path: str | None = None) -> LaunchCfg:
+        c = LaunchCfg()
+        _check(lib.tkdv_autotune(self._h, int(K), int(precision),
+                                 cache_path.encode() if cache_path else None, C.byref(c)), self._h)
+        return c
 
     def synthesize(self, xhat, precision: int = BF16X3, s3=None, stream=None):
         """s3[r] = sum_j u~_j^3 on the N = 4K grid for rows x^ (n, 2K) float32 on the device."""
