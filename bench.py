@@ -18,6 +18,9 @@ learned defensive-mixture proposal against the paper's Sigma proposal.
   KS p-values of u(0) between the two samplers' outputs are reported.
 --workload plain: the paper's sampler alone on 8 beta' x beta'C3/C2 in
 {6000, 12000}, 1e9 proposals per point (the plain GPU configuration).
+--workload sweep: 256 points of K in {16, 32, 64} with accepted targets in
+[1e4, 1e6] (the batched-sweep configuration), windows replayed as a hipGraph
+with the autotuner's launch configuration.
 
 Prints one JSON line with the roofline of the dominant kernel (ALU-bound)
 from HIP events recorded inside the library on the kernel's own stream, and
@@ -441,12 +444,117 @@ def learned_bench(args) -> int:
     return 0
 
 
+def sweep_bench(args) -> int:
+    """The batched sweep: 256 points of mixed K with accepted targets, windows
+    replayed as a hipGraph, launch configuration from the autotuner."""
+    import numpy as np
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs an MI355X GPU", file=sys.stderr)
+        return 1
+    from paper_2411_16952_amd import tkdv as T
+    from paper_2411_16952_amd import workloads as W
+
+    prec = T.PRECISIONS[args.precision]
+    ctx = T.Context(0)
+    t0 = time.perf_counter()
+    tuned = {K: ctx.autotune(K, prec, args.tune_cache).to_dict() for K in (16, 32, 64)}
+    tune_s = time.perf_counter() - t0
+    print(f"autotune {tune_s:.1f}s: {tuned}", file=sys.stderr, flush=True)
+    # screen the seeded candidates: acceptance >= 1e-4 on 1e6 proposals
+    t0 = time.perf_counter()
+    kept, kept_plans = [], []
+    cands = W.sweep_candidates()
+    def plan_or_none(p):
+        try:
+            return T.plan_point(p, T.SIGMA)
+        except T.TkdvError:
+            return None
+
+    pool = cf.ThreadPoolExecutor(max_workers=16)
+    for b0 in range(0, len(cands), 64):
+        batch = cands[b0:b0 + 64]
+        cpts = [T.make_point(sp.point.K, sp.point.E0, sp.point.beta_p, sp.point.c32, seed=sp.point.seed,
+                             point_id=sp.point.point_id) for sp in batch]
+        cplans = list(pool.map(plan_or_none, cpts))
+        pts, plans, specs = [], [], []
+        for sp, p, pl in zip(batch, cpts, cplans):
+            if pl is not None:
+                pts.append(p)
+                plans.append(pl)
+                specs.append(sp)
+        out, _, _ = ctx.sample_batch(pts, [10**6] * len(pts), plans=plans, precision=prec)
+        for sp, p, pl, o in zip(specs, pts, plans, out):
+            if o["n_accepted"] >= 100 and len(kept) < W.SWEEP_N:
+                kept.append((sp, p))
+                kept_plans.append(pl)
+        if len(kept) >= W.SWEEP_N:
+            break
+    pool.shutdown()
+    screen_s = time.perf_counter() - t0
+    pts = [p for _, p in kept]
+    targets = [int(sp.target) for sp, _ in kept]
+    maxp = [W.SWEEP_CAP] * len(pts)
+    caps = [min(t, 1 << 14) for t in targets]
+    Ks = [p.K for p in pts]
+    print(f"sweep: {len(pts)} points (K=16: {Ks.count(16)}, 32: {Ks.count(32)}, 64: {Ks.count(64)}), "
+          f"targets sum {sum(targets):.3g}; screening {screen_s:.1f}s", file=sys.stderr, flush=True)
+
+    def step():
+        return ctx.sample_sweep(pts, targets, maxp, plans=kept_plans, precision=prec, capacity=caps)[0]
+
+    for w in range(args.warmup):
+        step()
+        print(f"warmup {w} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    acc = prop = 0
+    ops = 0.0
+    windows = []
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        out = step()
+        windows.append(ctx.timing()["windows"])
+        acc += sum(int(o["n_accepted"]) for o in out)
+        prop += sum(int(o["n_proposed"]) for o in out)
+        ops += sum(alu_ops_per_proposal(p.K, "sigma", args.precision) * int(o["n_proposed"])
+                   for p, o in zip(pts, out))
+        print(f"sweep step {s}: {ctx.timing()['total_ms']:.0f} ms, {windows[-1]} windows", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    met = sum(int(o["n_accepted"]) >= t for o, t in zip(out, targets))
+    roof = {"bound": "alu", "achieved": ops / dt / 1e12, "peak": ALU_OPS_PER_S / 1e12, "unit": "T ALU ops/s",
+            "frac": ops / dt / ALU_OPS_PER_S, "traffic": None, "kernel": "k_decide (all K, whole sweep)",
+            "note": "algorithmic ops of all proposals over the whole sweep's wall time (every phase), a lower "
+                    "bound on the decide kernels' own rate"}
+    n_cpu = (1 << 12) if args.cpu_sample < 0 else args.cpu_sample
+    cpu = cpu_baseline(pts, kept_plans, n_cpu) if n_cpu > 0 else None
+    line = {
+        "metric": "accepted samples/sec, batched sweep (256 points, K in {16,32,64}, accepted targets)",
+        "value": acc / dt, "unit": "accepted samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched sweep: 256 points, K uniform in {16,32,64}, beta' ~ U[10,80], E0 in "
+                               "{0.5,1,pi/2,2}, beta'C3/C2 sqrt(E0) ~ U[0, P_max(K)], acceptance >= 1e-4, "
+                               "targets log-uniform in [1e4,1e6], cap 1e10 proposals/point, windows as hipGraph "
+                               "replays", "points": len(pts), "targets_sum": sum(targets),
+                   "synthesis": args.precision},
+        "proposals_per_s": prop / dt, "targets_met": met, "windows_per_step": windows,
+        "autotuned": {str(k): v for k, v in tuned.items()}, "autotune_seconds": tune_s,
+        "screen_seconds": screen_s, "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="learned", choices=["learned", "plain"])
+    ap.add_argument("--workload", default="learned", choices=["learned", "plain", "sweep"])
+    ap.add_argument("--tune-cache", default="/tmp/tkdv_autotune.txt", help="autotuner cache (sweep workload)")
     ap.add_argument("--proposals", type=float, default=1e9, help="proposals per point (per sampler)")
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16", "bf16x3"])
     ap.add_argument("--cpu-sample", type=int, default=-1,
@@ -476,6 +584,8 @@ def main() -> int:
               file=sys.stderr)
         return 2
 
+    if args.workload == "sweep":
+        return sweep_bench(args)
     return learned_bench(args) if args.workload == "learned" else plain_bench(args)
 
 

@@ -68,3 +68,38 @@ def learned_eval_points() -> list[PointSpec]:
             pid = 1000 + len(pts)
             pts.append(PointSpec(32, 1.0, bp, lvl / bp, pid, pid))
     return pts
+
+# Batched sweep: 256 points, K uniform in {16, 32, 64}, beta' ~ U[10, 80],
+# E0 in {0.5, 1, pi/2, 2}, beta' C3/C2 sqrt(E0) ~ U[0, P_max(K)] (the ranges of
+# Tables 1-2 scaled with K), accepted targets log-uniform in [1e4, 1e6], a cap
+# of 1e10 proposals per point; half of the points labelled "upstream", half
+# "downstream" (a label only: the paper gives no depth -> (C3, C2) map).
+# Candidates come in a fixed seeded sequence; the benchmark keeps the first
+# 256 whose acceptance (measured on 1e6 proposals) is at least 1e-4.
+SWEEP_N = 256
+SWEEP_P_MAX = {16: 2800.0, 32: 7500.0, 64: 18000.0}
+SWEEP_E0 = (0.5, 1.0, 1.5707963267948966, 2.0)
+SWEEP_CAP = 10**10
+
+
+@dataclass(frozen=True)
+class SweepSpec:
+    point: PointSpec
+    target: int
+    label: str
+
+
+def sweep_candidates(seed: int = 2024, n: int = 4 * SWEEP_N) -> list[SweepSpec]:
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(n):
+        K = int(rng.choice([16, 32, 64]))
+        bp = float(rng.uniform(10.0, 80.0))
+        E0 = float(rng.choice(SWEEP_E0))
+        P = float(rng.uniform(0.0, SWEEP_P_MAX[K]))
+        c = P / (bp * E0 ** 0.5)
+        target = int(round(10 ** rng.uniform(4.0, 6.0)))
+        out.append(SweepSpec(PointSpec(K, E0, bp, c, 5000 + q, 5000 + q), target,
+                             "upstream" if q % 2 == 0 else "downstream"))
+    return out
