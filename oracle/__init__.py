@@ -42,6 +42,7 @@ from .core import (  # noqa: F401
     mix_log_q,
     mix_draw,
     mix_sample,
+    mix_proposal,
     mix_eps,
     mix_threshold,
     stats_of,

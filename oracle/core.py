@@ -331,6 +331,15 @@ def mix_draw(K, E0, beta_p, c32, alpha_star, mixture, seed, point_id, i):
     return xh, comp, lu.value
 
 
+def mix_proposal(K, E0, beta_p, c32, alpha_star, log_M_mix, mixture, seed, point_id, i):
+    """(x^, log a, log U) of mixture proposal i (log a with log M_mix)."""
+    p = _point(K, 4 * K, 1, point_id, E0, beta_p, c32, alpha_star, log_M_mix, seed)
+    xh = np.zeros(2 * K)
+    lu = C.c_double()
+    la = lib.orc_mix_proposal(C.byref(p), C.byref(mixture), i, _dp(xh), C.byref(lu))
+    return xh, la, lu.value
+
+
 def mix_sample(K, E0, beta_p, c32, alpha_star, log_M_mix, mixture, seed, point_id, n, i0=0,
                cap=0, want_log=False, nthreads=0):
     """Rejection sampler with the mixture proposal over indices [i0, i0+n)."""
