@@ -39,10 +39,26 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X vector ALU peak: 256 compute units x 2.4 GHz x 128 lane-operations per
-# clock per CU -- the published FP32 vector rate of 157.3 TFLOP/s counted as
-# operations (an FMA is one operation).
-ALU_OPS_PER_S = 256 * 2.4e9 * 128
+# MI355X vector ALU issue peak: 256 compute units x 4 SIMDs x 16 lanes x 2.4 GHz
+# = 39.3e12 lane-operations/s for instructions without a packed form (a wave
+# of 64 lanes issues over 4 clocks; FP64 FMA runs at this rate: 78.6 TFLOP/s).
+# The published FP32 vector rate of 157.3 TFLOP/s is twice this with an FMA
+# counted as one operation, reached only by packed two-wide FP32 instructions;
+# the sampler's operations are mostly integer products, bit operations,
+# conversions and transcendentals (quarter rate), which have no packed form,
+# and the library is built without packed FP32.  Both figures are reported.
+ALU_OPS_PER_S = 256 * 4 * 16 * 2.4e9
+PACKED_FP32_OPS_PER_S = 2 * ALU_OPS_PER_S
+
+
+def alu_roof(achieved: float, **extra) -> dict:
+    """Roofline object of an ALU-bound kernel (achieved in lane-operations/s)."""
+    r = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_OPS_PER_S / 1e12, "unit": "T ALU ops/s",
+         "frac": achieved / ALU_OPS_PER_S}
+    r.update(extra)
+    r["peak_packed_fp32"] = PACKED_FP32_OPS_PER_S / 1e12
+    r["frac_of_packed_fp32"] = achieved / PACKED_FP32_OPS_PER_S
+    return r
 
 
 def alu_ops_per_proposal(K: int, proposal: str = "sigma", precision: str = "bf16x3") -> float:
@@ -209,15 +225,13 @@ def plain_bench(args) -> int:
     ops = alu_ops_per_proposal(K, "sigma", args.precision)
     achieved = ops * per_launch_props / avg_decide_s
     traffic = load_traffic(K, args.precision, per_launch_props)
-    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_OPS_PER_S / 1e12,
-            "unit": "T ALU ops/s", "frac": achieved / ALU_OPS_PER_S,
-            "traffic": traffic, "kernel": "k_decide",
-            "algorithmic_ops_per_proposal": ops,
-            "avg_launch_ms": avg_decide_s * 1e3,
-            "proposals_per_launch": per_launch_props,
-            "mfma_flops_per_proposal": mfma_flops_per_proposal(K, args.precision),
-            "mfma_frac": mfma_flops_per_proposal(K, args.precision) * per_launch_props / avg_decide_s
-                         / (2.5e15 if args.precision != "fp32" else 157.3e12)}
+    roof = alu_roof(achieved, traffic=traffic, kernel="k_decide",
+                    algorithmic_ops_per_proposal=ops,
+                    avg_launch_ms=avg_decide_s * 1e3,
+                    proposals_per_launch=per_launch_props,
+                    mfma_flops_per_proposal=mfma_flops_per_proposal(K, args.precision),
+                    mfma_frac=mfma_flops_per_proposal(K, args.precision) * per_launch_props / avg_decide_s
+                    / (2.5e15 if args.precision != "fp32" else 157.3e12))
 
     cpu = None
     n_cpu = (1 << 22) if args.cpu_sample < 0 else args.cpu_sample
@@ -384,12 +398,11 @@ def learned_bench(args) -> int:
     ops = alu_ops_per_proposal(K, "mixture", args.precision)
     achieved = ops * n_per / avg_launch_s
     mflops = mfma_flops_per_proposal(K, args.precision, "mixture")
-    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_OPS_PER_S / 1e12,
-            "unit": "T ALU ops/s", "frac": achieved / ALU_OPS_PER_S,
-            "traffic": load_traffic(K, args.precision, n_per, "k_decide_mix"), "kernel": "k_decide_mix",
-            "algorithmic_ops_per_proposal": ops, "avg_launch_ms": avg_launch_s * 1e3,
-            "proposals_per_launch": n_per, "mfma_flops_per_proposal": mflops,
-            "mfma_frac": mflops * n_per / avg_launch_s / (2.5e15 if args.precision != "fp32" else 157.3e12)}
+    roof = alu_roof(achieved, traffic=load_traffic(K, args.precision, n_per, "k_decide_mix"),
+                    kernel="k_decide_mix", algorithmic_ops_per_proposal=ops,
+                    avg_launch_ms=avg_launch_s * 1e3, proposals_per_launch=n_per,
+                    mfma_flops_per_proposal=mflops,
+                    mfma_frac=mflops * n_per / avg_launch_s / (2.5e15 if args.precision != "fp32" else 157.3e12))
 
     n_cpu = (1 << 17) if args.cpu_sample < 0 else args.cpu_sample
     cpu = cpu_plain = None
@@ -523,10 +536,9 @@ def sweep_bench(args) -> int:
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     met = sum(int(o["n_accepted"]) >= t for o, t in zip(out, targets))
-    roof = {"bound": "alu", "achieved": ops / dt / 1e12, "peak": ALU_OPS_PER_S / 1e12, "unit": "T ALU ops/s",
-            "frac": ops / dt / ALU_OPS_PER_S, "traffic": None, "kernel": "k_decide (all K, whole sweep)",
-            "note": "algorithmic ops of all proposals over the whole sweep's wall time (every phase), a lower "
-                    "bound on the decide kernels' own rate"}
+    roof = alu_roof(ops / dt, traffic=None, kernel="k_decide (all K, whole sweep)",
+                    note="algorithmic ops of all proposals over the whole sweep's wall time (every phase), a "
+                         "lower bound on the decide kernels' own rate")
     n_cpu = (1 << 12) if args.cpu_sample < 0 else args.cpu_sample
     cpu = cpu_baseline(pts, kept_plans, n_cpu) if n_cpu > 0 else None
     line = {

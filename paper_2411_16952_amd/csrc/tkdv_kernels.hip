@@ -409,72 +409,107 @@ __global__ void __launch_bounds__(kBlock) k_fixup(KernelArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// k_fixup_mix: FP64 re-decision of listed proposals of the mixture sampler,
-// one wave per proposal, lane m = coordinate m (2K <= 64): the draw of
-// gen_x_mix in FP64 (component from the same word, in integers), log f with
-// H3 by the double sum over triads (lane n - 2 takes the inner sum of n),
-// and log q_mix with x^T L0^-1 x = e^T A e + |g|^2, g = G^-1 V^T A w,
-// e = w - V g for w = R_j^T x^ (no cancellation), summed over the shifts
-// with a running log-sum-exp.  log a = log f - log q_mix - log M.
+// k_fixup_mix: FP64 re-decision of listed proposals of the mixture sampler.
+// Each half-wave takes one proposal (two per wave), lane l of the half:
+//   * the Box-Muller pair l (coordinates 2l, 2l+1) of the draw of gen_x_mix
+//     in FP64, the component from the same word, in integers;
+//   * mode n = l + 2 of the double sum over triads of H3;
+//   * shift j = l of q_net: x^T L0^-1 x of w = R_j^T x^ as e^T A e + |g|^2,
+//     g = G^-1 V^T A w, e = w - V g (no cancellation), over all K modes;
+// then a half-wave log-sum-exp over the shifts.
+// log a = log f - log q_mix - log M.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double half_sum_f64(double v)
+{
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double half_max_f64(double v)
+{
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ unsigned long long read_lane_u64(unsigned long long v, int l)
+{
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 template <int K>
 __global__ void __launch_bounds__(kBlock) k_fixup_mix(KernelArgs a)
 {
-    __shared__ double xs[kBlock / kWave][2 * K];
-    const int m = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    double *x = xs[wv];
-    const bool act = m < 2 * K;
-    const bool sinb = m >= K;
-    const int k = m % K + 1;  // mode of this lane's coordinate
+    static_assert(K <= 32 && kMixS == 32, "one lane per Box-Muller pair, triad mode and shift");
+    __shared__ double xs[kBlock / kWave][2][2 * K];
+    const int lane = threadIdx.x & 63, h = lane >> 5, l = lane & 31;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double *x = xs[wv][h];
     const double pi = 3.14159265358979323846;
     const unsigned long long cnt = *a.defer_count;
     const unsigned long long n = cnt < a.defer_cap ? cnt : a.defer_cap;
     const unsigned long long nw = (unsigned long long)gridDim.x * (kBlock / kWave);
-    for (unsigned long long e = (unsigned long long)blockIdx.x * (kBlock / kWave) + wv; e < n; e += nw) {
-        const unsigned long long v = bcast_lane0(a.defer_list[e]);
+    for (unsigned long long e0 = 2ull * ((unsigned long long)blockIdx.x * (kBlock / kWave) + wv); e0 < n;
+         e0 += 2ull * nw) {
+        // a second half past the end repeats the first half's proposal; its
+        // result is not used
+        const bool item = e0 + h < n;
+        const unsigned long long v = a.defer_list[item ? e0 + h : e0];
         const int p = (int)(v >> 40);
         const uint64_t i = v & ((1ull << 40) - 1ull);
         const DevPoint &P = a.pts[p];
         const DevMix &M = a.mix[p];
         const uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32);
-        // normal of coordinate m: Box-Muller pair (words 2q, 2q+1) of block m/4
-        double z = 0.0;
-        if (act) {
-            const uint4 w = philox4x32_10(c0, c1, P.point_id, (uint32_t)(m / 4), P.key0, P.key1);
-            const int q = (m % 4) & ~1;
-            const uint32_t w1 = q == 0 ? w.x : w.z, w2 = q == 0 ? w.y : w.w;
+        const uint4 wl = philox4x32_10(c0, c1, P.point_id, (uint32_t)(K / 2), P.key0, P.key1);
+        const int comp = wl.y < M.E ? -1 : (int)((wl.y - M.E) / M.B);
+        // eta pair of the component (every lane; used when comp >= 0)
+        double e0v = 0.0, e1v = 0.0;
+        if (comp >= 0) {
+            const double r = sqrt(-2.0 * log(((double)wl.z + 0.5) * 0x1p-32));
+            const double th = 2.0 * pi * (((double)wl.w + 0.5) * 0x1p-32);
+            e0v = r * cos(th);
+            e1v = r * sin(th);
+        }
+        // coordinate m from its normal z
+        auto coord = [&](int m, double z) {
+            const int k = m % K + 1;
+            if (comp < 0) return P.sig64[k - 1] * z;
+            const int mi = (k * comp) & (kMixS - 1);
+            const double cs = M.cs64[mi], sn = M.sn64[mi];
+            const double *vc = M.V64[k - 1], *vs = M.V64[K + k - 1];
+            const bool sinb = m >= K;
+            const double r0 = sinb ? vs[0] * cs - vc[0] * sn : vc[0] * cs + vs[0] * sn;
+            const double r1 = sinb ? vs[1] * cs - vc[1] * sn : vc[1] * cs + vs[1] * sn;
+            return M.sqd64[k - 1] * z + r0 * e0v + r1 * e1v;
+        };
+        double X0 = 0.0, X1 = 0.0;
+        if (l < K) {
+            const uint4 w = philox4x32_10(c0, c1, P.point_id, (uint32_t)(l / 2), P.key0, P.key1);
+            const uint32_t w1 = (l & 1) ? w.z : w.x, w2 = (l & 1) ? w.w : w.y;
             const double r = sqrt(-2.0 * log(((double)w1 + 0.5) * 0x1p-32));
             const double th = 2.0 * pi * (((double)w2 + 0.5) * 0x1p-32);
-            z = (m & 1) ? r * sin(th) : r * cos(th);
+            X0 = coord(2 * l, r * cos(th));
+            X1 = coord(2 * l + 1, r * sin(th));
         }
-        const uint4 wl = philox4x32_10(c0, c1, P.point_id, (uint32_t)(K / 2), P.key0, P.key1);
-        const double log_u = log(((double)wl.x + 0.5) * 0x1p-32);
-        const int comp = wl.y < M.E ? -1 : (int)((wl.y - M.E) / M.B);
-        double X = 0.0;
-        if (act) {
-            if (comp < 0) {
-                X = P.sig64[k - 1] * z;
-            } else {
-                const double r = sqrt(-2.0 * log(((double)wl.z + 0.5) * 0x1p-32));
-                const double th = 2.0 * pi * (((double)wl.w + 0.5) * 0x1p-32);
-                const double e0 = r * cos(th), e1 = r * sin(th);
-                const int mi = (k * comp) & (kMixS - 1);
-                const double cs = M.cs64[mi], sn = M.sn64[mi];
-                const double *vc = M.V64[k - 1], *vs = M.V64[K + k - 1];
-                const double r0 = sinb ? vs[0] * cs - vc[0] * sn : vc[0] * cs + vs[0] * sn;
-                const double r1 = sinb ? vs[1] * cs - vc[1] * sn : vc[1] * cs + vs[1] * sn;
-                X = M.sqd64[k - 1] * z + r0 * e0 + r1 * e1;
-            }
+        const double inv_r = 1.0 / sqrt(half_sum_f64(X0 * X0 + X1 * X1));
+        const double x0 = X0 * inv_r, x1 = X1 * inv_r;
+        if (l < K) {
+            x[2 * l] = x0;
+            x[2 * l + 1] = x1;
         }
-        const double xm = X / sqrt(wave_sum_f64(X * X));
-        if (act) x[m] = xm;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        const double t = wave_sum_f64(act ? (double)k * k * xm * xm : 0.0);
+        double tk = 0.0;
+        if (l < K) {
+            const double k0 = (2 * l) % K + 1, k1 = (2 * l + 1) % K + 1;
+            tk = k0 * k0 * x0 * x0 + k1 * k1 * x1 * x1;
+        }
+        const double t = half_sum_f64(tk);
         // H3 by the double sum: lane l takes n = l + 2
         double tri = 0.0;
         {
-            const int nn = m + 2;
+            const int nn = l + 2;
             if (nn <= K) {
                 const double s = sqrt(P.E0 / (2.0 * pi));
                 double in_re = 0.0, in_im = 0.0;
@@ -487,45 +522,59 @@ __global__ void __launch_bounds__(kBlock) k_fixup_mix(KernelArgs a)
                 tri = (s * x[nn - 1]) * in_re + (-s * x[K + nn - 1]) * in_im;
             }
         }
-        const double H3 = 2.0 * pi * wave_sum_f64(tri);
+        const double H3 = 2.0 * pi * half_sum_f64(tri);
         const double lf = -(P.beta_p / (P.E0 * (double)K * K) * (P.E0 * t - P.c32 * H3));
-        // q_net over the shifts
-        const double xp = act ? x[sinb ? m - K : m + K] : 0.0;
-        const double am = act ? M.a64[k - 1] : 0.0;
-        const double v0 = act ? M.V64[m][0] : 0.0, v1 = act ? M.V64[m][1] : 0.0;
-        double mx = -INFINITY, se = 0.0;
-        for (int j = 0; j < kMixS; ++j) {
-            const int mi = (k * j) & (kMixS - 1);
+        // q_net: shift j = l
+        double y0 = 0.0, y1 = 0.0;
+#pragma unroll 4
+        for (int k = 1; k <= K; ++k) {
+            const int mi = (k * l) & (kMixS - 1);
             const double cs = M.cs64[mi], sn = M.sn64[mi];
-            const double w = act ? (sinb ? xm * cs + xp * sn : xm * cs - xp * sn) : 0.0;
-            const double y0 = wave_sum_f64(v0 * am * w), y1 = wave_sum_f64(v1 * am * w);
-            const double g0 = M.gi64[0][0] * y0 + M.gi64[0][1] * y1;
-            const double g1 = M.gi64[1][0] * y0 + M.gi64[1][1] * y1;
-            const double ee = w - (v0 * g0 + v1 * g1);
-            const double qf = wave_sum_f64(am * ee * ee) + g0 * g0 + g1 * g1;
-            const double l = -K * log(qf);
-            if (l > mx) {
-                se = se * exp(mx - l) + 1.0;
-                mx = l;
-            } else {
-                se += exp(l - mx);
-            }
+            const double xc = x[k - 1], xsn = x[K + k - 1];
+            const double wc = xc * cs - xsn * sn, ws = xsn * cs + xc * sn;
+            const double ak = M.a64[k - 1];
+            y0 += ak * (M.V64[k - 1][0] * wc + M.V64[K + k - 1][0] * ws);
+            y1 += ak * (M.V64[k - 1][1] * wc + M.V64[K + k - 1][1] * ws);
         }
+        const double g0 = M.gi64[0][0] * y0 + M.gi64[0][1] * y1;
+        const double g1 = M.gi64[1][0] * y0 + M.gi64[1][1] * y1;
+        double qf = g0 * g0 + g1 * g1;
+#pragma unroll 4
+        for (int k = 1; k <= K; ++k) {
+            const int mi = (k * l) & (kMixS - 1);
+            const double cs = M.cs64[mi], sn = M.sn64[mi];
+            const double xc = x[k - 1], xsn = x[K + k - 1];
+            const double wc = xc * cs - xsn * sn, ws = xsn * cs + xc * sn;
+            const double ec = wc - (M.V64[k - 1][0] * g0 + M.V64[k - 1][1] * g1);
+            const double es = ws - (M.V64[K + k - 1][0] * g0 + M.V64[K + k - 1][1] * g1);
+            qf += M.a64[k - 1] * (ec * ec + es * es);
+        }
+        const double lj = -K * log(qf);
+        const double mx = half_max_f64(lj);
+        const double se = half_sum_f64(exp(lj - mx));
         const double lnet = -0.5 * M.logdetL0 + mx + log(se) - log((double)kMixS);
         const double lg = M.lng - K * log1p(P.alpha_star * P.beta_p * t / ((double)K * K * K));
         const double A = M.log_eps + lg, B = M.log_1m_eps + lnet;
         const double hi = A > B ? A : B;
         const double lq = hi + log(exp(A - hi) + exp(B - hi));
+        const double log_u = log(((double)wl.x + 0.5) * 0x1p-32);
         const double log_a = lf - lq - P.log_M64;
-        // every lane issues the updates (lane 0 carries them): no lane-0-only
-        // region next to the wave reductions of the next iteration
-        const bool acc = __builtin_amdgcn_readfirstlane((int)(log_u < log_a)) != 0;
-        if (acc) {
-            const uint64_t local = i - P.i0;
-            atomicOr(&a.bitmap[P.bm_off + local / 32], m == 0 ? 1u << (local % 32) : 0u);
-            atomicAdd(&a.cnt[p].fix_accepted, m == 0 ? 1ull : 0ull);
+        // updates of each half in turn, under a wave-uniform condition at a
+        // wave-uniform address (lane 0 of the wave carries the value)
+        const bool acc = item && log_u < log_a;
+        const unsigned long long bm_word = P.bm_off + (i - P.i0) / 32;
+        const uint32_t bit = 1u << ((i - P.i0) % 32);
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            if (__builtin_amdgcn_readlane((int)acc, 32 * hh) != 0) {
+                const unsigned long long wrd = read_lane_u64(bm_word, 32 * hh);
+                const uint32_t b = __builtin_amdgcn_readlane(bit, 32 * hh);
+                const int pp = __builtin_amdgcn_readlane(p, 32 * hh);
+                atomicOr(&a.bitmap[wrd], lane == 0 ? b : 0u);
+                atomicAdd(&a.cnt[pp].fix_accepted, lane == 0 ? 1ull : 0ull);
+            }
         }
-        // the next proposal overwrites this wave's copy of x^
+        // the next proposals overwrite this wave's copies of x^
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
     }
@@ -919,7 +968,9 @@ __global__ void __launch_bounds__(BLOCK) k_synth(const float *__restrict__ xhat,
                                                  const void *phi_lo)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
-    constexpr int tab = PREC == PREC_FP32 ? f32_table_bytes<K>() : bf16_table_bytes<K>();
+    // the first synth_table_tiles<K>() grid tiles of the tables (cube_sum_os)
+    constexpr int tab = (PREC == PREC_FP32 ? f32_table_bytes<K>() : bf16_table_bytes<K>()) /
+                        (K / 8) * synth_table_tiles<K>();
     {
         const uint4 *s0 = reinterpret_cast<const uint4 *>(phi_hi);
         uint4 *d = reinterpret_cast<uint4 *>(lds);
@@ -935,8 +986,9 @@ __global__ void __launch_bounds__(BLOCK) k_synth(const float *__restrict__ xhat,
     const unsigned long long waves = (unsigned long long)gridDim.x * (BLOCK / kWave);
     unsigned long long tile = (unsigned long long)blockIdx.x * (BLOCK / kWave) + (threadIdx.x >> 6);
     // rows of the next tile are loaded while the current tile is on the matrix
-    // cores, where the register budget allows it (8-wave workgroups)
-    constexpr bool prefetch = BLOCK <= 512;
+    // cores, where the register budget allows it (not beside the four live
+    // K = 32 FP32 and BF16x3 accumulators)
+    constexpr bool prefetch = BLOCK <= 512 && !(K == 32 && PREC != PREC_BF16);
     float4 nxt[K / 4];
     auto load_tile = [&](unsigned long long tl) {
         const unsigned long long row = tl * kTile + pl;
@@ -959,22 +1011,32 @@ __global__ void __launch_bounds__(BLOCK) k_synth(const float *__restrict__ xhat,
             x[4 * q + 3] = nxt[q].w;
         }
         if (prefetch && tile + waves < n_tiles) load_tile(tile + waves);
-        const float s3l = synth_cube_sum<K, PREC, true>(x, lds, lds + tab, lane);
+        bf16x8 bh[K / 8], bl[K / 8];
+        if constexpr (PREC != PREC_FP32) split_bf16<K, PREC>(x, bh, bl);
+        const float s3l = cube_sum_os<K, PREC>(x, bh, bl, lds, lds + tab, lane);
         const float s3 = s3l + xor32(s3l);
         if (valid && half == 0) s3_out[row] = s3;
     }
 }
 
-// Workgroup size: at K = 64 the tables fill most of the LDS, so one workgroup
-// of 16 waves (4 per SIMD) runs per CU; smaller K use 8-wave workgroups.
+// Workgroup size: 8 waves, 4 at K = 64 (two workgroups per CU with the
+// halved tables in LDS; measured fastest there).
 template <int K>
-constexpr int synth_block() { return K >= 64 ? 1024 : kSynthBlock; }
+constexpr int synth_block() { return K == 64 ? kSynthBlock / 2 : kSynthBlock; }
+
+template <int K, int PREC>
+constexpr int synth_lds_bytes()
+{
+    constexpr int tab = (PREC == PREC_FP32 ? f32_table_bytes<K>() : bf16_table_bytes<K>()) / (K / 8) *
+                        synth_table_tiles<K>();
+    return PREC == PREC_BF16X3 ? 2 * tab : tab;
+}
 
 template <int K, int PREC>
 static hipError_t launch_synth_t(const float *xhat, unsigned long long n, float *s3, const void *phi_hi,
                                  const void *phi_lo, int n_cu, hipStream_t st, int *grid_out)
 {
-    constexpr int lds = decide_lds_bytes<K, PREC>();
+    constexpr int lds = synth_lds_bytes<K, PREC>();
     constexpr int B = synth_block<K>();
     auto kern = k_synth<K, PREC, B>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
