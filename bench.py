@@ -478,32 +478,25 @@ def sweep_bench(args) -> int:
     t0 = time.perf_counter()
     kept, kept_plans = [], []
     cands = W.sweep_candidates()
-    def plan_or_none(p):
-        try:
-            return T.plan_point(p, T.SIGMA)
-        except T.TkdvError:
-            return None
+    plan_s = 0.0
 
-    pool = cf.ThreadPoolExecutor(max_workers=16)
+    def alpha_root_exists(p):  # a root of F exists iff beta' < K^2 sum_k 1/k^2 (Sec. III.A)
+        return p.beta_p < p.K * p.K * sum(1.0 / (k * k) for k in range(1, p.K + 1))
+
     for b0 in range(0, len(cands), 64):
-        batch = cands[b0:b0 + 64]
+        batch = [sp for sp in cands[b0:b0 + 64] if alpha_root_exists(sp.point)]
         cpts = [T.make_point(sp.point.K, sp.point.E0, sp.point.beta_p, sp.point.c32, seed=sp.point.seed,
                              point_id=sp.point.point_id) for sp in batch]
-        cplans = list(pool.map(plan_or_none, cpts))
-        pts, plans, specs = [], [], []
-        for sp, p, pl in zip(batch, cpts, cplans):
-            if pl is not None:
-                pts.append(p)
-                plans.append(pl)
-                specs.append(sp)
-        out, _, _ = ctx.sample_batch(pts, [10**6] * len(pts), plans=plans, precision=prec)
-        for sp, p, pl, o in zip(specs, pts, plans, out):
+        tp = time.perf_counter()
+        cplans, _ = ctx.plan_batch(cpts, T.SIGMA, n_starts=16, seed=2024)   # log M searched on the GPU
+        plan_s += time.perf_counter() - tp
+        out, _, _ = ctx.sample_batch(cpts, [10**6] * len(cpts), plans=cplans, precision=prec)
+        for sp, p, pl, o in zip(batch, cpts, cplans, out):
             if o["n_accepted"] >= 100 and len(kept) < W.SWEEP_N:
                 kept.append((sp, p))
                 kept_plans.append(pl)
         if len(kept) >= W.SWEEP_N:
             break
-    pool.shutdown()
     screen_s = time.perf_counter() - t0
     pts = [p for _, p in kept]
     targets = [int(sp.target) for sp, _ in kept]
@@ -553,7 +546,8 @@ def sweep_bench(args) -> int:
                    "synthesis": args.precision},
         "proposals_per_s": prop / dt, "targets_met": met, "windows_per_step": windows,
         "autotuned": {str(k): v for k, v in tuned.items()}, "autotune_seconds": tune_s,
-        "screen_seconds": screen_s, "roofline": roof, "cpu_baseline": cpu,
+        "screen_seconds": screen_s, "plan_seconds": plan_s, "plan": "GPU multi-start search (tkdv_plan_batch, 16 starts)",
+        "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

@@ -123,7 +123,7 @@ typedef struct {
     double sigma2[TKDV_KMAX];   /* proposal variances s_k^2, k = 1..K                        */
     int32_t N;                  /* synthesis grid, 4K                                        */
     int32_t proposal;           /* tkdv_proposal                                             */
-    int32_t M_source;           /* 0 closed form (C3/C2 = 0), 1 optimiser                    */
+    int32_t M_source;           /* 0 closed form (C3/C2 = 0), 1 host optimiser, 2 GPU search */
     int32_t n_optimiser_evals;  /* objective evaluations spent on log_M                      */
 } tkdv_plan;
 
@@ -175,6 +175,56 @@ tkdv_status tkdv_destroy(tkdv_ctx *ctx);
  * Nelder-Mead from the zero-mean Dirichlet kernel of Sec. IV.A plus further
  * starts, then refined by gradient ascent on the sphere).  Needs no device. */
 tkdv_status tkdv_plan_point(const tkdv_point *pt, tkdv_proposal proposal, tkdv_plan *out);
+
+/*
+ * Step 1 of Sec. IV.B for many points at once, with the rejection constant
+ * searched on the GPU (the maximisation of Sec. IV.A).  alpha*, s_k^2 and
+ * log_norm_g as tkdv_plan_point; C3/C2 = 0 takes the closed form unless
+ * flags has TKDV_PLAN_SEARCH_ALWAYS.  Otherwise log M is the largest value of
+ * log f - log g (the unnormalised ratio of tkdv_plan_point; log f alone for
+ * the uniform proposal) reached by FP64 L-BFGS ascent on the sphere from
+ * n_starts starts per point, one wavefront each: the zero-mean Dirichlet
+ * kernel of Sec. IV.A, the single-mode state, and n_starts - 2 directions of
+ * independent normal coordinates drawn by Philox4x32-10 with key `seed` and
+ * counter (start, point_id, coordinate pair, 0x504C414E), so a point's plan
+ * does not depend on the other points of the call.  The value and
+ * gradient use the exact N = 4K grid quadrature of H3.  The result is a
+ * lower bound on the supremum, like any search (M_source = 2).
+ *   n_points >= 0; pts and out: host arrays [n_points]; 1 <= K <= 64 (any K);
+ *   n_starts in [1, 256]; proposal UNIFORM or SIGMA;
+ *   xhat_best: host [n_points][2 TKDV_KMAX] doubles or NULL; row p receives
+ *     the maximiser found (first 2K entries, unit norm; zeros where the
+ *     closed form was taken);
+ *   stream: HIP stream (NULL: the null stream); the call returns after it.
+ * Errors: TKDV_E_ARG (bad point, argument or flag), TKDV_E_NO_ALPHA_ROOT (the
+ * point's index in tkdv_last_error), TKDV_E_DEVICE.
+ */
+#define TKDV_PLAN_SEARCH_ALWAYS 1
+tkdv_status tkdv_plan_batch(tkdv_ctx *ctx, int32_t n_points, const tkdv_point *pts, tkdv_proposal proposal,
+                            int32_t n_starts, uint64_t seed, int32_t flags, tkdv_plan *out, double *xhat_best,
+                            void *stream);
+
+/*
+ * Extreme wave fields among stored samples (Sec. V: the largest surface
+ * displacement among individual samples, against 4 sigma = 4 sqrt(E0/pi)).
+ * For each row x^ of d_xhat, u = sqrt(2 E0/pi) Phi^T x^ on the grid
+ * xi_j = -pi + 2 pi j/N, N = 4K (FP32 matrix products); its maximum u_max and
+ * the first grid index j attaining it.  Returns the top_k rows by u_max
+ * (descending, ties by lower row index) and the number of rows with
+ * u_max > threshold.
+ *   K in {8,16,32,64}; E0 > 0; d_xhat: device [n][row_stride] floats, 16-byte
+ *     aligned, row_stride >= 2K and a multiple of 4 (the sampler's rows);
+ *   top_k in [0, TKDV_EXTREMES_MAX_K]; h_rows, h_umax, h_jmax: host arrays
+ *     [top_k] (entries beyond n are UINT64_MAX, NaN, -1); h_n_exceed: host;
+ *   d_umax [n] floats, d_jmax [n] ints: optional device outputs per row;
+ *   stream: HIP stream (NULL: the null stream); the call returns after it.
+ * Errors: TKDV_E_ARG, TKDV_E_UNSUPPORTED (K, or more than 65536 rows tied at
+ * the k-th largest maximum), TKDV_E_DEVICE.
+ */
+#define TKDV_EXTREMES_MAX_K 4096
+tkdv_status tkdv_extremes(tkdv_ctx *ctx, int32_t K, double E0, const float *d_xhat, uint64_t n, uint64_t row_stride,
+                          int32_t top_k, double threshold, uint64_t *h_rows, double *h_umax, int32_t *h_jmax,
+                          uint64_t *h_n_exceed, float *d_umax, int32_t *d_jmax, void *stream);
 
 /*
  * Rejection-sample one point (Sec. IV.B steps 2-5) on the GPU.

@@ -43,6 +43,7 @@ from .core import (  # noqa: F401
     mix_draw,
     mix_sample,
     mix_proposal,
+    extremes,
     mix_eps,
     mix_threshold,
     stats_of,

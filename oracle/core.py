@@ -231,6 +231,24 @@ def grid(xh, E0: float, N: int) -> np.ndarray:
     return u
 
 
+def extremes(xhat, E0: float, N: int, top_k: int, threshold: float) -> dict:
+    """Largest surface displacement of each row (Sec. V, individual wave fields):
+    u on the N-point grid xi_j = -pi + 2 pi j/N (``grid``), its maximum and
+    the first grid index attaining it; the top_k rows by maximum (descending,
+    ties by lower row index); the number of rows whose maximum exceeds
+    `threshold`."""
+    x = np.asarray(xhat, dtype=np.float64)
+    n = x.shape[0]
+    um = np.empty(n)
+    jm = np.empty(n, dtype=np.int64)
+    for r in range(n):
+        u = grid(x[r], E0, N)
+        jm[r] = int(np.argmax(u))
+        um[r] = u[jm[r]]
+    order = np.lexsort((np.arange(n), -um))[:top_k]
+    return {"umax": um, "jmax": jm, "rows": order, "n_exceed": int(np.sum(um > threshold))}
+
+
 def log_ratio(xh, E0, beta_p, c32, alpha, proposal_kind: int, normalise_input=False) -> float:
     """log f/g (proposal_kind 1) or log f (0), unnormalised, at x^ (or y/|y|)."""
     x = _f64(xh)

@@ -11,11 +11,13 @@
 #include <vector>
 
 #include "../../include/tkdv.h"
+#include "tkdv_extremes.h"
 #include "tkdv_internal.h"
 #include "tkdv_kernels.h"
 #include "tkdv_host_math.h"
 #include "tkdv_mixture.h"
 #include "tkdv_plan.h"
+#include "tkdv_plan_gpu.h"
 #include "tkdv_runtime.h"
 
 using namespace tkdv;
@@ -68,6 +70,8 @@ struct tkdv_ctx {
     hipStream_t sweep_stream = nullptr;
     hipEvent_t join[2] = {};
     DevBuf sweep, active;
+    DevBuf plan_pts, plan_val, plan_x, plan_ev;  // tkdv_plan_batch
+    DevBuf ext_keys, ext_jmax, ext_misc, ext_list;  // tkdv_extremes
     void *h_poll = nullptr;  // pinned: active count, FP64 list count
     std::string arch;
 };
@@ -824,7 +828,9 @@ tkdv_status tkdv_destroy(tkdv_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     DevBuf *bufs[] = {&ctx->bitmap, &ctx->defer_list, &ctx->defer_count, &ctx->counters, &ctx->points,
                       &ctx->seg_cnt, &ctx->seg_base, &ctx->seg_stats, &ctx->results, &ctx->plist,
-                      &ctx->mix, &ctx->mix_tab, &ctx->sweep, &ctx->active};
+                      &ctx->mix, &ctx->mix_tab, &ctx->sweep, &ctx->active, &ctx->plan_pts, &ctx->plan_val,
+                      &ctx->plan_x, &ctx->plan_ev, &ctx->ext_keys, &ctx->ext_jmax, &ctx->ext_misc,
+                      &ctx->ext_list};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (int i = 0; i < 4; ++i) {
@@ -851,6 +857,204 @@ tkdv_status tkdv_plan_point(const tkdv_point *pt, tkdv_proposal proposal, tkdv_p
     if (!pt || !out) return set_err(nullptr, TKDV_E_ARG, "NULL argument");
     tkdv_status s = (tkdv_status)plan_point_host(pt, proposal, 2, out);
     if (s != TKDV_OK) return set_err(nullptr, s, "planning failed");
+    return TKDV_OK;
+}
+
+tkdv_status tkdv_plan_batch(tkdv_ctx *ctx, int32_t n_points, const tkdv_point *pts, tkdv_proposal proposal,
+                            int32_t n_starts, uint64_t seed, int32_t flags, tkdv_plan *out, double *xhat_best,
+                            void *stream)
+{
+    if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");
+    if (n_points < 0) return set_err(ctx, TKDV_E_ARG, "n_points < 0");
+    if (n_points == 0) return TKDV_OK;
+    if (!pts || !out) return set_err(ctx, TKDV_E_ARG, "NULL argument");
+    if (n_starts < 1 || n_starts > 256) return set_err(ctx, TKDV_E_ARG, "n_starts must be in [1, 256]");
+    if (proposal != TKDV_PROP_UNIFORM && proposal != TKDV_PROP_SIGMA)
+        return set_err(ctx, TKDV_E_ARG, "proposal must be UNIFORM or SIGMA");
+    if (flags & ~TKDV_PLAN_SEARCH_ALWAYS) return set_err(ctx, TKDV_E_ARG, "unknown flags");
+    if ((int64_t)n_points * n_starts > (int64_t)(1 << 30)) return set_err(ctx, TKDV_E_ARG, "too many starts");
+    std::vector<PlanPoint> pp;
+    std::vector<int> which;
+    for (int p = 0; p < n_points; ++p) {
+        const int st = plan_base_host(&pts[p], proposal, &out[p]);
+        if (st != TKDV_OK)
+            return set_err(ctx, (tkdv_status)st, "point " + std::to_string(p) + ": planning failed");
+        if (xhat_best) std::fill(xhat_best + (size_t)p * 2 * TKDV_KMAX, xhat_best + (size_t)(p + 1) * 2 * TKDV_KMAX, 0.0);
+        if (out[p].M_source == 0 && !(flags & TKDV_PLAN_SEARCH_ALWAYS)) continue;
+        const tkdv_point &q = pts[p];
+        const int K = q.K;
+        PlanPoint P{};
+        P.K = K;
+        P.N = 4 * K;
+        P.sigma = proposal == TKDV_PROP_SIGMA ? 1 : 0;
+        P.point_id = q.point_id;
+        P.dt0 = -q.beta_p / ((double)K * K);
+        P.cH = q.beta_p * q.c32 / (q.E0 * (double)K * K);
+        const double amp = std::sqrt(2.0 * q.E0 / kPi);
+        P.amp3 = amp * amp * amp;
+        P.a = out[p].alpha_star * q.beta_p / ((double)K * K * K);
+        pp.push_back(P);
+        which.push_back(p);
+    }
+    if (which.empty()) return TKDV_OK;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const int n_items = (int)which.size() * n_starts;
+    HIP_TRY(ctx, ensure(ctx->plan_pts, pp.size() * sizeof(PlanPoint)));
+    HIP_TRY(ctx, ensure(ctx->plan_val, (size_t)n_items * sizeof(double)));
+    HIP_TRY(ctx, ensure(ctx->plan_x, (size_t)n_items * 128 * sizeof(double)));
+    HIP_TRY(ctx, ensure(ctx->plan_ev, (size_t)n_items * sizeof(int)));
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->plan_pts.p, pp.data(), pp.size() * sizeof(PlanPoint), hipMemcpyHostToDevice, st));
+    PlanArgs a{};
+    a.pts = (const PlanPoint *)ctx->plan_pts.p;
+    a.n_items = n_items;
+    a.n_starts = n_starts;
+    a.seed_lo = (uint32_t)seed;
+    a.seed_hi = (uint32_t)(seed >> 32);
+    a.val = (double *)ctx->plan_val.p;
+    a.xbest = (double *)ctx->plan_x.p;
+    a.evals = (int *)ctx->plan_ev.p;
+    HIP_TRY(ctx, launch_plan_search(a, st));
+    std::vector<double> val(n_items), xb((size_t)n_items * 128);
+    std::vector<int> ev(n_items);
+    HIP_TRY(ctx, hipMemcpyAsync(val.data(), a.val, val.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipMemcpyAsync(xb.data(), a.xbest, xb.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipMemcpyAsync(ev.data(), a.evals, ev.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    for (size_t w = 0; w < which.size(); ++w) {
+        const int p = which[w];
+        int best = -1;
+        long total = 0;
+        for (int s = 0; s < n_starts; ++s) {
+            const int it = (int)w * n_starts + s;
+            total += ev[it];
+            if (!std::isfinite(val[it])) continue;
+            if (best < 0 || val[it] > val[(size_t)w * n_starts + best]) best = s;
+        }
+        if (best < 0) return set_err(ctx, TKDV_E_DEVICE, "point " + std::to_string(p) + ": search gave no value");
+        const size_t bi = (size_t)w * n_starts + best;
+        out[p].log_M = val[bi];
+        out[p].M_source = 2;
+        out[p].n_optimiser_evals = (int32_t)std::min<long>(total, INT32_MAX);
+        if (xhat_best)
+            for (int m = 0; m < 2 * pts[p].K; ++m) xhat_best[(size_t)p * 2 * TKDV_KMAX + m] = xb[bi * 128 + m];
+    }
+    return TKDV_OK;
+}
+
+tkdv_status tkdv_extremes(tkdv_ctx *ctx, int32_t K, double E0, const float *d_xhat, uint64_t n, uint64_t row_stride,
+                          int32_t top_k, double threshold, uint64_t *h_rows, double *h_umax, int32_t *h_jmax,
+                          uint64_t *h_n_exceed, float *d_umax, int32_t *d_jmax, void *stream)
+{
+    if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");
+    if (kindex(K) < 0) return set_err(ctx, TKDV_E_UNSUPPORTED, "tkdv_extremes supports K in {8,16,32,64}");
+    if (!std::isfinite(E0) || !(E0 > 0.0)) return set_err(ctx, TKDV_E_ARG, "E0 must be finite and > 0");
+    if (top_k < 0 || top_k > TKDV_EXTREMES_MAX_K) return set_err(ctx, TKDV_E_ARG, "top_k out of range");
+    if (top_k > 0 && (!h_rows || !h_umax || !h_jmax)) return set_err(ctx, TKDV_E_ARG, "NULL output array");
+    if (!h_n_exceed) return set_err(ctx, TKDV_E_ARG, "h_n_exceed is NULL");
+    if (std::isnan(threshold)) return set_err(ctx, TKDV_E_ARG, "threshold is NaN");
+    if (row_stride < (uint64_t)(2 * K) || row_stride % 4 != 0)
+        return set_err(ctx, TKDV_E_ARG, "row_stride must be >= 2K and a multiple of 4");
+    if (n > 0 && (!d_xhat || ((uintptr_t)d_xhat & 15u)))
+        return set_err(ctx, TKDV_E_ARG, "d_xhat must be a 16-byte aligned device pointer");
+    for (int i = 0; i < top_k; ++i) {
+        h_rows[i] = UINT64_MAX;
+        h_umax[i] = std::nan("");
+        h_jmax[i] = -1;
+    }
+    *h_n_exceed = 0;
+    if (n == 0) return TKDV_OK;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    tkdv_status bs = build_tables(ctx, K);
+    if (bs != TKDV_OK) return bs;
+    hipStream_t st = (hipStream_t)stream;
+    const int ki = kindex(K);
+    const unsigned long long cap_eq = 1ull << 16;
+    HIP_TRY(ctx, ensure(ctx->ext_keys, n * sizeof(uint32_t)));
+    if (!d_jmax) HIP_TRY(ctx, ensure(ctx->ext_jmax, n * sizeof(int32_t)));
+    // misc: n_exceed, histogram[256], counts[2], then the gathered keys and grid indices
+    HIP_TRY(ctx, ensure(ctx->ext_misc, (1 + 256 + 2) * sizeof(unsigned long long) + (size_t)top_k * 8));
+    HIP_TRY(ctx, ensure(ctx->ext_list, ((size_t)top_k + cap_eq) * sizeof(unsigned long long)));
+    unsigned long long *misc = (unsigned long long *)ctx->ext_misc.p;
+    HIP_TRY(ctx, hipMemsetAsync(misc, 0, (1 + 256 + 2) * sizeof(unsigned long long), st));
+    ExtArgs ea{};
+    ea.xhat = d_xhat;
+    ea.n = n;
+    ea.stride = row_stride;
+    ea.phi_f32 = ctx->phi_f32[ki].p;
+    ea.amp = (float)std::sqrt(2.0 * E0 / kPi);
+    ea.threshold = (float)threshold;
+    ea.keys = (uint32_t *)ctx->ext_keys.p;
+    ea.umax = d_umax;
+    ea.jmax = d_jmax ? d_jmax : (int *)ctx->ext_jmax.p;
+    ea.n_exceed = misc;
+    HIP_TRY(ctx, launch_grid_max(K, ea, ctx->n_cu, st));
+    unsigned long long n_exc = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&n_exc, misc, sizeof(n_exc), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    *h_n_exceed = n_exc;
+    const int k = (int)std::min<uint64_t>((uint64_t)top_k, n);
+    if (k == 0) return TKDV_OK;
+    // radix select of the k-th largest key, 8 bits per pass from the top
+    uint32_t prefix = 0;
+    unsigned long long need = (unsigned long long)k;  // still to take at or below the prefix
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        HIP_TRY(ctx, hipMemsetAsync(misc + 1, 0, 256 * sizeof(unsigned long long), st));
+        HIP_TRY(ctx, launch_key_hist(ea.keys, n, prefix, shift, misc + 1, ctx->n_cu, st));
+        unsigned long long hist[256];
+        HIP_TRY(ctx, hipMemcpyAsync(hist, misc + 1, sizeof(hist), hipMemcpyDeviceToHost, st));
+        HIP_TRY(ctx, hipStreamSynchronize(st));
+        int b = 255;
+        for (; b > 0; --b) {
+            if (hist[b] >= need) break;
+            need -= hist[b];
+        }
+        prefix = (prefix << 8) | (uint32_t)b;
+    }
+    const uint32_t kth = prefix;  // rows with a larger key: k - need; with this key: >= need
+    unsigned long long *above = (unsigned long long *)ctx->ext_list.p;
+    unsigned long long *equal = above + top_k;
+    HIP_TRY(ctx, launch_key_collect(ea.keys, n, kth, above, (unsigned long long)top_k, equal, cap_eq, misc + 257,
+                                    ctx->n_cu, st));
+    unsigned long long counts[2];
+    HIP_TRY(ctx, hipMemcpyAsync(counts, misc + 257, sizeof(counts), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    if (counts[0] != (unsigned long long)k - need || counts[1] < need)
+        return set_err(ctx, TKDV_E_DEVICE, "tkdv_extremes: inconsistent selection counts");
+    if (counts[1] > cap_eq) return set_err(ctx, TKDV_E_UNSUPPORTED, "tkdv_extremes: more than 65536 tied maxima");
+    std::vector<unsigned long long> ra(counts[0]), re(counts[1]);
+    if (!ra.empty())
+        HIP_TRY(ctx, hipMemcpyAsync(ra.data(), above, ra.size() * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipMemcpyAsync(re.data(), equal, re.size() * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    std::sort(re.begin(), re.end());
+    re.resize(need);
+    ra.insert(ra.end(), re.begin(), re.end());  // the k rows
+    // the selected rows' keys and grid indices, gathered on the device
+    std::vector<uint32_t> keys(ra.size());
+    std::vector<int32_t> jm(ra.size());
+    uint32_t *g_keys = (uint32_t *)(misc + 259);
+    int *g_jm = (int *)(g_keys + top_k);
+    HIP_TRY(ctx, hipMemcpyAsync(above, ra.data(), ra.size() * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(ctx, launch_ext_gather(above, (int)ra.size(), ea.keys, ea.jmax, g_keys, g_jm, st));
+    HIP_TRY(ctx, hipMemcpyAsync(keys.data(), g_keys, keys.size() * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipMemcpyAsync(jm.data(), g_jm, jm.size() * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    std::vector<size_t> order(ra.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+        return keys[x] != keys[y] ? keys[x] > keys[y] : ra[x] < ra[y];
+    });
+    for (int i = 0; i < k; ++i) {
+        const size_t o = order[i];
+        const uint32_t kk = keys[o];
+        const uint32_t bits = (kk & 0x80000000u) ? (kk & 0x7FFFFFFFu) : ~kk;
+        float f;
+        std::memcpy(&f, &bits, 4);
+        h_rows[i] = ra[o];
+        h_umax[i] = f;
+        h_jmax[i] = jm[o];
+    }
     return TKDV_OK;
 }
 

@@ -203,7 +203,7 @@ static uint64_t splitmix64(uint64_t &s)
     return z ^ (z >> 31);
 }
 
-int plan_point_host(const tkdv_point *pt, int proposal, int n_random, tkdv_plan *out)
+int plan_base_host(const tkdv_point *pt, int proposal, tkdv_plan *out)
 {
     if (!pt || !out) return TKDV_E_ARG;
     const int K = pt->K;
@@ -244,6 +244,16 @@ int plan_point_host(const tkdv_point *pt, int proposal, int n_random, tkdv_plan 
         }
         return TKDV_OK;
     }
+    out->M_source = -1;
+    return TKDV_OK;
+}
+
+int plan_point_host(const tkdv_point *pt, int proposal, int n_random, tkdv_plan *out)
+{
+    const int st = plan_base_host(pt, proposal, out);
+    if (st != TKDV_OK || out->M_source == 0) return st;
+    const int K = pt->K;
+    const double alpha = out->alpha_star;
     Objective obj{K, pt->E0, pt->beta_p, pt->c32, alpha, proposal};
     std::vector<std::vector<double>> starts;
     {

@@ -1,0 +1,250 @@
+// Multi-start search for the rejection constant M = sup over the sphere of
+// f/g (Sec. IV.A; step 1 of the algorithm of Sec. IV.B), one wavefront per
+// (point, start), in FP64.
+//
+// Each wave maximises phi(x^) = log f(x^) - log g(x^) (the unnormalised ratio
+// of tkdv_plan_point) by L-BFGS ascent on the unit sphere: retraction by
+// normalisation, the tangent gradient, Armijo backtracking, 8 curvature pairs
+// kept in registers.  The value and the gradient come from the N = 4K grid:
+//   u~_j = sum_k (-1)^k (x^_k cos(2 pi k j/N) + x^_{K+k} sin(2 pi k j/N)),
+//   H3 = (pi/(3N)) amp^3 sum_j u~_j^3 (exact for N >= 3K + 1),
+//   d/dx^_m sum_j u~_j^3 = 3 sum_j u~_j^2 Phi_mj,
+// with one table of cos(2 pi r/N) in LDS (sin by a quarter-period offset).
+// Lane l holds coordinates l and l + 64 of x^ and the gradient, and grid
+// points l + 64 r.  Every branch taken on a wave-reduced quantity goes
+// through readfirstlane, so all lanes of a wave follow one path.
+#include "tkdv_device.h"
+#include "tkdv_plan_gpu.h"
+
+namespace tkdv {
+namespace {
+
+constexpr double kPiP = 3.14159265358979323846;
+
+// Butterfly sum: every lane ends with the same bits (each stage adds the same
+// two partial sums in both lanes of a pair).
+__device__ __forceinline__ double wsum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ bool uniform(bool c) { return __builtin_amdgcn_readfirstlane((int)c) != 0; }
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// phi at the unit vector (x0, x1) and its tangent gradient (g0, g1).
+__device__ double plan_eval(const PlanPoint &P, double *xs, double *us, const double *ct, int lane, double x0,
+                            double x1, double &g0, double &g1)
+{
+    const int K = P.K, N = P.N, n2 = 2 * K, q = N / 4;
+    const int m0 = lane, m1 = lane + 64;
+    const bool v0 = m0 < n2, v1 = m1 < n2;
+    if (v0) xs[m0] = x0;
+    if (v1) xs[m1] = x1;
+    wave_sync_lds();
+    const int k0 = m0 % K + 1, k1 = m1 % K + 1;
+    const double t = wsum((v0 ? (double)k0 * k0 * x0 * x0 : 0.0) + (v1 ? (double)k1 * k1 * x1 * x1 : 0.0));
+    double s3 = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int j = lane + 64 * r;
+        if (j < N) {
+            double u = 0.0;
+            int ic = 0;
+            for (int k = 1; k <= K; ++k) {
+                ic += j;
+                if (ic >= N) ic -= N;
+                int is = ic - q;
+                if (is < 0) is += N;
+                const double term = xs[k - 1] * ct[ic] + xs[K + k - 1] * ct[is];
+                u += (k & 1) ? -term : term;
+            }
+            us[j] = u * u;
+            s3 += u * u * u;
+        }
+    }
+    const double S3 = wsum(s3);
+    wave_sync_lds();
+    auto dh = [&](int m) {
+        const int k = m % K + 1;
+        const int off = m >= K ? q : 0;
+        double acc = 0.0;
+        int ic = 0;
+        for (int j = 0; j < N; ++j) {
+            int idx = ic - off;
+            if (idx < 0) idx += N;
+            acc += us[j] * ct[idx];
+            ic += k;
+            if (ic >= N) ic -= N;
+        }
+        return (k & 1) ? -acc : acc;
+    };
+    const double d0 = v0 ? dh(m0) : 0.0, d1 = v1 ? dh(m1) : 0.0;
+    double val = P.dt0 * t + P.cH * (kPiP / (3.0 * N)) * P.amp3 * S3;
+    double dt = P.dt0;
+    if (P.sigma) {
+        val += K * log1p(P.a * t);
+        dt += K * P.a / (1.0 + P.a * t);
+    }
+    const double cg = P.cH * kPiP * P.amp3 / N;
+    g0 = v0 ? dt * 2.0 * k0 * k0 * x0 + cg * d0 : 0.0;
+    g1 = v1 ? dt * 2.0 * k1 * k1 * x1 + cg * d1 : 0.0;
+    const double gx = wsum(g0 * x0 + g1 * x1);
+    g0 -= gx * x0;
+    g1 -= gx * x1;
+    wave_sync_lds();  // the next evaluation overwrites xs and us
+    return val;
+}
+
+__global__ void __launch_bounds__(64 * kPlanWaves) k_plan_search(PlanArgs a)
+{
+    __shared__ double xs_all[kPlanWaves][128];
+    __shared__ double us_all[kPlanWaves][256];
+    __shared__ double ct_all[kPlanWaves][256];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int item = blockIdx.x * kPlanWaves + w;
+    if (item >= a.n_items) return;  // whole wave; no workgroup barrier follows
+    const int p = item / a.n_starts, s = item % a.n_starts;
+    const PlanPoint P = a.pts[p];
+    double *xs = xs_all[w], *us = us_all[w], *ct = ct_all[w];
+    const int K = P.K, N = P.N, n2 = 2 * K;
+    for (int r = lane; r < N; r += 64) ct[r] = cos(2.0 * kPiP * r / N);
+    const int m0 = lane, m1 = lane + 64;
+    double x0 = 0.0, x1 = 0.0;
+    if (s == 0) {  // zero-mean Dirichlet kernel: equal cos coefficients
+        x0 = m0 < K ? 1.0 : 0.0;
+        x1 = m1 < K ? 1.0 : 0.0;
+    } else if (s == 1) {  // all energy in mode 1
+        x0 = m0 == 0 ? 1.0 : 0.0;
+    } else {  // independent normal coordinates, Box-Muller pairs of Philox words
+        auto normal = [&](int m) {
+            const uint4 wd = philox4x32_10((uint32_t)s, P.point_id, (uint32_t)(m >> 1), 0x504C414Eu, a.seed_lo,
+                                           a.seed_hi);
+            const double u1 = ((double)wd.x + 0.5) * 0x1p-32, u2 = ((double)wd.y + 0.5) * 0x1p-32;
+            const double r = sqrt(-2.0 * log(u1)), th = 2.0 * kPiP * u2;
+            return (m & 1) ? r * sin(th) : r * cos(th);
+        };
+        x0 = m0 < n2 ? normal(m0) : 0.0;
+        x1 = m1 < n2 ? normal(m1) : 0.0;
+    }
+    {
+        const double r = sqrt(wsum(x0 * x0 + x1 * x1));
+        x0 /= r;
+        x1 /= r;
+    }
+    wave_sync_lds();  // cos table
+    double g0, g1;
+    double f = plan_eval(P, xs, us, ct, lane, x0, x1, g0, g1);
+    int evals = 1;
+    // curvature pairs, newest first: s = x_new - x_old, y = g_old - g_new
+    double S0[kPlanMem], S1[kPlanMem], Y0[kPlanMem], Y1[kPlanMem], RHO[kPlanMem];
+#pragma unroll
+    for (int i = 0; i < kPlanMem; ++i) S0[i] = S1[i] = Y0[i] = Y1[i] = RHO[i] = 0.0;
+    int mc = 0;
+    double gamma = 1.0;
+    for (int it = 0; it < kPlanMaxIter; ++it) {
+        const double gn = sqrt(wsum(g0 * g0 + g1 * g1));
+        if (uniform(!(gn > 1e-13 * (1.0 + fabs(f))))) break;
+        // two-loop recursion on the ascent problem: d = H g
+        double q0 = g0, q1 = g1, al[kPlanMem];
+#pragma unroll
+        for (int i = 0; i < kPlanMem; ++i) {
+            al[i] = 0.0;
+            if (i < mc) {
+                al[i] = RHO[i] * wsum(S0[i] * q0 + S1[i] * q1);
+                q0 -= al[i] * Y0[i];
+                q1 -= al[i] * Y1[i];
+            }
+        }
+        q0 *= gamma;
+        q1 *= gamma;
+#pragma unroll
+        for (int i = kPlanMem - 1; i >= 0; --i) {
+            if (i < mc) {
+                const double b = RHO[i] * wsum(Y0[i] * q0 + Y1[i] * q1);
+                q0 += S0[i] * (al[i] - b);
+                q1 += S1[i] * (al[i] - b);
+            }
+        }
+        double d0 = q0, d1 = q1;
+        double slope = wsum(d0 * g0 + d1 * g1);
+        double step = 1.0;
+        if (uniform(!(slope > 0.0)) || mc == 0) {  // steepest ascent, at most half a radian
+            d0 = g0;
+            d1 = g1;
+            slope = gn * gn;
+            mc = 0;
+            gamma = 1.0;
+            step = fmin(1.0, 0.5 / gn);
+        }
+        double f2 = f, x20 = x0, x21 = x1, g20 = g0, g21 = g1;
+        bool ok = false;
+        for (int ls = 0; ls < kPlanMaxBacktrack; ++ls) {
+            x20 = x0 + step * d0;
+            x21 = x1 + step * d1;
+            const double r = sqrt(wsum(x20 * x20 + x21 * x21));
+            x20 /= r;
+            x21 /= r;
+            f2 = plan_eval(P, xs, us, ct, lane, x20, x21, g20, g21);
+            ++evals;
+            if (uniform(f2 >= f + 1e-4 * step * slope)) {
+                ok = true;
+                break;
+            }
+            step *= 0.5;
+        }
+        if (!ok) break;
+        const double sx0 = x20 - x0, sx1 = x21 - x1, yv0 = g0 - g20, yv1 = g1 - g21;
+        const double sy = wsum(sx0 * yv0 + sx1 * yv1), yy = wsum(yv0 * yv0 + yv1 * yv1);
+        const double gain = f2 - f;
+        x0 = x20;
+        x1 = x21;
+        g0 = g20;
+        g1 = g21;
+        f = f2;
+        if (uniform(sy > 1e-300 && yy > 0.0)) {
+#pragma unroll
+            for (int i = kPlanMem - 1; i > 0; --i) {
+                S0[i] = S0[i - 1];
+                S1[i] = S1[i - 1];
+                Y0[i] = Y0[i - 1];
+                Y1[i] = Y1[i - 1];
+                RHO[i] = RHO[i - 1];
+            }
+            S0[0] = sx0;
+            S1[0] = sx1;
+            Y0[0] = yv0;
+            Y1[0] = yv1;
+            RHO[0] = 1.0 / sy;
+            gamma = sy / yy;
+            mc = mc < kPlanMem ? mc + 1 : kPlanMem;
+        }
+        if (uniform(gain < 1e-16 * (1.0 + fabs(f)) && it > 5)) break;
+    }
+    double *xo = a.xbest + (size_t)item * 128;
+    xo[m0] = m0 < n2 ? x0 : 0.0;
+    xo[m1] = m1 < n2 ? x1 : 0.0;
+    if (lane == 0) {
+        a.val[item] = f;
+        a.evals[item] = evals;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_plan_search(const PlanArgs &a, hipStream_t st)
+{
+    if (a.n_items <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)((a.n_items + kPlanWaves - 1) / kPlanWaves);
+    hipLaunchKernelGGL(k_plan_search, dim3(grid), dim3(64 * kPlanWaves), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace tkdv

@@ -7,6 +7,7 @@ Importing this module fails loudly when the library has not been built.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 from dataclasses import dataclass
 
@@ -39,6 +40,9 @@ class TkdvError(RuntimeError):
 class Point(C.Structure):
     _fields_ = [("K", C.c_int32), ("point_id", C.c_uint32), ("E0", C.c_double),
                 ("beta_p", C.c_double), ("c32", C.c_double), ("seed", C.c_uint64)]
+
+
+PLAN_SEARCH_ALWAYS = 1  # tkdv_plan_batch: search also where C3/C2 = 0
 
 
 class Plan(C.Structure):
@@ -113,7 +117,7 @@ EXPORTS = ["tkdv_create", "tkdv_destroy", "tkdv_plan_point", "tkdv_sample", "tkd
            "tkdv_learner_add_rows_host", "tkdv_learner_train", "tkdv_learner_gradients",
            "tkdv_learner_mixture", "tkdv_learner_n_weights", "tkdv_learner_get_weights",
            "tkdv_learner_set_weights", "tkdv_sample_sweep", "tkdv_set_launch_cfg", "tkdv_get_launch_cfg",
-           "tkdv_autotune"]
+           "tkdv_autotune", "tkdv_plan_batch", "tkdv_extremes"]
 
 _P = C.c_void_p
 lib.tkdv_create.argtypes = [C.c_int, C.POINTER(_P)]
@@ -158,6 +162,11 @@ lib.tkdv_sample_sweep.argtypes = [_P, C.c_int32, C.POINTER(Point), C.POINTER(Pla
 lib.tkdv_set_launch_cfg.argtypes = [_P, C.c_int32, C.c_int, C.POINTER(LaunchCfg)]
 lib.tkdv_get_launch_cfg.argtypes = [_P, C.c_int32, C.c_int, C.POINTER(LaunchCfg)]
 lib.tkdv_autotune.argtypes = [_P, C.c_int32, C.c_int, C.c_char_p, C.POINTER(LaunchCfg)]
+lib.tkdv_extremes.argtypes = [_P, C.c_int32, C.c_double, _P, C.c_uint64, C.c_uint64, C.c_int32, C.c_double,
+                              C.POINTER(C.c_uint64), C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                              C.POINTER(C.c_uint64), _P, _P, _P]
+lib.tkdv_plan_batch.argtypes = [_P, C.c_int32, C.POINTER(Point), C.c_int, C.c_int32, C.c_uint64, C.c_int32,
+                                C.POINTER(Plan), C.POINTER(C.c_double), _P]
 lib.tkdv_status_str.argtypes = [C.c_int]
 lib.tkdv_status_str.restype = C.c_char_p
 lib.tkdv_last_error.argtypes = [_P]
@@ -400,6 +409,49 @@ class Context:
         _check(lib.tkdv_autotune(self._h, int(K), int(precision),
                                  cache_path.encode() if cache_path else None, C.byref(c)), self._h)
         return c
+
+    def plan_batch(self, points: list, proposal: int = SIGMA, n_starts: int = 16, seed: int = 0,
+                   search_always: bool = False, stream=None) -> tuple[list, np.ndarray]:
+        """Plans of many points with log M searched on the GPU (tkdv_plan_batch):
+        (plans, maximisers [n, 2K_max])."""
+        n = len(points)
+        pts = (Point * max(n, 1))(*points)
+        plans = (Plan * max(n, 1))()
+        xb = np.zeros((max(n, 1), 2 * KMAX))
+        _check(lib.tkdv_plan_batch(self._h, n, pts, int(proposal), int(n_starts), int(seed),
+                                   PLAN_SEARCH_ALWAYS if search_always else 0, plans,
+                                   xb.ctypes.data_as(C.POINTER(C.c_double)),
+                                   _stream(stream) if n else None), self._h)
+        return [plans[i] for i in range(n)], xb[:n]
+
+    def extremes(self, xhat, K: int, E0: float = 1.0, top_k: int = 10, threshold: float | None = None,
+                 per_row: bool = False, stream=None) -> dict:
+        """Largest surface displacements among rows x^ (tkdv_extremes): the top_k rows
+        by max_j u(xi_j) (descending, ties by lower row), their maxima and grid
+        indices, and the number of rows whose maximum exceeds `threshold`
+        (default 4 sigma = 4 sqrt(E0/pi)).  xhat: float32 device tensor (n, >= 2K)
+        with unit column stride."""
+        import torch
+        assert xhat.dtype == torch.float32 and xhat.dim() == 2 and (xhat.shape[0] == 0 or xhat.stride(1) == 1)
+        n = int(xhat.shape[0])
+        stride = int(xhat.stride(0)) if n else 2 * K
+        thr = 4.0 * math.sqrt(E0 / math.pi) if threshold is None else float(threshold)
+        kk = max(int(top_k), 1)
+        rows = (C.c_uint64 * kk)()
+        um = (C.c_double * kk)()
+        jm = (C.c_int32 * kk)()
+        nex = C.c_uint64()
+        du = dj = None
+        if per_row:
+            du = torch.empty((n,), dtype=torch.float32, device=xhat.device)
+            dj = torch.empty((n,), dtype=torch.int32, device=xhat.device)
+        _check(lib.tkdv_extremes(self._h, int(K), float(E0), _ptr(xhat) if n else None, n, stride, int(top_k), thr,
+                                 rows, um, jm, C.byref(nex), _ptr(du) if n else None, _ptr(dj) if n else None,
+                                 _stream(stream)), self._h)
+        k = min(int(top_k), n)
+        return {"rows": np.array(rows[:k], dtype=np.uint64), "umax": np.array(um[:k]),
+                "jmax": np.array(jm[:k], dtype=np.int64), "n_exceed": int(nex.value), "threshold": thr,
+                "umax_rows": du, "jmax_rows": dj}
 
     def synthesize(self, xhat, precision: int = BF16X3, s3=None, stream=None):
         """s3[r] = sum_j u~_j^3 on the N = 4K grid for rows x^ (n, 2K) float32 on the device."""

@@ -67,6 +67,15 @@ def test_plan_argument_errors():
     assert e.value.status == -1
 
 
+def test_plan_batch_without_context_is_an_argument_error():
+    import ctypes as C
+    from paper_2411_16952_amd import tkdv as T
+    pts = (T.Point * 1)(T.make_point(8, 1.0, 40.0, 20.0))
+    plans = (T.Plan * 1)()
+    st = T.lib.tkdv_plan_batch(None, 1, pts, T.SIGMA, 4, 0, 0, plans, None, None)
+    assert st == -1
+
+
 def test_decision_window_orders_precisions():
     """The window bounds the fast path's error: it widens from FP32 to BF16x3
     to BF16 and grows with beta' C3/C2."""

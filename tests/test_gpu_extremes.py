@@ -1,0 +1,146 @@
+"""The extreme-wave search on the GPU (tkdv_extremes) against the oracle.
+
+* Per row: the grid maximum within the FP32 product error of the oracle's
+  FP64 value, and the same grid index except where the two largest grid
+  values are closer than that error.
+* The top k: every selected row is, in the oracle's values, within the error
+  of the k-th largest; the order is descending with ties by lower row.
+* The exceedance count equals the oracle's except for rows within the error
+  of the threshold.
+* The Dirichlet kernel planted among random rows is the first, with
+  u_max = sqrt(2 K E0/pi) at xi = 0; duplicated rows keep the lower row first.
+* Rows from the sampler's own output (row stride 2 KMAX), ragged sizes, empty
+  input, top_k beyond n, and argument errors.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = 3e-5  # FP32 products of 2K terms, |u| <= sqrt(2 K E0/pi)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2411_16952_amd import tkdv
+    return tkdv
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    c = T.Context(0)
+    yield c
+    c.close()
+
+
+def _rows(K, n, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((n, 2 * K)) / np.sqrt(1.0 + np.tile(np.arange(K), 2))  # decaying spectrum
+    return x / np.linalg.norm(x, axis=1, keepdims=True)
+
+
+def _check(res, ref, top_k, thr, x64, E0, N, label):
+    um_g = res["umax_rows"].cpu().numpy().astype(np.float64)
+    jm_g = res["jmax_rows"].cpu().numpy()
+    scale = math.sqrt(2 * E0 / math.pi)
+    tol = TOL * scale * math.sqrt(x64.shape[1] / 2)
+    err = np.abs(um_g - ref["umax"])
+    say(f"{label}: n={len(um_g)} max |du_max| {err.max():.2e} (tol {tol:.1e}); exceed gpu {res['n_exceed']} "
+        f"oracle {ref['n_exceed']}")
+    assert err.max() <= tol
+    bad = np.nonzero(jm_g != ref["jmax"])[0]
+    for r in bad:  # only near-ties of the two largest grid values
+        u = oracle.grid(x64[r], E0, N)
+        assert abs(u[jm_g[r]] - u[ref["jmax"][r]]) <= 2 * tol, f"row {r}: grid index {jm_g[r]} vs {ref['jmax'][r]}"
+    near = np.sum(np.abs(ref["umax"] - thr) <= tol)
+    assert abs(res["n_exceed"] - ref["n_exceed"]) <= near
+    k = min(top_k, len(um_g))
+    rows = res["rows"].astype(np.int64)
+    assert len(rows) == k and len(set(rows.tolist())) == k
+    if k:
+        kth = np.sort(ref["umax"])[::-1][k - 1]
+        assert np.all(ref["umax"][rows] >= kth - 2 * tol)
+        # descending in the GPU's values, ties by lower row; the values are the per-row ones
+        assert np.array_equal(res["umax"], um_g[rows].astype(np.float32).astype(np.float64))
+        for i in range(k - 1):
+            a, b = res["umax"][i], res["umax"][i + 1]
+            assert a > b or (a == b and rows[i] < rows[i + 1])
+        assert np.array_equal(res["jmax"], jm_g[rows])
+
+
+@pytest.mark.parametrize("K,n,E0", [(8, 100_003, 1.0), (16, 40_001, 2.0), (32, 20_011, 1.0), (64, 5_003, 0.5)])
+def test_random_rows_against_oracle(T, ctx, K, n, E0):
+    import torch
+    x64 = _rows(K, n, seed=K)
+    d = x64.astype(np.float32)
+    x = torch.from_numpy(d).cuda()
+    thr = 2.0 * math.sqrt(E0 / math.pi)
+    res = ctx.extremes(x, K, E0, top_k=64, threshold=thr, per_row=True)
+    ref = oracle.extremes(d.astype(np.float64), E0, 4 * K, 64, thr)
+    _check(res, ref, 64, thr, d.astype(np.float64), E0, 4 * K, f"K={K}")
+
+
+def test_sampler_rows_and_planted_extremes(T, ctx):
+    import torch
+    K, E0 = 16, 1.0
+    # two of the paper's individual-sample cases (K = 16, beta' = 40, C3/C2 = 75 and 0)
+    pts = [T.make_point(K, E0, 40.0, 75.0, seed=1, point_id=0), T.make_point(K, E0, 40.0, 0.0, seed=1, point_id=1)]
+    plans = [T.plan_point(p, T.SIGMA) for p in pts]
+    out, xall, _ = ctx.sample_batch(pts, [8_000_000, 4_000_000], plans=plans, capacity=[20_000, 20_000])
+    for o, p in zip(out, pts):
+        rows = o["xhat"]                      # a view with row stride 2 KMAX
+        assert rows.stride(0) == 2 * T.KMAX and rows.shape[0] > 500
+        x64 = rows.cpu().numpy().astype(np.float64)
+        thr = 4.0 * math.sqrt(E0 / math.pi)
+        res = ctx.extremes(rows, K, E0, top_k=20, per_row=True)
+        ref = oracle.extremes(x64, E0, 4 * K, 20, thr)
+        _check(res, ref, 20, thr, x64, E0, 4 * K, f"sampler C3/C2={p.c32}")
+        say(f"C3/C2={p.c32}: largest u {res['umax'][0]:.4f} (4 sigma {thr:.4f}, cap "
+            f"{math.sqrt(2 * K * E0 / math.pi):.4f}), {res['n_exceed']} of {rows.shape[0]} above 4 sigma")
+    # the Dirichlet kernel and a duplicated row planted in random rows
+    x64 = _rows(K, 3000, seed=9)
+    x64[1234] = 0.0
+    x64[1234, :K] = 1.0 / math.sqrt(K)
+    x64[77] = x64[2500]
+    x = torch.from_numpy(x64.astype(np.float32)).cuda()
+    res = ctx.extremes(x, K, E0, top_k=3000, per_row=True)
+    assert res["rows"][0] == 1234 and res["jmax"][0] == 2 * K
+    assert abs(res["umax"][0] - math.sqrt(2 * K * E0 / math.pi)) < 1e-5
+    order = res["rows"].tolist()
+    assert order.index(77) == order.index(2500) - 1
+
+
+def test_edges_and_errors(T, ctx):
+    import torch
+    K = 8
+    empty = torch.empty((0, 2 * K), dtype=torch.float32, device="cuda")
+    r = ctx.extremes(empty, K, top_k=5)
+    assert r["n_exceed"] == 0 and len(r["rows"]) == 0
+    x = torch.from_numpy(_rows(K, 7, 1).astype(np.float32)).cuda()
+    r = ctx.extremes(x, K, top_k=50)               # top_k beyond n
+    assert sorted(r["rows"].tolist()) == list(range(7))
+    r0 = ctx.extremes(x, K, top_k=0, threshold=-10.0)
+    assert len(r0["rows"]) == 0 and r0["n_exceed"] == 7
+    with pytest.raises(T.TkdvError):
+        ctx.extremes(torch.zeros((4, 24), dtype=torch.float32, device="cuda"), 12)          # K
+    with pytest.raises(T.TkdvError):
+        ctx.extremes(x, K, top_k=4097)                                                     # top_k
+    big = torch.zeros((4, 2 * K + 1), dtype=torch.float32, device="cuda")
+    with pytest.raises(T.TkdvError):
+        ctx.extremes(big, K)                                                               # stride 17
+    wide = torch.zeros((4, 2 * K + 4), dtype=torch.float32, device="cuda")
+    with pytest.raises(T.TkdvError):
+        ctx.extremes(wide[:, 1:], K)                                                       # unaligned rows

@@ -1,0 +1,164 @@
+"""The rejection-constant search on the GPU (tkdv_plan_batch) against the oracle.
+
+* C3/C2 = 0, searched anyway: log M equals the closed form (the ratio is a
+  function of t alone, maximised at t* clamped to [1, K^2]) for both
+  proposals and K from 1 to 64;
+* C3/C2 != 0: log M is at least the oracle's Nelder-Mead maximum (to 1e-10),
+  the returned maximiser gives the reported value under the oracle's FP64
+  objective (triad double sum for H3) to 1e-10, and it is a local maximum
+  of that objective (no small rotation in a random tangent direction gains);
+* K = 2 (the oracle's maximum there is pinned to a 2-D brute-force
+  quadrature) and odd K; the oracle's maxima are stored in
+  tests/golden/plan_log_M.txt by tests/golden/make_plan_log_M.py;
+* alpha*, s_k^2 and log_norm_g equal the host plan's bit for bit;
+* a point's plan does not depend on the other points of the call;
+* a sampler run with the GPU plan meets no M violation;
+* argument errors.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import plan as OP
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2411_16952_amd import tkdv
+    return tkdv
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    c = T.Context(0)
+    yield c
+    c.close()
+
+
+LINEAR = [(1, 0.5), (2, 3.0), (5, 20.0), (8, 40.0), (16, 20.0), (32, 40.0), (32, 60.0), (64, 40.0)]
+
+
+@pytest.mark.parametrize("proposal", [0, 1])
+def test_linear_case_reaches_closed_form(T, ctx, proposal):
+    pts = [T.make_point(K, 1.0, bp, 0.0, seed=3, point_id=i) for i, (K, bp) in enumerate(LINEAR)]
+    plans, _ = ctx.plan_batch(pts, proposal=proposal, n_starts=6, seed=11, search_always=True)
+    for (K, bp), pl in zip(LINEAR, plans):
+        a = OP.alpha_star(K, bp) if proposal == 1 else 1.0
+        closed = OP.log_M_linear(K, bp, a, proposal)
+        say(f"K={K} beta'={bp} proposal={proposal}: GPU {pl.log_M:.15f} closed {closed:.15f} "
+            f"evals {pl.n_optimiser_evals}")
+        assert pl.M_source == 2
+        assert abs(pl.log_M - closed) < 1e-10 * (1.0 + abs(closed))
+
+
+def _load_refs():
+    """(K, E0, beta', C3/C2, proposal) -> the oracle's log M, written by
+    tests/golden/make_plan_log_M.py (the oracle's Nelder-Mead takes minutes at
+    K = 64)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "plan_log_M.txt")
+    refs = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        K, E0, bp, c, prop, lm = line.split()
+        refs[(int(K), float(E0), float(bp), float(c), int(prop))] = float(lm)
+    return refs
+
+
+REFS = _load_refs()
+NONLINEAR = list(REFS)
+
+
+def _oracle_value(K, E0, bp, c, prop, alpha, x):
+    return oracle.log_ratio(np.asarray(x, dtype=np.float64), E0, bp, c, alpha, prop, normalise_input=True)
+
+
+def test_nonlinear_points_against_oracle(T, ctx):
+    pts = [T.make_point(K, E0, bp, c, seed=0, point_id=i) for i, (K, E0, bp, c, _) in enumerate(NONLINEAR)]
+    rng = np.random.default_rng(7)
+    for prop in (0, 1):
+        idx = [i for i, s in enumerate(NONLINEAR) if s[4] == prop]
+        plans, xb = ctx.plan_batch([pts[i] for i in idx], proposal=prop, n_starts=12, seed=5)
+        for j, i in enumerate(idx):
+            K, E0, bp, c, _ = NONLINEAR[i]
+            pl, x = plans[j], xb[j, :2 * K]
+            a = OP.alpha_star(K, bp) if prop == 1 else 1.0
+            ref = REFS[NONLINEAR[i]]
+            val = _oracle_value(K, E0, bp, c, prop, a, x)
+            say(f"K={K} E0={E0} beta'={bp} c={c} proposal={prop}: GPU {pl.log_M:.13f} oracle NM {ref:.13f} "
+                f"oracle at GPU argmax {val:.13f} evals {pl.n_optimiser_evals}")
+            assert pl.M_source == 2
+            assert abs(np.linalg.norm(x) - 1.0) < 1e-12
+            assert abs(val - pl.log_M) < 1e-10 * (1.0 + abs(val))
+            assert pl.log_M >= ref - 1e-10 * (1.0 + abs(ref))
+            # a local maximum of the oracle's objective
+            for _ in range(8):
+                v = rng.standard_normal(2 * K)
+                v -= (v @ x) * x
+                v /= np.linalg.norm(v)
+                for h in (1e-3, 1e-5):
+                    y = x + h * v
+                    assert _oracle_value(K, E0, bp, c, prop, a, y / np.linalg.norm(y)) <= val + 1e-12
+
+
+def test_plan_fields_equal_host_plan(T, ctx):
+    pts = [T.make_point(K, 1.0, bp, c, point_id=i) for i, (K, bp, c) in
+           enumerate([(8, 40.0, 20.0), (32, 40.0, 0.0), (64, 20.0, 50.0)])]
+    plans, _ = ctx.plan_batch(pts, proposal=T.SIGMA, n_starts=4, seed=1)
+    for p, pl in zip(pts, plans):
+        h = T.plan_point(p, T.SIGMA)
+        assert pl.alpha_star == h.alpha_star and pl.log_norm_g == h.log_norm_g and pl.N == h.N
+        assert list(pl.sigma2) == list(h.sigma2)
+        if p.c32 == 0.0:
+            assert pl.M_source == 0 and pl.log_M == h.log_M
+        else:
+            assert abs(pl.log_M - h.log_M) < 1e-9 * (1.0 + abs(h.log_M))
+
+
+def test_plan_independent_of_the_batch(T, ctx):
+    specs = [(8, 40.0, 20.0), (16, 40.0, 60.0), (32, 0.0, 0.0), (32, 20.0, 300.0), (64, 40.0, 150.0)]
+    pts = [T.make_point(K, 1.0, bp, c, point_id=100 + i) for i, (K, bp, c) in enumerate(specs)]
+    plans, xb = ctx.plan_batch(pts, n_starts=8, seed=9)
+    for i, p in enumerate(pts):
+        one, x1 = ctx.plan_batch([p], n_starts=8, seed=9)
+        assert one[0].log_M == plans[i].log_M
+        assert np.array_equal(x1[0], xb[i])
+    again, xb2 = ctx.plan_batch(pts, n_starts=8, seed=9)
+    assert [q.log_M for q in again] == [q.log_M for q in plans] and np.array_equal(xb, xb2)
+
+
+def test_sampling_with_gpu_plan_has_no_violation(T, ctx):
+    pts = [T.make_point(32, 1.0, 40.0, 75.0, seed=2, point_id=0), T.make_point(16, 1.0, 40.0, 60.0, seed=2, point_id=1)]
+    plans, _ = ctx.plan_batch(pts, n_starts=16, seed=3)
+    out, _, _ = ctx.sample_batch(pts, [20_000_000] * 2, plans=plans, capacity=[0, 0])
+    for o in out:
+        say(f"accepted {o['n_accepted']} of {o['n_proposed']}, violations {o['n_M_violations']}, "
+            f"max log a {o['max_log_a']:.3e}")
+        assert o["n_M_violations"] == 0 and o["n_accepted"] > 0
+
+
+def test_plan_batch_argument_errors(T, ctx):
+    p = T.make_point(8, 1.0, 40.0, 20.0)
+    for kw in (dict(n_starts=0), dict(n_starts=257), dict(proposal=2)):
+        with pytest.raises(T.TkdvError):
+            ctx.plan_batch([p], **kw)
+    with pytest.raises(T.TkdvError):
+        ctx.plan_batch([T.make_point(0, 1.0, 40.0, 20.0)])
+    with pytest.raises(T.TkdvError) as e:
+        ctx.plan_batch([p, T.make_point(8, 1.0, 1000.0, 20.0)])   # no alpha root at K=8
+    assert "point 1" in str(e.value)
+    plans, xb = ctx.plan_batch([])
+    assert plans == [] and xb.shape == (0, 2 * T.KMAX)
