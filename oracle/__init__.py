@@ -44,6 +44,7 @@ from .core import (  # noqa: F401
     mix_sample,
     mix_proposal,
     extremes,
+    sir,
     mix_eps,
     mix_threshold,
     stats_of,

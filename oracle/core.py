@@ -151,6 +151,8 @@ lib.orc_sample_until.restype = C.c_uint64
 lib.orc_stats_of.argtypes = [C.c_int, C.c_int, _D, _PD, C.c_uint64, C.POINTER(_Stats)]
 lib.orc_eval_batch.argtypes = [C.POINTER(_Point), C.c_uint64, C.c_uint64, _PD, _PD, _PD, _PD, _PD, _PD, C.c_int]
 lib.orc_shift.argtypes = [C.c_int, _D, _PD, _PD]
+lib.orc_sir.argtypes = [C.POINTER(_Point), C.c_uint64, C.c_uint64, C.c_uint64, _D, _PD,
+                        C.POINTER(C.c_uint64), _PD, C.c_int]
 lib.orc_mix_log_q.argtypes = [C.POINTER(_Point), C.POINTER(_Mixture), _PD, _PD, _PD]
 lib.orc_mix_draw.argtypes = [C.POINTER(_Point), C.POINTER(_Mixture), C.c_uint64, _PD, _PD]
 lib.orc_mix_draw.restype = C.c_int
@@ -321,6 +323,24 @@ def eval_batch(K, E0, beta_p, c32, proposal_kind, alpha_star, log_M, seed, point
     lib.orc_eval_batch(C.byref(p), i0, n, g("H2"), g("H3"), g("S3"), g("S3abs"), g("log_a"), g("log_u"),
                        nthreads)
     return out
+
+
+def sir(K, E0, beta_p, c32, proposal_kind, alpha_star, log_M, seed, point_id, n, m, u0, i0=0, N=None,
+        nthreads=0) -> dict:
+    """Sampling-importance resampling over proposal indices i0..i0+n-1 with the
+    paper's proposal (orc_sir): weights w_i = f/(M g), their sums, the
+    self-normalised grid moments and m systematic draws with offset u0."""
+    p = _point(K, N or 4 * K, proposal_kind, point_id, E0, beta_p, c32, alpha_star, log_M, seed)
+    w = np.zeros(max(n, 1))
+    idx = np.zeros(max(m, 1), dtype=np.uint64)
+    sums = np.zeros(8)
+    lib.orc_sir(C.byref(p), i0, n, m, float(u0), _dp(w), idx.ctypes.data_as(C.POINTER(C.c_uint64)), _dp(sums),
+                nthreads)
+    W, W2 = sums[0], sums[1]
+    m2 = sums[4]
+    return {"weights": w[:n], "index": idx[:m], "W": W, "W2": W2, "ess": W * W / W2 if W2 > 0 else 0.0,
+            "max_w": sums[2], "moments": sums[3:7].copy(), "n_over_one": int(sums[7]),
+            "skewness": sums[5] / m2 ** 1.5 if m2 > 0 else 0.0, "kurtosis": sums[6] / m2 ** 2 if m2 > 0 else 0.0}
 
 
 def shift(x, phi: float) -> np.ndarray:

@@ -756,3 +756,81 @@ uint64_t orc_mix_sample(const orc_point *p, const orc_mixture *m, uint64_t i0, u
     }
     return nacc;
 }
+
+/*
+ * Sampling-importance resampling with the same proposals, the alternative to
+ * the rejection step that the paper names (Sec. I, Sec. IV.B).  For proposal
+ * indices [i0, i0+n) in increasing order:
+ *   w_i = exp(log a_i) = f/(M g) at proposal i (the importance weight up to
+ *         the constant 1/M, the acceptance probability of the rejection step);
+ *   W = sum w_i, W2 = sum w_i^2, and the self-normalised grid moments
+ *         m_p = sum_i w_i (1/N) sum_j u_ij^p / W, p = 1..4 (u on the N-grid);
+ *   C_i = w_0 + ... + w_i; systematic resampling: draw r = 0..m-1 takes the
+ *         first proposal with C_i > (u0 + r) W/m.
+ * weights[n] (optional), index[m] (proposal indices), sums[8] = {W, W2,
+ * max w, m1, m2, m3, m4, number of w > 1}.
+ */
+void orc_sir(const orc_point *p, uint64_t i0, uint64_t n, uint64_t m, double u0, double *weights,
+             uint64_t *index, double *sums, int nthreads)
+{
+    int K = p->K, N = p->N;
+    orc_grid_table g;
+    grid_table_init(&g, K, N, p->E0);
+    double *w = (double *)malloc(sizeof(double) * (n ? n : 1));
+    double *mom = (double *)malloc(sizeof(double) * 4 * (n ? n : 1));
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < (int64_t)n; ++q) {
+        double xh[2 * ORC_KMAX], lu;
+        double la = orc_proposal(p, i0 + (uint64_t)q, xh, &lu);
+        w[q] = exp(la);
+        double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+        for (int j = 0; j < N; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < K; ++k)
+                s += xh[k] * g.cosv[(size_t)j * K + k] + xh[K + k] * g.sinv[(size_t)j * K + k];
+            double u = g.amp * s;
+            s1 += u;
+            s2 += u * u;
+            s3 += u * u * u;
+            s4 += u * u * u * u;
+        }
+        mom[4 * q + 0] = s1 / N;
+        mom[4 * q + 1] = s2 / N;
+        mom[4 * q + 2] = s3 / N;
+        mom[4 * q + 3] = s4 / N;
+    }
+    double W = 0.0, W2 = 0.0, mx = 0.0, M[4] = {0.0, 0.0, 0.0, 0.0};
+    uint64_t over = 0;
+    for (uint64_t q = 0; q < n; ++q) {
+        W += w[q];
+        W2 += w[q] * w[q];
+        if (w[q] > mx) mx = w[q];
+        if (w[q] > 1.0) over++;
+        for (int c = 0; c < 4; ++c) M[c] += w[q] * mom[4 * q + c];
+        if (weights) weights[q] = w[q];
+    }
+    /* systematic resampling: walk the cumulative sums once */
+    uint64_t q = 0;
+    double C = n ? w[0] : 0.0;
+    for (uint64_t r = 0; r < m && n; ++r) {
+        double pos = (u0 + (double)r) * W / (double)m;
+        while (C <= pos && q + 1 < n) {
+            q++;
+            C += w[q];
+        }
+        index[r] = i0 + q;
+    }
+    sums[0] = W;
+    sums[1] = W2;
+    sums[2] = mx;
+    for (int c = 0; c < 4; ++c) sums[3 + c] = W > 0.0 ? M[c] / W : 0.0;
+    sums[7] = (double)over;
+    free(w);
+    free(mom);
+    grid_table_free(&g);
+}
