@@ -226,6 +226,41 @@ tkdv_status tkdv_extremes(tkdv_ctx *ctx, int32_t K, double E0, const float *d_xh
                           int32_t top_k, double threshold, uint64_t *h_rows, double *h_umax, int32_t *h_jmax,
                           uint64_t *h_n_exceed, float *d_umax, int32_t *d_jmax, void *stream);
 
+/* Result of tkdv_sir. */
+typedef struct {
+    uint64_t n;            /* proposals weighted                                          */
+    uint64_t m;            /* draws                                                       */
+    uint64_t n_over_one;   /* weights above 1 (where M is not a bound on f/g)             */
+    uint64_t pad;
+    double W;              /* sum of the weights w_i = f/(M g) at proposal i               */
+    double W2;             /* sum of w_i^2                                                 */
+    double ess;            /* effective sample size W^2/W2                                 */
+    double max_w;          /* largest weight                                               */
+    double mean, m2, m3, m4;   /* self-normalised grid moments sum_i w_i (1/N) sum_j u_ij^p / W */
+    double skewness, kurtosis; /* m3/m2^{3/2}, m4/m2^2                                     */
+} tkdv_sir_stats;
+
+/*
+ * Sampling-importance resampling with the paper's proposals, the alternative
+ * to the rejection step that the paper names (Sec. I, Sec. IV.B).  Proposals
+ * 0..n-1 of the point (the sampler's own draws, tkdv_sample) are weighted by
+ * w_i = f/(M g) (the fast-path acceptance probability of the rejection step,
+ * FP32 with FP32 or BF16x3 synthesis; M cancels in every normalised result).
+ * Systematic resampling: draw r = 0..m-1 takes the first proposal whose
+ * cumulative weight exceeds (u0 + r) W/m (cumulative sums in FP64, in
+ * proposal order, monotone by construction).
+ *   proposal UNIFORM or SIGMA; plan NULL plans internally; 1 <= n < 2^40;
+ *   u0 in [0, 1); d_index: device [m] proposal indices (non-decreasing),
+ *   required when m > 0; d_xhat: device [m][2K] rows of the drawn proposals
+ *   or NULL; d_weight: device [n] weights or NULL; h_stats: host.
+ *   stream: HIP stream (NULL: the null stream); the call returns after it.
+ * Errors: TKDV_E_ARG, TKDV_E_UNSUPPORTED (K, BF16 precision, all weights
+ * zero with m > 0), TKDV_E_DEVICE.
+ */
+tkdv_status tkdv_sir(tkdv_ctx *ctx, const tkdv_point *pt, tkdv_proposal proposal, const tkdv_plan *plan, uint64_t n,
+                     uint64_t m, double u0, tkdv_precision precision, uint64_t *d_index, float *d_xhat,
+                     float *d_weight, tkdv_sir_stats *h_stats, void *stream);
+
 /*
  * Rejection-sample one point (Sec. IV.B steps 2-5) on the GPU.
  *   mode = TKDV_COUNT_PROPOSALS: evaluate proposals 0..n-1;

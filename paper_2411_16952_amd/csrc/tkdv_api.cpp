@@ -19,6 +19,7 @@
 #include "tkdv_plan.h"
 #include "tkdv_plan_gpu.h"
 #include "tkdv_runtime.h"
+#include "tkdv_sir.h"
 
 using namespace tkdv;
 
@@ -72,6 +73,7 @@ struct tkdv_ctx {
     DevBuf sweep, active;
     DevBuf plan_pts, plan_val, plan_x, plan_ev;  // tkdv_plan_batch
     DevBuf ext_keys, ext_jmax, ext_misc, ext_list;  // tkdv_extremes
+    DevBuf sir_pt, sir_w, sir_tile, sir_chunk, sir_part;  // tkdv_sir
     void *h_poll = nullptr;  // pinned: active count, FP64 list count
     std::string arch;
 };
@@ -830,7 +832,7 @@ tkdv_status tkdv_destroy(tkdv_ctx *ctx)
                       &ctx->seg_cnt, &ctx->seg_base, &ctx->seg_stats, &ctx->results, &ctx->plist,
                       &ctx->mix, &ctx->mix_tab, &ctx->sweep, &ctx->active, &ctx->plan_pts, &ctx->plan_val,
                       &ctx->plan_x, &ctx->plan_ev, &ctx->ext_keys, &ctx->ext_jmax, &ctx->ext_misc,
-                      &ctx->ext_list};
+                      &ctx->ext_list, &ctx->sir_pt, &ctx->sir_w, &ctx->sir_tile, &ctx->sir_chunk, &ctx->sir_part};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (int i = 0; i < 4; ++i) {
@@ -1054,6 +1056,123 @@ tkdv_status tkdv_extremes(tkdv_ctx *ctx, int32_t K, double E0, const float *d_xh
         h_rows[i] = ra[o];
         h_umax[i] = f;
         h_jmax[i] = jm[o];
+    }
+    return TKDV_OK;
+}
+
+tkdv_status tkdv_sir(tkdv_ctx *ctx, const tkdv_point *pt, tkdv_proposal proposal, const tkdv_plan *plan, uint64_t n,
+                     uint64_t m, double u0, tkdv_precision precision, uint64_t *d_index, float *d_xhat,
+                     float *d_weight, tkdv_sir_stats *h_stats, void *stream)
+{
+    if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");
+    if (!pt || !h_stats) return set_err(ctx, TKDV_E_ARG, "NULL argument");
+    tkdv_status s = check_point(ctx, *pt);
+    if (s != TKDV_OK) return s;
+    if (proposal != TKDV_PROP_UNIFORM && proposal != TKDV_PROP_SIGMA)
+        return set_err(ctx, TKDV_E_ARG, "proposal must be UNIFORM or SIGMA");
+    if (precision != TKDV_FP32 && precision != TKDV_BF16X3)
+        return set_err(ctx, TKDV_E_UNSUPPORTED, "tkdv_sir computes weights with FP32 or BF16x3 synthesis");
+    if (n == 0 || n >= (1ull << 40)) return set_err(ctx, TKDV_E_ARG, "n must be in [1, 2^40)");
+    if (!(u0 >= 0.0 && u0 < 1.0)) return set_err(ctx, TKDV_E_ARG, "u0 must be in [0, 1)");
+    if (m > 0 && !d_index) return set_err(ctx, TKDV_E_ARG, "d_index is NULL");
+    if (plan && plan->proposal != proposal) return set_err(ctx, TKDV_E_ARG, "plan is for another proposal");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    tkdv_plan pl;
+    if (plan) {
+        pl = *plan;
+    } else {
+        const int ps = plan_point_host(pt, proposal, 2, &pl);
+        if (ps != TKDV_OK) return set_err(ctx, (tkdv_status)ps, "planning failed");
+    }
+    const int K = pt->K, ki = kindex(K);
+    s = build_tables(ctx, K);
+    if (s != TKDV_OK) return s;
+    DevPoint d;
+    fill_devpoint(d, *pt, pl, proposal, precision);
+    d.i0 = 0;
+    d.n = n;
+    d.n_tiles = (n + kTile - 1) / kTile;
+    const unsigned long long n_tiles = d.n_tiles, n_chunks = (n_tiles + kSirChunk - 1) / kSirChunk;
+    const int waves = sir_waves(ctx->n_cu);
+    HIP_TRY(ctx, ensure(ctx->sir_pt, sizeof(DevPoint)));
+    if (!d_weight) HIP_TRY(ctx, ensure(ctx->sir_w, n * sizeof(float)));
+    HIP_TRY(ctx, ensure(ctx->sir_tile, 2 * n_tiles * sizeof(double)));
+    HIP_TRY(ctx, ensure(ctx->sir_chunk, (2 * n_chunks + 1) * sizeof(double)));
+    HIP_TRY(ctx, ensure(ctx->sir_part, (size_t)waves * kSirPart * sizeof(double)));
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->sir_pt.p, &d, sizeof(d), hipMemcpyHostToDevice, st));
+    SirArgs a{};
+    a.pt = (const DevPoint *)ctx->sir_pt.p;
+    a.phi_hi = precision == TKDV_FP32 ? ctx->phi_f32[ki].p : ctx->phi_hi[ki].p;
+    a.phi_lo = ctx->phi_lo[ki].p;
+    a.n = n;
+    a.n_tiles = n_tiles;
+    a.w = d_weight ? d_weight : (float *)ctx->sir_w.p;
+    a.tile_sum = (double *)ctx->sir_tile.p;
+    a.tile_off = a.tile_sum + n_tiles;
+    a.chunk_sum = (double *)ctx->sir_chunk.p;
+    a.chunk_off = a.chunk_sum + n_chunks;
+    a.n_chunks = n_chunks;
+    a.wave_part = (double *)ctx->sir_part.p;
+    a.m = m;
+    a.u0 = u0;
+    a.index = reinterpret_cast<unsigned long long *>(d_index);
+    a.xhat = d_xhat;
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[0], st));
+    HIP_TRY(ctx, launch_sir_weights(K, precision, proposal, a, ctx->n_cu, st));
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[1], st));
+    HIP_TRY(ctx, launch_sir_scan(a, st));
+    double W = 0.0;
+    std::vector<double> part((size_t)waves * kSirPart);
+    HIP_TRY(ctx, hipMemcpyAsync(&W, a.chunk_off + n_chunks, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipMemcpyAsync(part.data(), a.wave_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    if (m > 0) {
+        if (!(W > 0.0)) return set_err(ctx, TKDV_E_UNSUPPORTED, "all weights are zero: nothing to resample");
+        a.W = W;
+        a.scale = (double)m / W;
+        HIP_TRY(ctx, launch_sir_resample(K, proposal, a, ctx->n_cu, st));
+    }
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[2], st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    {
+        float ms = 0.0f;
+        ctx->timing = tkdv_timing{};
+        if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) ctx->timing.decide_ms = ms;
+        if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[2]) == hipSuccess) ctx->timing.total_ms = ms;
+        ctx->timing.decide_grid = 4 * ctx->n_cu;
+        ctx->timing.decide_block = kBlock;
+    }
+    // per-wave partials in wave order
+    double W2 = 0.0, mx = 0.0, M[4] = {0.0, 0.0, 0.0, 0.0}, over = 0.0;
+    for (int w = 0; w < waves; ++w) {
+        const double *o = &part[(size_t)w * kSirPart];
+        W2 += o[0];
+        mx = std::max(mx, o[1]);
+        for (int c = 0; c < 4; ++c) M[c] += o[2 + c];
+        over += o[6];
+    }
+    std::memset(h_stats, 0, sizeof(*h_stats));
+    h_stats->n = n;
+    h_stats->m = m;
+    h_stats->n_over_one = (uint64_t)over;
+    h_stats->W = W;
+    h_stats->W2 = W2;
+    h_stats->ess = W2 > 0.0 ? W * W / W2 : 0.0;
+    h_stats->max_w = mx;
+    if (W > 0.0) {
+        const double amp = std::sqrt(2.0 * pt->E0 / kPi), N = 4.0 * K;
+        double ap = amp;
+        double mom[4];
+        for (int c = 0; c < 4; ++c, ap *= amp) mom[c] = M[c] * ap / N / W;
+        h_stats->mean = mom[0];
+        h_stats->m2 = mom[1];
+        h_stats->m3 = mom[2];
+        h_stats->m4 = mom[3];
+        if (mom[1] > 0.0) {
+            h_stats->skewness = mom[2] / std::pow(mom[1], 1.5);
+            h_stats->kurtosis = mom[3] / (mom[1] * mom[1]);
+        }
     }
     return TKDV_OK;
 }

@@ -51,6 +51,17 @@ class Plan(C.Structure):
                 ("M_source", C.c_int32), ("n_optimiser_evals", C.c_int32)]
 
 
+class SirStats(C.Structure):
+    """Result of tkdv_sir."""
+    _fields_ = [("n", C.c_uint64), ("m", C.c_uint64), ("n_over_one", C.c_uint64), ("pad", C.c_uint64),
+                ("W", C.c_double), ("W2", C.c_double), ("ess", C.c_double), ("max_w", C.c_double),
+                ("mean", C.c_double), ("m2", C.c_double), ("m3", C.c_double), ("m4", C.c_double),
+                ("skewness", C.c_double), ("kurtosis", C.c_double)]
+
+    def to_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
+
+
 class Mixture(C.Structure):
     """Learned defensive mixture (tkdv_mixture): base ACG L0 = D + V V^T and its S shifts."""
     _fields_ = [("K", C.c_int32), ("pad", C.c_int32), ("eps", C.c_double),
@@ -117,7 +128,7 @@ EXPORTS = ["tkdv_create", "tkdv_destroy", "tkdv_plan_point", "tkdv_sample", "tkd
            "tkdv_learner_add_rows_host", "tkdv_learner_train", "tkdv_learner_gradients",
            "tkdv_learner_mixture", "tkdv_learner_n_weights", "tkdv_learner_get_weights",
            "tkdv_learner_set_weights", "tkdv_sample_sweep", "tkdv_set_launch_cfg", "tkdv_get_launch_cfg",
-           "tkdv_autotune", "tkdv_plan_batch", "tkdv_extremes"]
+           "tkdv_autotune", "tkdv_plan_batch", "tkdv_extremes", "tkdv_sir"]
 
 _P = C.c_void_p
 lib.tkdv_create.argtypes = [C.c_int, C.POINTER(_P)]
@@ -165,6 +176,8 @@ lib.tkdv_autotune.argtypes = [_P, C.c_int32, C.c_int, C.c_char_p, C.POINTER(Laun
 lib.tkdv_extremes.argtypes = [_P, C.c_int32, C.c_double, _P, C.c_uint64, C.c_uint64, C.c_int32, C.c_double,
                               C.POINTER(C.c_uint64), C.POINTER(C.c_double), C.POINTER(C.c_int32),
                               C.POINTER(C.c_uint64), _P, _P, _P]
+lib.tkdv_sir.argtypes = [_P, C.POINTER(Point), C.c_int, C.POINTER(Plan), C.c_uint64, C.c_uint64, C.c_double,
+                         C.c_int, _P, _P, _P, C.POINTER(SirStats), _P]
 lib.tkdv_plan_batch.argtypes = [_P, C.c_int32, C.POINTER(Point), C.c_int, C.c_int32, C.c_uint64, C.c_int32,
                                 C.POINTER(Plan), C.POINTER(C.c_double), _P]
 lib.tkdv_status_str.argtypes = [C.c_int]
@@ -452,6 +465,27 @@ class Context:
         return {"rows": np.array(rows[:k], dtype=np.uint64), "umax": np.array(um[:k]),
                 "jmax": np.array(jm[:k], dtype=np.int64), "n_exceed": int(nex.value), "threshold": thr,
                 "umax_rows": du, "jmax_rows": dj}
+
+    def sir(self, point: Point, n: int, m: int, u0: float = 0.5, proposal: int = SIGMA, plan: Plan | None = None,
+            precision: int = BF16X3, rows: bool = False, weights: bool = False, stream=None) -> dict:
+        """Sampling-importance resampling over proposals 0..n-1 (tkdv_sir): the
+        statistics, m drawn proposal indices and, when asked, their rows of x^
+        and the weights of all n proposals."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        K = point.K
+        index = torch.empty((max(m, 1),), dtype=torch.int64, device=dev)
+        xh = torch.empty((max(m, 1), 2 * K), dtype=torch.float32, device=dev) if rows else None
+        w = torch.empty((n,), dtype=torch.float32, device=dev) if weights else None
+        st = SirStats()
+        _check(lib.tkdv_sir(self._h, C.byref(point), int(proposal), C.byref(plan) if plan is not None else None,
+                            int(n), int(m), float(u0), int(precision), _ptr(index), _ptr(xh), _ptr(w),
+                            C.byref(st), _stream(stream)), self._h)
+        d = st.to_dict()
+        d["index"] = index[:m]
+        d["xhat"] = xh[:m] if rows else None
+        d["weights"] = w
+        return d
 
     def synthesize(self, xhat, precision: int = BF16X3, s3=None, stream=None):
         """s3[r] = sum_j u~_j^3 on the N = 4K grid for rows x^ (n, 2K) float32 on the device."""
