@@ -175,6 +175,79 @@ def synthesis_bench(args) -> int:
     return 0
 
 
+def sir_bench(args) -> int:
+    """Sampling-importance resampling (tkdv_sir) on one K = 32 point of the plain
+    configuration (beta' = 40, beta'C3/C2 = 6000), beside the rejection
+    sampler on the same proposals.  value = effective samples/s (ESS per
+    second of the whole call: weights, scan and m = 1e6 draws with rows)."""
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs an MI355X GPU", file=sys.stderr)
+        return 1
+    from paper_2411_16952_amd import tkdv as T
+    K, bp, c = 32, 40.0, 150.0
+    n, m = int(args.proposals), 1_000_000
+    prec = T.PRECISIONS[args.precision]
+    pt = T.make_point(K, 1.0, bp, c, seed=1, point_id=7)
+    pl = T.plan_point(pt, T.SIGMA)
+    ctx = T.Context(0)
+    for _ in range(args.warmup):
+        ctx.sir(pt, n, m, 0.5, plan=pl, precision=prec, rows=True)
+    torch.cuda.synchronize()
+    wms, tms, ess = [], [], []
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        r = ctx.sir(pt, n, m, 0.5 + 0.1 * s, plan=pl, precision=prec, rows=True)
+        tm = ctx.timing()
+        wms.append(tm["decide_ms"])
+        tms.append(tm["total_ms"])
+        ess.append(r["ess"])
+        print(f"sir step {s}: {tm['total_ms']:.1f} ms (weights {tm['decide_ms']:.1f} ms), W {r['W']:.6g}, "
+              f"ESS {r['ess']:.6g}, skewness {r['skewness']:.5f}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # the rejection sampler on the same proposals
+    rj = ctx.sample(pt, n, proposal=T.SIGMA, plan=pl, precision=prec, capacity=1 << 20)
+    rj_ms = ctx.timing()["total_ms"]
+    # the extreme-wave search over the m drawn rows, and GPU plans of 64 points
+    rows = r["xhat"]
+    ctx.extremes(rows, K, top_k=100)
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    ex = ctx.extremes(rows, K, top_k=100)
+    ext_ms = (time.perf_counter() - te) * 1e3
+    pts64 = [T.make_point(K, 1.0, 20.0 + 0.5 * q, 3000.0 / (20.0 + 0.5 * q), seed=q, point_id=q) for q in range(64)]
+    ctx.plan_batch(pts64[:2], n_starts=16)
+    tp = time.perf_counter()
+    ctx.plan_batch(pts64, n_starts=16)
+    plan_ms = (time.perf_counter() - tp) * 1e3
+    print(f"extremes over {rows.shape[0]} rows: {ext_ms:.2f} ms (largest u {ex['umax'][0]:.4f}, "
+          f"{ex['n_exceed']} above 4 sigma); GPU plans of 64 points x 16 starts: {plan_ms:.1f} ms",
+          file=sys.stderr, flush=True)
+    avg_w = sum(wms) / len(wms) / 1e3
+    ops = alu_ops_per_proposal(K, "sigma", args.precision) + 12 * K   # + the power sums S1, S2, S4
+    roof = alu_roof(ops * n / avg_w, traffic=None, kernel="k_sir_weights", algorithmic_ops_per_proposal=ops,
+                    avg_launch_ms=avg_w * 1e3, proposals_per_launch=n,
+                    note="4 B written per proposal (the weights) + 8 B per tile (tile sums)")
+    line = {"metric": "effective samples/sec (SIR, K=32)", "value": sum(ess) / dt, "unit": "effective samples/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"SIR over {n:.3g} Sigma proposals of K=32, beta'=40, C3/C2={c}, "
+                                   f"{m} systematic draws with rows", "K": K, "proposals": n, "draws": m,
+                       "synthesis": args.precision},
+            "proposals_per_s": n * args.steps / dt, "ess_per_step": sum(ess) / len(ess),
+            "rejection": {"accepted": rj["n_accepted"], "ms": rj_ms,
+                          "accepted_per_s": rj["n_accepted"] / (rj_ms * 1e-3)},
+            "extremes": {"rows": int(rows.shape[0]), "ms": ext_ms, "largest_u": float(ex["umax"][0]),
+                         "above_4sigma": ex["n_exceed"]},
+            "plan_batch_64_points_16_starts_ms": plan_ms,
+            "roofline": roof, "cpu_baseline": None}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+    return 0
+
+
 def plain_bench(args) -> int:
     import torch
     if not torch.cuda.is_available():
@@ -559,7 +632,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="learned", choices=["learned", "plain", "sweep"])
+    ap.add_argument("--workload", default="learned", choices=["learned", "plain", "sweep", "sir"])
     ap.add_argument("--tune-cache", default="/tmp/tkdv_autotune.txt", help="autotuner cache (sweep workload)")
     ap.add_argument("--proposals", type=float, default=1e9, help="proposals per point (per sampler)")
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16", "bf16x3"])
@@ -592,6 +665,8 @@ def main() -> int:
 
     if args.workload == "sweep":
         return sweep_bench(args)
+    if args.workload == "sir":
+        return sir_bench(args)
     return learned_bench(args) if args.workload == "learned" else plain_bench(args)
 
 

@@ -251,6 +251,7 @@ __global__ void __launch_bounds__(kBlock) k_sir_resample(SirArgs a)
         const bool last_tile = tile + 1 == a.n_tiles;
         const unsigned long long A0 = draw_of(off, a, 0ull, a.m);
         const unsigned long long A1 = last_tile ? a.m : draw_of(a.tile_off[tile + 1], a, 0ull, a.m);
+        if (__builtin_amdgcn_readfirstlane((int)(A1 <= A0))) continue;  // no draw in this tile
         const unsigned long long local = tile * kTile + pl;
         const bool valid = local < a.n;
         const double w = (half == 0 && valid) ? (double)a.w[local] : 0.0;
@@ -329,7 +330,7 @@ hipError_t launch_sir_scan(const SirArgs &a, hipStream_t st)
 
 hipError_t launch_sir_resample(int K, int proposal, const SirArgs &a, int n_cu, hipStream_t st)
 {
-    const dim3 g(4 * n_cu), b(kBlock);
+    const dim3 g(12 * n_cu), b(kBlock);  // three waves per SIMD: the tile scan is latency-bound
 #define TKDV_SIRR(KK)                                                                                    \
     if (K == KK) {                                                                                       \
         if (proposal == PROP_SIGMA) hipLaunchKernelGGL((k_sir_resample<KK, PROP_SIGMA>), g, b, 0, st, a); \
