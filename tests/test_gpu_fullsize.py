@@ -2,7 +2,8 @@
 
 The samplers run 1e9 proposals per point (the plain GPU and learned
 configurations): the paper's sampler as one batched launch over two K = 32
-points, the mixture sampler on one K = 32 point.  The oracle then checks
+points, the mixture sampler on one K = 32 point, and SIR over the same
+proposals as the rejection sampler.  The oracle then checks
 sampled outputs one by one: 600 random proposal indices over the whole range
 (decision and, for accepted ones, the stored row), and 300 random accepted
 samples (an accept in FP64, the same row); the accepted count must be
@@ -41,6 +42,11 @@ def ctx(T):
     c = T.Context(0)
     yield c
     c.close()
+
+
+def torch_index(idx):
+    import torch
+    return torch.from_numpy(np.asarray(idx, dtype=np.int64)).cuda()
 
 
 def _check_sampled(res, decide, n, rng, label):
@@ -105,3 +111,48 @@ def test_mixture_1e9(T, ctx):
         return oracle.mix_proposal(K, 1.0, bp, c, pl.alpha_star, pl.log_M, mo, pt.seed, pt.point_id, i)
 
     _check_sampled(o, decide, N_PROP, rng, "mixture")
+
+
+def test_sir_1e9(T, ctx):
+    """SIR at the benchmark size: sampled weights against the oracle, and
+    sum_i a_i = W against the rejection sampler's accepted count on the same
+    proposals (the expected number of accepts is exactly W)."""
+    K, bp, c = 32, 40.0, 150.0
+    pt = T.make_point(K, 1.0, bp, c, seed=1, point_id=7)
+    pl = T.plan_point(pt, T.SIGMA)
+    tau = T.decision_window(pt, T.SIGMA, T.BF16X3)
+    g = ctx.sir(pt, N_PROP, 100_000, 0.5, plan=pl, precision=T.BF16X3, weights=True)
+    r = ctx.sample(pt, N_PROP, proposal=T.SIGMA, plan=pl, precision=T.BF16X3, capacity=0)
+    say(f"SIR 1e9: W {g['W']:.6g}, ESS {g['ess']:.6g}; rejection accepted {r['n_accepted']}")
+    assert r["n_M_violations"] == 0 and g["n_over_one"] == 0
+    assert abs(r["n_accepted"] - g["W"]) < 6.0 * math.sqrt(g["W"])
+    assert 0 < g["ess"] <= N_PROP
+    rng = np.random.default_rng(8)
+    idx = rng.integers(0, N_PROP, 300)
+    wg = g["weights"][torch_index(idx)].cpu().numpy().astype(np.float64)
+    for i, w in zip(idx, wg):
+        _, la, _ = oracle.proposal(K, 1.0, bp, c, 1, pl.alpha_star, pl.log_M, 1, 7, int(i))
+        assert abs(math.log(w) - la) <= tau / 2
+    d = g["index"].cpu().numpy()
+    assert np.all(np.diff(d.astype(np.int64)) >= 0)
+
+
+def test_sir_draws_against_the_weights_2e27(T, ctx):
+    """Every draw of a 2^27-proposal SIR call lies in its proposal's cumulative
+    interval of the returned weights (host FP64 prefix sums)."""
+    K, n, m, u0 = 16, 1 << 27, 200_003, 0.6180339887
+    pt = T.make_point(K, 1.0, 40.0, 60.0, seed=3, point_id=1)
+    pl = T.plan_point(pt, T.SIGMA)
+    g = ctx.sir(pt, n, m, u0, plan=pl, precision=T.BF16X3, weights=True)
+    w = g["weights"].cpu().numpy().astype(np.float64)
+    C = np.cumsum(w)
+    W = C[-1]
+    assert abs(W / g["W"] - 1) < 1e-10      # two summation orders of 2^27 terms
+    d = g["index"].cpu().numpy().astype(np.int64)
+    pos = (u0 + np.arange(m)) * g["W"] / m
+    ref = np.searchsorted(C, pos, side="right")
+    bad = np.nonzero(d != ref)[0]
+    for r in bad:   # only where the position sits on a boundary to rounding
+        lo, hi = sorted((d[r], ref[r]))
+        assert np.min(np.abs(C[lo:hi] - pos[r])) <= 1e-9 * W
+    say(f"SIR 2^27: {len(bad)} of {m} draws differ from the host search, all at boundaries")

@@ -4,7 +4,8 @@ Each case edits one line of a temporary copy of ``oracle/tkdv_oracle.c`` (a
 sign, an index, a dropped factor, a swapped function), builds it, and runs the
 fast subset of ``test_oracle_pins.py`` against that build in a subprocess.  The
 pins pass on the real oracle (that is ``test_oracle_pins.py`` itself); here
-every mutant must make at least one of them fail.  Mistakes in the Philox
+every mutant must make at least one of them fail (the mixture and SIR
+mutants run against their own pin files).  Mistakes in the Philox
 constants are not in this list: no closed form fixes them, and they are
 caught by bit-exact comparison with the independent HIP implementation.
 """
@@ -72,6 +73,19 @@ MIX_MUTATIONS = {
 }
 
 
+# mistakes in the sampling-importance resampling, run against its pins
+SIR_PINS = " or ".join(["equal_weights", "parseval_moments", "rejection_probabilities", "systematic_resampling",
+                        "agrees_with_rejection"])
+SIR_MUTATIONS = {
+    "sir_weight_power": ("        w[q] = exp(la);\n", "        w[q] = exp(2.0 * la);\n"),
+    "sir_no_offset": ("double pos = (u0 + (double)r) * W / (double)m;", "double pos = (double)r * W / (double)m;"),
+    "sir_unweighted_moments": ("for (int c = 0; c < 4; ++c) M[c] += w[q] * mom[4 * q + c];",
+                               "for (int c = 0; c < 4; ++c) M[c] += mom[4 * q + c];"),
+    "sir_fourth_power": ("s4 += u * u * u * u;", "s4 += u * u * u;"),
+    "sir_second_sum": ("W2 += w[q] * w[q];", "W2 += w[q];"),
+}
+
+
 def _run_mutant(name, old, new, pins_file, pins):
     src = open(SRC).read()
     assert src.count(old) == 1, f"mutation anchor for {name} not found exactly once"
@@ -92,6 +106,13 @@ def _run_mutant(name, old, new, pins_file, pins):
 def test_planted_mixture_mistake_is_caught(name):
     old, new = MIX_MUTATIONS[name]
     r = _run_mutant(name, old, new, "test_mixture_oracle.py", MIX_PINS)
+    assert r.returncode == 1, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
+
+
+@pytest.mark.parametrize("name", sorted(SIR_MUTATIONS))
+def test_planted_sir_mistake_is_caught(name):
+    old, new = SIR_MUTATIONS[name]
+    r = _run_mutant(name, old, new, "test_sir_oracle.py", SIR_PINS)
     assert r.returncode == 1, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
 
 
