@@ -401,12 +401,8 @@ def learned_bench(args) -> int:
     specs = W.learned_eval_points()
     pts = [T.make_point(s.K, s.E0, s.beta_p, s.c32, seed=s.seed, point_id=s.point_id) for s in specs]
     t0 = time.perf_counter()
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(pts))) as ex:
-        planned = list(ex.map(lambda p: learned.plan_for(res, p, margin=0.02), pts))
+    mixes, mplans, splans = learned.plan_for_points(ctx, res, pts, margin=0.02)   # M_mix searched on the GPU
     plan_s = time.perf_counter() - t0
-    mixes = [m for m, _, _ in planned]
-    mplans = [pl for _, pl, _ in planned]
-    splans = [sp for _, _, sp in planned]
     log_gain = [learned.log_M_sigma_normalised(sp) - pl.log_M for sp, pl in zip(splans, mplans)]
     n_per = int(args.proposals)
     cap = 1 << 20

@@ -123,7 +123,8 @@ typedef struct {
     double sigma2[TKDV_KMAX];   /* proposal variances s_k^2, k = 1..K                        */
     int32_t N;                  /* synthesis grid, 4K                                        */
     int32_t proposal;           /* tkdv_proposal                                             */
-    int32_t M_source;           /* 0 closed form (C3/C2 = 0), 1 host optimiser, 2 GPU search */
+    int32_t M_source;           /* 0 closed form (C3/C2 = 0), 1 host search, 2 GPU search,
+                                   3 the mixture's cap log M_Sigma - log_norm_g - log eps */
     int32_t n_optimiser_evals;  /* objective evaluations spent on log_M                      */
 } tkdv_plan;
 
@@ -337,10 +338,29 @@ tkdv_status tkdv_mixture_log_q(const tkdv_point *pt, const tkdv_plan *sigma_plan
  * log(1 + margin) and capped at log M_Sigma - log_norm_g - log eps (valid since
  * q_mix >= eps g_Sigma).  *out is the Sigma plan with log_M replaced and
  * proposal = TKDV_PROP_MIXTURE; argmax (host [2K], may be NULL) receives the
- * best point found. */
+ * best point found.  M_source: 1, or 3 where the cap applies. */
 tkdv_status tkdv_plan_mixture(const tkdv_point *pt, const tkdv_plan *sigma_plan, const tkdv_mixture *mix,
                               const double *starts, int32_t n_starts, double margin, tkdv_plan *out,
                               double *argmax);
+
+/*
+ * The same rejection constant for many points at once, searched on the GPU:
+ * one wavefront per (point, start) maximises log f - log q_mix by FP64 L-BFGS
+ * on the sphere (the search of tkdv_plan_batch with the mixture's log q_mix
+ * and its analytic gradient), from the zero-mean Dirichlet kernel, the
+ * single-mode state, n_starts - 2 seeded normal directions (key seed, counter
+ * (start, point_id, ...)) and n_user caller starts per point.  Margin and cap
+ * as tkdv_plan_mixture; M_source 2, or 3 where the cap applies.
+ *   pts, sigma_plans, mixes, out: host arrays [n_points]; 1 <= K <= 32;
+ *   starts: host [n_points][n_user][2 TKDV_KMAX] (first 2K entries used) or
+ *   NULL with n_user = 0; n_starts in [1, 256]; xhat_best: host
+ *   [n_points][2 TKDV_KMAX] or NULL; stream: HIP stream; returns after it.
+ * Errors: TKDV_E_ARG (a mixture or start that is not finite, K, counts).
+ */
+tkdv_status tkdv_plan_mixture_batch(tkdv_ctx *ctx, int32_t n_points, const tkdv_point *pts,
+                                    const tkdv_plan *sigma_plans, const tkdv_mixture *mixes, const double *starts,
+                                    int32_t n_user, int32_t n_starts, uint64_t seed, double margin, tkdv_plan *out,
+                                    double *xhat_best, void *stream);
 
 /* tkdv_sample with the learned proposal (plan from tkdv_plan_mixture), same
  * outputs and statistics.  K in {8, 16, 32}: at K = 64 the synthesis and shift

@@ -71,7 +71,7 @@ struct tkdv_ctx {
     hipStream_t sweep_stream = nullptr;
     hipEvent_t join[2] = {};
     DevBuf sweep, active;
-    DevBuf plan_pts, plan_val, plan_x, plan_ev;  // tkdv_plan_batch
+    DevBuf plan_pts, plan_val, plan_x, plan_ev, plan_mix, plan_user;  // tkdv_plan_batch, _mixture_batch
     DevBuf ext_keys, ext_jmax, ext_misc, ext_list;  // tkdv_extremes
     DevBuf sir_pt, sir_w, sir_tile, sir_chunk, sir_part;  // tkdv_sir
     void *h_poll = nullptr;  // pinned: active count, FP64 list count
@@ -831,7 +831,7 @@ tkdv_status tkdv_destroy(tkdv_ctx *ctx)
     DevBuf *bufs[] = {&ctx->bitmap, &ctx->defer_list, &ctx->defer_count, &ctx->counters, &ctx->points,
                       &ctx->seg_cnt, &ctx->seg_base, &ctx->seg_stats, &ctx->results, &ctx->plist,
                       &ctx->mix, &ctx->mix_tab, &ctx->sweep, &ctx->active, &ctx->plan_pts, &ctx->plan_val,
-                      &ctx->plan_x, &ctx->plan_ev, &ctx->ext_keys, &ctx->ext_jmax, &ctx->ext_misc,
+                      &ctx->plan_x, &ctx->plan_ev, &ctx->plan_mix, &ctx->plan_user, &ctx->ext_keys, &ctx->ext_jmax, &ctx->ext_misc,
                       &ctx->ext_list, &ctx->sir_pt, &ctx->sir_w, &ctx->sir_tile, &ctx->sir_chunk, &ctx->sir_part};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
@@ -861,6 +861,73 @@ tkdv_status tkdv_plan_point(const tkdv_point *pt, tkdv_proposal proposal, tkdv_p
     if (s != TKDV_OK) return set_err(nullptr, s, "planning failed");
     return TKDV_OK;
 }
+
+namespace {
+
+// The multi-start search of k_plan_search for the points pp (mixtures and
+// caller starts optional): values, final iterates [item][128] and evaluation
+// counts per item, item = point * (n_starts + n_user) + start.
+tkdv_status run_plan_search(tkdv_ctx *ctx, const std::vector<PlanPoint> &pp, const std::vector<PlanMix> *mix,
+                            const std::vector<double> *user, int n_user, int n_starts, uint64_t seed,
+                            hipStream_t st, std::vector<double> &val, std::vector<double> &xb,
+                            std::vector<int> &ev)
+{
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const int per = n_starts + n_user;
+    const int n_items = (int)pp.size() * per;
+    HIP_TRY(ctx, ensure(ctx->plan_pts, pp.size() * sizeof(PlanPoint)));
+    HIP_TRY(ctx, ensure(ctx->plan_val, (size_t)n_items * sizeof(double)));
+    HIP_TRY(ctx, ensure(ctx->plan_x, (size_t)n_items * 128 * sizeof(double)));
+    HIP_TRY(ctx, ensure(ctx->plan_ev, (size_t)n_items * sizeof(int)));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->plan_pts.p, pp.data(), pp.size() * sizeof(PlanPoint), hipMemcpyHostToDevice, st));
+    PlanArgs a{};
+    if (mix) {
+        HIP_TRY(ctx, ensure(ctx->plan_mix, mix->size() * sizeof(PlanMix)));
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->plan_mix.p, mix->data(), mix->size() * sizeof(PlanMix),
+                                    hipMemcpyHostToDevice, st));
+        a.mix = (const PlanMix *)ctx->plan_mix.p;
+    }
+    if (n_user > 0) {
+        HIP_TRY(ctx, ensure(ctx->plan_user, user->size() * sizeof(double)));
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->plan_user.p, user->data(), user->size() * sizeof(double),
+                                    hipMemcpyHostToDevice, st));
+        a.x_user = (const double *)ctx->plan_user.p;
+    }
+    a.pts = (const PlanPoint *)ctx->plan_pts.p;
+    a.n_user = n_user;
+    a.n_items = n_items;
+    a.n_starts = n_starts;
+    a.seed_lo = (uint32_t)seed;
+    a.seed_hi = (uint32_t)(seed >> 32);
+    a.val = (double *)ctx->plan_val.p;
+    a.xbest = (double *)ctx->plan_x.p;
+    a.evals = (int *)ctx->plan_ev.p;
+    HIP_TRY(ctx, launch_plan_search(a, st));
+    val.assign(n_items, 0.0);
+    xb.assign((size_t)n_items * 128, 0.0);
+    ev.assign(n_items, 0);
+    HIP_TRY(ctx, hipMemcpyAsync(val.data(), a.val, val.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipMemcpyAsync(xb.data(), a.xbest, xb.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipMemcpyAsync(ev.data(), a.evals, ev.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    return TKDV_OK;
+}
+
+// The best item of point w: index into val (-1 if no finite value), total evaluations.
+int best_item(const std::vector<double> &val, const std::vector<int> &ev, int w, int per, long *total)
+{
+    int best = -1;
+    *total = 0;
+    for (int s = 0; s < per; ++s) {
+        const int it = w * per + s;
+        *total += ev[it];
+        if (!std::isfinite(val[it])) continue;
+        if (best < 0 || val[it] > val[best]) best = it;
+    }
+    return best;
+}
+
+}  // namespace
 
 tkdv_status tkdv_plan_batch(tkdv_ctx *ctx, int32_t n_points, const tkdv_point *pts, tkdv_proposal proposal,
                             int32_t n_starts, uint64_t seed, int32_t flags, tkdv_plan *out, double *xhat_best,
@@ -899,47 +966,109 @@ tkdv_status tkdv_plan_batch(tkdv_ctx *ctx, int32_t n_points, const tkdv_point *p
         which.push_back(p);
     }
     if (which.empty()) return TKDV_OK;
-    HIP_TRY(ctx, hipSetDevice(ctx->device));
-    const int n_items = (int)which.size() * n_starts;
-    HIP_TRY(ctx, ensure(ctx->plan_pts, pp.size() * sizeof(PlanPoint)));
-    HIP_TRY(ctx, ensure(ctx->plan_val, (size_t)n_items * sizeof(double)));
-    HIP_TRY(ctx, ensure(ctx->plan_x, (size_t)n_items * 128 * sizeof(double)));
-    HIP_TRY(ctx, ensure(ctx->plan_ev, (size_t)n_items * sizeof(int)));
-    hipStream_t st = (hipStream_t)stream;
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->plan_pts.p, pp.data(), pp.size() * sizeof(PlanPoint), hipMemcpyHostToDevice, st));
-    PlanArgs a{};
-    a.pts = (const PlanPoint *)ctx->plan_pts.p;
-    a.n_items = n_items;
-    a.n_starts = n_starts;
-    a.seed_lo = (uint32_t)seed;
-    a.seed_hi = (uint32_t)(seed >> 32);
-    a.val = (double *)ctx->plan_val.p;
-    a.xbest = (double *)ctx->plan_x.p;
-    a.evals = (int *)ctx->plan_ev.p;
-    HIP_TRY(ctx, launch_plan_search(a, st));
-    std::vector<double> val(n_items), xb((size_t)n_items * 128);
-    std::vector<int> ev(n_items);
-    HIP_TRY(ctx, hipMemcpyAsync(val.data(), a.val, val.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(ctx, hipMemcpyAsync(xb.data(), a.xbest, xb.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(ctx, hipMemcpyAsync(ev.data(), a.evals, ev.size() * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_TRY(ctx, hipStreamSynchronize(st));
+    std::vector<double> val, xb;
+    std::vector<int> ev;
+    tkdv_status rs = run_plan_search(ctx, pp, nullptr, nullptr, 0, n_starts, seed, (hipStream_t)stream, val, xb, ev);
+    if (rs != TKDV_OK) return rs;
     for (size_t w = 0; w < which.size(); ++w) {
         const int p = which[w];
-        int best = -1;
         long total = 0;
-        for (int s = 0; s < n_starts; ++s) {
-            const int it = (int)w * n_starts + s;
-            total += ev[it];
-            if (!std::isfinite(val[it])) continue;
-            if (best < 0 || val[it] > val[(size_t)w * n_starts + best]) best = s;
-        }
-        if (best < 0) return set_err(ctx, TKDV_E_DEVICE, "point " + std::to_string(p) + ": search gave no value");
-        const size_t bi = (size_t)w * n_starts + best;
+        const int bi = best_item(val, ev, (int)w, n_starts, &total);
+        if (bi < 0) return set_err(ctx, TKDV_E_DEVICE, "point " + std::to_string(p) + ": search gave no value");
         out[p].log_M = val[bi];
         out[p].M_source = 2;
         out[p].n_optimiser_evals = (int32_t)std::min<long>(total, INT32_MAX);
         if (xhat_best)
-            for (int m = 0; m < 2 * pts[p].K; ++m) xhat_best[(size_t)p * 2 * TKDV_KMAX + m] = xb[bi * 128 + m];
+            for (int m = 0; m < 2 * pts[p].K; ++m) xhat_best[(size_t)p * 2 * TKDV_KMAX + m] = xb[(size_t)bi * 128 + m];
+    }
+    return TKDV_OK;
+}
+
+tkdv_status tkdv_plan_mixture_batch(tkdv_ctx *ctx, int32_t n_points, const tkdv_point *pts,
+                                    const tkdv_plan *sigma_plans, const tkdv_mixture *mixes, const double *starts,
+                                    int32_t n_user, int32_t n_starts, uint64_t seed, double margin, tkdv_plan *out,
+                                    double *xhat_best, void *stream)
+{
+    if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");
+    if (n_points < 0) return set_err(ctx, TKDV_E_ARG, "n_points < 0");
+    if (n_points == 0) return TKDV_OK;
+    if (!pts || !sigma_plans || !mixes || !out) return set_err(ctx, TKDV_E_ARG, "NULL argument");
+    if (n_starts < 1 || n_starts > 256) return set_err(ctx, TKDV_E_ARG, "n_starts must be in [1, 256]");
+    if (n_user < 0 || n_user > 256 || (n_user > 0 && !starts)) return set_err(ctx, TKDV_E_ARG, "bad caller starts");
+    if (!(margin >= 0.0) || !std::isfinite(margin)) return set_err(ctx, TKDV_E_ARG, "margin must be >= 0");
+    if ((int64_t)n_points * (n_starts + n_user) > (int64_t)(1 << 30)) return set_err(ctx, TKDV_E_ARG, "too many starts");
+    std::vector<PlanPoint> pp(n_points);
+    std::vector<PlanMix> pm(n_points);
+    std::vector<double> user((size_t)n_points * std::max(n_user, 0) * 128, 0.0);
+    std::vector<double> cap(n_points), log_eps(n_points);
+    for (int p = 0; p < n_points; ++p) {
+        const tkdv_point &q = pts[p];
+        const tkdv_plan &sp = sigma_plans[p];
+        if (q.K < 1 || q.K > 32) return set_err(ctx, TKDV_E_ARG, "point " + std::to_string(p) + ": K must be <= 32");
+        if (!std::isfinite(q.E0) || !(q.E0 > 0.0) || !std::isfinite(q.beta_p) || !std::isfinite(q.c32))
+            return set_err(ctx, TKDV_E_ARG, "point " + std::to_string(p) + ": bad point");
+        if (sp.proposal != TKDV_PROP_SIGMA) return set_err(ctx, TKDV_E_ARG, "sigma_plans must be Sigma plans");
+        MixHost mh;
+        const int st = mh.init(q, sp, mixes[p]);
+        if (st != TKDV_OK) return set_err(ctx, (tkdv_status)st, "point " + std::to_string(p) + ": bad mixture");
+        const int K = q.K, n2 = 2 * K;
+        PlanPoint P{};
+        P.K = K;
+        P.N = 4 * K;
+        P.sigma = 0;  // log f alone; the mixture term is added in the kernel
+        P.point_id = q.point_id;
+        P.dt0 = -q.beta_p / ((double)K * K);
+        P.cH = q.beta_p * q.c32 / (q.E0 * (double)K * K);
+        const double amp = std::sqrt(2.0 * q.E0 / kPi);
+        P.amp3 = amp * amp * amp;
+        pp[p] = P;
+        PlanMix &M = pm[p];
+        std::memset(&M, 0, sizeof(M));
+        for (int c = 0; c < n2; ++c) {
+            M.a[c] = mh.a[c];
+            M.V[c][0] = mh.V[(size_t)c * 2];
+            M.V[c][1] = mh.V[(size_t)c * 2 + 1];
+        }
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 2; ++c) M.gi[r][c] = mh.Ginv[r][c];
+        for (int m = 0; m < 32; ++m) {
+            M.cs[m] = std::cos(2.0 * kPi * m / 32.0);
+            M.sn[m] = std::sin(2.0 * kPi * m / 32.0);
+        }
+        M.logdetL0 = mh.logdetL0;
+        M.lng = mh.lng;
+        M.log_eps = mh.log_eps;
+        M.log_1m_eps = mh.log_1m_eps;
+        M.gc = mh.alpha * mh.beta_p / ((double)K * K * K);
+        cap[p] = sp.log_M - sp.log_norm_g - mh.log_eps;
+        for (int u = 0; u < n_user; ++u) {
+            const double *src = starts + ((size_t)p * n_user + u) * 2 * TKDV_KMAX;
+            double r2 = 0.0;
+            for (int c = 0; c < n2; ++c) r2 += src[c] * src[c];
+            if (!(r2 > 0.0) || !std::isfinite(r2))
+                return set_err(ctx, TKDV_E_ARG, "point " + std::to_string(p) + ": a caller start is zero or not finite");
+            for (int c = 0; c < n2; ++c) user[((size_t)p * n_user + u) * 128 + c] = src[c];
+        }
+    }
+    std::vector<double> val, xb;
+    std::vector<int> ev;
+    tkdv_status rs = run_plan_search(ctx, pp, &pm, &user, n_user, n_starts, seed, (hipStream_t)stream, val, xb, ev);
+    if (rs != TKDV_OK) return rs;
+    const int per = n_starts + n_user;
+    for (int p = 0; p < n_points; ++p) {
+        long total = 0;
+        const int bi = best_item(val, ev, p, per, &total);
+        if (bi < 0) return set_err(ctx, TKDV_E_DEVICE, "point " + std::to_string(p) + ": search gave no value");
+        const double lm = val[bi] + std::log1p(margin);
+        out[p] = sigma_plans[p];
+        out[p].proposal = TKDV_PROP_MIXTURE;
+        out[p].log_M = std::min(lm, cap[p]);
+        out[p].M_source = lm > cap[p] ? 3 : 2;
+        out[p].n_optimiser_evals = (int32_t)std::min<long>(total, INT32_MAX);
+        if (xhat_best) {
+            std::fill(xhat_best + (size_t)p * 2 * TKDV_KMAX, xhat_best + (size_t)(p + 1) * 2 * TKDV_KMAX, 0.0);
+            for (int m = 0; m < 2 * pts[p].K; ++m) xhat_best[(size_t)p * 2 * TKDV_KMAX + m] = xb[(size_t)bi * 128 + m];
+        }
     }
     return TKDV_OK;
 }

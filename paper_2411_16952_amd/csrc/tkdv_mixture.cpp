@@ -395,7 +395,7 @@ extern "C" tkdv_status tkdv_plan_mixture(const tkdv_point *pt, const tkdv_plan *
     *out = *sp;
     out->proposal = TKDV_PROP_MIXTURE;
     out->log_M = std::min(lm, cap);
-    out->M_source = lm > cap ? 2 : 1;
+    out->M_source = lm > cap ? 3 : 1;
     out->n_optimiser_evals = (int32_t)std::min<long>(total, INT32_MAX);
     if (argmax) std::memcpy(argmax, S[best].data(), sizeof(double) * n);
     return TKDV_OK;

@@ -24,10 +24,27 @@ struct PlanPoint {
     double dt0, cH, amp3, a;
 };
 
+// The learned mixture of a point (K <= 32), for the search of
+// M_mix = sup f/q_mix: phi = log f - log q_mix with
+//   log q_mix = LSE(log eps + lg(t), log(1 - eps) + log q_net),
+//   lg(t) = lng - K log(1 + gc t) (the normalised g_Sigma),
+//   log q_net = -logdetL0/2 + LSE_j(-K log qf_j) - log S,
+//   qf_j = e^T A e + |g|^2, w = R_j^T x, g = Ginv V^T A w, e = w - V g.
+struct PlanMix {
+    double a[64];         // 1/d per coordinate
+    double V[64][2];      // base rank-2 factor, rows = coordinates
+    double gi[2][2];      // (I + V^T A V)^-1
+    double cs[32], sn[32];  // cos, sin of 2 pi m/S
+    double logdetL0, lng, log_eps, log_1m_eps, gc;
+};
+
 struct PlanArgs {
     const PlanPoint *pts;
-    int n_items;        // points x starts
-    int n_starts;
+    const PlanMix *mix;     // [points] or nullptr: the mixture objective
+    const double *x_user;   // [points][n_user][128] caller starts or nullptr
+    int n_user;             // caller starts per point (items n_starts .. n_starts + n_user - 1)
+    int n_items;        // points x (n_starts + n_user)
+    int n_starts;       // generated starts per point
     uint32_t seed_lo, seed_hi;
     double *val;        // [n_items] objective at the final iterate
     double *xbest;      // [n_items][128] final iterate (unit vector)

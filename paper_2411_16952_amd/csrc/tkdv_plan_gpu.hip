@@ -3,7 +3,8 @@
 // (point, start), in FP64.
 //
 // Each wave maximises phi(x^) = log f(x^) - log g(x^) (the unnormalised ratio
-// of tkdv_plan_point) by L-BFGS ascent on the unit sphere: retraction by
+// of tkdv_plan_point), or log f - log q_mix for the learned mixture (K <= 32),
+// by L-BFGS ascent on the unit sphere: retraction by
 // normalisation, the tangent gradient, Armijo backtracking, 8 curvature pairs
 // kept in registers.  The value and the gradient come from the N = 4K grid:
 //   u~_j = sum_k (-1)^k (x^_k cos(2 pi k j/N) + x^_{K+k} sin(2 pi k j/N)),
@@ -38,9 +39,58 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_wave_barrier();
 }
 
+// log q_mix of the mixture at the unit vector x (K <= 32: coordinate `lane`)
+// and its ambient gradient for this lane's coordinate; t = sum_k k^2 s_k.
+// The shifts' log-sum-exp runs online (rescaled when a larger term appears).
+__device__ double mix_log_q(const PlanMix &M, int K, int lane, double x0, double t, double &dq)
+{
+    const int n2 = 2 * K;
+    const bool act = lane < n2;
+    const bool sinb = lane >= K;
+    const int k = lane % K + 1;
+    const int partner = act ? (sinb ? lane - K : lane + K) : lane;
+    const double xp = __shfl(x0, partner, 64);
+    const double am = act ? M.a[lane] : 0.0;
+    const double v0 = act ? M.V[lane][0] : 0.0, v1 = act ? M.V[lane][1] : 0.0;
+    double mx = -INFINITY, se = 0.0, G = 0.0;
+    for (int j = 0; j < 32; ++j) {
+        const int mi = (k * j) & 31;
+        const double cs = M.cs[mi], sn = M.sn[mi];
+        const double w = act ? (sinb ? x0 * cs + xp * sn : x0 * cs - xp * sn) : 0.0;
+        const double y0 = wsum(am * v0 * w), y1 = wsum(am * v1 * w);
+        const double g0 = M.gi[0][0] * y0 + M.gi[0][1] * y1, g1 = M.gi[1][0] * y0 + M.gi[1][1] * y1;
+        const double e = w - (v0 * g0 + v1 * g1);
+        const double h = am * e;
+        const double qf = wsum(h * e) + g0 * g0 + g1 * g1;
+        const double hp = __shfl(h, partner, 64);
+        // d qf_j / d x = 2 R_j (A e): the shift of A e back by +phi_j
+        const double dqj = 2.0 * (sinb ? cs * h - sn * hp : cs * h + sn * hp);
+        const double l = -0.5 * M.logdetL0 - K * log(qf);
+        const double gl = act ? (-K / qf) * dqj : 0.0;
+        if (uniform(l > mx)) {
+            const double r = exp(mx - l);
+            se = se * r + 1.0;
+            G = G * r + gl;
+            mx = l;
+        } else {
+            const double r = exp(l - mx);
+            se += r;
+            G += r * gl;
+        }
+    }
+    const double lnet = mx + log(se) - log(32.0);
+    const double lg = M.lng - K * log1p(M.gc * t);
+    const double A = M.log_eps + lg, B = M.log_1m_eps + lnet;
+    const double hi = A > B ? A : B;
+    const double lm = hi + log(exp(A - hi) + exp(B - hi));
+    const double wg = exp(A - lm), wn = exp(B - lm);
+    dq = act ? wg * (-K * M.gc / (1.0 + M.gc * t)) * 2.0 * k * k * x0 + wn * (G / se) : 0.0;
+    return lm;
+}
+
 // phi at the unit vector (x0, x1) and its tangent gradient (g0, g1).
-__device__ double plan_eval(const PlanPoint &P, double *xs, double *us, const double *ct, int lane, double x0,
-                            double x1, double &g0, double &g1)
+__device__ double plan_eval(const PlanPoint &P, const PlanMix *mix, double *xs, double *us, const double *ct,
+                            int lane, double x0, double x1, double &g0, double &g1)
 {
     const int K = P.K, N = P.N, n2 = 2 * K, q = N / 4;
     const int m0 = lane, m1 = lane + 64;
@@ -95,6 +145,11 @@ __device__ double plan_eval(const PlanPoint &P, double *xs, double *us, const do
     const double cg = P.cH * kPiP * P.amp3 / N;
     g0 = v0 ? dt * 2.0 * k0 * k0 * x0 + cg * d0 : 0.0;
     g1 = v1 ? dt * 2.0 * k1 * k1 * x1 + cg * d1 : 0.0;
+    if (mix) {  // phi = log f - log q_mix (K <= 32: x1 is unused)
+        double dq;
+        val -= mix_log_q(*mix, K, lane, x0, t, dq);
+        g0 -= dq;
+    }
     const double gx = wsum(g0 * x0 + g1 * x1);
     g0 -= gx * x0;
     g1 -= gx * x1;
@@ -111,14 +166,20 @@ __global__ void __launch_bounds__(64 * kPlanWaves) k_plan_search(PlanArgs a)
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int item = blockIdx.x * kPlanWaves + w;
     if (item >= a.n_items) return;  // whole wave; no workgroup barrier follows
-    const int p = item / a.n_starts, s = item % a.n_starts;
+    const int per = a.n_starts + a.n_user;
+    const int p = item / per, s = item % per;
     const PlanPoint P = a.pts[p];
+    const PlanMix *M = a.mix ? a.mix + p : nullptr;
     double *xs = xs_all[w], *us = us_all[w], *ct = ct_all[w];
     const int K = P.K, N = P.N, n2 = 2 * K;
     for (int r = lane; r < N; r += 64) ct[r] = cos(2.0 * kPiP * r / N);
     const int m0 = lane, m1 = lane + 64;
     double x0 = 0.0, x1 = 0.0;
-    if (s == 0) {  // zero-mean Dirichlet kernel: equal cos coefficients
+    if (s >= a.n_starts) {  // a caller start
+        const double *u = a.x_user + ((size_t)p * a.n_user + (s - a.n_starts)) * 128;
+        x0 = m0 < n2 ? u[m0] : 0.0;
+        x1 = m1 < n2 ? u[m1] : 0.0;
+    } else if (s == 0) {  // zero-mean Dirichlet kernel: equal cos coefficients
         x0 = m0 < K ? 1.0 : 0.0;
         x1 = m1 < K ? 1.0 : 0.0;
     } else if (s == 1) {  // all energy in mode 1
@@ -141,7 +202,7 @@ __global__ void __launch_bounds__(64 * kPlanWaves) k_plan_search(PlanArgs a)
     }
     wave_sync_lds();  // cos table
     double g0, g1;
-    double f = plan_eval(P, xs, us, ct, lane, x0, x1, g0, g1);
+    double f = plan_eval(P, M, xs, us, ct, lane, x0, x1, g0, g1);
     int evals = 1;
     // curvature pairs, newest first: s = x_new - x_old, y = g_old - g_new
     double S0[kPlanMem], S1[kPlanMem], Y0[kPlanMem], Y1[kPlanMem], RHO[kPlanMem];
@@ -192,7 +253,7 @@ __global__ void __launch_bounds__(64 * kPlanWaves) k_plan_search(PlanArgs a)
             const double r = sqrt(wsum(x20 * x20 + x21 * x21));
             x20 /= r;
             x21 /= r;
-            f2 = plan_eval(P, xs, us, ct, lane, x20, x21, g20, g21);
+            f2 = plan_eval(P, M, xs, us, ct, lane, x20, x21, g20, g21);
             ++evals;
             if (uniform(f2 >= f + 1e-4 * step * slope)) {
                 ok = true;

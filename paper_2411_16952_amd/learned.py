@@ -4,7 +4,8 @@ Cutting-plane minimax fit of the network's mixtures to a set of training
 points, on the GPU:
   1. accepted samples of each point from the paper's sampler (kind-0 rows);
   2. each round: for every point, the network's mixture, its rejection
-     constant M_mix = sup f/q_mix by tkdv_plan_mixture (multi-start BFGS),
+     constant M_mix = sup f/q_mix (tkdv_plan_mixture_batch: all points at
+     once, multi-start L-BFGS on the GPU; or the host's tkdv_plan_mixture),
      and the arg max plus copies of it shifted by fractions of 2 pi/S (the
      target is invariant under every xi-shift, q_mix only under multiples of
      2 pi/S) added as kind-1 rows; then Adam steps on the loss of
@@ -53,9 +54,26 @@ def log_M_sigma_normalised(sp: T.Plan) -> float:
     return sp.log_M - sp.log_norm_g
 
 
+def plan_mixtures(ctx: T.Context, points: list, sigma_plans: list, mixes: list, starts=None, margin: float = 0.0,
+                  seed: int = 0, planner: str = "gpu") -> tuple[list, np.ndarray]:
+    """(mixture plans, maximisers [n, 2K]) of many points: on the GPU in one call
+    (planner "gpu") or point by point on the host ("host"); starts: None or
+    (n, n_user, 2K) caller starts."""
+    if planner == "gpu":
+        plans, xb = ctx.plan_mixture_batch(points, sigma_plans, mixes, starts=starts, n_starts=16, seed=seed,
+                                           margin=margin)
+        return plans, xb[:, : 2 * points[0].K] if points else xb
+    out, am = [], []
+    for i, (pt, sp, mx) in enumerate(zip(points, sigma_plans, mixes)):
+        pl, a = T.plan_mixture(pt, sp, mx, starts=None if starts is None else starts[i], margin=margin)
+        out.append(pl)
+        am.append(a)
+    return out, np.array(am)
+
+
 def fit(ctx: T.Context, points: list, cfg: T.LearnerCfg, samples_per_point: int = 4096, rounds: int = 8,
         steps: int = 150, max_proposals: int = 1 << 32, n_shift_copies: int = 7, margin: float = 0.0,
-        precision: int = T.BF16X3, log=None) -> FitResult:
+        precision: int = T.BF16X3, log=None, planner: str = "gpu") -> FitResult:
     sps = [T.plan_point(p, T.SIGMA) for p in points]
     L = T.Learner(ctx, cfg)
     L.set_points(points, sps)
@@ -72,11 +90,11 @@ def fit(ctx: T.Context, points: list, cfg: T.LearnerCfg, samples_per_point: int 
     best = (-np.inf, None, -1)
     for rnd in range(rounds + 1):
         t0 = time.time()
+        mixes = [L.mixture(pt, sp) for pt, sp in zip(points, sps)]
+        st = np.array([s_[-8:] for s_ in starts]) if starts[0] else None
+        plans, ams = plan_mixtures(ctx, points, sps, mixes, starts=st, margin=margin, seed=rnd, planner=planner)
         gains = []
-        for i, (pt, sp) in enumerate(zip(points, sps)):
-            mix = L.mixture(pt, sp)
-            st = np.array(starts[i][-8:]) if starts[i] else None
-            pl, am = T.plan_mixture(pt, sp, mix, starts=st, margin=margin)
+        for i, (sp, pl, am) in enumerate(zip(sps, plans, ams)):
             gains.append(log_M_sigma_normalised(sp) - pl.log_M)
             if rnd < rounds:
                 rows = np.vstack([am[None, :], shift_rows(am, fracs)])
@@ -98,6 +116,18 @@ def fit(ctx: T.Context, points: list, cfg: T.LearnerCfg, samples_per_point: int 
     if log:
         log(f"kept the weights of round {best[2]} (mean M_Sigma/M_mix {math.exp(best[0]):.2f})")
     return res
+
+
+def plan_for_points(ctx: T.Context, res_or_learner, points: list, margin: float = 0.02, planner: str = "gpu"):
+    """(mixtures, mixture plans, Sigma plans) of the trained network at many points."""
+    L = res_or_learner.learner if isinstance(res_or_learner, FitResult) else res_or_learner
+    if planner == "gpu":
+        sps, _ = ctx.plan_batch(points, T.SIGMA, n_starts=16, seed=1)
+    else:
+        sps = [T.plan_point(p, T.SIGMA) for p in points]
+    mixes = [L.mixture(p, sp) for p, sp in zip(points, sps)]
+    plans, _ = plan_mixtures(ctx, points, sps, mixes, margin=margin, planner=planner)
+    return mixes, plans, sps
 
 
 def plan_for(res_or_learner, point: T.Point, margin: float = 0.02, starts=None):

@@ -128,7 +128,7 @@ EXPORTS = ["tkdv_create", "tkdv_destroy", "tkdv_plan_point", "tkdv_sample", "tkd
            "tkdv_learner_add_rows_host", "tkdv_learner_train", "tkdv_learner_gradients",
            "tkdv_learner_mixture", "tkdv_learner_n_weights", "tkdv_learner_get_weights",
            "tkdv_learner_set_weights", "tkdv_sample_sweep", "tkdv_set_launch_cfg", "tkdv_get_launch_cfg",
-           "tkdv_autotune", "tkdv_plan_batch", "tkdv_extremes", "tkdv_sir"]
+           "tkdv_autotune", "tkdv_plan_batch", "tkdv_extremes", "tkdv_sir", "tkdv_plan_mixture_batch"]
 
 _P = C.c_void_p
 lib.tkdv_create.argtypes = [C.c_int, C.POINTER(_P)]
@@ -178,6 +178,9 @@ lib.tkdv_extremes.argtypes = [_P, C.c_int32, C.c_double, _P, C.c_uint64, C.c_uin
                               C.POINTER(C.c_uint64), _P, _P, _P]
 lib.tkdv_sir.argtypes = [_P, C.POINTER(Point), C.c_int, C.POINTER(Plan), C.c_uint64, C.c_uint64, C.c_double,
                          C.c_int, _P, _P, _P, C.POINTER(SirStats), _P]
+lib.tkdv_plan_mixture_batch.argtypes = [_P, C.c_int32, C.POINTER(Point), C.POINTER(Plan), C.POINTER(Mixture),
+                                        C.POINTER(C.c_double), C.c_int32, C.c_int32, C.c_uint64, C.c_double,
+                                        C.POINTER(Plan), C.POINTER(C.c_double), _P]
 lib.tkdv_plan_batch.argtypes = [_P, C.c_int32, C.POINTER(Point), C.c_int, C.c_int32, C.c_uint64, C.c_int32,
                                 C.POINTER(Plan), C.POINTER(C.c_double), _P]
 lib.tkdv_status_str.argtypes = [C.c_int]
@@ -436,6 +439,32 @@ class Context:
                                    xb.ctypes.data_as(C.POINTER(C.c_double)),
                                    _stream(stream) if n else None), self._h)
         return [plans[i] for i in range(n)], xb[:n]
+
+    def plan_mixture_batch(self, points: list, sigma_plans: list, mixes: list, starts=None, n_starts: int = 16,
+                           seed: int = 0, margin: float = 0.0, stream=None) -> tuple[list, np.ndarray]:
+        """log M_mix of many points searched on the GPU (tkdv_plan_mixture_batch):
+        (mixture plans, maximisers [n, 2K_max]).  starts: None or an array
+        (n, n_user, 2K) of caller starts per point."""
+        n = len(points)
+        pts = (Point * max(n, 1))(*points)
+        sps = (Plan * max(n, 1))(*sigma_plans)
+        mxs = (Mixture * max(n, 1))(*mixes)
+        n_user = 0
+        st = None
+        if starts is not None:
+            a = np.asarray(starts, dtype=np.float64)
+            n_user = a.shape[1]
+            st = np.zeros((n, n_user, 2 * KMAX))
+            st[:, :, :a.shape[2]] = a
+            st = np.ascontiguousarray(st)
+        out = (Plan * max(n, 1))()
+        xb = np.zeros((max(n, 1), 2 * KMAX))
+        _check(lib.tkdv_plan_mixture_batch(self._h, n, pts, sps, mxs,
+                                           st.ctypes.data_as(C.POINTER(C.c_double)) if st is not None else None,
+                                           n_user, int(n_starts), int(seed), float(margin), out,
+                                           xb.ctypes.data_as(C.POINTER(C.c_double)),
+                                           _stream(stream) if n else None), self._h)
+        return [out[i] for i in range(n)], xb[:n]
 
     def extremes(self, xhat, K: int, E0: float = 1.0, top_k: int = 10, threshold: float | None = None,
                  per_row: bool = False, stream=None) -> dict:

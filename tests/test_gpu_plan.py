@@ -15,6 +15,7 @@
 * a sampler run with the GPU plan meets no M violation;
 * argument errors.
 """
+import math
 import os
 import sys
 
@@ -162,3 +163,86 @@ def test_plan_batch_argument_errors(T, ctx):
     assert "point 1" in str(e.value)
     plans, xb = ctx.plan_batch([])
     assert plans == [] and xb.shape == (0, 2 * T.KMAX)
+
+
+# ---------------------------------------------------------------------------
+# the learned mixture's rejection constant (tkdv_plan_mixture_batch)
+# ---------------------------------------------------------------------------
+MIXPTS = [(8, 40.0, 20.0, 3), (16, 40.0, 60.0, 4), (32, 40.0, 75.0, 5), (32, 20.0, 300.0, 6), (16, 2.0 * 20, 30.0, 7)]
+
+
+def _mixtures(T):
+    out = []
+    for i, (K, bp, c, seed) in enumerate(MIXPTS):
+        pt = T.make_point(K, 1.0, bp, c, seed=seed, point_id=50 + i)
+        sp = T.plan_point(pt, T.SIGMA)
+        rng = np.random.default_rng(seed)
+        logd = np.log(np.array(sp.sigma2[:K])) + 0.1 * rng.standard_normal(K)
+        V = 0.8 * rng.standard_normal((2 * K, 2)) / np.sqrt(K)
+        out.append((pt, sp, T.make_mixture(K, 0.2, logd, V), oracle.make_mixture(K, 0.2, logd, V)))
+    return out
+
+
+def _oracle_mix_value(pt, sp, mo, x):
+    x = np.asarray(x, dtype=np.float64)
+    x = x / np.linalg.norm(x)
+    lf = oracle.log_ratio(x, pt.E0, pt.beta_p, pt.c32, 1.0, 0)
+    _, lq = oracle.mix_log_q(pt.K, pt.E0, pt.beta_p, pt.c32, sp.alpha_star, mo, x)
+    return lf - lq
+
+
+def test_mixture_constant_against_host_and_oracle(T, ctx):
+    ms = _mixtures(T)
+    plans, xb = ctx.plan_mixture_batch([m[0] for m in ms], [m[1] for m in ms], [m[2] for m in ms], n_starts=16, seed=2)
+    rng = np.random.default_rng(3)
+    for (pt, sp, mx, mo), pl, x in zip(ms, plans, xb):
+        K = pt.K
+        x = x[:2 * K]
+        host, hx = T.plan_mixture(pt, sp, mx, margin=0.0)
+        val = _oracle_mix_value(pt, sp, mo, x)
+        say(f"K={K} beta'={pt.beta_p} c={pt.c32}: GPU log M_mix {pl.log_M:.12f} (source {pl.M_source}, evals "
+            f"{pl.n_optimiser_evals}); host {host.log_M:.12f}; oracle at GPU argmax {val:.12f}")
+        assert pl.proposal == T.MIXTURE
+        assert pl.log_M >= host.log_M - 1e-9 * (1.0 + abs(host.log_M))
+        if pl.M_source == 2:
+            assert abs(val - pl.log_M) < 1e-10 * (1.0 + abs(val))
+            for _ in range(6):
+                v = rng.standard_normal(2 * K)
+                v -= (v @ x) * x
+                v /= np.linalg.norm(v)
+                for h in (1e-3, 1e-5):
+                    assert _oracle_mix_value(pt, sp, mo, x + h * v) <= val + 1e-11
+        else:
+            assert pl.M_source == 3 and pl.log_M == pytest.approx(sp.log_M - sp.log_norm_g - math.log(0.2), abs=1e-3)
+
+
+def test_mixture_constant_caller_starts_margin_and_batch(T, ctx):
+    ms = _mixtures(T)[:3]
+    pts, sps, mxs = [m[0] for m in ms], [m[1] for m in ms], [m[2] for m in ms]
+    hosts = [T.plan_mixture(p, s, m, margin=0.0) for p, s, m in zip(pts, sps, mxs)]
+    K = max(p.K for p in pts)
+    starts = np.zeros((3, 1, 2 * K))
+    for i, (_, hx) in enumerate(hosts):
+        starts[i, 0, :hx.size] = hx
+    a, _ = ctx.plan_mixture_batch(pts, sps, mxs, starts=starts, n_starts=4, seed=1, margin=0.0)
+    for pl, (h, _) in zip(a, hosts):
+        assert pl.log_M >= h.log_M - 1e-12 * (1.0 + abs(h.log_M))   # from the host's maximiser
+    b, _ = ctx.plan_mixture_batch(pts, sps, mxs, n_starts=8, seed=4, margin=0.05)
+    for i in range(3):
+        one, _ = ctx.plan_mixture_batch([pts[i]], [sps[i]], [mxs[i]], n_starts=8, seed=4, margin=0.05)
+        assert one[0].log_M == b[i].log_M
+    c, _ = ctx.plan_mixture_batch(pts, sps, mxs, n_starts=8, seed=4, margin=0.0)
+    for pb, pc in zip(b, c):
+        if pb.M_source == 2:
+            assert pb.log_M == pytest.approx(pc.log_M + math.log1p(0.05), abs=1e-12)
+
+
+def test_mixture_constant_argument_errors(T, ctx):
+    (pt, sp, mx, _), = _mixtures(T)[:1]
+    big = T.make_point(64, 1.0, 40.0, 150.0)
+    with pytest.raises(T.TkdvError):
+        ctx.plan_mixture_batch([big], [T.plan_point(big, T.SIGMA)], [mx])
+    with pytest.raises(T.TkdvError):
+        ctx.plan_mixture_batch([pt], [sp], [mx], starts=np.zeros((1, 1, 2 * pt.K)))    # a zero start
+    with pytest.raises(T.TkdvError):
+        ctx.plan_mixture_batch([pt], [T.plan_point(pt, T.UNIFORM)], [mx])              # not a Sigma plan
