@@ -1,0 +1,74 @@
+"""The standalone synthesis kernel (tkdv_synthesize) at every K and arithmetic.
+
+For rows x^ (seeded unit vectors with a decaying spectrum, FP32 in device
+memory; ragged row counts that leave partial tiles and partial waves), the
+kernel's S3 = sum_j u~_j^3 over the N = 4K grid against the oracle's FP64 sum
+of the same FP32 rows (oracle.grid, scaled back to the unscaled field).  The
+error is measured against S3abs = sum_j |u~_j|^3 (S3 itself can vanish), with
+the bound of each arithmetic: FP32 products 2e-5, BF16x3 1e-4, BF16 2e-2.
+K >= 16 takes the half-table path (grid tiles t and t + T/2 from one table
+fragment, the second with its odd modes negated); K = 8 the whole table.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+BOUND = {"fp32": 2e-5, "bf16x3": 1e-4, "bf16": 2e-2}
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2411_16952_amd import tkdv
+    return tkdv
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    c = T.Context(0)
+    yield c
+    c.close()
+
+
+def _rows(K, n, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((n, 2 * K)) / np.sqrt(1.0 + np.tile(np.arange(K), 2) ** 1.5)
+    return (x / np.linalg.norm(x, axis=1, keepdims=True)).astype(np.float32)
+
+
+@pytest.mark.parametrize("K,n", [(8, 3_001), (16, 2_047), (32, 1_057), (64, 777)])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16"])
+def test_synthesis_against_oracle(T, ctx, K, n, prec):
+    import torch
+    x = _rows(K, n, seed=K + len(prec))
+    s3 = ctx.synthesize(torch.from_numpy(x).cuda(), precision=T.PRECISIONS[prec]).cpu().numpy().astype(np.float64)
+    amp = math.sqrt(2.0 / math.pi)            # E0 = 1: u = amp u~
+    err = 0.0
+    for r in range(n):
+        u = oracle.grid(x[r].astype(np.float64), 1.0, 4 * K) / amp
+        ref, scale = np.sum(u ** 3), np.sum(np.abs(u) ** 3)
+        err = max(err, abs(s3[r] - ref) / scale)
+    print(f"K={K} {prec}: n={n} max |dS3|/S3abs = {err:.2e} (bound {BOUND[prec]:.0e})", flush=True)
+    sys.stdout.flush()
+    assert err <= BOUND[prec]
+
+
+def test_synthesis_edges(T, ctx):
+    import torch
+    x = torch.from_numpy(_rows(16, 1, seed=1)).cuda()
+    one = ctx.synthesize(x, precision=T.BF16X3)
+    assert one.shape == (1,)
+    d = np.zeros((1, 32), dtype=np.float32)
+    d[0, :16] = 1.0 / 4.0                      # the Dirichlet kernel: H3 = (K-1)/(2 sqrt(2 pi K)) at E0 = 1
+    s3 = ctx.synthesize(torch.from_numpy(d).cuda(), precision=T.FP32).cpu().numpy()[0]
+    amp = math.sqrt(2.0 / math.pi)
+    h3 = math.pi / (3 * 64) * amp ** 3 * s3
+    assert h3 == pytest.approx(15 / (2 * math.sqrt(2 * math.pi * 16)), rel=1e-5)
