@@ -1483,11 +1483,9 @@ tkdv_status tkdv_synthesize(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, 
     const int ki = kindex(K);
     hipStream_t st = (hipStream_t)stream;
     std::memset(&ctx->timing, 0, sizeof(ctx->timing));
-    ctx->timing.decide_block = kSynthBlock;
-    HIP_TRY(ctx, hipEventRecord(ctx->ev[0], st));
     HIP_TRY(ctx, launch_synth(K, precision, d_xhat, n, d_s3,
                               precision == TKDV_FP32 ? ctx->phi_f32[ki].p : ctx->phi_hi[ki].p, ctx->phi_lo[ki].p,
-                              ctx->n_cu, st, &ctx->timing.decide_grid));
+                              ctx->n_cu, st, ctx->ev[0], &ctx->timing.decide_grid, &ctx->timing.decide_block));
     HIP_TRY(ctx, hipEventRecord(ctx->ev[1], st));
     HIP_TRY(ctx, hipEventSynchronize(ctx->ev[1]));
     float ms = 0.0f;

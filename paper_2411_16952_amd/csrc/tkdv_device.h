@@ -175,10 +175,7 @@ __device__ __forceinline__ void split_bf16(const float (&x)[K], bf16x8 (&bh)[K /
 
 // Sum over this lane's grid values of u~^3 (u~ = unscaled synthesis), with
 // the products in the requested arithmetic (FP32 reads x, BF16 reads bh/bl).
-// TWO_CHAINS accumulates even and odd k-steps of the BF16 paths in separate
-// registers (two independent dependency chains on the matrix pipe), summed
-// before the cube.
-template <int K, int PREC, bool TWO_CHAINS = false>
+template <int K, int PREC>
 __device__ __forceinline__ float cube_sum_ops(const float (&x)[K], const bf16x8 (&bh)[K / 8],
                                               const bf16x8 (&bl)[K / 8], const char *lds_hi,
                                               const char *lds_lo, int lane)
@@ -206,22 +203,17 @@ __device__ __forceinline__ float cube_sum_ops(const float (&x)[K], const bf16x8 
         // at K = 64 a full unroll keeps every grid tile's operands live (spills)
 #pragma unroll(K >= 64 ? 2 : K / 8)
         for (int t = 0; t < K / 8; ++t) {
-            f32x16 acc = {}, acc2 = {};
+            f32x16 acc = {};
 #pragma unroll
             for (int s = 0; s < K / 8; ++s) {
                 const int idx = (t * (K / 8) + s) * kWave + lane;
                 const bf16x8 ah = th[idx];
-                f32x16 &a = (TWO_CHAINS && (s & 1)) ? acc2 : acc;
                 if constexpr (PREC == PREC_BF16X3) {
                     const bf16x8 al = tl[idx];
-                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[s], a, 0, 0, 0);
-                    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[s], a, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[s], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[s], acc, 0, 0, 0);
                 }
-                a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[s], a, 0, 0, 0);
-            }
-            if constexpr (TWO_CHAINS) {
-#pragma unroll
-                for (int v = 0; v < 16; ++v) acc[v] += acc2[v];
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[s], acc, 0, 0, 0);
             }
 #pragma unroll
             for (int v = 0; v < 16; ++v) s3 = __builtin_fmaf(acc[v] * acc[v], acc[v], s3);
@@ -230,106 +222,13 @@ __device__ __forceinline__ float cube_sum_ops(const float (&x)[K], const bf16x8 
     return s3;
 }
 
-// The same sum for the standalone synthesis kernel, with half the tables.
-// Shifting the grid by half a period (N/2 points, i.e. T/2 grid tiles) turns
-// mode k's cos/sin row into (-1)^k times itself, so grid tile t + T/2 is
-// tile t with the odd modes negated: one table fragment read from LDS feeds
-// the products of both tiles, the second after a sign flip of its odd-mode
-// entries.  In a 16-byte fragment of k-step s, entry e is mode 8s + e + 1
-// (odd for even e, the low half of each 32-bit word); in an FP32 fragment of
-// k-step q, entry e is mode 4q + e + 1.  The k-steps run outermost inside
-// groups of TP tile pairs whose 2 TP accumulators are live together, so
-// consecutive matrix instructions update different accumulators.  K = 8 (a
-// single grid tile) reads the whole table.
-typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ bf16x8 negate_odd_modes(bf16x8 a)
-{
-    u32x4_t u = __builtin_bit_cast(u32x4_t, a);
-    u ^= 0x00008000u;
-    return __builtin_bit_cast(bf16x8, u);
-}
-
-template <int K>
-constexpr int synth_table_tiles() { return K / 8 >= 2 ? K / 16 : 1; }
-
 template <int K, int PREC>
-__device__ __forceinline__ float cube_sum_os(const float (&x)[K], const bf16x8 (&bh)[K / 8],
-                                             const bf16x8 (&bl)[K / 8], const char *lds_hi, const char *lds_lo,
-                                             int lane)
-{
-    constexpr int H = synth_table_tiles<K>();  // table tiles read
-    constexpr bool PAIR = K / 8 >= 2;          // each also stands for tile t + T/2
-    constexpr int TP = H < 2 ? H : 2;          // table tiles per group
-    constexpr int NA = PAIR ? 2 * TP : TP;     // live accumulators
-    float s3 = 0.0f;
-#pragma unroll 1
-    for (int g = 0; g < H; g += TP) {
-        f32x16 acc[NA];
-#pragma unroll
-        for (int u = 0; u < NA; ++u) acc[u] = f32x16{};
-        if constexpr (PREC == PREC_FP32) {
-            const float4 *tab = reinterpret_cast<const float4 *>(lds_hi);
-#pragma unroll
-            for (int q = 0; q < K / 4; ++q)
-#pragma unroll
-                for (int u = 0; u < TP; ++u) {
-                    const float4 a = tab[((g + u) * (K / 4) + q) * kWave + lane];
-                    f32x16 &c0 = acc[PAIR ? 2 * u : u];
-                    c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, x[4 * q + 0], c0, 0, 0, 0);
-                    c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, x[4 * q + 1], c0, 0, 0, 0);
-                    c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, x[4 * q + 2], c0, 0, 0, 0);
-                    c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, x[4 * q + 3], c0, 0, 0, 0);
-                    if constexpr (PAIR) {
-                        f32x16 &c1 = acc[2 * u + 1];
-                        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.x, x[4 * q + 0], c1, 0, 0, 0);
-                        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, x[4 * q + 1], c1, 0, 0, 0);
-                        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.z, x[4 * q + 2], c1, 0, 0, 0);
-                        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, x[4 * q + 3], c1, 0, 0, 0);
-                    }
-                }
-        } else {
-            const bf16x8 *th = reinterpret_cast<const bf16x8 *>(lds_hi);
-            const bf16x8 *tl = reinterpret_cast<const bf16x8 *>(lds_lo);
-#pragma unroll
-            for (int s = 0; s < K / 8; ++s)
-#pragma unroll
-                for (int u = 0; u < TP; ++u) {
-                    const int idx = ((g + u) * (K / 8) + s) * kWave + lane;
-                    const bf16x8 ah = th[idx];
-                    f32x16 &c0 = acc[PAIR ? 2 * u : u];
-                    if constexpr (PREC == PREC_BF16X3) {
-                        const bf16x8 al = tl[idx];
-                        c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[s], c0, 0, 0, 0);
-                        if constexpr (PAIR)
-                            acc[2 * u + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                negate_odd_modes(al), bh[s], acc[2 * u + 1], 0, 0, 0);
-                        c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[s], c0, 0, 0, 0);
-                        if constexpr (PAIR)
-                            acc[2 * u + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                negate_odd_modes(ah), bl[s], acc[2 * u + 1], 0, 0, 0);
-                    }
-                    c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[s], c0, 0, 0, 0);
-                    if constexpr (PAIR)
-                        acc[2 * u + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(negate_odd_modes(ah), bh[s],
-                                                                                 acc[2 * u + 1], 0, 0, 0);
-                }
-        }
-#pragma unroll
-        for (int u = 0; u < NA; ++u)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) s3 = __builtin_fmaf(acc[u][v] * acc[u][v], acc[u][v], s3);
-    }
-    return s3;
-}
-
-template <int K, int PREC, bool TWO_CHAINS = false>
 __device__ __forceinline__ float synth_cube_sum(const float (&x)[K], const char *lds_hi,
                                                 const char *lds_lo, int lane)
 {
     bf16x8 bh[K / 8], bl[K / 8];
     if constexpr (PREC != PREC_FP32) split_bf16<K, PREC>(x, bh, bl);
-    return cube_sum_ops<K, PREC, TWO_CHAINS>(x, bh, bl, lds_hi, lds_lo, lane);
+    return cube_sum_ops<K, PREC>(x, bh, bl, lds_hi, lds_lo, lane);
 }
 
 // log a = log f/(M g) in FP32 from t and S3 = sum_j u~_j^3 (both lanes identical).

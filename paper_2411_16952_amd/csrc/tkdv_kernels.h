@@ -24,8 +24,11 @@ hipError_t launch_materialize(int K, int prop, const KernelArgs &a, const int *p
 hipError_t launch_finalize(const KernelArgs &a, const unsigned long long *seg_cnt,
                            const unsigned long long *seg_base, const SegStats *seg_stats, PointResult *res,
                            hipStream_t st);
+// the standalone synthesis (tkdv_synth.hip); ev_start (optional) is recorded
+// on st immediately before the kernel launch
 hipError_t launch_synth(int K, int prec, const float *xhat, unsigned long long n, float *s3, const void *phi_hi,
-                        const void *phi_lo, int n_cu, hipStream_t st, int *grid_out);
+                        const void *phi_lo, int n_cu, hipStream_t st, hipEvent_t ev_start, int *grid_out,
+                        int *block_out);
 hipError_t launch_window_advance(DevPoint *pts, const DevCounters *cnt, const PointResult *res, SweepState *sw,
                                  int n_points, unsigned long long *active, hipStream_t st);
 hipError_t launch_fill_u32(void *p, unsigned long long n_words, uint32_t v, hipStream_t st);

@@ -954,120 +954,6 @@ hipError_t launch_window_advance(DevPoint *pts, const DevCounters *cnt, const Po
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// k_synth: the spectral-to-grid synthesis on its own, with x^ read from HBM.
-// Row r of x^ (2K floats) -> S3[r] = sum_j u~_j^3 over the N = 4K grid,
-// u~ = Phi^T x^ (unscaled), products in the requested arithmetic.  Persistent
-// workgroups keep the synthesis tables in LDS and loop over 32-row tiles;
-// lane p / p + 32 read the cos / sin half of row p (256 contiguous bytes at
-// K = 64) straight into the matrix-operand registers.
-// ---------------------------------------------------------------------------
-template <int K, int PREC, int BLOCK>
-__global__ void __launch_bounds__(BLOCK) k_synth(const float *__restrict__ xhat, unsigned long long n,
-                                                 float *__restrict__ s3_out, const void *phi_hi,
-                                                 const void *phi_lo)
-{
-    extern __shared__ __attribute__((aligned(16))) char lds[];
-    // the first synth_table_tiles<K>() grid tiles of the tables (cube_sum_os)
-    constexpr int tab = (PREC == PREC_FP32 ? f32_table_bytes<K>() : bf16_table_bytes<K>()) /
-                        (K / 8) * synth_table_tiles<K>();
-    {
-        const uint4 *s0 = reinterpret_cast<const uint4 *>(phi_hi);
-        uint4 *d = reinterpret_cast<uint4 *>(lds);
-        for (int v = threadIdx.x; v < tab / 16; v += BLOCK) d[v] = s0[v];
-        if constexpr (PREC == PREC_BF16X3) {
-            const uint4 *s1 = reinterpret_cast<const uint4 *>(phi_lo);
-            for (int v = threadIdx.x; v < tab / 16; v += BLOCK) d[tab / 16 + v] = s1[v];
-        }
-    }
-    __syncthreads();
-    const int lane = threadIdx.x & 63, half = lane >> 5, pl = lane & 31;
-    const unsigned long long n_tiles = (n + kTile - 1) / kTile;
-    const unsigned long long waves = (unsigned long long)gridDim.x * (BLOCK / kWave);
-    unsigned long long tile = (unsigned long long)blockIdx.x * (BLOCK / kWave) + (threadIdx.x >> 6);
-    // rows of the next tile are loaded while the current tile is on the matrix
-    // cores, where the register budget allows it (not beside the four live
-    // K = 32 FP32 and BF16x3 accumulators)
-    constexpr bool prefetch = BLOCK <= 512 && !(K == 32 && PREC != PREC_BF16);
-    float4 nxt[K / 4];
-    auto load_tile = [&](unsigned long long tl) {
-        const unsigned long long row = tl * kTile + pl;
-        const unsigned long long r = (tl < n_tiles && row < n) ? row : 0ull;
-        const float4 *src = reinterpret_cast<const float4 *>(xhat + r * (2 * K) + half * K);
-#pragma unroll
-        for (int q = 0; q < K / 4; ++q) nxt[q] = src[q];
-    };
-    if (prefetch && tile < n_tiles) load_tile(tile);
-    for (; tile < n_tiles; tile += waves) {
-        if (!prefetch) load_tile(tile);
-        const unsigned long long row = tile * kTile + pl;
-        const bool valid = row < n;
-        float x[K];
-#pragma unroll
-        for (int q = 0; q < K / 4; ++q) {
-            x[4 * q + 0] = nxt[q].x;
-            x[4 * q + 1] = nxt[q].y;
-            x[4 * q + 2] = nxt[q].z;
-            x[4 * q + 3] = nxt[q].w;
-        }
-        if (prefetch && tile + waves < n_tiles) load_tile(tile + waves);
-        bf16x8 bh[K / 8], bl[K / 8];
-        if constexpr (PREC != PREC_FP32) split_bf16<K, PREC>(x, bh, bl);
-        const float s3l = cube_sum_os<K, PREC>(x, bh, bl, lds, lds + tab, lane);
-        const float s3 = s3l + xor32(s3l);
-        if (valid && half == 0) s3_out[row] = s3;
-    }
-}
-
-// Workgroup size: 8 waves, 4 at K = 64 (two workgroups per CU with the
-// halved tables in LDS; measured fastest there).
-template <int K>
-constexpr int synth_block() { return K == 64 ? kSynthBlock / 2 : kSynthBlock; }
-
-template <int K, int PREC>
-constexpr int synth_lds_bytes()
-{
-    constexpr int tab = (PREC == PREC_FP32 ? f32_table_bytes<K>() : bf16_table_bytes<K>()) / (K / 8) *
-                        synth_table_tiles<K>();
-    return PREC == PREC_BF16X3 ? 2 * tab : tab;
-}
-
-template <int K, int PREC>
-static hipError_t launch_synth_t(const float *xhat, unsigned long long n, float *s3, const void *phi_hi,
-                                 const void *phi_lo, int n_cu, hipStream_t st, int *grid_out)
-{
-    constexpr int lds = synth_lds_bytes<K, PREC>();
-    constexpr int B = synth_block<K>();
-    auto kern = k_synth<K, PREC, B>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
-    int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, B, lds);
-    if (e != hipSuccess) return e;
-    if (per_cu < 1) per_cu = 1;
-    const unsigned long long tiles = (n + kTile - 1) / kTile;
-    unsigned long long grid = (unsigned long long)per_cu * n_cu;
-    const unsigned long long want = (tiles + B / kWave - 1) / (B / kWave);
-    if (want < grid) grid = want;
-    if (grid < 1) grid = 1;
-    if (grid_out) *grid_out = (int)grid;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(B), lds, st, xhat, n, s3, phi_hi, phi_lo);
-    return hipGetLastError();
-}
-
-hipError_t launch_synth(int K, int prec, const float *xhat, unsigned long long n, float *s3, const void *phi_hi,
-                        const void *phi_lo, int n_cu, hipStream_t st, int *grid_out)
-{
-#define TKDV_DISPATCH_S(KK, PR) \
-    if (K == KK && prec == PR) return launch_synth_t<KK, PR>(xhat, n, s3, phi_hi, phi_lo, n_cu, st, grid_out);
-    TKDV_DISPATCH_S(8, PREC_FP32) TKDV_DISPATCH_S(8, PREC_BF16) TKDV_DISPATCH_S(8, PREC_BF16X3)
-    TKDV_DISPATCH_S(16, PREC_FP32) TKDV_DISPATCH_S(16, PREC_BF16) TKDV_DISPATCH_S(16, PREC_BF16X3)
-    TKDV_DISPATCH_S(32, PREC_FP32) TKDV_DISPATCH_S(32, PREC_BF16) TKDV_DISPATCH_S(32, PREC_BF16X3)
-    TKDV_DISPATCH_S(64, PREC_FP32) TKDV_DISPATCH_S(64, PREC_BF16) TKDV_DISPATCH_S(64, PREC_BF16X3)
-#undef TKDV_DISPATCH_S
-    return hipErrorInvalidValue;
-}
-
 __global__ void k_fill_u32(uint32_t *p, unsigned long long n, uint32_t v)
 {
     for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;

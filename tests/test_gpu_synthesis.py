@@ -6,8 +6,10 @@ kernel's S3 = sum_j u~_j^3 over the N = 4K grid against the oracle's FP64 sum
 of the same FP32 rows (oracle.grid, scaled back to the unscaled field).  The
 error is measured against S3abs = sum_j |u~_j|^3 (S3 itself can vanish), with
 the bound of each arithmetic: FP32 products 2e-5, BF16x3 1e-4, BF16 2e-2.
-K >= 16 takes the half-table path (grid tiles t and t + T/2 from one table
-fragment, the second with its odd modes negated); K = 8 the whole table.
+K >= 16 takes the half-period form (on the first half of the grid the even-
+and odd-mode syntheses E, O; the second half holds E - O, and the cubes of
+both halves sum to 2E(E^2 + 3O^2)); K = 8 the plain product.  Edge cases: one
+row, one partial tile, rows that end inside the last wave's tile.
 """
 import math
 import sys
@@ -72,3 +74,18 @@ def test_synthesis_edges(T, ctx):
     amp = math.sqrt(2.0 / math.pi)
     h3 = math.pi / (3 * 64) * amp ** 3 * s3
     assert h3 == pytest.approx(15 / (2 * math.sqrt(2 * math.pi * 16)), rel=1e-5)
+
+
+@pytest.mark.parametrize("K", [32, 64])
+@pytest.mark.parametrize("n", [1, 33, 4099])
+def test_synthesis_small_and_partial(T, ctx, K, n):
+    import torch
+    x = _rows(K, n, seed=100 + K + n)
+    amp = math.sqrt(2.0 / math.pi)
+    for prec in ("bf16x3", "fp32"):
+        s3 = ctx.synthesize(torch.from_numpy(x).cuda(), precision=T.PRECISIONS[prec]).cpu().numpy()
+        err = 0.0
+        for r in range(n):
+            u = oracle.grid(x[r].astype(np.float64), 1.0, 4 * K) / amp
+            err = max(err, abs(float(s3[r]) - np.sum(u ** 3)) / np.sum(np.abs(u) ** 3))
+        assert err <= BOUND[prec], (K, n, prec, err)
