@@ -180,6 +180,22 @@ def synthesis_bench(args) -> int:
                      "mfma_frac_executed": executed / sec / peak, "dense_equivalent_frac": dense / sec / peak,
                      "grid": ctx.timing()["decide_grid"], "block": ctx.timing()["decide_block"]}
         print(f"synthesis {name}: {avg:.4f} ms", file=sys.stderr, flush=True)
+    # the same synthesis with x^ drawn in registers instead of read (Philox, Box-Muller, Sigma
+    # scaling, projection): the sampler's decision kernel at this point, no samples stored
+    n_gen = 16 * n
+    gen_ms = []
+    for rep in range(1 + max(args.steps, 3)):
+        ctx.sample(pt, n_gen, plan=plan, precision=T.BF16X3)
+        if rep:
+            gen_ms.append(ctx.timing()["decide_ms"])
+    g_ms = sum(gen_ms) / len(gen_ms)
+    dense_gen = 3 * 2.0 * (2 * K) * (4 * K) * n_gen
+    res["bf16x3_from_philox"] = {
+        "ms": g_ms, "proposals": n_gen, "rows_per_s": n_gen / (g_ms * 1e-3),
+        "mfma_frac_executed": dense_gen / (g_ms * 1e-3) / 2.5e15,
+        "alu_frac": alu_ops_per_proposal(K) * n_gen / (g_ms * 1e-3) / ALU_OPS_PER_S,
+        "kernel": "k_decide (dense product, decisions included)"}
+    print(f"synthesis from Philox (k_decide, {n_gen} proposals): {g_ms:.3f} ms", file=sys.stderr, flush=True)
     r = res["bf16x3"]
     # measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated), if taken on these sources
     traffic = None
