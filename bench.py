@@ -64,38 +64,47 @@ def alu_roof(achieved: float, **extra) -> dict:
 
 
 def alu_ops_per_proposal(K: int, proposal: str = "sigma", precision: str = "bf16x3") -> float:
-    """Algorithmic ALU operations of one proposal (each add, multiply, FMA,
-    compare, conversion, bit operation or transcendental counts 1):
-      Philox4x32-10: K/2 + 1 blocks x 10 rounds x (2 products x 2 halves + 4 xor) = 80 (K/2 + 1)
-      word -> uniform (2K + 1 words, convert + scale)                          = 2 (2K + 1)
-      Box-Muller: K pairs x (ln, x-2, sqrt, sin, cos, 2 products)              = 7 K
-      Sigma scaling (2K products; uniform proposal: none)                      = 2 K
-      |x|^2 (2K FMA), 1/sqrt, projection (2K products), t = sum k^2 s_k (4K)   = 8 K + 1
-      synthesis operand split (BF16x3: round, subtract, round per coordinate;
-        BF16: round; FP32: none)                                               = 6 K / 2 K / 0
-      cube-and-sum over the N = 4K grid values (square, FMA)                   = 8 K
-      log U, log a, comparison                                                 = 12
-    The synthesis products themselves run on the matrix cores.
-    The learned mixture adds (mixture_extra_ops): component choice from one
-    word (6), the Box-Muller pair eta (2 conversions + 7), the low-rank part
-    of the draw (2 FMA per coordinate: 4K), Q = X^T A X (2K), and per shift
-    j < S = 32: the 2x2 quadratic form of y_j and r_j (6), log2, running
-    minimum, then exp2 of K (l_min - l_j) and its sum (4) = 12 S, plus the
-    final log-sum and the two-term mixture (20)."""
-    split = {"bf16x3": 6 * K, "bf16": 2 * K, "fp32": 0}[precision]
+    """Vector-ALU issue slots one proposal needs: each operation the method
+    performs, counted as the gfx950 instructions that carry it (a 32x32 -> 64-bit
+    product, a three-input XOR, an FMA: one slot each; the transcendentals
+    log2, exp2, sqrt, 1/sqrt, sin, cos: one issue slot each, their execution
+    overlapping the vector ALU), so that the count compares with the issue
+    peak ALU_OPS_PER_S:
+      Philox4x32-10: K/2 + 1 blocks x 10 rounds x (2 products + 2 three-input XORs)  = 40 (K/2 + 1)
+      word -> uniform (2K + 1 words, convert + scale)                               = 2 (2K + 1)
+      Box-Muller: K pairs x (log2, sqrt, sin, cos; log scale, 2 products)           = 7 K
+      Sigma scaling (2K products; uniform proposal: none)                           = 2 K
+      |x|^2 and t = sum k^2 s_k (square, add, FMA per coordinate), lane sums,
+        1/sqrt, t scaling                                                           = 6 K + 7
+      synthesis operands (BF16x3: round pair, two unpacks, two subtractions, round
+        pair per two coordinates; BF16: round pair; FP32: none)                     = 6 K / K / 0
+      sum of cubes over the N = 4K grid values (half-period form: 4 per pair)       = 8 K
+      lane sum and scaling of S3, log a (with log1p), log U, exp2, window edges,
+        comparisons                                                                 = 24
+    The synthesis products themselves run on the matrix cores.  The learned
+    mixture adds mixture_extra_ops."""
+    split = {"bf16x3": 6 * K, "bf16": K, "fp32": 0}[precision]
     scale = 2 * K if proposal in ("sigma", "mixture") else 0
-    base = 80 * (K / 2 + 1) + 2 * (2 * K + 1) + 7 * K + scale + 8 * K + 1 + split + 8 * K + 12
+    base = 40 * (K / 2 + 1) + 2 * (2 * K + 1) + 7 * K + scale + 6 * K + 7 + split + 8 * K + 24
     return base + (mixture_extra_ops(K) if proposal == "mixture" else 0)
 
 
 def mixture_extra_ops(K: int, S: int = 32) -> float:
-    return 6 + 9 + 4 * K + 2 * K + 12 * S + 20
+    """Issue slots the learned mixture adds per proposal: component choice from
+    one word (6); the Box-Muller pair eta (2 conversions, 4 transcendentals, 3:
+    9); the low-rank part of the draw (2 FMA per coordinate: 4K); Q = X^T A X
+    (2K); per shift j < S: the 2x2 quadratic form of y_j and r_j (6), log2,
+    running minimum, exp2 and its sum (4) = 10 S; the final log-sum and the
+    two-term mixture (20)."""
+    return 6 + 9 + 4 * K + 2 * K + 10 * S + 20
 
 
 def mfma_flops_per_proposal(K: int, precision: str = "bf16x3", proposal: str = "sigma") -> float:
-    """Synthesis u~ = Phi^T x^ on the N = 4K grid: 2 x 2K x N flops per product
-    term; the mixture adds y = (R_j A V)^T x for S = 32 shifts x rank 2 rows."""
-    rows = 4 * K + (64 if proposal == "mixture" else 0)
+    """Matrix flops executed per proposal: the synthesis in the half-period form
+    (K >= 16: the even- and odd-mode products on half the grid, 2 x 2K x N/2
+    flops per product term, half the plain product's 2 x 2K x N; K = 8 the plain
+    product); the mixture adds y = (R_j A V)^T x for S = 32 shifts x rank 2 rows."""
+    rows = (2 * K if K >= 16 else 4 * K) + (64 if proposal == "mixture" else 0)
     return {"bf16x3": 3, "bf16": 1, "fp32": 1}[precision] * 2 * (2 * K) * rows
 
 
@@ -181,7 +190,7 @@ def synthesis_bench(args) -> int:
                      "grid": ctx.timing()["decide_grid"], "block": ctx.timing()["decide_block"]}
         print(f"synthesis {name}: {avg:.4f} ms", file=sys.stderr, flush=True)
     # the same synthesis with x^ drawn in registers instead of read (Philox, Box-Muller, Sigma
-    # scaling, projection): the sampler's decision kernel at this point, no samples stored
+    # scaling): the sampler's decision kernel at this point, no samples stored
     n_gen = 16 * n
     gen_ms = []
     for rep in range(1 + max(args.steps, 3)):
@@ -189,12 +198,11 @@ def synthesis_bench(args) -> int:
         if rep:
             gen_ms.append(ctx.timing()["decide_ms"])
     g_ms = sum(gen_ms) / len(gen_ms)
-    dense_gen = 3 * 2.0 * (2 * K) * (4 * K) * n_gen
     res["bf16x3_from_philox"] = {
         "ms": g_ms, "proposals": n_gen, "rows_per_s": n_gen / (g_ms * 1e-3),
-        "mfma_frac_executed": dense_gen / (g_ms * 1e-3) / 2.5e15,
+        "mfma_frac_executed": mfma_flops_per_proposal(K) * n_gen / (g_ms * 1e-3) / 2.5e15,
         "alu_frac": alu_ops_per_proposal(K) * n_gen / (g_ms * 1e-3) / ALU_OPS_PER_S,
-        "kernel": "k_decide (dense product, decisions included)"}
+        "kernel": "k_decide (half-period synthesis, decisions included)"}
     print(f"synthesis from Philox (k_decide, {n_gen} proposals): {g_ms:.3f} ms", file=sys.stderr, flush=True)
     r = res["bf16x3"]
     # measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated), if taken on these sources

@@ -326,11 +326,12 @@ tkdv_status run(tkdv_ctx *ctx, Call &call, int precision, int proposal, float *d
     }
     const int *d_plist = reinterpret_cast<const int *>(ctx->plist.p);
     std::memset(&ctx->timing, 0, sizeof(ctx->timing));
-    ctx->timing.decide_block = proposal == TKDV_PROP_MIXTURE ? kMixBlock : kBlock;
     HIP_TRY(ctx, hipEventRecord(ctx->ev[0], st));
     for (int ki = 0; ki < 4; ++ki) {
         if (call.plist_n[ki] == 0) continue;
         const int K = 8 << ki;
+        // the largest K of the call sets the reported workgroup size
+        ctx->timing.decide_block = proposal == TKDV_PROP_MIXTURE ? kMixBlock : decide_block(K);
         a.phi_hi = precision == TKDV_FP32 ? ctx->phi_f32[ki].p : ctx->phi_hi[ki].p;
         a.phi_lo = ctx->phi_lo[ki].p;
         unsigned long long tiles = 0;
@@ -738,7 +739,8 @@ tkdv_status sweep(tkdv_ctx *ctx, int np, const tkdv_point *pts, const tkdv_plan 
         }
     }
     std::memset(&ctx->timing, 0, sizeof(ctx->timing));
-    ctx->timing.decide_block = kBlock;
+    for (int ki = 0; ki < 4; ++ki)  // the largest K of the sweep sets the reported workgroup size
+        if (!by_k[ki].empty()) ctx->timing.decide_block = decide_block(8 << ki);
     unsigned long long *poll = reinterpret_cast<unsigned long long *>(ctx->h_poll);
     tkdv_status st_out = TKDV_OK;
     int windows = 0;

@@ -231,6 +231,240 @@ __device__ __forceinline__ float synth_cube_sum(const float (&x)[K], const char 
     return cube_sum_ops<K, PREC>(x, bh, bl, lds_hi, lds_lo, lane);
 }
 
+// ---------------------------------------------------------------------------
+// Half-period form of the synthesis (K >= 16).  Shifting the grid
+// xi_j = -pi + 2 pi j/N by half a period (N/2 points, T/2 of the T = N/32
+// grid tiles) multiplies mode k's cos and sin rows by (-1)^k.  With E and O
+// the syntheses over the even and over the odd modes on grid tile t < T/2,
+// tile t holds u~ = E + O and tile t + T/2 holds u~ = E - O, so that
+//     u~(t)^3 + u~(t + T/2)^3 = 2 E (E^2 + 3 O^2):
+// two products over half the modes each give both tiles, half the matrix
+// work of the plain product for the same sum of cubes.
+//   BF16 tables (hi, lo): fragment ((t * K/16 + s) * 2 + p) * 64 + l holds for
+//   lane l the 8 entries Phi(block l/32, mode 16 s + 2 e + 2 - p) at grid
+//   point 32 t + l%32 (p = 0 even modes, p = 1 odd modes), t < T/2, gathered
+//   from the plain tables when a workgroup stages them.
+//   FP32 table: the first T/2 grid tiles of the plain table (each FP32 matrix
+//   instruction takes one mode; the parity selects the accumulator).
+// ---------------------------------------------------------------------------
+template <int K>
+__host__ __device__ constexpr int eo_steps() { return K / 16; }  // k-steps of one parity = tile pairs
+
+// bytes of one staged table (hi or lo)
+template <int K, int PREC>
+__host__ __device__ constexpr int eo_table_bytes()
+{
+    return (PREC == PREC_FP32 ? f32_table_bytes<K>() : bf16_table_bytes<K>()) / 2;
+}
+
+// Even-mode (p = 0) or odd-mode (p = 1) fragment from two consecutive k-step
+// fragments a, b of the plain BF16 table (modes 8 s + 1 .. 8 s + 16): the even
+// modes are their odd entries, the high halves of the 32-bit words.
+__device__ __forceinline__ uint4 gather_parity(uint4 a, uint4 b, int p)
+{
+    if (p == 0)
+        return make_uint4((a.x >> 16) | (a.y & 0xffff0000u), (a.z >> 16) | (a.w & 0xffff0000u),
+                          (b.x >> 16) | (b.y & 0xffff0000u), (b.z >> 16) | (b.w & 0xffff0000u));
+    return make_uint4((a.x & 0xffffu) | (a.y << 16), (a.z & 0xffffu) | (a.w << 16), (b.x & 0xffffu) | (b.y << 16),
+                      (b.z & 0xffffu) | (b.w << 16));
+}
+
+// A workgroup of BLOCK threads permutes n_tiles row tiles of plain-layout
+// BF16 fragments (tile t, k-step s: modes 8 s + 1 .. 8 s + 8) into the parity
+// layout: fragment ((t * K/16 + s) * 2 + p) * 64 + l.
+template <int K, int BLOCK>
+__device__ __forceinline__ void stage_parity_frags(uint4 *dst, const uint4 *src, int n_tiles)
+{
+    constexpr int S = eo_steps<K>();
+    const int n = n_tiles * (K / 8) * kWave;
+    for (int v = threadIdx.x; v < n; v += BLOCK) {
+        const int l = v % kWave, p = (v / kWave) % 2, s = (v / (2 * kWave)) % S, t = v / (2 * kWave * S);
+        const int f = (t * (K / 8) + 2 * s) * kWave + l;  // plain fragment of k-step 2s
+        dst[v] = gather_parity(src[f], src[f + kWave], p);
+    }
+}
+
+// A workgroup of BLOCK threads stages the half-period tables: hi at lds, lo
+// (BF16x3) at lds + eo_table_bytes.
+template <int K, int PREC, int BLOCK>
+__device__ __forceinline__ void stage_eo_tables(char *lds, const void *phi_hi, const void *phi_lo)
+{
+    constexpr int tab = eo_table_bytes<K, PREC>();
+    uint4 *d = reinterpret_cast<uint4 *>(lds);
+    if constexpr (PREC == PREC_FP32) {
+        const uint4 *s0 = reinterpret_cast<const uint4 *>(phi_hi);
+        for (int v = threadIdx.x; v < tab / 16; v += BLOCK) d[v] = s0[v];
+    } else {
+        stage_parity_frags<K, BLOCK>(d, reinterpret_cast<const uint4 *>(phi_hi), eo_steps<K>());
+        if constexpr (PREC == PREC_BF16X3)
+            stage_parity_frags<K, BLOCK>(d + tab / 16, reinterpret_cast<const uint4 *>(phi_lo), eo_steps<K>());
+    }
+}
+
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+// Two floats as packed BF16: hi = RNE(v), lo = RNE(v - hi) (the subtraction
+// is exact: hi is v rounded to its top 16 bits).
+__device__ __forceinline__ uint32_t pack_hi(float v0, float v1)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){v0, v1}, bf16x2_t));
+}
+__device__ __forceinline__ uint32_t pack_lo(float v0, float v1, uint32_t hi)
+{
+    const float h0 = __uint_as_float(hi << 16), h1 = __uint_as_float(hi & 0xffff0000u);
+    return pack_hi(v0 - h0, v1 - h1);
+}
+
+// This lane's operands by parity (x[j] is the coordinate of mode j + 1):
+// e*[s] entry e is mode 16 s + 2 e + 2, o*[s] entry e is mode 16 s + 2 e + 1.
+// BF16 products fill eh and oh only.
+template <int K, int PREC>
+__device__ __forceinline__ void split_eo(const float (&x)[K], bf16x8 (&eh)[K / 16], bf16x8 (&el)[K / 16],
+                                         bf16x8 (&oh)[K / 16], bf16x8 (&ol)[K / 16])
+{
+#pragma unroll
+    for (int s = 0; s < K / 16; ++s) {
+        u32x4_t weh, wel, woh, wol;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int j = 16 * s + 4 * w;
+            weh[w] = pack_hi(x[j + 1], x[j + 3]);
+            woh[w] = pack_hi(x[j], x[j + 2]);
+            if constexpr (PREC == PREC_BF16X3) {
+                wel[w] = pack_lo(x[j + 1], x[j + 3], weh[w]);
+                wol[w] = pack_lo(x[j], x[j + 2], woh[w]);
+            }
+        }
+        eh[s] = __builtin_bit_cast(bf16x8, weh);
+        oh[s] = __builtin_bit_cast(bf16x8, woh);
+        if constexpr (PREC == PREC_BF16X3) {
+            el[s] = __builtin_bit_cast(bf16x8, wel);
+            ol[s] = __builtin_bit_cast(bf16x8, wol);
+        }
+    }
+}
+
+// hi operands only (BF16 products)
+template <int K>
+__device__ __forceinline__ void split_eo_hi(const float (&x)[K], bf16x8 (&eh)[K / 16], bf16x8 (&oh)[K / 16])
+{
+#pragma unroll
+    for (int s = 0; s < K / 16; ++s) {
+        u32x4_t weh, woh;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int j = 16 * s + 4 * w;
+            weh[w] = pack_hi(x[j + 1], x[j + 3]);
+            woh[w] = pack_hi(x[j], x[j + 2]);
+        }
+        eh[s] = __builtin_bit_cast(bf16x8, weh);
+        oh[s] = __builtin_bit_cast(bf16x8, woh);
+    }
+}
+
+// sum over the pair's grid values of u~^3 = 2 E (E^2 + 3 O^2), elementwise
+// (the factor 2 is applied by the caller)
+__device__ __forceinline__ float pair_cubes(const f32x16 &ce, const f32x16 &co, float s)
+{
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const float e = ce[v], o = co[v];
+        const float q = __builtin_fmaf(3.0f * o, o, e * e);
+        s = __builtin_fmaf(e, q, s);
+    }
+    return s;
+}
+
+// S3 over this lane's grid values in the half-period form, FP32 products; G
+// tile pairs per group have their accumulators live together.
+template <int K, int G>
+__device__ __forceinline__ float cube_sum_eo_f32(const float (&x)[K], const char *lds, int lane)
+{
+    constexpr int P = eo_steps<K>();
+    const float4 *tab = reinterpret_cast<const float4 *>(lds);
+    float s3 = 0.0f;
+#pragma unroll 1
+    for (int g = 0; g < P; g += G) {
+        f32x16 ce[G], co[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) ce[u] = co[u] = f32x16{};
+#pragma unroll
+        for (int q = 0; q < K / 4; ++q)
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                // entries 0..3: modes 4q+1 (odd), 4q+2 (even), 4q+3 (odd), 4q+4 (even)
+                const float4 a = tab[((g + u) * (K / 4) + q) * kWave + lane];
+                co[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, x[4 * q + 0], co[u], 0, 0, 0);
+                ce[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, x[4 * q + 1], ce[u], 0, 0, 0);
+                co[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, x[4 * q + 2], co[u], 0, 0, 0);
+                ce[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, x[4 * q + 3], ce[u], 0, 0, 0);
+            }
+#pragma unroll
+        for (int u = 0; u < G; ++u) s3 = pair_cubes(ce[u], co[u], s3);
+    }
+    return 2.0f * s3;
+}
+
+// The same with BF16 (hi) or BF16x3 (hi/lo) products from the split operands;
+// the lo operands el, ol are read for BF16x3 only (null for BF16).
+template <int K, int PREC, int G>
+__device__ __forceinline__ float cube_sum_eo_bf16(const bf16x8 (&eh)[K / 16], const bf16x8 *el,
+                                                  const bf16x8 (&oh)[K / 16], const bf16x8 *ol,
+                                                  const char *lds_hi, const char *lds_lo, int lane)
+{
+    constexpr int P = eo_steps<K>(), S = eo_steps<K>();
+    const bf16x8 *th = reinterpret_cast<const bf16x8 *>(lds_hi);
+    const bf16x8 *tl = reinterpret_cast<const bf16x8 *>(lds_lo);
+    float s3 = 0.0f;
+#pragma unroll 1
+    for (int g = 0; g < P; g += G) {
+        f32x16 ce[G], co[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) ce[u] = co[u] = f32x16{};
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const int idx = ((g + u) * S + s) * 2 * kWave + lane;
+                const bf16x8 aeh = th[idx], aoh = th[idx + kWave];
+                if constexpr (PREC == PREC_BF16X3) {
+                    const bf16x8 ael = tl[idx], aol = tl[idx + kWave];
+                    ce[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ael, eh[s], ce[u], 0, 0, 0);
+                    co[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aol, oh[s], co[u], 0, 0, 0);
+                    ce[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aeh, el[s], ce[u], 0, 0, 0);
+                    co[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aoh, ol[s], co[u], 0, 0, 0);
+                }
+                ce[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aeh, eh[s], ce[u], 0, 0, 0);
+                co[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aoh, oh[s], co[u], 0, 0, 0);
+            }
+#pragma unroll
+        for (int u = 0; u < G; ++u) s3 = pair_cubes(ce[u], co[u], s3);
+    }
+    return 2.0f * s3;
+}
+
+// S3 of coordinates x in the half-period form with G tile pairs per group.
+template <int K, int PREC, int G>
+__device__ __forceinline__ float eo_cube_sum(const float (&x)[K], const char *lds_hi, const char *lds_lo, int lane)
+{
+    if constexpr (PREC == PREC_FP32) {
+        return cube_sum_eo_f32<K, G>(x, lds_hi, lane);
+    } else {
+        constexpr int S = eo_steps<K>();
+        bf16x8 eh[S], oh[S];
+        if constexpr (PREC == PREC_BF16X3) {
+            bf16x8 el[S], ol[S];
+            split_eo<K, PREC>(x, eh, el, oh, ol);
+            return cube_sum_eo_bf16<K, PREC, G>(eh, el, oh, ol, lds_hi, lds_lo, lane);
+        } else {
+            split_eo_hi<K>(x, eh, oh);
+            return cube_sum_eo_bf16<K, PREC, G>(eh, nullptr, oh, nullptr, lds_hi, lds_lo, lane);
+        }
+    }
+}
+
 // log a = log f/(M g) in FP32 from t and S3 = sum_j u~_j^3 (both lanes identical).
 template <int PROP>
 __device__ __forceinline__ float log_a_f32(const DevPoint &P, float t, float s3)
@@ -384,6 +618,44 @@ __device__ __forceinline__ void mix_y(const float (&x)[K], const bf16x8 (&bh)[K 
             }
             if (t == 0) y0 = acc; else y1 = acc;
         }
+    }
+}
+
+// The same products from the parity-split operands (split_eo) against the
+// y tables staged in the parity layout (stage_parity_frags, 2 row tiles); the
+// two row tiles accumulate as independent chains.  FP32 reads x as mix_y.
+template <int K, int PREC>
+__device__ __forceinline__ void mix_y_eo(const float (&x)[K], const bf16x8 (&eh)[K / 16], const bf16x8 *el,
+                                         const bf16x8 (&oh)[K / 16], const bf16x8 *ol, const char *yt_hi,
+                                         const char *yt_lo, int lane, f32x16 &y0, f32x16 &y1)
+{
+    if constexpr (PREC == PREC_FP32) {
+        bf16x8 bh[K / 8], bl[K / 8];
+        mix_y<K, PREC>(x, bh, bl, yt_hi, yt_lo, lane, y0, y1);
+    } else {
+        constexpr int S = eo_steps<K>();
+        const bf16x8 *th = reinterpret_cast<const bf16x8 *>(yt_hi);
+        const bf16x8 *tl = reinterpret_cast<const bf16x8 *>(yt_lo);
+        f32x16 acc[2] = {f32x16{}, f32x16{}};
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int idx = ((t * S + s) * 2 + p) * kWave + lane;
+                    const bf16x8 &bh = p == 0 ? eh[s] : oh[s];
+                    const bf16x8 ah = th[idx];
+                    if constexpr (PREC == PREC_BF16X3) {
+                        const bf16x8 &bl = p == 0 ? el[s] : ol[s];
+                        const bf16x8 al = tl[idx];
+                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[t], 0, 0, 0);
+                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[t], 0, 0, 0);
+                    }
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[t], 0, 0, 0);
+                }
+        y0 = acc[0];
+        y1 = acc[1];
     }
 }
 

@@ -83,35 +83,49 @@ __device__ __forceinline__ void add_lane0(unsigned long long *ctr, unsigned long
 
 static_assert(kClaimTiles == kWave, "one accept word per lane per claim");
 
+// k_decide's synthesis form: the half-period form (half the matrix work and
+// half the tables) where it is faster, the plain product elsewhere
+template <int K>
+__host__ __device__ constexpr bool decide_half_period() { return K >= 16; }
+
+// k_decide: one staged table (hi or lo)
+template <int K, int PREC>
+__host__ __device__ constexpr int decide_tab_bytes()
+{
+    return decide_half_period<K>() ? eo_table_bytes<K, PREC>()
+                                   : (PREC == PREC_FP32 ? f32_table_bytes<K>() : bf16_table_bytes<K>());
+}
 template <int K, int PREC>
 __host__ __device__ constexpr int decide_lds_bytes()
 {
-    return PREC == PREC_FP32 ? f32_table_bytes<K>()
-                             : (PREC == PREC_BF16X3 ? 2 : 1) * bf16_table_bytes<K>();
+    return (PREC == PREC_BF16X3 ? 2 : 1) * decide_tab_bytes<K, PREC>();
 }
 
 // ---------------------------------------------------------------------------
 // k_decide
 // ---------------------------------------------------------------------------
 template <int K, int PREC, int PROP>
-__global__ void __launch_bounds__(kBlock) k_decide(KernelArgs a, const int *plist, int n_plist)
+__global__ void __launch_bounds__(decide_block(K)) k_decide(KernelArgs a, const int *plist, int n_plist)
 {
+    constexpr int B = decide_block(K);
     extern __shared__ __attribute__((aligned(16))) char lds[];
-    constexpr int tab = PREC == PREC_FP32 ? f32_table_bytes<K>() : bf16_table_bytes<K>();
-    {
+    constexpr int tab = decide_tab_bytes<K, PREC>();
+    if constexpr (!decide_half_period<K>()) {
         const uint4 *s0 = reinterpret_cast<const uint4 *>(a.phi_hi);
         uint4 *d = reinterpret_cast<uint4 *>(lds);
-        for (int v = threadIdx.x; v < tab / 16; v += kBlock) d[v] = s0[v];
+        for (int v = threadIdx.x; v < tab / 16; v += B) d[v] = s0[v];
         if constexpr (PREC == PREC_BF16X3) {
             const uint4 *s1 = reinterpret_cast<const uint4 *>(a.phi_lo);
-            for (int v = threadIdx.x; v < tab / 16; v += kBlock) d[tab / 16 + v] = s1[v];
+            for (int v = threadIdx.x; v < tab / 16; v += B) d[tab / 16 + v] = s1[v];
         }
+    } else {
+        stage_eo_tables<K, PREC, B>(lds, a.phi_hi, a.phi_lo);
     }
     __syncthreads();
     const char *lds_hi = lds;
     const char *lds_lo = lds + tab;
     const int lane = threadIdx.x & 63, half = lane >> 5, pl = lane & 31;
-    const int gwave = blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6);
+    const int gwave = blockIdx.x * (B / kWave) + (threadIdx.x >> 6);
     int cursor = gwave % n_plist;
     int misses = 0;
     while (misses < n_plist) {
@@ -144,7 +158,9 @@ __global__ void __launch_bounds__(kBlock) k_decide(KernelArgs a, const int *plis
 #pragma unroll
                 for (int j = 0; j < K; ++j) a.dbg_xhat[local * (2 * K) + half * K + j] = x[j] * inv;
             }
-            const float s3l = synth_cube_sum<K, PREC>(x, lds_hi, lds_lo, lane);
+            float s3l;
+            if constexpr (decide_half_period<K>()) s3l = eo_cube_sum<K, PREC, 1>(x, lds_hi, lds_lo, lane);
+            else s3l = synth_cube_sum<K, PREC>(x, lds_hi, lds_lo, lane);
             const float s3 = (s3l + xor32(s3l)) * (inv * inv * inv);
             const float la = log_a_f32<PROP>(P, t, s3);
             // ln U < ln a - tau  <=>  U < a e^-tau (accept); within the window: FP64.
@@ -204,23 +220,36 @@ __host__ __device__ constexpr int mix_ytab_lds_bytes()
 {
     return PREC == PREC_FP32 ? mix_ytab_f32_bytes<K>() : (PREC == PREC_BF16X3 ? 2 : 1) * mix_ytab_bf16_bytes<K>();
 }
+// the mixture kernel's synthesis form and its tables (hi and lo) in LDS
+template <int K>
+__host__ __device__ constexpr bool mix_half_period() { return K >= 16; }
+template <int K, int PREC>
+__host__ __device__ constexpr int mix_tab_bytes()
+{
+    return mix_half_period<K>() ? eo_table_bytes<K, PREC>()
+                                : (PREC == PREC_FP32 ? f32_table_bytes<K>() : bf16_table_bytes<K>());
+}
 template <int K, int PREC>
 __host__ __device__ constexpr int decide_mix_lds_bytes()
 {
-    return decide_lds_bytes<K, PREC>() + mix_ytab_lds_bytes<K, PREC>() + mix_rv_bytes<K>();
+    return (PREC == PREC_BF16X3 ? 2 : 1) * mix_tab_bytes<K, PREC>() + mix_ytab_lds_bytes<K, PREC>() +
+           mix_rv_bytes<K>();
 }
 
 template <int K, int PREC>
 __global__ void __launch_bounds__(kMixBlock) k_decide_mix(KernelArgs a, const int *plist, int n_plist)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
-    constexpr int tab = PREC == PREC_FP32 ? f32_table_bytes<K>() : bf16_table_bytes<K>();
-    constexpr int phi_bytes = decide_lds_bytes<K, PREC>();
+    constexpr bool EO = mix_half_period<K>();
+    constexpr int tab = mix_tab_bytes<K, PREC>();
+    constexpr int phi_bytes = (PREC == PREC_BF16X3 ? 2 : 1) * tab;
     constexpr int yb = PREC == PREC_FP32 ? mix_ytab_f32_bytes<K>() : mix_ytab_bf16_bytes<K>();
     constexpr int ytab_bytes = mix_ytab_lds_bytes<K, PREC>();
     constexpr int rv_bytes = mix_rv_bytes<K>();
     static_assert(phi_bytes % 16 == 0 && ytab_bytes % 16 == 0 && rv_bytes % 16 == 0, "16-byte staging");
-    {
+    if constexpr (EO) {
+        stage_eo_tables<K, PREC, kMixBlock>(lds, a.phi_hi, a.phi_lo);
+    } else {
         const uint4 *s0 = reinterpret_cast<const uint4 *>(a.phi_hi);
         uint4 *d = reinterpret_cast<uint4 *>(lds);
         for (int v = threadIdx.x; v < tab / 16; v += kMixBlock) d[v] = s0[v];
@@ -251,7 +280,12 @@ __global__ void __launch_bounds__(kMixBlock) k_decide_mix(KernelArgs a, const in
                 src + 2 * mix_ytab_bf16_bytes<K>() + mix_ytab_f32_bytes<K>());
             uint4 *dy = reinterpret_cast<uint4 *>(lds + phi_bytes);
             uint4 *drv = reinterpret_cast<uint4 *>(lds + phi_bytes + ytab_bytes);
-            for (int v = threadIdx.x; v < ytab_bytes / 16; v += kMixBlock) dy[v] = sy[v];
+            if constexpr (EO && PREC != PREC_FP32) {  // the parity layout of the split operands
+                stage_parity_frags<K, kMixBlock>(dy, sy, 2);
+                if constexpr (PREC == PREC_BF16X3) stage_parity_frags<K, kMixBlock>(dy + yb / 16, sy + yb / 16, 2);
+            } else {
+                for (int v = threadIdx.x; v < ytab_bytes / 16; v += kMixBlock) dy[v] = sy[v];
+            }
             for (int v = threadIdx.x; v < rv_bytes / 16; v += kMixBlock) drv[v] = srv[v];
         }
         __syncthreads();
@@ -276,12 +310,31 @@ __global__ void __launch_bounds__(kMixBlock) k_decide_mix(KernelArgs a, const in
 #pragma unroll
                     for (int j = 0; j < K; ++j) a.dbg_xhat[local * (2 * K) + half * K + j] = x[j] * inv;
                 }
-                bf16x8 bh[K / 8], bl[K / 8];
-                if constexpr (PREC != PREC_FP32) split_bf16<K, PREC>(x, bh, bl);
-                const float s3l = cube_sum_ops<K, PREC>(x, bh, bl, lds_hi, lds_lo, lane);
-                const float s3 = (s3l + xor32(s3l)) * (inv * inv * inv);
+                float s3l;
                 f32x16 y0, y1;
-                mix_y<K, PREC>(x, bh, bl, y_hi, y_lo, lane, y0, y1);
+                if constexpr (EO && PREC == PREC_FP32) {
+                    s3l = cube_sum_eo_f32<K, 1>(x, lds_hi, lane);
+                    bf16x8 bh[K / 8], bl[K / 8];
+                    mix_y<K, PREC>(x, bh, bl, y_hi, y_lo, lane, y0, y1);
+                } else if constexpr (EO && PREC == PREC_BF16X3) {
+                    constexpr int S = eo_steps<K>();
+                    bf16x8 eh[S], el[S], oh[S], ol[S];
+                    split_eo<K, PREC>(x, eh, el, oh, ol);
+                    s3l = cube_sum_eo_bf16<K, PREC, 1>(eh, el, oh, ol, lds_hi, lds_lo, lane);
+                    mix_y_eo<K, PREC>(x, eh, el, oh, ol, y_hi, y_lo, lane, y0, y1);
+                } else if constexpr (EO) {  // BF16: hi operands only
+                    constexpr int S = eo_steps<K>();
+                    bf16x8 eh[S], oh[S];
+                    split_eo_hi<K>(x, eh, oh);
+                    s3l = cube_sum_eo_bf16<K, PREC, 1>(eh, nullptr, oh, nullptr, lds_hi, lds_lo, lane);
+                    mix_y_eo<K, PREC>(x, eh, nullptr, oh, nullptr, y_hi, y_lo, lane, y0, y1);
+                } else {
+                    bf16x8 bh[K / 8], bl[K / 8];
+                    if constexpr (PREC != PREC_FP32) split_bf16<K, PREC>(x, bh, bl);
+                    s3l = cube_sum_ops<K, PREC>(x, bh, bl, lds_hi, lds_lo, lane);
+                    mix_y<K, PREC>(x, bh, bl, y_hi, y_lo, lane, y0, y1);
+                }
+                const float s3 = (s3l + xor32(s3l)) * (inv * inv * inv);
                 const float lq = mix_log_q_f32(P, M, y0, y1, Qa, inv * inv, t, Kf);
                 const float lf = __builtin_fmaf(P.neg_bp_K2, t, P.c3coef * s3);
                 const float la = (lf - lq) - P.log_M;
@@ -976,21 +1029,22 @@ static hipError_t launch_decide_t(const KernelArgs &a, const int *plist, int n_p
                                   unsigned long long total_tiles, hipStream_t st, int *grid_out)
 {
     constexpr int lds = decide_lds_bytes<K, PREC>();
+    constexpr int B = decide_block(K);
     auto kern = k_decide<K, PREC, PROP>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, B, lds);
     if (e != hipSuccess) return e;
     if (a.blocks_per_cu > 0 && a.blocks_per_cu < per_cu) per_cu = a.blocks_per_cu;
     if (per_cu < 1) per_cu = 1;
-    unsigned long long want = (total_tiles + (unsigned long long)(kBlock / kWave) * kClaimTiles - 1) /
-                              ((unsigned long long)(kBlock / kWave) * kClaimTiles);
+    unsigned long long want = (total_tiles + (unsigned long long)(B / kWave) * kClaimTiles - 1) /
+                              ((unsigned long long)(B / kWave) * kClaimTiles);
     unsigned long long grid = (unsigned long long)per_cu * n_cu;
     if (want < grid) grid = want;
     if (grid < 1) grid = 1;
     if (grid_out) *grid_out = (int)grid;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kBlock), lds, st, a, plist, n_plist);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(B), lds, st, a, plist, n_plist);
     return hipGetLastError();
 }
 
@@ -1018,7 +1072,7 @@ static int decide_blocks_per_cu_t()
     if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
         return 1;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, lds) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, decide_block(K), lds) != hipSuccess) return 1;
     return per_cu < 1 ? 1 : per_cu;
 }
 

@@ -34,12 +34,95 @@ __device__ __forceinline__ double max64(double v)
     return v;
 }
 
+// One staged synthesis table (hi or lo): the half-period form for K >= 16,
+// the plain table at K = 8.
+template <int K, int PREC>
+__host__ __device__ constexpr int sir_tab_bytes()
+{
+    return K >= 16 ? eo_table_bytes<K, PREC>() : (PREC == PREC_FP32 ? f32_table_bytes<K>() : bf16_table_bytes<K>());
+}
+
+// The power sums of the half-period form: with u~ = E + O on grid tile t and
+// E - O on tile t + T/2, per pair of grid values
+//   sum u~ = 2E, sum u~^2 = 2(E^2 + O^2), sum u~^3 = 2E(E^2 + 3 O^2),
+//   sum u~^4 = 2((E^2 + O^2)^2 + 4 E^2 O^2);
+// the factor 2 is applied at the end.
+__device__ __forceinline__ void pair_power_sums(const f32x16 &ce, const f32x16 &co, float &s1, float &s2,
+                                                float &s3, float &s4)
+{
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const float e = ce[v], o = co[v];
+        const float e2 = e * e, o2 = o * o, w = e2 + o2;
+        s1 += e;
+        s2 += w;
+        s3 = __builtin_fmaf(e, __builtin_fmaf(3.0f, o2, e2), s3);
+        s4 = __builtin_fmaf(w, w, s4);
+        s4 = __builtin_fmaf(4.0f * e2, o2, s4);
+    }
+}
+
+template <int K, int PREC>
+__device__ __forceinline__ void grid_power_sums_eo(const float (&x)[K], const char *lds_hi, const char *lds_lo,
+                                                   int lane, float &s1, float &s2, float &s3, float &s4)
+{
+    constexpr int P = eo_steps<K>();
+    static_assert(PREC != PREC_BF16, "weights are computed with FP32 or BF16x3 products");
+    s1 = s2 = s3 = s4 = 0.0f;
+    if constexpr (PREC == PREC_FP32) {
+        const float4 *tab = reinterpret_cast<const float4 *>(lds_hi);
+#pragma unroll 1
+        for (int g = 0; g < P; ++g) {
+            f32x16 ce = {}, co = {};
+#pragma unroll
+            for (int q = 0; q < K / 4; ++q) {
+                const float4 a = tab[(g * (K / 4) + q) * kWave + lane];
+                co = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, x[4 * q + 0], co, 0, 0, 0);
+                ce = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, x[4 * q + 1], ce, 0, 0, 0);
+                co = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, x[4 * q + 2], co, 0, 0, 0);
+                ce = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, x[4 * q + 3], ce, 0, 0, 0);
+            }
+            pair_power_sums(ce, co, s1, s2, s3, s4);
+        }
+    } else {
+        bf16x8 eh[P], el[P], oh[P], ol[P];
+        split_eo<K, PREC>(x, eh, el, oh, ol);
+        const bf16x8 *th = reinterpret_cast<const bf16x8 *>(lds_hi);
+        const bf16x8 *tl = reinterpret_cast<const bf16x8 *>(lds_lo);
+#pragma unroll 1
+        for (int g = 0; g < P; ++g) {
+            f32x16 ce = {}, co = {};
+#pragma unroll
+            for (int s = 0; s < P; ++s) {
+                const int idx = (g * P + s) * 2 * kWave + lane;
+                const bf16x8 aeh = th[idx], aoh = th[idx + kWave], ael = tl[idx], aol = tl[idx + kWave];
+                ce = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ael, eh[s], ce, 0, 0, 0);
+                co = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aol, oh[s], co, 0, 0, 0);
+                ce = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aeh, el[s], ce, 0, 0, 0);
+                co = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aoh, ol[s], co, 0, 0, 0);
+                ce = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aeh, eh[s], ce, 0, 0, 0);
+                co = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aoh, oh[s], co, 0, 0, 0);
+            }
+            pair_power_sums(ce, co, s1, s2, s3, s4);
+        }
+    }
+    s1 *= 2.0f;
+    s2 *= 2.0f;
+    s3 *= 2.0f;
+    s4 *= 2.0f;
+}
+
 // Per-lane sums of u~^p over this lane's grid values (p = 1..4), products in
 // the requested arithmetic, from unnormalised x (the caller scales by |x|^-p).
+// K >= 16 takes the half-period form.
 template <int K, int PREC>
 __device__ __forceinline__ void grid_power_sums(const float (&x)[K], const char *lds_hi, const char *lds_lo,
                                                 int lane, float &s1, float &s2, float &s3, float &s4)
 {
+    if constexpr (K >= 16) {
+        grid_power_sums_eo<K, PREC>(x, lds_hi, lds_lo, lane, s1, s2, s3, s4);
+        return;
+    }
     s1 = s2 = s3 = s4 = 0.0f;
     auto fold = [&](const f32x16 &acc) {
 #pragma unroll
@@ -94,8 +177,10 @@ template <int K, int PREC, int PROP>
 __global__ void __launch_bounds__(kBlock) k_sir_weights(SirArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
-    constexpr int tab = PREC == PREC_FP32 ? f32_table_bytes<K>() : bf16_table_bytes<K>();
-    {
+    constexpr int tab = sir_tab_bytes<K, PREC>();
+    if constexpr (K >= 16) {
+        stage_eo_tables<K, PREC, kBlock>(lds, a.phi_hi, a.phi_lo);
+    } else {
         const uint4 *s0 = reinterpret_cast<const uint4 *>(a.phi_hi);
         uint4 *d = reinterpret_cast<uint4 *>(lds);
         for (int v = threadIdx.x; v < tab / 16; v += kBlock) d[v] = s0[v];
@@ -297,7 +382,7 @@ hipError_t launch_sir_weights(int K, int prec, int proposal, const SirArgs &a, i
     const int grid = 4 * n_cu;  // sir_waves(n_cu) waves
 #define TKDV_SIRW(KK, PR, PP)                                                                            \
     if (K == KK && prec == PR && proposal == PP) {                                                       \
-        constexpr int tab = PR == PREC_FP32 ? f32_table_bytes<KK>() : bf16_table_bytes<KK>();            \
+        constexpr int tab = sir_tab_bytes<KK, PR>();                                                     \
         constexpr int lds = PR == PREC_BF16X3 ? 2 * tab : tab;                                           \
         auto kern = k_sir_weights<KK, PR, PP>;                                                           \
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds); \
