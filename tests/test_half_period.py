@@ -1,0 +1,97 @@
+"""The half-period identities the GPU synthesis relies on, checked on the CPU.
+
+The kernels evaluate the grid sums of u~ = Phi^T x^ (N = 4K points
+xi_j = -pi + 2 pi j/N) from the even-mode and odd-mode syntheses E_j, O_j on
+the first half of the grid only: shifting xi by pi multiplies mode k by
+(-1)^k, so u~_j = E_j + O_j and u~_{j+N/2} = E_j - O_j, and
+
+    sum_j u~_j   = sum_{j<N/2} 2 E_j
+    sum_j u~_j^2 = sum_{j<N/2} 2 (E_j^2 + O_j^2)
+    sum_j u~_j^3 = sum_{j<N/2} 2 E_j (E_j^2 + 3 O_j^2)
+    sum_j u~_j^4 = sum_{j<N/2} 2 ((E_j^2 + O_j^2)^2 + 4 E_j^2 O_j^2).
+
+Here E and O are formed directly from their definitions (cos/sin sums over
+the modes of one parity) and compared with the oracle's grid (`oracle.grid`,
+the full synthesis on all N points), in FP64.  The pair-term bound the decision
+window uses, 2 |E| (E^2 + 3 O^2) <= |u~_j|^3 + |u~_{j+N/2}|^3, is checked too,
+and the mode order of the operand split (entry e of k-step s: modes
+16 s + 2 e + 2 for the even part, 16 s + 2 e + 1 for the odd part) against the
+gather of the plain fragments (odd entries of k-steps 2s and 2s + 1).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+
+def _parity_syntheses(x, K, N):
+    """E_j, O_j for j < N/2 from x = [cos block | sin block] (unscaled)."""
+    j = np.arange(N // 2)
+    xi = -math.pi + 2 * math.pi * j / N
+    E = np.zeros(N // 2)
+    O = np.zeros(N // 2)
+    for k in range(1, K + 1):
+        term = x[k - 1] * np.cos(k * xi) + x[K + k - 1] * np.sin(k * xi)
+        if k % 2 == 0:
+            E += term
+        else:
+            O += term
+    return E, O
+
+
+@pytest.mark.parametrize("K", [16, 32, 64])
+def test_power_sums_from_half_the_grid(K):
+    N = 4 * K
+    rng = np.random.default_rng(K)
+    amp = math.sqrt(2.0 / math.pi)  # E0 = 1: the oracle's u = amp u~
+    for _ in range(20):
+        x = rng.standard_normal(2 * K) / np.sqrt(1.0 + np.tile(np.arange(K), 2))
+        x /= np.linalg.norm(x)
+        u = oracle.grid(x, 1.0, N) / amp
+        E, O = _parity_syntheses(x, K, N)
+        # the two halves of the grid
+        assert np.allclose(u[: N // 2], E + O, atol=1e-13)
+        assert np.allclose(u[N // 2:], E - O, atol=1e-13)
+        scale = np.sum(np.abs(u) ** 4) + 1.0
+        assert abs(np.sum(u) - np.sum(2 * E)) < 1e-12 * scale
+        assert abs(np.sum(u ** 2) - np.sum(2 * (E * E + O * O))) < 1e-12 * scale
+        assert abs(np.sum(u ** 3) - np.sum(2 * E * (E * E + 3 * O * O))) < 1e-12 * scale
+        w = E * E + O * O
+        assert abs(np.sum(u ** 4) - np.sum(2 * (w * w + 4 * E * E * O * O))) < 1e-12 * scale
+        # Parseval on the grid (|x^| = 1): sum u~^2 = N/2, and sum u~ = 0
+        assert abs(np.sum(u ** 2) - N / 2) < 1e-10
+        assert abs(np.sum(u)) < 1e-10
+        # the bound used by the decision window, pair by pair
+        lhs = 2 * np.abs(E) * (E * E + 3 * O * O)
+        rhs = np.abs(E + O) ** 3 + np.abs(E - O) ** 3
+        assert np.all(lhs <= rhs * (1 + 1e-12) + 1e-15)
+
+
+def test_the_split_needs_only_an_even_grid():
+    # N = 3K is below the exactness threshold N > 3K of the cube quadrature;
+    # the half-period split itself still holds (it only needs N even)
+    K = 16
+    N = 3 * K
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(2 * K)
+    x /= np.linalg.norm(x)
+    u = oracle.grid(x, 1.0, N) / math.sqrt(2.0 / math.pi)
+    E, O = _parity_syntheses(x, K, N)
+    assert np.allclose(u[: N // 2], E + O, atol=1e-13)
+
+
+@pytest.mark.parametrize("K", [16, 32, 64])
+def test_parity_operand_order_matches_the_table_gather(K):
+    # plain fragment (k-step s) entry e holds mode 8 s + e + 1; the gather
+    # takes entries 1, 3, 5, 7 (even modes) or 0, 2, 4, 6 (odd modes) of
+    # k-steps 2s and 2s + 1
+    for s in range(K // 16):
+        for p in (0, 1):
+            gathered = [8 * (2 * s + e // 4) + 2 * (e % 4) + (1 - p) + 1 for e in range(8)]
+            operand = [16 * s + 2 * e + 2 - p for e in range(8)]
+            assert gathered == operand
+    # together the parities cover every mode once
+    modes = sorted(16 * s + 2 * e + 2 - p for s in range(K // 16) for p in (0, 1) for e in range(8))
+    assert modes == list(range(1, K + 1))
