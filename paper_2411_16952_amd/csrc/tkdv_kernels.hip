@@ -718,9 +718,15 @@ constexpr int kWaveWords = kSegWords / (kBlock / kWave);  // 512 words per wave
 constexpr int kGroupWords = kWave;                         // one word per lane per group
 
 template <int K>
+__host__ __device__ constexpr int materialize_tab_bytes()
+{
+    // the FP32 table; for K >= 16 its first half (the half-period form)
+    return K >= 16 ? eo_table_bytes<K, PREC_FP32>() : f32_table_bytes<K>();
+}
+template <int K>
 __host__ __device__ constexpr int materialize_lds_bytes()
 {
-    return f32_table_bytes<K>() + (kBlock / kWave) * kGroupWords * 32 * 2 + 1024;
+    return materialize_tab_bytes<K>() + (kBlock / kWave) * kGroupWords * 32 * 2 + 1024;
 }
 
 template <int K, int PROP>
@@ -732,7 +738,7 @@ __global__ void __launch_bounds__(kBlock) k_materialize(KernelArgs a, const int 
                                                         float *out_xhat, unsigned long long *out_index)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
-    constexpr int tab = f32_table_bytes<K>();
+    constexpr int tab = materialize_tab_bytes<K>();
     uint16_t *lists = reinterpret_cast<uint16_t *>(lds + tab);
     unsigned int *hist = reinterpret_cast<unsigned int *>(lds + tab + (kBlock / kWave) * kGroupWords * 32 * 2);
     __shared__ unsigned long long wave_cnt[kBlock / kWave];
@@ -822,28 +828,53 @@ __global__ void __launch_bounds__(kBlock) k_materialize(KernelArgs a, const int 
                 }
                 if (valid && half == 0 && r + 1 == limit) a.cnt[p].last_index = i;
                 // statistics on the grid: u = sqrt(2 E0/pi) u~, u~ from FP32 products
+                // (K >= 16: the half-period form, u~ = E + O and E - O on the two halves)
                 const float4 *ftab = reinterpret_cast<const float4 *>(lds);
+                auto fold = [&](float uf) {
+                    const double u = P.amp * (double)uf;
+                    const double u2 = u * u;
+                    S1 += u;
+                    S2 += u2;
+                    S3 += u2 * u;
+                    S4 += u2 * u2;
+                    n_ex += uf > 1.41421356237309515f ? 1ull : 0ull;  // u > 2 sqrt(E0/pi)
+                };
+                if constexpr (K >= 16) {
 #pragma unroll
-                for (int tt = 0; tt < K / 8; ++tt) {
-                    f32x16 acc = {};
+                    for (int tp = 0; tp < K / 16; ++tp) {
+                        f32x16 ce = {}, co = {};
 #pragma unroll
-                    for (int q = 0; q < K / 4; ++q) {
-                        const float4 av = ftab[(tt * (K / 4) + q) * kWave + lane];
-                        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, x[4 * q + 0], acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, x[4 * q + 1], acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, x[4 * q + 2], acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, x[4 * q + 3], acc, 0, 0, 0);
+                        for (int q = 0; q < K / 4; ++q) {
+                            // entries 0..3: modes 4q+1 (odd), 4q+2 (even), 4q+3 (odd), 4q+4 (even)
+                            const float4 av = ftab[(tp * (K / 4) + q) * kWave + lane];
+                            co = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, x[4 * q + 0], co, 0, 0, 0);
+                            ce = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, x[4 * q + 1], ce, 0, 0, 0);
+                            co = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, x[4 * q + 2], co, 0, 0, 0);
+                            ce = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, x[4 * q + 3], ce, 0, 0, 0);
+                        }
+                        if (valid) {
+#pragma unroll
+                            for (int v = 0; v < 16; ++v) {
+                                fold(ce[v] + co[v]);
+                                fold(ce[v] - co[v]);
+                            }
+                        }
                     }
-                    if (valid) {
+                } else {
 #pragma unroll
-                        for (int v = 0; v < 16; ++v) {
-                            const double u = P.amp * (double)acc[v];
-                            const double u2 = u * u;
-                            S1 += u;
-                            S2 += u2;
-                            S3 += u2 * u;
-                            S4 += u2 * u2;
-                            n_ex += acc[v] > 1.41421356237309515f ? 1ull : 0ull;  // u > 2 sqrt(E0/pi)
+                    for (int tt = 0; tt < K / 8; ++tt) {
+                        f32x16 acc = {};
+#pragma unroll
+                        for (int q = 0; q < K / 4; ++q) {
+                            const float4 av = ftab[(tt * (K / 4) + q) * kWave + lane];
+                            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, x[4 * q + 0], acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, x[4 * q + 1], acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, x[4 * q + 2], acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, x[4 * q + 3], acc, 0, 0, 0);
+                        }
+                        if (valid) {
+#pragma unroll
+                            for (int v = 0; v < 16; ++v) fold(acc[v]);
                         }
                     }
                 }
