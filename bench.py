@@ -137,19 +137,27 @@ def load_traffic(K: int, precision: str, proposals_per_launch: int, kernel: str 
 def cpu_baseline(points, plans, n_sample: int) -> dict:
     import oracle
     cores = oracle.max_threads()
-    t0 = time.perf_counter()
-    n_acc = 0
-    for p, pl in zip(points, plans):
-        r = oracle.sample(p.K, p.E0, p.beta_p, p.c32, 1, pl.alpha_star, pl.log_M, p.seed, p.point_id,
-                          n_sample, 4 * p.K, cap=0, nthreads=cores)
-        n_acc += r["stats"].n_accepted
-    dt = time.perf_counter() - t0
+
+    def run(n, threads):
+        t0 = time.perf_counter()
+        n_acc = 0
+        for p, pl in zip(points, plans):
+            r = oracle.sample(p.K, p.E0, p.beta_p, p.c32, 1, pl.alpha_star, pl.log_M, p.seed, p.point_id,
+                              n, 4 * p.K, cap=0, nthreads=threads)
+            n_acc += r["stats"].n_accepted
+        return n_acc, time.perf_counter() - t0
+
+    n_acc, dt = run(n_sample, cores)
+    n_one = max(n_sample // cores, 4096)
+    acc1, dt1 = run(n_one, 1)
     n_prop = n_sample * len(points)
     return {
         "value": n_acc / dt, "unit": "accepted samples/s", "cores": cores, "kind": "oracle",
         "proposals_per_s": n_prop / dt, "accepted": n_acc, "seconds": dt,
         "sample": f"first {n_sample} proposal indices of each of the {len(points)} points "
                   f"({n_prop} proposals, same Philox counters), FP64 oracle with OpenMP",
+        "single_core": {"value": acc1 / dt1, "proposals_per_s": n_one * len(points) / dt1, "accepted": acc1,
+                        "seconds": dt1, "sample": f"first {n_one} proposal indices of each point, one thread"},
     }
 
 
@@ -401,16 +409,22 @@ def cpu_baseline_mixture(points, mixtures, mix_plans, n_sample: int) -> dict:
     import numpy as np
     import oracle
     cores = oracle.max_threads()
-    t0 = time.perf_counter()
-    n_acc = 0
-    for p, mix, pl in zip(points, mixtures, mix_plans):
-        K = p.K
-        mo = oracle.make_mixture(K, mix.eps, np.array(mix.logd[:K]),
-                                 np.array([[mix.V[r][q] for q in range(2)] for r in range(2 * K)]))
-        r = oracle.mix_sample(K, p.E0, p.beta_p, p.c32, pl.alpha_star, pl.log_M, mo, p.seed, p.point_id,
-                              n_sample, nthreads=cores)
-        n_acc += int(r["n_accepted"])
-    dt = time.perf_counter() - t0
+    mos = [oracle.make_mixture(p.K, mix.eps, np.array(mix.logd[:p.K]),
+                               np.array([[mix.V[r][q] for q in range(2)] for r in range(2 * p.K)]))
+           for p, mix in zip(points, mixtures)]
+
+    def run(n, threads):
+        t0 = time.perf_counter()
+        n_acc = 0
+        for p, mo, pl in zip(points, mos, mix_plans):
+            r = oracle.mix_sample(p.K, p.E0, p.beta_p, p.c32, pl.alpha_star, pl.log_M, mo, p.seed, p.point_id,
+                                  n, nthreads=threads)
+            n_acc += int(r["n_accepted"])
+        return n_acc, time.perf_counter() - t0
+
+    n_acc, dt = run(n_sample, cores)
+    n_one = max(n_sample // cores, 1024)
+    acc1, dt1 = run(n_one, 1)
     n_prop = n_sample * len(points)
     return {
         "value": n_acc / dt, "unit": "accepted samples/s", "cores": cores, "kind": "oracle",
@@ -418,6 +432,8 @@ def cpu_baseline_mixture(points, mixtures, mix_plans, n_sample: int) -> dict:
         "sample": f"first {n_sample} proposal indices of each of the {len(points)} evaluation points "
                   f"({n_prop} proposals, same Philox counters, trained mixtures and M_mix), FP64 oracle "
                   f"mixture sampler with OpenMP",
+        "single_core": {"value": acc1 / dt1, "proposals_per_s": n_one * len(points) / dt1, "accepted": acc1,
+                        "seconds": dt1, "sample": f"first {n_one} proposal indices of each point, one thread"},
     }
 
 
