@@ -7,7 +7,8 @@ learned defensive-mixture proposal against the paper's Sigma proposal.
     GPU) is fitted on 16 training points (beta' = linspace(20, 60, 16),
     C3/C2 = 9000/beta') from the paper's sampler's accepted samples, and the
     plans of the evaluation points are made: alpha*, M_Sigma (the paper's
-    step 1) and M_mix of the network's mixture (multi-start BFGS of f/q_mix);
+    step 1) and M_mix of the network's mixture (multi-start L-BFGS of f/q_mix
+    on the GPU);
   * one step: 32 evaluation points (the 16 beta' at beta' C3/C2 = 9000 and
     12000, seeds not used in training), 1e9 proposals per point with the
     mixture sampler, then 1e9 per point with the paper's sampler (one batched
@@ -21,10 +22,17 @@ learned defensive-mixture proposal against the paper's Sigma proposal.
 --workload sweep: 256 points of K in {16, 32, 64} with accepted targets in
 [1e4, 1e6] (the batched-sweep configuration), windows replayed as a hipGraph
 with the autotuner's launch configuration.
+--workload sir: sampling-importance resampling at one K = 32 point (effective
+samples/s), beside the rejection sampler and the extreme-wave search.
+--synthesis: the standalone synthesis on the precision configuration (K = 64,
+2^20 rows of x^ in HBM; HBM roofline), plus the same synthesis with x^ drawn
+in registers (the decision kernel).
 
-Prints one JSON line with the roofline of the dominant kernel (ALU-bound)
-from HIP events recorded inside the library on the kernel's own stream, and
-the CPU FP64 oracle's throughput on a bounded sample of the same workload.
+Prints one JSON line with the roofline of the dominant kernel (ALU-bound:
+algorithmic issue slots, alu_ops_per_proposal) from HIP events recorded
+inside the library on the kernel's own stream, and the CPU FP64 oracle's
+throughput on a bounded sample of the same workload (all host threads, and
+one thread).
 """
 from __future__ import annotations
 
