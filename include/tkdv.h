@@ -314,15 +314,19 @@ tkdv_status tkdv_eval_proposals(tkdv_ctx *ctx, const tkdv_point *pt, tkdv_propos
  *   d_s3[r] = sum_j u~_j^3,  u~_j = sum_k (x^_k cos k xi_j + x^_{K+k} sin k xi_j),
  * i.e. H3 = (1/6) int u^3 dxi = (pi/(3N)) (2 E0/pi)^{3/2} d_s3[r] exactly when
  * |x^| = 1 (Sec. II.A; N >= 3K + 1).  The products run on the matrix cores in
- * the requested arithmetic with FP32 accumulation.  K in {8, 16, 32, 64};
- * both pointers are device pointers owned by the caller.
+ * the requested arithmetic with FP32 accumulation; for K >= 16 the sum is
+ * formed from the even- and odd-mode syntheses on half the grid (the other
+ * half holds their difference).  K in {8, 16, 32, 64}; both pointers are
+ * device pointers owned by the caller.
  */
 tkdv_status tkdv_synthesize(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, const float *d_xhat,
                             uint64_t n, float *d_s3, void *stream);
 
 /* The decision window used for a point: proposals with |log U - log a| below
- * it are re-decided in FP64.  It is an upper bound on the fast path's error
- * in log a (see the library's design notes) times a safety factor of 2. */
+ * it are re-decided in FP64.  It is twice an upper bound on the fast path's
+ * error in log a: the synthesis products of the requested arithmetic and
+ * their FP32 accumulation, the error of the FP32 x^ and t, and the FP32
+ * rounding of every term of log a and of log U. */
 double tkdv_decision_window(const tkdv_point *pt, tkdv_proposal proposal, tkdv_precision precision);
 
 /* Host FP64: log q_net and log q_mix (normalised, w.r.t. mu0) at n points x^

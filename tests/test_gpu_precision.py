@@ -6,7 +6,8 @@ compared proposal by proposal with the oracle (H3 relative to the scale
 S3abs = sum_j |u_j|^3, H2 relative to itself); accept-decision mismatches of
 the FP32 fast path alone and after the FP64 re-decision; and the standalone
 synthesis kernel (x^ read from HBM) on the same rows.  A JSON report is
-written to gpurun_out/ when that directory exists.
+written to the directory named by the environment variable TKDV_REPORT_DIR
+when it is set.
 """
 import json
 import os
@@ -87,8 +88,8 @@ def test_precision_study_k64(T, ctx, c32):
     assert p["fp32"]["H3_rel_median"] < 1e-6           # FP32: 1e-6 relative
     assert p["bf16"]["H3_rel_median"] < 1e-2           # BF16 before split recovery
     assert p["bf16x3"]["H3_rel_median"] < 1e-4         # BF16x3: measured and reported
-    out = os.path.join(ROOT, "gpurun_out")
-    if os.path.isdir(out):
+    out = os.environ.get("TKDV_REPORT_DIR", "")
+    if out and os.path.isdir(out):
         with open(os.path.join(out, f"precision_k64_c{int(c32)}.json"), "w") as f:
             json.dump(report, f, indent=1)
     sys.stdout.flush()
