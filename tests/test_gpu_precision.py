@@ -20,7 +20,6 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 N_BATCH = 1 << 20
 
 
