@@ -12,10 +12,11 @@ constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kTile = 32;          // proposals per wave tile (two lanes per proposal)
 constexpr int kBlock = 256;        // threads per workgroup of the sampling kernels
 // Workgroup of the decision kernel k_decide: at K = 64 one copy of its
-// synthesis tables (64 KB of LDS with BF16x3) serves 16 waves, 4 per SIMD
-// (the 128-register limit spills a few 8-byte values, reloaded a few times
-// per tile; measured faster than 3 waves per SIMD without spills).
-constexpr int decide_block(int K) { return K == 64 ? 1024 : kBlock; }
+// synthesis tables (64 KB of LDS with BF16x3) serves 12 waves, 3 per SIMD
+// (168 registers a lane; measured faster than 4 waves per SIMD, whose
+// 128-register limit spills inside the tile loop, and than 2 workgroups of
+// 4 waves).
+constexpr int decide_block(int K) { return K == 64 ? 768 : kBlock; }
 constexpr int kSynthBlock = 512;   // threads per workgroup of the standalone synthesis kernel
 constexpr int kClaimTiles = 64;    // tiles claimed per work-queue claim (2048 proposals);
                                    // lane c keeps the accept word of tile c
