@@ -55,6 +55,9 @@ struct tkdv_ctx {
     DevBuf bitmap, defer_list, defer_count, counters, points, seg_cnt, seg_base, seg_stats, results, plist;
     DevBuf mix, mix_tab;  // learned-proposal constants and tables of the current call
     DevBuf phi_hi[4], phi_lo[4], phi_f32[4];
+    // the same tables with the odd-mode rows scaled by sqrt(3), for the kernels
+    // that form S3 in the half-period form (K >= 16): s3_tables()
+    DevBuf phi3_hi[4], phi3_lo[4], phi3_f32[4];
     void *h_results = nullptr;  // pinned
     size_t h_results_bytes = 0;
     void *h_counters = nullptr;  // pinned
@@ -129,7 +132,9 @@ hipError_t ensure_host(void *&p, size_t &have, size_t bytes)
 
 // Synthesis tables for K modes on the grid xi_j = -pi + 2 pi j/N, N = 4K.
 // Row (block b, mode k) of Phi is cos(k xi_j) (b = 0) or sin(k xi_j) (b = 1);
-// angles are reduced exactly: k xi_j = -k pi + 2 pi (k j mod N)/N.
+// angles are reduced exactly: k xi_j = -k pi + 2 pi (k j mod N)/N.  For
+// K >= 16 a second set carries the odd-mode rows times sqrt(3): the half-period
+// cube sum 2 E (E^2 + 3 O^2) then reads 2 E (E^2 + o^2) with o = sqrt(3) O.
 tkdv_status build_tables(tkdv_ctx *ctx, int K)
 {
     const int ki = kindex(K);
@@ -141,34 +146,51 @@ tkdv_status build_tables(tkdv_ctx *ctx, int K)
         const double sign = (k & 1) ? -1.0 : 1.0;  // shift by -k pi
         return block == 0 ? sign * std::cos(ang) : sign * std::sin(ang);
     };
-    std::vector<uint16_t> hi((size_t)T * S * 64 * 8), lo(hi.size());
-    for (int t = 0; t < T; ++t)
-        for (int s = 0; s < S; ++s)
-            for (int l = 0; l < 64; ++l)
-                for (int e = 0; e < 8; ++e) {
-                    const int block = l / 32, j = 32 * t + l % 32, k = 8 * s + e + 1;
-                    const double v = phi(block, k, j);
-                    const uint16_t h = bf16_bits((float)v);
-                    const double rem = v - (double)bf16_value(h);
-                    const size_t idx = (((size_t)t * S + s) * 64 + l) * 8 + e;
-                    hi[idx] = h;
-                    lo[idx] = bf16_bits((float)rem);
-                }
-    std::vector<float> f32((size_t)T * Q * 64 * 4);
-    for (int t = 0; t < T; ++t)
-        for (int q = 0; q < Q; ++q)
-            for (int l = 0; l < 64; ++l)
-                for (int e = 0; e < 4; ++e) {
-                    const int block = l / 32, j = 32 * t + l % 32, k = 4 * q + e + 1;
-                    f32[(((size_t)t * Q + q) * 64 + l) * 4 + e] = (float)phi(block, k, j);
-                }
-    HIP_TRY(ctx, ensure(ctx->phi_hi[ki], hi.size() * 2));
-    HIP_TRY(ctx, ensure(ctx->phi_lo[ki], lo.size() * 2));
-    HIP_TRY(ctx, ensure(ctx->phi_f32[ki], f32.size() * 4));
-    HIP_TRY(ctx, hipMemcpy(ctx->phi_hi[ki].p, hi.data(), hi.size() * 2, hipMemcpyHostToDevice));
-    HIP_TRY(ctx, hipMemcpy(ctx->phi_lo[ki].p, lo.data(), lo.size() * 2, hipMemcpyHostToDevice));
-    HIP_TRY(ctx, hipMemcpy(ctx->phi_f32[ki].p, f32.data(), f32.size() * 4, hipMemcpyHostToDevice));
+    auto upload = [&](double odd_scale, DevBuf &d_hi, DevBuf &d_lo, DevBuf &d_f32) -> hipError_t {
+        auto row = [&](int block, int k, int j) { return ((k & 1) ? odd_scale : 1.0) * phi(block, k, j); };
+        std::vector<uint16_t> hi((size_t)T * S * 64 * 8), lo(hi.size());
+        for (int t = 0; t < T; ++t)
+            for (int s = 0; s < S; ++s)
+                for (int l = 0; l < 64; ++l)
+                    for (int e = 0; e < 8; ++e) {
+                        const int block = l / 32, j = 32 * t + l % 32, k = 8 * s + e + 1;
+                        const double v = row(block, k, j);
+                        const uint16_t h = bf16_bits((float)v);
+                        const double rem = v - (double)bf16_value(h);
+                        const size_t idx = (((size_t)t * S + s) * 64 + l) * 8 + e;
+                        hi[idx] = h;
+                        lo[idx] = bf16_bits((float)rem);
+                    }
+        std::vector<float> f32((size_t)T * Q * 64 * 4);
+        for (int t = 0; t < T; ++t)
+            for (int q = 0; q < Q; ++q)
+                for (int l = 0; l < 64; ++l)
+                    for (int e = 0; e < 4; ++e) {
+                        const int block = l / 32, j = 32 * t + l % 32, k = 4 * q + e + 1;
+                        f32[(((size_t)t * Q + q) * 64 + l) * 4 + e] = (float)row(block, k, j);
+                    }
+        hipError_t e = ensure(d_hi, hi.size() * 2);
+        if (e == hipSuccess) e = ensure(d_lo, lo.size() * 2);
+        if (e == hipSuccess) e = ensure(d_f32, f32.size() * 4);
+        if (e == hipSuccess) e = hipMemcpy(d_hi.p, hi.data(), hi.size() * 2, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d_lo.p, lo.data(), lo.size() * 2, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d_f32.p, f32.data(), f32.size() * 4, hipMemcpyHostToDevice);
+        return e;
+    };
+    if (K >= 16) HIP_TRY(ctx, upload(std::sqrt(3.0), ctx->phi3_hi[ki], ctx->phi3_lo[ki], ctx->phi3_f32[ki]));
+    HIP_TRY(ctx, upload(1.0, ctx->phi_hi[ki], ctx->phi_lo[ki], ctx->phi_f32[ki]));
     return TKDV_OK;
+}
+
+// Tables read by the S3 kernels (k_decide, k_decide_mix, k_synth): the scaled
+// set in the half-period form (K >= 16), the plain tables at K = 8.
+void s3_tables(const tkdv_ctx *ctx, int ki, int precision, const void *&hi, const void *&lo)
+{
+    const bool eo = ki >= 1;
+    const DevBuf &h = precision == TKDV_FP32 ? (eo ? ctx->phi3_f32[ki] : ctx->phi_f32[ki])
+                                             : (eo ? ctx->phi3_hi[ki] : ctx->phi_hi[ki]);
+    hi = h.p;
+    lo = eo ? ctx->phi3_lo[ki].p : ctx->phi_lo[ki].p;
 }
 
 tkdv_status check_point(tkdv_ctx *ctx, const tkdv_point &pt)
@@ -332,8 +354,7 @@ tkdv_status run(tkdv_ctx *ctx, Call &call, int precision, int proposal, float *d
         const int K = 8 << ki;
         // the largest K of the call sets the reported workgroup size
         ctx->timing.decide_block = proposal == TKDV_PROP_MIXTURE ? kMixBlock : decide_block(K);
-        a.phi_hi = precision == TKDV_FP32 ? ctx->phi_f32[ki].p : ctx->phi_hi[ki].p;
-        a.phi_lo = ctx->phi_lo[ki].p;
+        s3_tables(ctx, ki, precision, a.phi_hi, a.phi_lo);
         unsigned long long tiles = 0;
         for (int q = 0; q < call.plist_n[ki]; ++q) tiles += call.pts[call.plist[call.plist_off[ki] + q]].n_tiles;
         if (proposal == TKDV_PROP_MIXTURE)
@@ -691,8 +712,7 @@ tkdv_status sweep(tkdv_ctx *ctx, int np, const tkdv_point *pts, const tkdv_plan 
             if (call.plist_n[ki] == 0) continue;
             const int K = 8 << ki;
             a.blocks_per_cu = kcfg[ki].blocks_per_cu;
-            a.phi_hi = precision == TKDV_FP32 ? ctx->phi_f32[ki].p : ctx->phi_hi[ki].p;
-            a.phi_lo = ctx->phi_lo[ki].p;
+            s3_tables(ctx, ki, precision, a.phi_hi, a.phi_lo);
             const unsigned long long tiles = (unsigned long long)call.plist_n[ki] * (kcfg[ki].window / kTile);
             HIP_TRY(ctx, launch_decide(K, precision, TKDV_PROP_SIGMA, a, d_plist + call.plist_off[ki],
                                        call.plist_n[ki], ctx->n_cu, tiles, sst, nullptr));
@@ -841,6 +861,9 @@ tkdv_status tkdv_destroy(tkdv_ctx *ctx)
         if (ctx->phi_hi[i].p) (void)hipFree(ctx->phi_hi[i].p);
         if (ctx->phi_lo[i].p) (void)hipFree(ctx->phi_lo[i].p);
         if (ctx->phi_f32[i].p) (void)hipFree(ctx->phi_f32[i].p);
+        if (ctx->phi3_hi[i].p) (void)hipFree(ctx->phi3_hi[i].p);
+        if (ctx->phi3_lo[i].p) (void)hipFree(ctx->phi3_lo[i].p);
+        if (ctx->phi3_f32[i].p) (void)hipFree(ctx->phi3_f32[i].p);
     }
     if (ctx->h_results) (void)hipHostFree(ctx->h_results);
     if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
@@ -1485,9 +1508,10 @@ tkdv_status tkdv_synthesize(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, 
     const int ki = kindex(K);
     hipStream_t st = (hipStream_t)stream;
     std::memset(&ctx->timing, 0, sizeof(ctx->timing));
-    HIP_TRY(ctx, launch_synth(K, precision, d_xhat, n, d_s3,
-                              precision == TKDV_FP32 ? ctx->phi_f32[ki].p : ctx->phi_hi[ki].p, ctx->phi_lo[ki].p,
-                              ctx->n_cu, st, ctx->ev[0], &ctx->timing.decide_grid, &ctx->timing.decide_block));
+    const void *tab_hi = nullptr, *tab_lo = nullptr;
+    s3_tables(ctx, ki, precision, tab_hi, tab_lo);
+    HIP_TRY(ctx, launch_synth(K, precision, d_xhat, n, d_s3, tab_hi, tab_lo, ctx->n_cu, st, ctx->ev[0],
+                              &ctx->timing.decide_grid, &ctx->timing.decide_block));
     HIP_TRY(ctx, hipEventRecord(ctx->ev[1], st));
     HIP_TRY(ctx, hipEventSynchronize(ctx->ev[1]));
     float ms = 0.0f;

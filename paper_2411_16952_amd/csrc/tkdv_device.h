@@ -281,7 +281,8 @@ __device__ __forceinline__ void stage_parity_frags(uint4 *dst, const uint4 *src,
 }
 
 // A workgroup of BLOCK threads stages the half-period tables: hi at lds, lo
-// (BF16x3) at lds + eo_table_bytes.
+// (BF16x3) at lds + eo_table_bytes.  The cube sums read tables whose odd-mode
+// rows carry sqrt(3) (pair_cubes); the SIR power sums read the plain ones.
 template <int K, int PREC, int BLOCK>
 __device__ __forceinline__ void stage_eo_tables(char *lds, const void *phi_hi, const void *phi_lo)
 {
@@ -360,21 +361,24 @@ __device__ __forceinline__ void split_eo_hi(const float (&x)[K], bf16x8 (&eh)[K 
     }
 }
 
-// sum over the pair's grid values of u~^3 = 2 E (E^2 + 3 O^2), elementwise
-// (the factor 2 is applied by the caller)
+// sum over the pair's grid values of u~^3 = 2 E (E^2 + 3 O^2), elementwise,
+// from co = sqrt(3) O: the odd-mode rows of the tables these sums read carry
+// the factor sqrt(3), which saves a product per grid value (the factor 2 is
+// applied by the caller)
 __device__ __forceinline__ float pair_cubes(const f32x16 &ce, const f32x16 &co, float s)
 {
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const float e = ce[v], o = co[v];
-        const float q = __builtin_fmaf(3.0f * o, o, e * e);
+        const float q = __builtin_fmaf(o, o, e * e);
         s = __builtin_fmaf(e, q, s);
     }
     return s;
 }
 
 // S3 over this lane's grid values in the half-period form, FP32 products; G
-// tile pairs per group have their accumulators live together.
+// tile pairs per group have their accumulators live together.  The tables are
+// the S3 tables: odd-mode rows scaled by sqrt(3) (pair_cubes).
 template <int K, int G>
 __device__ __forceinline__ float cube_sum_eo_f32(const float (&x)[K], const char *lds, int lane)
 {

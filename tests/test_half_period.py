@@ -10,6 +10,9 @@ the first half of the grid only: shifting xi by pi multiplies mode k by
     sum_j u~_j^3 = sum_{j<N/2} 2 E_j (E_j^2 + 3 O_j^2)
     sum_j u~_j^4 = sum_{j<N/2} 2 ((E_j^2 + O_j^2)^2 + 4 E_j^2 O_j^2).
 
+The cube sum is also checked in the form the kernels evaluate it, from odd-mode
+syntheses whose rows carry the factor sqrt(3): 2 E (E^2 + o^2), o = sqrt(3) O.
+
 Here E and O are formed directly from their definitions (cos/sin sums over
 the modes of one parity) and compared with the oracle's grid (`oracle.grid`,
 the full synthesis on all N points), in FP64.  The pair-term bound the decision
@@ -60,6 +63,9 @@ def test_power_sums_from_half_the_grid(K):
         assert abs(np.sum(u ** 3) - np.sum(2 * E * (E * E + 3 * O * O))) < 1e-12 * scale
         w = E * E + O * O
         assert abs(np.sum(u ** 4) - np.sum(2 * (w * w + 4 * E * E * O * O))) < 1e-12 * scale
+        # the cube kernels read odd-mode rows scaled by sqrt(3): o = sqrt(3) O
+        o = math.sqrt(3.0) * O
+        assert abs(np.sum(u ** 3) - np.sum(2 * E * (E * E + o * o))) < 1e-12 * scale
         # Parseval on the grid (|x^| = 1): sum u~^2 = N/2, and sum u~ = 0
         assert abs(np.sum(u ** 2) - N / 2) < 1e-10
         assert abs(np.sum(u)) < 1e-10
