@@ -44,6 +44,19 @@
 #define M_PI 3.14159265358979323846
 #endif
 
+/* Threads of one parallel loop: nthreads if positive, else the OpenMP
+   default.  The choice applies to that loop only, so a one-thread call leaves
+   no process-wide setting behind. */
+static inline int orc_threads(int nthreads)
+{
+#ifdef _OPENMP
+    return nthreads > 0 ? nthreads : omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
+}
+
 #define ORC_KMAX 128
 #define ORC_NBINS 64
 
@@ -556,12 +569,7 @@ uint64_t orc_sample(const orc_point *p, uint64_t i0, uint64_t n, uint8_t *accept
     uint8_t *acc = accept ? accept : (uint8_t *)malloc(n ? n : 1);
     double max_la = -INFINITY;
     uint64_t nviol = 0;
-#ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-#else
-    (void)nthreads;
-#endif
-#pragma omp parallel for schedule(static) reduction(max : max_la) reduction(+ : nviol)
+#pragma omp parallel for num_threads(orc_threads(nthreads)) schedule(static) reduction(max : max_la) reduction(+ : nviol)
     for (int64_t q = 0; q < (int64_t)n; ++q) {
         double xh[2 * ORC_KMAX];
         double lu;
@@ -669,12 +677,7 @@ void orc_eval_batch(const orc_point *p, uint64_t i0, uint64_t n, double *H2, dou
     int K = p->K, N = p->N;
     orc_grid_table g; /* cos(k xi_j), sin(k xi_j) */
     grid_table_init(&g, K, N, p->E0);
-#ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-#else
-    (void)nthreads;
-#endif
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for num_threads(orc_threads(nthreads)) schedule(static)
     for (int64_t q = 0; q < (int64_t)n; ++q) {
         double xh[2 * ORC_KMAX];
         double lu;
@@ -729,12 +732,7 @@ uint64_t orc_mix_sample(const orc_point *p, const orc_mixture *m, uint64_t i0, u
                         uint64_t *index_out, uint64_t cap, int nthreads)
 {
     int K = p->K;
-#ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-#else
-    (void)nthreads;
-#endif
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for num_threads(orc_threads(nthreads)) schedule(static)
     for (int64_t q = 0; q < (int64_t)n; ++q) {
         double xh[2 * ORC_KMAX], lu;
         double la = orc_mix_proposal(p, m, i0 + (uint64_t)q, xh, &lu);
@@ -778,12 +776,7 @@ void orc_sir(const orc_point *p, uint64_t i0, uint64_t n, uint64_t m, double u0,
     grid_table_init(&g, K, N, p->E0);
     double *w = (double *)malloc(sizeof(double) * (n ? n : 1));
     double *mom = (double *)malloc(sizeof(double) * 4 * (n ? n : 1));
-#ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-#else
-    (void)nthreads;
-#endif
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for num_threads(orc_threads(nthreads)) schedule(static)
     for (int64_t q = 0; q < (int64_t)n; ++q) {
         double xh[2 * ORC_KMAX], lu;
         double la = orc_proposal(p, i0 + (uint64_t)q, xh, &lu);

@@ -487,3 +487,12 @@ def test_sampler_determinism_and_modes():
     ref = oracle.stats_of(a["xhat"][:n_t], 1.0, 32)
     assert u["stats"].S3 == pytest.approx(ref.S3, rel=1e-12)
     assert np.array_equal(u["stats"].hist, ref.hist)
+
+
+def test_one_thread_call_leaves_the_thread_count():
+    # a call with nthreads=1 (the single-core baseline) must not lower the
+    # thread count of later calls
+    n0 = oracle.max_threads()
+    pl = plan.plan_point(8, 1.0, 40.0, 20.0, plan.SIGMA)
+    oracle.sample(8, 1.0, 40.0, 20.0, 1, pl.alpha_star, pl.log_M, 0, 0, 256, 32, nthreads=1)
+    assert oracle.max_threads() == n0
