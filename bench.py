@@ -71,7 +71,8 @@ def alu_roof(achieved: float, **extra) -> dict:
     return r
 
 
-def alu_ops_per_proposal(K: int, proposal: str = "sigma", precision: str = "bf16x3") -> float:
+def alu_ops_per_proposal(K: int, proposal: str = "sigma", precision: str = "bf16x3",
+                         scaled_odd_rows: bool = True) -> float:
     """Vector-ALU issue slots one proposal needs: each operation the method
     performs, counted as the gfx950 instructions that carry it (a 32x32 -> 64-bit
     product, a three-input XOR, an FMA: one slot each; the transcendentals
@@ -86,14 +87,18 @@ def alu_ops_per_proposal(K: int, proposal: str = "sigma", precision: str = "bf16
         1/sqrt, t scaling                                                           = 6 K + 7
       synthesis operands (BF16x3: round pair, two unpacks, two subtractions, round
         pair per two coordinates; BF16: round pair; FP32: none)                     = 6 K / K / 0
-      sum of cubes over the N = 4K grid values (half-period form: 4 per pair)       = 8 K
+      sum of cubes over the N = 4K grid values: half-period form (K >= 16), 2K
+        pairs, E E, q = o o + E E, s += E q with o = sqrt(3) O read from tables
+        whose odd-mode rows carry sqrt(3): 3 per pair (4 from the plain tables,
+        scaled_odd_rows=False); K = 8: u u and s += u u^2 per grid value      = 6 K / 8 K
       lane sum and scaling of S3, log a (with log1p), log U, exp2, window edges,
         comparisons                                                                 = 24
     The synthesis products themselves run on the matrix cores.  The learned
     mixture adds mixture_extra_ops."""
     split = {"bf16x3": 6 * K, "bf16": K, "fp32": 0}[precision]
     scale = 2 * K if proposal in ("sigma", "mixture") else 0
-    base = 40 * (K / 2 + 1) + 2 * (2 * K + 1) + 7 * K + scale + 6 * K + 7 + split + 8 * K + 24
+    cubes = 6 * K if (K >= 16 and scaled_odd_rows) else 8 * K
+    base = 40 * (K / 2 + 1) + 2 * (2 * K + 1) + 7 * K + scale + 6 * K + 7 + split + cubes + 24
     return base + (mixture_extra_ops(K) if proposal == "mixture" else 0)
 
 
@@ -290,7 +295,8 @@ def sir_bench(args) -> int:
           f"{ex['n_exceed']} above 4 sigma); GPU plans of 64 points x 16 starts: {plan_ms:.1f} ms",
           file=sys.stderr, flush=True)
     avg_w = sum(wms) / len(wms) / 1e3
-    ops = alu_ops_per_proposal(K, "sigma", args.precision) + 12 * K   # + the power sums S1, S2, S4
+    # the power sums read the plain tables (4 per pair for the cubes), + S1, S2, S4
+    ops = alu_ops_per_proposal(K, "sigma", args.precision, scaled_odd_rows=False) + 12 * K
     roof = alu_roof(ops * n / avg_w, traffic=None, kernel="k_sir_weights", algorithmic_ops_per_proposal=ops,
                     avg_launch_ms=avg_w * 1e3, proposals_per_launch=n,
                     note="4 B written per proposal (the weights) + 8 B per tile (tile sums)")
