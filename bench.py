@@ -106,10 +106,11 @@ def mixture_extra_ops(K: int, S: int = 32) -> float:
     """Issue slots the learned mixture adds per proposal: component choice from
     one word (6); the Box-Muller pair eta (2 conversions, 4 transcendentals, 3:
     9); the low-rank part of the draw (2 FMA per coordinate: 4K); Q = X^T A X
-    (2K); per shift j < S: the 2x2 quadratic form of y_j and r_j (6), log2,
-    running minimum, exp2 and its sum (4) = 10 S; the final log-sum and the
-    two-term mixture (20)."""
-    return 6 + 9 + 4 * K + 2 * K + 10 * S + 20
+    (2K); per shift j < S: |z_j|^2 (the 2x2 form y^T G^-1 y with the Cholesky
+    factor of G^-1 folded into the tables: 2) and r_j (1), log2, running
+    minimum, exp2 and its sum (4) = 7 S; the final log-sum and the two-term
+    mixture (20)."""
+    return 6 + 9 + 4 * K + 2 * K + 7 * S + 20
 
 
 def mfma_flops_per_proposal(K: int, precision: str = "bf16x3", proposal: str = "sigma") -> float:

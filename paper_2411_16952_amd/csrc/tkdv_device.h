@@ -577,9 +577,10 @@ __device__ __forceinline__ float gen_x_mix(const DevPoint &P, const DevMix &M, c
     return inv;
 }
 
-// y = (R_j A V)^T X for the S shifts on the matrix cores: row tile q holds
-// rank index q, row j the shift, column the proposal (the B operand layout).
-// Row tiles share their row order, so y0[v] and y1[v] belong to one shift.
+// z = (R_j A V C^T)^T X for the S shifts on the matrix cores (C^T C = G^-1, so
+// that y_j^T G^-1 y_j = |z_j|^2): row tile q holds rank index q, row j the
+// shift, column the proposal (the B operand layout).  Row tiles share their row
+// order, so y0[v] and y1[v] are the two entries of one shift's z.
 template <int K, int PREC>
 __device__ __forceinline__ void mix_y(const float (&x)[K], const bf16x8 (&bh)[K / 8], const bf16x8 (&bl)[K / 8],
                                       const char *yt_hi, const char *yt_lo, int lane, f32x16 &y0, f32x16 &y1)
@@ -659,8 +660,8 @@ __device__ __forceinline__ void mix_y_eo(const float (&x)[K], const bf16x8 (&eh)
     }
 }
 
-// log q_mix in FP32 from the shifts' y, Qa = X^T A X (both unprojected: the
-// ratios r_j = qf_j/Q = 1 - y_j^T G^-1 y_j/Qa are scale free), |X|^-2 and t.
+// log q_mix in FP32 from the shifts' z, Qa = X^T A X (both unprojected: the
+// ratios r_j = qf_j/Q = 1 - |z_j|^2/Qa are scale free), |X|^-2 and t.
 //   ln q_net + ln(1 - eps) = c_net - K ln(Qa |X|^-2) + ln sum_j r_j^-K,
 //   ln(eps g_Sigma) = c_g - K ln(1 + alpha beta' t/K^3).
 // The sum is taken relative to the smallest r_j of the proposal (all terms
@@ -674,8 +675,7 @@ __device__ __forceinline__ float mix_log_q_f32(const DevPoint &P, const DevMix &
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const float a0 = y0[v], a1 = y1[v];
-        const float t1 = __builtin_fmaf(M.g01x2, a1, M.g00 * a0);
-        const float quad = __builtin_fmaf(a0, t1, (M.g11 * a1) * a1);
+        const float quad = __builtin_fmaf(a0, a0, a1 * a1);
         const float r = fmaxf(__builtin_fmaf(-quad, invQ, 1.0f), 1e-30f);
         l[v] = log2_hw(r);
         lmin = fminf(lmin, l[v]);

@@ -60,15 +60,16 @@ struct DevPoint {
 
 // Per-point constants of the learned mixture proposal (see tkdv_mixture).
 // Its tables live at tab_off in the mixture table buffer:
-//   y tables  B[(q, j)][c] = a_c (R_j V_q)_c as matrix-core A operands, row
-//             tile q (rank index), row j (shift) -- BF16 hi, BF16 lo, FP32;
+//   y tables  B[(q, j)][c] = a_c (R_j V C^T)_{c q} as matrix-core A operands,
+//             row tile q (rank index), row j (shift) -- BF16 hi, BF16 lo, FP32;
+//             C is the upper Cholesky factor of (I + V^T D^-1 V)^-1 = C^T C, so
+//             the products give z_j = C y_j and y_j^T G^-1 y_j = |z_j|^2;
 //   RV table  (R_j V)_c for shift j, half h, coordinate k of that half:
 //             float2 at ((2 j + h) (2K + 2) + 2 k) floats (rows padded by
 //             two floats to spread the shifts over the LDS banks).
 struct DevMix {
     float sqd[TKDV_KMAX];    // sqrt(d_k)
     float a[TKDV_KMAX];      // 1/d_k
-    float g00, g01x2, g11;   // (I + V^T D^-1 V)^-1: entries 00, 2*01, 11
     float c_net;             // ln(1 - eps) - ln|L0|/2 - ln S
     float c_g;               // ln eps + sum_k ln(1 + alpha beta' k^2/K^3)
     float invB;              // 1/B rounded to FP32

@@ -171,7 +171,15 @@ static void mix_tables(const MixHost &mh, std::vector<uint8_t> &tab)
             mh.rot(j, v.data(), r.data());
             for (int c = 0; c < 2 * K; ++c) R[((size_t)j * 2 * K + c) * 2 + q] = r[c];
         }
-    auto B = [&](int q, int j, int c) { return mh.a[c] * R[((size_t)j * 2 * K + c) * 2 + q]; };
+    // C: upper Cholesky factor of G^-1 = (I + V^T D^-1 V)^-1 = C^T C; the
+    // tables hold A R_j V C^T, so the products give z_j = C y_j directly
+    const double c00 = std::sqrt(mh.Ginv[0][0]), c01 = mh.Ginv[0][1] / c00;
+    const double c11 = std::sqrt(std::max(0.0, mh.Ginv[1][1] - c01 * c01));
+    const double C[2][2] = {{c00, c01}, {0.0, c11}};
+    auto B = [&](int q, int j, int c) {
+        const double *r = &R[((size_t)j * 2 * K + c) * 2];
+        return mh.a[c] * (C[q][0] * r[0] + C[q][1] * r[1]);
+    };
     for (int t = 0; t < 2; ++t)
         for (int s = 0; s < K / 8; ++s)
             for (int l = 0; l < 64; ++l)
@@ -212,9 +220,6 @@ void mix_device_data(const MixHost &mh, DevMix &d, std::vector<uint8_t> &tab)
         for (int q = 0; q < 2; ++q) d.V64[c][q] = mh.V[c * 2 + q];
     for (int p = 0; p < 2; ++p)
         for (int q = 0; q < 2; ++q) d.gi64[p][q] = mh.Ginv[p][q];
-    d.g00 = (float)mh.Ginv[0][0];
-    d.g01x2 = (float)(2.0 * mh.Ginv[0][1]);
-    d.g11 = (float)mh.Ginv[1][1];
     d.c_net = (float)(mh.log_1m_eps - 0.5 * mh.logdetL0 - std::log((double)TKDV_MIX_S));
     d.c_g = (float)(mh.log_eps + mh.lng);
     d.E = (uint32_t)mh.E;
@@ -262,7 +267,9 @@ double mix_window_extra(const MixHost &mh, int precision)
     const double cond = (dmax + vf2) / dmin;
     // (a) x^ error: |d ln qf_j| <= 2 |dx| sqrt(cond L0)
     const double e_in = K * 2.0 * eps_x * std::sqrt(cond);
-    // (b) y products: |d qf|/qf <= 2 kappa eps_p |A V|_F / sqrt(a_min)
+    // (b) y products: |d qf|/qf <= 2 kappa eps_p |A V|_F / sqrt(a_min); the
+    //     products form z = C y with C^T C = G^-1, and |A V C^T|_F <= |A V|_F
+    //     because |C|_2^2 = |G^-1|_2 <= 1 (G = I + V^T D^-1 V >= I)
     const double e_y = K * 2.0 * kap * eps_p * std::sqrt(avf2) / std::sqrt(amin);
     // (c) FP32 rounding of Q, the 2x2 form and r_j = 1 - quad/Q, relative to r_j >= 1/kappa
     const double e_r = K * kap * (2.0 * K + 10.0) * 0x1p-24;
