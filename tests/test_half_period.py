@@ -101,3 +101,22 @@ def test_parity_operand_order_matches_the_table_gather(K):
     # together the parities cover every mode once
     modes = sorted(16 * s + 2 * e + 2 - p for s in range(K // 16) for p in (0, 1) for e in range(8))
     assert modes == list(range(1, K + 1))
+
+
+def test_folded_cholesky_factor_gives_the_woodbury_term():
+    # the mixture's y tables carry C with C^T C = G^-1 (c00 = sqrt(m00),
+    # c01 = m01/c00, c11 = sqrt(m11 - c01^2)), so |C y|^2 = y^T G^-1 y; and
+    # |C|_2 <= 1 whenever G >= I, which keeps the window's product term valid
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        B = rng.standard_normal((2, 2)) * rng.uniform(0.01, 10.0)
+        G = np.eye(2) + B @ B.T  # I + V^T D^-1 V is of this form
+        M = np.linalg.inv(G)
+        c00 = math.sqrt(M[0, 0])
+        c01 = M[0, 1] / c00
+        c11 = math.sqrt(max(0.0, M[1, 1] - c01 * c01))
+        C = np.array([[c00, c01], [0.0, c11]])
+        assert np.allclose(C.T @ C, M, rtol=1e-12, atol=1e-15)
+        y = rng.standard_normal(2)
+        assert abs(np.sum((C @ y) ** 2) - y @ M @ y) <= 1e-12 * (y @ M @ y + 1e-300) + 1e-15
+        assert np.linalg.norm(C, 2) <= 1.0 + 1e-12
