@@ -12,6 +12,8 @@ the first half of the grid only: shifting xi by pi multiplies mode k by
 
 The cube sum is also checked in the form the kernels evaluate it, from odd-mode
 syntheses whose rows carry the factor sqrt(3): 2 E (E^2 + o^2), o = sqrt(3) O.
+Likewise the mixture's Woodbury term y^T G^-1 y as |C y|^2 with the Cholesky
+factor C the y tables carry.
 
 Here E and O are formed directly from their definitions (cos/sin sums over
 the modes of one parity) and compared with the oracle's grid (`oracle.grid`,
