@@ -171,6 +171,8 @@ __device__ __forceinline__ void split_bf16(const float (&x)[K], bf16x8 (&bh)[K /
 
 // Sum over this lane's grid values of u~^3 (u~ = unscaled synthesis), with
 // the products in the requested arithmetic (FP32 reads x, BF16 reads bh/bl).
+// The plain (dense) form; the kernels take it at K = 8, a single grid-tile
+// group, and the half-period form below for K >= 16.
 template <int K, int PREC>
 __device__ __forceinline__ float cube_sum_ops(const float (&x)[K], const bf16x8 (&bh)[K / 8],
                                               const bf16x8 (&bl)[K / 8], const char *lds_hi,
@@ -179,7 +181,7 @@ __device__ __forceinline__ float cube_sum_ops(const float (&x)[K], const bf16x8 
     float s3 = 0.0f;
     if constexpr (PREC == PREC_FP32) {
         const float4 *tab = reinterpret_cast<const float4 *>(lds_hi);
-#pragma unroll(K >= 64 ? 2 : K / 8)
+#pragma unroll
         for (int t = 0; t < K / 8; ++t) {
             f32x16 acc = {};
 #pragma unroll
@@ -196,8 +198,7 @@ __device__ __forceinline__ float cube_sum_ops(const float (&x)[K], const bf16x8 
     } else {
         const bf16x8 *th = reinterpret_cast<const bf16x8 *>(lds_hi);
         const bf16x8 *tl = reinterpret_cast<const bf16x8 *>(lds_lo);
-        // at K = 64 a full unroll keeps every grid tile's operands live (spills)
-#pragma unroll(K >= 64 ? 2 : K / 8)
+#pragma unroll
         for (int t = 0; t < K / 8; ++t) {
             f32x16 acc = {};
 #pragma unroll

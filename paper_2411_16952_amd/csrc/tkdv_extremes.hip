@@ -54,7 +54,8 @@ __global__ void __launch_bounds__(kExtBlock) k_grid_max(ExtArgs a)
         }
         float best = -INFINITY;
         int bj = 0;
-#pragma unroll(T < 4 ? T : 2)
+        constexpr int kTileUnroll = T < 4 ? T : 2;  // grid tiles unrolled
+#pragma unroll kTileUnroll
         for (int t = 0; t < T; ++t) {
             f32x16 acc = {};
 #pragma unroll

@@ -134,9 +134,10 @@ __device__ __forceinline__ void grid_power_sums(const float (&x)[K], const char 
             s4 = __builtin_fmaf(u2, u2, s4);
         }
     };
+    constexpr int kTileUnroll = K >= 64 ? 2 : K / 8;  // grid-tile groups unrolled
     if constexpr (PREC == PREC_FP32) {
         const float4 *tab = reinterpret_cast<const float4 *>(lds_hi);
-#pragma unroll(K >= 64 ? 2 : K / 8)
+#pragma unroll kTileUnroll
         for (int t = 0; t < K / 8; ++t) {
             f32x16 acc = {};
 #pragma unroll
@@ -154,7 +155,7 @@ __device__ __forceinline__ void grid_power_sums(const float (&x)[K], const char 
         split_bf16<K, PREC>(x, bh, bl);
         const bf16x8 *th = reinterpret_cast<const bf16x8 *>(lds_hi);
         const bf16x8 *tl = reinterpret_cast<const bf16x8 *>(lds_lo);
-#pragma unroll(K >= 64 ? 2 : K / 8)
+#pragma unroll kTileUnroll
         for (int t = 0; t < K / 8; ++t) {
             f32x16 acc = {};
 #pragma unroll
