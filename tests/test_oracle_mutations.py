@@ -5,9 +5,9 @@ sign, an index, a dropped factor, a swapped function), builds it, and runs the
 fast subset of ``test_oracle_pins.py`` against that build in a subprocess.  The
 pins pass on the real oracle (that is ``test_oracle_pins.py`` itself); here
 every mutant must make at least one of them fail (the mixture and SIR
-mutants run against their own pin files).  Mistakes in the Philox
-constants are not in this list: no closed form fixes them, and they are
-caught by bit-exact comparison with the independent HIP implementation.
+mutants run against their own pin files).  Mistakes in the Philox constants,
+word order and round count are caught by the generator's published
+known-answer vectors.
 """
 import os
 import subprocess
@@ -21,7 +21,7 @@ SRC = os.path.join(ROOT, "oracle", "tkdv_oracle.c")
 
 FAST_PINS = " or ".join([
     "appendix_A", "dirichlet_kernel", "double_sum_equals", "parseval", "H3_odd",
-    "box_muller", "uniform_sphere_law", "K2_brute_force", "uniform_proposal_linear",
+    "box_muller", "philox_known", "uniform_sphere_law", "K2_brute_force", "uniform_proposal_linear",
     "paper_linear_rows and 16-", "positive_nonlinearity",
 ])
 
@@ -40,6 +40,13 @@ MUTATIONS = {
                     "scale = sqrt(orc_sigma2(K, p->beta_p, p->alpha_star, m / 2 + 1));"),
     "grid_sin_as_cos": ("s += xh[k - 1] * cos(k * xi) + xh[K + k - 1] * sin(k * xi);",
                         "s += xh[k - 1] * cos(k * xi) + xh[K + k - 1] * cos(k * xi);"),
+    "philox_multipliers_swapped": (
+        "uint64_t prod_a = (uint64_t)PHILOX_MUL_A * (uint64_t)x0;\n        uint64_t prod_b = (uint64_t)PHILOX_MUL_B * (uint64_t)x2;",
+        "uint64_t prod_a = (uint64_t)PHILOX_MUL_B * (uint64_t)x0;\n        uint64_t prod_b = (uint64_t)PHILOX_MUL_A * (uint64_t)x2;"),
+    "philox_weyl_constant": ("static const uint32_t PHILOX_WEYL_B = 0xBB67AE85u;",
+                             "static const uint32_t PHILOX_WEYL_B = 0xBB67AE87u;"),
+    "philox_word_order": ("uint32_t y0 = hi_b ^ x1 ^ k0;", "uint32_t y0 = hi_a ^ x1 ^ k0;"),
+    "philox_nine_rounds": ("for (int round = 0; round < 10; ++round) {", "for (int round = 0; round < 9; ++round) {"),
     "box_muller_pair": ("z[2 * m + 1] = r * sin(th);", "z[2 * m + 1] = r * cos(th);"),
     "box_muller_radius": ("double r = sqrt(-2.0 * log(u1));", "double r = sqrt(-log(u1));"),
     "hamiltonian_sign": ("return beta_p / (E0 * (double)K * K) * (H2 - c32 * H3);",

@@ -69,7 +69,7 @@ def test_appendix_A_two_mode_exact(E0):
         assert oracle.H3_quad(xh, E0, 7) == pytest.approx(H3, rel=1e-12, abs=1e-14)
 
 
-@pytest.mark.parametrize("K", [2, 8, 16, 32, 64])
+@pytest.mark.parametrize("K", [2, 8, 16, 32, 64, 128])
 def test_dirichlet_kernel_closed_forms(K):
     """Zero-mean Dirichlet kernel u^_k = sqrt(E0/(2 pi K)) (Sec. IV.A):
     H2 = E0 (K+1)(2K+1)/6, H3 = E0^{3/2} (K-1)/(2 sqrt(2 pi K)), u(0) = sqrt(2 K E0/pi)."""
@@ -89,7 +89,7 @@ def test_dirichlet_kernel_closed_forms(K):
         assert oracle.H3_triad(plan.dirichlet_direction(32), 1.0) == pytest.approx(1.093117, abs=1e-6)
 
 
-@pytest.mark.parametrize("K", [3, 8, 16, 32, 64])
+@pytest.mark.parametrize("K", [3, 8, 16, 32, 64, 128])
 def test_double_sum_equals_quadrature_iff_grid_fine_enough(K):
     """The double sum (Sec. IV.A) and the trapezoid rule on (1/6) int u^3
     (Sec. II.A) agree for N >= 3K + 1 (u^3 has degree 3K) and not at N = 3K."""
@@ -158,6 +158,10 @@ def test_alpha_star_paper_figure_1():
     assert all(x > 1.0 for x in seq)
     assert seq[-1] - 1.0 < 0.06
     assert plan.alpha_star(16, 0.0) == 1.0
+    # the roots of F (Sec. III.A) at beta' = 20, found once by 50-digit mpmath
+    # bisection and rounded to 4 decimals
+    for K, ref in zip((8, 16, 32, 64, 128), (2.2827, 1.5021, 1.2279, 1.1089, 1.0533)):
+        assert plan.alpha_star(K, 20.0) == pytest.approx(ref, abs=6e-5)
     for K, bp in [(8, 40.0), (16, 60.0), (32, 20.0), (64, 40.0)]:
         a = plan.alpha_star(K, bp)
         assert abs(oracle.F_alpha(K, bp, a)) < 1e-14
@@ -220,6 +224,23 @@ def test_philox_words_statistics():
     assert not np.array_equal(a, oracle.proposal_words(1, 5 + (1 << 32), 0, 8))
     # uniforms are strictly inside (0, 1)
     assert oracle.uniform_of_word(0) > 0 and oracle.uniform_of_word(0xFFFFFFFF) < 1
+
+
+def test_philox_known_answers():
+    """The generator's published known-answer vectors (tests/golden/philox_kat.txt):
+    these fix the multipliers, the Weyl constants, the word order of a round and
+    the round count, which the statistical pins below cannot tell apart."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox_kat.txt")
+    n = 0
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            v = [int(w, 16) for w in line.split()]
+            out = oracle.philox4x32_10(np.array(v[0:4], dtype=np.uint32), np.array(v[4:6], dtype=np.uint32))
+            assert [int(o) for o in out] == v[6:10]
+            n += 1
+    assert n == 3
 
 
 def test_philox_round_structure():
