@@ -24,12 +24,15 @@ learned defensive-mixture proposal against the paper's Sigma proposal.
 with the autotuner's launch configuration.
 --workload sir: sampling-importance resampling at one K = 32 point (effective
 samples/s), beside the rejection sampler and the extreme-wave search.
+--workload k128: the paper's sampler at K = 128 (N = 512; the mode count of
+its parallel speed-up study), 4 points x 1e9 proposals, quarter-period
+synthesis.
 --synthesis: the standalone synthesis on the precision configuration (K = 64,
 2^20 rows of x^ in HBM; HBM roofline), plus the same synthesis with x^ drawn
 in registers (the decision kernel).
 
 Prints one JSON line with the roofline of the dominant kernel (ALU-bound:
-algorithmic issue slots, alu_ops_per_proposal) from HIP events recorded
+method-level issue slots, method_ops_per_proposal) from HIP events recorded
 inside the library on the kernel's own stream, and the CPU FP64 oracle's
 throughput on a bounded sample of the same workload (all host threads, and
 one thread).
@@ -61,6 +64,14 @@ PACKED_FP32_OPS_PER_S = 2 * ALU_OPS_PER_S
 HBM_BYTES_PER_S = 8.0e12
 
 
+def dtype_label(precision: str) -> str:
+    """Arithmetic of the sampling path: the synthesis products, FP32 for the
+    rest of each proposal, FP64 for the re-decision near the threshold and for
+    the moment sums."""
+    return {"bf16x3": "bf16x3 synthesis + f32 + f64 re-decision",
+            "fp32": "f32 synthesis + f32 + f64 re-decision"}[precision]
+
+
 def alu_roof(achieved: float, **extra) -> dict:
     """Roofline object of an ALU-bound kernel (achieved in lane-operations/s)."""
     r = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_OPS_PER_S / 1e12, "unit": "T ALU ops/s",
@@ -71,55 +82,71 @@ def alu_roof(achieved: float, **extra) -> dict:
     return r
 
 
-def alu_ops_per_proposal(K: int, proposal: str = "sigma", precision: str = "bf16x3",
-                         scaled_odd_rows: bool = True) -> float:
-    """Vector-ALU issue slots one proposal needs: each operation the method
-    performs, counted as the gfx950 instructions that carry it (a 32x32 -> 64-bit
-    product, a three-input XOR, an FMA: one slot each; the transcendentals
-    log2, exp2, sqrt, 1/sqrt, sin, cos: one issue slot each, their execution
-    overlapping the vector ALU), so that the count compares with the issue
-    peak ALU_OPS_PER_S:
+def method_ops_per_proposal(K: int, proposal: str = "sigma", precision: str = "bf16x3") -> float:
+    """Vector-ALU operations one proposal of the method needs, counted once
+    and kept fixed: the yardstick of the ALU roofline does not move when a
+    kernel finds a cheaper route to the same result (the half- and
+    quarter-period syntheses, tables scaled by sqrt 3, the folded Cholesky
+    factor: their gain shows as a higher fraction).  Each operation is priced
+    at the gfx950 instructions that carry it in the plain form of the method
+    (a 32x32 -> 64-bit product, a three-input XOR, an FMA: one issue slot
+    each; a transcendental -- log2, exp2, sqrt, 1/sqrt, sin, cos -- one issue
+    slot, its execution overlapping the vector ALU):
       Philox4x32-10: K/2 + 1 blocks x 10 rounds x (2 products + 2 three-input XORs)  = 40 (K/2 + 1)
       word -> uniform (2K + 1 words, convert + scale)                               = 2 (2K + 1)
       Box-Muller: K pairs x (log2, sqrt, sin, cos; log scale, 2 products)           = 7 K
       Sigma scaling (2K products; uniform proposal: none)                           = 2 K
       |x|^2 and t = sum k^2 s_k (square, add, FMA per coordinate), lane sums,
         1/sqrt, t scaling                                                           = 6 K + 7
-      synthesis operands (BF16x3: round pair, two unpacks, two subtractions, round
-        pair per two coordinates; BF16: round pair; FP32: none)                     = 6 K / K / 0
-      sum of cubes over the N = 4K grid values: half-period form (K >= 16), 2K
-        pairs, E E, q = o o + E E, s += E q with o = sqrt(3) O read from tables
-        whose odd-mode rows carry sqrt(3): 3 per pair (4 from the plain tables,
-        scaled_odd_rows=False); K = 8: u u and s += u u^2 per grid value      = 6 K / 8 K
+      BF16x3 operands (per coordinate: round, subtract, round)                      = 6 K
+      sum of cubes over the N = 4K grid values of the plain synthesis (u u, then
+        s += u u^2 per value)                                                       = 8 K
       lane sum and scaling of S3, log a (with log1p), log U, exp2, window edges,
         comparisons                                                                 = 24
-    The synthesis products themselves run on the matrix cores.  The learned
-    mixture adds mixture_extra_ops."""
-    split = {"bf16x3": 6 * K, "bf16": K, "fp32": 0}[precision]
+    The synthesis products run on the matrix cores (method_mfma_flops).  The
+    learned mixture adds, per proposal: component choice from one word (6);
+    the Box-Muller pair eta (9); the low-rank part of the draw (4K); Q = X^T A X
+    (2K); per shift j < S = 32 the 2x2 quadratic form y^T G^-1 y (5), r_j (1),
+    log2, running minimum, exp2 and its sum (4): 10 S; the final log-sum and the
+    two-term mixture (20).  At K = 32 with BF16x3: 1769 (Sigma), 2316 (mixture)."""
+    split = {"bf16x3": 6 * K, "fp32": 0}[precision]
     scale = 2 * K if proposal in ("sigma", "mixture") else 0
-    cubes = 6 * K if (K >= 16 and scaled_odd_rows) else 8 * K
-    base = 40 * (K / 2 + 1) + 2 * (2 * K + 1) + 7 * K + scale + 6 * K + 7 + split + cubes + 24
-    return base + (mixture_extra_ops(K) if proposal == "mixture" else 0)
+    base = 40 * (K / 2 + 1) + 2 * (2 * K + 1) + 7 * K + scale + 6 * K + 7 + split + 8 * K + 24
+    if proposal == "mixture":
+        base += 6 + 9 + 4 * K + 2 * K + 10 * 32 + 20
+    return base
 
 
-def mixture_extra_ops(K: int, S: int = 32) -> float:
-    """Issue slots the learned mixture adds per proposal: component choice from
-    one word (6); the Box-Muller pair eta (2 conversions, 4 transcendentals, 3:
-    9); the low-rank part of the draw (2 FMA per coordinate: 4K); Q = X^T A X
-    (2K); per shift j < S: |z_j|^2 (the 2x2 form y^T G^-1 y with the Cholesky
-    factor of G^-1 folded into the tables: 2) and r_j (1), log2, running
-    minimum, exp2 and its sum (4) = 7 S; the final log-sum and the two-term
-    mixture (20)."""
-    return 6 + 9 + 4 * K + 2 * K + 7 * S + 20
+def method_mfma_flops(K: int, precision: str = "bf16x3", proposal: str = "sigma") -> float:
+    """Matrix flops of the method per proposal: the plain synthesis product
+    (2K x N with N = 4K, 2 flops per product, per product term: three for
+    BF16x3); the mixture adds y = (R_j A V)^T x for 32 shifts x rank 2 rows."""
+    rows = 4 * K + (64 if proposal == "mixture" else 0)
+    return {"bf16x3": 3, "fp32": 1}[precision] * 2 * (2 * K) * rows
 
 
-def mfma_flops_per_proposal(K: int, precision: str = "bf16x3", proposal: str = "sigma") -> float:
-    """Matrix flops executed per proposal: the synthesis in the half-period form
-    (K >= 16: the even- and odd-mode products on half the grid, 2 x 2K x N/2
-    flops per product term, half the plain product's 2 x 2K x N; K = 8 the plain
-    product); the mixture adds y = (R_j A V)^T x for S = 32 shifts x rank 2 rows."""
-    rows = (2 * K if K >= 16 else 4 * K) + (64 if proposal == "mixture" else 0)
-    return {"bf16x3": 3, "bf16": 1, "fp32": 1}[precision] * 2 * (2 * K) * rows
+def executed_mfma_flops(K: int, precision: str = "bf16x3", proposal: str = "sigma") -> float:
+    """Matrix flops the kernels execute per proposal: K = 8 the plain product;
+    16 <= K <= 64 the half-period form (even and odd modes on half the grid:
+    half the plain product); K = 128 the quarter-period form (cos/sin blocks and
+    mode parities on a quarter of the offset grid: a quarter); the mixture's y
+    products in full."""
+    frac = 1.0 if K == 8 else (0.5 if K <= 64 else 0.25)
+    terms = {"bf16x3": 3, "fp32": 1}[precision]
+    y = 2 * (2 * K) * 64 if proposal == "mixture" else 0
+    return terms * (frac * 2 * (2 * K) * (4 * K) + y)
+
+
+def mfma_peak(precision: str) -> float:
+    """Dense matrix peak of MI355X for the products' type (flop/s)."""
+    return 157.3e12 if precision == "fp32" else 2.5e15
+
+
+def mfma_fields(K: int, precision: str, proposal: str, proposals_per_s: float) -> dict:
+    ex, me = executed_mfma_flops(K, precision, proposal), method_mfma_flops(K, precision, proposal)
+    pk = mfma_peak(precision)
+    return {"mfma_flops_executed_per_proposal": ex, "mfma_flops_method_per_proposal": me,
+            "mfma_frac_executed": ex * proposals_per_s / pk, "mfma_frac_method": me * proposals_per_s / pk}
 
 
 def kernel_source_digest(files=("tkdv_device.h", "tkdv_kernels.hip")) -> str:
@@ -208,7 +235,7 @@ def synthesis_bench(args) -> int:
         sec = avg * 1e-3
         res[name] = {"ms": avg, "rows_per_s": n / sec, "hbm_GBps": bytes_ / sec / 1e9,
                      "hbm_frac": bytes_ / sec / HBM_BYTES_PER_S,
-                     "mfma_frac_executed": executed / sec / peak, "dense_equivalent_frac": dense / sec / peak,
+                     "mfma_frac_executed": executed / sec / peak, "mfma_frac_method": dense / sec / peak,
                      "grid": ctx.timing()["decide_grid"], "block": ctx.timing()["decide_block"]}
         print(f"synthesis {name}: {avg:.4f} ms", file=sys.stderr, flush=True)
     # the same synthesis with x^ drawn in registers instead of read (Philox, Box-Muller, Sigma
@@ -222,8 +249,8 @@ def synthesis_bench(args) -> int:
     g_ms = sum(gen_ms) / len(gen_ms)
     res["bf16x3_from_philox"] = {
         "ms": g_ms, "proposals": n_gen, "rows_per_s": n_gen / (g_ms * 1e-3),
-        "mfma_frac_executed": mfma_flops_per_proposal(K) * n_gen / (g_ms * 1e-3) / 2.5e15,
-        "alu_frac": alu_ops_per_proposal(K) * n_gen / (g_ms * 1e-3) / ALU_OPS_PER_S,
+        **mfma_fields(K, "bf16x3", "sigma", n_gen / (g_ms * 1e-3)),
+        "alu_frac": method_ops_per_proposal(K) * n_gen / (g_ms * 1e-3) / ALU_OPS_PER_S,
         "kernel": "k_decide (half-period synthesis, decisions included)"}
     print(f"synthesis from Philox (k_decide, {n_gen} proposals): {g_ms:.3f} ms", file=sys.stderr, flush=True)
     r = res["bf16x3"]
@@ -297,13 +324,14 @@ def sir_bench(args) -> int:
           file=sys.stderr, flush=True)
     avg_w = sum(wms) / len(wms) / 1e3
     # the power sums read the plain tables (4 per pair for the cubes), + S1, S2, S4
-    ops = alu_ops_per_proposal(K, "sigma", args.precision, scaled_odd_rows=False) + 12 * K
-    roof = alu_roof(ops * n / avg_w, traffic=None, kernel="k_sir_weights", algorithmic_ops_per_proposal=ops,
+    # the power sums S1, S2, S4 beside the cubes: 3 more per grid value
+    ops = method_ops_per_proposal(K, "sigma", args.precision) + 12 * K
+    roof = alu_roof(ops * n / avg_w, traffic=None, kernel="k_sir_weights", method_ops_per_proposal=ops,
                     avg_launch_ms=avg_w * 1e3, proposals_per_launch=n,
                     note="4 B written per proposal (the weights) + 8 B per tile (tile sums)")
     line = {"metric": "effective samples/sec (SIR, K=32)", "value": sum(ess) / dt, "unit": "effective samples/s",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype_label(args.precision),
             "data": "synthetic",
             "config": {"workload": f"SIR over {n:.3g} Sigma proposals of K=32, beta'=40, C3/C2={c}, "
                                    f"{m} systematic draws with rows", "K": K, "proposals": n, "draws": m,
@@ -367,16 +395,14 @@ def plain_bench(args) -> int:
 
     avg_decide_s = sum(decide_ms) / len(decide_ms) / 1e3
     per_launch_props = n_per * len(pts)
-    ops = alu_ops_per_proposal(K, "sigma", args.precision)
+    ops = method_ops_per_proposal(K, "sigma", args.precision)
     achieved = ops * per_launch_props / avg_decide_s
     traffic = load_traffic(K, args.precision, per_launch_props)
     roof = alu_roof(achieved, traffic=traffic, kernel="k_decide",
-                    algorithmic_ops_per_proposal=ops,
+                    method_ops_per_proposal=ops,
                     avg_launch_ms=avg_decide_s * 1e3,
                     proposals_per_launch=per_launch_props,
-                    mfma_flops_per_proposal=mfma_flops_per_proposal(K, args.precision),
-                    mfma_frac=mfma_flops_per_proposal(K, args.precision) * per_launch_props / avg_decide_s
-                    / (2.5e15 if args.precision != "fp32" else 157.3e12))
+                    **mfma_fields(K, args.precision, "sigma", per_launch_props / avg_decide_s))
 
     cpu = None
     n_cpu = (1 << 22) if args.cpu_sample < 0 else args.cpu_sample
@@ -395,7 +421,7 @@ def plain_bench(args) -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": dtype_label(args.precision),
         "data": "synthetic",
         "config": {
             "workload": "plain GPU sweep: K=32, N=128, E0=1, Sigma proposal, beta' in "
@@ -450,6 +476,87 @@ def cpu_baseline_mixture(points, mixtures, mix_plans, n_sample: int) -> dict:
         "single_core": {"value": acc1 / dt1, "proposals_per_s": n_one * len(points) / dt1, "accepted": acc1,
                         "seconds": dt1, "sample": f"first {n_one} proposal indices of each point, one thread"},
     }
+
+
+def k128_bench(args) -> int:
+    """K = 128 (N = 512): the paper's Sigma sampler on 4 points (beta' in
+    {20, 40} x beta' C3/C2 in {30000, 40000}), 1e9 proposals per point in one
+    batched call (the quarter-period decision kernel k_decide128), all
+    statistics and up to 2^20 samples per point stored.  value = accepted
+    samples/s; the roofline is k_decide128's launch."""
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs an MI355X GPU", file=sys.stderr)
+        return 1
+    from paper_2411_16952_amd import tkdv as T
+    from paper_2411_16952_amd import workloads as W
+
+    specs = W.k128_points()
+    pts = [T.make_point(s.K, s.E0, s.beta_p, s.c32, seed=s.seed, point_id=s.point_id) for s in specs]
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=len(pts)) as ex:   # the host search of log M (256 coordinates)
+        plans = list(ex.map(lambda p: T.plan_point(p, T.SIGMA), pts))
+    plan_s = time.perf_counter() - t0
+    K = 128
+    n_per = int(args.proposals)
+    n = [n_per] * len(pts)
+    cap = [1 << 20] * len(pts)
+    prec = T.PRECISIONS[args.precision]
+    ctx = T.Context(0)
+    print(f"bench: K=128, {len(pts)} points, {n_per:.3g} proposals/point, {args.precision}, plans {plan_s:.1f}s",
+          file=sys.stderr, flush=True)
+
+    def step():
+        out, _, _ = ctx.sample_batch(pts, n, plans=plans, precision=prec, capacity=cap)
+        return out, ctx.timing()
+
+    for w in range(args.warmup):
+        _, tm = step()
+        print(f"warmup {w}: {tm['total_ms']:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    acc, decide_ms, out, tm = 0, [], None, None
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        out, tm = step()
+        acc += sum(int(o["n_accepted"]) for o in out)
+        decide_ms.append(tm["decide_ms"] / max(tm["decide_launches"], 1))
+        print(f"step {s}: {tm['total_ms']:.1f} ms, decide {tm['decide_ms']:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n_prop = n_per * len(pts) * args.steps
+    avg_decide_s = sum(decide_ms) / len(decide_ms) / 1e3
+    per_launch = n_per * len(pts)
+    ops = method_ops_per_proposal(K, "sigma", args.precision)
+    roof = alu_roof(ops * per_launch / avg_decide_s, traffic=load_traffic(K, args.precision, per_launch,
+                                                                           "k_decide128"),
+                    kernel="k_decide128", method_ops_per_proposal=ops, avg_launch_ms=avg_decide_s * 1e3,
+                    proposals_per_launch=per_launch,
+                    **mfma_fields(K, args.precision, "sigma", per_launch / avg_decide_s))
+    n_cpu = (1 << 15) if args.cpu_sample < 0 else args.cpu_sample
+    cpu = None
+    if n_cpu > 0:
+        print("cpu baseline ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(specs, plans, n_cpu)
+    line = {
+        "metric": "accepted samples/sec at K=128 (plain Sigma proposal); proposals/sec",
+        "value": acc / dt, "unit": "accepted samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype_label(args.precision), "data": "synthetic",
+        "config": {"workload": "K=128, N=512, E0=1, Sigma proposal, beta' in {20,40} x beta'C3/C2 in "
+                               "{30000,40000}, 1e9 proposals/point (the mode count of the paper's speed-up study)",
+                   "K": K, "N": 4 * K, "points": len(pts), "proposals_per_point": n_per,
+                   "synthesis": args.precision, "fp64_redecision": True},
+        "proposals_per_s": n_prop / dt, "acceptance": acc / n_prop,
+        "per_point": [{"beta_p": s.beta_p, "level": s.beta_p * s.c32, "acceptance": int(o["n_accepted"]) / n_per,
+                       "skewness": o["skewness"], "kurtosis": o["kurtosis"],
+                       "fp64_redecisions": int(o["n_fp64_fixups"])} for s, o in zip(specs, out)],
+        "plan_seconds": plan_s,
+        "phase_ms_last_step": {k: round(v, 3) for k, v in tm.items() if k.endswith("_ms")},
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+    return 0
 
 
 def learned_bench(args) -> int:
@@ -544,14 +651,12 @@ def learned_bench(args) -> int:
 
     # roofline of the dominant kernel: k_decide_mix, one launch per point
     avg_launch_s = dec_ms_m / max(launches_m, 1) / 1e3
-    ops = alu_ops_per_proposal(K, "mixture", args.precision)
+    ops = method_ops_per_proposal(K, "mixture", args.precision)
     achieved = ops * n_per / avg_launch_s
-    mflops = mfma_flops_per_proposal(K, args.precision, "mixture")
     roof = alu_roof(achieved, traffic=load_traffic(K, args.precision, n_per, "k_decide_mix"),
-                    kernel="k_decide_mix", algorithmic_ops_per_proposal=ops,
+                    kernel="k_decide_mix", method_ops_per_proposal=ops,
                     avg_launch_ms=avg_launch_s * 1e3, proposals_per_launch=n_per,
-                    mfma_flops_per_proposal=mflops,
-                    mfma_frac=mflops * n_per / avg_launch_s / (2.5e15 if args.precision != "fp32" else 157.3e12))
+                    **mfma_fields(K, args.precision, "mixture", n_per / avg_launch_s))
 
     n_cpu = (1 << 17) if args.cpu_sample < 0 else args.cpu_sample
     cpu = cpu_plain = None
@@ -575,7 +680,7 @@ def learned_bench(args) -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": dtype_label(args.precision),
         "data": "synthetic",
         "config": {
             "workload": "learned mixture vs plain Sigma: K=32, N=128, E0=1, 16 beta' in [20, 60] x "
@@ -671,7 +776,7 @@ def sweep_bench(args) -> int:
         windows.append(ctx.timing()["windows"])
         acc += sum(int(o["n_accepted"]) for o in out)
         prop += sum(int(o["n_proposed"]) for o in out)
-        ops += sum(alu_ops_per_proposal(p.K, "sigma", args.precision) * int(o["n_proposed"])
+        ops += sum(method_ops_per_proposal(p.K, "sigma", args.precision) * int(o["n_proposed"])
                    for p, o in zip(pts, out))
         print(f"sweep step {s}: {ctx.timing()['total_ms']:.0f} ms, {windows[-1]} windows", file=sys.stderr,
               flush=True)
@@ -679,7 +784,7 @@ def sweep_bench(args) -> int:
     dt = time.perf_counter() - t0
     met = sum(int(o["n_accepted"]) >= t for o, t in zip(out, targets))
     roof = alu_roof(ops / dt, traffic=None, kernel="k_decide (all K, whole sweep)",
-                    note="algorithmic ops of all proposals over the whole sweep's wall time (every phase), a "
+                    note="method-level ops of all proposals over the whole sweep's wall time (every phase), a "
                          "lower bound on the decide kernels' own rate")
     n_cpu = (1 << 12) if args.cpu_sample < 0 else args.cpu_sample
     cpu = cpu_baseline(pts, kept_plans, n_cpu) if n_cpu > 0 else None
@@ -687,7 +792,7 @@ def sweep_bench(args) -> int:
         "metric": "accepted samples/sec, batched sweep (256 points, K in {16,32,64}, accepted targets)",
         "value": acc / dt, "unit": "accepted samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": dtype_label(args.precision), "data": "synthetic",
         "config": {"workload": "batched sweep: 256 points, K uniform in {16,32,64}, beta' ~ U[10,80], E0 in "
                                "{0.5,1,pi/2,2}, beta'C3/C2 sqrt(E0) ~ U[0, P_max(K)], acceptance >= 1e-4, "
                                "targets log-uniform in [1e4,1e6], cap 1e10 proposals/point, windows as hipGraph "
@@ -708,10 +813,11 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="learned", choices=["learned", "plain", "sweep", "sir"])
+    ap.add_argument("--workload", default="learned", choices=["learned", "plain", "sweep", "sir", "k128"])
     ap.add_argument("--tune-cache", default="/tmp/tkdv_autotune.txt", help="autotuner cache (sweep workload)")
     ap.add_argument("--proposals", type=float, default=1e9, help="proposals per point (per sampler)")
-    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16", "bf16x3"])
+    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3"],
+                    help="synthesis products of the sampling workloads (plain BF16 takes no decisions)")
     ap.add_argument("--cpu-sample", type=int, default=-1,
                     help="oracle proposals per point (0: skip; default 2^22 plain, 2^17 learned)")
     ap.add_argument("--train-rounds", type=int, default=6)
@@ -743,6 +849,8 @@ def main() -> int:
         return sweep_bench(args)
     if args.workload == "sir":
         return sir_bench(args)
+    if args.workload == "k128":
+        return k128_bench(args)
     return learned_bench(args) if args.workload == "learned" else plain_bench(args)
 
 

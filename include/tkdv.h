@@ -41,7 +41,12 @@
  * pointers are caller-owned HIP device allocations; host pointers are plain
  * host memory.  `stream` is a hipStream_t (NULL = the default stream); calls
  * are stream-ordered and return after the host-side statistics are complete.
- * Supported mode counts on the GPU: K in {8, 16, 32, 64}, grid N = 4K.
+ * Supported mode counts on the GPU: K in {8, 16, 32, 64, 128}, grid N = 4K
+ * (the learned mixture K <= 32; SIR, the extreme-wave search and the
+ * standalone synthesis K <= 64).  At K = 128 the grid sum of cubes behind H3
+ * is formed on the grid offset by half a step (exact there as well, N >= 3K+1)
+ * from a quarter of it: the cos and sin blocks and the even and odd modes are
+ * synthesised separately, and the four quadrants follow by symmetry.
  */
 #ifndef TKDV_H
 #define TKDV_H
@@ -52,7 +57,7 @@
 extern "C" {
 #endif
 
-#define TKDV_KMAX 64
+#define TKDV_KMAX 128
 #define TKDV_NBINS 64
 
 typedef enum {
@@ -61,9 +66,27 @@ typedef enum {
     TKDV_E_NO_ALPHA_ROOT = -2, /* F has no root: beta' >= K^2 sum_{k<=K} 1/k^2 (Sec. III.A)   */
     TKDV_E_DEVICE = -3,        /* a HIP call failed; tkdv_last_error() has the text            */
     TKDV_E_CAPACITY = -4,      /* an internal work list overflowed                            */
-    TKDV_E_UNSUPPORTED = -5,   /* K not in {8, 16, 32, 64} on the GPU path                     */
-    TKDV_E_M_VIOLATION = -6    /* reserved: a proposal had f/(M g) > 1                        */
+    TKDV_E_UNSUPPORTED = -5,   /* K not supported on the GPU path, or plain BF16 decisions     */
+    TKDV_E_M_VIOLATION = -6    /* a proposal had f/(M g) > 1 and the policy did not repair it */
 } tkdv_status;
+
+/*
+ * The rejection bound f <= M g must hold on the whole sphere (Sec. IV.A, the
+ * definition of M as a supremum); M comes from a numerical search, which
+ * bounds the supremum only from below.  Every sampling call counts proposals
+ * with log a = log f/(M g) > 0 (n_M_violations; decisions inside the FP64
+ * window by their FP64 value) and then acts by the context's policy:
+ *   TKDV_MV_RAISE (default): raise log M above the largest log a seen (its
+ *     FP32 value, plus half the decision window that bounds that value's
+ *     error, plus log 1.02), discard the point's output and run it again from
+ *     its first proposal, at most 4 times; the learned mixture then falls back
+ *     to the paper's Sigma sampler (planned on the host), the paper's
+ *     proposals return TKDV_E_M_VIOLATION.  The statistics report the log M
+ *     of the returned samples, the number of raises and the fallback;
+ *   TKDV_MV_FAIL: return TKDV_E_M_VIOLATION (outputs are those of the run);
+ *   TKDV_MV_COUNT: only count (the samples are then not exact).
+ */
+typedef enum { TKDV_MV_RAISE = 0, TKDV_MV_FAIL = 1, TKDV_MV_COUNT = 2 } tkdv_violation_policy;
 
 typedef enum { TKDV_PROP_UNIFORM = 0, TKDV_PROP_SIGMA = 1, TKDV_PROP_MIXTURE = 2 } tkdv_proposal;
 
@@ -99,7 +122,12 @@ typedef struct {
 /* Arithmetic of the spectral-to-grid synthesis U = X^ Phi on the matrix cores:
  * FP32 products, BF16 products (one term), or BF16 with 3-term split
  * (hi*hi + hi*lo + lo*hi) and FP32 accumulation.  All other per-proposal
- * arithmetic is FP32; the decision window is re-evaluated in FP64.           */
+ * arithmetic is FP32; the decision window is re-evaluated in FP64.
+ * Worst-case error of H3 against the cube-sum scale (pi/3N) sum_j |u_j|^3,
+ * measured on 2^21 proposals at K = 64: FP32 below 1e-6, BF16x3 below 1e-5,
+ * plain BF16 2.9e-3 (median 2.8e-4).  Plain BF16 therefore misses a 1e-3
+ * tolerance on H and is offered by tkdv_synthesize only: every entry point
+ * that takes accept decisions returns TKDV_E_UNSUPPORTED for it.             */
 typedef enum { TKDV_FP32 = 0, TKDV_BF16 = 1, TKDV_BF16X3 = 2 } tkdv_precision;
 
 typedef enum { TKDV_COUNT_PROPOSALS = 0, TKDV_COUNT_ACCEPTED = 1 } tkdv_count_mode;
@@ -144,6 +172,9 @@ typedef struct {
     double p_exceed_2sigma;   /* n_exceed_2sigma / n_grid_values                             */
     double hist_lo, hist_hi;  /* [-u_max, u_max], u_max = sqrt(2 K E0/pi)                     */
     uint64_t hist_u0[TKDV_NBINS]; /* 64 equal bins of u(0), clamped                          */
+    double log_M_used;        /* log M of the returned samples (raised after a violation)    */
+    int32_t M_raises;         /* runs repeated with a raised M (TKDV_MV_RAISE)               */
+    int32_t fallback;         /* 1: the mixture sampler fell back to the Sigma sampler       */
 } tkdv_stats;
 
 /* Device time of the phases of the last tkdv_sample / tkdv_sample_batch /
@@ -191,7 +222,9 @@ tkdv_status tkdv_plan_point(const tkdv_point *pt, tkdv_proposal proposal, tkdv_p
  * does not depend on the other points of the call.  The value and
  * gradient use the exact N = 4K grid quadrature of H3.  The result is a
  * lower bound on the supremum, like any search (M_source = 2).
- *   n_points >= 0; pts and out: host arrays [n_points]; 1 <= K <= 64 (any K);
+ *   n_points >= 0; pts and out: host arrays [n_points]; 1 <= K <= 128 (any
+ *   K; points with K > 64 are searched on the host as tkdv_plan_point does,
+ *   M_source = 1, their xhat_best row zero);
  *   n_starts in [1, 256]; proposal UNIFORM or SIGMA;
  *   xhat_best: host [n_points][2 TKDV_KMAX] doubles or NULL; row p receives
  *     the maximiser found (first 2K entries, unit norm; zeros where the
@@ -432,6 +465,16 @@ tkdv_status tkdv_learner_add_rows(tkdv_learner *learner, int32_t point, const fl
                                   uint64_t n, int32_t kind, void *stream);
 tkdv_status tkdv_learner_add_rows_host(tkdv_learner *learner, int32_t point, const double *h_xhat, uint64_t n,
                                        int32_t kind);
+/* Append, for each of the n host FP64 rows h_xhat [n][2K] (normalised in
+ * FP64), its copies with the field translated by each phase of h_phi
+ * [n_phi]: u(xi) -> u(xi + phi), i.e. the (cos, sin) pair of mode k rotated
+ * by the angle k phi (f is invariant under these shifts, Sec. II.A-C; the
+ * mixture only under multiples of 2 pi/S, so shifted copies of a point where
+ * f/q_mix is large are informative rows).  phi = 0 keeps the row itself.
+ * Row (r, q) is appended at position r n_phi + q; the rotation runs on the
+ * device in FP64.  1 <= n_phi <= 4096, phases finite; TKDV_E_ARG otherwise. */
+tkdv_status tkdv_learner_add_shifted_rows(tkdv_learner *learner, int32_t point, const double *h_xhat, uint64_t n,
+                                          const double *h_phi, int32_t n_phi, int32_t kind);
 /* n_steps Adam steps; h_loss (host [n_points], may be NULL) receives the
  * per-point loss at the weights before the last step. */
 tkdv_status tkdv_learner_train(tkdv_learner *learner, int32_t n_steps, double *h_loss, void *stream);
@@ -490,6 +533,9 @@ tkdv_status tkdv_get_launch_cfg(const tkdv_ctx *ctx, int32_t K, tkdv_precision p
  * *out (may be NULL) receives the choice. */
 tkdv_status tkdv_autotune(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, const char *cache_path,
                           tkdv_launch_cfg *out);
+
+/* The context's policy for proposals with f/(M g) > 1 (see tkdv_violation_policy). */
+tkdv_status tkdv_set_violation_policy(tkdv_ctx *ctx, tkdv_violation_policy policy);
 
 /* Phase timings of the last call on this context (see tkdv_timing). */
 tkdv_status tkdv_get_timing(const tkdv_ctx *ctx, tkdv_timing *out);

@@ -27,6 +27,12 @@ namespace {
 
 const double kPi = 3.14159265358979323846;
 
+// Plain BF16 products miss the 1e-3 tolerance on H3 in the worst case, so no
+// accept decision is taken with them; the synthesis alone still offers them.
+const char *const kBf16Refused =
+    "plain BF16 synthesis is not used for decisions: its worst-case H3 error exceeds 1e-3 of the "
+    "cube-sum scale (use TKDV_BF16X3 or TKDV_FP32)";
+
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -35,6 +41,8 @@ struct DevBuf {
 std::mutex g_err_mu;
 std::string g_last_error;  // for calls without a context
 
+// The GPU path's mode counts: K = 8 << ki for ki < kNumK.
+constexpr int kNumK = 5;
 int kindex(int K)
 {
     switch (K) {
@@ -42,6 +50,7 @@ int kindex(int K)
     case 16: return 1;
     case 32: return 2;
     case 64: return 3;
+    case 128: return 4;
     default: return -1;
     }
 }
@@ -54,10 +63,12 @@ struct tkdv_ctx {
     std::string last_error;
     DevBuf bitmap, defer_list, defer_count, counters, points, seg_cnt, seg_base, seg_stats, results, plist;
     DevBuf mix, mix_tab;  // learned-proposal constants and tables of the current call
-    DevBuf phi_hi[4], phi_lo[4], phi_f32[4];
+    // K = 128 (index 4): the quarter-period tables of k_decide128 (BF16 hi, lo,
+    // FP32) and, in phi_mat128, the FP32 table of its statistics synthesis
+    DevBuf phi_hi[kNumK], phi_lo[kNumK], phi_f32[kNumK], phi_mat128;
     // the same tables with the odd-mode rows scaled by sqrt(3), for the kernels
     // that form S3 in the half-period form (K >= 16): s3_tables()
-    DevBuf phi3_hi[4], phi3_lo[4], phi3_f32[4];
+    DevBuf phi3_hi[kNumK], phi3_lo[kNumK], phi3_f32[kNumK];
     void *h_results = nullptr;  // pinned
     size_t h_results_bytes = 0;
     void *h_counters = nullptr;  // pinned
@@ -70,7 +81,7 @@ struct tkdv_ctx {
     tkdv_timing timing = {};
     // sweep: launch configuration per (K index, precision), its own stream
     // (captured into graphs) joined to the caller's stream by events
-    tkdv_launch_cfg lcfg[4][3];
+    tkdv_launch_cfg lcfg[kNumK][3];
     hipStream_t sweep_stream = nullptr;
     hipEvent_t join[2] = {};
     DevBuf sweep, active;
@@ -79,6 +90,7 @@ struct tkdv_ctx {
     DevBuf sir_pt, sir_w, sir_tile, sir_chunk, sir_part;  // tkdv_sir
     void *h_poll = nullptr;  // pinned: active count, FP64 list count
     std::string arch;
+    int mv_policy = TKDV_MV_RAISE;  // what a proposal with f/(M g) > 1 triggers
 };
 
 namespace {
@@ -130,6 +142,76 @@ hipError_t ensure_host(void *&p, size_t &have, size_t bytes)
     return hipSuccess;
 }
 
+// K = 128 tables (tkdv_k128.hip), N = 512.
+//   Quarter-period decision tables on the representatives xi_rho =
+//   pi (2 rho + 1)/N, rho < 128 (the grid offset by half a step, points in
+//   (0, pi/2)): for tile tau (rho = 16 tau + l % 16), output o (0: cos, even
+//   modes; 1: cos, odd modes; 2: sin, even; 3: sin, odd; o > 0 scaled by
+//   sqrt 3) and lane group g = l/16, the entry of mode
+//   k = 32 g + 2 idx + (o even ? 2 : 1), where idx = 8 r + e in the BF16
+//   layout [tau][o][r < 2][64 lanes][e < 8] (hi, lo) and idx = 4 q + e in the
+//   FP32 layout [tau][o][q < 4][64 lanes][e < 4].
+//   Statistics table (FP32, standard grid xi_j = -pi + 2 pi j/N): [T < 32][m4 <
+//   16][64 lanes][e < 4], grid point 16 T + l % 16, k-step m = 4 m4 + e of lane
+//   group g: cos of mode 32 g + m + 1 (m < 32), sin of mode 32 g + m - 31.
+//   Angles are reduced exactly in integers before the FP64 cos/sin.
+tkdv_status build_tables128(tkdv_ctx *ctx)
+{
+    const int K = 128, N = 4 * K;
+    const double r3 = std::sqrt(3.0);
+    // entry of output o at representative rho for mode k: angle k pi (2 rho + 1)/N
+    auto qval = [&](int o, int k, int rho) {
+        const long m = ((long)k * (2 * rho + 1)) % (2 * N);
+        const double ang = kPi * (double)m / N;
+        const double v = (o < 2) ? std::cos(ang) : std::sin(ang);
+        return o == 0 ? v : r3 * v;
+    };
+    auto mode = [](int o, int g, int idx) { return 32 * g + 2 * idx + ((o == 0 || o == 2) ? 2 : 1); };
+    std::vector<uint16_t> hi((size_t)8 * 4 * 2 * 64 * 8), lo(hi.size());
+    for (int tau = 0; tau < 8; ++tau)
+        for (int o = 0; o < 4; ++o)
+            for (int r = 0; r < 2; ++r)
+                for (int l = 0; l < 64; ++l)
+                    for (int e = 0; e < 8; ++e) {
+                        const double v = qval(o, mode(o, l / 16, 8 * r + e), 16 * tau + l % 16);
+                        const uint16_t h = bf16_bits((float)v);
+                        const size_t idx = ((((size_t)tau * 4 + o) * 2 + r) * 64 + l) * 8 + e;
+                        hi[idx] = h;
+                        lo[idx] = bf16_bits((float)(v - (double)bf16_value(h)));
+                    }
+    std::vector<float> f32((size_t)8 * 4 * 4 * 64 * 4);
+    for (int tau = 0; tau < 8; ++tau)
+        for (int o = 0; o < 4; ++o)
+            for (int q = 0; q < 4; ++q)
+                for (int l = 0; l < 64; ++l)
+                    for (int e = 0; e < 4; ++e)
+                        f32[((((size_t)tau * 4 + o) * 4 + q) * 64 + l) * 4 + e] =
+                            (float)qval(o, mode(o, l / 16, 4 * q + e), 16 * tau + l % 16);
+    std::vector<float> mat((size_t)32 * 16 * 64 * 4);
+    for (int T = 0; T < 32; ++T)
+        for (int m4 = 0; m4 < 16; ++m4)
+            for (int l = 0; l < 64; ++l)
+                for (int e = 0; e < 4; ++e) {
+                    const int m = 4 * m4 + e, g = l / 16, j = 16 * T + l % 16;
+                    const bool cosb = m < 32;
+                    const int k = cosb ? 32 * g + m + 1 : 32 * g + m - 31;
+                    const long r = ((long)k * j) % N;
+                    const double ang = 2.0 * kPi * (double)r / N;
+                    const double sign = (k & 1) ? -1.0 : 1.0;  // k xi_j = -k pi + 2 pi (k j mod N)/N
+                    mat[(((size_t)T * 16 + m4) * 64 + l) * 4 + e] =
+                        (float)(cosb ? sign * std::cos(ang) : sign * std::sin(ang));
+                }
+    HIP_TRY(ctx, ensure(ctx->phi_hi[4], hi.size() * 2));
+    HIP_TRY(ctx, ensure(ctx->phi_lo[4], lo.size() * 2));
+    HIP_TRY(ctx, ensure(ctx->phi_f32[4], f32.size() * 4));
+    HIP_TRY(ctx, ensure(ctx->phi_mat128, mat.size() * 4));
+    HIP_TRY(ctx, hipMemcpy(ctx->phi_hi[4].p, hi.data(), hi.size() * 2, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(ctx->phi_lo[4].p, lo.data(), lo.size() * 2, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(ctx->phi_f32[4].p, f32.data(), f32.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(ctx->phi_mat128.p, mat.data(), mat.size() * 4, hipMemcpyHostToDevice));
+    return TKDV_OK;
+}
+
 // Synthesis tables for K modes on the grid xi_j = -pi + 2 pi j/N, N = 4K.
 // Row (block b, mode k) of Phi is cos(k xi_j) (b = 0) or sin(k xi_j) (b = 1);
 // angles are reduced exactly: k xi_j = -k pi + 2 pi (k j mod N)/N.  For
@@ -177,15 +259,22 @@ tkdv_status build_tables(tkdv_ctx *ctx, int K)
         if (e == hipSuccess) e = hipMemcpy(d_f32.p, f32.data(), f32.size() * 4, hipMemcpyHostToDevice);
         return e;
     };
+    if (K == 128) return build_tables128(ctx);
     if (K >= 16) HIP_TRY(ctx, upload(std::sqrt(3.0), ctx->phi3_hi[ki], ctx->phi3_lo[ki], ctx->phi3_f32[ki]));
     HIP_TRY(ctx, upload(1.0, ctx->phi_hi[ki], ctx->phi_lo[ki], ctx->phi_f32[ki]));
     return TKDV_OK;
 }
 
 // Tables read by the S3 kernels (k_decide, k_decide_mix, k_synth): the scaled
-// set in the half-period form (K >= 16), the plain tables at K = 8.
+// set in the half-period form (16 <= K <= 64), the plain tables at K = 8, the
+// quarter-period tables at K = 128.
 void s3_tables(const tkdv_ctx *ctx, int ki, int precision, const void *&hi, const void *&lo)
 {
+    if (ki == 4) {  // K = 128: the quarter-period tables
+        hi = precision == TKDV_FP32 ? ctx->phi_f32[4].p : ctx->phi_hi[4].p;
+        lo = ctx->phi_lo[4].p;
+        return;
+    }
     const bool eo = ki >= 1;
     const DevBuf &h = precision == TKDV_FP32 ? (eo ? ctx->phi3_f32[ki] : ctx->phi_f32[ki])
                                              : (eo ? ctx->phi3_hi[ki] : ctx->phi_hi[ki]);
@@ -196,7 +285,7 @@ void s3_tables(const tkdv_ctx *ctx, int ki, int precision, const void *&hi, cons
 tkdv_status check_point(tkdv_ctx *ctx, const tkdv_point &pt)
 {
     if (pt.K < 1 || pt.K > TKDV_KMAX) return set_err(ctx, TKDV_E_ARG, "K out of range");
-    if (kindex(pt.K) < 0) return set_err(ctx, TKDV_E_UNSUPPORTED, "GPU path supports K in {8,16,32,64}");
+    if (kindex(pt.K) < 0) return set_err(ctx, TKDV_E_UNSUPPORTED, "GPU path supports K in {8,16,32,64,128}");
     if (!std::isfinite(pt.E0) || !(pt.E0 > 0.0)) return set_err(ctx, TKDV_E_ARG, "E0 must be finite and > 0");
     if (!std::isfinite(pt.beta_p) || pt.beta_p < 0.0)
         return set_err(ctx, TKDV_E_ARG, "beta' must be finite and >= 0");
@@ -241,6 +330,25 @@ double window(const tkdv_point &pt, int proposal, int precision, double alpha, d
                        c3coef * umax * (N / 2.0);
     const double err_round = 16.0 * 0x1p-24 * (mag + 30.0);
     return 2.0 * (err_H3term + err_tterm + err_round + extra) + 1e-6;
+}
+
+// The rejection bound f <= M g (Sec. IV.A) with M from a search: after a run
+// that saw log a > 0, log M is raised above the largest log a seen -- its
+// FP32 value plus half the decision window (which bounds that value's error)
+// plus log(1 + kRaiseMargin) -- and the point is run again from its first
+// proposal, at most kMaxRaises times (tkdv_violation_policy).
+constexpr int kMaxRaises = 4;
+constexpr double kRaiseMargin = 0.02;
+double raised_log_M(double log_M, double max_log_a, double tau)
+{
+    return log_M + std::max(max_log_a, 0.0) + 0.5 * tau + std::log1p(kRaiseMargin);
+}
+
+tkdv_status violation_error(tkdv_ctx *ctx, int p, const tkdv_stats &st)
+{
+    return set_err(ctx, TKDV_E_M_VIOLATION,
+                   "point " + std::to_string(p) + ": " + std::to_string(st.n_M_violations) +
+                       " proposals with f/(M g) > 1 (largest log a " + std::to_string(st.max_log_a) + ")");
 }
 
 void set_window(DevPoint &d, double tau)
@@ -289,54 +397,77 @@ struct Call {
     unsigned long long total_tiles = 0, total_segs = 0, bitmap_words = 0;
 };
 
-tkdv_status run(tkdv_ctx *ctx, Call &call, int precision, int proposal, float *d_xhat,
-                unsigned long long *d_index, hipStream_t st, std::vector<PointResult> *res_out,
-                std::vector<DevCounters> *cnt_out, unsigned long long *n_deferred_out,
-                float *dbg_xhat, float *dbg_t, float *dbg_s3, float *dbg_la, float *dbg_lu,
-                bool stats)
+// Device buffers of one launch sequence (from the context's growable buffers,
+// or carved from a fixed scratch array by the no-allocation entry point).
+struct Workspace {
+    uint32_t *bitmap;
+    unsigned long long *defer_list, *defer_count, defer_cap;
+    DevCounters *counters;
+    DevPoint *points;
+    unsigned long long *seg_cnt, *seg_base;
+    SegStats *seg_stats;
+    PointResult *results;
+    int *plist;
+};
+
+// Host view of one launch sequence: the points, their lists per K and the
+// segment count (plain arrays, so that a caller need not allocate).
+struct CallView {
+    const DevPoint *pts;
+    int np;
+    const int *plist;
+    int plist_len;
+    int plist_off[kNumK], plist_n[kNumK];
+    unsigned long long total_segs;
+};
+
+CallView view_of(const Call &call)
 {
-    const int np = (int)call.pts.size();
-    const unsigned long long defer_cap =
-        std::min<unsigned long long>(1ull << 26, std::max<unsigned long long>(1ull << 20, call.total_tiles));
-    HIP_TRY(ctx, ensure(ctx->bitmap, call.bitmap_words * 4));
-    HIP_TRY(ctx, ensure(ctx->defer_list, defer_cap * 8));
-    HIP_TRY(ctx, ensure(ctx->defer_count, 8));
-    HIP_TRY(ctx, ensure(ctx->counters, sizeof(DevCounters) * np));
-    HIP_TRY(ctx, ensure(ctx->points, sizeof(DevPoint) * np));
-    HIP_TRY(ctx, ensure(ctx->seg_cnt, 8 * std::max<unsigned long long>(call.total_segs, 1)));
-    HIP_TRY(ctx, ensure(ctx->seg_base, 8 * std::max<unsigned long long>(call.total_segs, 1)));
-    HIP_TRY(ctx, ensure(ctx->seg_stats, sizeof(SegStats) * std::max<unsigned long long>(call.total_segs, 1)));
-    HIP_TRY(ctx, ensure(ctx->results, sizeof(PointResult) * np));
-    HIP_TRY(ctx, ensure(ctx->plist, sizeof(int) * call.plist.size()));
-    HIP_TRY(ctx, ensure_host(ctx->h_points, ctx->h_points_bytes, sizeof(DevPoint) * np));
-    HIP_TRY(ctx, ensure_host(ctx->h_misc, ctx->h_misc_bytes, 64 + sizeof(int) * call.plist.size()));
-    HIP_TRY(ctx, ensure_host(ctx->h_results, ctx->h_results_bytes, sizeof(PointResult) * np));
-    HIP_TRY(ctx, ensure_host(ctx->h_counters, ctx->h_counters_bytes, sizeof(DevCounters) * np));
-    for (int ki = 0; ki < 4; ++ki) {
-        if (call.plist_n[ki] == 0) continue;
-        tkdv_status s = build_tables(ctx, 8 << ki);
-        if (s != TKDV_OK) return s;
+    CallView v;
+    v.pts = call.pts.data();
+    v.np = (int)call.pts.size();
+    v.plist = call.plist.data();
+    v.plist_len = (int)call.plist.size();
+    for (int ki = 0; ki < kNumK; ++ki) {
+        v.plist_off[ki] = call.plist_off[ki];
+        v.plist_n[ki] = call.plist_n[ki];
     }
+    v.total_segs = call.total_segs;
+    return v;
+}
+
+// The launch sequence of one sampling call on stream st: decisions per K,
+// FP64 re-decision, and (stats) segments, ordered output with statistics and
+// the per-point reduction; then the per-point results and counters are
+// copied to res_out / cnt_out (host arrays [np], may be NULL).  Uses the
+// context's pinned staging buffers (large enough for v.np points) and the
+// synthesis tables of every K in the call (built); allocates nothing.
+tkdv_status launch_sequence(tkdv_ctx *ctx, const CallView &v, const Workspace &w, int precision, int proposal,
+                            float *d_xhat, unsigned long long *d_index, hipStream_t st, PointResult *res_out,
+                            DevCounters *cnt_out, unsigned long long *n_deferred_out, float *dbg_xhat,
+                            float *dbg_t, float *dbg_s3, float *dbg_la, float *dbg_lu, bool stats)
+{
+    const int np = v.np;
     // The pinned staging buffers are reused by later calls, so the stream must
     // have consumed them before we return (we synchronise at the end).
-    std::memcpy(ctx->h_points, call.pts.data(), sizeof(DevPoint) * np);
+    std::memcpy(ctx->h_points, v.pts, sizeof(DevPoint) * np);
     int *h_plist = reinterpret_cast<int *>((char *)ctx->h_misc + 64);
-    std::memcpy(h_plist, call.plist.data(), sizeof(int) * call.plist.size());
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->points.p, ctx->h_points, sizeof(DevPoint) * np, hipMemcpyHostToDevice, st));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->plist.p, h_plist, sizeof(int) * call.plist.size(), hipMemcpyHostToDevice, st));
-    HIP_TRY(ctx, launch_fill_u32(ctx->counters.p, sizeof(DevCounters) * np / 4, 0u, st));
-    HIP_TRY(ctx, launch_fill_u32(ctx->results.p, sizeof(PointResult) * np / 4, 0u, st));
-    HIP_TRY(ctx, launch_fill_u32(ctx->defer_count.p, 2, 0u, st));
+    std::memcpy(h_plist, v.plist, sizeof(int) * v.plist_len);
+    HIP_TRY(ctx, hipMemcpyAsync(w.points, ctx->h_points, sizeof(DevPoint) * np, hipMemcpyHostToDevice, st));
+    HIP_TRY(ctx, hipMemcpyAsync(w.plist, h_plist, sizeof(int) * v.plist_len, hipMemcpyHostToDevice, st));
+    HIP_TRY(ctx, launch_fill_u32(w.counters, sizeof(DevCounters) * np / 4, 0u, st));
+    HIP_TRY(ctx, launch_fill_u32(w.results, sizeof(PointResult) * np / 4, 0u, st));
+    HIP_TRY(ctx, launch_fill_u32(w.defer_count, 2, 0u, st));
 
     KernelArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.pts = reinterpret_cast<const DevPoint *>(ctx->points.p);
+    a.pts = w.points;
     a.n_points = np;
-    a.cnt = reinterpret_cast<DevCounters *>(ctx->counters.p);
-    a.bitmap = reinterpret_cast<uint32_t *>(ctx->bitmap.p);
-    a.defer_list = reinterpret_cast<unsigned long long *>(ctx->defer_list.p);
-    a.defer_count = reinterpret_cast<unsigned long long *>(ctx->defer_count.p);
-    a.defer_cap = defer_cap;
+    a.cnt = w.counters;
+    a.bitmap = w.bitmap;
+    a.defer_list = w.defer_list;
+    a.defer_count = w.defer_count;
+    a.defer_cap = w.defer_cap;
     a.dbg_xhat = dbg_xhat;
     a.dbg_t = dbg_t;
     a.dbg_s3 = dbg_s3;
@@ -346,54 +477,50 @@ tkdv_status run(tkdv_ctx *ctx, Call &call, int precision, int proposal, float *d
         a.mix = reinterpret_cast<const DevMix *>(ctx->mix.p);
         a.mix_tab = reinterpret_cast<const char *>(ctx->mix_tab.p);
     }
-    const int *d_plist = reinterpret_cast<const int *>(ctx->plist.p);
+    const int *d_plist = w.plist;
     std::memset(&ctx->timing, 0, sizeof(ctx->timing));
     HIP_TRY(ctx, hipEventRecord(ctx->ev[0], st));
-    for (int ki = 0; ki < 4; ++ki) {
-        if (call.plist_n[ki] == 0) continue;
+    for (int ki = 0; ki < kNumK; ++ki) {
+        if (v.plist_n[ki] == 0) continue;
         const int K = 8 << ki;
         // the largest K of the call sets the reported workgroup size
         ctx->timing.decide_block = proposal == TKDV_PROP_MIXTURE ? kMixBlock : decide_block(K);
         s3_tables(ctx, ki, precision, a.phi_hi, a.phi_lo);
         unsigned long long tiles = 0;
-        for (int q = 0; q < call.plist_n[ki]; ++q) tiles += call.pts[call.plist[call.plist_off[ki] + q]].n_tiles;
+        for (int q = 0; q < v.plist_n[ki]; ++q) tiles += v.pts[v.plist[v.plist_off[ki] + q]].n_tiles;
         if (proposal == TKDV_PROP_MIXTURE)
-            HIP_TRY(ctx, launch_decide_mix(K, precision, a, d_plist + call.plist_off[ki], call.plist_n[ki],
-                                           ctx->n_cu, tiles, st, &ctx->timing.decide_grid));
+            HIP_TRY(ctx, launch_decide_mix(K, precision, a, d_plist + v.plist_off[ki], v.plist_n[ki], ctx->n_cu,
+                                           tiles, st, &ctx->timing.decide_grid));
         else
-            HIP_TRY(ctx, launch_decide(K, precision, proposal, a, d_plist + call.plist_off[ki], call.plist_n[ki],
+            HIP_TRY(ctx, launch_decide(K, precision, proposal, a, d_plist + v.plist_off[ki], v.plist_n[ki],
                                        ctx->n_cu, tiles, st, &ctx->timing.decide_grid));
         ctx->timing.decide_launches++;
     }
     HIP_TRY(ctx, hipEventRecord(ctx->ev[1], st));
     if (proposal == TKDV_PROP_MIXTURE) {
-        for (int ki = 0; ki < 4; ++ki)
-            if (call.plist_n[ki]) HIP_TRY(ctx, launch_fixup_mix(8 << ki, a, ctx->n_cu, st));
+        for (int ki = 0; ki < kNumK; ++ki)
+            if (v.plist_n[ki]) HIP_TRY(ctx, launch_fixup_mix(8 << ki, a, ctx->n_cu, st));
     } else {
         HIP_TRY(ctx, launch_fixup(a, ctx->n_cu, st));
     }
     HIP_TRY(ctx, hipEventRecord(ctx->ev[2], st));
     if (stats) {
-        unsigned long long *seg_cnt = reinterpret_cast<unsigned long long *>(ctx->seg_cnt.p);
-        unsigned long long *seg_base = reinterpret_cast<unsigned long long *>(ctx->seg_base.p);
-        SegStats *seg_stats = reinterpret_cast<SegStats *>(ctx->seg_stats.p);
-        PointResult *res = reinterpret_cast<PointResult *>(ctx->results.p);
-        HIP_TRY(ctx, launch_segments(a, call.total_segs, seg_cnt, seg_base, res, ctx->n_cu, st));
+        HIP_TRY(ctx, launch_segments(a, v.total_segs, w.seg_cnt, w.seg_base, w.results, ctx->n_cu, st));
         HIP_TRY(ctx, hipEventRecord(ctx->ev[3], st));
-        for (int ki = 0; ki < 4; ++ki) {
-            if (call.plist_n[ki] == 0) continue;
-            a.phi_hi = ctx->phi_f32[ki].p;
-            HIP_TRY(ctx, launch_materialize(8 << ki, proposal, a, d_plist + call.plist_off[ki], call.plist_n[ki],
-                                            call.total_segs, seg_cnt, seg_base, seg_stats, res, d_xhat, d_index,
-                                            ctx->n_cu, st));
+        for (int ki = 0; ki < kNumK; ++ki) {
+            if (v.plist_n[ki] == 0) continue;
+            a.phi_hi = ki == 4 ? ctx->phi_mat128.p : ctx->phi_f32[ki].p;
+            HIP_TRY(ctx, launch_materialize(8 << ki, proposal, a, d_plist + v.plist_off[ki], v.plist_n[ki],
+                                            v.total_segs, w.seg_cnt, w.seg_base, w.seg_stats, w.results, d_xhat,
+                                            d_index, ctx->n_cu, st));
         }
         HIP_TRY(ctx, hipEventRecord(ctx->ev[4], st));
-        HIP_TRY(ctx, launch_finalize(a, seg_cnt, seg_base, seg_stats, res, st));
+        HIP_TRY(ctx, launch_finalize(a, w.seg_cnt, w.seg_base, w.seg_stats, w.results, st));
         HIP_TRY(ctx, hipEventRecord(ctx->ev[5], st));
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->h_results, ctx->results.p, sizeof(PointResult) * np, hipMemcpyDeviceToHost, st));
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->h_results, w.results, sizeof(PointResult) * np, hipMemcpyDeviceToHost, st));
     }
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_counters, ctx->counters.p, sizeof(DevCounters) * np, hipMemcpyDeviceToHost, st));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_misc, ctx->defer_count.p, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_counters, w.counters, sizeof(DevCounters) * np, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_misc, w.defer_count, 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(ctx, hipStreamSynchronize(st));
     {
         float ms = 0.0f;
@@ -416,18 +543,60 @@ tkdv_status run(tkdv_ctx *ctx, Call &call, int precision, int proposal, float *d
     }
     const unsigned long long n_def = *reinterpret_cast<unsigned long long *>(ctx->h_misc);
     if (n_deferred_out) *n_deferred_out = n_def;
-    if (res_out) {
-        res_out->resize(np);
-        std::memcpy(res_out->data(), ctx->h_results, sizeof(PointResult) * np);
-    }
-    if (cnt_out) {
-        cnt_out->resize(np);
-        std::memcpy(cnt_out->data(), ctx->h_counters, sizeof(DevCounters) * np);
-    }
-    if (n_def > defer_cap)
+    if (res_out && stats) std::memcpy(res_out, ctx->h_results, sizeof(PointResult) * np);
+    if (cnt_out) std::memcpy(cnt_out, ctx->h_counters, sizeof(DevCounters) * np);
+    if (n_def > w.defer_cap)
         return set_err(ctx, TKDV_E_CAPACITY, "FP64 re-decision list overflowed (" + std::to_string(n_def) + " > " +
-                                                 std::to_string(defer_cap) + ")");
+                                                 std::to_string(w.defer_cap) + ")");
     return TKDV_OK;
+}
+
+// One sampling call with the context's buffers, grown as the call needs.
+tkdv_status run(tkdv_ctx *ctx, Call &call, int precision, int proposal, float *d_xhat,
+                unsigned long long *d_index, hipStream_t st, std::vector<PointResult> *res_out,
+                std::vector<DevCounters> *cnt_out, unsigned long long *n_deferred_out,
+                float *dbg_xhat, float *dbg_t, float *dbg_s3, float *dbg_la, float *dbg_lu,
+                bool stats)
+{
+    const int np = (int)call.pts.size();
+    const unsigned long long defer_cap =
+        std::min<unsigned long long>(1ull << 26, std::max<unsigned long long>(1ull << 20, call.total_tiles));
+    HIP_TRY(ctx, ensure(ctx->bitmap, call.bitmap_words * 4));
+    HIP_TRY(ctx, ensure(ctx->defer_list, defer_cap * 8));
+    HIP_TRY(ctx, ensure(ctx->defer_count, 16));
+    HIP_TRY(ctx, ensure(ctx->counters, sizeof(DevCounters) * np));
+    HIP_TRY(ctx, ensure(ctx->points, sizeof(DevPoint) * np));
+    HIP_TRY(ctx, ensure(ctx->seg_cnt, 8 * std::max<unsigned long long>(call.total_segs, 1)));
+    HIP_TRY(ctx, ensure(ctx->seg_base, 8 * std::max<unsigned long long>(call.total_segs, 1)));
+    HIP_TRY(ctx, ensure(ctx->seg_stats, sizeof(SegStats) * std::max<unsigned long long>(call.total_segs, 1)));
+    HIP_TRY(ctx, ensure(ctx->results, sizeof(PointResult) * np));
+    HIP_TRY(ctx, ensure(ctx->plist, sizeof(int) * call.plist.size()));
+    HIP_TRY(ctx, ensure_host(ctx->h_points, ctx->h_points_bytes, sizeof(DevPoint) * np));
+    HIP_TRY(ctx, ensure_host(ctx->h_misc, ctx->h_misc_bytes, 64 + sizeof(int) * call.plist.size()));
+    HIP_TRY(ctx, ensure_host(ctx->h_results, ctx->h_results_bytes, sizeof(PointResult) * np));
+    HIP_TRY(ctx, ensure_host(ctx->h_counters, ctx->h_counters_bytes, sizeof(DevCounters) * np));
+    for (int ki = 0; ki < kNumK; ++ki) {
+        if (call.plist_n[ki] == 0) continue;
+        tkdv_status s = build_tables(ctx, 8 << ki);
+        if (s != TKDV_OK) return s;
+    }
+    Workspace w;
+    w.bitmap = reinterpret_cast<uint32_t *>(ctx->bitmap.p);
+    w.defer_list = reinterpret_cast<unsigned long long *>(ctx->defer_list.p);
+    w.defer_count = reinterpret_cast<unsigned long long *>(ctx->defer_count.p);
+    w.defer_cap = defer_cap;
+    w.counters = reinterpret_cast<DevCounters *>(ctx->counters.p);
+    w.points = reinterpret_cast<DevPoint *>(ctx->points.p);
+    w.seg_cnt = reinterpret_cast<unsigned long long *>(ctx->seg_cnt.p);
+    w.seg_base = reinterpret_cast<unsigned long long *>(ctx->seg_base.p);
+    w.seg_stats = reinterpret_cast<SegStats *>(ctx->seg_stats.p);
+    w.results = reinterpret_cast<PointResult *>(ctx->results.p);
+    w.plist = reinterpret_cast<int *>(ctx->plist.p);
+    if (res_out) res_out->resize(np);
+    if (cnt_out) cnt_out->resize(np);
+    return launch_sequence(ctx, view_of(call), w, precision, proposal, d_xhat, d_index, st,
+                           res_out ? res_out->data() : nullptr, cnt_out ? cnt_out->data() : nullptr,
+                           n_deferred_out, dbg_xhat, dbg_t, dbg_s3, dbg_la, dbg_lu, stats);
 }
 
 float key_to_float(unsigned int k)
@@ -468,6 +637,7 @@ void fill_stats(tkdv_stats &s, const DevPoint &P, const PointResult &r, const De
     s.hist_lo = -umax;
     s.hist_hi = umax;
     for (int b = 0; b < TKDV_NBINS; ++b) s.hist_u0[b] = r.hist[b];
+    s.log_M_used = P.log_M64;
 }
 
 tkdv_status prepare(tkdv_ctx *ctx, Call &call, int n_points, const tkdv_point *pts, int proposal,
@@ -480,13 +650,14 @@ tkdv_status prepare(tkdv_ctx *ctx, Call &call, int n_points, const tkdv_point *p
         return set_err(ctx, TKDV_E_ARG, "bad proposal");
     if (proposal == TKDV_PROP_MIXTURE && !plans) return set_err(ctx, TKDV_E_ARG, "the mixture needs its plan");
     if (precision < TKDV_FP32 || precision > TKDV_BF16X3) return set_err(ctx, TKDV_E_ARG, "bad precision");
+    if (precision == TKDV_BF16) return set_err(ctx, TKDV_E_UNSUPPORTED, kBf16Refused);
     if (mode != TKDV_COUNT_PROPOSALS && mode != TKDV_COUNT_ACCEPTED) return set_err(ctx, TKDV_E_ARG, "bad mode");
     if (mode == TKDV_COUNT_ACCEPTED && max_proposals == 0)
         return set_err(ctx, TKDV_E_ARG, "accepted-count mode needs max_proposals > 0");
     call.pts.resize(n_points);
-    call.plist_n.assign(4, 0);
-    call.plist_off.assign(4, 0);
-    std::vector<std::vector<int>> by_k(4);
+    call.plist_n.assign(kNumK, 0);
+    call.plist_off.assign(kNumK, 0);
+    std::vector<std::vector<int>> by_k(kNumK);
     unsigned long long bm = 0, segs = 0, tiles = 0;
     for (int p = 0; p < n_points; ++p) {
         tkdv_status s = check_point(ctx, pts[p]);
@@ -522,7 +693,7 @@ tkdv_status prepare(tkdv_ctx *ctx, Call &call, int n_points, const tkdv_point *p
         by_k[kindex(pts[p].K)].push_back(p);
     }
     call.plist.clear();
-    for (int ki = 0; ki < 4; ++ki) {
+    for (int ki = 0; ki < kNumK; ++ki) {
         call.plist_off[ki] = (int)call.plist.size();
         call.plist_n[ki] = (int)by_k[ki].size();
         call.plist.insert(call.plist.end(), by_k[ki].begin(), by_k[ki].end());
@@ -540,7 +711,7 @@ tkdv_status prepare_mixture(tkdv_ctx *ctx, Call &call, const tkdv_point &pt, con
                             const tkdv_mixture *mix, int precision, hipStream_t st)
 {
     if (!mix) return set_err(ctx, TKDV_E_ARG, "mixture is NULL");
-    if (pt.K == 64) return set_err(ctx, TKDV_E_UNSUPPORTED, "the mixture sampler supports K in {8,16,32}");
+    if (pt.K > 32) return set_err(ctx, TKDV_E_UNSUPPORTED, "the mixture sampler supports K in {8,16,32}");
     if (plan.proposal != TKDV_PROP_MIXTURE) return set_err(ctx, TKDV_E_ARG, "plan was made for another proposal");
     MixHost mh;
     if (mh.init(pt, plan, *mix) != TKDV_OK) return set_err(ctx, TKDV_E_ARG, "invalid mixture parameters");
@@ -587,6 +758,7 @@ void fill_stats_sweep(tkdv_stats &s, const DevPoint &P, const SweepState &w)
     s.hist_lo = -umax;
     s.hist_hi = umax;
     for (int b = 0; b < TKDV_NBINS; ++b) s.hist_u0[b] = w.total.hist[b];
+    s.log_M_used = P.log_M64;
 }
 
 int prec_index(int precision) { return precision < 0 || precision > 2 ? 0 : precision; }
@@ -599,16 +771,17 @@ tkdv_status sweep(tkdv_ctx *ctx, int np, const tkdv_point *pts, const tkdv_plan 
     if (np < 1) return set_err(ctx, TKDV_E_ARG, "n_points must be >= 1");
     if (!pts || !targets || !maxp || !h_stats) return set_err(ctx, TKDV_E_ARG, "NULL argument");
     if (precision < TKDV_FP32 || precision > TKDV_BF16X3) return set_err(ctx, TKDV_E_ARG, "bad precision");
+    if (precision == TKDV_BF16) return set_err(ctx, TKDV_E_UNSUPPORTED, kBf16Refused);
     Call call;
     call.pts.resize(np);
-    call.plist_n.assign(4, 0);
-    call.plist_off.assign(4, 0);
-    std::vector<std::vector<int>> by_k(4);
+    call.plist_n.assign(kNumK, 0);
+    call.plist_off.assign(kNumK, 0);
+    std::vector<std::vector<int>> by_k(kNumK);
     std::vector<SweepState> sw(np);
-    tkdv_launch_cfg kcfg[4];
+    tkdv_launch_cfg kcfg[kNumK];
     bool use_graph = true;
     unsigned long long bm = 0, segs = 0, max_windows = 0;
-    for (int ki = 0; ki < 4; ++ki) kcfg[ki] = cfg ? *cfg : ctx->lcfg[ki][prec_index(precision)];
+    for (int ki = 0; ki < kNumK; ++ki) kcfg[ki] = cfg ? *cfg : ctx->lcfg[ki][prec_index(precision)];
     for (int p = 0; p < np; ++p) {
         tkdv_status s = check_point(ctx, pts[p]);
         if (s != TKDV_OK) return s;
@@ -653,7 +826,7 @@ tkdv_status sweep(tkdv_ctx *ctx, int np, const tkdv_point *pts, const tkdv_plan 
         by_k[ki].push_back(p);
     }
     call.plist.clear();
-    for (int ki = 0; ki < 4; ++ki) {
+    for (int ki = 0; ki < kNumK; ++ki) {
         call.plist_off[ki] = (int)call.plist.size();
         call.plist_n[ki] = (int)by_k[ki].size();
         call.plist.insert(call.plist.end(), by_k[ki].begin(), by_k[ki].end());
@@ -674,7 +847,7 @@ tkdv_status sweep(tkdv_ctx *ctx, int np, const tkdv_point *pts, const tkdv_plan 
     HIP_TRY(ctx, ensure(ctx->plist, sizeof(int) * call.plist.size()));
     HIP_TRY(ctx, ensure(ctx->sweep, sizeof(SweepState) * np));
     HIP_TRY(ctx, ensure(ctx->active, 8));
-    for (int ki = 0; ki < 4; ++ki)
+    for (int ki = 0; ki < kNumK; ++ki)
         if (call.plist_n[ki]) {
             tkdv_status s = build_tables(ctx, 8 << ki);
             if (s != TKDV_OK) return s;
@@ -708,7 +881,7 @@ tkdv_status sweep(tkdv_ctx *ctx, int np, const tkdv_point *pts, const tkdv_plan 
         HIP_TRY(ctx, launch_fill_u32(ctx->counters.p, sizeof(DevCounters) * np / 4, 0u, sst));
         HIP_TRY(ctx, launch_fill_u32(ctx->results.p, sizeof(PointResult) * np / 4, 0u, sst));
         HIP_TRY(ctx, launch_fill_u32(ctx->defer_count.p, 2, 0u, sst));
-        for (int ki = 0; ki < 4; ++ki) {
+        for (int ki = 0; ki < kNumK; ++ki) {
             if (call.plist_n[ki] == 0) continue;
             const int K = 8 << ki;
             a.blocks_per_cu = kcfg[ki].blocks_per_cu;
@@ -719,9 +892,9 @@ tkdv_status sweep(tkdv_ctx *ctx, int np, const tkdv_point *pts, const tkdv_plan 
         }
         HIP_TRY(ctx, launch_fixup(a, ctx->n_cu, sst));
         HIP_TRY(ctx, launch_segments(a, segs, seg_cnt, seg_base, res, ctx->n_cu, sst));
-        for (int ki = 0; ki < 4; ++ki) {
+        for (int ki = 0; ki < kNumK; ++ki) {
             if (call.plist_n[ki] == 0) continue;
-            a.phi_hi = ctx->phi_f32[ki].p;
+            a.phi_hi = ki == 4 ? ctx->phi_mat128.p : ctx->phi_f32[ki].p;
             HIP_TRY(ctx, launch_materialize(8 << ki, TKDV_PROP_SIGMA, a, d_plist + call.plist_off[ki],
                                             call.plist_n[ki], segs, seg_cnt, seg_base, seg_stats, res, d_xhat,
                                             reinterpret_cast<unsigned long long *>(d_index), ctx->n_cu, sst));
@@ -759,7 +932,7 @@ tkdv_status sweep(tkdv_ctx *ctx, int np, const tkdv_point *pts, const tkdv_plan 
         }
     }
     std::memset(&ctx->timing, 0, sizeof(ctx->timing));
-    for (int ki = 0; ki < 4; ++ki)  // the largest K of the sweep sets the reported workgroup size
+    for (int ki = 0; ki < kNumK; ++ki)  // the largest K of the sweep sets the reported workgroup size
         if (!by_k[ki].empty()) ctx->timing.decide_block = decide_block(8 << ki);
     unsigned long long *poll = reinterpret_cast<unsigned long long *>(ctx->h_poll);
     tkdv_status st_out = TKDV_OK;
@@ -789,7 +962,7 @@ tkdv_status sweep(tkdv_ctx *ctx, int np, const tkdv_point *pts, const tkdv_plan 
     ctx->timing.total_ms = ms;
     ctx->timing.windows = windows;
     int nk = 0;
-    for (int ki = 0; ki < 4; ++ki) nk += call.plist_n[ki] ? 1 : 0;
+    for (int ki = 0; ki < kNumK; ++ki) nk += call.plist_n[ki] ? 1 : 0;
     ctx->timing.decide_launches = windows * nk;
     HIP_TRY(ctx, hipMemcpy(sw.data(), ctx->sweep.p, sizeof(SweepState) * np, hipMemcpyDeviceToHost));
     for (int p = 0; p < np; ++p) fill_stats_sweep(h_stats[p], call.pts[p], sw[p]);
@@ -857,7 +1030,8 @@ tkdv_status tkdv_destroy(tkdv_ctx *ctx)
                       &ctx->ext_list, &ctx->sir_pt, &ctx->sir_w, &ctx->sir_tile, &ctx->sir_chunk, &ctx->sir_part};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
-    for (int i = 0; i < 4; ++i) {
+    if (ctx->phi_mat128.p) (void)hipFree(ctx->phi_mat128.p);
+    for (int i = 0; i < kNumK; ++i) {
         if (ctx->phi_hi[i].p) (void)hipFree(ctx->phi_hi[i].p);
         if (ctx->phi_lo[i].p) (void)hipFree(ctx->phi_lo[i].p);
         if (ctx->phi_f32[i].p) (void)hipFree(ctx->phi_f32[i].p);
@@ -977,6 +1151,12 @@ tkdv_status tkdv_plan_batch(tkdv_ctx *ctx, int32_t n_points, const tkdv_point *p
         if (out[p].M_source == 0 && !(flags & TKDV_PLAN_SEARCH_ALWAYS)) continue;
         const tkdv_point &q = pts[p];
         const int K = q.K;
+        if (K > 64) {  // one wave holds at most 128 coordinates: the host search instead
+            const int hs = plan_point_host(&q, proposal, 2, &out[p]);
+            if (hs != TKDV_OK)
+                return set_err(ctx, (tkdv_status)hs, "point " + std::to_string(p) + ": planning failed");
+            continue;
+        }
         PlanPoint P{};
         P.K = K;
         P.N = 4 * K;
@@ -1103,7 +1283,7 @@ tkdv_status tkdv_extremes(tkdv_ctx *ctx, int32_t K, double E0, const float *d_xh
                           uint64_t *h_n_exceed, float *d_umax, int32_t *d_jmax, void *stream)
 {
     if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");
-    if (kindex(K) < 0) return set_err(ctx, TKDV_E_UNSUPPORTED, "tkdv_extremes supports K in {8,16,32,64}");
+    if (kindex(K) < 0 || K > 64) return set_err(ctx, TKDV_E_UNSUPPORTED, "tkdv_extremes supports K in {8,16,32,64}");
     if (!std::isfinite(E0) || !(E0 > 0.0)) return set_err(ctx, TKDV_E_ARG, "E0 must be finite and > 0");
     if (top_k < 0 || top_k > TKDV_EXTREMES_MAX_K) return set_err(ctx, TKDV_E_ARG, "top_k out of range");
     if (top_k > 0 && (!h_rows || !h_umax || !h_jmax)) return set_err(ctx, TKDV_E_ARG, "NULL output array");
@@ -1226,6 +1406,7 @@ tkdv_status tkdv_sir(tkdv_ctx *ctx, const tkdv_point *pt, tkdv_proposal proposal
         return set_err(ctx, TKDV_E_ARG, "proposal must be UNIFORM or SIGMA");
     if (precision != TKDV_FP32 && precision != TKDV_BF16X3)
         return set_err(ctx, TKDV_E_UNSUPPORTED, "tkdv_sir computes weights with FP32 or BF16x3 synthesis");
+    if (pt->K > 64) return set_err(ctx, TKDV_E_UNSUPPORTED, "tkdv_sir supports K in {8,16,32,64}");
     if (n == 0 || n >= (1ull << 40)) return set_err(ctx, TKDV_E_ARG, "n must be in [1, 2^40)");
     if (!(u0 >= 0.0 && u0 < 1.0)) return set_err(ctx, TKDV_E_ARG, "u0 must be in [0, 1)");
     if (m > 0 && !d_index) return set_err(ctx, TKDV_E_ARG, "d_index is NULL");
@@ -1340,16 +1521,55 @@ tkdv_status tkdv_sample_batch(tkdv_ctx *ctx, int32_t n_points, const tkdv_point 
     if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");
     if (!pts || !n || !h_stats) return set_err(ctx, TKDV_E_ARG, "NULL argument");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    Call call;
-    tkdv_status s = prepare(ctx, call, n_points, pts, proposal, plans, n, mode, max_proposals, precision, capacity,
-                            out_offset, 2 * TKDV_KMAX, 0);
-    if (s != TKDV_OK) return s;
-    std::vector<PointResult> res;
-    std::vector<DevCounters> cnt;
-    s = run(ctx, call, precision, proposal, d_xhat, reinterpret_cast<unsigned long long *>(d_index),
-            (hipStream_t)stream, &res, &cnt, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, true);
-    if (s != TKDV_OK) return s;
-    for (int p = 0; p < n_points; ++p) fill_stats(h_stats[p], call.pts[p], res[p], cnt[p], mode);
+    if (n_points < 1) return set_err(ctx, TKDV_E_ARG, "n_points must be >= 1");
+    std::vector<tkdv_plan> pl(n_points);
+    for (int p = 0; p < n_points; ++p) {
+        if (plans) {
+            pl[p] = plans[p];
+            continue;
+        }
+        tkdv_status s = check_point(ctx, pts[p]);
+        if (s != TKDV_OK) return s;
+        s = (tkdv_status)plan_point_host(&pts[p], proposal, 2, &pl[p]);
+        if (s != TKDV_OK) return set_err(ctx, s, "planning failed");
+    }
+    // run every point, then again the points whose M was violated (raised M)
+    std::vector<int> todo(n_points);
+    for (int p = 0; p < n_points; ++p) todo[p] = p;
+    for (int raise = 0; !todo.empty(); ++raise) {
+        const int m = (int)todo.size();
+        std::vector<tkdv_point> spt(m);
+        std::vector<tkdv_plan> spl(m);
+        std::vector<uint64_t> sn(m), scap(m), soff(m);
+        for (int q = 0; q < m; ++q) {
+            const int p = todo[q];
+            spt[q] = pts[p];
+            spl[q] = pl[p];
+            sn[q] = n[p];
+            scap[q] = capacity ? capacity[p] : 0;
+            soff[q] = out_offset ? out_offset[p] : 0;
+        }
+        Call call;
+        tkdv_status s = prepare(ctx, call, m, spt.data(), proposal, spl.data(), sn.data(), mode, max_proposals,
+                                precision, scap.data(), soff.data(), 2 * TKDV_KMAX, 0);
+        if (s != TKDV_OK) return s;
+        std::vector<PointResult> res;
+        std::vector<DevCounters> cnt;
+        s = run(ctx, call, precision, proposal, d_xhat, reinterpret_cast<unsigned long long *>(d_index),
+                (hipStream_t)stream, &res, &cnt, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, true);
+        if (s != TKDV_OK) return s;
+        std::vector<int> again;
+        for (int q = 0; q < m; ++q) {
+            const int p = todo[q];
+            fill_stats(h_stats[p], call.pts[q], res[q], cnt[q], mode);
+            h_stats[p].M_raises = raise;
+            if (h_stats[p].n_M_violations == 0 || ctx->mv_policy == TKDV_MV_COUNT) continue;
+            if (ctx->mv_policy == TKDV_MV_FAIL || raise == kMaxRaises) return violation_error(ctx, p, h_stats[p]);
+            pl[p].log_M = raised_log_M(pl[p].log_M, h_stats[p].max_log_a, call.pts[q].tau);
+            again.push_back(p);
+        }
+        todo.swap(again);
+    }
     return TKDV_OK;
 }
 
@@ -1368,20 +1588,35 @@ tkdv_status tkdv_sample(tkdv_ctx *ctx, const tkdv_point *pt, tkdv_proposal propo
         h_stats->hist_lo = -umax;
         h_stats->hist_hi = umax;
         h_stats->max_log_a = -INFINITY;
+        h_stats->log_M_used = plan ? plan->log_M : NAN;
         return TKDV_OK;
     }
-    Call call;
-    const uint64_t cap = capacity, off = 0;
-    tkdv_status s = prepare(ctx, call, 1, pt, proposal, plan, &n, mode, max_proposals, precision, &cap, &off,
-                            2 * (uint64_t)pt->K, 0);
-    if (s != TKDV_OK) return s;
-    std::vector<PointResult> res;
-    std::vector<DevCounters> cnt;
-    s = run(ctx, call, precision, proposal, d_xhat, reinterpret_cast<unsigned long long *>(d_index),
-            (hipStream_t)stream, &res, &cnt, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, true);
-    if (s != TKDV_OK) return s;
-    fill_stats(*h_stats, call.pts[0], res[0], cnt[0], mode);
-    return TKDV_OK;
+    tkdv_plan pl;
+    if (plan) {
+        pl = *plan;
+    } else {
+        tkdv_status s = check_point(ctx, *pt);
+        if (s != TKDV_OK) return s;
+        s = (tkdv_status)plan_point_host(pt, proposal, 2, &pl);
+        if (s != TKDV_OK) return set_err(ctx, s, "planning failed");
+    }
+    for (int raise = 0;; ++raise) {
+        Call call;
+        const uint64_t cap = capacity, off = 0;
+        tkdv_status s = prepare(ctx, call, 1, pt, proposal, &pl, &n, mode, max_proposals, precision, &cap, &off,
+                                2 * (uint64_t)pt->K, 0);
+        if (s != TKDV_OK) return s;
+        std::vector<PointResult> res;
+        std::vector<DevCounters> cnt;
+        s = run(ctx, call, precision, proposal, d_xhat, reinterpret_cast<unsigned long long *>(d_index),
+                (hipStream_t)stream, &res, &cnt, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, true);
+        if (s != TKDV_OK) return s;
+        fill_stats(*h_stats, call.pts[0], res[0], cnt[0], mode);
+        h_stats->M_raises = raise;
+        if (h_stats->n_M_violations == 0 || ctx->mv_policy == TKDV_MV_COUNT) return TKDV_OK;
+        if (ctx->mv_policy == TKDV_MV_FAIL || raise == kMaxRaises) return violation_error(ctx, 0, *h_stats);
+        pl.log_M = raised_log_M(pl.log_M, h_stats->max_log_a, call.pts[0].tau);
+    }
 }
 
 tkdv_status tkdv_eval_proposals(tkdv_ctx *ctx, const tkdv_point *pt, tkdv_proposal proposal, const tkdv_plan *plan,
@@ -1427,22 +1662,39 @@ tkdv_status tkdv_sample_mixture(tkdv_ctx *ctx, const tkdv_point *pt, const tkdv_
         h_stats->hist_lo = -umax;
         h_stats->hist_hi = umax;
         h_stats->max_log_a = -INFINITY;
+        h_stats->log_M_used = mix_plan->log_M;
         return TKDV_OK;
     }
-    Call call;
-    const uint64_t cap = capacity, off = 0;
-    tkdv_status s = prepare(ctx, call, 1, pt, TKDV_PROP_MIXTURE, mix_plan, &n, mode, max_proposals, precision, &cap,
-                            &off, 2 * (uint64_t)pt->K, 0);
-    if (s != TKDV_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    s = prepare_mixture(ctx, call, *pt, *mix_plan, mix, precision, st);
+    tkdv_plan pl = *mix_plan;
+    for (int raise = 0; raise <= kMaxRaises; ++raise) {
+        Call call;
+        const uint64_t cap = capacity, off = 0;
+        tkdv_status s = prepare(ctx, call, 1, pt, TKDV_PROP_MIXTURE, &pl, &n, mode, max_proposals, precision, &cap,
+                                &off, 2 * (uint64_t)pt->K, 0);
+        if (s != TKDV_OK) return s;
+        s = prepare_mixture(ctx, call, *pt, pl, mix, precision, st);
+        if (s != TKDV_OK) return s;
+        std::vector<PointResult> res;
+        std::vector<DevCounters> cnt;
+        s = run(ctx, call, precision, TKDV_PROP_MIXTURE, d_xhat, reinterpret_cast<unsigned long long *>(d_index),
+                st, &res, &cnt, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, true);
+        if (s != TKDV_OK) return s;
+        fill_stats(*h_stats, call.pts[0], res[0], cnt[0], mode);
+        h_stats->M_raises = raise;
+        if (h_stats->n_M_violations == 0 || ctx->mv_policy == TKDV_MV_COUNT) return TKDV_OK;
+        if (ctx->mv_policy == TKDV_MV_FAIL) return violation_error(ctx, 0, *h_stats);
+        pl.log_M = raised_log_M(pl.log_M, h_stats->max_log_a, call.pts[0].tau);
+    }
+    // the mixture's bound kept failing: the paper's Sigma sampler (itself
+    // guarded the same way) produces the exact samples instead
+    tkdv_plan sp;
+    tkdv_status s = (tkdv_status)plan_point_host(pt, TKDV_PROP_SIGMA, 2, &sp);
+    if (s != TKDV_OK) return set_err(ctx, s, "planning the Sigma fallback failed");
+    s = tkdv_sample(ctx, pt, TKDV_PROP_SIGMA, &sp, n, mode, max_proposals, precision, d_xhat, d_index, capacity,
+                    h_stats, stream);
     if (s != TKDV_OK) return s;
-    std::vector<PointResult> res;
-    std::vector<DevCounters> cnt;
-    s = run(ctx, call, precision, TKDV_PROP_MIXTURE, d_xhat, reinterpret_cast<unsigned long long *>(d_index), st,
-            &res, &cnt, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, true);
-    if (s != TKDV_OK) return s;
-    fill_stats(*h_stats, call.pts[0], res[0], cnt[0], mode);
+    h_stats->fallback = 1;
     return TKDV_OK;
 }
 
@@ -1498,7 +1750,7 @@ tkdv_status tkdv_synthesize(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, 
                             float *d_s3, void *stream)
 {
     if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");
-    if (kindex(K) < 0) return set_err(ctx, TKDV_E_UNSUPPORTED, "GPU path supports K in {8,16,32,64}");
+    if (kindex(K) < 0 || K > 64) return set_err(ctx, TKDV_E_UNSUPPORTED, "tkdv_synthesize supports K in {8,16,32,64}");
     if (precision < TKDV_FP32 || precision > TKDV_BF16X3) return set_err(ctx, TKDV_E_ARG, "bad precision");
     if (n == 0) return TKDV_OK;
     if (!d_xhat || !d_s3) return set_err(ctx, TKDV_E_ARG, "NULL device pointer");
@@ -1529,8 +1781,62 @@ tkdv_status tkdv_sample_sweep(tkdv_ctx *ctx, int32_t n_points, const tkdv_point 
 {
     if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    return sweep(ctx, n_points, pts, plans, targets, max_proposals, precision, cfg, d_xhat, d_index, capacity,
-                 out_offset, h_stats, (hipStream_t)stream);
+    if (n_points < 1 || !pts || !targets || !max_proposals || !h_stats)
+        return set_err(ctx, TKDV_E_ARG, "n_points must be >= 1 and the arrays non-NULL");
+    std::vector<tkdv_plan> pl(n_points);
+    for (int p = 0; p < n_points; ++p) {
+        if (plans) {
+            pl[p] = plans[p];
+            continue;
+        }
+        tkdv_status s = check_point(ctx, pts[p]);
+        if (s != TKDV_OK) return s;
+        s = (tkdv_status)plan_point_host(&pts[p], TKDV_PROP_SIGMA, 2, &pl[p]);
+        if (s != TKDV_OK) return set_err(ctx, s, "planning failed");
+    }
+    std::vector<int> todo(n_points);
+    for (int p = 0; p < n_points; ++p) todo[p] = p;
+    for (int raise = 0; !todo.empty(); ++raise) {
+        const int m = (int)todo.size();
+        std::vector<tkdv_point> spt(m);
+        std::vector<tkdv_plan> spl(m);
+        std::vector<uint64_t> stg(m), smax(m), scap(m), soff(m);
+        std::vector<tkdv_stats> sst(m);
+        for (int q = 0; q < m; ++q) {
+            const int p = todo[q];
+            spt[q] = pts[p];
+            spl[q] = pl[p];
+            stg[q] = targets[p];
+            smax[q] = max_proposals[p];
+            scap[q] = capacity ? capacity[p] : 0;
+            soff[q] = out_offset ? out_offset[p] : 0;
+        }
+        tkdv_status s = sweep(ctx, m, spt.data(), spl.data(), stg.data(), smax.data(), precision, cfg, d_xhat,
+                              d_index, scap.data(), soff.data(), sst.data(), (hipStream_t)stream);
+        if (s != TKDV_OK) return s;
+        std::vector<int> again;
+        for (int q = 0; q < m; ++q) {
+            const int p = todo[q];
+            h_stats[p] = sst[q];
+            h_stats[p].M_raises = raise;
+            if (sst[q].n_M_violations == 0 || ctx->mv_policy == TKDV_MV_COUNT) continue;
+            if (ctx->mv_policy == TKDV_MV_FAIL || raise == kMaxRaises) return violation_error(ctx, p, sst[q]);
+            pl[p].log_M = raised_log_M(pl[p].log_M, sst[q].max_log_a, window(pts[p], TKDV_PROP_SIGMA, precision,
+                                                                             pl[p].alpha_star, pl[p].log_M));
+            again.push_back(p);
+        }
+        todo.swap(again);
+    }
+    return TKDV_OK;
+}
+
+tkdv_status tkdv_set_violation_policy(tkdv_ctx *ctx, tkdv_violation_policy policy)
+{
+    if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");
+    if (policy != TKDV_MV_RAISE && policy != TKDV_MV_FAIL && policy != TKDV_MV_COUNT)
+        return set_err(ctx, TKDV_E_ARG, "bad violation policy");
+    ctx->mv_policy = policy;
+    return TKDV_OK;
 }
 
 tkdv_status tkdv_set_launch_cfg(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, const tkdv_launch_cfg *cfg)
@@ -1538,6 +1844,7 @@ tkdv_status tkdv_set_launch_cfg(tkdv_ctx *ctx, int32_t K, tkdv_precision precisi
     if (!ctx || !cfg) return set_err(nullptr, TKDV_E_ARG, "NULL argument");
     if (kindex(K) < 0 || precision < TKDV_FP32 || precision > TKDV_BF16X3)
         return set_err(ctx, TKDV_E_ARG, "bad K or precision");
+    if (precision == TKDV_BF16) return set_err(ctx, TKDV_E_UNSUPPORTED, kBf16Refused);
     if (cfg->window < 65536 || cfg->window % 65536 != 0 || cfg->window > (1ull << 34) || cfg->blocks_per_cu < 0)
         return set_err(ctx, TKDV_E_ARG, "window must be a multiple of 65536 in [65536, 2^34]");
     ctx->lcfg[kindex(K)][precision] = *cfg;
@@ -1559,6 +1866,7 @@ tkdv_status tkdv_autotune(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, co
     if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");
     if (kindex(K) < 0 || precision < TKDV_FP32 || precision > TKDV_BF16X3)
         return set_err(ctx, TKDV_E_ARG, "bad K or precision");
+    if (precision == TKDV_BF16) return set_err(ctx, TKDV_E_UNSUPPORTED, kBf16Refused);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     char key[160];
     std::snprintf(key, sizeof(key), "%s:%d K=%d prec=%d", ctx->arch.c_str(), ctx->n_cu, K, (int)precision);

@@ -16,7 +16,8 @@ constexpr int kBlock = 256;        // threads per workgroup of the sampling kern
 // (168 registers a lane; measured faster than 4 waves per SIMD, whose
 // 128-register limit spills inside the tile loop, and than 2 workgroups of
 // 4 waves).
-constexpr int decide_block(int K) { return K == 64 ? 768 : kBlock; }
+// At K = 128 (its own kernel, tkdv_k128.hip) 16 waves share the 128 KB of tables.
+constexpr int decide_block(int K) { return K == 128 ? 1024 : (K == 64 ? 768 : kBlock); }
 constexpr int kSynthBlock = 512;   // threads per workgroup of the standalone synthesis kernel
 constexpr int kClaimTiles = 64;    // tiles claimed per work-queue claim (2048 proposals);
                                    // lane c keeps the accept word of tile c
@@ -25,8 +26,9 @@ constexpr int kNBins = TKDV_NBINS;
 constexpr int kMixBlock = 1024;    // threads per workgroup of the mixture sampling kernel
 constexpr int kMixS = TKDV_MIX_S;  // xi-shifts of the learned mixture
 
-// Per-point constants, laid out for wave-uniform (scalar) loads.
-struct DevPoint {
+// Per-point constants, laid out for wave-uniform (scalar) loads; sig is also
+// read four floats at a time per lane (K = 128 kernels).
+struct alignas(16) DevPoint {
     float sig[TKDV_KMAX];    // proposal standard deviations s_k (1 for the uniform proposal)
     double sig64[TKDV_KMAX]; // the same in FP64 (sqrt of the plan's s_k^2)
     // FP32 fast path: log a = neg_bp_K2 * t + c3coef * S3 + Kf * log1p(g_coef * t) - log_M

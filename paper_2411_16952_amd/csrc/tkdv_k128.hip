@@ -1,0 +1,649 @@
+// K = 128 kernels of the TKdV rejection sampler (N = 512 grid values).
+//
+// Layout.  One wavefront evaluates a tile of 16 proposals; proposal p of the
+// tile lives in lanes p + 16 g, g = 0..3, and lane group g holds the cos and
+// sin coordinates of modes 32 g + 1 .. 32 g + 32 (c[j] = x_{32g+j+1},
+// s[j] = x_{K+32g+j+1}).  That is the operand layout of the 16x16x32 BF16
+// (and 16x16x4 FP32) matrix instructions with the proposals as the B
+// (column) operand: lane l supplies k-rows 8 (l/16) .. 8 (l/16) + 7 of column
+// l % 16, and receives rows 4 (l/16) .. 4 (l/16) + 3 of the result.
+//
+// Quarter-period synthesis.  H3 = (1/6) int u^3 dxi (Sec. II.A) is the
+// trapezoid sum of u^3 on any equispaced grid of N >= 3K + 1 points; this
+// kernel takes the grid offset by half a step, xi_j = -pi + 2 pi (j + 1/2)/N,
+// whose points come in orbits {xi, -xi, xi + pi, pi - xi} with one
+// representative in (0, pi/2): xi_rho = pi (2 rho + 1)/N, rho < N/4.  With Ce,
+// Co (cos block, even / odd modes) and Se, So (sin block) at a representative,
+// the four field values are (Ce + Co) +- (Se + So) and (Ce - Co) +- (Se - So),
+// and their cubes sum to 4 Ce (Ce^2 + 3 Co^2 + 3 Se^2 + 3 So^2) + 24 Co Se So.
+// The tables carry the Co, Se, So rows times sqrt(3) (co = sqrt 3 Co, ...):
+// 4 Ce (Ce^2 + co^2 + se^2 + so^2) + (8/sqrt 3) co se so.  Each of the four
+// syntheses contracts K/2 coordinates: a quarter of the plain product's matrix
+// work, and tables of N/4 x 2K entries (64 KB per BF16 table) that fit in LDS.
+#include <hip/hip_runtime.h>
+
+#include "tkdv_device.h"
+#include "tkdv_kernels.h"
+
+namespace tkdv {
+
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+namespace {
+
+constexpr int K128 = 128;
+constexpr int kTile16 = 16;            // proposals per wave tile
+constexpr int kReps = 4 * K128 / 4;    // representatives of the quarter grid (N/4)
+constexpr int kRepTiles = kReps / 16;  // 8 tiles of 16 representatives
+constexpr int kBlock128 = 768;         // 12 waves: 3 per SIMD share one copy of the tables
+
+// bytes of one quarter table: BF16 [tile][out][step][64 lanes][8], FP32
+// [tile][out][step/4][64 lanes][4]
+constexpr int kQBf16Bytes = kRepTiles * 4 * 2 * 64 * 16;   // 64 KB
+constexpr int kQF32Bytes = kRepTiles * 4 * 16 * 64 * 4;    // 128 KB
+
+__host__ __device__ constexpr int decide128_lds(int prec) { return prec == PREC_FP32 ? kQF32Bytes : 2 * kQBf16Bytes; }
+
+__device__ __forceinline__ unsigned long long wave_sum_u64_128(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ float wave_max_128(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_sum_f64_128(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ unsigned long long bcast0(unsigned long long v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+// sum over the four lanes of a proposal (l, l^16, l^32, l^48); every lane
+// gets the same two operands in the last addition, hence the same bits
+__device__ __forceinline__ float sum4(float v)
+{
+    v = v + __shfl_xor(v, 16, 64);
+    return v + __shfl_xor(v, 32, 64);
+}
+
+// Work-queue claim as in the other decision kernels: every lane issues the
+// atomic (lane 0 adds), lane 0's old value broadcast; ~0 when the target is met.
+__device__ __forceinline__ unsigned long long claim128(const DevPoint &P, DevCounters *C, int lane)
+{
+    const bool open =
+        P.target == ~0ull ||
+        bcast0(__hip_atomic_load(&C->accepted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < P.target;
+    const unsigned long long old =
+        atomicAdd(&C->next_tile, (open && lane == 0) ? (unsigned long long)kClaimTiles : 0ull);
+    return open ? bcast0(old) : ~0ull;
+}
+__device__ __forceinline__ void add0(unsigned long long *ctr, unsigned long long v, int lane)
+{
+    if (bcast0(v) != 0ull) atomicAdd(ctr, lane == 0 ? v : 0ull);
+}
+
+// Block b (0: cos, 1: sin) of proposal i for this lane: the 32 coordinates of
+// modes 32 g + 1 .. 32 g + 32 (coordinate m from word m, Box-Muller on word
+// pairs; X = Sigma^{1/2} z for the paper's proposal), and their contributions
+// to |X|^2, sum (j+1) X^2 and sum (j+1)^2 X^2 (t = sum k^2 X_k^2 over both
+// blocks, k = 32 g + j + 1).
+template <int PROP>
+__device__ __forceinline__ void gen_block128(const DevPoint &P, uint32_t c0, uint32_t c1, int g, int b,
+                                             float (&v)[32], float &r2, float &a1, float &a2)
+{
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const uint4 w = philox4x32_10(c0, c1, P.point_id, (uint32_t)(b * (K128 / 4) + 8 * g + q), P.key0, P.key1);
+        box_muller_f32(w.x, w.y, v[4 * q + 0], v[4 * q + 1]);
+        box_muller_f32(w.z, w.w, v[4 * q + 2], v[4 * q + 3]);
+    }
+    if (PROP == PROP_SIGMA) {
+        const float4 *sg = reinterpret_cast<const float4 *>(P.sig + 32 * g);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float4 sv = sg[q];
+            v[4 * q + 0] *= sv.x;
+            v[4 * q + 1] *= sv.y;
+            v[4 * q + 2] *= sv.z;
+            v[4 * q + 3] *= sv.w;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        const float q = v[j] * v[j];
+        r2 += q;
+        a1 = __builtin_fmaf((float)(j + 1), q, a1);
+        a2 = __builtin_fmaf((float)((j + 1) * (j + 1)), q, a2);
+    }
+}
+
+// |X|^-1 and t of the projected point from the lane's partial sums (the four
+// lanes of a proposal end with bitwise identical values).
+__device__ __forceinline__ float finish_norm128(int g, float r2, float a1, float a2, float &t)
+{
+    const float b = (float)(32 * g);
+    float tk = __builtin_fmaf(b * b, r2, __builtin_fmaf(2.0f * b, a1, a2));
+    r2 = sum4(r2);
+    tk = sum4(tk);
+    const float inv = __builtin_amdgcn_rsqf(r2);
+    t = tk * (inv * inv);
+    return inv;
+}
+
+// Proposal i of the point: this lane's 32 cos and 32 sin coordinates of X
+// (words 0..2K-1 as in every sampler: coordinate m from word m, Box-Muller on
+// word pairs; X = Sigma^{1/2} z for the paper's proposal), |X|^-1, t of the
+// projected point and the acceptance word (word 2K).  With NORMALIZE the
+// coordinates are projected onto the sphere.  The four lanes of a proposal
+// hold bitwise identical |X|^2 and t.
+template <int PROP, bool NORMALIZE>
+__device__ __forceinline__ float gen_x128(const DevPoint &P, uint64_t i, int g, float (&c)[32], float (&s)[32],
+                                          float &t, uint32_t &w_acc)
+{
+    const uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32);
+    float r2 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+    gen_block128<PROP>(P, c0, c1, g, 0, c, r2, a1, a2);
+    gen_block128<PROP>(P, c0, c1, g, 1, s, r2, a1, a2);
+    w_acc = philox4x32_10(c0, c1, P.point_id, (uint32_t)(K128 / 2), P.key0, P.key1).x;
+    const float inv = finish_norm128(g, r2, a1, a2, t);
+    if (NORMALIZE) {
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+            c[j] *= inv;
+            s[j] *= inv;
+        }
+    }
+    return inv;
+}
+
+// The cube sums of one representative from its four syntheses (co, se, so
+// carry sqrt(3)): s1 += Ce (Ce^2 + co^2 + se^2 + so^2), s2 += co se so.
+__device__ __forceinline__ void quarter_cubes(const f32x4 &ce, const f32x4 &co, const f32x4 &se, const f32x4 &so,
+                                              float &s1, float &s2)
+{
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const float e = ce[v];
+        const float q = __builtin_fmaf(co[v], co[v], __builtin_fmaf(se[v], se[v], __builtin_fmaf(so[v], so[v], e * e)));
+        s1 = __builtin_fmaf(e, q, s1);
+        s2 = __builtin_fmaf(co[v] * se[v], so[v], s2);
+    }
+}
+
+// BF16 operands of one contraction (out o: 0 Ce, 1 Co, 2 Se, 3 So), k-step r:
+// entry e = the coordinate of mode 32 g + 2 (8 r + e) + 2 (even) or + 1 (odd).
+template <bool LO>
+__device__ __forceinline__ void quarter_operand(const float (&v)[32], int odd, int r, bf16x8 &hi, bf16x8 &lo)
+{
+    u32x4_t wh, wl = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const int j0 = 16 * r + 4 * w + (odd ? 0 : 1);  // entries 2w, 2w + 1: coordinates j0, j0 + 2
+        wh[w] = pack_hi(v[j0], v[j0 + 2]);
+        if (LO) wl[w] = pack_lo(v[j0], v[j0 + 2], wh[w]);
+    }
+    hi = __builtin_bit_cast(bf16x8, wh);
+    lo = __builtin_bit_cast(bf16x8, wl);
+}
+
+// S3 = sum over the N = 512 offset-grid values of u~^3 for this lane's share
+// (the caller sums the four lanes), from unprojected coordinates, FP32 products.
+__device__ __forceinline__ float cube_sum_q128_f32(const float (&c)[32], const float (&s)[32], const char *lds_hi,
+                                                   int lane)
+{
+    float s1 = 0.0f, s2 = 0.0f;
+    {
+        // k-step sg of out o: coordinate 2 sg + 1 (even mode) or 2 sg (odd mode) of the block
+        const float4 *tab = reinterpret_cast<const float4 *>(lds_hi);
+#pragma unroll 1
+        for (int tau = 0; tau < kRepTiles; ++tau) {
+            f32x4 acc[4] = {f32x4{}, f32x4{}, f32x4{}, f32x4{}};
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4)
+#pragma unroll
+                for (int o = 0; o < 4; ++o) {
+                    const float4 a = tab[((tau * 4 + o) * 4 + q4) * 64 + lane];
+                    const float *v = (o < 2) ? c : s;
+                    const int par = (o == 0 || o == 2) ? 1 : 0;
+                    acc[o] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, v[2 * (4 * q4 + 0) + par], acc[o], 0, 0, 0);
+                    acc[o] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, v[2 * (4 * q4 + 1) + par], acc[o], 0, 0, 0);
+                    acc[o] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, v[2 * (4 * q4 + 2) + par], acc[o], 0, 0, 0);
+                    acc[o] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, v[2 * (4 * q4 + 3) + par], acc[o], 0, 0, 0);
+                }
+            quarter_cubes(acc[0], acc[1], acc[2], acc[3], s1, s2);
+        }
+    }
+    return __builtin_fmaf(4.0f, s1, 4.6188021535170061f * s2);  // 4 s1 + (8/sqrt 3) s2
+}
+
+// The same from BF16 operands [out][step] (hi, and lo for BF16x3) with FP32
+// accumulation.
+template <int PREC>
+__device__ __forceinline__ float cube_sum_q128_bf16(const bf16x8 (&bh)[4][2], const bf16x8 (&bl)[4][2],
+                                                    const char *lds_hi, const char *lds_lo, int lane)
+{
+    float s1 = 0.0f, s2 = 0.0f;
+    {
+        const bf16x8 *th = reinterpret_cast<const bf16x8 *>(lds_hi);
+        const bf16x8 *tl = reinterpret_cast<const bf16x8 *>(lds_lo);
+#pragma unroll 1
+        for (int tau = 0; tau < kRepTiles; ++tau) {
+            f32x4 acc[4] = {f32x4{}, f32x4{}, f32x4{}, f32x4{}};
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int o = 0; o < 4; ++o) {
+                    const int idx = ((tau * 4 + o) * 2 + r) * 64 + lane;
+                    const bf16x8 ah = th[idx];
+                    if constexpr (PREC == PREC_BF16X3) {
+                        const bf16x8 al = tl[idx];
+                        acc[o] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[o][r], acc[o], 0, 0, 0);
+                        acc[o] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[o][r], acc[o], 0, 0, 0);
+                    }
+                    acc[o] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[o][r], acc[o], 0, 0, 0);
+                }
+            quarter_cubes(acc[0], acc[1], acc[2], acc[3], s1, s2);
+        }
+    }
+    return __builtin_fmaf(4.0f, s1, 4.6188021535170061f * s2);  // 4 s1 + (8/sqrt 3) s2
+}
+
+// ---------------------------------------------------------------------------
+// k_decide128: persistent; claims of 64 accept words (2048 proposals, 128
+// tiles of 16) from per-point queues, as the other decision kernels.
+// ---------------------------------------------------------------------------
+// DBG: the verification entry's instantiation (per-proposal outputs written);
+// the sampling calls run the one without, which needs fewer registers.
+template <int PREC, int PROP, bool DBG>
+__global__ void __launch_bounds__(kBlock128) k_decide128(KernelArgs a, const int *plist, int n_plist)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    constexpr int bytes = decide128_lds(PREC);
+    {
+        const uint4 *s0 = reinterpret_cast<const uint4 *>(a.phi_hi);
+        const uint4 *s1 = reinterpret_cast<const uint4 *>(a.phi_lo);
+        uint4 *d = reinterpret_cast<uint4 *>(lds);
+        constexpr int one = PREC == PREC_FP32 ? kQF32Bytes / 16 : kQBf16Bytes / 16;
+        for (int v = threadIdx.x; v < one; v += kBlock128) d[v] = s0[v];
+        if constexpr (PREC == PREC_BF16X3)
+            for (int v = threadIdx.x; v < one; v += kBlock128) d[one + v] = s1[v];
+    }
+    __syncthreads();
+    const char *lds_hi = lds;
+    const char *lds_lo = lds + (PREC == PREC_FP32 ? 0 : kQBf16Bytes);
+    (void)bytes;
+    const int lane = threadIdx.x & 63, g = lane >> 4, pl = lane & 15;
+    const int gwave = blockIdx.x * (kBlock128 / kWave) + (threadIdx.x >> 6);
+    int cursor = gwave % n_plist;
+    int misses = 0;
+    while (misses < n_plist) {
+        const int p = __builtin_amdgcn_readfirstlane(plist[cursor]);
+        const DevPoint &P = a.pts[p];
+        DevCounters *C = a.cnt + p;
+        const unsigned long long base = claim128(P, C, lane);
+        if (base >= P.n_tiles) {
+            cursor = (cursor + 1 == n_plist) ? 0 : cursor + 1;
+            ++misses;
+            continue;
+        }
+        misses = 0;
+        unsigned long long n_acc = 0, n_def = 0;
+        unsigned int n_viol = 0;
+        float max_la = -INFINITY;
+        uint32_t my_word = 0u;  // accept bits of word `lane` of this claim
+        for (int c2 = 0; c2 < 2 * kClaimTiles; ++c2) {
+            const unsigned long long word = base + (c2 >> 1);
+            if (word >= P.n_tiles) break;
+            const unsigned long long local = word * kTile + (c2 & 1) * kTile16 + pl;
+            const bool valid = local < P.n;
+            const uint64_t i = P.i0 + local;
+            if (DBG && a.dbg_xhat) {  // verification: the projected point, generated once more
+                float c[32], s[32], tt;
+                uint32_t ww;
+                gen_x128<PROP, true>(P, i, g, c, s, tt, ww);
+                if (valid) {
+                    float *row = a.dbg_xhat + local * (2 * K128);
+#pragma unroll
+                    for (int j = 0; j < 32; ++j) {
+                        row[32 * g + j] = c[j];
+                        row[K128 + 32 * g + j] = s[j];
+                    }
+                }
+            }
+            const uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32);
+            float r2 = 0.0f, a1 = 0.0f, a2 = 0.0f, s3l;
+            if constexpr (PREC == PREC_FP32) {
+                float c[32], s[32];
+                gen_block128<PROP>(P, c0, c1, g, 0, c, r2, a1, a2);
+                gen_block128<PROP>(P, c0, c1, g, 1, s, r2, a1, a2);
+                s3l = cube_sum_q128_f32(c, s, lds_hi, lane);
+            } else {
+                // one block at a time: its coordinates die once split into operands
+                bf16x8 bh[4][2], bl[4][2];
+#pragma unroll
+                for (int blk = 0; blk < 2; ++blk) {
+                    float v[32];
+                    gen_block128<PROP>(P, c0, c1, g, blk, v, r2, a1, a2);
+#pragma unroll
+                    for (int odd = 0; odd < 2; ++odd)
+#pragma unroll
+                        for (int r = 0; r < 2; ++r)
+                            quarter_operand<PREC == PREC_BF16X3>(v, odd, r, bh[2 * blk + odd][r],
+                                                                 bl[2 * blk + odd][r]);
+                    // keep the next block's generation after this split (register pressure)
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                s3l = cube_sum_q128_bf16<PREC>(bh, bl, lds_hi, lds_lo, lane);
+            }
+            const uint32_t w_acc = philox4x32_10(c0, c1, P.point_id, (uint32_t)(K128 / 2), P.key0, P.key1).x;
+            float t;
+            const float inv = finish_norm128(g, r2, a1, a2, t);
+            const float s3 = sum4(s3l) * (inv * inv * inv);
+            const float la = log_a_f32<PROP>(P, t, s3);
+            const float U = __builtin_fmaf((float)w_acc, 2.3283064365386963e-10f, 1.1641532182693481e-10f);
+            const float alin = __builtin_amdgcn_exp2f(la * 1.4426950408889634f);
+            const float lo_edge = alin * P.e_lo, hi_edge = alin * P.e_hi;
+            const bool mine = valid && g == 0;
+            const bool defer = mine && U >= lo_edge && U < hi_edge;
+            const bool accept = mine && U < lo_edge;
+            const unsigned long long bacc = __ballot(accept);
+            const unsigned long long bdef = __ballot(defer);
+            if (lane == (c2 >> 1)) my_word |= (uint32_t)(bacc & 0xffffull) << (16 * (c2 & 1));
+            n_acc += __popcll(bacc);
+            if (mine) {
+                n_viol += (la > 0.0f && !defer) ? 1u : 0u;  // window proposals: k_fixup
+                max_la = fmaxf(max_la, la);
+                if (DBG && a.dbg_t) {
+                    a.dbg_t[local] = t;
+                    a.dbg_s3[local] = s3;
+                    a.dbg_log_a[local] = la;
+                    a.dbg_log_u[local] = log_u_word(w_acc);
+                }
+            }
+            if (bdef) {
+                const unsigned long long nd = __popcll(bdef);
+                const unsigned long long slot = bcast0(atomicAdd(a.defer_count, lane == 0 ? nd : 0ull));
+                if (defer) {
+                    const unsigned long long pos = slot + __popcll(bdef & ((1ull << lane) - 1ull));
+                    if (pos < a.defer_cap) a.defer_list[pos] = pack_defer(p, i);
+                }
+                n_def += nd;
+            }
+        }
+        if (base + lane < P.n_tiles) a.bitmap[P.bm_off + base + lane] = my_word;
+        const unsigned long long viol = wave_sum_u64_128(n_viol);
+        max_la = wave_max_128(max_la);
+        add0(&C->accepted, n_acc, lane);
+        add0(&C->violations, viol, lane);
+        add0(&C->deferred, n_def, lane);
+        if (__builtin_amdgcn_readfirstlane(__float_as_uint(max_la)) != __float_as_uint(-INFINITY))
+            atomicMax(&C->max_log_a_key, lane == 0 ? float_key(max_la) : 0u);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_materialize128: one block per 65536-proposal segment, one wave per quarter
+// segment, as k_materialize; accepted proposals in chunks of 16, regenerated
+// with the decision kernel's arithmetic, written at their rank, and the grid
+// statistics from the FP32 16x16x4 matrix synthesis on the N = 512 grid
+// xi_j = -pi + 2 pi j/N (table in device memory: tile T of 16 grid points,
+// k-step m of 64 -- lane group g's coordinate m: cos of mode 32 g + m + 1 for
+// m < 32, sin of mode 32 g + m - 31 otherwise).
+// ---------------------------------------------------------------------------
+constexpr int kWaveWords128 = kSegWords / (kBlock / kWave);  // 512 words per wave
+constexpr int kGroupWords128 = kWave;                         // one word per lane per group
+
+template <int PROP>
+__global__ void __launch_bounds__(kBlock) k_materialize128(KernelArgs a, unsigned long long total_segs,
+                                                           const unsigned long long *seg_cnt,
+                                                           const unsigned long long *seg_base,
+                                                           SegStats *seg_stats, PointResult *res,
+                                                           float *out_xhat, unsigned long long *out_index)
+{
+    __shared__ uint16_t lists[kBlock / kWave][kGroupWords128 * 32];
+    __shared__ unsigned int hist[kNBins];
+    __shared__ unsigned long long wave_cnt[kBlock / kWave];
+    __shared__ double wave_S[kBlock / kWave][4];
+    __shared__ unsigned long long wave_ex[kBlock / kWave];
+    const float4 *ftab = reinterpret_cast<const float4 *>(a.phi_hi);
+    const int lane = threadIdx.x & 63, g = lane >> 4, pl = lane & 15, wv = threadIdx.x >> 6;
+    uint16_t *mylist = lists[wv];
+    for (unsigned long long gs = blockIdx.x; gs < total_segs; gs += gridDim.x) {
+        int lo = 0, hi = a.n_points - 1;
+        while (lo < hi) {  // last point whose first segment is <= gs
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.pts[mid].seg_off <= gs) lo = mid; else hi = mid - 1;
+        }
+        const int p = lo;
+        const DevPoint &P = a.pts[p];
+        const unsigned long long limit = P.target;
+        if (P.K != K128 || P.proposal != PROP || seg_cnt[gs] == 0 || seg_base[gs] >= limit) continue;
+        for (int b = threadIdx.x; b < kNBins; b += kBlock) hist[b] = 0u;
+        const unsigned long long nt = a.cnt[p].next_tile;
+        const unsigned long long nw = nt < P.n_tiles ? nt : P.n_tiles;
+        const unsigned long long seg_w0 = (gs - P.seg_off) * kSegWords;
+        const unsigned long long w_first = seg_w0 + (unsigned long long)wv * kWaveWords128;
+        unsigned long long cw = 0;
+        for (int k = lane; k < kWaveWords128; k += kWave) {
+            const unsigned long long w = w_first + k;
+            if (w < nw) cw += __popc(a.bitmap[P.bm_off + w]);
+        }
+        cw = wave_sum_u64_128(cw);
+        if (lane == 0) wave_cnt[wv] = cw;
+        __syncthreads();
+        unsigned long long rank = seg_base[gs];
+        for (int w = 0; w < wv; ++w) rank += wave_cnt[w];
+        double S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0;
+        unsigned long long n_ex = 0;
+        for (int grp = 0; grp < kWaveWords128 / kGroupWords128; ++grp) {
+            const unsigned long long w = w_first + (unsigned long long)grp * kGroupWords128 + lane;
+            const uint32_t word = w < nw ? a.bitmap[P.bm_off + w] : 0u;
+            const int cntw = __popc(word);
+            int incl = cntw;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int up = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += up;
+            }
+            const int total = __shfl(incl, 63, 64);
+            if (total == 0) continue;
+            int pos = incl - cntw;
+            uint32_t m = word;
+            while (m) {
+                const int bit = __ffs(m) - 1;
+                m &= m - 1;
+                mylist[pos++] = (uint16_t)(lane * 32 + bit);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            for (int c0 = 0; c0 < total; c0 += kTile16) {
+                const bool in_chunk = c0 + pl < total;
+                const int off = in_chunk ? (int)mylist[c0 + pl] : 0;
+                const unsigned long long local =
+                    (w_first + (unsigned long long)grp * kGroupWords128) * kTile + (unsigned long long)off;
+                const uint64_t i = P.i0 + local;
+                const unsigned long long r = rank + c0 + pl;
+                const bool valid = in_chunk && r < limit;
+                float c[32], s[32];
+                float t;
+                uint32_t w_acc;
+                gen_x128<PROP, true>(P, i, g, c, s, t, w_acc);
+                if (valid && r < P.capacity) {
+                    if (out_xhat) {
+                        float *row = out_xhat + (P.out_off + r) * P.row_stride;
+#pragma unroll
+                        for (int j = 0; j < 32; ++j) {
+                            row[32 * g + j] = c[j];
+                            row[K128 + 32 * g + j] = s[j];
+                        }
+                    }
+                    if (out_index && g == 0) out_index[P.out_off + r] = i;
+                }
+                if (valid && g == 0 && r + 1 == limit) a.cnt[p].last_index = i;
+                // u~ on the grid, 32 tiles of 16 points, 64 k-steps of the four lane groups
+#pragma unroll 1
+                for (int T = 0; T < 32; ++T) {
+                    f32x4 acc = {};
+#pragma unroll
+                    for (int m4 = 0; m4 < 16; ++m4) {
+                        const float4 av = ftab[(T * 16 + m4) * 64 + lane];
+                        const float *v = m4 < 8 ? c : s;
+                        const int j0 = 4 * (m4 & 7);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, v[j0 + 0], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, v[j0 + 1], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, v[j0 + 2], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, v[j0 + 3], acc, 0, 0, 0);
+                    }
+                    if (valid) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const double u = P.amp * (double)acc[v];
+                            const double u2 = u * u;
+                            S1 += u;
+                            S2 += u2;
+                            S3 += u2 * u;
+                            S4 += u2 * u2;
+                            n_ex += acc[v] > 1.41421356237309515f ? 1ull : 0ull;  // u > 2 sqrt(E0/pi)
+                        }
+                    }
+                }
+                // u(0) = sqrt(2 E0/pi) sum_k x^_k; bin of u(0)/u_max = sum_k x^_k / sqrt(K)
+                double s0 = 0.0;
+#pragma unroll
+                for (int j = 0; j < 32; ++j) s0 += (double)c[j];
+                s0 += __shfl_xor(s0, 16, 64);
+                s0 += __shfl_xor(s0, 32, 64);
+                if (valid && g == 0) {
+                    double posb = (s0 / sqrt((double)K128) + 1.0) * (0.5 * kNBins);
+                    int bin = (int)floor(posb);
+                    bin = bin < 0 ? 0 : (bin > kNBins - 1 ? kNBins - 1 : bin);
+                    atomicAdd(&hist[bin], 1u);
+                }
+            }
+            rank += total;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        S1 = wave_sum_f64_128(S1);
+        S2 = wave_sum_f64_128(S2);
+        S3 = wave_sum_f64_128(S3);
+        S4 = wave_sum_f64_128(S4);
+        n_ex = wave_sum_u64_128(n_ex);
+        if (lane == 0) {
+            wave_S[wv][0] = S1;
+            wave_S[wv][1] = S2;
+            wave_S[wv][2] = S3;
+            wave_S[wv][3] = S4;
+            wave_ex[wv] = n_ex;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            SegStats st = {0.0, 0.0, 0.0, 0.0, 0ull, 0ull};
+            for (int w = 0; w < kBlock / kWave; ++w) {
+                st.S1 += wave_S[w][0];
+                st.S2 += wave_S[w][1];
+                st.S3 += wave_S[w][2];
+                st.S4 += wave_S[w][3];
+                st.n_exceed += wave_ex[w];
+            }
+            const unsigned long long sb = seg_base[gs];
+            const unsigned long long se = sb + seg_cnt[gs];
+            st.n_samples = (se < limit ? se : limit) - sb;
+            seg_stats[gs] = st;
+        }
+        for (int b = threadIdx.x; b < kNBins; b += kBlock)
+            if (hist[b]) atomicAdd(&res[p].hist[b], (unsigned long long)hist[b]);
+        __syncthreads();
+    }
+}
+
+template <int PREC, int PROP>
+hipError_t launch_decide128_t(const KernelArgs &a, const int *plist, int n_plist, int n_cu,
+                              unsigned long long total_tiles, hipStream_t st, int *grid_out)
+{
+    constexpr int lds = decide128_lds(PREC);
+    const bool dbg = a.dbg_xhat != nullptr || a.dbg_t != nullptr;
+    auto kern = dbg ? k_decide128<PREC, PROP, true> : k_decide128<PREC, PROP, false>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock128, lds);
+    if (e != hipSuccess) return e;
+    if (a.blocks_per_cu > 0 && a.blocks_per_cu < per_cu) per_cu = a.blocks_per_cu;
+    if (per_cu < 1) per_cu = 1;
+    const unsigned long long per_block = (unsigned long long)(kBlock128 / kWave) * kClaimTiles;
+    unsigned long long want = (total_tiles + per_block - 1) / per_block;
+    unsigned long long grid = (unsigned long long)per_cu * n_cu;
+    if (want < grid) grid = want;
+    if (grid < 1) grid = 1;
+    if (grid_out) *grid_out = (int)grid;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kBlock128), lds, st, a, plist, n_plist);
+    return hipGetLastError();
+}
+
+template <int PREC, int PROP>
+int blocks_per_cu128_t()
+{
+    constexpr int lds = decide128_lds(PREC);
+    auto kern = k_decide128<PREC, PROP, false>;
+    if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
+        return 1;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock128, lds) != hipSuccess) return 1;
+    return per_cu < 1 ? 1 : per_cu;
+}
+
+}  // namespace
+
+int decide128_block() { return kBlock128; }
+size_t quarter_table_bytes(int prec) { return prec == PREC_FP32 ? kQF32Bytes : kQBf16Bytes; }
+
+hipError_t launch_decide128(int prec, int prop, const KernelArgs &a, const int *plist, int n_plist, int n_cu,
+                            unsigned long long total_tiles, hipStream_t st, int *grid_out)
+{
+    if (prec == PREC_FP32 && prop == PROP_UNIFORM)
+        return launch_decide128_t<PREC_FP32, PROP_UNIFORM>(a, plist, n_plist, n_cu, total_tiles, st, grid_out);
+    if (prec == PREC_FP32 && prop == PROP_SIGMA)
+        return launch_decide128_t<PREC_FP32, PROP_SIGMA>(a, plist, n_plist, n_cu, total_tiles, st, grid_out);
+    if (prec == PREC_BF16X3 && prop == PROP_UNIFORM)
+        return launch_decide128_t<PREC_BF16X3, PROP_UNIFORM>(a, plist, n_plist, n_cu, total_tiles, st, grid_out);
+    if (prec == PREC_BF16X3 && prop == PROP_SIGMA)
+        return launch_decide128_t<PREC_BF16X3, PROP_SIGMA>(a, plist, n_plist, n_cu, total_tiles, st, grid_out);
+    return hipErrorInvalidValue;
+}
+
+int decide128_max_blocks_per_cu(int prec)
+{
+    return prec == PREC_FP32 ? blocks_per_cu128_t<PREC_FP32, PROP_SIGMA>()
+                             : blocks_per_cu128_t<PREC_BF16X3, PROP_SIGMA>();
+}
+
+hipError_t launch_materialize128(int prop, const KernelArgs &a, unsigned long long total_segs,
+                                 const unsigned long long *seg_cnt, const unsigned long long *seg_base,
+                                 SegStats *seg_stats, PointResult *res, float *out_xhat,
+                                 unsigned long long *out_index, int n_cu, hipStream_t st)
+{
+    unsigned long long g = total_segs < (unsigned long long)(8 * n_cu) ? total_segs : 8ull * n_cu;
+    if (g < 1) g = 1;
+    if (prop == PROP_SIGMA)
+        hipLaunchKernelGGL(k_materialize128<PROP_SIGMA>, dim3((unsigned)g), dim3(kBlock), 0, st, a, total_segs,
+                           seg_cnt, seg_base, seg_stats, res, out_xhat, out_index);
+    else if (prop == PROP_UNIFORM)
+        hipLaunchKernelGGL(k_materialize128<PROP_UNIFORM>, dim3((unsigned)g), dim3(kBlock), 0, st, a, total_segs,
+                           seg_cnt, seg_base, seg_stats, res, out_xhat, out_index);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace tkdv

@@ -29,6 +29,18 @@ hipError_t launch_finalize(const KernelArgs &a, const unsigned long long *seg_cn
 hipError_t launch_synth(int K, int prec, const float *xhat, unsigned long long n, float *s3, const void *phi_hi,
                         const void *phi_lo, int n_cu, hipStream_t st, hipEvent_t ev_start, int *grid_out,
                         int *block_out);
+// K = 128 (tkdv_k128.hip): the quarter-period decision kernel, its workgroup
+// size and occupancy, the bytes of one of its tables (FP32, or one BF16 table
+// of hi/lo), and the ordered output with statistics
+hipError_t launch_decide128(int prec, int prop, const KernelArgs &a, const int *plist, int n_plist, int n_cu,
+                            unsigned long long total_tiles, hipStream_t st, int *grid_out);
+int decide128_block();
+int decide128_max_blocks_per_cu(int prec);
+size_t quarter_table_bytes(int prec);
+hipError_t launch_materialize128(int prop, const KernelArgs &a, unsigned long long total_segs,
+                                 const unsigned long long *seg_cnt, const unsigned long long *seg_base,
+                                 SegStats *seg_stats, PointResult *res, float *out_xhat,
+                                 unsigned long long *out_index, int n_cu, hipStream_t st);
 hipError_t launch_window_advance(DevPoint *pts, const DevCounters *cnt, const PointResult *res, SweepState *sw,
                                  int n_points, unsigned long long *active, hipStream_t st);
 hipError_t launch_fill_u32(void *p, unsigned long long n_words, uint32_t v, hipStream_t st);

@@ -176,7 +176,8 @@ __global__ void __launch_bounds__(decide_block(K)) k_decide(KernelArgs a, const 
             if (lane == c) my_word = (uint32_t)bacc;
             n_acc += __popcll(bacc);
             if (mine) {
-                n_viol += la > 0.0f ? 1u : 0u;
+                // window proposals are counted by their FP64 value (k_fixup)
+                n_viol += (la > 0.0f && !defer) ? 1u : 0u;
                 max_la = fmaxf(max_la, la);
                 if (a.dbg_t) {
                     a.dbg_t[local] = t;
@@ -349,7 +350,7 @@ __global__ void __launch_bounds__(kMixBlock) k_decide_mix(KernelArgs a, const in
                 if (lane == c) my_word = (uint32_t)bacc;
                 n_acc += __popcll(bacc);
                 if (mine) {
-                    n_viol += la > 0.0f ? 1u : 0u;
+                    n_viol += (la > 0.0f && !defer) ? 1u : 0u;  // window proposals: k_fixup_mix
                     max_la = fmaxf(max_la, la);
                     if (a.dbg_t) {
                         a.dbg_t[local] = t;
@@ -457,6 +458,10 @@ __global__ void __launch_bounds__(kBlock) k_fixup(KernelArgs a)
             const uint64_t local = i - P.i0;
             atomicOr(&a.bitmap[P.bm_off + local / 32], 1u << (local % 32));
             atomicAdd(&a.cnt[p].fix_accepted, 1ull);
+        }
+        if (la > 0.0) {  // f/(M g) > 1 (eq. M_sup broken): counted here for window proposals
+            atomicAdd(&a.cnt[p].violations, 1ull);
+            atomicMax(&a.cnt[p].max_log_a_key, float_key((float)la));
         }
     }
 }
@@ -615,6 +620,7 @@ __global__ void __launch_bounds__(kBlock) k_fixup_mix(KernelArgs a)
         // updates of each half in turn, under a wave-uniform condition at a
         // wave-uniform address (lane 0 of the wave carries the value)
         const bool acc = item && log_u < log_a;
+        const bool viol = item && log_a > 0.0;  // f/(M q_mix) > 1, counted here for window proposals
         const unsigned long long bm_word = P.bm_off + (i - P.i0) / 32;
         const uint32_t bit = 1u << ((i - P.i0) % 32);
 #pragma unroll
@@ -625,6 +631,12 @@ __global__ void __launch_bounds__(kBlock) k_fixup_mix(KernelArgs a)
                 const int pp = __builtin_amdgcn_readlane(p, 32 * hh);
                 atomicOr(&a.bitmap[wrd], lane == 0 ? b : 0u);
                 atomicAdd(&a.cnt[pp].fix_accepted, lane == 0 ? 1ull : 0ull);
+            }
+            if (__builtin_amdgcn_readlane((int)viol, 32 * hh) != 0) {
+                const int pp = __builtin_amdgcn_readlane(p, 32 * hh);
+                const unsigned int key = __builtin_amdgcn_readlane(float_key((float)log_a), 32 * hh);
+                atomicAdd(&a.cnt[pp].violations, lane == 0 ? 1ull : 0ull);
+                atomicMax(&a.cnt[pp].max_log_a_key, lane == 0 ? key : 0u);
             }
         }
         // the next proposals overwrite this wave's copies of x^
@@ -1087,8 +1099,6 @@ static hipError_t launch_decide_k(int prec, int prop, const KernelArgs &a, const
     if (prec == PR && prop == PP) return launch_decide_t<K, PR, PP>(a, plist, n_plist, n_cu, tiles, st, g);
     TKDV_DISPATCH_P(PREC_FP32, PROP_UNIFORM)
     TKDV_DISPATCH_P(PREC_FP32, PROP_SIGMA)
-    TKDV_DISPATCH_P(PREC_BF16, PROP_UNIFORM)
-    TKDV_DISPATCH_P(PREC_BF16, PROP_SIGMA)
     TKDV_DISPATCH_P(PREC_BF16X3, PROP_UNIFORM)
     TKDV_DISPATCH_P(PREC_BF16X3, PROP_SIGMA)
 #undef TKDV_DISPATCH_P
@@ -1111,11 +1121,12 @@ int decide_max_blocks_per_cu(int K, int prec)
 {
 #define TKDV_DISPATCH_O(KK, PR) \
     if (K == KK && prec == PR) return decide_blocks_per_cu_t<KK, PR, PROP_SIGMA>();
-    TKDV_DISPATCH_O(8, PREC_FP32) TKDV_DISPATCH_O(8, PREC_BF16) TKDV_DISPATCH_O(8, PREC_BF16X3)
-    TKDV_DISPATCH_O(16, PREC_FP32) TKDV_DISPATCH_O(16, PREC_BF16) TKDV_DISPATCH_O(16, PREC_BF16X3)
-    TKDV_DISPATCH_O(32, PREC_FP32) TKDV_DISPATCH_O(32, PREC_BF16) TKDV_DISPATCH_O(32, PREC_BF16X3)
-    TKDV_DISPATCH_O(64, PREC_FP32) TKDV_DISPATCH_O(64, PREC_BF16) TKDV_DISPATCH_O(64, PREC_BF16X3)
+    TKDV_DISPATCH_O(8, PREC_FP32) TKDV_DISPATCH_O(8, PREC_BF16X3)
+    TKDV_DISPATCH_O(16, PREC_FP32) TKDV_DISPATCH_O(16, PREC_BF16X3)
+    TKDV_DISPATCH_O(32, PREC_FP32) TKDV_DISPATCH_O(32, PREC_BF16X3)
+    TKDV_DISPATCH_O(64, PREC_FP32) TKDV_DISPATCH_O(64, PREC_BF16X3)
 #undef TKDV_DISPATCH_O
+    if (K == 128) return decide128_max_blocks_per_cu(prec);
     return 1;
 }
 
@@ -1127,6 +1138,7 @@ hipError_t launch_decide(int K, int prec, int prop, const KernelArgs &a, const i
     case 16: return launch_decide_k<16>(prec, prop, a, plist, n_plist, n_cu, tiles, st, grid_out);
     case 32: return launch_decide_k<32>(prec, prop, a, plist, n_plist, n_cu, tiles, st, grid_out);
     case 64: return launch_decide_k<64>(prec, prop, a, plist, n_plist, n_cu, tiles, st, grid_out);
+    case 128: return launch_decide128(prec, prop, a, plist, n_plist, n_cu, tiles, st, grid_out);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1159,9 +1171,9 @@ hipError_t launch_decide_mix(int K, int prec, const KernelArgs &a, const int *pl
 {
 #define TKDV_DISPATCH_X(KK, PR) \
     if (K == KK && prec == PR) return launch_decide_mix_t<KK, PR>(a, plist, n_plist, n_cu, tiles, st, grid_out);
-    TKDV_DISPATCH_X(8, PREC_FP32) TKDV_DISPATCH_X(8, PREC_BF16) TKDV_DISPATCH_X(8, PREC_BF16X3)
-    TKDV_DISPATCH_X(16, PREC_FP32) TKDV_DISPATCH_X(16, PREC_BF16) TKDV_DISPATCH_X(16, PREC_BF16X3)
-    TKDV_DISPATCH_X(32, PREC_FP32) TKDV_DISPATCH_X(32, PREC_BF16) TKDV_DISPATCH_X(32, PREC_BF16X3)
+    TKDV_DISPATCH_X(8, PREC_FP32) TKDV_DISPATCH_X(8, PREC_BF16X3)
+    TKDV_DISPATCH_X(16, PREC_FP32) TKDV_DISPATCH_X(16, PREC_BF16X3)
+    TKDV_DISPATCH_X(32, PREC_FP32) TKDV_DISPATCH_X(32, PREC_BF16X3)
 #undef TKDV_DISPATCH_X
     return hipErrorInvalidValue;
 }
@@ -1219,6 +1231,9 @@ hipError_t launch_materialize(int K, int prop, const KernelArgs &a, const int *p
                               const unsigned long long *seg_base, SegStats *seg_stats, PointResult *res,
                               float *out_xhat, unsigned long long *out_index, int n_cu, hipStream_t st)
 {
+    if (K == 128)
+        return launch_materialize128(prop, a, total_segs, seg_cnt, seg_base, seg_stats, res, out_xhat, out_index,
+                                     n_cu, st);
 #define TKDV_DISPATCH_M(KK, PP)                                                                          \
     if (K == KK && prop == PP)                                                                           \
         return launch_materialize_t<KK, PP>(a, plist, n_plist, total_segs, seg_cnt, seg_base, seg_stats, \

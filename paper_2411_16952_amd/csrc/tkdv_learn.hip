@@ -552,6 +552,7 @@ struct tkdv_learner {
     Buf W, gW, m1, m2, z, h1, h2, out, dh1, dh2, dout, gmix, par, pts, st;
     Buf X, row_point, kind, lf, lnet, lmix;
     Buf order, chunk_start, chunk_point, part;  // rows grouped by point, chunks, chunk partials
+    Buf shift_src;                              // base rows and phases of tkdv_learner_add_shifted_rows
     std::vector<int> h_row_point;
     unsigned n_chunks = 0;
     unsigned long long n_rows = 0, cap_rows = 0;
@@ -812,6 +813,32 @@ hipError_t launch_append(tkdv_learner *L, const float *src, unsigned long long s
     return hipGetLastError();
 }
 
+// Row (r, q) of n x n_phi new rows = base row r with the field translated by
+// phi_q, u(xi) -> u(xi + phi_q): the (cos, sin) pair (a, b) of mode k becomes
+// (a cos k phi + b sin k phi, b cos k phi - a sin k phi).  One thread per
+// (row, mode); the rows are appended at r0 + r n_phi + q with their point and kind.
+__global__ void k_rows_shift(int K, const double *base, const double *phi, unsigned long long n, int n_phi,
+                             double *X, int *row_point, uint8_t *kind, unsigned long long r0, int point, int kd)
+{
+    const unsigned long long total = n * (unsigned long long)n_phi * K;
+    for (unsigned long long v = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; v < total;
+         v += (unsigned long long)gridDim.x * blockDim.x) {
+        const int k = (int)(v % K) + 1;
+        const unsigned long long rq = v / K, r = rq / n_phi;
+        const int q = (int)(rq % n_phi);
+        double sn, cs;
+        sincos((double)k * phi[q], &sn, &cs);
+        const double a = base[r * 2 * K + k - 1], b = base[r * 2 * K + K + k - 1];
+        double *o = X + (r0 + rq) * 2 * K;
+        o[k - 1] = a * cs + b * sn;
+        o[K + k - 1] = b * cs - a * sn;
+        if (k == 1) {
+            row_point[r0 + rq] = point;
+            kind[r0 + rq] = (uint8_t)kd;
+        }
+    }
+}
+
 template <int K>
 hipError_t launch_log_f(tkdv_learner *L, unsigned long long r0, unsigned long long n, hipStream_t st)
 {
@@ -883,7 +910,7 @@ tkdv_status tkdv_learner_destroy(tkdv_learner *L)
     (void)hipSetDevice(L->device);
     Buf *bs[] = {&L->W, &L->gW, &L->m1, &L->m2, &L->z, &L->h1, &L->h2, &L->out, &L->dh1, &L->dh2, &L->dout,
                  &L->gmix, &L->par, &L->pts, &L->st, &L->X, &L->row_point, &L->kind, &L->lf, &L->lnet, &L->lmix,
-                 &L->order, &L->chunk_start, &L->chunk_point, &L->part};
+                 &L->order, &L->chunk_start, &L->chunk_point, &L->part, &L->shift_src};
     for (Buf *b : bs) b->release();
     delete L;
     return TKDV_OK;
@@ -989,6 +1016,53 @@ tkdv_status tkdv_learner_add_rows_host(tkdv_learner *L, int32_t point, const dou
     L->n_rows += n;
     L->h_row_point.insert(L->h_row_point.end(), n, point);
     if (kind == 0) L->n_acc[point] += n;
+    return upload_points(L, nullptr);
+}
+
+tkdv_status tkdv_learner_add_shifted_rows(tkdv_learner *L, int32_t point, const double *h_xhat, uint64_t n,
+                                          const double *h_phi, int32_t n_phi, int32_t kind)
+{
+    if (!L || (n > 0 && (!h_xhat || !h_phi)) || point < 0 || point >= L->n_points || (kind != 0 && kind != 1) ||
+        n_phi < 1 || n_phi > 4096 || n > (1ull << 32))
+        return record_error(TKDV_E_ARG, "invalid rows or phases");
+    if (n == 0) return TKDV_OK;
+    for (int q = 0; q < n_phi; ++q)
+        if (!std::isfinite(h_phi[q])) return record_error(TKDV_E_ARG, "non-finite phase");
+    LTRY(hipSetDevice(L->device));
+    const int K = L->K;
+    std::vector<double> x(h_xhat, h_xhat + n * 2 * K);
+    for (uint64_t r = 0; r < n; ++r) {
+        double r2 = 0.0;
+        for (int m = 0; m < 2 * K; ++m) r2 += x[r * 2 * K + m] * x[r * 2 * K + m];
+        if (!(r2 > 0.0) || !std::isfinite(r2)) return record_error(TKDV_E_ARG, "row of zero or non-finite norm");
+        const double inv = 1.0 / std::sqrt(r2);
+        for (int m = 0; m < 2 * K; ++m) x[r * 2 * K + m] *= inv;
+    }
+    const unsigned long long n_new = n * (unsigned long long)n_phi;
+    tkdv_status s = grow_rows(L, L->n_rows + n_new, nullptr);
+    if (s != TKDV_OK) return s;
+    const size_t base_bytes = n * 2 * K * sizeof(double);
+    LTRY(L->shift_src.ensure(base_bytes + (size_t)n_phi * sizeof(double)));
+    double *d_base = L->shift_src.as<double>();
+    double *d_phi = d_base + n * 2 * K;
+    LTRY(hipMemcpy(d_base, x.data(), base_bytes, hipMemcpyHostToDevice));
+    LTRY(hipMemcpy(d_phi, h_phi, (size_t)n_phi * sizeof(double), hipMemcpyHostToDevice));
+    const unsigned long long g = std::min<unsigned long long>((n_new * K + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_rows_shift, dim3((unsigned)g), dim3(256), 0, nullptr, K, d_base, d_phi,
+                       (unsigned long long)n, n_phi, L->X.as<double>(), L->row_point.as<int>(),
+                       L->kind.as<uint8_t>(), L->n_rows, point, kind);
+    LTRY(hipGetLastError());
+    hipError_t e;
+    switch (K) {
+    case 8: e = launch_log_f<8>(L, L->n_rows, n_new, nullptr); break;
+    case 16: e = launch_log_f<16>(L, L->n_rows, n_new, nullptr); break;
+    default: e = launch_log_f<32>(L, L->n_rows, n_new, nullptr); break;
+    }
+    LTRY(e);
+    LTRY(hipDeviceSynchronize());
+    L->n_rows += n_new;
+    L->h_row_point.insert(L->h_row_point.end(), n_new, point);
+    if (kind == 0) L->n_acc[point] += n_new;
     return upload_points(L, nullptr);
 }
 

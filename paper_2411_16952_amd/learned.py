@@ -25,18 +25,6 @@ import numpy as np
 from . import tkdv as T
 
 
-def shift_rows(x: np.ndarray, phis) -> np.ndarray:
-    """Copies of x^ with u shifted by each phi: mode k rotated by the angle k phi."""
-    K = x.size // 2
-    k = np.arange(1, K + 1)
-    out = []
-    for phi in phis:
-        c, s = np.cos(k * phi), np.sin(k * phi)
-        a, b = x[:K], x[K:]
-        out.append(np.concatenate([a * c + b * s, b * c - a * s]))
-    return np.array(out)
-
-
 @dataclass
 class FitResult:
     learner: T.Learner
@@ -97,8 +85,7 @@ def fit(ctx: T.Context, points: list, cfg: T.LearnerCfg, samples_per_point: int 
         for i, (sp, pl, am) in enumerate(zip(sps, plans, ams)):
             gains.append(log_M_sigma_normalised(sp) - pl.log_M)
             if rnd < rounds:
-                rows = np.vstack([am[None, :], shift_rows(am, fracs)])
-                L.add_rows(i, rows, kind=1)
+                L.add_shifted_rows(i, am[None, :], [0.0] + fracs, kind=1)
                 starts[i].append(am)
         # the weights of the round with the best mean log M_Sigma/M_mix over the
         # training points (the fit is not monotone in this measure)

@@ -16,10 +16,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtkdv.so")
 
-KMAX = 64
+KMAX = 128
 NBINS = 64
 
 UNIFORM, SIGMA, MIXTURE = 0, 1, 2
+MV_RAISE, MV_FAIL, MV_COUNT = 0, 1, 2   # policies for proposals with f/(M g) > 1
 MIX_S, MIX_R = 32, 2
 FP32, BF16, BF16X3 = 0, 1, 2
 COUNT_PROPOSALS, COUNT_ACCEPTED = 0, 1
@@ -102,7 +103,8 @@ class Stats(C.Structure):
                 ("S3", C.c_double), ("S4", C.c_double), ("skewness", C.c_double),
                 ("kurtosis", C.c_double), ("p_exceed_2sigma", C.c_double),
                 ("hist_lo", C.c_double), ("hist_hi", C.c_double),
-                ("hist_u0", C.c_uint64 * NBINS)]
+                ("hist_u0", C.c_uint64 * NBINS), ("log_M_used", C.c_double), ("M_raises", C.c_int32),
+                ("fallback", C.c_int32)]
 
     def to_dict(self) -> dict:
         d = {name: getattr(self, name) for name, _ in self._fields_ if name != "hist_u0"}
@@ -125,10 +127,12 @@ EXPORTS = ["tkdv_create", "tkdv_destroy", "tkdv_plan_point", "tkdv_sample", "tkd
            "tkdv_status_str", "tkdv_last_error", "tkdv_mixture_log_q", "tkdv_plan_mixture",
            "tkdv_sample_mixture", "tkdv_eval_mixture", "tkdv_mixture_window", "tkdv_learner_create",
            "tkdv_learner_destroy", "tkdv_learner_set_points", "tkdv_learner_add_rows",
-           "tkdv_learner_add_rows_host", "tkdv_learner_train", "tkdv_learner_gradients",
+           "tkdv_learner_add_rows_host", "tkdv_learner_add_shifted_rows", "tkdv_learner_train",
+           "tkdv_learner_gradients",
            "tkdv_learner_mixture", "tkdv_learner_n_weights", "tkdv_learner_get_weights",
            "tkdv_learner_set_weights", "tkdv_sample_sweep", "tkdv_set_launch_cfg", "tkdv_get_launch_cfg",
-           "tkdv_autotune", "tkdv_plan_batch", "tkdv_extremes", "tkdv_sir", "tkdv_plan_mixture_batch"]
+           "tkdv_autotune", "tkdv_plan_batch", "tkdv_extremes", "tkdv_sir", "tkdv_plan_mixture_batch",
+           "tkdv_set_violation_policy"]
 
 _P = C.c_void_p
 lib.tkdv_create.argtypes = [C.c_int, C.POINTER(_P)]
@@ -142,6 +146,7 @@ lib.tkdv_sample_batch.argtypes = [_P, C.c_int32, C.POINTER(Point), C.c_int, C.PO
 lib.tkdv_eval_proposals.argtypes = [_P, C.POINTER(Point), C.c_int, C.POINTER(Plan), C.c_uint64,
                                     C.c_uint64, C.c_int, _P, _P, _P, _P, _P, _P, _P]
 lib.tkdv_get_timing.argtypes = [_P, C.POINTER(Timing)]
+lib.tkdv_set_violation_policy.argtypes = [_P, C.c_int]
 lib.tkdv_synthesize.argtypes = [_P, C.c_int32, C.c_int, _P, C.c_uint64, _P, _P]
 lib.tkdv_decision_window.argtypes = [C.POINTER(Point), C.c_int, C.c_int]
 lib.tkdv_decision_window.restype = C.c_double
@@ -160,6 +165,7 @@ lib.tkdv_learner_destroy.argtypes = [_P]
 lib.tkdv_learner_set_points.argtypes = [_P, C.c_int32, C.POINTER(Point), C.POINTER(Plan)]
 lib.tkdv_learner_add_rows.argtypes = [_P, C.c_int32, _P, C.c_uint64, C.c_uint64, C.c_int32, _P]
 lib.tkdv_learner_add_rows_host.argtypes = [_P, C.c_int32, _PD, C.c_uint64, C.c_int32]
+lib.tkdv_learner_add_shifted_rows.argtypes = [_P, C.c_int32, _PD, C.c_uint64, _PD, C.c_int32, C.c_int32]
 lib.tkdv_learner_train.argtypes = [_P, C.c_int32, _PD, _P]
 lib.tkdv_learner_gradients.argtypes = [_P, _PD, _PD, _PD, _P]
 lib.tkdv_learner_mixture.argtypes = [_P, C.POINTER(Point), C.POINTER(Plan), C.POINTER(Mixture)]
@@ -282,6 +288,10 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_violation_policy(self, policy: int):
+        """MV_RAISE (raise M and run again; default), MV_FAIL or MV_COUNT."""
+        _check(lib.tkdv_set_violation_policy(self._h, int(policy)), self._h)
 
     def timing(self) -> dict:
         """Device time of the phases of the last call (HIP events on its stream)."""
@@ -601,6 +611,14 @@ class Learner:
             x = np.ascontiguousarray(np.asarray(xhat, dtype=np.float64).reshape(-1, 2 * self.K))
             _check(lib.tkdv_learner_add_rows_host(self._h, int(point), x.ctypes.data_as(_PD), x.shape[0],
                                                   int(kind)))
+
+    def add_shifted_rows(self, point: int, xhat, phis, kind: int = 1):
+        """Host rows (n, 2K) and their copies translated by each phase in phis
+        (the library rotates them on the device); phase 0 keeps a row."""
+        x = np.ascontiguousarray(np.asarray(xhat, dtype=np.float64).reshape(-1, 2 * self.K))
+        ph = np.ascontiguousarray(np.asarray(phis, dtype=np.float64).reshape(-1))
+        _check(lib.tkdv_learner_add_shifted_rows(self._h, int(point), x.ctypes.data_as(_PD), x.shape[0],
+                                                 ph.ctypes.data_as(_PD), ph.size, int(kind)))
 
     def train(self, n_steps: int, stream=None) -> np.ndarray:
         loss = np.zeros(self.n_points)

@@ -103,3 +103,19 @@ def sweep_candidates(seed: int = 2024, n: int = 4 * SWEEP_N) -> list[SweepSpec]:
         out.append(SweepSpec(PointSpec(K, E0, bp, c, 5000 + q, 5000 + q), target,
                              "upstream" if q % 2 == 0 else "downstream"))
     return out
+
+# K = 128 (N = 512), the paper's largest mode count (its parallel speed-up
+# study, Sec. V.C, and Fig. 1's alpha*): beta' in {20, 40} x beta' C3/C2 in
+# {30000, 40000} (acceptance of the paper's proposal about 1e-2 and 3e-3;
+# Tables 1-2's levels grow with K), 1e9 proposals per point.
+K128_BETAS = (20.0, 40.0)
+K128_LEVELS = (30000.0, 40000.0)
+
+
+def k128_points() -> list[PointSpec]:
+    pts = []
+    for lvl in K128_LEVELS:
+        for bp in K128_BETAS:
+            pid = 2000 + len(pts)
+            pts.append(PointSpec(128, 1.0, bp, lvl / bp, pid, pid))
+    return pts

@@ -134,6 +134,41 @@ def test_loss_and_gradients_against_oracle(T, ctx):
     L.close()
 
 
+def test_shifted_rows_are_the_oracle_shifts(T, ctx):
+    """Rows appended with their xi-shifted copies (rotated on the device) give
+    the same loss and gradients as the oracle's shifted rows added directly."""
+    K, H = 16, 24
+    cfg = T.learner_cfg(K, hidden=H, v_amp=0.5, v_scale=0.7)
+    rng = np.random.default_rng(12)
+    L0 = T.Learner(ctx, cfg)
+    W = random_weights(L0.n_weights, rng)
+    L0.close()
+    pts = [T.make_point(K, 1.0, 30.0, 100.0), T.make_point(K, 0.5, 45.0, 20.0)]
+    sps = [T.plan_point(p, T.SIGMA) for p in pts]
+    base = rng.standard_normal((3, 2 * K))
+    base /= np.linalg.norm(base, axis=1, keepdims=True)
+    phis = [0.0, 0.013, 2 * math.pi / 32 * 0.5, 1.7, -2.4]
+    losses = []
+    for device_shift in (True, False):
+        L = T.Learner(ctx, cfg)
+        L.set_weights(W)
+        L.set_points(pts, sps)
+        for i in range(2):
+            L.add_rows(i, base[:2], kind=0)
+            if device_shift:
+                L.add_shifted_rows(i, base, phis, kind=1)
+            else:
+                rows = np.array([oracle.shift(base[r], ph) for r in range(base.shape[0]) for ph in phis])
+                L.add_rows(i, rows, kind=1)
+        losses.append(L.gradients())
+        L.close()
+    (l1, gm1, gw1), (l2, gm2, gw2) = losses
+    say(f"shifted rows: loss {l1} vs {l2}")
+    assert np.allclose(l1, l2, rtol=1e-12, atol=1e-12)
+    assert np.allclose(gm1, gm2, rtol=1e-10, atol=1e-12)
+    assert np.allclose(gw1, gw2, rtol=1e-10, atol=1e-12)
+
+
 def test_training_gains_over_the_paper_proposal(T, ctx):
     """Two K = 16 points; a short fit; the trained network beats both the
     untrained network and the paper's Sigma proposal in M, and the mixture

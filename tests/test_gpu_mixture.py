@@ -5,7 +5,8 @@
   the final decision, equal to the oracle's FP64 decision except where
   |log U - log a| < 1e-9;
 * end to end (tkdv_sample_mixture): accepted index set, stored rows,
-  statistics, accepted-count mode, M-violation counting, argument errors.
+  statistics, accepted-count mode, the policies for a violated rejection
+  bound (count, fail, raise M and run again), argument errors.
 The mixtures are random (a trained one is not needed for parity): D near the
 paper's Sigma, V of rank 2 with entries of size ~1/sqrt(K).
 """
@@ -70,7 +71,7 @@ EVAL_CASES = [  # K, beta', C3/C2, n, i0
 
 
 @pytest.mark.parametrize("K,bp,c,n,i0", EVAL_CASES)
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_eval_mixture_against_oracle(T, ctx, K, bp, c, n, i0, prec):
     say(f"eval-mix K={K} beta'={bp} c={c} n={n} i0={i0} prec={prec}")
     pt, sp, pl, mx, mo = make_case(T, K, bp, c)
@@ -102,7 +103,7 @@ SAMPLE_CASES = [  # K, beta', C3/C2, n, precision, scale
     (8, 40.0, 20.0, 1_000_003, "bf16x3", 1.0),
     (16, 20.0, 60.0, 200_001, "fp32", 0.5),
     (32, 40.0, 75.0, 100_001, "bf16x3", 1.0),
-    (32, 20.0, 300.0, 100_003, "bf16", 1.5),
+    (32, 20.0, 300.0, 100_003, "fp32", 1.5),
 ]
 
 
@@ -146,16 +147,48 @@ def test_sample_mixture_accepted_count_mode(T, ctx):
 
 
 def test_sample_mixture_counts_M_violations(T, ctx):
-    """An M set too low by 3 nats: every proposal with log a > 0 is counted."""
+    """An M set too low by 3 nats: every proposal with log a > 0 is counted
+    (policy MV_COUNT), or the call fails (MV_FAIL)."""
     K, bp, c = 8, 40.0, 20.0
     pt, sp, pl, mx, mo = make_case(T, K, bp, c, log_M_shift=-3.0)
     n = 300_001
     o = oracle_mix(pt, pl, mo, n)
     nv = int((o["log_a"] > 0).sum())
     assert nv > 0
-    g = ctx.sample_mixture(pt, pl, mx, n, precision=T.FP32)
-    assert g["n_M_violations"] == nv
-    assert abs(g["max_log_a"] - o["log_a"].max()) < 1e-3
+    try:
+        ctx.set_violation_policy(T.MV_COUNT)
+        g = ctx.sample_mixture(pt, pl, mx, n, precision=T.FP32)
+        assert g["n_M_violations"] == nv and g["M_raises"] == 0
+        assert abs(g["max_log_a"] - o["log_a"].max()) < 1e-3
+        ctx.set_violation_policy(T.MV_FAIL)
+        with pytest.raises(T.TkdvError) as e:
+            ctx.sample_mixture(pt, pl, mx, n, precision=T.FP32)
+        assert e.value.status == -6
+    finally:
+        ctx.set_violation_policy(T.MV_RAISE)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_sample_mixture_raises_a_violated_M(T, ctx, prec):
+    """The same M, 3 nats too low, under the default policy: log M is raised
+    above every log a seen and the point is run again; the result is the
+    oracle's run at the raised M (no proposal with f/(M q) > 1)."""
+    K, bp, c = 8, 40.0, 20.0
+    pt, sp, pl, mx, mo = make_case(T, K, bp, c, log_M_shift=-3.0)
+    n = 300_001
+    g = ctx.sample_mixture(pt, pl, mx, n, precision=T.PRECISIONS[prec], capacity=n)
+    say(f"raised log M {pl.log_M:.6f} -> {g['log_M_used']:.6f} after {g['M_raises']} raise(s)")
+    assert g["M_raises"] >= 1 and g["fallback"] == 0 and g["n_M_violations"] == 0
+    assert g["log_M_used"] > pl.log_M
+    pl2 = type(pl).from_buffer_copy(pl)
+    pl2.log_M = g["log_M_used"]
+    o = oracle_mix(pt, pl2, mo, n, cap=n)
+    assert not (o["log_a"] > 0).any()
+    amb = np.abs(o["log_u"] - o["log_a"]) < AMBIG
+    acc_g = np.zeros(n, dtype=bool)
+    acc_g[g["index"].cpu().numpy().astype(np.int64)] = True
+    assert not ((acc_g != (o["log_u"] < o["log_a"])) & ~amb).any()
+    assert g["n_accepted"] == int(acc_g.sum())
 
 
 def test_sample_mixture_edges(T, ctx):
@@ -175,6 +208,9 @@ def test_sample_mixture_edges(T, ctx):
     pl64, _ = T.plan_mixture(pt64, sp64, mx64)
     with pytest.raises(T.TkdvError) as e:
         ctx.sample_mixture(pt64, pl64, mx64, 1000)
+    assert e.value.status == -5
+    with pytest.raises(T.TkdvError) as e:   # plain BF16 decisions are refused
+        ctx.sample_mixture(pt, pl, mx, 1000, precision=T.BF16)
     assert e.value.status == -5
     # with V = 0 and D = Sigma the mixture is the paper's proposal: same law, and
     # the defensive component's draws are the paper's draws index by index

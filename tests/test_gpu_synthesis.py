@@ -5,7 +5,10 @@ memory; ragged row counts that leave partial tiles and partial waves), the
 kernel's S3 = sum_j u~_j^3 over the N = 4K grid against the oracle's FP64 sum
 of the same FP32 rows (oracle.grid, scaled back to the unscaled field).  The
 error is measured against S3abs = sum_j |u~_j|^3 (S3 itself can vanish), with
-the bound of each arithmetic: FP32 products 2e-5, BF16x3 1e-4, BF16 2e-2.
+the worst-case bound of each arithmetic: FP32 products 1e-6, BF16x3 1e-5 (below
+the per-product bound 3 2^-18 of the split), plain BF16 8e-3 (a measured miss
+of 1e-3 in the worst case, 5.9e-3 at K = 8 and 2.9e-3 at K = 64; its median
+must stay below 1e-3).
 K >= 16 takes the half-period form (on the first half of the grid the even-
 and odd-mode syntheses E, O; the second half holds E - O, and the cubes of
 both halves sum to 2E(E^2 + 3O^2)); K = 8 the plain product.  Edge cases: one
@@ -21,7 +24,8 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 
-BOUND = {"fp32": 2e-5, "bf16x3": 1e-4, "bf16": 2e-2}
+BOUND = {"fp32": 1e-6, "bf16x3": 1e-5, "bf16": 8e-3}
+MEDIAN_BOUND = {"fp32": 1e-6, "bf16x3": 1e-5, "bf16": 1e-3}
 
 
 @pytest.fixture(scope="module")
@@ -53,14 +57,17 @@ def test_synthesis_against_oracle(T, ctx, K, n, prec):
     x = _rows(K, n, seed=K + len(prec))
     s3 = ctx.synthesize(torch.from_numpy(x).cuda(), precision=T.PRECISIONS[prec]).cpu().numpy().astype(np.float64)
     amp = math.sqrt(2.0 / math.pi)            # E0 = 1: u = amp u~
-    err = 0.0
+    errs = np.empty(n)
     for r in range(n):
         u = oracle.grid(x[r].astype(np.float64), 1.0, 4 * K) / amp
         ref, scale = np.sum(u ** 3), np.sum(np.abs(u) ** 3)
-        err = max(err, abs(s3[r] - ref) / scale)
-    print(f"K={K} {prec}: n={n} max |dS3|/S3abs = {err:.2e} (bound {BOUND[prec]:.0e})", flush=True)
+        errs[r] = abs(s3[r] - ref) / scale
+    err, med = errs.max(), np.median(errs)
+    print(f"K={K} {prec}: n={n} max |dS3|/S3abs = {err:.2e} (bound {BOUND[prec]:.0e}), median {med:.2e}",
+          flush=True)
     sys.stdout.flush()
     assert err <= BOUND[prec]
+    assert med <= MEDIAN_BOUND[prec]
 
 
 def test_synthesis_edges(T, ctx):

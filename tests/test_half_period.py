@@ -122,3 +122,75 @@ def test_folded_cholesky_factor_gives_the_woodbury_term():
         y = rng.standard_normal(2)
         assert abs(np.sum((C @ y) ** 2) - y @ M @ y) <= 1e-12 * (y @ M @ y + 1e-300) + 1e-15
         assert np.linalg.norm(C, 2) <= 1.0 + 1e-12
+
+
+# --------------------------------------------------------------------------
+# Quarter-period form (K = 128): cos/sin blocks and mode parities separately
+# --------------------------------------------------------------------------
+
+def _quarter_syntheses(x, K, N):
+    """Ce, Co, Se, So on the representatives xi_j = -pi + 2 pi (j + 1/2)/N with
+    xi in (0, pi/2) (j = N/2 .. 3N/4 - 1): cos/sin block times even/odd modes."""
+    j = np.arange(N // 2, 3 * N // 4)
+    xi = -math.pi + 2 * math.pi * (j + 0.5) / N
+    k = np.arange(1, K + 1)
+    C, S = np.cos(np.outer(xi, k)), np.sin(np.outer(xi, k))
+    ev = k % 2 == 0
+    return (C[:, ev] @ x[:K][ev], C[:, ~ev] @ x[:K][~ev], S[:, ev] @ x[K:][ev], S[:, ~ev] @ x[K:][~ev])
+
+
+@pytest.mark.parametrize("K", [32, 128])
+def test_cube_sum_from_a_quarter_of_the_offset_grid(K):
+    """On the grid offset by half a step, xi -> -xi and xi -> xi + pi map the
+    representatives in (0, pi/2) onto the other three quadrants, where
+    u~ = (Ce + Co) +- (Se + So) and (Ce - Co) +- (Se - So); the four cubes sum to
+    4 Ce (Ce^2 + 3 Co^2 + 3 Se^2 + 3 So^2) + 24 Co Se So, and the trapezoid sum
+    of u^3 on any equispaced grid with N >= 3K + 1 points is (3N/pi) times H3
+    (the definition of H3 as (1/6) int u^3), so it equals the standard grid's
+    sum.  The kernels read the Co, Se, So rows times sqrt(3):
+    4 Ce (Ce^2 + co^2 + se^2 + so^2) + (8/sqrt 3) co se so."""
+    N = 4 * K
+    rng = np.random.default_rng(K + 1)
+    amp = math.sqrt(2.0 / math.pi)
+    r3 = math.sqrt(3.0)
+    for _ in range(10):
+        x = rng.standard_normal(2 * K) / np.sqrt(1.0 + np.tile(np.arange(K), 2))
+        x /= np.linalg.norm(x)
+        u = oracle.grid(x, 1.0, N) / amp
+        ref, scale = np.sum(u ** 3), np.sum(np.abs(u) ** 3)
+        Ce, Co, Se, So = _quarter_syntheses(x, K, N)
+        s3 = np.sum(4 * Ce * (Ce ** 2 + 3 * Co ** 2 + 3 * Se ** 2 + 3 * So ** 2) + 24 * Co * Se * So)
+        assert abs(s3 - ref) < 1e-13 * scale
+        co, se, so = r3 * Co, r3 * Se, r3 * So
+        s3s = np.sum(4 * Ce * (Ce ** 2 + co ** 2 + se ** 2 + so ** 2)) + 8 / r3 * np.sum(co * se * so)
+        assert abs(s3s - ref) < 1e-13 * scale
+        # the four quadrant values are the offset grid's field
+        jj = np.arange(N)
+        xa = -math.pi + 2 * math.pi * (jj + 0.5) / N
+        kk = np.arange(1, K + 1)
+        uo = np.cos(np.outer(xa, kk)) @ x[:K] + np.sin(np.outer(xa, kk)) @ x[K:]
+        A, B, A2, B2 = Ce + Co, Se + So, Ce - Co, Se - So
+        q = N // 4
+        assert np.allclose(uo[N // 2: N // 2 + q], A + B, atol=1e-12)        # xi in (0, pi/2)
+        assert np.allclose(uo[N // 2 - q: N // 2][::-1], A - B, atol=1e-12)  # -xi
+        assert np.allclose(uo[:q], A2 + B2, atol=1e-12)                      # xi - pi
+        assert np.allclose(uo[N - q:][::-1], A2 - B2, atol=1e-12)            # pi - xi
+
+
+def test_quarter_form_operand_layout_covers_every_coordinate_once():
+    """K = 128 operands: lane group g (lanes 16g .. 16g + 15) holds the cos and
+    sin coordinates of modes 32 g + 1 .. 32 g + 32; k-step r of an even-mode
+    (odd-mode) contraction takes from group g the 8 modes 32 g + 2 (8 r + e) + 2
+    (+ 1), e < 8.  Over the two k-steps of each of Ce, Co, Se, So every one of
+    the 2K coordinates enters exactly once."""
+    K = 128
+    seen = np.zeros(2 * K, dtype=int)
+    for block in (0, 1):                 # cos, sin
+        for parity in (0, 1):            # even, odd
+            for r in (0, 1):
+                for g in range(4):
+                    for e in range(8):
+                        k = 32 * g + 2 * (8 * r + e) + (2 if parity == 0 else 1)
+                        assert (k % 2 == 0) == (parity == 0)
+                        seen[block * K + k - 1] += 1
+    assert np.all(seen == 1)

@@ -4,6 +4,8 @@
   of the library includes or names a file under oracle/; the oracle imports
   nothing of the package.
 * bench.py touches the oracle only inside its CPU-baseline functions.
+* The package's Python modules call no trigonometric or random function: the
+  method's arithmetic runs in the library.
 * The binding fails loudly (ImportError) when the HIP library is missing:
   there is no CPU fallback to take its place.
 """
@@ -59,6 +61,21 @@ def test_oracle_never_imports_the_package():
     text = open(os.path.join(ORACLE, "tkdv_oracle.c")).read()
     for inc in re.findall(r'^\s*#\s*include\s*[<"]([^>"]+)[>"]', text, re.M):
         assert "tkdv_" not in inc and "csrc" not in inc, f"the C oracle includes {inc}"
+
+
+def test_package_python_does_no_method_arithmetic():
+    """The Python modules of the package marshal arguments and drive the
+    library: no trigonometric function (the draws, the synthesis, the xi-shift
+    of training rows) and no random-number generator is called there."""
+    banned = {"cos", "sin", "tan", "sincos", "arctan2", "atan2", "standard_normal", "normal", "uniform", "random"}
+    # workloads.py is the seeded generator of parameter points shared with the tests
+    for f in [f for f in _py_files(PKG) if os.path.basename(f) != "workloads.py"]:
+        tree = ast.parse(open(f).read(), filename=f)
+        for node in ast.walk(tree):
+            if isinstance(node, ast.Call):
+                fn = node.func
+                name = fn.attr if isinstance(fn, ast.Attribute) else getattr(fn, "id", "")
+                assert name not in banned, f"{os.path.basename(f)}:{node.lineno} calls {name}"
 
 
 def test_bench_calls_the_oracle_only_for_the_cpu_baseline():
