@@ -314,6 +314,29 @@ tkdv_status tkdv_sample(tkdv_ctx *ctx, const tkdv_point *pt, tkdv_proposal propo
                         tkdv_stats *h_stats, void *stream);
 
 /*
+ * tkdv_sample for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels, outputs and statistics, with every work buffer of the call
+ * (accept bitmap, FP64 re-decision list, counters, segment arrays) taken from
+ * a fixed array in device memory that the library holds per GPU from its
+ * first tkdv_create on that GPU until the process ends (17 MiB); the context
+ * has built every K's synthesis tables at creation.  The call allocates
+ * nothing, on the device or in pinned host memory.  Limits: plan must not be
+ * NULL; proposal UNIFORM or SIGMA; at most 2^26 proposals (n, or
+ * max_proposals in accepted-count mode), TKDV_E_ARG beyond; at most 2^20
+ * proposals inside the FP64 decision window, TKDV_E_CAPACITY beyond.  All
+ * calls on one GPU share the array, so calls that overlap on one GPU (other
+ * streams, other threads, other contexts) race; the array keeps the last
+ * call's contents, and each call clears what must start at zero.  The
+ * violation policy of the context applies (reruns use the same array).
+ */
+tkdv_status tkdv_sample_noalloc(tkdv_ctx *ctx, const tkdv_point *pt, tkdv_proposal proposal,
+                                const tkdv_plan *plan, uint64_t n, tkdv_count_mode mode,
+                                uint64_t max_proposals, tkdv_precision precision,
+                                float *d_xhat, uint64_t *d_index, uint64_t capacity,
+                                tkdv_stats *h_stats, void *stream);
+
+/*
  * Many points in one launch sequence (the points may have different K).
  * pts, plans (may be NULL), n, capacity, out_offset and h_stats are host
  * arrays of length n_points; point p writes rows out_offset[p] ..

@@ -19,6 +19,7 @@
 #include "tkdv_plan.h"
 #include "tkdv_plan_gpu.h"
 #include "tkdv_runtime.h"
+#include "tkdv_scratch.h"
 #include "tkdv_sir.h"
 
 using namespace tkdv;
@@ -1015,8 +1016,128 @@ tkdv_status tkdv_create(int hip_device, tkdv_ctx **out)
             return set_err(nullptr, TKDV_E_DEVICE, hipGetErrorString(e));
         }
     }
+    // set-up of tkdv_sample_noalloc: the device address of this GPU's fixed
+    // scratch array, every K's synthesis tables and the one-point pinned
+    // staging, so that its calls find everything in place
+    e = scratch_init(hip_device);
+    if (e == hipSuccess) e = ensure_host(ctx->h_points, ctx->h_points_bytes, sizeof(DevPoint));
+    if (e == hipSuccess) e = ensure_host(ctx->h_misc, ctx->h_misc_bytes, 64 + sizeof(int));
+    if (e == hipSuccess) e = ensure_host(ctx->h_results, ctx->h_results_bytes, sizeof(PointResult));
+    if (e == hipSuccess) e = ensure_host(ctx->h_counters, ctx->h_counters_bytes, sizeof(DevCounters));
+    if (e != hipSuccess) {
+        tkdv_destroy(ctx);
+        return set_err(nullptr, TKDV_E_DEVICE, std::string("set-up of the fixed scratch: ") + hipGetErrorString(e));
+    }
+    for (int ki = 0; ki < kNumK; ++ki) {
+        const tkdv_status st = build_tables(ctx, 8 << ki);
+        if (st != TKDV_OK) {
+            const std::string msg = ctx->last_error;
+            tkdv_destroy(ctx);
+            return set_err(nullptr, st, msg);
+        }
+    }
     *out = ctx;
     return TKDV_OK;
+}
+
+tkdv_status tkdv_sample_noalloc(tkdv_ctx *ctx, const tkdv_point *pt, tkdv_proposal proposal, const tkdv_plan *plan,
+                                uint64_t n, tkdv_count_mode mode, uint64_t max_proposals, tkdv_precision precision,
+                                float *d_xhat, uint64_t *d_index, uint64_t capacity, tkdv_stats *h_stats,
+                                void *stream)
+{
+    if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");
+    if (!pt || !plan || !h_stats) return set_err(ctx, TKDV_E_ARG, "NULL argument (the plan is required)");
+    tkdv_status s = check_point(ctx, *pt);
+    if (s != TKDV_OK) return s;
+    if (proposal != TKDV_PROP_UNIFORM && proposal != TKDV_PROP_SIGMA)
+        return set_err(ctx, TKDV_E_ARG, "proposal must be UNIFORM or SIGMA");
+    if (plan->proposal != proposal) return set_err(ctx, TKDV_E_ARG, "plan was made for another proposal");
+    if (!std::isfinite(plan->log_M) || !(plan->alpha_star > 0.0))
+        return set_err(ctx, TKDV_E_ARG, "plan has non-finite log_M or alpha*");
+    if (precision != TKDV_FP32 && precision != TKDV_BF16X3)
+        return set_err(ctx, precision == TKDV_BF16 ? TKDV_E_UNSUPPORTED : TKDV_E_ARG, kBf16Refused);
+    if (mode != TKDV_COUNT_PROPOSALS && mode != TKDV_COUNT_ACCEPTED) return set_err(ctx, TKDV_E_ARG, "bad mode");
+    if (mode == TKDV_COUNT_ACCEPTED && max_proposals == 0)
+        return set_err(ctx, TKDV_E_ARG, "accepted-count mode needs max_proposals > 0");
+    const uint64_t covered = mode == TKDV_COUNT_PROPOSALS ? n : max_proposals;
+    if (covered > kScratchMaxProposals)
+        return set_err(ctx, TKDV_E_ARG,
+                       "tkdv_sample_noalloc covers at most 2^26 proposals per call (its fixed scratch); "
+                       "use tkdv_sample for more");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const int ki = kindex(pt->K);
+    char *base = static_cast<char *>(scratch_ptr(ctx->device));
+    if (!base || !ctx->phi_hi[ki].p || !ctx->h_points || ctx->h_points_bytes < sizeof(DevPoint) ||
+        ctx->h_misc_bytes < 64 + sizeof(int) || ctx->h_results_bytes < sizeof(PointResult) ||
+        ctx->h_counters_bytes < sizeof(DevCounters))
+        return set_err(ctx, TKDV_E_DEVICE, "the context's set-up of the fixed scratch is missing");
+    if (n == 0) {
+        std::memset(h_stats, 0, sizeof(*h_stats));
+        const double umax = std::sqrt(2.0 * pt->K * pt->E0 / kPi);
+        h_stats->hist_lo = -umax;
+        h_stats->hist_hi = umax;
+        h_stats->max_log_a = -INFINITY;
+        h_stats->log_M_used = plan->log_M;
+        return TKDV_OK;
+    }
+    // the scratch: accept bitmap, FP64 re-decision list, then the small
+    // records, each 256-byte aligned
+    const uint64_t n_tiles = (covered + kTile - 1) / kTile, n_segs = (n_tiles + kSegWords - 1) / kSegWords;
+    auto carve = [&](size_t &off, size_t bytes) {
+        char *p = base + off;
+        off += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    size_t off = 0;
+    Workspace w;
+    w.bitmap = reinterpret_cast<uint32_t *>(carve(off, (kScratchMaxProposals / 32) * 4));
+    w.defer_list = reinterpret_cast<unsigned long long *>(carve(off, kScratchDeferCap * 8));
+    w.defer_cap = kScratchDeferCap;
+    w.defer_count = reinterpret_cast<unsigned long long *>(carve(off, 16));
+    w.counters = reinterpret_cast<DevCounters *>(carve(off, sizeof(DevCounters)));
+    w.points = reinterpret_cast<DevPoint *>(carve(off, sizeof(DevPoint)));
+    w.results = reinterpret_cast<PointResult *>(carve(off, sizeof(PointResult)));
+    w.plist = reinterpret_cast<int *>(carve(off, sizeof(int)));
+    const size_t max_segs = (kScratchMaxProposals / 32 + kSegWords - 1) / kSegWords;
+    w.seg_cnt = reinterpret_cast<unsigned long long *>(carve(off, max_segs * 8));
+    w.seg_base = reinterpret_cast<unsigned long long *>(carve(off, max_segs * 8));
+    w.seg_stats = reinterpret_cast<SegStats *>(carve(off, max_segs * sizeof(SegStats)));
+    if (off > kScratchBytes) return set_err(ctx, TKDV_E_CAPACITY, "fixed scratch layout exceeds its size");
+    tkdv_plan pl = *plan;
+    const int plist0 = 0;
+    for (int raise = 0;; ++raise) {
+        DevPoint d;
+        fill_devpoint(d, *pt, pl, proposal, precision);
+        d.i0 = 0;
+        d.n = covered;
+        d.n_tiles = n_tiles;
+        d.target = mode == TKDV_COUNT_ACCEPTED ? n : ~0ull;
+        d.bm_off = 0;
+        d.seg_off = 0;
+        d.n_segs = n_segs;
+        d.out_off = 0;
+        d.capacity = capacity;
+        d.row_stride = 2 * (uint64_t)pt->K;
+        CallView v;
+        v.pts = &d;
+        v.np = 1;
+        v.plist = &plist0;
+        v.plist_len = 1;
+        for (int q = 0; q < kNumK; ++q) v.plist_off[q] = v.plist_n[q] = 0;
+        v.plist_n[ki] = 1;
+        v.total_segs = n_segs;
+        PointResult res;
+        DevCounters cnt;
+        s = launch_sequence(ctx, v, w, precision, proposal, d_xhat, reinterpret_cast<unsigned long long *>(d_index),
+                            (hipStream_t)stream, &res, &cnt, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                            true);
+        if (s != TKDV_OK) return s;
+        fill_stats(*h_stats, d, res, cnt, mode);
+        h_stats->M_raises = raise;
+        if (h_stats->n_M_violations == 0 || ctx->mv_policy == TKDV_MV_COUNT) return TKDV_OK;
+        if (ctx->mv_policy == TKDV_MV_FAIL || raise == kMaxRaises) return violation_error(ctx, 0, *h_stats);
+        pl.log_M = raised_log_M(pl.log_M, h_stats->max_log_a, d.tau);
+    }
 }
 
 tkdv_status tkdv_destroy(tkdv_ctx *ctx)

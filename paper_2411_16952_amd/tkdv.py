@@ -132,7 +132,7 @@ EXPORTS = ["tkdv_create", "tkdv_destroy", "tkdv_plan_point", "tkdv_sample", "tkd
            "tkdv_learner_mixture", "tkdv_learner_n_weights", "tkdv_learner_get_weights",
            "tkdv_learner_set_weights", "tkdv_sample_sweep", "tkdv_set_launch_cfg", "tkdv_get_launch_cfg",
            "tkdv_autotune", "tkdv_plan_batch", "tkdv_extremes", "tkdv_sir", "tkdv_plan_mixture_batch",
-           "tkdv_set_violation_policy"]
+           "tkdv_set_violation_policy", "tkdv_sample_noalloc"]
 
 _P = C.c_void_p
 lib.tkdv_create.argtypes = [C.c_int, C.POINTER(_P)]
@@ -140,6 +140,8 @@ lib.tkdv_destroy.argtypes = [_P]
 lib.tkdv_plan_point.argtypes = [C.POINTER(Point), C.c_int, C.POINTER(Plan)]
 lib.tkdv_sample.argtypes = [_P, C.POINTER(Point), C.c_int, C.POINTER(Plan), C.c_uint64, C.c_int,
                             C.c_uint64, C.c_int, _P, _P, C.c_uint64, C.POINTER(Stats), _P]
+lib.tkdv_sample_noalloc.argtypes = [_P, C.POINTER(Point), C.c_int, C.POINTER(Plan), C.c_uint64, C.c_int,
+                                    C.c_uint64, C.c_int, _P, _P, C.c_uint64, C.POINTER(Stats), _P]
 lib.tkdv_sample_batch.argtypes = [_P, C.c_int32, C.POINTER(Point), C.c_int, C.POINTER(Plan),
                                   C.POINTER(C.c_uint64), C.c_int, C.c_uint64, C.c_int, _P, _P,
                                   C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(Stats), _P]
@@ -314,6 +316,24 @@ class Context:
                                C.byref(plan) if plan is not None else None, int(n), int(mode),
                                int(max_proposals), int(precision), _ptr(xhat), _ptr(index),
                                int(capacity), C.byref(st), _stream(stream)), self._h)
+        d = st.to_dict()
+        nw = d["n_written"]
+        d["xhat"] = xhat[:nw] if xhat is not None else None
+        d["index"] = index[:nw] if index is not None else None
+        return d
+
+    def sample_noalloc(self, point: Point, n: int, plan: Plan, proposal: int = SIGMA,
+                       mode: int = COUNT_PROPOSALS, max_proposals: int = 0, precision: int = BF16X3,
+                       xhat=None, index=None, stream=None) -> dict:
+        """tkdv_sample_noalloc: the library allocates nothing; the caller passes
+        the output tensors (xhat (capacity, 2K) float32, index (capacity,) int64,
+        both or neither), the plan is required."""
+        assert (xhat is None) == (index is None)
+        capacity = 0 if xhat is None else int(xhat.shape[0])
+        st = Stats()
+        _check(lib.tkdv_sample_noalloc(self._h, C.byref(point), int(proposal), C.byref(plan), int(n), int(mode),
+                                       int(max_proposals), int(precision), _ptr(xhat), _ptr(index), capacity,
+                                       C.byref(st), _stream(stream)), self._h)
         d = st.to_dict()
         nw = d["n_written"]
         d["xhat"] = xhat[:nw] if xhat is not None else None
