@@ -127,11 +127,11 @@ def method_mfma_flops(K: int, precision: str = "bf16x3", proposal: str = "sigma"
 
 def executed_mfma_flops(K: int, precision: str = "bf16x3", proposal: str = "sigma") -> float:
     """Matrix flops the kernels execute per proposal: K = 8 the plain product;
-    16 <= K <= 64 the half-period form (even and odd modes on half the grid:
-    half the plain product); K = 128 the quarter-period form (cos/sin blocks and
+    K = 16, 32 the half-period form (even and odd modes on half the grid: half
+    the plain product); K = 64, 128 the quarter-period form (cos/sin blocks and
     mode parities on a quarter of the offset grid: a quarter); the mixture's y
     products in full."""
-    frac = 1.0 if K == 8 else (0.5 if K <= 64 else 0.25)
+    frac = 1.0 if K == 8 else (0.5 if K <= 32 else 0.25)
     terms = {"bf16x3": 3, "fp32": 1}[precision]
     y = 2 * (2 * K) * 64 if proposal == "mixture" else 0
     return terms * (frac * 2 * (2 * K) * (4 * K) + y)

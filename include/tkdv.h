@@ -191,7 +191,8 @@ typedef struct {
     int32_t decide_launches;
     int32_t decide_grid;    /* workgroups of the (last) k_decide launch             */
     int32_t decide_block;   /* threads per workgroup                                */
-    int32_t windows;        /* tkdv_sample_sweep: windows run (graph replays)        */
+    int32_t windows;        /* tkdv_sample_sweep: windows run                         */
+    int32_t graph_launches; /* tkdv_sample_sweep: graph launches (16 windows each)     */
 } tkdv_timing;
 
 typedef struct tkdv_ctx tkdv_ctx;
@@ -518,26 +519,39 @@ tkdv_status tkdv_learner_set_weights(tkdv_learner *learner, const double *h_in, 
  * points of mixed K in windows of proposals.  Launch configuration per
  * (K, arithmetic):
  */
+#define TKDV_DECIDE_VARIANTS 4
 typedef struct {
-    int32_t blocks_per_cu;  /* decide workgroups per compute unit, 0: as many as fit  */
-    int32_t use_graph;      /* 1: one window captured in a hipGraph and replayed       */
-    uint64_t window;        /* proposals per point per window, a multiple of 65536     */
+    int32_t blocks_per_cu;  /* decide workgroups per compute unit, 0: as many as fit   */
+    int32_t use_graph;      /* 1: 16 windows captured in one hipGraph, launched once     */
+    uint64_t window;        /* proposals of a point's first window, a multiple of 65536 */
+    int32_t variant;        /* tile variant of the decision kernel, 0..3 (BF16x3 at
+                               K = 16, 32, 64: workgroup threads x tile pairs per group;
+                               0 elsewhere)                                             */
+    int32_t adaptive;       /* 1: later windows sized on the device from the measured
+                               acceptance; 0: every window `window` proposals           */
 } tkdv_launch_cfg;
 
 /* Point p draws proposals i = 0, 1, ... until targets[p] (>= 1) samples are
  * accepted or max_proposals[p] proposals are used (Sec. IV.B's loop, in
  * windows).  One window is one launch sequence over every unfinished point:
- * decisions per K, FP64 re-decision, ordered compaction and statistics, and
- * a device-side advance of every point to its next window; it is captured
- * once as a hipGraph and replayed until no point is left, the host reading
- * one counter per window.  Output as in tkdv_sample_batch: the first
- * targets[p] accepted samples by index in rows (out_offset[p] + r) of d_xhat
- * (stride 2 * TKDV_KMAX floats) and d_index, at most capacity[p] rows; stats
- * cover the same samples; n_proposed counts the proposals up to the last of
- * them (or max_proposals[p]).  cfg NULL: the context's configuration of each
- * K (tkdv_set_launch_cfg / tkdv_autotune), by default all workgroups that
- * fit and windows of 2^26 proposals; otherwise cfg for every K.  Plans must
- * be Sigma plans (or NULL: planned here). */
+ * decisions per K, FP64 re-decision, ordered compaction and statistics, and a
+ * device-side advance of every point to its next window.  The first window of
+ * a point has `window` proposals; with `adaptive` the device sizes each later
+ * one from the point's measured acceptance (1.25 times the proposals still
+ * needed, four times those so far while none is accepted), sharing a bitmap
+ * pool of up to 2^33 proposals in proportion when they do not fit, so that
+ * most points finish in their second window.  16 windows are captured in one
+ * hipGraph and launched at once (use_graph; otherwise the same 16 windows are
+ * launched directly); the host reads the device state once per 16 windows,
+ * and a window without unfinished points does nothing.  Output as in
+ * tkdv_sample_batch: the first targets[p] accepted samples by index in rows
+ * (out_offset[p] + r) of d_xhat (stride 2 * TKDV_KMAX floats) and d_index, at
+ * most capacity[p] rows; stats cover the same samples; n_proposed counts the
+ * proposals up to the last of them (or max_proposals[p]).  cfg NULL: the
+ * context's configuration of each K (tkdv_set_launch_cfg / tkdv_autotune), by
+ * default all workgroups that fit, first windows of 2^26 proposals, variant 0,
+ * adaptive; otherwise cfg for every K.  Plans must be Sigma plans (or NULL:
+ * planned here). */
 tkdv_status tkdv_sample_sweep(tkdv_ctx *ctx, int32_t n_points, const tkdv_point *pts, const tkdv_plan *plans,
                               const uint64_t *targets, const uint64_t *max_proposals, tkdv_precision precision,
                               const tkdv_launch_cfg *cfg, float *d_xhat, uint64_t *d_index,
@@ -549,8 +563,10 @@ tkdv_status tkdv_set_launch_cfg(tkdv_ctx *ctx, int32_t K, tkdv_precision precisi
 tkdv_status tkdv_get_launch_cfg(const tkdv_ctx *ctx, int32_t K, tkdv_precision precision, tkdv_launch_cfg *out);
 
 /* Autotuner: times a probe sweep (16 points of this K, beta' in [20, 60],
- * accepted targets of about 2^14) for every blocks_per_cu that fits and
- * windows of 2^24, 2^25 and 2^26 proposals, keeps the fastest (proposals/s),
+ * a fixed number of proposals each) for every tile variant of the decision
+ * kernel (TKDV_DECIDE_VARIANTS: workgroup size and tile pairs per group, at
+ * K = 16, 32, 64 with BF16x3), every blocks_per_cu that fits it, and first
+ * windows of 2^24, 2^25 and 2^26 proposals; keeps the fastest (proposals/s),
  * stores it in the context and, when cache_path is not NULL, in a text cache
  * keyed by device, K and precision (a cached entry is used without timing).
  * *out (may be NULL) receives the choice. */

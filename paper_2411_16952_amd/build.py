@@ -15,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtkdv.so")
-SOURCES = ["tkdv_kernels.hip", "tkdv_k128.hip", "tkdv_scratch.hip", "tkdv_synth.hip", "tkdv_learn.hip", "tkdv_plan_gpu.hip", "tkdv_extremes.hip", "tkdv_sir.hip",
+SOURCES = ["tkdv_kernels.hip", "tkdv_quarter.hip", "tkdv_scratch.hip", "tkdv_synth.hip", "tkdv_learn.hip", "tkdv_plan_gpu.hip", "tkdv_extremes.hip", "tkdv_sir.hip",
            "tkdv_api.cpp",
            "tkdv_plan.cpp",
            "tkdv_mixture.cpp"]

@@ -67,6 +67,7 @@ struct tkdv_ctx {
     // K = 128 (index 4): the quarter-period tables of k_decide128 (BF16 hi, lo,
     // FP32) and, in phi_mat128, the FP32 table of its statistics synthesis
     DevBuf phi_hi[kNumK], phi_lo[kNumK], phi_f32[kNumK], phi_mat128;
+    DevBuf q64_hi, q64_lo, q64_f32;  // K = 64's quarter-period tables (its tile variant 3)
     // the same tables with the odd-mode rows scaled by sqrt(3), for the kernels
     // that form S3 in the half-period form (K >= 16): s3_tables()
     DevBuf phi3_hi[kNumK], phi3_lo[kNumK], phi3_f32[kNumK];
@@ -156,9 +157,9 @@ hipError_t ensure_host(void *&p, size_t &have, size_t bytes)
 //   16][64 lanes][e < 4], grid point 16 T + l % 16, k-step m = 4 m4 + e of lane
 //   group g: cos of mode 32 g + m + 1 (m < 32), sin of mode 32 g + m - 31.
 //   Angles are reduced exactly in integers before the FP64 cos/sin.
-tkdv_status build_tables128(tkdv_ctx *ctx)
+hipError_t upload_quarter(int K, DevBuf &d_hi, DevBuf &d_lo, DevBuf &d_f32)
 {
-    const int K = 128, N = 4 * K;
+    const int N = 4 * K, CPL = K / 4, TILES = K / 16, STEPS = K / 64, QG = K / 32;
     const double r3 = std::sqrt(3.0);
     // entry of output o at representative rho for mode k: angle k pi (2 rho + 1)/N
     auto qval = [&](int o, int k, int rho) {
@@ -167,27 +168,40 @@ tkdv_status build_tables128(tkdv_ctx *ctx)
         const double v = (o < 2) ? std::cos(ang) : std::sin(ang);
         return o == 0 ? v : r3 * v;
     };
-    auto mode = [](int o, int g, int idx) { return 32 * g + 2 * idx + ((o == 0 || o == 2) ? 2 : 1); };
-    std::vector<uint16_t> hi((size_t)8 * 4 * 2 * 64 * 8), lo(hi.size());
-    for (int tau = 0; tau < 8; ++tau)
+    auto mode = [&](int o, int g, int idx) { return CPL * g + 2 * idx + ((o == 0 || o == 2) ? 2 : 1); };
+    std::vector<uint16_t> hi((size_t)TILES * 4 * STEPS * 64 * 8), lo(hi.size());
+    for (int tau = 0; tau < TILES; ++tau)
         for (int o = 0; o < 4; ++o)
-            for (int r = 0; r < 2; ++r)
+            for (int r = 0; r < STEPS; ++r)
                 for (int l = 0; l < 64; ++l)
                     for (int e = 0; e < 8; ++e) {
                         const double v = qval(o, mode(o, l / 16, 8 * r + e), 16 * tau + l % 16);
                         const uint16_t h = bf16_bits((float)v);
-                        const size_t idx = ((((size_t)tau * 4 + o) * 2 + r) * 64 + l) * 8 + e;
+                        const size_t idx = ((((size_t)tau * 4 + o) * STEPS + r) * 64 + l) * 8 + e;
                         hi[idx] = h;
                         lo[idx] = bf16_bits((float)(v - (double)bf16_value(h)));
                     }
-    std::vector<float> f32((size_t)8 * 4 * 4 * 64 * 4);
-    for (int tau = 0; tau < 8; ++tau)
+    std::vector<float> f32((size_t)TILES * 4 * QG * 64 * 4);
+    for (int tau = 0; tau < TILES; ++tau)
         for (int o = 0; o < 4; ++o)
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < QG; ++q)
                 for (int l = 0; l < 64; ++l)
                     for (int e = 0; e < 4; ++e)
-                        f32[((((size_t)tau * 4 + o) * 4 + q) * 64 + l) * 4 + e] =
+                        f32[((((size_t)tau * 4 + o) * QG + q) * 64 + l) * 4 + e] =
                             (float)qval(o, mode(o, l / 16, 4 * q + e), 16 * tau + l % 16);
+    hipError_t e = ensure(d_hi, hi.size() * 2);
+    if (e == hipSuccess) e = ensure(d_lo, lo.size() * 2);
+    if (e == hipSuccess) e = ensure(d_f32, f32.size() * 4);
+    if (e == hipSuccess) e = hipMemcpy(d_hi.p, hi.data(), hi.size() * 2, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_lo.p, lo.data(), lo.size() * 2, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_f32.p, f32.data(), f32.size() * 4, hipMemcpyHostToDevice);
+    return e;
+}
+
+tkdv_status build_tables128(tkdv_ctx *ctx)
+{
+    const int N = 4 * 128;
+    HIP_TRY(ctx, upload_quarter(128, ctx->phi_hi[4], ctx->phi_lo[4], ctx->phi_f32[4]));
     std::vector<float> mat((size_t)32 * 16 * 64 * 4);
     for (int T = 0; T < 32; ++T)
         for (int m4 = 0; m4 < 16; ++m4)
@@ -202,13 +216,7 @@ tkdv_status build_tables128(tkdv_ctx *ctx)
                     mat[(((size_t)T * 16 + m4) * 64 + l) * 4 + e] =
                         (float)(cosb ? sign * std::cos(ang) : sign * std::sin(ang));
                 }
-    HIP_TRY(ctx, ensure(ctx->phi_hi[4], hi.size() * 2));
-    HIP_TRY(ctx, ensure(ctx->phi_lo[4], lo.size() * 2));
-    HIP_TRY(ctx, ensure(ctx->phi_f32[4], f32.size() * 4));
     HIP_TRY(ctx, ensure(ctx->phi_mat128, mat.size() * 4));
-    HIP_TRY(ctx, hipMemcpy(ctx->phi_hi[4].p, hi.data(), hi.size() * 2, hipMemcpyHostToDevice));
-    HIP_TRY(ctx, hipMemcpy(ctx->phi_lo[4].p, lo.data(), lo.size() * 2, hipMemcpyHostToDevice));
-    HIP_TRY(ctx, hipMemcpy(ctx->phi_f32[4].p, f32.data(), f32.size() * 4, hipMemcpyHostToDevice));
     HIP_TRY(ctx, hipMemcpy(ctx->phi_mat128.p, mat.data(), mat.size() * 4, hipMemcpyHostToDevice));
     return TKDV_OK;
 }
@@ -261,6 +269,7 @@ tkdv_status build_tables(tkdv_ctx *ctx, int K)
         return e;
     };
     if (K == 128) return build_tables128(ctx);
+    if (K == 64) HIP_TRY(ctx, upload_quarter(64, ctx->q64_hi, ctx->q64_lo, ctx->q64_f32));
     if (K >= 16) HIP_TRY(ctx, upload(std::sqrt(3.0), ctx->phi3_hi[ki], ctx->phi3_lo[ki], ctx->phi3_f32[ki]));
     HIP_TRY(ctx, upload(1.0, ctx->phi_hi[ki], ctx->phi_lo[ki], ctx->phi_f32[ki]));
     return TKDV_OK;
@@ -269,6 +278,20 @@ tkdv_status build_tables(tkdv_ctx *ctx, int K)
 // Tables read by the S3 kernels (k_decide, k_decide_mix, k_synth): the scaled
 // set in the half-period form (16 <= K <= 64), the plain tables at K = 8, the
 // quarter-period tables at K = 128.
+// Tables of the default decision kernel of K = 8 << ki (variant 0 of the
+// tuner's tile variants; the others read the S3 tables): the quarter-period
+// tables at K = 64.
+void s3_tables(const tkdv_ctx *ctx, int ki, int precision, const void *&hi, const void *&lo);
+void decide_tables(const tkdv_ctx *ctx, int ki, int precision, int variant, const void *&hi, const void *&lo)
+{
+    if (ki == 3 && variant == 0) {
+        hi = precision == TKDV_FP32 ? ctx->q64_f32.p : ctx->q64_hi.p;
+        lo = ctx->q64_lo.p;
+        return;
+    }
+    s3_tables(ctx, ki, precision, hi, lo);
+}
+
 void s3_tables(const tkdv_ctx *ctx, int ki, int precision, const void *&hi, const void *&lo)
 {
     if (ki == 4) {  // K = 128: the quarter-period tables
@@ -486,7 +509,7 @@ tkdv_status launch_sequence(tkdv_ctx *ctx, const CallView &v, const Workspace &w
         const int K = 8 << ki;
         // the largest K of the call sets the reported workgroup size
         ctx->timing.decide_block = proposal == TKDV_PROP_MIXTURE ? kMixBlock : decide_block(K);
-        s3_tables(ctx, ki, precision, a.phi_hi, a.phi_lo);
+        decide_tables(ctx, ki, precision, 0, a.phi_hi, a.phi_lo);
         unsigned long long tiles = 0;
         for (int q = 0; q < v.plist_n[ki]; ++q) tiles += v.pts[v.plist[v.plist_off[ki] + q]].n_tiles;
         if (proposal == TKDV_PROP_MIXTURE)
@@ -764,6 +787,9 @@ void fill_stats_sweep(tkdv_stats &s, const DevPoint &P, const SweepState &w)
 
 int prec_index(int precision) { return precision < 0 || precision > 2 ? 0 : precision; }
 
+// Windows captured into one graph (one launch, one host synchronisation).
+constexpr int kSweepGraphWindows = 16;
+
 tkdv_status sweep(tkdv_ctx *ctx, int np, const tkdv_point *pts, const tkdv_plan *plans, const uint64_t *targets,
                   const uint64_t *maxp, int precision, const tkdv_launch_cfg *cfg, float *d_xhat,
                   uint64_t *d_index, const uint64_t *capacity, const uint64_t *out_offset, tkdv_stats *h_stats,
@@ -780,9 +806,9 @@ tkdv_status sweep(tkdv_ctx *ctx, int np, const tkdv_point *pts, const tkdv_plan 
     std::vector<std::vector<int>> by_k(kNumK);
     std::vector<SweepState> sw(np);
     tkdv_launch_cfg kcfg[kNumK];
-    bool use_graph = true;
-    unsigned long long bm = 0, segs = 0, max_windows = 0;
+    bool use_graph = true, adaptive = np <= 1024;
     for (int ki = 0; ki < kNumK; ++ki) kcfg[ki] = cfg ? *cfg : ctx->lcfg[ki][prec_index(precision)];
+    unsigned long long first_words = 0, sum_maxp = 0;
     for (int p = 0; p < np; ++p) {
         tkdv_status s = check_point(ctx, pts[p]);
         if (s != TKDV_OK) return s;
@@ -798,24 +824,25 @@ tkdv_status sweep(tkdv_ctx *ctx, int np, const tkdv_point *pts, const tkdv_plan 
         }
         const int ki = kindex(pts[p].K);
         const tkdv_launch_cfg &lc = kcfg[ki];
-        if (lc.window < 65536 || lc.window % 65536 != 0 || lc.window > (1ull << 34) || lc.blocks_per_cu < 0)
-            return set_err(ctx, TKDV_E_ARG, "window must be a multiple of 65536 in [65536, 2^34]");
+        if (lc.window < 65536 || lc.window % 65536 != 0 || lc.window > (1ull << 34) || lc.blocks_per_cu < 0 ||
+            lc.variant < 0 || lc.variant >= TKDV_DECIDE_VARIANTS)
+            return set_err(ctx, TKDV_E_ARG, "window must be a multiple of 65536 in [65536, 2^34], variant in range");
         use_graph = use_graph && lc.use_graph;
+        adaptive = adaptive && lc.adaptive;
         DevPoint &d = call.pts[p];
         fill_devpoint(d, pts[p], pl, TKDV_PROP_SIGMA, precision);
-        const uint64_t W = lc.window, words = W / kTile;
+        const uint64_t W = lc.window;
         d.i0 = 0;
         d.n = std::min<uint64_t>(W, maxp[p]);
         d.n_tiles = (d.n + kTile - 1) / kTile;
+        d.n_segs = (d.n_tiles + kSegWords - 1) / kSegWords;
         d.target = targets[p];
-        d.bm_off = bm;
-        d.seg_off = segs;
-        d.n_segs = (words + kSegWords - 1) / kSegWords;
+        d.bm_off = first_words;
         d.out_off = out_offset ? out_offset[p] : 0;
         d.capacity = capacity ? capacity[p] : 0;
         d.row_stride = 2 * TKDV_KMAX;
-        bm += words;
-        segs += d.n_segs;
+        first_words += d.n_tiles;
+        sum_maxp += maxp[p];
         std::memset(&sw[p], 0, sizeof(SweepState));
         sw[p].i_start = 0;
         sw[p].i_end = maxp[p];
@@ -823,8 +850,23 @@ tkdv_status sweep(tkdv_ctx *ctx, int np, const tkdv_point *pts, const tkdv_plan 
         sw[p].target = targets[p];
         sw[p].capacity = d.capacity;
         sw[p].out_off = d.out_off;
-        max_windows = std::max<unsigned long long>(max_windows, (maxp[p] + W - 1) / W);
         by_k[ki].push_back(p);
+    }
+    // the window's accept bitmap: the first windows, or (adaptive) a pool of up
+    // to 2^33 proposals shared by the points' later windows, plus one segment
+    // per point of rounding
+    unsigned long long pool_words = first_words;
+    if (adaptive) pool_words = std::max<unsigned long long>(first_words, std::min<unsigned long long>(
+                                                                              (1ull << 33) / kTile, sum_maxp / kTile));
+    const unsigned long long bm_words = pool_words + (unsigned long long)np * kSegWords;
+    const unsigned long long max_segs = bm_words / kSegWords + np;
+    {
+        unsigned long long segs = 0;
+        for (int p = 0; p < np; ++p) {
+            call.pts[p].seg_off = segs;
+            segs += call.pts[p].n_segs;
+        }
+        call.total_segs = segs;
     }
     call.plist.clear();
     for (int ki = 0; ki < kNumK; ++ki) {
@@ -832,27 +874,32 @@ tkdv_status sweep(tkdv_ctx *ctx, int np, const tkdv_point *pts, const tkdv_plan 
         call.plist_n[ki] = (int)by_k[ki].size();
         call.plist.insert(call.plist.end(), by_k[ki].begin(), by_k[ki].end());
     }
-    call.bitmap_words = bm;
-    call.total_segs = segs;
     hipStream_t sst = ctx->sweep_stream;
-    const unsigned long long defer_cap = std::min<unsigned long long>(1ull << 26, std::max<unsigned long long>(1ull << 20, bm));
-    HIP_TRY(ctx, ensure(ctx->bitmap, bm * 4));
+    const unsigned long long defer_cap = std::min<unsigned long long>(1ull << 26, std::max<unsigned long long>(1ull << 20, bm_words));
+    HIP_TRY(ctx, ensure(ctx->bitmap, bm_words * 4));
     HIP_TRY(ctx, ensure(ctx->defer_list, defer_cap * 8));
-    HIP_TRY(ctx, ensure(ctx->defer_count, 8));
+    HIP_TRY(ctx, ensure(ctx->defer_count, 16));
     HIP_TRY(ctx, ensure(ctx->counters, sizeof(DevCounters) * np));
     HIP_TRY(ctx, ensure(ctx->points, sizeof(DevPoint) * np));
-    HIP_TRY(ctx, ensure(ctx->seg_cnt, 8 * segs));
-    HIP_TRY(ctx, ensure(ctx->seg_base, 8 * segs));
-    HIP_TRY(ctx, ensure(ctx->seg_stats, sizeof(SegStats) * segs));
+    HIP_TRY(ctx, ensure(ctx->seg_cnt, 8 * max_segs));
+    HIP_TRY(ctx, ensure(ctx->seg_base, 8 * max_segs));
+    HIP_TRY(ctx, ensure(ctx->seg_stats, sizeof(SegStats) * max_segs));
     HIP_TRY(ctx, ensure(ctx->results, sizeof(PointResult) * np));
     HIP_TRY(ctx, ensure(ctx->plist, sizeof(int) * call.plist.size()));
     HIP_TRY(ctx, ensure(ctx->sweep, sizeof(SweepState) * np));
-    HIP_TRY(ctx, ensure(ctx->active, 8));
+    HIP_TRY(ctx, ensure(ctx->active, sizeof(SweepGlobal)));
     for (int ki = 0; ki < kNumK; ++ki)
         if (call.plist_n[ki]) {
             tkdv_status s = build_tables(ctx, 8 << ki);
             if (s != TKDV_OK) return s;
         }
+    SweepGlobal g0;
+    std::memset(&g0, 0, sizeof(g0));
+    g0.pool_tiles = pool_words;
+    g0.total_segs = call.total_segs;
+    g0.active = (unsigned long long)np;
+    g0.defer_cap = defer_cap;
+    g0.adaptive = adaptive ? 1 : 0;
     // the caller's stream has finished its earlier work before the sweep reads
     // or writes the caller's buffers
     HIP_TRY(ctx, hipEventRecord(ctx->join[0], user_st));
@@ -861,8 +908,10 @@ tkdv_status sweep(tkdv_ctx *ctx, int np, const tkdv_point *pts, const tkdv_plan 
     HIP_TRY(ctx, hipMemcpyAsync(ctx->plist.p, call.plist.data(), sizeof(int) * call.plist.size(),
                                 hipMemcpyHostToDevice, sst));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->sweep.p, sw.data(), sizeof(SweepState) * np, hipMemcpyHostToDevice, sst));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->active.p, &g0, sizeof(g0), hipMemcpyHostToDevice, sst));
     HIP_TRY(ctx, hipStreamSynchronize(sst));  // host vectors are pageable and go out of scope
 
+    SweepGlobal *dG = reinterpret_cast<SweepGlobal *>(ctx->active.p);
     KernelArgs a;
     std::memset(&a, 0, sizeof(a));
     a.pts = reinterpret_cast<const DevPoint *>(ctx->points.p);
@@ -872,12 +921,14 @@ tkdv_status sweep(tkdv_ctx *ctx, int np, const tkdv_point *pts, const tkdv_plan 
     a.defer_list = reinterpret_cast<unsigned long long *>(ctx->defer_list.p);
     a.defer_count = reinterpret_cast<unsigned long long *>(ctx->defer_count.p);
     a.defer_cap = defer_cap;
+    a.d_total_segs = &dG->total_segs;
     const int *d_plist = reinterpret_cast<const int *>(ctx->plist.p);
     unsigned long long *seg_cnt = reinterpret_cast<unsigned long long *>(ctx->seg_cnt.p);
     unsigned long long *seg_base = reinterpret_cast<unsigned long long *>(ctx->seg_base.p);
     SegStats *seg_stats = reinterpret_cast<SegStats *>(ctx->seg_stats.p);
     PointResult *res = reinterpret_cast<PointResult *>(ctx->results.p);
-    unsigned long long *active = reinterpret_cast<unsigned long long *>(ctx->active.p);
+    // one window: every launch is sized for the largest window (persistent
+    // kernels), the device holds the current window's extent
     auto window = [&]() -> tkdv_status {
         HIP_TRY(ctx, launch_fill_u32(ctx->counters.p, sizeof(DevCounters) * np / 4, 0u, sst));
         HIP_TRY(ctx, launch_fill_u32(ctx->results.p, sizeof(PointResult) * np / 4, 0u, sst));
@@ -886,24 +937,35 @@ tkdv_status sweep(tkdv_ctx *ctx, int np, const tkdv_point *pts, const tkdv_plan 
             if (call.plist_n[ki] == 0) continue;
             const int K = 8 << ki;
             a.blocks_per_cu = kcfg[ki].blocks_per_cu;
-            s3_tables(ctx, ki, precision, a.phi_hi, a.phi_lo);
-            const unsigned long long tiles = (unsigned long long)call.plist_n[ki] * (kcfg[ki].window / kTile);
-            HIP_TRY(ctx, launch_decide(K, precision, TKDV_PROP_SIGMA, a, d_plist + call.plist_off[ki],
-                                       call.plist_n[ki], ctx->n_cu, tiles, sst, nullptr));
+            // the tile variants other than 0 run with BF16x3 products only
+            decide_tables(ctx, ki, precision, precision == TKDV_BF16X3 ? kcfg[ki].variant : 0, a.phi_hi,
+                          a.phi_lo);
+            HIP_TRY(ctx, launch_decide_variant(K, precision, TKDV_PROP_SIGMA, kcfg[ki].variant, a,
+                                               d_plist + call.plist_off[ki], call.plist_n[ki], ctx->n_cu,
+                                               pool_words, sst, nullptr));
         }
         HIP_TRY(ctx, launch_fixup(a, ctx->n_cu, sst));
-        HIP_TRY(ctx, launch_segments(a, segs, seg_cnt, seg_base, res, ctx->n_cu, sst));
+        HIP_TRY(ctx, launch_segments(a, max_segs, seg_cnt, seg_base, res, ctx->n_cu, sst));
         for (int ki = 0; ki < kNumK; ++ki) {
             if (call.plist_n[ki] == 0) continue;
             a.phi_hi = ki == 4 ? ctx->phi_mat128.p : ctx->phi_f32[ki].p;
             HIP_TRY(ctx, launch_materialize(8 << ki, TKDV_PROP_SIGMA, a, d_plist + call.plist_off[ki],
-                                            call.plist_n[ki], segs, seg_cnt, seg_base, seg_stats, res, d_xhat,
+                                            call.plist_n[ki], max_segs, seg_cnt, seg_base, seg_stats, res, d_xhat,
                                             reinterpret_cast<unsigned long long *>(d_index), ctx->n_cu, sst));
         }
         HIP_TRY(ctx, launch_finalize(a, seg_cnt, seg_base, seg_stats, res, sst));
-        HIP_TRY(ctx, launch_fill_u32(ctx->active.p, 2, 0u, sst));
         HIP_TRY(ctx, launch_window_advance(reinterpret_cast<DevPoint *>(ctx->points.p), a.cnt, res,
-                                           reinterpret_cast<SweepState *>(ctx->sweep.p), np, active, sst));
+                                           reinterpret_cast<SweepState *>(ctx->sweep.p), np, dG,
+                                           reinterpret_cast<const unsigned long long *>(ctx->defer_count.p), sst));
+        return TKDV_OK;
+    };
+    // kSweepGraphWindows windows per launch (a window with no point left does
+    // nothing); the host looks at the device state once per launch
+    auto batch = [&]() -> tkdv_status {
+        for (int w = 0; w < kSweepGraphWindows; ++w) {
+            tkdv_status s = window();
+            if (s != TKDV_OK) return s;
+        }
         return TKDV_OK;
     };
     hipGraph_t graph = nullptr;
@@ -916,7 +978,7 @@ tkdv_status sweep(tkdv_ctx *ctx, int np, const tkdv_point *pts, const tkdv_plan 
     };
     if (use_graph) {
         HIP_TRY(ctx, hipStreamBeginCapture(sst, hipStreamCaptureModeThreadLocal));
-        tkdv_status s = window();
+        tkdv_status s = batch();
         hipError_t e = hipStreamEndCapture(sst, &graph);
         if (s != TKDV_OK) {
             release();
@@ -934,24 +996,25 @@ tkdv_status sweep(tkdv_ctx *ctx, int np, const tkdv_point *pts, const tkdv_plan 
     }
     std::memset(&ctx->timing, 0, sizeof(ctx->timing));
     for (int ki = 0; ki < kNumK; ++ki)  // the largest K of the sweep sets the reported workgroup size
-        if (!by_k[ki].empty()) ctx->timing.decide_block = decide_block(8 << ki);
-    unsigned long long *poll = reinterpret_cast<unsigned long long *>(ctx->h_poll);
+        if (!by_k[ki].empty()) ctx->timing.decide_block = decide_variant_block(8 << ki, kcfg[ki].variant);
+    SweepGlobal *poll = reinterpret_cast<SweepGlobal *>(ctx->h_poll);
     tkdv_status st_out = TKDV_OK;
-    int windows = 0;
+    int launches = 0;
+    // a point takes at least one window per 2^34 proposals of its range
+    const unsigned long long max_launches = 1 + (sum_maxp / 65536 + (unsigned long long)np) / kSweepGraphWindows;
     hipError_t e = hipEventRecord(ctx->ev[0], sst);
-    for (unsigned long long w = 0; w < max_windows && e == hipSuccess && st_out == TKDV_OK; ++w) {
+    for (unsigned long long L = 0; L < max_launches && e == hipSuccess && st_out == TKDV_OK; ++L) {
         if (use_graph) e = hipGraphLaunch(exec, sst);
-        else st_out = window();
+        else st_out = batch();
         if (e != hipSuccess || st_out != TKDV_OK) break;
-        ++windows;
-        if ((e = hipMemcpyAsync(poll, active, 8, hipMemcpyDeviceToHost, sst)) != hipSuccess) break;
-        if ((e = hipMemcpyAsync(poll + 1, ctx->defer_count.p, 8, hipMemcpyDeviceToHost, sst)) != hipSuccess) break;
+        ++launches;
+        if ((e = hipMemcpyAsync(poll, dG, sizeof(SweepGlobal), hipMemcpyDeviceToHost, sst)) != hipSuccess) break;
         if ((e = hipStreamSynchronize(sst)) != hipSuccess) break;
-        if (poll[1] > defer_cap) {
+        if (poll->overflow) {
             st_out = set_err(ctx, TKDV_E_CAPACITY, "FP64 re-decision list overflowed in a sweep window");
             break;
         }
-        if (poll[0] == 0) break;
+        if (poll->active == 0) break;
     }
     if (e == hipSuccess) e = hipEventRecord(ctx->ev[1], sst);
     if (e == hipSuccess) e = hipEventSynchronize(ctx->ev[1]);
@@ -961,10 +1024,11 @@ tkdv_status sweep(tkdv_ctx *ctx, int np, const tkdv_point *pts, const tkdv_plan 
     float ms = 0.0f;
     HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
     ctx->timing.total_ms = ms;
-    ctx->timing.windows = windows;
+    ctx->timing.windows = (int)poll->windows;
+    ctx->timing.graph_launches = launches;
     int nk = 0;
     for (int ki = 0; ki < kNumK; ++ki) nk += call.plist_n[ki] ? 1 : 0;
-    ctx->timing.decide_launches = windows * nk;
+    ctx->timing.decide_launches = (int)poll->windows * nk;
     HIP_TRY(ctx, hipMemcpy(sw.data(), ctx->sweep.p, sizeof(SweepState) * np, hipMemcpyDeviceToHost));
     for (int p = 0; p < np; ++p) fill_stats_sweep(h_stats[p], call.pts[p], sw[p]);
     // later work on the caller's stream sees the sweep's outputs
@@ -1000,11 +1064,11 @@ tkdv_status tkdv_create(int hip_device, tkdv_ctx **out)
     ctx->n_cu = prop.multiProcessorCount;
     ctx->arch = prop.gcnArchName;
     for (auto &row : ctx->lcfg)
-        for (auto &c : row) c = tkdv_launch_cfg{0, 1, 1ull << 26};
+        for (auto &c : row) c = tkdv_launch_cfg{0, 1, 1ull << 26, 0, 1};
     e = hipStreamCreateWithFlags(&ctx->sweep_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join[0], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join[1], hipEventDisableTiming);
-    if (e == hipSuccess) e = hipHostMalloc(&ctx->h_poll, 64, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(&ctx->h_poll, 256, hipHostMallocDefault);
     if (e != hipSuccess) {
         tkdv_destroy(ctx);
         return set_err(nullptr, TKDV_E_DEVICE, hipGetErrorString(e));
@@ -1152,6 +1216,8 @@ tkdv_status tkdv_destroy(tkdv_ctx *ctx)
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (ctx->phi_mat128.p) (void)hipFree(ctx->phi_mat128.p);
+    for (DevBuf *b : {&ctx->q64_hi, &ctx->q64_lo, &ctx->q64_f32})
+        if (b->p) (void)hipFree(b->p);
     for (int i = 0; i < kNumK; ++i) {
         if (ctx->phi_hi[i].p) (void)hipFree(ctx->phi_hi[i].p);
         if (ctx->phi_lo[i].p) (void)hipFree(ctx->phi_lo[i].p);
@@ -1966,8 +2032,10 @@ tkdv_status tkdv_set_launch_cfg(tkdv_ctx *ctx, int32_t K, tkdv_precision precisi
     if (kindex(K) < 0 || precision < TKDV_FP32 || precision > TKDV_BF16X3)
         return set_err(ctx, TKDV_E_ARG, "bad K or precision");
     if (precision == TKDV_BF16) return set_err(ctx, TKDV_E_UNSUPPORTED, kBf16Refused);
-    if (cfg->window < 65536 || cfg->window % 65536 != 0 || cfg->window > (1ull << 34) || cfg->blocks_per_cu < 0)
-        return set_err(ctx, TKDV_E_ARG, "window must be a multiple of 65536 in [65536, 2^34]");
+    if (cfg->window < 65536 || cfg->window % 65536 != 0 || cfg->window > (1ull << 34) || cfg->blocks_per_cu < 0 ||
+        cfg->variant < 0 || cfg->variant >= TKDV_DECIDE_VARIANTS || (cfg->adaptive != 0 && cfg->adaptive != 1))
+        return set_err(ctx, TKDV_E_ARG,
+                       "window must be a multiple of 65536 in [65536, 2^34], variant in [0, 4), adaptive 0 or 1");
     ctx->lcfg[kindex(K)][precision] = *cfg;
     return TKDV_OK;
 }
@@ -1997,12 +2065,13 @@ tkdv_status tkdv_autotune(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, co
             while (std::fgets(line, sizeof(line), f)) {
                 const size_t kl = std::strlen(key);
                 if (std::strncmp(line, key, kl) != 0 || line[kl] != ' ') continue;
-                int bpc = 0, graph = 1;
+                int bpc = 0, graph = 1, var = 0, adap = 1;
                 unsigned long long win = 0;
-                if (std::sscanf(line + kl, " bpc=%d window=%llu graph=%d", &bpc, &win, &graph) == 3 &&
-                    win >= 65536 && win % 65536 == 0 && bpc >= 0) {
+                if (std::sscanf(line + kl, " bpc=%d window=%llu graph=%d variant=%d adaptive=%d", &bpc, &win, &graph,
+                                &var, &adap) == 5 &&
+                    win >= 65536 && win % 65536 == 0 && bpc >= 0 && var >= 0 && var < TKDV_DECIDE_VARIANTS) {
                     std::fclose(f);
-                    tkdv_launch_cfg c{bpc, graph, win};
+                    tkdv_launch_cfg c{bpc, graph, win, var, adap};
                     ctx->lcfg[kindex(K)][precision] = c;
                     if (out) *out = c;
                     return TKDV_OK;
@@ -2012,7 +2081,7 @@ tkdv_status tkdv_autotune(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, co
         }
     }
     // probe: 16 points of this K, beta' in [20, 60], beta'C3/C2 = 6000 (K/32)^2,
-    // a fixed number of proposals each (the targets are never met)
+    // a fixed number of proposals each (the targets are never met), fixed windows
     const int np = 16;
     const uint64_t per_point = K >= 64 ? (1ull << 26) : (1ull << 27);
     std::vector<tkdv_point> pts(np);
@@ -2025,28 +2094,33 @@ tkdv_status tkdv_autotune(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, co
         if (s != TKDV_OK) return set_err(ctx, s, "autotune planning failed");
     }
     std::vector<tkdv_stats> st(np);
-    const int max_bpc = decide_max_blocks_per_cu(K, precision);
-    tkdv_launch_cfg best{0, 1, 1ull << 26};
+    tkdv_launch_cfg best{0, 1, 1ull << 26, 0, 1};
     double best_rate = -1.0;
     const uint64_t windows[3] = {1ull << 24, 1ull << 25, 1ull << 26};
-    for (int bpc = 1; bpc <= max_bpc; ++bpc)
-        for (uint64_t w : windows) {
-            tkdv_launch_cfg c{bpc, 1, w};
-            tkdv_status s = sweep(ctx, np, pts.data(), plans.data(), tgt.data(), maxp.data(), precision, &c, nullptr,
-                                  nullptr, cap.data(), off.data(), st.data(), nullptr);
-            if (s != TKDV_OK) return s;
-            const double rate = (double)per_point * np / (ctx->timing.total_ms * 1e-3);
-            if (rate > best_rate) {
-                best_rate = rate;
-                best = c;
+    const int n_var = (precision == TKDV_BF16X3 && (K == 16 || K == 32 || K == 64)) ? TKDV_DECIDE_VARIANTS : 1;
+    for (int var = 0; var < n_var; ++var) {
+        const int max_bpc = decide_variant_max_blocks_per_cu(K, precision, var);
+        for (int bpc = 1; bpc <= max_bpc; ++bpc)
+            for (uint64_t w : windows) {
+                tkdv_launch_cfg c{bpc, 1, w, var, 0};
+                tkdv_status s = sweep(ctx, np, pts.data(), plans.data(), tgt.data(), maxp.data(), precision, &c,
+                                      nullptr, nullptr, cap.data(), off.data(), st.data(), nullptr);
+                if (s != TKDV_OK) return s;
+                const double rate = (double)per_point * np / (ctx->timing.total_ms * 1e-3);
+                if (rate > best_rate) {
+                    best_rate = rate;
+                    best = c;
+                }
             }
-        }
+    }
+    best.adaptive = 1;  // the probe runs fixed windows; sweeps size later windows adaptively
     ctx->lcfg[kindex(K)][precision] = best;
     if (out) *out = best;
     if (cache_path) {
         if (FILE *f = std::fopen(cache_path, "a")) {
-            std::fprintf(f, "%s bpc=%d window=%llu graph=%d rate=%.6e\n", key, best.blocks_per_cu,
-                         (unsigned long long)best.window, best.use_graph, best_rate);
+            std::fprintf(f, "%s bpc=%d window=%llu graph=%d variant=%d adaptive=%d rate=%.6e\n", key,
+                         best.blocks_per_cu, (unsigned long long)best.window, best.use_graph, best.variant,
+                         best.adaptive, best_rate);
             std::fclose(f);
         }
     }

@@ -11,13 +11,16 @@ namespace tkdv {
 constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kTile = 32;          // proposals per wave tile (two lanes per proposal)
 constexpr int kBlock = 256;        // threads per workgroup of the sampling kernels
-// Workgroup of the decision kernel k_decide: at K = 64 one copy of its
-// synthesis tables (64 KB of LDS with BF16x3) serves 12 waves, 3 per SIMD
-// (168 registers a lane; measured faster than 4 waves per SIMD, whose
-// 128-register limit spills inside the tile loop, and than 2 workgroups of
-// 4 waves).
-// At K = 128 (its own kernel, tkdv_k128.hip) 16 waves share the 128 KB of tables.
-constexpr int decide_block(int K) { return K == 128 ? 1024 : (K == 64 ? 768 : kBlock); }
+// Workgroup of the default decision kernel of each K: at K <= 32 the
+// half-period k_decide; at K = 64 and K = 128 the quarter-period kernel
+// (tkdv_quarter.hip): workgroups of 256 threads at K = 64 (32 KB of tables
+// with BF16x3, several workgroups per CU), of 768 at K = 128 (128 KB of
+// tables, one workgroup of 12 waves per CU).
+constexpr int decide_block(int K) { return K == 128 ? 768 : kBlock; }
+// The half-period k_decide at K = 64 (a tile variant of the sweep's tuner):
+// one copy of its 64 KB of tables served 12 waves, 3 per SIMD (168 registers a
+// lane; four waves spill inside the tile loop).
+constexpr int kHalfPeriod64Block = 768;
 constexpr int kSynthBlock = 512;   // threads per workgroup of the standalone synthesis kernel
 constexpr int kClaimTiles = 64;    // tiles claimed per work-queue claim (2048 proposals);
                                    // lane c keeps the accept word of tile c
@@ -133,7 +136,7 @@ struct PointResult {
 // proposals; the device advances it after every window).
 struct SweepState {
     uint64_t i_start, i_end;      // proposal indices [i_start, i_end) of the point
-    uint64_t window;              // proposals per window
+    uint64_t window;              // proposals of the first window (of every window when not adaptive)
     uint64_t target;              // accepted samples wanted
     uint64_t capacity, out_off;   // output rows of the point
     uint64_t accepted;            // accepted samples so far (at most target)
@@ -142,6 +145,18 @@ struct SweepState {
     uint64_t n_fixups, n_violations;
     uint32_t done, max_log_a_key;
     PointResult total;            // statistics of the accepted samples so far
+};
+
+// Shared state of a sweep on the device.
+struct SweepGlobal {
+    unsigned long long pool_tiles;   // accept-bitmap words available to one window
+    unsigned long long total_segs;   // statistics segments of the current window
+    unsigned long long active;       // points not done
+    unsigned long long windows;      // windows run with at least one point active
+    unsigned long long overflow;     // a window's FP64 re-decision list overflowed
+    unsigned long long defer_cap;
+    int adaptive;                    // 1: size each window from the measured acceptance
+    int pad;
 };
 
 struct KernelArgs {
@@ -159,6 +174,9 @@ struct KernelArgs {
     const char *mix_tab;   // mixture tables (learned proposal only)
     // optional per-proposal outputs of the evaluation entry point (point 0 only)
     float *dbg_xhat, *dbg_t, *dbg_s3, *dbg_log_a, *dbg_log_u;
+    // sweeps: the current window's segment count on the device (the windows
+    // change size there); NULL elsewhere (the launch's own count is used)
+    const unsigned long long *d_total_segs;
 };
 
 }  // namespace tkdv

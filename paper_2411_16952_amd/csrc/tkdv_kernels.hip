@@ -104,10 +104,13 @@ __host__ __device__ constexpr int decide_lds_bytes()
 // ---------------------------------------------------------------------------
 // k_decide
 // ---------------------------------------------------------------------------
-template <int K, int PREC, int PROP>
-__global__ void __launch_bounds__(decide_block(K)) k_decide(KernelArgs a, const int *plist, int n_plist)
+// B threads per workgroup sharing one copy of the tables; G tile pairs of the
+// half-period synthesis with their accumulators live together (a tile variant
+// the sweep's autotuner chooses among; G divides the K/16 tile pairs).
+template <int K, int PREC, int PROP, int B = decide_block(K), int G = 1>
+__global__ void __launch_bounds__(B) k_decide(KernelArgs a, const int *plist, int n_plist)
 {
-    constexpr int B = decide_block(K);
+    static_assert(K < 16 || (K / 16) % G == 0, "G must divide the tile pairs");
     extern __shared__ __attribute__((aligned(16))) char lds[];
     constexpr int tab = decide_tab_bytes<K, PREC>();
     if constexpr (!decide_half_period<K>()) {
@@ -159,7 +162,7 @@ __global__ void __launch_bounds__(decide_block(K)) k_decide(KernelArgs a, const 
                 for (int j = 0; j < K; ++j) a.dbg_xhat[local * (2 * K) + half * K + j] = x[j] * inv;
             }
             float s3l;
-            if constexpr (decide_half_period<K>()) s3l = eo_cube_sum<K, PREC, 1>(x, lds_hi, lds_lo, lane);
+            if constexpr (decide_half_period<K>()) s3l = eo_cube_sum<K, PREC, G>(x, lds_hi, lds_lo, lane);
             else s3l = synth_cube_sum<K, PREC>(x, lds_hi, lds_lo, lane);
             const float s3 = (s3l + xor32(s3l)) * (inv * inv * inv);
             const float la = log_a_f32<PROP>(P, t, s3);
@@ -668,6 +671,7 @@ __global__ void __launch_bounds__(kBlock) k_seg_count(KernelArgs a, unsigned lon
                                                       unsigned long long *seg_cnt)
 {
     __shared__ unsigned long long red[kBlock / kWave];
+    if (a.d_total_segs) total_segs = *a.d_total_segs;
     for (unsigned long long gs = blockIdx.x; gs < total_segs; gs += gridDim.x) {
         const int p = point_of_segment(a.pts, a.n_points, gs);
         const DevPoint &P = a.pts[p];
@@ -763,6 +767,7 @@ __global__ void __launch_bounds__(kBlock) k_materialize(KernelArgs a, const int 
     }
     const int lane = threadIdx.x & 63, half = lane >> 5, pl = lane & 31, wv = threadIdx.x >> 6;
     uint16_t *mylist = lists + wv * (kGroupWords * 32);
+    if (a.d_total_segs) total_segs = *a.d_total_segs;
     __syncthreads();
     for (unsigned long long gs = blockIdx.x; gs < total_segs; gs += gridDim.x) {
         const int p = point_of_segment(a.pts, a.n_points, gs);
@@ -992,61 +997,117 @@ __global__ void __launch_bounds__(kBlock) k_finalize(KernelArgs a, const unsigne
 }
 
 // ---------------------------------------------------------------------------
-// k_window_advance: after one window of a sweep, per point (one thread):
-// fold the window's statistics into the running totals, count the accepted
-// samples (the window's target is what was still missing), and set up the
-// next window -- its first index, size, remaining target and capacity, and
-// output offset -- or mark the point done (target met or index range used
-// up; a done point gets no tiles).  *active counts the points not done.
+// k_window_advance: after one window of a sweep, one workgroup:
+//   per point: fold the window's statistics into the running totals, count
+//   the accepted samples (the window's target is what was still missing) and
+//   mark the point done when its target is met or its index range used up
+//   (a done point gets no tiles);
+//   then, in point order: the next window of every active point -- its first
+//   index, size, remaining target and capacity, output offset, and its place
+//   in the window's accept bitmap and segments.  Adaptive windows take the
+//   proposals the point still needs at its measured acceptance, times 1.25
+//   (four times the proposals so far while it has accepted none), shared out
+//   of the bitmap pool in proportion when they do not fit; otherwise every
+//   window has the first window's size.
 // ---------------------------------------------------------------------------
-__global__ void k_window_advance(DevPoint *pts, const DevCounters *cnt, const PointResult *res,
-                                 SweepState *sw, int n_points, unsigned long long *active)
+__global__ void __launch_bounds__(1024) k_window_advance(DevPoint *pts, const DevCounters *cnt,
+                                                         const PointResult *res, SweepState *sw, int n_points,
+                                                         SweepGlobal *G, const unsigned long long *defer_count)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n_points) return;
-    SweepState &S = sw[p];
-    DevPoint &P = pts[p];
-    if (S.done) return;
-    const PointResult &r = res[p];
-    const DevCounters &c = cnt[p];
-    S.total.S1 += r.S1;
-    S.total.S2 += r.S2;
-    S.total.S3 += r.S3;
-    S.total.S4 += r.S4;
-    S.total.n_exceed += r.n_exceed;
-    for (int b = 0; b < kNBins; ++b) S.total.hist[b] += r.hist[b];
-    S.accepted += r.n_samples;
-    S.written += r.n_written;
-    S.n_fixups += c.deferred;
-    S.n_violations += c.violations;
-    if (c.max_log_a_key > S.max_log_a_key) S.max_log_a_key = c.max_log_a_key;
-    if (S.accepted >= S.target) {
-        S.n_proposed = c.last_index - S.i_start + 1;
-        S.done = 1;
-    } else {
-        S.n_proposed += P.n;
-        if (P.i0 + P.n >= S.i_end) S.done = 1;
+    __shared__ double need[1024];
+    __shared__ int any_active;
+    if (threadIdx.x == 0) any_active = 0;
+    __syncthreads();
+    for (int p = threadIdx.x; p < n_points; p += blockDim.x) {
+        SweepState &S = sw[p];
+        DevPoint &P = pts[p];
+        if (S.done) continue;
+        any_active = 1;
+        const PointResult &r = res[p];
+        const DevCounters &c = cnt[p];
+        S.total.S1 += r.S1;
+        S.total.S2 += r.S2;
+        S.total.S3 += r.S3;
+        S.total.S4 += r.S4;
+        S.total.n_exceed += r.n_exceed;
+        for (int b = 0; b < kNBins; ++b) S.total.hist[b] += r.hist[b];
+        S.accepted += r.n_samples;
+        S.written += r.n_written;
+        S.n_fixups += c.deferred;
+        S.n_violations += c.violations;
+        if (c.max_log_a_key > S.max_log_a_key) S.max_log_a_key = c.max_log_a_key;
+        if (S.accepted >= S.target) {
+            S.n_proposed = c.last_index - S.i_start + 1;
+            S.done = 1;
+        } else {
+            S.n_proposed += P.n;
+            if (P.i0 + P.n >= S.i_end) S.done = 1;
+        }
     }
-    if (S.done) {
-        P.n = 0;
-        P.n_tiles = 0;
-        return;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    if (any_active) G->windows += 1;
+    if (*defer_count > G->defer_cap) G->overflow = 1;
+    // sizes of the next windows, in point order
+    double sum_need = 0.0;
+    for (int p = 0; p < n_points; ++p) {
+        const SweepState &S = sw[p];
+        const DevPoint &P = pts[p];
+        if (S.done) continue;
+        const double next_i0 = (double)(P.i0 + P.n), left = (double)S.i_end - next_i0;
+        double w = (double)S.window;
+        if (G->adaptive) {
+            const double used = (double)(P.i0 + P.n - S.i_start);
+            const double missing = (double)(S.target - S.accepted);
+            w = S.accepted > 0 ? 1.25 * missing * used / (double)S.accepted : 4.0 * used;
+            w = w < (double)S.window ? (double)S.window : w;
+        }
+        w = w > left ? left : w;
+        if (p < 1024) need[p] = w;
+        sum_need += w;
     }
-    P.i0 += P.n;
-    const unsigned long long left = S.i_end - P.i0;
-    P.n = left < S.window ? left : S.window;
-    P.n_tiles = (P.n + kTile - 1) / kTile;
-    P.target = S.target - S.accepted;
-    P.capacity = S.capacity > S.written ? S.capacity - S.written : 0;
-    P.out_off = S.out_off + S.written;
-    atomicAdd(active, 1ull);
+    const double pool = (double)G->pool_tiles * kTile;
+    const double scale = sum_need > pool ? pool / sum_need : 1.0;
+    unsigned long long bm = 0, segs = 0, active = 0;
+    for (int p = 0; p < n_points; ++p) {
+        SweepState &S = sw[p];
+        DevPoint &P = pts[p];
+        P.bm_off = bm;
+        P.seg_off = segs;
+        if (S.done) {
+            P.n = 0;
+            P.n_tiles = 0;
+            P.n_segs = 0;
+            continue;
+        }
+        P.i0 += P.n;
+        const unsigned long long left = S.i_end - P.i0;
+        unsigned long long w = S.window;
+        if (G->adaptive && p < 1024) {
+            // whole segments (65536 proposals), at least one, within the pool share
+            const double share = need[p] * scale;
+            const unsigned long long seg = (unsigned long long)kSegWords * kTile;
+            w = (unsigned long long)(share / (double)seg) * seg;
+            w = w < seg ? seg : w;
+        }
+        P.n = left < w ? left : w;
+        P.n_tiles = (P.n + kTile - 1) / kTile;
+        P.n_segs = (P.n_tiles + kSegWords - 1) / kSegWords;
+        P.target = S.target - S.accepted;
+        P.capacity = S.capacity > S.written ? S.capacity - S.written : 0;
+        P.out_off = S.out_off + S.written;
+        bm += P.n_tiles;
+        segs += P.n_segs;
+        ++active;
+    }
+    G->total_segs = segs;
+    G->active = active;
 }
 
 hipError_t launch_window_advance(DevPoint *pts, const DevCounters *cnt, const PointResult *res, SweepState *sw,
-                                 int n_points, unsigned long long *active, hipStream_t st)
+                                 int n_points, SweepGlobal *G, const unsigned long long *defer_count, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_window_advance, dim3((n_points + 63) / 64), dim3(64), 0, st, pts, cnt, res, sw, n_points,
-                       active);
+    hipLaunchKernelGGL(k_window_advance, dim3(1), dim3(1024), 0, st, pts, cnt, res, sw, n_points, G, defer_count);
     return hipGetLastError();
 }
 
@@ -1067,13 +1128,12 @@ __global__ void k_bits_to_bytes(const uint32_t *bitmap, unsigned long long n, ui
 // ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
-template <int K, int PREC, int PROP>
+template <int K, int PREC, int PROP, int B = decide_block(K), int G = 1>
 static hipError_t launch_decide_t(const KernelArgs &a, const int *plist, int n_plist, int n_cu,
                                   unsigned long long total_tiles, hipStream_t st, int *grid_out)
 {
     constexpr int lds = decide_lds_bytes<K, PREC>();
-    constexpr int B = decide_block(K);
-    auto kern = k_decide<K, PREC, PROP>;
+    auto kern = k_decide<K, PREC, PROP, B, G>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     int per_cu = 0;
@@ -1105,16 +1165,100 @@ static hipError_t launch_decide_k(int prec, int prop, const KernelArgs &a, const
     return hipErrorInvalidValue;
 }
 
-template <int K, int PREC, int PROP>
+template <int K, int PREC, int PROP, int B = decide_block(K), int G = 1>
 static int decide_blocks_per_cu_t()
 {
     constexpr int lds = decide_lds_bytes<K, PREC>();
-    auto kern = k_decide<K, PREC, PROP>;
+    auto kern = k_decide<K, PREC, PROP, B, G>;
     if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
         return 1;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, decide_block(K), lds) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, B, lds) != hipSuccess) return 1;
     return per_cu < 1 ? 1 : per_cu;
+}
+
+// Tile variants of the paper's-proposal decision kernel (BF16x3 products; the
+// sweep's autotuner times them).  Variant 0 is the default configuration;
+// variants 1..3 at K = 16, 32, 64 (workgroup threads, tile pairs per group):
+//   K = 16: (512, 1), (1024, 1), (768, 1)
+//   K = 32: (512, 1), (1024, 1), (256, 2)
+//   K = 64: variant 0 is the quarter-period kernel (16 proposals per wave,
+//           tkdv_quarter.hip, its own tables); 1..3 the half-period k_decide
+//           in (512, 1), (1024, 1), (768, 1)
+// K = 8 and K = 128, and FP32 products, have variant 0 only.
+template <int K>
+struct DecideVariant;
+template <>
+struct DecideVariant<16> {
+    static constexpr int B[4] = {decide_block(16), 512, 1024, 768}, G[4] = {1, 1, 1, 1};
+};
+template <>
+struct DecideVariant<32> {
+    static constexpr int B[4] = {decide_block(32), 512, 1024, 256}, G[4] = {1, 1, 1, 2};
+};
+template <>
+struct DecideVariant<64> {  // B[0]: the quarter-period kernel's workgroup
+    static constexpr int B[4] = {decide_block(64), 512, 1024, kHalfPeriod64Block}, G[4] = {1, 1, 1, 1};
+};
+
+template <int K, int V>
+static hipError_t launch_variant_t(const KernelArgs &a, const int *plist, int n_plist, int n_cu,
+                                   unsigned long long tiles, hipStream_t st, int *g)
+{
+    return launch_decide_t<K, PREC_BF16X3, PROP_SIGMA, DecideVariant<K>::B[V], DecideVariant<K>::G[V]>(
+        a, plist, n_plist, n_cu, tiles, st, g);
+}
+template <int K, int V>
+static int variant_blocks_per_cu_t()
+{
+    return decide_blocks_per_cu_t<K, PREC_BF16X3, PROP_SIGMA, DecideVariant<K>::B[V], DecideVariant<K>::G[V]>();
+}
+
+static bool has_variants(int K, int prec, int prop)
+{
+    return (K == 16 || K == 32 || K == 64) && prec == PREC_BF16X3 && prop == PROP_SIGMA;
+}
+
+int decide_variant_block(int K, int variant)
+{
+    if (variant <= 0 || variant >= TKDV_DECIDE_VARIANTS) return decide_block(K);
+    switch (K) {
+    case 16: return DecideVariant<16>::B[variant];
+    case 32: return DecideVariant<32>::B[variant];
+    case 64: return DecideVariant<64>::B[variant];
+    default: return decide_block(K);
+    }
+}
+
+hipError_t launch_decide_variant(int K, int prec, int prop, int variant, const KernelArgs &a, const int *plist,
+                                 int n_plist, int n_cu, unsigned long long tiles, hipStream_t st, int *grid_out)
+{
+    if (variant <= 0 || variant >= TKDV_DECIDE_VARIANTS || !has_variants(K, prec, prop))
+        return launch_decide(K, prec, prop, a, plist, n_plist, n_cu, tiles, st, grid_out);
+#define TKDV_DISPATCH_V(KK)                                                                          \
+    if (K == KK) {                                                                                  \
+        if (variant == 1) return launch_variant_t<KK, 1>(a, plist, n_plist, n_cu, tiles, st, grid_out); \
+        if (variant == 2) return launch_variant_t<KK, 2>(a, plist, n_plist, n_cu, tiles, st, grid_out); \
+        return launch_variant_t<KK, 3>(a, plist, n_plist, n_cu, tiles, st, grid_out);               \
+    }
+    TKDV_DISPATCH_V(16) TKDV_DISPATCH_V(32) TKDV_DISPATCH_V(64)
+#undef TKDV_DISPATCH_V
+    return hipErrorInvalidValue;
+}
+
+int decide_variant_max_blocks_per_cu(int K, int prec, int variant)
+{
+    if (variant <= 0 || variant >= TKDV_DECIDE_VARIANTS || !has_variants(K, prec, PROP_SIGMA))
+        return decide_max_blocks_per_cu(K, prec);
+#define TKDV_DISPATCH_W(KK)                                             \
+    if (K == KK) {                                                     \
+        if (variant == 1) return variant_blocks_per_cu_t<KK, 1>();      \
+        if (variant == 2) return variant_blocks_per_cu_t<KK, 2>();      \
+        return variant_blocks_per_cu_t<KK, 3>();                        \
+    }
+    TKDV_DISPATCH_W(16) TKDV_DISPATCH_W(32) TKDV_DISPATCH_W(64)
+#undef TKDV_DISPATCH_W
+    return 1;
 }
 
 int decide_max_blocks_per_cu(int K, int prec)
@@ -1124,8 +1268,8 @@ int decide_max_blocks_per_cu(int K, int prec)
     TKDV_DISPATCH_O(8, PREC_FP32) TKDV_DISPATCH_O(8, PREC_BF16X3)
     TKDV_DISPATCH_O(16, PREC_FP32) TKDV_DISPATCH_O(16, PREC_BF16X3)
     TKDV_DISPATCH_O(32, PREC_FP32) TKDV_DISPATCH_O(32, PREC_BF16X3)
-    TKDV_DISPATCH_O(64, PREC_FP32) TKDV_DISPATCH_O(64, PREC_BF16X3)
 #undef TKDV_DISPATCH_O
+    if (K == 64) return decide_quarter64_max_blocks_per_cu(prec);
     if (K == 128) return decide128_max_blocks_per_cu(prec);
     return 1;
 }
@@ -1137,7 +1281,7 @@ hipError_t launch_decide(int K, int prec, int prop, const KernelArgs &a, const i
     case 8: return launch_decide_k<8>(prec, prop, a, plist, n_plist, n_cu, tiles, st, grid_out);
     case 16: return launch_decide_k<16>(prec, prop, a, plist, n_plist, n_cu, tiles, st, grid_out);
     case 32: return launch_decide_k<32>(prec, prop, a, plist, n_plist, n_cu, tiles, st, grid_out);
-    case 64: return launch_decide_k<64>(prec, prop, a, plist, n_plist, n_cu, tiles, st, grid_out);
+    case 64: return launch_decide_quarter64(prec, prop, a, plist, n_plist, n_cu, tiles, st, grid_out);
     case 128: return launch_decide128(prec, prop, a, plist, n_plist, n_cu, tiles, st, grid_out);
     default: return hipErrorInvalidValue;
     }

@@ -1,9 +1,11 @@
-// K = 128 kernels of the TKdV rejection sampler (N = 512 grid values).
+// Quarter-period kernels of the TKdV rejection sampler: the decision kernel
+// at K = 128 (N = 512) and, as a tile variant, at K = 64; the ordered output
+// with statistics at K = 128.
 //
 // Layout.  One wavefront evaluates a tile of 16 proposals; proposal p of the
 // tile lives in lanes p + 16 g, g = 0..3, and lane group g holds the cos and
-// sin coordinates of modes 32 g + 1 .. 32 g + 32 (c[j] = x_{32g+j+1},
-// s[j] = x_{K+32g+j+1}).  That is the operand layout of the 16x16x32 BF16
+// sin coordinates of the K/4 modes K g/4 + 1 .. K g/4 + K/4 (c[j] =
+// x_{Kg/4+j+1}, s[j] = x_{K+Kg/4+j+1}).  That is the operand layout of the 16x16x32 BF16
 // (and 16x16x4 FP32) matrix instructions with the proposals as the B
 // (column) operand: lane l supplies k-rows 8 (l/16) .. 8 (l/16) + 7 of column
 // l % 16, and receives rows 4 (l/16) .. 4 (l/16) + 3 of the result.
@@ -19,7 +21,8 @@
 // The tables carry the Co, Se, So rows times sqrt(3) (co = sqrt 3 Co, ...):
 // 4 Ce (Ce^2 + co^2 + se^2 + so^2) + (8/sqrt 3) co se so.  Each of the four
 // syntheses contracts K/2 coordinates: a quarter of the plain product's matrix
-// work, and tables of N/4 x 2K entries (64 KB per BF16 table) that fit in LDS.
+// work, and tables of N/4 x 2K entries (64 KB per BF16 table at K = 128) that
+// fit in LDS.
 #include <hip/hip_runtime.h>
 
 #include "tkdv_device.h"
@@ -33,16 +36,25 @@ namespace {
 
 constexpr int K128 = 128;
 constexpr int kTile16 = 16;            // proposals per wave tile
-constexpr int kReps = 4 * K128 / 4;    // representatives of the quarter grid (N/4)
-constexpr int kRepTiles = kReps / 16;  // 8 tiles of 16 representatives
-constexpr int kBlock128 = 768;         // 12 waves: 3 per SIMD share one copy of the tables
 
-// bytes of one quarter table: BF16 [tile][out][step][64 lanes][8], FP32
-// [tile][out][step/4][64 lanes][4]
-constexpr int kQBf16Bytes = kRepTiles * 4 * 2 * 64 * 16;   // 64 KB
-constexpr int kQF32Bytes = kRepTiles * 4 * 16 * 64 * 4;    // 128 KB
-
-__host__ __device__ constexpr int decide128_lds(int prec) { return prec == PREC_FP32 ? kQF32Bytes : 2 * kQBf16Bytes; }
+// Sizes of the quarter-period form at K (64 or 128): CPL coordinates of each
+// block per lane, K/16 tiles of 16 representatives (N/4 = K of them), K/64
+// BF16 k-steps and K/32 groups of four FP32 k-steps per synthesis.
+template <int K>
+struct Quarter {
+    static constexpr int CPL = K / 4;
+    static constexpr int NB = CPL / 4;        // Philox blocks of one block's coordinates per lane
+    static constexpr int TILES = K / 16;
+    static constexpr int STEPS = K / 64;      // BF16 k-steps (32 k-rows, 8 per lane group)
+    static constexpr int QG = K / 32;         // FP32 k-steps in groups of 4
+    // bytes of one table: BF16 [tile][out][step][64 lanes][8], FP32 [tile][out][group][64 lanes][4]
+    static constexpr int BF16_BYTES = TILES * 4 * STEPS * 64 * 16;
+    static constexpr int F32_BYTES = TILES * 4 * QG * 64 * 16;
+    // workgroup: at K = 128 the 128 KB of tables leave one workgroup per CU, 12
+    // waves (3 per SIMD) share them; at K = 64 (32 KB) workgroups of 256
+    static constexpr int BLOCK = K == 128 ? 768 : 256;
+    static constexpr int lds(int prec) { return prec == PREC_FP32 ? F32_BYTES : 2 * BF16_BYTES; }
+};
 
 __device__ __forceinline__ unsigned long long wave_sum_u64_128(unsigned long long v)
 {
@@ -97,20 +109,21 @@ __device__ __forceinline__ void add0(unsigned long long *ctr, unsigned long long
 // pairs; X = Sigma^{1/2} z for the paper's proposal), and their contributions
 // to |X|^2, sum (j+1) X^2 and sum (j+1)^2 X^2 (t = sum k^2 X_k^2 over both
 // blocks, k = 32 g + j + 1).
-template <int PROP>
+template <int K, int PROP>
 __device__ __forceinline__ void gen_block128(const DevPoint &P, uint32_t c0, uint32_t c1, int g, int b,
-                                             float (&v)[32], float &r2, float &a1, float &a2)
+                                             float (&v)[K / 4], float &r2, float &a1, float &a2)
 {
+    constexpr int NB = Quarter<K>::NB;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const uint4 w = philox4x32_10(c0, c1, P.point_id, (uint32_t)(b * (K128 / 4) + 8 * g + q), P.key0, P.key1);
+    for (int q = 0; q < NB; ++q) {
+        const uint4 w = philox4x32_10(c0, c1, P.point_id, (uint32_t)(b * (K / 4) + NB * g + q), P.key0, P.key1);
         box_muller_f32(w.x, w.y, v[4 * q + 0], v[4 * q + 1]);
         box_muller_f32(w.z, w.w, v[4 * q + 2], v[4 * q + 3]);
     }
     if (PROP == PROP_SIGMA) {
-        const float4 *sg = reinterpret_cast<const float4 *>(P.sig + 32 * g);
+        const float4 *sg = reinterpret_cast<const float4 *>(P.sig + (K / 4) * g);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < NB; ++q) {
             const float4 sv = sg[q];
             v[4 * q + 0] *= sv.x;
             v[4 * q + 1] *= sv.y;
@@ -119,7 +132,7 @@ __device__ __forceinline__ void gen_block128(const DevPoint &P, uint32_t c0, uin
         }
     }
 #pragma unroll
-    for (int j = 0; j < 32; ++j) {
+    for (int j = 0; j < K / 4; ++j) {
         const float q = v[j] * v[j];
         r2 += q;
         a1 = __builtin_fmaf((float)(j + 1), q, a1);
@@ -129,9 +142,10 @@ __device__ __forceinline__ void gen_block128(const DevPoint &P, uint32_t c0, uin
 
 // |X|^-1 and t of the projected point from the lane's partial sums (the four
 // lanes of a proposal end with bitwise identical values).
+template <int K>
 __device__ __forceinline__ float finish_norm128(int g, float r2, float a1, float a2, float &t)
 {
-    const float b = (float)(32 * g);
+    const float b = (float)((K / 4) * g);
     float tk = __builtin_fmaf(b * b, r2, __builtin_fmaf(2.0f * b, a1, a2));
     r2 = sum4(r2);
     tk = sum4(tk);
@@ -146,19 +160,19 @@ __device__ __forceinline__ float finish_norm128(int g, float r2, float a1, float
 // projected point and the acceptance word (word 2K).  With NORMALIZE the
 // coordinates are projected onto the sphere.  The four lanes of a proposal
 // hold bitwise identical |X|^2 and t.
-template <int PROP, bool NORMALIZE>
-__device__ __forceinline__ float gen_x128(const DevPoint &P, uint64_t i, int g, float (&c)[32], float (&s)[32],
-                                          float &t, uint32_t &w_acc)
+template <int K, int PROP, bool NORMALIZE>
+__device__ __forceinline__ float gen_x128(const DevPoint &P, uint64_t i, int g, float (&c)[K / 4],
+                                          float (&s)[K / 4], float &t, uint32_t &w_acc)
 {
     const uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32);
     float r2 = 0.0f, a1 = 0.0f, a2 = 0.0f;
-    gen_block128<PROP>(P, c0, c1, g, 0, c, r2, a1, a2);
-    gen_block128<PROP>(P, c0, c1, g, 1, s, r2, a1, a2);
-    w_acc = philox4x32_10(c0, c1, P.point_id, (uint32_t)(K128 / 2), P.key0, P.key1).x;
-    const float inv = finish_norm128(g, r2, a1, a2, t);
+    gen_block128<K, PROP>(P, c0, c1, g, 0, c, r2, a1, a2);
+    gen_block128<K, PROP>(P, c0, c1, g, 1, s, r2, a1, a2);
+    w_acc = philox4x32_10(c0, c1, P.point_id, (uint32_t)(K / 2), P.key0, P.key1).x;
+    const float inv = finish_norm128<K>(g, r2, a1, a2, t);
     if (NORMALIZE) {
 #pragma unroll
-        for (int j = 0; j < 32; ++j) {
+        for (int j = 0; j < K / 4; ++j) {
             c[j] *= inv;
             s[j] *= inv;
         }
@@ -181,9 +195,9 @@ __device__ __forceinline__ void quarter_cubes(const f32x4 &ce, const f32x4 &co, 
 }
 
 // BF16 operands of one contraction (out o: 0 Ce, 1 Co, 2 Se, 3 So), k-step r:
-// entry e = the coordinate of mode 32 g + 2 (8 r + e) + 2 (even) or + 1 (odd).
-template <bool LO>
-__device__ __forceinline__ void quarter_operand(const float (&v)[32], int odd, int r, bf16x8 &hi, bf16x8 &lo)
+// entry e = the coordinate of mode K g/4 + 2 (8 r + e) + 2 (even) or + 1 (odd).
+template <int N, bool LO>
+__device__ __forceinline__ void quarter_operand(const float (&v)[N], int odd, int r, bf16x8 &hi, bf16x8 &lo)
 {
     u32x4_t wh, wl = {0u, 0u, 0u, 0u};
 #pragma unroll
@@ -198,21 +212,23 @@ __device__ __forceinline__ void quarter_operand(const float (&v)[32], int odd, i
 
 // S3 = sum over the N = 512 offset-grid values of u~^3 for this lane's share
 // (the caller sums the four lanes), from unprojected coordinates, FP32 products.
-__device__ __forceinline__ float cube_sum_q128_f32(const float (&c)[32], const float (&s)[32], const char *lds_hi,
-                                                   int lane)
+template <int K>
+__device__ __forceinline__ float cube_sum_q128_f32(const float (&c)[K / 4], const float (&s)[K / 4],
+                                                   const char *lds_hi, int lane)
 {
+    constexpr int QG = Quarter<K>::QG;
     float s1 = 0.0f, s2 = 0.0f;
     {
         // k-step sg of out o: coordinate 2 sg + 1 (even mode) or 2 sg (odd mode) of the block
         const float4 *tab = reinterpret_cast<const float4 *>(lds_hi);
 #pragma unroll 1
-        for (int tau = 0; tau < kRepTiles; ++tau) {
+        for (int tau = 0; tau < Quarter<K>::TILES; ++tau) {
             f32x4 acc[4] = {f32x4{}, f32x4{}, f32x4{}, f32x4{}};
 #pragma unroll
-            for (int q4 = 0; q4 < 4; ++q4)
+            for (int q4 = 0; q4 < QG; ++q4)
 #pragma unroll
                 for (int o = 0; o < 4; ++o) {
-                    const float4 a = tab[((tau * 4 + o) * 4 + q4) * 64 + lane];
+                    const float4 a = tab[((tau * 4 + o) * QG + q4) * 64 + lane];
                     const float *v = (o < 2) ? c : s;
                     const int par = (o == 0 || o == 2) ? 1 : 0;
                     acc[o] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, v[2 * (4 * q4 + 0) + par], acc[o], 0, 0, 0);
@@ -228,22 +244,23 @@ __device__ __forceinline__ float cube_sum_q128_f32(const float (&c)[32], const f
 
 // The same from BF16 operands [out][step] (hi, and lo for BF16x3) with FP32
 // accumulation.
-template <int PREC>
-__device__ __forceinline__ float cube_sum_q128_bf16(const bf16x8 (&bh)[4][2], const bf16x8 (&bl)[4][2],
+template <int K, int PREC>
+__device__ __forceinline__ float cube_sum_q128_bf16(const bf16x8 (&bh)[4][K / 64], const bf16x8 (&bl)[4][K / 64],
                                                     const char *lds_hi, const char *lds_lo, int lane)
 {
+    constexpr int R = Quarter<K>::STEPS;
     float s1 = 0.0f, s2 = 0.0f;
     {
         const bf16x8 *th = reinterpret_cast<const bf16x8 *>(lds_hi);
         const bf16x8 *tl = reinterpret_cast<const bf16x8 *>(lds_lo);
 #pragma unroll 1
-        for (int tau = 0; tau < kRepTiles; ++tau) {
+        for (int tau = 0; tau < Quarter<K>::TILES; ++tau) {
             f32x4 acc[4] = {f32x4{}, f32x4{}, f32x4{}, f32x4{}};
 #pragma unroll
-            for (int r = 0; r < 2; ++r)
+            for (int r = 0; r < R; ++r)
 #pragma unroll
                 for (int o = 0; o < 4; ++o) {
-                    const int idx = ((tau * 4 + o) * 2 + r) * 64 + lane;
+                    const int idx = ((tau * 4 + o) * R + r) * 64 + lane;
                     const bf16x8 ah = th[idx];
                     if constexpr (PREC == PREC_BF16X3) {
                         const bf16x8 al = tl[idx];
@@ -264,26 +281,25 @@ __device__ __forceinline__ float cube_sum_q128_bf16(const bf16x8 (&bh)[4][2], co
 // ---------------------------------------------------------------------------
 // DBG: the verification entry's instantiation (per-proposal outputs written);
 // the sampling calls run the one without, which needs fewer registers.
-template <int PREC, int PROP, bool DBG>
-__global__ void __launch_bounds__(kBlock128) k_decide128(KernelArgs a, const int *plist, int n_plist)
+template <int K, int PREC, int PROP, bool DBG>
+__global__ void __launch_bounds__(Quarter<K>::BLOCK) k_decide128(KernelArgs a, const int *plist, int n_plist)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
-    constexpr int bytes = decide128_lds(PREC);
+    constexpr int B = Quarter<K>::BLOCK, CPL = K / 4;
     {
         const uint4 *s0 = reinterpret_cast<const uint4 *>(a.phi_hi);
         const uint4 *s1 = reinterpret_cast<const uint4 *>(a.phi_lo);
         uint4 *d = reinterpret_cast<uint4 *>(lds);
-        constexpr int one = PREC == PREC_FP32 ? kQF32Bytes / 16 : kQBf16Bytes / 16;
-        for (int v = threadIdx.x; v < one; v += kBlock128) d[v] = s0[v];
+        constexpr int one = (PREC == PREC_FP32 ? Quarter<K>::F32_BYTES : Quarter<K>::BF16_BYTES) / 16;
+        for (int v = threadIdx.x; v < one; v += B) d[v] = s0[v];
         if constexpr (PREC == PREC_BF16X3)
-            for (int v = threadIdx.x; v < one; v += kBlock128) d[one + v] = s1[v];
+            for (int v = threadIdx.x; v < one; v += B) d[one + v] = s1[v];
     }
     __syncthreads();
     const char *lds_hi = lds;
-    const char *lds_lo = lds + (PREC == PREC_FP32 ? 0 : kQBf16Bytes);
-    (void)bytes;
+    const char *lds_lo = lds + (PREC == PREC_FP32 ? 0 : Quarter<K>::BF16_BYTES);
     const int lane = threadIdx.x & 63, g = lane >> 4, pl = lane & 15;
-    const int gwave = blockIdx.x * (kBlock128 / kWave) + (threadIdx.x >> 6);
+    const int gwave = blockIdx.x * (B / kWave) + (threadIdx.x >> 6);
     int cursor = gwave % n_plist;
     int misses = 0;
     while (misses < n_plist) {
@@ -308,46 +324,47 @@ __global__ void __launch_bounds__(kBlock128) k_decide128(KernelArgs a, const int
             const bool valid = local < P.n;
             const uint64_t i = P.i0 + local;
             if (DBG && a.dbg_xhat) {  // verification: the projected point, generated once more
-                float c[32], s[32], tt;
+                float c[CPL], s[CPL], tt;
                 uint32_t ww;
-                gen_x128<PROP, true>(P, i, g, c, s, tt, ww);
+                gen_x128<K, PROP, true>(P, i, g, c, s, tt, ww);
                 if (valid) {
-                    float *row = a.dbg_xhat + local * (2 * K128);
+                    float *row = a.dbg_xhat + local * (2 * K);
 #pragma unroll
-                    for (int j = 0; j < 32; ++j) {
-                        row[32 * g + j] = c[j];
-                        row[K128 + 32 * g + j] = s[j];
+                    for (int j = 0; j < CPL; ++j) {
+                        row[CPL * g + j] = c[j];
+                        row[K + CPL * g + j] = s[j];
                     }
                 }
             }
             const uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32);
             float r2 = 0.0f, a1 = 0.0f, a2 = 0.0f, s3l;
             if constexpr (PREC == PREC_FP32) {
-                float c[32], s[32];
-                gen_block128<PROP>(P, c0, c1, g, 0, c, r2, a1, a2);
-                gen_block128<PROP>(P, c0, c1, g, 1, s, r2, a1, a2);
-                s3l = cube_sum_q128_f32(c, s, lds_hi, lane);
+                float c[CPL], s[CPL];
+                gen_block128<K, PROP>(P, c0, c1, g, 0, c, r2, a1, a2);
+                gen_block128<K, PROP>(P, c0, c1, g, 1, s, r2, a1, a2);
+                s3l = cube_sum_q128_f32<K>(c, s, lds_hi, lane);
             } else {
                 // one block at a time: its coordinates die once split into operands
-                bf16x8 bh[4][2], bl[4][2];
+                constexpr int R = Quarter<K>::STEPS;
+                bf16x8 bh[4][R], bl[4][R];
 #pragma unroll
                 for (int blk = 0; blk < 2; ++blk) {
-                    float v[32];
-                    gen_block128<PROP>(P, c0, c1, g, blk, v, r2, a1, a2);
+                    float v[CPL];
+                    gen_block128<K, PROP>(P, c0, c1, g, blk, v, r2, a1, a2);
 #pragma unroll
                     for (int odd = 0; odd < 2; ++odd)
 #pragma unroll
-                        for (int r = 0; r < 2; ++r)
-                            quarter_operand<PREC == PREC_BF16X3>(v, odd, r, bh[2 * blk + odd][r],
-                                                                 bl[2 * blk + odd][r]);
+                        for (int r = 0; r < R; ++r)
+                            quarter_operand<CPL, PREC == PREC_BF16X3>(v, odd, r, bh[2 * blk + odd][r],
+                                                                      bl[2 * blk + odd][r]);
                     // keep the next block's generation after this split (register pressure)
                     __builtin_amdgcn_sched_barrier(0);
                 }
-                s3l = cube_sum_q128_bf16<PREC>(bh, bl, lds_hi, lds_lo, lane);
+                s3l = cube_sum_q128_bf16<K, PREC>(bh, bl, lds_hi, lds_lo, lane);
             }
-            const uint32_t w_acc = philox4x32_10(c0, c1, P.point_id, (uint32_t)(K128 / 2), P.key0, P.key1).x;
+            const uint32_t w_acc = philox4x32_10(c0, c1, P.point_id, (uint32_t)(K / 2), P.key0, P.key1).x;
             float t;
-            const float inv = finish_norm128(g, r2, a1, a2, t);
+            const float inv = finish_norm128<K>(g, r2, a1, a2, t);
             const float s3 = sum4(s3l) * (inv * inv * inv);
             const float la = log_a_f32<PROP>(P, t, s3);
             const float U = __builtin_fmaf((float)w_acc, 2.3283064365386963e-10f, 1.1641532182693481e-10f);
@@ -418,6 +435,7 @@ __global__ void __launch_bounds__(kBlock) k_materialize128(KernelArgs a, unsigne
     const float4 *ftab = reinterpret_cast<const float4 *>(a.phi_hi);
     const int lane = threadIdx.x & 63, g = lane >> 4, pl = lane & 15, wv = threadIdx.x >> 6;
     uint16_t *mylist = lists[wv];
+    if (a.d_total_segs) total_segs = *a.d_total_segs;
     for (unsigned long long gs = blockIdx.x; gs < total_segs; gs += gridDim.x) {
         int lo = 0, hi = a.n_points - 1;
         while (lo < hi) {  // last point whose first segment is <= gs
@@ -477,7 +495,7 @@ __global__ void __launch_bounds__(kBlock) k_materialize128(KernelArgs a, unsigne
                 float c[32], s[32];
                 float t;
                 uint32_t w_acc;
-                gen_x128<PROP, true>(P, i, g, c, s, t, w_acc);
+                gen_x128<K128, PROP, true>(P, i, g, c, s, t, w_acc);
                 if (valid && r < P.capacity) {
                     if (out_xhat) {
                         float *row = out_xhat + (P.out_off + r) * P.row_stride;
@@ -567,65 +585,90 @@ __global__ void __launch_bounds__(kBlock) k_materialize128(KernelArgs a, unsigne
     }
 }
 
-template <int PREC, int PROP>
+template <int K, int PREC, int PROP>
 hipError_t launch_decide128_t(const KernelArgs &a, const int *plist, int n_plist, int n_cu,
                               unsigned long long total_tiles, hipStream_t st, int *grid_out)
 {
-    constexpr int lds = decide128_lds(PREC);
+    constexpr int lds = Quarter<K>::lds(PREC), B = Quarter<K>::BLOCK;
     const bool dbg = a.dbg_xhat != nullptr || a.dbg_t != nullptr;
-    auto kern = dbg ? k_decide128<PREC, PROP, true> : k_decide128<PREC, PROP, false>;
+    auto kern = dbg ? k_decide128<K, PREC, PROP, true> : k_decide128<K, PREC, PROP, false>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock128, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, B, lds);
     if (e != hipSuccess) return e;
     if (a.blocks_per_cu > 0 && a.blocks_per_cu < per_cu) per_cu = a.blocks_per_cu;
     if (per_cu < 1) per_cu = 1;
-    const unsigned long long per_block = (unsigned long long)(kBlock128 / kWave) * kClaimTiles;
+    const unsigned long long per_block = (unsigned long long)(B / kWave) * kClaimTiles;
     unsigned long long want = (total_tiles + per_block - 1) / per_block;
     unsigned long long grid = (unsigned long long)per_cu * n_cu;
     if (want < grid) grid = want;
     if (grid < 1) grid = 1;
     if (grid_out) *grid_out = (int)grid;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kBlock128), lds, st, a, plist, n_plist);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(B), lds, st, a, plist, n_plist);
     return hipGetLastError();
 }
 
-template <int PREC, int PROP>
+template <int K, int PREC, int PROP>
 int blocks_per_cu128_t()
 {
-    constexpr int lds = decide128_lds(PREC);
-    auto kern = k_decide128<PREC, PROP, false>;
+    constexpr int lds = Quarter<K>::lds(PREC);
+    auto kern = k_decide128<K, PREC, PROP, false>;
     if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
         return 1;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock128, lds) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, Quarter<K>::BLOCK, lds) != hipSuccess) return 1;
     return per_cu < 1 ? 1 : per_cu;
+}
+
+template <int K>
+hipError_t launch_quarter_k(int prec, int prop, const KernelArgs &a, const int *plist, int n_plist, int n_cu,
+                            unsigned long long total_tiles, hipStream_t st, int *grid_out)
+{
+    if (prec == PREC_FP32 && prop == PROP_UNIFORM)
+        return launch_decide128_t<K, PREC_FP32, PROP_UNIFORM>(a, plist, n_plist, n_cu, total_tiles, st, grid_out);
+    if (prec == PREC_FP32 && prop == PROP_SIGMA)
+        return launch_decide128_t<K, PREC_FP32, PROP_SIGMA>(a, plist, n_plist, n_cu, total_tiles, st, grid_out);
+    if (prec == PREC_BF16X3 && prop == PROP_UNIFORM)
+        return launch_decide128_t<K, PREC_BF16X3, PROP_UNIFORM>(a, plist, n_plist, n_cu, total_tiles, st,
+                                                                grid_out);
+    if (prec == PREC_BF16X3 && prop == PROP_SIGMA)
+        return launch_decide128_t<K, PREC_BF16X3, PROP_SIGMA>(a, plist, n_plist, n_cu, total_tiles, st,
+                                                              grid_out);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-int decide128_block() { return kBlock128; }
-size_t quarter_table_bytes(int prec) { return prec == PREC_FP32 ? kQF32Bytes : kQBf16Bytes; }
+int decide128_block() { return Quarter<128>::BLOCK; }
+size_t quarter_table_bytes(int K, int prec)
+{
+    if (K == 64) return prec == PREC_FP32 ? Quarter<64>::F32_BYTES : Quarter<64>::BF16_BYTES;
+    return prec == PREC_FP32 ? Quarter<128>::F32_BYTES : Quarter<128>::BF16_BYTES;
+}
 
 hipError_t launch_decide128(int prec, int prop, const KernelArgs &a, const int *plist, int n_plist, int n_cu,
                             unsigned long long total_tiles, hipStream_t st, int *grid_out)
 {
-    if (prec == PREC_FP32 && prop == PROP_UNIFORM)
-        return launch_decide128_t<PREC_FP32, PROP_UNIFORM>(a, plist, n_plist, n_cu, total_tiles, st, grid_out);
-    if (prec == PREC_FP32 && prop == PROP_SIGMA)
-        return launch_decide128_t<PREC_FP32, PROP_SIGMA>(a, plist, n_plist, n_cu, total_tiles, st, grid_out);
-    if (prec == PREC_BF16X3 && prop == PROP_UNIFORM)
-        return launch_decide128_t<PREC_BF16X3, PROP_UNIFORM>(a, plist, n_plist, n_cu, total_tiles, st, grid_out);
-    if (prec == PREC_BF16X3 && prop == PROP_SIGMA)
-        return launch_decide128_t<PREC_BF16X3, PROP_SIGMA>(a, plist, n_plist, n_cu, total_tiles, st, grid_out);
-    return hipErrorInvalidValue;
+    return launch_quarter_k<128>(prec, prop, a, plist, n_plist, n_cu, total_tiles, st, grid_out);
+}
+
+hipError_t launch_decide_quarter64(int prec, int prop, const KernelArgs &a, const int *plist, int n_plist, int n_cu,
+                                   unsigned long long total_tiles, hipStream_t st, int *grid_out)
+{
+    return launch_quarter_k<64>(prec, prop, a, plist, n_plist, n_cu, total_tiles, st, grid_out);
 }
 
 int decide128_max_blocks_per_cu(int prec)
 {
-    return prec == PREC_FP32 ? blocks_per_cu128_t<PREC_FP32, PROP_SIGMA>()
-                             : blocks_per_cu128_t<PREC_BF16X3, PROP_SIGMA>();
+    return prec == PREC_FP32 ? blocks_per_cu128_t<128, PREC_FP32, PROP_SIGMA>()
+                             : blocks_per_cu128_t<128, PREC_BF16X3, PROP_SIGMA>();
+}
+
+int decide_quarter64_max_blocks_per_cu(int prec)
+{
+    return prec == PREC_FP32 ? blocks_per_cu128_t<64, PREC_FP32, PROP_SIGMA>()
+                             : blocks_per_cu128_t<64, PREC_BF16X3, PROP_SIGMA>();
 }
 
 hipError_t launch_materialize128(int prop, const KernelArgs &a, unsigned long long total_segs,

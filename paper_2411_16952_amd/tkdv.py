@@ -71,10 +71,15 @@ class Mixture(C.Structure):
 
 class LaunchCfg(C.Structure):
     """Launch configuration of the sweep (tkdv_launch_cfg)."""
-    _fields_ = [("blocks_per_cu", C.c_int32), ("use_graph", C.c_int32), ("window", C.c_uint64)]
+    _fields_ = [("blocks_per_cu", C.c_int32), ("use_graph", C.c_int32), ("window", C.c_uint64),
+                ("variant", C.c_int32), ("adaptive", C.c_int32)]
+
+    def __init__(self, blocks_per_cu: int = 0, use_graph: int = 1, window: int = 1 << 26, variant: int = 0,
+                 adaptive: int = 1):
+        super().__init__(int(blocks_per_cu), int(use_graph), int(window), int(variant), int(adaptive))
 
     def to_dict(self) -> dict:
-        return {"blocks_per_cu": self.blocks_per_cu, "use_graph": self.use_graph, "window": self.window}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class LearnerCfg(C.Structure):
@@ -89,7 +94,7 @@ class Timing(C.Structure):
                 ("materialize_ms", C.c_double), ("finalize_ms", C.c_double), ("synth_ms", C.c_double),
                 ("total_ms", C.c_double),
                 ("decide_launches", C.c_int32), ("decide_grid", C.c_int32), ("decide_block", C.c_int32),
-                ("windows", C.c_int32)]
+                ("windows", C.c_int32), ("graph_launches", C.c_int32)]
 
     def to_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -1,15 +1,19 @@
 """The batched sweep (tkdv_sample_sweep) and its autotuner on the GPU.
 
-* windows: a sweep over points of every K with windows much smaller than
-  the proposals each point needs gives, point by point, the same accepted
+* windows: a sweep over points of every K, with fixed windows much smaller
+  than the proposals each point needs and with windows sized on the device
+  from the measured acceptance, gives, point by point, the same accepted
   samples (indices and rows, bit for bit), the same proposal count and the
-  same statistics as a single accepted-count call of that point;
-* the hipGraph replay of a window gives bit-identical results to launching
+  same statistics as a single accepted-count call of that point; the
+  adaptive sweep of these points is one graph launch;
+* the hipGraph launch of 16 windows gives bit-identical results to launching
   the same sequence directly, and to itself on a second call;
+* every tile variant of the decision kernel gives bit-identical results;
 * a point that reaches its proposal cap stops there;
-* against the oracle: the first n accepted samples of the CPU-sized point;
-* the autotuner returns a valid configuration and reads it back from its
-  cache without timing again.
+* against the oracle: the first n accepted samples of a K = 8, 16, 32 and 64
+  point;
+* the autotuner returns a valid configuration (variant, workgroups per
+  compute unit, first window) and reads it back from its cache.
 """
 import os
 import sys
@@ -59,19 +63,24 @@ def _points(T):
     return pts, plans
 
 
-@pytest.mark.parametrize("use_graph", [0, 1])
-def test_sweep_equals_single_point_calls(T, ctx, use_graph):
+@pytest.mark.parametrize("use_graph,adaptive", [(0, 0), (1, 0), (1, 1)])
+def test_sweep_equals_single_point_calls(T, ctx, use_graph, adaptive):
     pts, plans = _points(T)
     targets = [s[3] for s in SPECS]
     maxp = [s[4] for s in SPECS]
-    cfg = T.LaunchCfg(0, use_graph, 1 << 16)   # windows of 2^16 proposals: several windows per point
+    # first windows of 2^16 proposals: several windows per point
+    cfg = T.LaunchCfg(0, use_graph, 1 << 16, 0, adaptive)
     caps = [t + 5 for t in targets]
     out, _, _ = ctx.sample_sweep(pts, targets, maxp, plans=plans, precision=T.BF16X3, cfg=cfg, capacity=caps)
-    windows = ctx.timing()["windows"]
-    say(f"use_graph={use_graph}: {windows} windows, {ctx.timing()['total_ms']:.1f} ms")
+    tm = ctx.timing()
+    windows = tm["windows"]
+    say(f"use_graph={use_graph} adaptive={adaptive}: {windows} windows, {tm['graph_launches']} launches, "
+        f"{tm['total_ms']:.1f} ms")
     for i, o in enumerate(out):
         say(f"   point {i}: accepted {o['n_accepted']} proposed {o['n_proposed']} written {o['n_written']}")
-    assert windows > 4
+    assert windows > (1 if adaptive else 4)
+    if adaptive:
+        assert tm["graph_launches"] == 1
     for i, (p, pl, o) in enumerate(zip(pts, plans, out)):
         r = ctx.sample(p, targets[i], proposal=T.SIGMA, plan=pl, mode=T.COUNT_ACCEPTED, max_proposals=maxp[i],
                        precision=T.BF16X3, capacity=caps[i])
@@ -103,12 +112,32 @@ def test_sweep_graph_replay_is_deterministic(T, ctx):
     assert res[0] == res[1] == res[2]
 
 
-def test_sweep_against_oracle(T, ctx):
-    K, bp, c, target = 8, 40.0, 20.0, 400
+def test_sweep_tile_variants_are_bit_identical(T, ctx):
+    """The tuner's variants change the workgroup size and how many tile pairs
+    keep their accumulators live together, not the arithmetic."""
+    pts, plans = _points(T)
+    idx = [1, 2, 3]   # K = 16, 32, 64
+    targets = [SPECS[i][3] for i in idx]
+    maxp = [SPECS[i][4] for i in idx]
+    res = []
+    for v in range(4):
+        out, _, _ = ctx.sample_sweep([pts[i] for i in idx], targets, maxp, plans=[plans[i] for i in idx],
+                                     precision=T.BF16X3, cfg=T.LaunchCfg(0, 1, 1 << 20, v, 1), capacity=targets)
+        say(f"variant {v}: {[o['n_accepted'] for o in out]}")
+        res.append([(o["n_accepted"], o["n_proposed"], o["S3"], o["index"].cpu().numpy().tobytes(),
+                     o["xhat"].cpu().numpy().tobytes()) for o in out])
+    assert res[0] == res[1] == res[2] == res[3]
+
+
+@pytest.mark.parametrize("K,bp,c,target,variant", [(8, 40.0, 20.0, 400, 0), (16, 20.0, 60.0, 500, 0),
+                                                   (32, 40.0, 75.0, 400, 0), (64, 40.0, 150.0, 300, 0),
+                                                   (64, 40.0, 300.0, 300, 3)])
+def test_sweep_against_oracle(T, ctx, K, bp, c, target, variant):
     pt = T.make_point(K, 1.0, bp, c, seed=0, point_id=0)
     pl = T.plan_point(pt, T.SIGMA)
     out, _, _ = ctx.sample_sweep([pt], [target], [1 << 26], plans=[pl], precision=T.BF16X3,
-                                 cfg=T.LaunchCfg(0, 1, 1 << 16), capacity=[target])
+                                 cfg=T.LaunchCfg(0, 1, 1 << 16, variant, 1), capacity=[target])
+    say(f"K={K}: {ctx.timing()['windows']} windows")
     o = oracle.sample_until(K, 1.0, bp, c, 1, pl.alpha_star, pl.log_M, 0, 0, target, 1 << 26, 4 * K)
     assert out[0]["n_accepted"] == target == o["stats"].n_accepted
     assert np.array_equal(out[0]["index"].cpu().numpy().astype(np.uint64), o["index"])
@@ -116,12 +145,15 @@ def test_sweep_against_oracle(T, ctx):
     xg = out[0]["xhat"].cpu().numpy().astype(np.float64)
     assert np.max(np.linalg.norm(xg - o["xhat"], axis=1)) < 2e-6
     assert abs(out[0]["S2"] - o["stats"].S2) < 1e-6 * o["stats"].S2
+    assert abs(out[0]["S4"] - o["stats"].S4) < 2e-5 * o["stats"].S4
 
 
 def test_sweep_argument_errors(T, ctx):
     pts, plans = _points(T)
     with pytest.raises(T.TkdvError):
         ctx.sample_sweep(pts[:1], [10], [1 << 20], plans=plans[:1], cfg=T.LaunchCfg(0, 1, 1000))  # window
+    with pytest.raises(T.TkdvError):
+        ctx.sample_sweep(pts[:1], [10], [1 << 20], plans=plans[:1], cfg=T.LaunchCfg(0, 1, 1 << 16, 4))  # variant
     with pytest.raises(T.TkdvError):
         ctx.sample_sweep(pts[:1], [0], [1 << 20], plans=plans[:1])                                # target 0
     up = T.plan_point(pts[0], T.UNIFORM)
@@ -134,6 +166,7 @@ def test_autotune_and_cache(T, ctx, tmp_path):
     c1 = ctx.autotune(16, T.BF16X3, path)
     say(f"autotuned K=16: {c1.to_dict()}")
     assert c1.window in (1 << 24, 1 << 25, 1 << 26) and c1.blocks_per_cu >= 1 and c1.use_graph == 1
+    assert 0 <= c1.variant < 4 and c1.adaptive == 1
     assert os.path.exists(path) and "K=16" in open(path).read()
     ctx.set_launch_cfg(16, T.BF16X3, T.LaunchCfg(0, 1, 1 << 16))
     c2 = ctx.autotune(16, T.BF16X3, path)      # from the cache
