@@ -10,6 +10,7 @@ compiled on first use when it is missing.  The environment variable
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -56,6 +57,7 @@ class _Stats(C.Structure):
         ("skewness", C.c_double), ("kurtosis", C.c_double), ("p_exceed", C.c_double),
         ("hist_lo", C.c_double), ("hist_hi", C.c_double),
         ("hist", C.c_uint64 * NBINS),
+        ("n_exceed4", C.c_uint64), ("n_max4", C.c_uint64), ("peak_u", C.c_double), ("peak_index", C.c_uint64),
     ]
 
 
@@ -100,12 +102,17 @@ class OracleStats:
     hist_lo: float
     hist_hi: float
     hist: np.ndarray
+    n_exceed4: int = 0      # grid values above 4 sigma = 4 sqrt(E0/pi)
+    n_max4: int = 0         # samples whose largest grid value is above 4 sigma
+    peak_u: float = -math.inf   # largest grid value over the samples
+    peak_index: int = 2**64 - 1  # index of the sample attaining it (lowest among equal)
 
     @classmethod
     def _from(cls, s: _Stats) -> "OracleStats":
         return cls(s.n_proposed, s.n_accepted, s.n_written, s.n_violations, s.n_exceed,
                    s.n_grid, s.max_log_a, s.S1, s.S2, s.S3, s.S4, s.skewness, s.kurtosis,
-                   s.p_exceed, s.hist_lo, s.hist_hi, np.array(s.hist[:], dtype=np.uint64))
+                   s.p_exceed, s.hist_lo, s.hist_hi, np.array(s.hist[:], dtype=np.uint64),
+                   s.n_exceed4, s.n_max4, s.peak_u, s.peak_index)
 
     @property
     def acceptance(self) -> float:

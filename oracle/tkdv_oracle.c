@@ -476,7 +476,10 @@ uint64_t orc_mix_sample(const orc_point *p, const orc_mixture *m, uint64_t i0, u
 /* ------------------------------------------------------------------------ */
 /* Statistics of the accepted ensemble (moments of u pooled over samples x  */
 /* grid points, exceedance of 2 sigma with sigma = sqrt(E0/pi), histogram of */
-/* u(0) on [-u_max, u_max], u_max = sqrt(2 K E0/pi)).                       */
+/* u(0) on [-u_max, u_max], u_max = sqrt(2 K E0/pi)), and the extremes of    */
+/* Sec. V.D: grid values above 4 sigma, samples whose largest grid value is  */
+/* above 4 sigma, and the largest displacement with its sample's index      */
+/* (the lowest index among equal maxima).                                   */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     uint64_t n_proposed, n_accepted, n_written, n_violations, n_exceed, n_grid;
@@ -485,11 +488,14 @@ typedef struct {
     double skewness, kurtosis, p_exceed;
     double hist_lo, hist_hi;
     uint64_t hist[ORC_NBINS];
+    uint64_t n_exceed4, n_max4; /* grid values > 4 sigma; samples with max_j u_j > 4 sigma */
+    double peak_u;              /* largest u over samples x grid (-inf: no sample)        */
+    uint64_t peak_index;        /* index of the sample attaining it (UINT64_MAX: none)    */
 } orc_stats;
 
 typedef struct {
     int K, N;
-    double E0, amp, two_sigma, u_max;
+    double E0, amp, two_sigma, four_sigma, u_max;
     double *cosv, *sinv; /* [N][K] */
 } orc_grid_table;
 
@@ -498,6 +504,7 @@ static void grid_table_init(orc_grid_table *g, int K, int N, double E0)
     g->K = K; g->N = N; g->E0 = E0;
     g->amp = sqrt(2.0 * E0 / M_PI);
     g->two_sigma = 2.0 * sqrt(E0 / M_PI);
+    g->four_sigma = 4.0 * sqrt(E0 / M_PI);
     g->u_max = sqrt(2.0 * K * E0 / M_PI);
     g->cosv = (double *)malloc(sizeof(double) * (size_t)N * K);
     g->sinv = (double *)malloc(sizeof(double) * (size_t)N * K);
@@ -521,9 +528,21 @@ int orc_hist_bin(double u0, double u_max)
     return b;
 }
 
-static void stats_add_sample(orc_stats *st, const orc_grid_table *g, const double *xh)
+static void stats_init(orc_stats *st, const orc_grid_table *g)
+{
+    memset(st, 0, sizeof(*st));
+    st->hist_lo = -g->u_max;
+    st->hist_hi = g->u_max;
+    st->peak_u = -INFINITY;
+    st->peak_index = UINT64_MAX;
+}
+
+/* One accepted sample x^ (proposal index `index`); samples come in increasing
+   index, so a later sample replaces the peak only with a strictly larger u. */
+static void stats_add_sample(orc_stats *st, const orc_grid_table *g, const double *xh, uint64_t index)
 {
     int K = g->K;
+    double umax = -INFINITY;
     for (int j = 0; j < g->N; ++j) {
         double s = 0.0;
         for (int k = 0; k < K; ++k)
@@ -535,6 +554,13 @@ static void stats_add_sample(orc_stats *st, const orc_grid_table *g, const doubl
         st->S3 += u2 * u;
         st->S4 += u2 * u2;
         if (u > g->two_sigma) st->n_exceed++;
+        if (u > g->four_sigma) st->n_exceed4++;
+        if (u > umax) umax = u;
+    }
+    if (umax > g->four_sigma) st->n_max4++;
+    if (umax > st->peak_u) {
+        st->peak_u = umax;
+        st->peak_index = index;
     }
     st->n_grid += (uint64_t)g->N;
     /* u(0): xi = 0 is a grid point when N is even; evaluated spectrally. */
@@ -581,11 +607,9 @@ uint64_t orc_sample(const orc_point *p, uint64_t i0, uint64_t n, uint8_t *accept
         if (log_u_out) log_u_out[q] = lu;
     }
     orc_stats local;
-    memset(&local, 0, sizeof(local));
     orc_grid_table g;
     grid_table_init(&g, K, p->N, p->E0);
-    local.hist_lo = -g.u_max;
-    local.hist_hi = g.u_max;
+    stats_init(&local, &g);
     uint64_t nacc = 0;
     double xh[2 * ORC_KMAX];
     for (uint64_t q = 0; q < n; ++q) {
@@ -597,7 +621,7 @@ uint64_t orc_sample(const orc_point *p, uint64_t i0, uint64_t n, uint8_t *accept
             if (index_out) index_out[nacc] = i0 + q;
             local.n_written++;
         }
-        stats_add_sample(&local, &g, xh);
+        stats_add_sample(&local, &g, xh, i0 + q);
         nacc++;
     }
     grid_table_free(&g);
@@ -625,11 +649,9 @@ uint64_t orc_sample_until(const orc_point *p, uint64_t n_target, uint64_t max_pr
     const uint64_t block = 1u << 16;
     uint8_t *acc = (uint8_t *)malloc(block);
     orc_stats local;
-    memset(&local, 0, sizeof(local));
     orc_grid_table g;
     grid_table_init(&g, K, p->N, p->E0);
-    local.hist_lo = -g.u_max;
-    local.hist_hi = g.u_max;
+    stats_init(&local, &g);
     double max_la = -INFINITY;
     uint64_t nacc = 0, last = 0, nviol = 0;
     double xh[2 * ORC_KMAX];
@@ -649,7 +671,7 @@ uint64_t orc_sample_until(const orc_point *p, uint64_t n_target, uint64_t max_pr
                 if (index_out) index_out[nacc] = base + q;
                 local.n_written++;
             }
-            stats_add_sample(&local, &g, xh);
+            stats_add_sample(&local, &g, xh, base + q);
             nacc++;
         }
         free(la);
@@ -706,12 +728,10 @@ void orc_eval_batch(const orc_point *p, uint64_t i0, uint64_t n, double *H2, dou
 void orc_stats_of(int K, int N, double E0, const double *xhat, uint64_t n, orc_stats *st)
 {
     orc_stats local;
-    memset(&local, 0, sizeof(local));
     orc_grid_table g;
     grid_table_init(&g, K, N, E0);
-    local.hist_lo = -g.u_max;
-    local.hist_hi = g.u_max;
-    for (uint64_t s = 0; s < n; ++s) stats_add_sample(&local, &g, xhat + s * 2 * K);
+    stats_init(&local, &g);
+    for (uint64_t s = 0; s < n; ++s) stats_add_sample(&local, &g, xhat + s * 2 * K, s);
     grid_table_free(&g);
     local.n_accepted = n;
     stats_finish(&local);

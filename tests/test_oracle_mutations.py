@@ -22,7 +22,7 @@ SRC = os.path.join(ROOT, "oracle", "tkdv_oracle.c")
 FAST_PINS = " or ".join([
     "appendix_A", "dirichlet_kernel", "double_sum_equals", "parseval", "H3_odd",
     "box_muller", "philox_known", "uniform_sphere_law", "K2_brute_force", "uniform_proposal_linear",
-    "paper_linear_rows and 16-", "positive_nonlinearity",
+    "paper_linear_rows and 16-", "positive_nonlinearity", "extremes_",
 ])
 
 MUTATIONS = {
@@ -57,6 +57,10 @@ MUTATIONS = {
     "hist_bins": ("double pos = (u0 + u_max) / (2.0 * u_max) * ORC_NBINS;",
                   "double pos = (u0 + u_max) / (2.0 * u_max) * (ORC_NBINS - 1);"),
     "accept_rule": ("acc[q] = (uint8_t)(lu < la);", "acc[q] = (uint8_t)(lu < la + 0.05);"),
+    "four_sigma_scale": ("g->four_sigma = 4.0 * sqrt(E0 / M_PI);", "g->four_sigma = 4.0 * sqrt(E0 / (2 * M_PI));"),
+    "max4_counts_values": ("if (umax > g->four_sigma) st->n_max4++;", "if (umax > g->two_sigma) st->n_max4++;"),
+    "peak_keeps_last_tie": ("if (umax > st->peak_u) {", "if (umax >= st->peak_u) {"),
+    "peak_index_offset": ("stats_add_sample(&local, &g, xh, i0 + q);", "stats_add_sample(&local, &g, xh, q);"),
 }
 
 

@@ -310,6 +310,9 @@ def test_uniform_sphere_law_beta0(K):
     pex = 0.5 * special.betainc(K - 0.5, 0.5, 1 - 2 / K) if K > 2 else 0.0
     assert abs(s.p_exceed - pex) < 6 * math.sqrt(pex * (1 - pex) / n) + 1e-4
     assert abs(s.skewness) < 0.05
+    # 4 sigma: the same law at c = 4 sqrt(E0/pi), (c/u_max)^2 = 8/K
+    p4 = 0.5 * special.betainc(K - 0.5, 0.5, 1 - 8 / K) if K > 8 else 0.0
+    assert abs(s.n_exceed4 / s.n_grid - p4) < 6 * math.sqrt(p4 * (1 - p4) / n) + 2e-5
     # histogram of u(0): counts vs the exact bin probabilities
     edges = np.linspace(-umax, umax, 65)
     probs = np.diff(cdf(edges))
@@ -517,3 +520,71 @@ def test_one_thread_call_leaves_the_thread_count():
     pl = plan.plan_point(8, 1.0, 40.0, 20.0, plan.SIGMA)
     oracle.sample(8, 1.0, 40.0, 20.0, 1, pl.alpha_star, pl.log_M, 0, 0, 256, 32, nthreads=1)
     assert oracle.max_threads() == n0
+
+
+# --------------------------------------------------------------------------
+# Extremes of the accepted ensemble (Sec. V.D): 4 sigma = 4 sqrt(E0/pi)
+# --------------------------------------------------------------------------
+
+def _grid_fft(xhat, E0, N):
+    """u on xi_j = -pi + 2 pi j/N from numpy's inverse FFT: u_j = amp Re sum_k
+    (a_k - i b_k) (-1)^k e^{2 pi i k j/N} (a library routine, not the
+    oracle's direct cos/sin sum)."""
+    x = np.atleast_2d(np.asarray(xhat, dtype=np.float64))
+    K = x.shape[1] // 2
+    c = np.zeros((x.shape[0], N), dtype=np.complex128)
+    sign = (-1.0) ** np.arange(1, K + 1)
+    c[:, 1:K + 1] = (x[:, :K] - 1j * x[:, K:]) * sign
+    return math.sqrt(2 * E0 / math.pi) * np.real(np.fft.ifft(c, axis=1) * N)
+
+
+def test_extremes_dirichlet_closed_form():
+    """x^ = (1, ..., 1, 0, ..., 0)/sqrt(K): u = amp D_K(xi)/sqrt(K) with the
+    Dirichlet kernel D_K(xi) = sin((K + 1/2) xi)/(2 sin(xi/2)) - 1/2 (D_K(0) = K).
+    The peak is u_max = sqrt(2 K E0/pi) at xi = 0, above 4 sigma iff K > 8."""
+    for K, E0 in [(16, 1.0), (32, 2.0), (8, 1.0)]:
+        N = 4 * K
+        xh = np.zeros(2 * K)
+        xh[:K] = 1 / math.sqrt(K)
+        st = oracle.stats_of(np.stack([xh, -xh, xh]), E0, N)
+        assert st.peak_u == pytest.approx(math.sqrt(2 * K * E0 / math.pi), rel=1e-13)
+        assert st.peak_index == 0                 # sample 2 ties with sample 0
+        xi = -math.pi + 2 * math.pi * np.arange(N) / N
+        with np.errstate(divide="ignore", invalid="ignore"):
+            D = np.where(np.abs(xi) < 1e-12, K, np.sin((K + 0.5) * xi) / (2 * np.sin(xi / 2)) - 0.5)
+        u = math.sqrt(2 * E0 / math.pi) * D / math.sqrt(K)
+        four = 4 * math.sqrt(E0 / math.pi)
+        margin = np.min(np.abs(u - four))
+        if margin > 1e-9:
+            assert st.n_exceed4 == 2 * int(np.sum(u > four)) + int(np.sum(-u > four))
+            assert st.n_max4 == (2 if K > 8 else 0) + (1 if np.max(-u) > four else 0)
+
+
+@pytest.mark.parametrize("K,bp,c", [(8, 40.0, 20.0), (16, 40.0, 50.0)])
+def test_extremes_against_fft(K, bp, c):
+    """Accepted samples of a nonlinear point: 2 and 4 sigma counts, samples whose
+    maximum is above 4 sigma, the peak and its index, and S1..S4, all from the
+    grid values of numpy's FFT."""
+    p = plan.plan_point(K, 1.0, bp, c, n_random=0)
+    n = 200000 if K == 8 else 100000
+    i0 = 1 << 20
+    r = oracle.sample(K, 1.0, bp, c, 1, p.alpha_star, p.log_M, 3, 1, n, 4 * K, i0=i0, cap=n)
+    st = r["stats"]
+    assert st.n_accepted > 100
+    u = _grid_fft(r["xhat"], 1.0, 4 * K)
+    two, four = 2 / math.sqrt(math.pi), 4 / math.sqrt(math.pi)
+    assert np.min(np.abs(u - four)) > 1e-9 and np.min(np.abs(u - two)) > 1e-9
+    assert st.n_exceed == int(np.sum(u > two))
+    assert st.n_exceed4 == int(np.sum(u > four))
+    um = u.max(axis=1)
+    assert st.n_max4 == int(np.sum(um > four))
+    assert st.peak_u == pytest.approx(um.max(), rel=1e-12)
+    assert st.peak_index == int(r["index"][int(np.argmax(um))])
+    for q, S in ((1, st.S1), (2, st.S2), (3, st.S3), (4, st.S4)):
+        assert S == pytest.approx(float(np.sum(u ** q)), rel=1e-9, abs=1e-9 * float(np.sum(np.abs(u) ** q)))
+    # accepted-count mode keeps the first n_t by index, so its peak is theirs
+    n_t = 50
+    r0 = oracle.sample(K, 1.0, bp, c, 1, p.alpha_star, p.log_M, 3, 1, n, 4 * K, cap=n)
+    um0 = _grid_fft(r0["xhat"][:n_t], 1.0, 4 * K).max(axis=1)
+    w = oracle.sample_until(K, 1.0, bp, c, 1, p.alpha_star, p.log_M, 3, 1, n_t, n, 4 * K)
+    assert w["stats"].peak_index == int(r0["index"][int(np.argmax(um0))])
