@@ -26,7 +26,7 @@ with the autotuner's launch configuration.
 samples/s), beside the rejection sampler and the extreme-wave search.
 --workload k128: the paper's sampler at K = 128 (N = 512; the mode count of
 its parallel speed-up study), 4 points x 1e9 proposals, quarter-period
-synthesis.
+synthesis; --workload k64 the same at K = 64 (N = 256).
 --synthesis: the standalone synthesis on the precision configuration (K = 64,
 2^20 rows of x^ in HBM; HBM roofline), plus the same synthesis with x^ drawn
 in registers (the decision kernel).
@@ -170,7 +170,8 @@ def load_traffic(K: int, precision: str, proposals_per_launch: int, kernel: str 
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("kernel_source_digest") != kernel_source_digest():
+    src = ("tkdv_device.h", "tkdv_quarter.hip") if kernel == "k_decide128" else ("tkdv_device.h", "tkdv_kernels.hip")
+    if d.get("kernel_source_digest") != kernel_source_digest(src):
         return None
     return d["bytes_per_proposal"] * proposals_per_launch
 
@@ -478,12 +479,20 @@ def cpu_baseline_mixture(points, mixtures, mix_plans, n_sample: int) -> dict:
     }
 
 
-def k128_bench(args) -> int:
-    """K = 128 (N = 512): the paper's Sigma sampler on 4 points (beta' in
-    {20, 40} x beta' C3/C2 in {30000, 40000}), 1e9 proposals per point in one
-    batched call (the quarter-period decision kernel k_decide128), all
-    statistics and up to 2^20 samples per point stored.  value = accepted
-    samples/s; the roofline is k_decide128's launch."""
+QUARTER_WORKLOADS = {
+    "k64": (64, "K=64, N=256, E0=1, Sigma proposal, beta' in {20,40} x beta'C3/C2 in {9000,15000}, "
+                "1e9 proposals/point (the mode count of the precision configuration)"),
+    "k128": (128, "K=128, N=512, E0=1, Sigma proposal, beta' in {20,40} x beta'C3/C2 in {30000,40000}, "
+                  "1e9 proposals/point (the mode count of the paper's speed-up study)"),
+}
+
+
+def quarter_bench(args) -> int:
+    """K = 64 (N = 256) or K = 128 (N = 512): the paper's Sigma sampler on 4
+    points, 1e9 proposals per point in one batched call (the quarter-period
+    decision kernel k_decide128<K>), all statistics and up to 2^20 samples per
+    point stored.  value = accepted samples/s; the roofline is the decision
+    kernel's launch."""
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs an MI355X GPU", file=sys.stderr)
@@ -491,19 +500,19 @@ def k128_bench(args) -> int:
     from paper_2411_16952_amd import tkdv as T
     from paper_2411_16952_amd import workloads as W
 
-    specs = W.k128_points()
+    K, workload = QUARTER_WORKLOADS[args.workload]
+    specs = W.k64_points() if K == 64 else W.k128_points()
     pts = [T.make_point(s.K, s.E0, s.beta_p, s.c32, seed=s.seed, point_id=s.point_id) for s in specs]
     t0 = time.perf_counter()
-    with cf.ThreadPoolExecutor(max_workers=len(pts)) as ex:   # the host search of log M (256 coordinates)
+    with cf.ThreadPoolExecutor(max_workers=len(pts)) as ex:   # the host search of log M (2K coordinates)
         plans = list(ex.map(lambda p: T.plan_point(p, T.SIGMA), pts))
     plan_s = time.perf_counter() - t0
-    K = 128
     n_per = int(args.proposals)
     n = [n_per] * len(pts)
     cap = [1 << 20] * len(pts)
     prec = T.PRECISIONS[args.precision]
     ctx = T.Context(0)
-    print(f"bench: K=128, {len(pts)} points, {n_per:.3g} proposals/point, {args.precision}, plans {plan_s:.1f}s",
+    print(f"bench: K={K}, {len(pts)} points, {n_per:.3g} proposals/point, {args.precision}, plans {plan_s:.1f}s",
           file=sys.stderr, flush=True)
 
     def step():
@@ -529,22 +538,20 @@ def k128_bench(args) -> int:
     ops = method_ops_per_proposal(K, "sigma", args.precision)
     roof = alu_roof(ops * per_launch / avg_decide_s, traffic=load_traffic(K, args.precision, per_launch,
                                                                            "k_decide128"),
-                    kernel="k_decide128", method_ops_per_proposal=ops, avg_launch_ms=avg_decide_s * 1e3,
+                    kernel=f"k_decide128<{K}>", method_ops_per_proposal=ops, avg_launch_ms=avg_decide_s * 1e3,
                     proposals_per_launch=per_launch,
                     **mfma_fields(K, args.precision, "sigma", per_launch / avg_decide_s))
-    n_cpu = (1 << 15) if args.cpu_sample < 0 else args.cpu_sample
+    n_cpu = ((1 << 16) if K == 64 else (1 << 15)) if args.cpu_sample < 0 else args.cpu_sample
     cpu = None
     if n_cpu > 0:
         print("cpu baseline ...", file=sys.stderr, flush=True)
         cpu = cpu_baseline(specs, plans, n_cpu)
     line = {
-        "metric": "accepted samples/sec at K=128 (plain Sigma proposal); proposals/sec",
+        "metric": f"accepted samples/sec at K={K} (plain Sigma proposal); proposals/sec",
         "value": acc / dt, "unit": "accepted samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": dtype_label(args.precision), "data": "synthetic",
-        "config": {"workload": "K=128, N=512, E0=1, Sigma proposal, beta' in {20,40} x beta'C3/C2 in "
-                               "{30000,40000}, 1e9 proposals/point (the mode count of the paper's speed-up study)",
-                   "K": K, "N": 4 * K, "points": len(pts), "proposals_per_point": n_per,
+        "config": {"workload": workload, "K": K, "N": 4 * K, "points": len(pts), "proposals_per_point": n_per,
                    "synthesis": args.precision, "fp64_redecision": True},
         "proposals_per_s": n_prop / dt, "acceptance": acc / n_prop,
         "per_point": [{"beta_p": s.beta_p, "level": s.beta_p * s.c32, "acceptance": int(o["n_accepted"]) / n_per,
@@ -769,11 +776,12 @@ def sweep_bench(args) -> int:
     torch.cuda.synchronize()
     acc = prop = 0
     ops = 0.0
-    windows = []
+    windows, graph_launches = [], []
     t0 = time.perf_counter()
     for s in range(args.steps):
         out = step()
         windows.append(ctx.timing()["windows"])
+        graph_launches.append(ctx.timing()["graph_launches"])
         acc += sum(int(o["n_accepted"]) for o in out)
         prop += sum(int(o["n_proposed"]) for o in out)
         ops += sum(method_ops_per_proposal(p.K, "sigma", args.precision) * int(o["n_proposed"])
@@ -799,6 +807,7 @@ def sweep_bench(args) -> int:
                                "replays", "points": len(pts), "targets_sum": sum(targets),
                    "synthesis": args.precision},
         "proposals_per_s": prop / dt, "targets_met": met, "windows_per_step": windows,
+        "graph_launches_per_step": graph_launches,
         "autotuned": {str(k): v for k, v in tuned.items()}, "autotune_seconds": tune_s,
         "screen_seconds": screen_s, "plan_seconds": plan_s, "plan": "GPU multi-start search (tkdv_plan_batch, 16 starts)",
         "roofline": roof, "cpu_baseline": cpu,
@@ -813,7 +822,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="learned", choices=["learned", "plain", "sweep", "sir", "k128"])
+    ap.add_argument("--workload", default="learned", choices=["learned", "plain", "sweep", "sir", "k64", "k128"])
     ap.add_argument("--tune-cache", default="/tmp/tkdv_autotune.txt", help="autotuner cache (sweep workload)")
     ap.add_argument("--proposals", type=float, default=1e9, help="proposals per point (per sampler)")
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16x3"],
@@ -849,8 +858,8 @@ def main() -> int:
         return sweep_bench(args)
     if args.workload == "sir":
         return sir_bench(args)
-    if args.workload == "k128":
-        return k128_bench(args)
+    if args.workload in QUARTER_WORKLOADS:
+        return quarter_bench(args)
     return learned_bench(args) if args.workload == "learned" else plain_bench(args)
 
 

@@ -156,7 +156,9 @@ typedef struct {
     int32_t n_optimiser_evals;  /* objective evaluations spent on log_M                      */
 } tkdv_plan;
 
-/* Statistics of one point's run (Sec. V: skewness, histograms, 2-sigma). */
+/* Statistics of one point's run (Sec. V: skewness, histograms, 2-sigma; the
+ * extremes of Sec. V.D against 4 sigma).  Grid values are u on the N = 4K grid
+ * xi_j = -pi + 2 pi j/N of every accepted sample. */
 typedef struct {
     uint64_t n_proposed;      /* proposals covered by the statistics                         */
     uint64_t n_accepted;      /* accepted among them                                         */
@@ -175,6 +177,11 @@ typedef struct {
     double log_M_used;        /* log M of the returned samples (raised after a violation)    */
     int32_t M_raises;         /* runs repeated with a raised M (TKDV_MV_RAISE)               */
     int32_t fallback;         /* 1: the mixture sampler fell back to the Sigma sampler       */
+    uint64_t n_exceed_4sigma; /* grid values with u > 4 sqrt(E0/pi)                          */
+    uint64_t n_samples_4sigma;/* accepted samples whose largest grid value is above that     */
+    double peak_u;            /* largest grid value over the accepted samples (-inf: none)   */
+    uint64_t peak_index;      /* proposal index of the sample attaining it, the lowest among
+                                 equal maxima (UINT64_MAX: none)                             */
 } tkdv_stats;
 
 /* Device time of the phases of the last tkdv_sample / tkdv_sample_batch /

@@ -64,10 +64,10 @@ struct tkdv_ctx {
     std::string last_error;
     DevBuf bitmap, defer_list, defer_count, counters, points, seg_cnt, seg_base, seg_stats, results, plist;
     DevBuf mix, mix_tab;  // learned-proposal constants and tables of the current call
-    // K = 128 (index 4): the quarter-period tables of k_decide128 (BF16 hi, lo,
-    // FP32) and, in phi_mat128, the FP32 table of its statistics synthesis
-    DevBuf phi_hi[kNumK], phi_lo[kNumK], phi_f32[kNumK], phi_mat128;
-    DevBuf q64_hi, q64_lo, q64_f32;  // K = 64's quarter-period tables (its tile variant 3)
+    // K = 128 (index 4): the quarter-period tables of k_decide128 (BF16 hi, lo, FP32)
+    DevBuf phi_hi[kNumK], phi_lo[kNumK], phi_f32[kNumK];
+    DevBuf q64_hi, q64_lo, q64_f32;  // K = 64's quarter-period decision tables
+    DevBuf qstat[2];                 // quarter-period statistics tables, K = 64 and 128
     // the same tables with the odd-mode rows scaled by sqrt(3), for the kernels
     // that form S3 in the half-period form (K >= 16): s3_tables()
     DevBuf phi3_hi[kNumK], phi3_lo[kNumK], phi3_f32[kNumK];
@@ -144,18 +144,17 @@ hipError_t ensure_host(void *&p, size_t &have, size_t bytes)
     return hipSuccess;
 }
 
-// K = 128 tables (tkdv_k128.hip), N = 512.
-//   Quarter-period decision tables on the representatives xi_rho =
-//   pi (2 rho + 1)/N, rho < 128 (the grid offset by half a step, points in
-//   (0, pi/2)): for tile tau (rho = 16 tau + l % 16), output o (0: cos, even
+// Quarter-period tables (tkdv_quarter.hip), K = 64 and 128, N = 4K.
+//   Decision tables on the representatives xi_rho = pi (2 rho + 1)/N, rho < K
+//   (the grid offset by half a step, points in (0, pi/2)): for tile tau
+//   (rho = 16 tau + l % 16), output o (0: cos, even
 //   modes; 1: cos, odd modes; 2: sin, even; 3: sin, odd; o > 0 scaled by
 //   sqrt 3) and lane group g = l/16, the entry of mode
 //   k = 32 g + 2 idx + (o even ? 2 : 1), where idx = 8 r + e in the BF16
 //   layout [tau][o][r < 2][64 lanes][e < 8] (hi, lo) and idx = 4 q + e in the
 //   FP32 layout [tau][o][q < 4][64 lanes][e < 4].
-//   Statistics table (FP32, standard grid xi_j = -pi + 2 pi j/N): [T < 32][m4 <
-//   16][64 lanes][e < 4], grid point 16 T + l % 16, k-step m = 4 m4 + e of lane
-//   group g: cos of mode 32 g + m + 1 (m < 32), sin of mode 32 g + m - 31.
+//   Statistics tables (FP32): the same layout on the statistics grid's own
+//   representatives xi_rho = 2 pi rho/N, rho < K, unscaled.
 //   Angles are reduced exactly in integers before the FP64 cos/sin.
 hipError_t upload_quarter(int K, DevBuf &d_hi, DevBuf &d_lo, DevBuf &d_f32)
 {
@@ -198,26 +197,30 @@ hipError_t upload_quarter(int K, DevBuf &d_hi, DevBuf &d_lo, DevBuf &d_f32)
     return e;
 }
 
+hipError_t upload_quarter_stats(int K, DevBuf &d_f32)
+{
+    const int N = 4 * K, CPL = K / 4, TILES = K / 16, QG = K / 32;
+    auto mode = [&](int o, int g, int idx) { return CPL * g + 2 * idx + ((o == 0 || o == 2) ? 2 : 1); };
+    std::vector<float> f32((size_t)TILES * 4 * QG * 64 * 4);
+    for (int tau = 0; tau < TILES; ++tau)
+        for (int o = 0; o < 4; ++o)
+            for (int q = 0; q < QG; ++q)
+                for (int l = 0; l < 64; ++l)
+                    for (int e = 0; e < 4; ++e) {
+                        const int k = mode(o, l / 16, 4 * q + e), rho = 16 * tau + l % 16;
+                        const double ang = 2.0 * kPi * (double)(((long)k * rho) % N) / N;
+                        f32[((((size_t)tau * 4 + o) * QG + q) * 64 + l) * 4 + e] =
+                            (float)(o < 2 ? std::cos(ang) : std::sin(ang));
+                    }
+    hipError_t e = ensure(d_f32, f32.size() * 4);
+    if (e == hipSuccess) e = hipMemcpy(d_f32.p, f32.data(), f32.size() * 4, hipMemcpyHostToDevice);
+    return e;
+}
+
 tkdv_status build_tables128(tkdv_ctx *ctx)
 {
-    const int N = 4 * 128;
     HIP_TRY(ctx, upload_quarter(128, ctx->phi_hi[4], ctx->phi_lo[4], ctx->phi_f32[4]));
-    std::vector<float> mat((size_t)32 * 16 * 64 * 4);
-    for (int T = 0; T < 32; ++T)
-        for (int m4 = 0; m4 < 16; ++m4)
-            for (int l = 0; l < 64; ++l)
-                for (int e = 0; e < 4; ++e) {
-                    const int m = 4 * m4 + e, g = l / 16, j = 16 * T + l % 16;
-                    const bool cosb = m < 32;
-                    const int k = cosb ? 32 * g + m + 1 : 32 * g + m - 31;
-                    const long r = ((long)k * j) % N;
-                    const double ang = 2.0 * kPi * (double)r / N;
-                    const double sign = (k & 1) ? -1.0 : 1.0;  // k xi_j = -k pi + 2 pi (k j mod N)/N
-                    mat[(((size_t)T * 16 + m4) * 64 + l) * 4 + e] =
-                        (float)(cosb ? sign * std::cos(ang) : sign * std::sin(ang));
-                }
-    HIP_TRY(ctx, ensure(ctx->phi_mat128, mat.size() * 4));
-    HIP_TRY(ctx, hipMemcpy(ctx->phi_mat128.p, mat.data(), mat.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, upload_quarter_stats(128, ctx->qstat[1]));
     return TKDV_OK;
 }
 
@@ -269,7 +272,10 @@ tkdv_status build_tables(tkdv_ctx *ctx, int K)
         return e;
     };
     if (K == 128) return build_tables128(ctx);
-    if (K == 64) HIP_TRY(ctx, upload_quarter(64, ctx->q64_hi, ctx->q64_lo, ctx->q64_f32));
+    if (K == 64) {
+        HIP_TRY(ctx, upload_quarter(64, ctx->q64_hi, ctx->q64_lo, ctx->q64_f32));
+        HIP_TRY(ctx, upload_quarter_stats(64, ctx->qstat[0]));
+    }
     if (K >= 16) HIP_TRY(ctx, upload(std::sqrt(3.0), ctx->phi3_hi[ki], ctx->phi3_lo[ki], ctx->phi3_f32[ki]));
     HIP_TRY(ctx, upload(1.0, ctx->phi_hi[ki], ctx->phi_lo[ki], ctx->phi_f32[ki]));
     return TKDV_OK;
@@ -533,7 +539,7 @@ tkdv_status launch_sequence(tkdv_ctx *ctx, const CallView &v, const Workspace &w
         HIP_TRY(ctx, hipEventRecord(ctx->ev[3], st));
         for (int ki = 0; ki < kNumK; ++ki) {
             if (v.plist_n[ki] == 0) continue;
-            a.phi_hi = ki == 4 ? ctx->phi_mat128.p : ctx->phi_f32[ki].p;
+            a.phi_hi = ki >= 3 ? ctx->qstat[ki - 3].p : ctx->phi_f32[ki].p;
             HIP_TRY(ctx, launch_materialize(8 << ki, proposal, a, d_plist + v.plist_off[ki], v.plist_n[ki],
                                             v.total_segs, w.seg_cnt, w.seg_base, w.seg_stats, w.results, d_xhat,
                                             d_index, ctx->n_cu, st));
@@ -631,6 +637,20 @@ float key_to_float(unsigned int k)
     return f;
 }
 
+// The extremes against 4 sigma: the peak from its u~ key, u = sqrt(2 E0/pi) u~.
+void fill_extremes(tkdv_stats &s, const DevPoint &P, const PointResult &r)
+{
+    s.n_exceed_4sigma = r.n_exceed4;
+    s.n_samples_4sigma = r.n_max4;
+    if (r.peak_key) {
+        s.peak_u = std::sqrt(2.0 * P.E0 / kPi) * (double)key_to_float(r.peak_key);
+        s.peak_index = r.peak_index;
+    } else {
+        s.peak_u = -INFINITY;
+        s.peak_index = UINT64_MAX;
+    }
+}
+
 void fill_stats(tkdv_stats &s, const DevPoint &P, const PointResult &r, const DevCounters &c, int mode)
 {
     std::memset(&s, 0, sizeof(s));
@@ -662,6 +682,7 @@ void fill_stats(tkdv_stats &s, const DevPoint &P, const PointResult &r, const De
     s.hist_hi = umax;
     for (int b = 0; b < TKDV_NBINS; ++b) s.hist_u0[b] = r.hist[b];
     s.log_M_used = P.log_M64;
+    fill_extremes(s, P, r);
 }
 
 tkdv_status prepare(tkdv_ctx *ctx, Call &call, int n_points, const tkdv_point *pts, int proposal,
@@ -783,6 +804,7 @@ void fill_stats_sweep(tkdv_stats &s, const DevPoint &P, const SweepState &w)
     s.hist_hi = umax;
     for (int b = 0; b < TKDV_NBINS; ++b) s.hist_u0[b] = w.total.hist[b];
     s.log_M_used = P.log_M64;
+    fill_extremes(s, P, w.total);
 }
 
 int prec_index(int precision) { return precision < 0 || precision > 2 ? 0 : precision; }
@@ -948,7 +970,7 @@ tkdv_status sweep(tkdv_ctx *ctx, int np, const tkdv_point *pts, const tkdv_plan 
         HIP_TRY(ctx, launch_segments(a, max_segs, seg_cnt, seg_base, res, ctx->n_cu, sst));
         for (int ki = 0; ki < kNumK; ++ki) {
             if (call.plist_n[ki] == 0) continue;
-            a.phi_hi = ki == 4 ? ctx->phi_mat128.p : ctx->phi_f32[ki].p;
+            a.phi_hi = ki >= 3 ? ctx->qstat[ki - 3].p : ctx->phi_f32[ki].p;
             HIP_TRY(ctx, launch_materialize(8 << ki, TKDV_PROP_SIGMA, a, d_plist + call.plist_off[ki],
                                             call.plist_n[ki], max_segs, seg_cnt, seg_base, seg_stats, res, d_xhat,
                                             reinterpret_cast<unsigned long long *>(d_index), ctx->n_cu, sst));
@@ -1215,7 +1237,8 @@ tkdv_status tkdv_destroy(tkdv_ctx *ctx)
                       &ctx->ext_list, &ctx->sir_pt, &ctx->sir_w, &ctx->sir_tile, &ctx->sir_chunk, &ctx->sir_part};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
-    if (ctx->phi_mat128.p) (void)hipFree(ctx->phi_mat128.p);
+    for (DevBuf *b : {&ctx->qstat[0], &ctx->qstat[1]})
+        if (b->p) (void)hipFree(b->p);
     for (DevBuf *b : {&ctx->q64_hi, &ctx->q64_lo, &ctx->q64_f32})
         if (b->p) (void)hipFree(b->p);
     for (int i = 0; i < kNumK; ++i) {

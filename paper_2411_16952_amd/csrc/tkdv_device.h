@@ -482,6 +482,32 @@ __device__ __forceinline__ unsigned int float_key(float f)
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
+// Thresholds of the statistics in units of u~ = u / sqrt(2 E0/pi): 2 sigma and
+// 4 sigma, sigma = sqrt(E0/pi), are u~ = sqrt 2 and 2 sqrt 2.
+constexpr float kTwoSigmaT = 1.41421356237309515f;
+constexpr float kFourSigmaT = 2.82842712474619031f;
+
+// The better of two peaks (float_key of the value, proposal index): the larger
+// value, the lower index among equal values; key 0 stands for none.
+__device__ __forceinline__ void peak_merge(unsigned int &key, unsigned long long &idx, unsigned int k2,
+                                           unsigned long long i2)
+{
+    if (k2 > key || (k2 == key && k2 != 0u && i2 < idx)) {
+        key = k2;
+        idx = i2;
+    }
+}
+// The peak of the wave, in every lane (the merge is a total order).
+__device__ __forceinline__ void wave_peak(unsigned int &key, unsigned long long &idx)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned int k2 = __shfl_xor(key, o, 64);
+        const unsigned long long i2 = __shfl_xor(idx, o, 64);
+        peak_merge(key, idx, k2, i2);
+    }
+}
+
 __device__ __forceinline__ unsigned long long pack_defer(int p, uint64_t i)
 {
     return ((unsigned long long)p << 40) | (unsigned long long)i;

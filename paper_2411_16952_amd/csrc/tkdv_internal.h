@@ -119,12 +119,19 @@ struct SegStats {
     double S1, S2, S3, S4;
     unsigned long long n_exceed;
     unsigned long long n_samples;
+    unsigned long long n_exceed4;   // grid values above 4 sigma
+    unsigned long long n_max4;      // samples whose largest grid value is above 4 sigma
+    unsigned long long peak_index;  // proposal index of the sample with the largest grid value
+    unsigned int peak_key;          // float_key of that value of u~ (0: no sample)
+    unsigned int pad;
 };
 
 // Per-point result of the finalisation kernel.
 struct PointResult {
     double S1, S2, S3, S4;
     unsigned long long n_exceed;
+    unsigned long long n_exceed4, n_max4, peak_index;  // as in SegStats
+    unsigned int peak_key, pad;
     unsigned long long n_samples;      // accepted samples covered by the statistics
     unsigned long long n_accepted;     // all accepted in the processed range
     unsigned long long n_written;

@@ -46,10 +46,12 @@ int decide128_block();
 int decide128_max_blocks_per_cu(int prec);
 int decide_quarter64_max_blocks_per_cu(int prec);
 size_t quarter_table_bytes(int K, int prec);
-hipError_t launch_materialize128(int prop, const KernelArgs &a, unsigned long long total_segs,
-                                 const unsigned long long *seg_cnt, const unsigned long long *seg_base,
-                                 SegStats *seg_stats, PointResult *res, float *out_xhat,
-                                 unsigned long long *out_index, int n_cu, hipStream_t st);
+// The ordered output and statistics at K = 64 and 128 (quarter-period form on
+// the statistics grid; a.phi_hi: the table of upload_quarter_stats).
+hipError_t launch_materialize_quarter(int K, int prop, const KernelArgs &a, unsigned long long total_segs,
+                                     const unsigned long long *seg_cnt, const unsigned long long *seg_base,
+                                     SegStats *seg_stats, PointResult *res, float *out_xhat,
+                                     unsigned long long *out_index, int n_cu, hipStream_t st);
 hipError_t launch_window_advance(DevPoint *pts, const DevCounters *cnt, const PointResult *res, SweepState *sw,
                                  int n_points, SweepGlobal *G, const unsigned long long *defer_count, hipStream_t st);
 hipError_t launch_fill_u32(void *p, unsigned long long n_words, uint32_t v, hipStream_t st);

@@ -732,6 +732,7 @@ __global__ void __launch_bounds__(1024) k_seg_scan(KernelArgs a, const unsigned 
 // ---------------------------------------------------------------------------
 constexpr int kWaveWords = kSegWords / (kBlock / kWave);  // 512 words per wave
 constexpr int kGroupWords = kWave;                         // one word per lane per group
+constexpr int kQueue = kGroupWords * 32 + kTile;           // one group's offsets + a partial chunk
 
 template <int K>
 __host__ __device__ constexpr int materialize_tab_bytes()
@@ -742,7 +743,7 @@ __host__ __device__ constexpr int materialize_tab_bytes()
 template <int K>
 __host__ __device__ constexpr int materialize_lds_bytes()
 {
-    return materialize_tab_bytes<K>() + (kBlock / kWave) * kGroupWords * 32 * 2 + 1024;
+    return materialize_tab_bytes<K>() + (kBlock / kWave) * kQueue * 2 + 1024;
 }
 
 template <int K, int PROP>
@@ -756,17 +757,19 @@ __global__ void __launch_bounds__(kBlock) k_materialize(KernelArgs a, const int 
     extern __shared__ __attribute__((aligned(16))) char lds[];
     constexpr int tab = materialize_tab_bytes<K>();
     uint16_t *lists = reinterpret_cast<uint16_t *>(lds + tab);
-    unsigned int *hist = reinterpret_cast<unsigned int *>(lds + tab + (kBlock / kWave) * kGroupWords * 32 * 2);
+    unsigned int *hist = reinterpret_cast<unsigned int *>(lds + tab + (kBlock / kWave) * kQueue * 2);
     __shared__ unsigned long long wave_cnt[kBlock / kWave];
     __shared__ double wave_S[kBlock / kWave][4];
-    __shared__ unsigned long long wave_ex[kBlock / kWave];
+    __shared__ unsigned long long wave_ex[kBlock / kWave][3];
+    __shared__ unsigned long long wave_peak_idx[kBlock / kWave];
+    __shared__ unsigned int wave_peak_key[kBlock / kWave];
     {
         const uint4 *s0 = reinterpret_cast<const uint4 *>(a.phi_hi);
         uint4 *d = reinterpret_cast<uint4 *>(lds);
         for (int v = threadIdx.x; v < tab / 16; v += kBlock) d[v] = s0[v];
     }
     const int lane = threadIdx.x & 63, half = lane >> 5, pl = lane & 31, wv = threadIdx.x >> 6;
-    uint16_t *mylist = lists + wv * (kGroupWords * 32);
+    uint16_t *mylist = lists + wv * kQueue;
     if (a.d_total_segs) total_segs = *a.d_total_segs;
     __syncthreads();
     for (unsigned long long gs = blockIdx.x; gs < total_segs; gs += gridDim.x) {
@@ -791,7 +794,11 @@ __global__ void __launch_bounds__(kBlock) k_materialize(KernelArgs a, const int 
         unsigned long long rank = seg_base[gs];
         for (int w = 0; w < wv; ++w) rank += wave_cnt[w];
         double S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0;
-        unsigned long long n_ex = 0;
+        unsigned long long n_ex = 0, n_ex4 = 0, n_max4 = 0, peak_idx = ~0ull;
+        unsigned int peak_key = 0u;
+        // accepted offsets (proposals from the wave's first word) queue up in
+        // index order; full chunks are regenerated, the last group flushes
+        int queued = 0;
         for (int g = 0; g < kWaveWords / kGroupWords; ++g) {
             const unsigned long long w = w_first + (unsigned long long)g * kGroupWords + lane;
             const uint32_t word = w < nw ? a.bitmap[P.bm_off + w] : 0u;
@@ -804,22 +811,23 @@ __global__ void __launch_bounds__(kBlock) k_materialize(KernelArgs a, const int 
                 if (lane >= o) incl += up;
             }
             const int total = __shfl(incl, 63, 64);
-            if (total == 0) continue;
-            int pos = incl - cntw;
+            int pos = queued + incl - cntw;
             uint32_t m = word;
             while (m) {
                 const int bit = __ffs(m) - 1;
                 m &= m - 1;
-                mylist[pos++] = (uint16_t)(lane * 32 + bit);
+                mylist[pos++] = (uint16_t)((g * kGroupWords + lane) * 32 + bit);
             }
+            queued += total;
+            const int upto = g + 1 == kWaveWords / kGroupWords ? queued : queued & ~(kTile - 1);
+            if (upto == 0) continue;
             // the list is written and read by lanes of this wave only
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            for (int c0 = 0; c0 < total; c0 += kTile) {
-                const bool in_chunk = c0 + pl < total;
+            for (int c0 = 0; c0 < upto; c0 += kTile) {
+                const bool in_chunk = c0 + pl < upto;
                 const int off = in_chunk ? (int)mylist[c0 + pl] : 0;
-                const unsigned long long local =
-                    (w_first + (unsigned long long)g * kGroupWords) * kTile + (unsigned long long)off;
+                const unsigned long long local = w_first * kTile + (unsigned long long)off;
                 const uint64_t i = P.i0 + local;
                 const unsigned long long r = rank + c0 + pl;
                 const bool valid = in_chunk && r < limit;
@@ -847,6 +855,7 @@ __global__ void __launch_bounds__(kBlock) k_materialize(KernelArgs a, const int 
                 // statistics on the grid: u = sqrt(2 E0/pi) u~, u~ from FP32 products
                 // (K >= 16: the half-period form, u~ = E + O and E - O on the two halves)
                 const float4 *ftab = reinterpret_cast<const float4 *>(lds);
+                float umax = -INFINITY;  // the largest of this lane's grid values of the proposal
                 auto fold = [&](float uf) {
                     const double u = P.amp * (double)uf;
                     const double u2 = u * u;
@@ -854,7 +863,9 @@ __global__ void __launch_bounds__(kBlock) k_materialize(KernelArgs a, const int 
                     S2 += u2;
                     S3 += u2 * u;
                     S4 += u2 * u2;
-                    n_ex += uf > 1.41421356237309515f ? 1ull : 0ull;  // u > 2 sqrt(E0/pi)
+                    n_ex += uf > kTwoSigmaT ? 1ull : 0ull;    // u > 2 sqrt(E0/pi)
+                    n_ex4 += uf > kFourSigmaT ? 1ull : 0ull;  // u > 4 sqrt(E0/pi)
+                    umax = fmaxf(umax, uf);
                 };
                 if constexpr (K >= 16) {
 #pragma unroll
@@ -895,6 +906,12 @@ __global__ void __launch_bounds__(kBlock) k_materialize(KernelArgs a, const int 
                         }
                     }
                 }
+                // the proposal's grid values are split over lanes l and l + 32
+                umax = fmaxf(umax, __shfl_xor(umax, 32, 64));
+                if (valid && half == 0) {
+                    n_max4 += umax > kFourSigmaT ? 1ull : 0ull;
+                    peak_merge(peak_key, peak_idx, float_key(umax), i);
+                }
                 if (valid && half == 0) {
                     // u(0) = sqrt(2 E0/pi) sum_k x^_k; bin of u(0)/u_max = sum_k x^_k / sqrt(K)
                     double s0 = 0.0;
@@ -906,7 +923,14 @@ __global__ void __launch_bounds__(kBlock) k_materialize(KernelArgs a, const int 
                     atomicAdd(&hist[bin], 1u);
                 }
             }
-            rank += total;
+            rank += upto;
+            // the partial chunk left moves to the front of the queue
+            const int left = queued - upto;
+            const uint16_t keep = lane < left ? mylist[upto + lane] : (uint16_t)0;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (lane < left) mylist[lane] = keep;
+            queued = left;
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
@@ -915,22 +939,32 @@ __global__ void __launch_bounds__(kBlock) k_materialize(KernelArgs a, const int 
         S3 = wave_sum_f64(S3);
         S4 = wave_sum_f64(S4);
         n_ex = wave_sum_u64(n_ex);
+        n_ex4 = wave_sum_u64(n_ex4);
+        n_max4 = wave_sum_u64(n_max4);
+        wave_peak(peak_key, peak_idx);
         if (lane == 0) {
             wave_S[wv][0] = S1;
             wave_S[wv][1] = S2;
             wave_S[wv][2] = S3;
             wave_S[wv][3] = S4;
-            wave_ex[wv] = n_ex;
+            wave_ex[wv][0] = n_ex;
+            wave_ex[wv][1] = n_ex4;
+            wave_ex[wv][2] = n_max4;
+            wave_peak_key[wv] = peak_key;
+            wave_peak_idx[wv] = peak_idx;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            SegStats st = {0.0, 0.0, 0.0, 0.0, 0ull, 0ull};
+            SegStats st = {0.0, 0.0, 0.0, 0.0, 0ull, 0ull, 0ull, 0ull, ~0ull, 0u, 0u};
             for (int w = 0; w < kBlock / kWave; ++w) {
                 st.S1 += wave_S[w][0];
                 st.S2 += wave_S[w][1];
                 st.S3 += wave_S[w][2];
                 st.S4 += wave_S[w][3];
-                st.n_exceed += wave_ex[w];
+                st.n_exceed += wave_ex[w][0];
+                st.n_exceed4 += wave_ex[w][1];
+                st.n_max4 += wave_ex[w][2];
+                peak_merge(st.peak_key, st.peak_index, wave_peak_key[w], wave_peak_idx[w]);
             }
             const unsigned long long sb = seg_base[gs];
             const unsigned long long se = sb + seg_cnt[gs];
@@ -952,13 +986,15 @@ __global__ void __launch_bounds__(kBlock) k_finalize(KernelArgs a, const unsigne
                                                      const SegStats *seg_stats, PointResult *res)
 {
     __shared__ double sS[4][kBlock];
-    __shared__ unsigned long long sE[kBlock], sN[kBlock];
+    __shared__ unsigned long long sE[3][kBlock], sN[kBlock], sPI[kBlock];
+    __shared__ unsigned int sPK[kBlock];
     const int p = blockIdx.x, tid = threadIdx.x;
     const DevPoint &P = a.pts[p];
     const unsigned long long per = (P.n_segs + kBlock - 1) / kBlock;
     const unsigned long long s0 = per * tid, s1 = s0 + per < P.n_segs ? s0 + per : P.n_segs;
     double S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0;
-    unsigned long long ex = 0, ns = 0;
+    unsigned long long ex = 0, ex4 = 0, mx4 = 0, ns = 0, pi = ~0ull;
+    unsigned int pk = 0u;
     for (unsigned long long s = s0; s < s1; ++s) {
         const unsigned long long gs = P.seg_off + s;
         if (seg_cnt[gs] == 0 || seg_base[gs] >= P.target) continue;
@@ -968,20 +1004,32 @@ __global__ void __launch_bounds__(kBlock) k_finalize(KernelArgs a, const unsigne
         S3 += st.S3;
         S4 += st.S4;
         ex += st.n_exceed;
+        ex4 += st.n_exceed4;
+        mx4 += st.n_max4;
         ns += st.n_samples;
+        peak_merge(pk, pi, st.peak_key, st.peak_index);
     }
     sS[0][tid] = S1;
     sS[1][tid] = S2;
     sS[2][tid] = S3;
     sS[3][tid] = S4;
-    sE[tid] = ex;
+    sE[0][tid] = ex;
+    sE[1][tid] = ex4;
+    sE[2][tid] = mx4;
     sN[tid] = ns;
+    sPK[tid] = pk;
+    sPI[tid] = pi;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
         if (tid < w) {
             for (int q = 0; q < 4; ++q) sS[q][tid] += sS[q][tid + w];
-            sE[tid] += sE[tid + w];
+            for (int q = 0; q < 3; ++q) sE[q][tid] += sE[q][tid + w];
             sN[tid] += sN[tid + w];
+            unsigned int k0 = sPK[tid];
+            unsigned long long i0 = sPI[tid];
+            peak_merge(k0, i0, sPK[tid + w], sPI[tid + w]);
+            sPK[tid] = k0;
+            sPI[tid] = i0;
         }
         __syncthreads();
     }
@@ -990,7 +1038,11 @@ __global__ void __launch_bounds__(kBlock) k_finalize(KernelArgs a, const unsigne
         res[p].S2 = sS[1][0];
         res[p].S3 = sS[2][0];
         res[p].S4 = sS[3][0];
-        res[p].n_exceed = sE[0];
+        res[p].n_exceed = sE[0][0];
+        res[p].n_exceed4 = sE[1][0];
+        res[p].n_max4 = sE[2][0];
+        res[p].peak_key = sPK[0];
+        res[p].peak_index = sPI[0];
         res[p].n_samples = sN[0];
         res[p].n_written = sN[0] < P.capacity ? sN[0] : P.capacity;
     }
@@ -1030,6 +1082,13 @@ __global__ void __launch_bounds__(1024) k_window_advance(DevPoint *pts, const De
         S.total.S3 += r.S3;
         S.total.S4 += r.S4;
         S.total.n_exceed += r.n_exceed;
+        S.total.n_exceed4 += r.n_exceed4;
+        S.total.n_max4 += r.n_max4;
+        // windows come in increasing index: a later one replaces the peak only when larger
+        if (r.peak_key > S.total.peak_key) {
+            S.total.peak_key = r.peak_key;
+            S.total.peak_index = r.peak_index;
+        }
         for (int b = 0; b < kNBins; ++b) S.total.hist[b] += r.hist[b];
         S.accepted += r.n_samples;
         S.written += r.n_written;
@@ -1375,9 +1434,9 @@ hipError_t launch_materialize(int K, int prop, const KernelArgs &a, const int *p
                               const unsigned long long *seg_base, SegStats *seg_stats, PointResult *res,
                               float *out_xhat, unsigned long long *out_index, int n_cu, hipStream_t st)
 {
-    if (K == 128)
-        return launch_materialize128(prop, a, total_segs, seg_cnt, seg_base, seg_stats, res, out_xhat, out_index,
-                                     n_cu, st);
+    if (K == 64 || K == 128)
+        return launch_materialize_quarter(K, prop, a, total_segs, seg_cnt, seg_base, seg_stats, res, out_xhat,
+                                          out_index, n_cu, st);
 #define TKDV_DISPATCH_M(KK, PP)                                                                          \
     if (K == KK && prop == PP)                                                                           \
         return launch_materialize_t<KK, PP>(a, plist, n_plist, total_segs, seg_cnt, seg_base, seg_stats, \
@@ -1388,8 +1447,6 @@ hipError_t launch_materialize(int K, int prop, const KernelArgs &a, const int *p
     TKDV_DISPATCH_M(16, PROP_SIGMA)
     TKDV_DISPATCH_M(32, PROP_UNIFORM)
     TKDV_DISPATCH_M(32, PROP_SIGMA)
-    TKDV_DISPATCH_M(64, PROP_UNIFORM)
-    TKDV_DISPATCH_M(64, PROP_SIGMA)
     TKDV_DISPATCH_M(8, PROP_MIXTURE)
     TKDV_DISPATCH_M(16, PROP_MIXTURE)
     TKDV_DISPATCH_M(32, PROP_MIXTURE)

@@ -1,6 +1,6 @@
-// Quarter-period kernels of the TKdV rejection sampler: the decision kernel
-// at K = 128 (N = 512) and, as a tile variant, at K = 64; the ordered output
-// with statistics at K = 128.
+// Quarter-period kernels of the TKdV rejection sampler at K = 64 and 128
+// (N = 256, 512): the decision kernel, and the ordered output with the
+// statistics.
 //
 // Layout.  One wavefront evaluates a tile of 16 proposals; proposal p of the
 // tile lives in lanes p + 16 g, g = 0..3, and lane group g holds the cos and
@@ -409,33 +409,56 @@ __global__ void __launch_bounds__(Quarter<K>::BLOCK) k_decide128(KernelArgs a, c
 }
 
 // ---------------------------------------------------------------------------
-// k_materialize128: one block per 65536-proposal segment, one wave per quarter
-// segment, as k_materialize; accepted proposals in chunks of 16, regenerated
-// with the decision kernel's arithmetic, written at their rank, and the grid
-// statistics from the FP32 16x16x4 matrix synthesis on the N = 512 grid
-// xi_j = -pi + 2 pi j/N (table in device memory: tile T of 16 grid points,
-// k-step m of 64 -- lane group g's coordinate m: cos of mode 32 g + m + 1 for
-// m < 32, sin of mode 32 g + m - 31 otherwise).
+// k_materialize_q: the ordered output and the statistics at K = 64 and 128.
+// One workgroup per 65536-proposal segment, its W waves taking equal runs of
+// its accept words in groups of 32; accepted proposals in chunks of 16 (the
+// decision kernel's layout), regenerated with the decision kernel's
+// arithmetic and written at their rank.  The grid values come from the
+// quarter-period form on the statistics grid xi_j = -pi + 2 pi j/N itself:
+// representatives xi_rho = 2 pi rho/N, rho < K (FP32 16x16x4 products, table
+// in LDS, entries unscaled), each giving u at xi, -xi, pi - xi and xi - pi
+// from Ce, Co, Se, So; rho = 0 has only the two points 0 and pi, and the
+// points +-pi/2 (rho = K) come from direct sums: cos(k pi/2) and sin(k pi/2)
+// are 0 or +-1.  Each wave queues its accepted offsets in LDS, in index order,
+// and regenerates full chunks only (the last group flushes the rest): at an
+// acceptance of 1e-3 a group of 32 words holds one accepted proposal.
 // ---------------------------------------------------------------------------
-constexpr int kWaveWords128 = kSegWords / (kBlock / kWave);  // 512 words per wave
-constexpr int kGroupWords128 = kWave;                         // one word per lane per group
+template <int K>
+struct MatQ {
+    static constexpr int W = K == 128 ? 8 : 4;       // waves per workgroup
+    static constexpr int WAVE_WORDS = kSegWords / W; // accept words per wave
+    static constexpr int GROUP = 32;                 // words per group (lanes 0..31)
+    static constexpr int QUEUE = GROUP * 32 + 16;    // one group's offsets + a partial chunk
+    static constexpr int LIST_BYTES = W * QUEUE * 2;
+    static constexpr int LDS = Quarter<K>::F32_BYTES + LIST_BYTES;
+};
 
-template <int PROP>
-__global__ void __launch_bounds__(kBlock) k_materialize128(KernelArgs a, unsigned long long total_segs,
-                                                           const unsigned long long *seg_cnt,
-                                                           const unsigned long long *seg_base,
-                                                           SegStats *seg_stats, PointResult *res,
-                                                           float *out_xhat, unsigned long long *out_index)
+template <int K, int PROP>
+__global__ void __launch_bounds__(MatQ<K>::W * kWave) k_materialize_q(KernelArgs a, unsigned long long total_segs,
+                                                                      const unsigned long long *seg_cnt,
+                                                                      const unsigned long long *seg_base,
+                                                                      SegStats *seg_stats, PointResult *res,
+                                                                      float *out_xhat, unsigned long long *out_index)
 {
-    __shared__ uint16_t lists[kBlock / kWave][kGroupWords128 * 32];
+    constexpr int W = MatQ<K>::W, B = W * kWave, CPL = K / 4, QG = Quarter<K>::QG;
+    constexpr int WW = MatQ<K>::WAVE_WORDS, GW = MatQ<K>::GROUP;
+    extern __shared__ __attribute__((aligned(16))) char lds[];
     __shared__ unsigned int hist[kNBins];
-    __shared__ unsigned long long wave_cnt[kBlock / kWave];
-    __shared__ double wave_S[kBlock / kWave][4];
-    __shared__ unsigned long long wave_ex[kBlock / kWave];
-    const float4 *ftab = reinterpret_cast<const float4 *>(a.phi_hi);
+    __shared__ unsigned long long wave_cnt[W];
+    __shared__ double wave_S[W][4];
+    __shared__ unsigned long long wave_ex[W][3];
+    __shared__ unsigned long long wave_peak_idx[W];
+    __shared__ unsigned int wave_peak_key[W];
+    {
+        const uint4 *s0 = reinterpret_cast<const uint4 *>(a.phi_hi);
+        uint4 *d = reinterpret_cast<uint4 *>(lds);
+        for (int v = threadIdx.x; v < Quarter<K>::F32_BYTES / 16; v += B) d[v] = s0[v];
+    }
+    const float4 *tab = reinterpret_cast<const float4 *>(lds);
     const int lane = threadIdx.x & 63, g = lane >> 4, pl = lane & 15, wv = threadIdx.x >> 6;
-    uint16_t *mylist = lists[wv];
+    uint16_t *mylist = reinterpret_cast<uint16_t *>(lds + Quarter<K>::F32_BYTES) + wv * MatQ<K>::QUEUE;
     if (a.d_total_segs) total_segs = *a.d_total_segs;
+    __syncthreads();
     for (unsigned long long gs = blockIdx.x; gs < total_segs; gs += gridDim.x) {
         int lo = 0, hi = a.n_points - 1;
         while (lo < hi) {  // last point whose first segment is <= gs
@@ -444,15 +467,14 @@ __global__ void __launch_bounds__(kBlock) k_materialize128(KernelArgs a, unsigne
         }
         const int p = lo;
         const DevPoint &P = a.pts[p];
-        const unsigned long long limit = P.target;
-        if (P.K != K128 || P.proposal != PROP || seg_cnt[gs] == 0 || seg_base[gs] >= limit) continue;
-        for (int b = threadIdx.x; b < kNBins; b += kBlock) hist[b] = 0u;
+        const unsigned long long limit = P.target;  // ranks >= target are not part of the result
+        if (P.K != K || P.proposal != PROP || seg_cnt[gs] == 0 || seg_base[gs] >= limit) continue;  // uniform
+        for (int b = threadIdx.x; b < kNBins; b += B) hist[b] = 0u;
         const unsigned long long nt = a.cnt[p].next_tile;
         const unsigned long long nw = nt < P.n_tiles ? nt : P.n_tiles;
-        const unsigned long long seg_w0 = (gs - P.seg_off) * kSegWords;
-        const unsigned long long w_first = seg_w0 + (unsigned long long)wv * kWaveWords128;
+        const unsigned long long w_first = (gs - P.seg_off) * kSegWords + (unsigned long long)wv * WW;
         unsigned long long cw = 0;
-        for (int k = lane; k < kWaveWords128; k += kWave) {
+        for (int k = lane; k < WW; k += kWave) {
             const unsigned long long w = w_first + k;
             if (w < nw) cw += __popc(a.bitmap[P.bm_off + w]);
         }
@@ -462,10 +484,12 @@ __global__ void __launch_bounds__(kBlock) k_materialize128(KernelArgs a, unsigne
         unsigned long long rank = seg_base[gs];
         for (int w = 0; w < wv; ++w) rank += wave_cnt[w];
         double S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0;
-        unsigned long long n_ex = 0;
-        for (int grp = 0; grp < kWaveWords128 / kGroupWords128; ++grp) {
-            const unsigned long long w = w_first + (unsigned long long)grp * kGroupWords128 + lane;
-            const uint32_t word = w < nw ? a.bitmap[P.bm_off + w] : 0u;
+        unsigned long long n_ex = 0, n_ex4 = 0, n_max4 = 0, peak_idx = ~0ull;
+        unsigned int peak_key = 0u;
+        int queued = 0;  // offsets (proposals from the wave's first word) waiting in mylist
+        for (int grp = 0; grp < WW / GW; ++grp) {
+            const unsigned long long w = w_first + (unsigned long long)grp * GW + lane;
+            const uint32_t word = (lane < GW && w < nw) ? a.bitmap[P.bm_off + w] : 0u;
             const int cntw = __popc(word);
             int incl = cntw;
 #pragma unroll
@@ -474,81 +498,123 @@ __global__ void __launch_bounds__(kBlock) k_materialize128(KernelArgs a, unsigne
                 if (lane >= o) incl += up;
             }
             const int total = __shfl(incl, 63, 64);
-            if (total == 0) continue;
-            int pos = incl - cntw;
+            int pos = queued + incl - cntw;
             uint32_t m = word;
             while (m) {
                 const int bit = __ffs(m) - 1;
                 m &= m - 1;
-                mylist[pos++] = (uint16_t)(lane * 32 + bit);
+                mylist[pos++] = (uint16_t)((grp * GW + lane) * 32 + bit);
             }
+            queued += total;
+            const int upto = grp + 1 == WW / GW ? queued : queued & ~(kTile16 - 1);
+            if (upto == 0) continue;
+            // the list is written and read by lanes of this wave only
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            for (int c0 = 0; c0 < total; c0 += kTile16) {
-                const bool in_chunk = c0 + pl < total;
+            for (int c0 = 0; c0 < upto; c0 += kTile16) {
+                const bool in_chunk = c0 + pl < upto;
                 const int off = in_chunk ? (int)mylist[c0 + pl] : 0;
-                const unsigned long long local =
-                    (w_first + (unsigned long long)grp * kGroupWords128) * kTile + (unsigned long long)off;
+                const unsigned long long local = w_first * kTile + (unsigned long long)off;
                 const uint64_t i = P.i0 + local;
                 const unsigned long long r = rank + c0 + pl;
                 const bool valid = in_chunk && r < limit;
-                float c[32], s[32];
-                float t;
+                float c[CPL], s[CPL], t;
                 uint32_t w_acc;
-                gen_x128<K128, PROP, true>(P, i, g, c, s, t, w_acc);
+                gen_x128<K, PROP, true>(P, i, g, c, s, t, w_acc);
                 if (valid && r < P.capacity) {
                     if (out_xhat) {
                         float *row = out_xhat + (P.out_off + r) * P.row_stride;
 #pragma unroll
-                        for (int j = 0; j < 32; ++j) {
-                            row[32 * g + j] = c[j];
-                            row[K128 + 32 * g + j] = s[j];
+                        for (int j = 0; j < CPL; ++j) {
+                            row[CPL * g + j] = c[j];
+                            row[K + CPL * g + j] = s[j];
                         }
                     }
                     if (out_index && g == 0) out_index[P.out_off + r] = i;
                 }
                 if (valid && g == 0 && r + 1 == limit) a.cnt[p].last_index = i;
-                // u~ on the grid, 32 tiles of 16 points, 64 k-steps of the four lane groups
+                float umax = -INFINITY;  // the largest of this lane's grid values of the proposal
+                auto fold = [&](float uf) {
+                    const double u = P.amp * (double)uf;
+                    const double u2 = u * u;
+                    S1 += u;
+                    S2 += u2;
+                    S3 += u2 * u;
+                    S4 += u2 * u2;
+                    n_ex += uf > kTwoSigmaT ? 1ull : 0ull;    // u > 2 sqrt(E0/pi)
+                    n_ex4 += uf > kFourSigmaT ? 1ull : 0ull;  // u > 4 sqrt(E0/pi)
+                    umax = fmaxf(umax, uf);
+                };
 #pragma unroll 1
-                for (int T = 0; T < 32; ++T) {
-                    f32x4 acc = {};
+                for (int tau = 0; tau < Quarter<K>::TILES; ++tau) {
+                    f32x4 acc[4] = {f32x4{}, f32x4{}, f32x4{}, f32x4{}};
 #pragma unroll
-                    for (int m4 = 0; m4 < 16; ++m4) {
-                        const float4 av = ftab[(T * 16 + m4) * 64 + lane];
-                        const float *v = m4 < 8 ? c : s;
-                        const int j0 = 4 * (m4 & 7);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, v[j0 + 0], acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, v[j0 + 1], acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, v[j0 + 2], acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, v[j0 + 3], acc, 0, 0, 0);
-                    }
+                    for (int q4 = 0; q4 < QG; ++q4)
+#pragma unroll
+                        for (int o = 0; o < 4; ++o) {
+                            // out o: 0 Ce, 1 Co, 2 Se, 3 So; coordinate 2 idx + 1 (even mode) or 2 idx (odd)
+                            const float4 av = tab[((tau * 4 + o) * QG + q4) * 64 + lane];
+                            const float *v = (o < 2) ? c : s;
+                            const int par = (o == 0 || o == 2) ? 1 : 0;
+                            acc[o] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, v[2 * (4 * q4 + 0) + par], acc[o], 0, 0, 0);
+                            acc[o] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, v[2 * (4 * q4 + 1) + par], acc[o], 0, 0, 0);
+                            acc[o] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, v[2 * (4 * q4 + 2) + par], acc[o], 0, 0, 0);
+                            acc[o] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, v[2 * (4 * q4 + 3) + par], acc[o], 0, 0, 0);
+                        }
                     if (valid) {
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const double u = P.amp * (double)acc[v];
-                            const double u2 = u * u;
-                            S1 += u;
-                            S2 += u2;
-                            S3 += u2 * u;
-                            S4 += u2 * u2;
-                            n_ex += acc[v] > 1.41421356237309515f ? 1ull : 0ull;  // u > 2 sqrt(E0/pi)
+                        for (int v = 0; v < 4; ++v) {  // representative rho = 16 tau + 4 g + v
+                            const float pe = acc[0][v] + acc[1][v], me = acc[0][v] - acc[1][v];
+                            const float ps = acc[2][v] + acc[3][v], ms = acc[2][v] - acc[3][v];
+                            fold(pe + ps);  // xi
+                            fold(me + ms);  // xi - pi
+                            if (tau != 0 || v != 0 || g != 0) {  // rho = 0: xi = 0 and pi only
+                                fold(pe - ps);  // -xi
+                                fold(me - ms);  // pi - xi
+                            }
                         }
                     }
                 }
+                // xi = +-pi/2: A = sum_k a_k cos(k pi/2), B = sum_k b_k sin(k pi/2); mode
+                // K g/4 + j + 1 is j + 1 modulo 4
+                float Av = 0.0f, Bv = 0.0f;
+#pragma unroll
+                for (int j = 0; j < CPL; j += 4) {
+                    Av += c[j + 3] - c[j + 1];
+                    Bv += s[j] - s[j + 2];
+                }
+                Av = sum4(Av);
+                Bv = sum4(Bv);
+                if (valid && g == 0) {
+                    fold(Av + Bv);
+                    fold(Av - Bv);
+                }
+                // the proposal's grid values are split over lanes l, l ^ 16, l ^ 32, l ^ 48
+                umax = fmaxf(umax, __shfl_xor(umax, 16, 64));
+                umax = fmaxf(umax, __shfl_xor(umax, 32, 64));
                 // u(0) = sqrt(2 E0/pi) sum_k x^_k; bin of u(0)/u_max = sum_k x^_k / sqrt(K)
                 double s0 = 0.0;
 #pragma unroll
-                for (int j = 0; j < 32; ++j) s0 += (double)c[j];
+                for (int j = 0; j < CPL; ++j) s0 += (double)c[j];
                 s0 += __shfl_xor(s0, 16, 64);
                 s0 += __shfl_xor(s0, 32, 64);
                 if (valid && g == 0) {
-                    double posb = (s0 / sqrt((double)K128) + 1.0) * (0.5 * kNBins);
+                    n_max4 += umax > kFourSigmaT ? 1ull : 0ull;
+                    peak_merge(peak_key, peak_idx, float_key(umax), i);
+                    double posb = (s0 / sqrt((double)K) + 1.0) * (0.5 * kNBins);
                     int bin = (int)floor(posb);
                     bin = bin < 0 ? 0 : (bin > kNBins - 1 ? kNBins - 1 : bin);
                     atomicAdd(&hist[bin], 1u);
                 }
             }
-            rank += total;
+            rank += upto;
+            // the partial chunk left moves to the front of the queue
+            const int left = queued - upto;
+            const uint16_t keep = lane < left ? mylist[upto + lane] : (uint16_t)0;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (lane < left) mylist[lane] = keep;
+            queued = left;
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
@@ -557,32 +623,64 @@ __global__ void __launch_bounds__(kBlock) k_materialize128(KernelArgs a, unsigne
         S3 = wave_sum_f64_128(S3);
         S4 = wave_sum_f64_128(S4);
         n_ex = wave_sum_u64_128(n_ex);
+        n_ex4 = wave_sum_u64_128(n_ex4);
+        n_max4 = wave_sum_u64_128(n_max4);
+        wave_peak(peak_key, peak_idx);
         if (lane == 0) {
             wave_S[wv][0] = S1;
             wave_S[wv][1] = S2;
             wave_S[wv][2] = S3;
             wave_S[wv][3] = S4;
-            wave_ex[wv] = n_ex;
+            wave_ex[wv][0] = n_ex;
+            wave_ex[wv][1] = n_ex4;
+            wave_ex[wv][2] = n_max4;
+            wave_peak_key[wv] = peak_key;
+            wave_peak_idx[wv] = peak_idx;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            SegStats st = {0.0, 0.0, 0.0, 0.0, 0ull, 0ull};
-            for (int w = 0; w < kBlock / kWave; ++w) {
+            SegStats st = {0.0, 0.0, 0.0, 0.0, 0ull, 0ull, 0ull, 0ull, ~0ull, 0u, 0u};
+            for (int w = 0; w < W; ++w) {
                 st.S1 += wave_S[w][0];
                 st.S2 += wave_S[w][1];
                 st.S3 += wave_S[w][2];
                 st.S4 += wave_S[w][3];
-                st.n_exceed += wave_ex[w];
+                st.n_exceed += wave_ex[w][0];
+                st.n_exceed4 += wave_ex[w][1];
+                st.n_max4 += wave_ex[w][2];
+                peak_merge(st.peak_key, st.peak_index, wave_peak_key[w], wave_peak_idx[w]);
             }
             const unsigned long long sb = seg_base[gs];
             const unsigned long long se = sb + seg_cnt[gs];
             st.n_samples = (se < limit ? se : limit) - sb;
             seg_stats[gs] = st;
         }
-        for (int b = threadIdx.x; b < kNBins; b += kBlock)
+        for (int b = threadIdx.x; b < kNBins; b += B)
             if (hist[b]) atomicAdd(&res[p].hist[b], (unsigned long long)hist[b]);
         __syncthreads();
     }
+}
+
+template <int K, int PROP>
+hipError_t launch_materialize_q_t(const KernelArgs &a, unsigned long long total_segs,
+                                  const unsigned long long *seg_cnt, const unsigned long long *seg_base,
+                                  SegStats *seg_stats, PointResult *res, float *out_xhat,
+                                  unsigned long long *out_index, int n_cu, hipStream_t st)
+{
+    constexpr int lds = MatQ<K>::LDS, B = MatQ<K>::W * kWave;
+    auto kern = k_materialize_q<K, PROP>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, B, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    unsigned long long g = (unsigned long long)per_cu * n_cu;
+    if (total_segs < g) g = total_segs;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(kern, dim3((unsigned)g), dim3(B), lds, st, a, total_segs, seg_cnt, seg_base, seg_stats, res,
+                       out_xhat, out_index);
+    return hipGetLastError();
 }
 
 template <int K, int PREC, int PROP>
@@ -671,22 +769,21 @@ int decide_quarter64_max_blocks_per_cu(int prec)
                              : blocks_per_cu128_t<64, PREC_BF16X3, PROP_SIGMA>();
 }
 
-hipError_t launch_materialize128(int prop, const KernelArgs &a, unsigned long long total_segs,
-                                 const unsigned long long *seg_cnt, const unsigned long long *seg_base,
-                                 SegStats *seg_stats, PointResult *res, float *out_xhat,
-                                 unsigned long long *out_index, int n_cu, hipStream_t st)
+hipError_t launch_materialize_quarter(int K, int prop, const KernelArgs &a, unsigned long long total_segs,
+                                     const unsigned long long *seg_cnt, const unsigned long long *seg_base,
+                                     SegStats *seg_stats, PointResult *res, float *out_xhat,
+                                     unsigned long long *out_index, int n_cu, hipStream_t st)
 {
-    unsigned long long g = total_segs < (unsigned long long)(8 * n_cu) ? total_segs : 8ull * n_cu;
-    if (g < 1) g = 1;
-    if (prop == PROP_SIGMA)
-        hipLaunchKernelGGL(k_materialize128<PROP_SIGMA>, dim3((unsigned)g), dim3(kBlock), 0, st, a, total_segs,
-                           seg_cnt, seg_base, seg_stats, res, out_xhat, out_index);
-    else if (prop == PROP_UNIFORM)
-        hipLaunchKernelGGL(k_materialize128<PROP_UNIFORM>, dim3((unsigned)g), dim3(kBlock), 0, st, a, total_segs,
-                           seg_cnt, seg_base, seg_stats, res, out_xhat, out_index);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+#define TKDV_DISPATCH_MQ(KK, PP)                                                                            \
+    if (K == KK && prop == PP)                                                                             \
+        return launch_materialize_q_t<KK, PP>(a, total_segs, seg_cnt, seg_base, seg_stats, res, out_xhat, \
+                                              out_index, n_cu, st);
+    TKDV_DISPATCH_MQ(64, PROP_SIGMA)
+    TKDV_DISPATCH_MQ(64, PROP_UNIFORM)
+    TKDV_DISPATCH_MQ(128, PROP_SIGMA)
+    TKDV_DISPATCH_MQ(128, PROP_UNIFORM)
+#undef TKDV_DISPATCH_MQ
+    return hipErrorInvalidValue;
 }
 
 }  // namespace tkdv

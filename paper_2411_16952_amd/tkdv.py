@@ -109,7 +109,8 @@ class Stats(C.Structure):
                 ("kurtosis", C.c_double), ("p_exceed_2sigma", C.c_double),
                 ("hist_lo", C.c_double), ("hist_hi", C.c_double),
                 ("hist_u0", C.c_uint64 * NBINS), ("log_M_used", C.c_double), ("M_raises", C.c_int32),
-                ("fallback", C.c_int32)]
+                ("fallback", C.c_int32), ("n_exceed_4sigma", C.c_uint64), ("n_samples_4sigma", C.c_uint64),
+                ("peak_u", C.c_double), ("peak_index", C.c_uint64)]
 
     def to_dict(self) -> dict:
         d = {name: getattr(self, name) for name, _ in self._fields_ if name != "hist_u0"}

@@ -119,3 +119,18 @@ def k128_points() -> list[PointSpec]:
             pid = 2000 + len(pts)
             pts.append(PointSpec(128, 1.0, bp, lvl / bp, pid, pid))
     return pts
+
+
+# K = 64 (N = 256): the same four-point layout at the mode count of the
+# precision configuration, levels inside the batched sweep's K = 64 range.
+K64_BETAS = (20.0, 40.0)
+K64_LEVELS = (9000.0, 15000.0)
+
+
+def k64_points() -> list[PointSpec]:
+    pts = []
+    for lvl in K64_LEVELS:
+        for bp in K64_BETAS:
+            pid = 3000 + len(pts)
+            pts.append(PointSpec(64, 1.0, bp, lvl / bp, pid, pid))
+    return pts

@@ -25,6 +25,7 @@ import numpy as np
 import pytest
 
 import oracle
+from conftest import check_extremes
 
 pytestmark = pytest.mark.gpu
 
@@ -162,6 +163,7 @@ def test_sample_k128_matches_oracle(T, ctx, case, prop, n, prec):
     assert r["n_grid_values"] == so.n_grid
     assert abs(int(r["n_exceed_2sigma"]) - int(so.n_exceed)) <= 2 + so.n_exceed // 100000
     assert np.abs(r["hist_u0"].astype(np.int64) - so.hist.astype(np.int64)).sum() <= 2
+    check_extremes(r, so, pt.E0, K, o["xhat"], o["index"])
     assert r["n_M_violations"] == 0
 
 

@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import oracle
+from conftest import check_extremes
 
 pytestmark = pytest.mark.gpu
 
@@ -130,6 +131,9 @@ def test_sample_mixture_against_oracle(T, ctx, K, bp, c, n, prec, scale):
     assert abs(g["S3"] - st.S3) < 1e-5 * (st.S2 * math.sqrt(2 * K / math.pi) + 1.0)
     assert g["n_exceed_2sigma"] == st.n_exceed or abs(g["n_exceed_2sigma"] - st.n_exceed) <= 2
     assert np.abs(g["hist_u0"].astype(np.int64) - st.hist.astype(np.int64)).sum() <= 2
+    # stats_of indexes the rows; the rows are the accepted proposals in index order
+    st.peak_index = int(o["index"][st.peak_index]) if st.n_accepted else st.peak_index
+    check_extremes(g, st, 1.0, K, o["xhat"], o["index"])
 
 
 def test_sample_mixture_accepted_count_mode(T, ctx):

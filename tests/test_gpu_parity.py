@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import oracle
+from conftest import check_extremes
 
 pytestmark = pytest.mark.gpu
 
@@ -154,6 +155,7 @@ def test_sample_matches_oracle(T, ctx, K, bp, c, prop, n, prec):
         assert r["n_grid_values"] == so.n_grid
         assert abs(int(r["n_exceed_2sigma"]) - int(so.n_exceed)) <= 2 + so.n_exceed // 100000
         assert np.abs(r["hist_u0"].astype(np.int64) - so.hist.astype(np.int64)).sum() <= 2
+    check_extremes(r, so, 1.0, K, o["xhat"], o["index"])
     assert r["n_M_violations"] == so.n_violations == 0
 
 
@@ -170,6 +172,7 @@ def test_accepted_count_mode(T, ctx):
     assert r["n_proposed"] == o["stats"].n_proposed
     assert r["S2"] == pytest.approx(o["stats"].S2, rel=2e-5)
     assert np.abs(r["hist_u0"].astype(np.int64) - o["stats"].hist.astype(np.int64)).sum() <= 2
+    check_extremes(r, o["stats"], 1.0, 16, o["xhat"], o["index"])
 
 
 def test_capacity_truncates_rows_not_statistics(T, ctx):

@@ -22,6 +22,7 @@ import numpy as np
 import pytest
 
 import oracle
+from conftest import check_extremes
 
 pytestmark = pytest.mark.gpu
 
@@ -92,6 +93,8 @@ def test_sweep_equals_single_point_calls(T, ctx, use_graph, adaptive):
         assert np.array_equal(o["xhat"].cpu().numpy(), r["xhat"].cpu().numpy())
         assert o["hist_u0"].tolist() == r["hist_u0"].tolist()
         assert o["n_exceed_2sigma"] == r["n_exceed_2sigma"]
+        for f in ("n_exceed_4sigma", "n_samples_4sigma", "peak_u", "peak_index"):
+            assert o[f] == r[f], f
         for k in ("S1", "S2", "S3", "S4"):  # sums of the same values in another order
             assert abs(o[k] - r[k]) <= 1e-10 * (abs(r[k]) + r["S2"] + 1.0), k
     # the capped point
@@ -146,6 +149,7 @@ def test_sweep_against_oracle(T, ctx, K, bp, c, target, variant):
     assert np.max(np.linalg.norm(xg - o["xhat"], axis=1)) < 2e-6
     assert abs(out[0]["S2"] - o["stats"].S2) < 1e-6 * o["stats"].S2
     assert abs(out[0]["S4"] - o["stats"].S4) < 2e-5 * o["stats"].S4
+    check_extremes(out[0], o["stats"], 1.0, K, o["xhat"], o["index"])
 
 
 def test_sweep_argument_errors(T, ctx):
