@@ -565,6 +565,50 @@ tkdv_status tkdv_sample_sweep(tkdv_ctx *ctx, int32_t n_points, const tkdv_point 
                               const uint64_t *capacity, const uint64_t *out_offset, tkdv_stats *h_stats,
                               void *stream);
 
+/*
+ * Extremes map over parameter space (Sec. V.D: the largest displacements of
+ * individual samples against 4 sigma at several (beta', C3/C2); the paper's
+ * outlook of ensembles over whole regions of parameter space).  The
+ * n_beta x n_c points (K, E0, betas[b], c32s[c]) -- cell b * n_c + c, Philox
+ * key `seed`, point_id point_id0 + cell -- are planned on the GPU
+ * (tkdv_plan_batch, 16 starts) and sampled with the paper's proposal in one
+ * batched sweep (tkdv_sample_sweep, the context's launch configuration and
+ * violation policy): n_accepted samples per cell, or max_proposals proposals;
+ * no sample is stored.  Each cell gets its plan, counts and moments, and the
+ * extremes: the fraction of grid values above 4 sigma, the fraction of
+ * samples whose largest grid value is above 4 sigma, and the largest
+ * displacement with its sample's proposal index (regenerated by
+ * tkdv_eval_proposals with the cell's point and plan).  With n_accepted =
+ * 500, peak_u is the 1-in-500 event of Sec. V.D's figures.  A cell without a
+ * root alpha* (beta' >= K^2 sum_k 1/k^2, Sec. III.A) gets status
+ * TKDV_E_NO_ALPHA_ROOT and is not sampled.
+ *   K a sampler K (8, 16, 32, 64, 128); E0 > 0; n_beta, n_c >= 1 with
+ *   n_beta n_c <= TKDV_MAP_MAX_CELLS; betas >= 0 and c32s finite: host arrays;
+ *   n_accepted >= 1, max_proposals >= 1; precision FP32 or BF16X3;
+ *   cells: host [n_beta n_c]; stream: HIP stream (NULL: the null stream),
+ *   the call returns after it.
+ * Errors: TKDV_E_ARG, TKDV_E_UNSUPPORTED, TKDV_E_DEVICE, TKDV_E_M_VIOLATION
+ * (policy TKDV_MV_FAIL).
+ */
+typedef struct {
+    double beta_p, c32;
+    double alpha_star, log_M;   /* the cell's plan                                        */
+    uint64_t n_proposed, n_accepted;
+    double acceptance, skewness, kurtosis;
+    double p_exceed_2sigma;     /* grid values above 2 sqrt(E0/pi) / grid values            */
+    double p_exceed_4sigma;     /* grid values above 4 sqrt(E0/pi) / grid values            */
+    double p_sample_4sigma;     /* samples whose largest grid value is above 4 sigma / n    */
+    double peak_u;              /* largest grid value over the samples (-inf: none)         */
+    uint64_t peak_index;        /* its sample's proposal index (UINT64_MAX: none)           */
+    int32_t status;             /* TKDV_OK, or TKDV_E_NO_ALPHA_ROOT (cell not sampled)      */
+    int32_t M_raises;           /* the cell's runs with a raised M                          */
+} tkdv_map_cell;
+#define TKDV_MAP_MAX_CELLS 4096
+tkdv_status tkdv_extremes_map(tkdv_ctx *ctx, int32_t K, double E0, int32_t n_beta, const double *betas,
+                              int32_t n_c, const double *c32s, uint64_t seed, uint32_t point_id0,
+                              uint64_t n_accepted, uint64_t max_proposals, tkdv_precision precision,
+                              tkdv_map_cell *cells, void *stream);
+
 /* The context's launch configuration of the sweep for (K, precision). */
 tkdv_status tkdv_set_launch_cfg(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, const tkdv_launch_cfg *cfg);
 tkdv_status tkdv_get_launch_cfg(const tkdv_ctx *ctx, int32_t K, tkdv_precision precision, tkdv_launch_cfg *out);

@@ -2040,6 +2040,80 @@ tkdv_status tkdv_sample_sweep(tkdv_ctx *ctx, int32_t n_points, const tkdv_point 
     return TKDV_OK;
 }
 
+tkdv_status tkdv_extremes_map(tkdv_ctx *ctx, int32_t K, double E0, int32_t n_beta, const double *betas,
+                              int32_t n_c, const double *c32s, uint64_t seed, uint32_t point_id0,
+                              uint64_t n_accepted, uint64_t max_proposals, tkdv_precision precision,
+                              tkdv_map_cell *cells, void *stream)
+{
+    if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");
+    if (!betas || !c32s || !cells) return set_err(ctx, TKDV_E_ARG, "NULL argument");
+    if (n_beta < 1 || n_c < 1 || (int64_t)n_beta * n_c > TKDV_MAP_MAX_CELLS)
+        return set_err(ctx, TKDV_E_ARG, "n_beta, n_c >= 1 and n_beta * n_c <= TKDV_MAP_MAX_CELLS");
+    if (n_accepted < 1 || max_proposals < 1) return set_err(ctx, TKDV_E_ARG, "n_accepted, max_proposals >= 1");
+    if (precision != TKDV_FP32 && precision != TKDV_BF16X3)
+        return set_err(ctx, TKDV_E_UNSUPPORTED, "the map decides with FP32 or BF16x3 products");
+    std::vector<tkdv_point> pts;
+    std::vector<int> cell_of;
+    for (int b = 0; b < n_beta; ++b)
+        for (int c = 0; c < n_c; ++c) {
+            const int q = b * n_c + c;
+            tkdv_map_cell &m = cells[q];
+            std::memset(&m, 0, sizeof(m));
+            m.beta_p = betas[b];
+            m.c32 = c32s[c];
+            m.peak_u = -INFINITY;
+            m.peak_index = UINT64_MAX;
+            tkdv_point pt;
+            std::memset(&pt, 0, sizeof(pt));
+            pt.K = K;
+            pt.point_id = point_id0 + (uint32_t)q;
+            pt.E0 = E0;
+            pt.beta_p = betas[b];
+            pt.c32 = c32s[c];
+            pt.seed = seed;
+            tkdv_status s = check_point(ctx, pt);
+            if (s != TKDV_OK) return s;
+            double alpha = 0.0;
+            const int rs = plan_alpha_star(K, pt.beta_p, &alpha);
+            if (rs == TKDV_E_NO_ALPHA_ROOT) {
+                m.status = TKDV_E_NO_ALPHA_ROOT;
+                continue;
+            }
+            if (rs != TKDV_OK) return set_err(ctx, (tkdv_status)rs, "bad beta'");
+            pts.push_back(pt);
+            cell_of.push_back(q);
+        }
+    const int np = (int)pts.size();
+    if (np == 0) return TKDV_OK;
+    std::vector<tkdv_plan> plans(np);
+    tkdv_status s = tkdv_plan_batch(ctx, np, pts.data(), TKDV_PROP_SIGMA, 16, seed, 0, plans.data(), nullptr, stream);
+    if (s != TKDV_OK) return s;
+    std::vector<uint64_t> targets(np, n_accepted), maxp(np, max_proposals);
+    std::vector<tkdv_stats> st(np);
+    s = tkdv_sample_sweep(ctx, np, pts.data(), plans.data(), targets.data(), maxp.data(), precision, nullptr,
+                          nullptr, nullptr, nullptr, nullptr, st.data(), stream);
+    if (s != TKDV_OK) return s;
+    for (int q = 0; q < np; ++q) {
+        tkdv_map_cell &m = cells[cell_of[q]];
+        const tkdv_stats &r = st[q];
+        m.alpha_star = plans[q].alpha_star;
+        m.log_M = r.log_M_used;
+        m.n_proposed = r.n_proposed;
+        m.n_accepted = r.n_accepted;
+        m.acceptance = r.n_proposed ? (double)r.n_accepted / (double)r.n_proposed : 0.0;
+        m.skewness = r.skewness;
+        m.kurtosis = r.kurtosis;
+        m.p_exceed_2sigma = r.p_exceed_2sigma;
+        m.p_exceed_4sigma = r.n_grid_values ? (double)r.n_exceed_4sigma / (double)r.n_grid_values : 0.0;
+        m.p_sample_4sigma = r.n_accepted ? (double)r.n_samples_4sigma / (double)r.n_accepted : 0.0;
+        m.peak_u = r.peak_u;
+        m.peak_index = r.peak_index;
+        m.M_raises = r.M_raises;
+        m.status = TKDV_OK;
+    }
+    return TKDV_OK;
+}
+
 tkdv_status tkdv_set_violation_policy(tkdv_ctx *ctx, tkdv_violation_policy policy)
 {
     if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");

@@ -100,6 +100,20 @@ class Timing(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class MapCell(C.Structure):
+    _fields_ = [("beta_p", C.c_double), ("c32", C.c_double), ("alpha_star", C.c_double), ("log_M", C.c_double),
+                ("n_proposed", C.c_uint64), ("n_accepted", C.c_uint64), ("acceptance", C.c_double),
+                ("skewness", C.c_double), ("kurtosis", C.c_double), ("p_exceed_2sigma", C.c_double),
+                ("p_exceed_4sigma", C.c_double), ("p_sample_4sigma", C.c_double), ("peak_u", C.c_double),
+                ("peak_index", C.c_uint64), ("status", C.c_int32), ("M_raises", C.c_int32)]
+
+    def to_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+MAP_MAX_CELLS = 4096
+
+
 class Stats(C.Structure):
     _fields_ = [("n_proposed", C.c_uint64), ("n_accepted", C.c_uint64), ("n_written", C.c_uint64),
                 ("n_fp64_fixups", C.c_uint64), ("n_M_violations", C.c_uint64),
@@ -138,7 +152,7 @@ EXPORTS = ["tkdv_create", "tkdv_destroy", "tkdv_plan_point", "tkdv_sample", "tkd
            "tkdv_learner_mixture", "tkdv_learner_n_weights", "tkdv_learner_get_weights",
            "tkdv_learner_set_weights", "tkdv_sample_sweep", "tkdv_set_launch_cfg", "tkdv_get_launch_cfg",
            "tkdv_autotune", "tkdv_plan_batch", "tkdv_extremes", "tkdv_sir", "tkdv_plan_mixture_batch",
-           "tkdv_set_violation_policy", "tkdv_sample_noalloc"]
+           "tkdv_set_violation_policy", "tkdv_sample_noalloc", "tkdv_extremes_map"]
 
 _P = C.c_void_p
 lib.tkdv_create.argtypes = [C.c_int, C.POINTER(_P)]
@@ -197,6 +211,8 @@ lib.tkdv_plan_mixture_batch.argtypes = [_P, C.c_int32, C.POINTER(Point), C.POINT
                                         C.POINTER(Plan), C.POINTER(C.c_double), _P]
 lib.tkdv_plan_batch.argtypes = [_P, C.c_int32, C.POINTER(Point), C.c_int, C.c_int32, C.c_uint64, C.c_int32,
                                 C.POINTER(Plan), C.POINTER(C.c_double), _P]
+lib.tkdv_extremes_map.argtypes = [_P, C.c_int32, C.c_double, C.c_int32, _PD, C.c_int32, _PD, C.c_uint64,
+                                  C.c_uint32, C.c_uint64, C.c_uint64, C.c_int, C.POINTER(MapCell), _P]
 lib.tkdv_status_str.argtypes = [C.c_int]
 lib.tkdv_status_str.restype = C.c_char_p
 lib.tkdv_last_error.argtypes = [_P]
@@ -447,6 +463,18 @@ class Context:
             d["index"] = index[o:o + nw]
             out.append(d)
         return out, xhat, index
+
+    def extremes_map(self, K: int, E0: float, betas, c32s, n_accepted: int, max_proposals: int, seed: int = 0,
+                     point_id0: int = 0, precision: int = BF16X3, stream=None) -> list:
+        """Extremes over a (beta', C3/C2) grid (tkdv_extremes_map): one dict per
+        cell, row-major over betas x c32s."""
+        b = np.ascontiguousarray(betas, dtype=np.float64)
+        c = np.ascontiguousarray(c32s, dtype=np.float64)
+        cells = (MapCell * max(b.size * c.size, 1))()
+        _check(lib.tkdv_extremes_map(self._h, int(K), float(E0), b.size, b.ctypes.data_as(_PD), c.size,
+                                     c.ctypes.data_as(_PD), int(seed), int(point_id0), int(n_accepted),
+                                     int(max_proposals), int(precision), cells, _stream(stream)), self._h)
+        return [cells[q].to_dict() for q in range(b.size * c.size)]
 
     def set_launch_cfg(self, K: int, precision: int, cfg: LaunchCfg):
         _check(lib.tkdv_set_launch_cfg(self._h, int(K), int(precision), C.byref(cfg)), self._h)

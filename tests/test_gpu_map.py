@@ -1,0 +1,109 @@
+"""The extremes map over (beta', C3/C2) (tkdv_extremes_map, Sec. V.D) against
+the CPU FP64 oracle: every cell's accepted-count run (the first n accepted
+samples by index, the proposals used, alpha*), its 4-sigma extremes (samples
+whose largest grid value exceeds 4 sqrt(E0/pi), grid values above it, the
+largest displacement and its sample's index), a cell without a root alpha*,
+and the peak sample regenerated from its index by the oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import plan as oplan
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2411_16952_amd import tkdv
+    return tkdv
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    c = T.Context(0)
+    yield c
+    c.close()
+
+
+def check_cell(T, cell, K, E0, seed, point_id, n_acc, maxp):
+    bp, c = cell["beta_p"], cell["c32"]
+    assert cell["status"] == 0
+    assert cell["alpha_star"] == pytest.approx(oplan.alpha_star(K, bp), rel=1e-9)
+    o = oracle.sample_until(K, E0, bp, c, 1, cell["alpha_star"], cell["log_M"], seed, point_id, n_acc, maxp,
+                            4 * K)
+    so = o["stats"]
+    say(f"   cell beta'={bp} c={c}: acc {cell['n_accepted']} / {cell['n_proposed']} (oracle "
+        f"{so.n_accepted} / {so.n_proposed}); peak {cell['peak_u']:.4f} (oracle {so.peak_u:.4f}) "
+        f"at {cell['peak_index']} ({so.peak_index}); 4-sigma samples {cell['p_sample_4sigma']:.4f}")
+    assert cell["n_accepted"] == so.n_accepted == n_acc
+    assert cell["n_proposed"] == so.n_proposed
+    n_grid = n_acc * 4 * K
+    assert abs(round(cell["p_sample_4sigma"] * n_acc) - so.n_max4) <= 1
+    assert abs(round(cell["p_exceed_4sigma"] * n_grid) - so.n_exceed4) <= 2
+    assert abs(round(cell["p_exceed_2sigma"] * n_grid) - so.n_exceed) <= 2 + so.n_exceed // 100000
+    assert cell["skewness"] == pytest.approx(so.skewness, abs=1e-5)
+    tol = 1e-5 * math.sqrt(2 * K * E0 / math.pi)
+    assert abs(cell["peak_u"] - so.peak_u) < tol
+    # the peak sample, regenerated from its index by the oracle
+    r = oracle.sample(K, E0, bp, c, 1, cell["alpha_star"], cell["log_M"], seed, point_id, 1, 4 * K,
+                      i0=int(cell["peak_index"]), cap=1)
+    assert r["stats"].n_accepted == 1
+    assert abs(r["stats"].peak_u - cell["peak_u"]) < tol
+    return so
+
+
+def test_map_k16_against_oracle(T, ctx):
+    K, E0, seed, pid0 = 16, 1.0, 11, 100
+    betas, c32s = [20.0, 40.0, 500.0], [0.0, 30.0]
+    n_acc, maxp = 500, 10**7
+    cells = ctx.extremes_map(K, E0, betas, c32s, n_acc, maxp, seed=seed, point_id0=pid0, precision=T.BF16X3)
+    assert len(cells) == 6
+    for q, cell in enumerate(cells):
+        if cell["beta_p"] == 500.0:   # beta' >= K^2 sum 1/k^2: no alpha*
+            assert cell["status"] == -2 and cell["n_accepted"] == 0 and cell["peak_index"] == 2**64 - 1
+            continue
+        check_cell(T, cell, K, E0, seed, pid0 + q, n_acc, maxp)
+    # the linear cells (C3/C2 = 0) accept nearly every proposal
+    assert cells[0]["acceptance"] > 0.5 and cells[2]["acceptance"] > 0.5
+
+
+def test_map_k32_crosses_four_sigma(T, ctx):
+    """K = 32, beta' = 40 at C3/C2 = 150 and 225 (skewness 0.07 and 0.12 in the
+    paper's Table 2): 1-in-500 events reach 4 sigma (Sec. V.D), so the 4-sigma
+    counts are exercised, not only zero."""
+    K, E0, seed, pid0 = 32, 1.0, 7, 300
+    n_acc, maxp = 500, 5 * 10**7
+    cells = ctx.extremes_map(K, E0, [40.0], [150.0, 225.0], n_acc, maxp, seed=seed, point_id0=pid0,
+                             precision=T.BF16X3)
+    so = [check_cell(T, cell, K, E0, seed, pid0 + q, n_acc, maxp) for q, cell in enumerate(cells)]
+    assert sum(s.n_max4 for s in so) > 0
+
+
+def test_map_k64_fp32_cell(T, ctx):
+    K, E0, seed, pid0 = 64, 1.0, 5, 900
+    cells = ctx.extremes_map(K, E0, [40.0], [60.0], 200, 10**7, seed=seed, point_id0=pid0, precision=T.FP32)
+    check_cell(T, cells[0], K, E0, seed, pid0, 200, 10**7)
+
+
+def test_map_arguments(T, ctx):
+    with pytest.raises(T.TkdvError):
+        ctx.extremes_map(16, 1.0, [], [0.0], 10, 100)
+    with pytest.raises(T.TkdvError):
+        ctx.extremes_map(16, 1.0, [20.0], [0.0], 0, 100)
+    with pytest.raises(T.TkdvError) as e:
+        ctx.extremes_map(16, 1.0, [20.0], [0.0], 10, 100, precision=T.BF16)
+    assert e.value.status == -5
+    with pytest.raises(T.TkdvError):
+        ctx.extremes_map(12, 1.0, [20.0], [0.0], 10, 100)
