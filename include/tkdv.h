@@ -531,9 +531,11 @@ typedef struct {
     int32_t blocks_per_cu;  /* decide workgroups per compute unit, 0: as many as fit   */
     int32_t use_graph;      /* 1: 16 windows captured in one hipGraph, launched once     */
     uint64_t window;        /* proposals of a point's first window, a multiple of 65536 */
-    int32_t variant;        /* tile variant of the decision kernel, 0..3 (BF16x3 at
-                               K = 16, 32, 64: workgroup threads x tile pairs per group;
-                               0 elsewhere)                                             */
+    int32_t variant;        /* tile variant of the decision kernel, 0..3 (BF16x3: at
+                               K = 16, 32, 64 workgroup threads x tile pairs per group,
+                               or the half- against the quarter-period form; at K = 128
+                               0..2, workgroup threads); a variant a K does not have
+                               runs its variant 0                                       */
     int32_t adaptive;       /* 1: later windows sized on the device from the measured
                                acceptance; 0: every window `window` proposals           */
 } tkdv_launch_cfg;

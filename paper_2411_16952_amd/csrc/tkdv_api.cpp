@@ -2194,7 +2194,7 @@ tkdv_status tkdv_autotune(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, co
     tkdv_launch_cfg best{0, 1, 1ull << 26, 0, 1};
     double best_rate = -1.0;
     const uint64_t windows[3] = {1ull << 24, 1ull << 25, 1ull << 26};
-    const int n_var = (precision == TKDV_BF16X3 && (K == 16 || K == 32 || K == 64)) ? TKDV_DECIDE_VARIANTS : 1;
+    const int n_var = decide_n_variants(K, precision);
     for (int var = 0; var < n_var; ++var) {
         const int max_bpc = decide_variant_max_blocks_per_cu(K, precision, var);
         for (int bpc = 1; bpc <= max_bpc; ++bpc)

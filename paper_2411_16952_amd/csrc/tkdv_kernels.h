@@ -45,6 +45,14 @@ hipError_t launch_decide_quarter64(int prec, int prop, const KernelArgs &a, cons
 int decide128_block();
 int decide128_max_blocks_per_cu(int prec);
 int decide_quarter64_max_blocks_per_cu(int prec);
+// K = 128 tile variants (BF16x3, the paper's proposal); variant 0 is launch_decide128's
+int decide128_n_variants();
+int decide128_variant_block(int variant);
+hipError_t launch_decide128_variant(int variant, const KernelArgs &a, const int *plist, int n_plist, int n_cu,
+                                    unsigned long long total_tiles, hipStream_t st, int *grid_out);
+int decide128_variant_max_blocks_per_cu(int variant);
+// tile variants of K under the given arithmetic (1: the default kernel only)
+int decide_n_variants(int K, int prec);
 size_t quarter_table_bytes(int K, int prec);
 // The ordered output and statistics at K = 64 and 128 (quarter-period form on
 // the statistics grid; a.phi_hi: the table of upload_quarter_stats).

@@ -1244,7 +1244,8 @@ static int decide_blocks_per_cu_t()
 //   K = 64: variant 0 is the quarter-period kernel (16 proposals per wave,
 //           tkdv_quarter.hip, its own tables); 1..3 the half-period k_decide
 //           in (512, 1), (1024, 1), (768, 1)
-// K = 8 and K = 128, and FP32 products, have variant 0 only.
+//   K = 128: the quarter-period kernel in workgroups of 768, 512, 1024
+// K = 8, and FP32 products, have variant 0 only.
 template <int K>
 struct DecideVariant;
 template <>
@@ -1278,10 +1279,18 @@ static bool has_variants(int K, int prec, int prop)
     return (K == 16 || K == 32 || K == 64) && prec == PREC_BF16X3 && prop == PROP_SIGMA;
 }
 
+int decide_n_variants(int K, int prec)
+{
+    if (prec != PREC_BF16X3) return 1;
+    if (K == 128) return decide128_n_variants();
+    return has_variants(K, prec, PROP_SIGMA) ? TKDV_DECIDE_VARIANTS : 1;
+}
+
 int decide_variant_block(int K, int variant)
 {
     if (variant <= 0 || variant >= TKDV_DECIDE_VARIANTS) return decide_block(K);
     switch (K) {
+    case 128: return decide128_variant_block(variant);
     case 16: return DecideVariant<16>::B[variant];
     case 32: return DecideVariant<32>::B[variant];
     case 64: return DecideVariant<64>::B[variant];
@@ -1292,6 +1301,8 @@ int decide_variant_block(int K, int variant)
 hipError_t launch_decide_variant(int K, int prec, int prop, int variant, const KernelArgs &a, const int *plist,
                                  int n_plist, int n_cu, unsigned long long tiles, hipStream_t st, int *grid_out)
 {
+    if (K == 128 && prec == PREC_BF16X3 && prop == PROP_SIGMA && variant > 0 && variant < decide128_n_variants())
+        return launch_decide128_variant(variant, a, plist, n_plist, n_cu, tiles, st, grid_out);
     if (variant <= 0 || variant >= TKDV_DECIDE_VARIANTS || !has_variants(K, prec, prop))
         return launch_decide(K, prec, prop, a, plist, n_plist, n_cu, tiles, st, grid_out);
 #define TKDV_DISPATCH_V(KK)                                                                          \
@@ -1307,6 +1318,8 @@ hipError_t launch_decide_variant(int K, int prec, int prop, int variant, const K
 
 int decide_variant_max_blocks_per_cu(int K, int prec, int variant)
 {
+    if (K == 128 && prec == PREC_BF16X3 && variant > 0 && variant < decide128_n_variants())
+        return decide128_variant_max_blocks_per_cu(variant);
     if (variant <= 0 || variant >= TKDV_DECIDE_VARIANTS || !has_variants(K, prec, PROP_SIGMA))
         return decide_max_blocks_per_cu(K, prec);
 #define TKDV_DISPATCH_W(KK)                                             \

@@ -281,11 +281,12 @@ __device__ __forceinline__ float cube_sum_q128_bf16(const bf16x8 (&bh)[4][K / 64
 // ---------------------------------------------------------------------------
 // DBG: the verification entry's instantiation (per-proposal outputs written);
 // the sampling calls run the one without, which needs fewer registers.
-template <int K, int PREC, int PROP, bool DBG>
-__global__ void __launch_bounds__(Quarter<K>::BLOCK) k_decide128(KernelArgs a, const int *plist, int n_plist)
+// BL: workgroup threads (Quarter<K>::BLOCK, or a tile variant's).
+template <int K, int PREC, int PROP, bool DBG, int BL = Quarter<K>::BLOCK>
+__global__ void __launch_bounds__(BL) k_decide128(KernelArgs a, const int *plist, int n_plist)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
-    constexpr int B = Quarter<K>::BLOCK, CPL = K / 4;
+    constexpr int B = BL, CPL = K / 4;
     {
         const uint4 *s0 = reinterpret_cast<const uint4 *>(a.phi_hi);
         const uint4 *s1 = reinterpret_cast<const uint4 *>(a.phi_lo);
@@ -683,13 +684,13 @@ hipError_t launch_materialize_q_t(const KernelArgs &a, unsigned long long total_
     return hipGetLastError();
 }
 
-template <int K, int PREC, int PROP>
+template <int K, int PREC, int PROP, int BL = Quarter<K>::BLOCK>
 hipError_t launch_decide128_t(const KernelArgs &a, const int *plist, int n_plist, int n_cu,
                               unsigned long long total_tiles, hipStream_t st, int *grid_out)
 {
-    constexpr int lds = Quarter<K>::lds(PREC), B = Quarter<K>::BLOCK;
+    constexpr int lds = Quarter<K>::lds(PREC), B = BL;
     const bool dbg = a.dbg_xhat != nullptr || a.dbg_t != nullptr;
-    auto kern = dbg ? k_decide128<K, PREC, PROP, true> : k_decide128<K, PREC, PROP, false>;
+    auto kern = dbg ? k_decide128<K, PREC, PROP, true> : k_decide128<K, PREC, PROP, false, BL>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     int per_cu = 0;
@@ -707,17 +708,23 @@ hipError_t launch_decide128_t(const KernelArgs &a, const int *plist, int n_plist
     return hipGetLastError();
 }
 
-template <int K, int PREC, int PROP>
+template <int K, int PREC, int PROP, int BL = Quarter<K>::BLOCK>
 int blocks_per_cu128_t()
 {
     constexpr int lds = Quarter<K>::lds(PREC);
-    auto kern = k_decide128<K, PREC, PROP, false>;
+    auto kern = k_decide128<K, PREC, PROP, false, BL>;
     if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
         return 1;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, Quarter<K>::BLOCK, lds) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BL, lds) != hipSuccess) return 1;
     return per_cu < 1 ? 1 : per_cu;
 }
+
+// Tile variants at K = 128 (BF16x3, the paper's proposal): workgroups of 768
+// threads (the default: 3 waves per SIMD share the 128 KB of tables), 512 (2
+// waves per SIMD, registers without spills) and 1024 (4 waves per SIMD).
+constexpr int kVariants128 = 3;
+constexpr int kVariant128Block[kVariants128] = {Quarter<128>::BLOCK, 512, 1024};
 
 template <int K>
 hipError_t launch_quarter_k(int prec, int prop, const KernelArgs &a, const int *plist, int n_plist, int n_cu,
@@ -755,6 +762,31 @@ hipError_t launch_decide_quarter64(int prec, int prop, const KernelArgs &a, cons
                                    unsigned long long total_tiles, hipStream_t st, int *grid_out)
 {
     return launch_quarter_k<64>(prec, prop, a, plist, n_plist, n_cu, total_tiles, st, grid_out);
+}
+
+int decide128_n_variants() { return kVariants128; }
+int decide128_variant_block(int variant)
+{
+    return variant > 0 && variant < kVariants128 ? kVariant128Block[variant] : Quarter<128>::BLOCK;
+}
+
+hipError_t launch_decide128_variant(int variant, const KernelArgs &a, const int *plist, int n_plist, int n_cu,
+                                    unsigned long long total_tiles, hipStream_t st, int *grid_out)
+{
+    if (variant == 1)
+        return launch_decide128_t<128, PREC_BF16X3, PROP_SIGMA, kVariant128Block[1]>(a, plist, n_plist, n_cu,
+                                                                                   total_tiles, st, grid_out);
+    if (variant == 2)
+        return launch_decide128_t<128, PREC_BF16X3, PROP_SIGMA, kVariant128Block[2]>(a, plist, n_plist, n_cu,
+                                                                                   total_tiles, st, grid_out);
+    return launch_decide128_t<128, PREC_BF16X3, PROP_SIGMA>(a, plist, n_plist, n_cu, total_tiles, st, grid_out);
+}
+
+int decide128_variant_max_blocks_per_cu(int variant)
+{
+    if (variant == 1) return blocks_per_cu128_t<128, PREC_BF16X3, PROP_SIGMA, kVariant128Block[1]>();
+    if (variant == 2) return blocks_per_cu128_t<128, PREC_BF16X3, PROP_SIGMA, kVariant128Block[2]>();
+    return blocks_per_cu128_t<128, PREC_BF16X3, PROP_SIGMA>();
 }
 
 int decide128_max_blocks_per_cu(int prec)
