@@ -1244,7 +1244,7 @@ static int decide_blocks_per_cu_t()
 //   K = 64: variant 0 is the quarter-period kernel (16 proposals per wave,
 //           tkdv_quarter.hip, its own tables); 1..3 the half-period k_decide
 //           in (512, 1), (1024, 1), (768, 1)
-//   K = 128: the quarter-period kernel in workgroups of 768, 512, 1024
+//   K = 128: the quarter-period kernel in workgroups of 512, 768, 1024
 // K = 8, and FP32 products, have variant 0 only.
 template <int K>
 struct DecideVariant;

@@ -50,9 +50,11 @@ struct Quarter {
     // bytes of one table: BF16 [tile][out][step][64 lanes][8], FP32 [tile][out][group][64 lanes][4]
     static constexpr int BF16_BYTES = TILES * 4 * STEPS * 64 * 16;
     static constexpr int F32_BYTES = TILES * 4 * QG * 64 * 16;
-    // workgroup: at K = 128 the 128 KB of tables leave one workgroup per CU, 12
-    // waves (3 per SIMD) share them; at K = 64 (32 KB) workgroups of 256
-    static constexpr int BLOCK = K == 128 ? 768 : 256;
+    // workgroup: at K = 128 the 128 KB of tables leave one workgroup per CU;
+    // 8 waves (2 per SIMD) share them with every register they need (12 waves
+    // spill some 30 registers a lane, whose stores reach HBM, for no gain in
+    // speed); at K = 64 (32 KB) workgroups of 256
+    static constexpr int BLOCK = K == 128 ? 512 : 256;
     static constexpr int lds(int prec) { return prec == PREC_FP32 ? F32_BYTES : 2 * BF16_BYTES; }
 };
 
@@ -720,11 +722,11 @@ int blocks_per_cu128_t()
     return per_cu < 1 ? 1 : per_cu;
 }
 
-// Tile variants at K = 128 (BF16x3, the paper's proposal): workgroups of 768
-// threads (the default: 3 waves per SIMD share the 128 KB of tables), 512 (2
-// waves per SIMD, registers without spills) and 1024 (4 waves per SIMD).
+// Tile variants at K = 128 (BF16x3, the paper's proposal): workgroups of 512
+// threads (the default: 2 waves per SIMD, no register spills), 768 (3 waves
+// per SIMD, some 30 registers spilled) and 1024 (4 waves per SIMD).
 constexpr int kVariants128 = 3;
-constexpr int kVariant128Block[kVariants128] = {Quarter<128>::BLOCK, 512, 1024};
+constexpr int kVariant128Block[kVariants128] = {Quarter<128>::BLOCK, 768, 1024};
 
 template <int K>
 hipError_t launch_quarter_k(int prec, int prop, const KernelArgs &a, const int *plist, int n_plist, int n_cu,
