@@ -585,12 +585,14 @@ def learned_bench(args) -> int:
     train = [T.make_point(s.K, s.E0, s.beta_p, s.c32, seed=s.seed, point_id=s.point_id)
              for s in W.learned_train_points()]
     K = train[0].K
-    cfg = T.learner_cfg(K, hidden=256, eps=W.LEARNED_EPS, v_amp=0.5, v_scale=1.0, lr=3e-3, seed=7)
+    seeds = [int(v) for v in args.train_seeds.split(",")]
+    cfgs = [T.learner_cfg(K, hidden=256, eps=W.LEARNED_EPS, v_amp=0.5, v_scale=1.0, lr=3e-3, seed=sd) for sd in seeds]
     t0 = time.perf_counter()
-    res = learned.fit(ctx, train, cfg, samples_per_point=4096, rounds=args.train_rounds, steps=args.train_steps,
-                      max_proposals=1 << 36, precision=prec,
-                      log=lambda m: print("train " + m, file=sys.stderr, flush=True))
+    res = learned.fit_best(ctx, train, cfgs, samples_per_point=4096, rounds=args.train_rounds,
+                           steps=args.train_steps, max_proposals=1 << 36, precision=prec,
+                           log=lambda m: print("train " + m, file=sys.stderr, flush=True))
     train_s = time.perf_counter() - t0
+    train_gain = math.exp(float(np.mean(res.history[res.best_round]["log_gain"])))
 
     specs = W.learned_eval_points()
     pts = [T.make_point(s.K, s.E0, s.beta_p, s.c32, seed=s.seed, point_id=s.point_id) for s in specs]
@@ -696,6 +698,8 @@ def learned_bench(args) -> int:
             "K": K, "N": 4 * K, "points": len(pts), "proposals_per_point": n_per,
             "synthesis": args.precision, "fp64_redecision": True,
         },
+        "training": {"seconds": train_s, "seeds_tried": seeds, "seed_kept": res.learner.cfg.seed,
+                     "train_points_M_gain": train_gain, "best_round": res.best_round},
         "plain_value": acc_p / dt_p,
         "ratio_vs_plain": (acc_m / dt_m) / (acc_p / dt_p) if acc_p else None,
         "proposals_per_s": n_prop / dt_m,
@@ -831,6 +835,8 @@ def main() -> int:
                     help="oracle proposals per point (0: skip; default 2^22 plain, 2^17 learned)")
     ap.add_argument("--train-rounds", type=int, default=6)
     ap.add_argument("--train-steps", type=int, default=150)
+    ap.add_argument("--train-seeds", default="5,7,11,23",
+                    help="network initialisations tried; the best on the training points is kept")
     ap.add_argument("--synthesis", action="store_true",
                     help="only time the standalone synthesis kernel (K = 64, N = 256, 2^20 rows of x^ "
                          "in HBM) for FP32, BF16 and BF16x3 products; prints one JSON line")

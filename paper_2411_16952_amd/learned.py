@@ -105,6 +105,26 @@ def fit(ctx: T.Context, points: list, cfg: T.LearnerCfg, samples_per_point: int 
     return res
 
 
+def fit_best(ctx: T.Context, points: list, cfgs: list, log=None, **kw) -> FitResult:
+    """fit() from several network initialisations (cfgs differ in their seed);
+    keeps the one whose best round has the largest mean log M_Sigma/M_mix over
+    the training points (only training points enter the choice)."""
+    best, best_gain = None, -math.inf
+    for cfg in cfgs:
+        res = fit(ctx, points, cfg, log=log, **kw)
+        gain = res.history[res.best_round]["log_gain"]
+        g = float(np.mean(gain))
+        if log:
+            log(f"initialisation seed {cfg.seed}: mean M_Sigma/M_mix {math.exp(g):.2f} over the training points")
+        if g > best_gain:
+            if best is not None:
+                best.learner.close()
+            best, best_gain = res, g
+        else:
+            res.learner.close()
+    return best
+
+
 def plan_for_points(ctx: T.Context, res_or_learner, points: list, margin: float = 0.02, planner: str = "gpu"):
     """(mixtures, mixture plans, Sigma plans) of the trained network at many points."""
     L = res_or_learner.learner if isinstance(res_or_learner, FitResult) else res_or_learner
