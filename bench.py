@@ -240,7 +240,8 @@ def synthesis_bench(args) -> int:
                      "grid": ctx.timing()["decide_grid"], "block": ctx.timing()["decide_block"]}
         print(f"synthesis {name}: {avg:.4f} ms", file=sys.stderr, flush=True)
     # the same synthesis with x^ drawn in registers instead of read (Philox, Box-Muller, Sigma
-    # scaling): the sampler's decision kernel at this point, no samples stored
+    # scaling): the sampler's decision kernel at this point (the quarter-period form, a quarter
+    # of the dense product's matrix work), no samples stored
     n_gen = 16 * n
     gen_ms = []
     for rep in range(1 + max(args.steps, 3)):
@@ -252,8 +253,8 @@ def synthesis_bench(args) -> int:
         "ms": g_ms, "proposals": n_gen, "rows_per_s": n_gen / (g_ms * 1e-3),
         **mfma_fields(K, "bf16x3", "sigma", n_gen / (g_ms * 1e-3)),
         "alu_frac": method_ops_per_proposal(K) * n_gen / (g_ms * 1e-3) / ALU_OPS_PER_S,
-        "kernel": "k_decide (half-period synthesis, decisions included)"}
-    print(f"synthesis from Philox (k_decide, {n_gen} proposals): {g_ms:.3f} ms", file=sys.stderr, flush=True)
+        "kernel": "k_decide128<64> (quarter-period synthesis, decisions included)"}
+    print(f"synthesis from Philox (k_decide128<64>, {n_gen} proposals): {g_ms:.3f} ms", file=sys.stderr, flush=True)
     r = res["bf16x3"]
     # measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated), if taken on these sources
     traffic = None
