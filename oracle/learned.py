@@ -10,8 +10,11 @@ row and one point at a time, written from the definitions:
   mixture      log d_k = log s_k^2 + o_{k-1};  V = V0 + v_scale o_{K..5K-1}
                (row-major [2K][2]), V0 = v_amp/sqrt(K) on the cos block of
                column 0 and the sin block of column 1
-  loss         L = sum_p [ T log sum_{s in p} exp((log f(x_s) - log q_mix(x_s))/T)
-                           - lambda mean_{s in p, kind 0} log q_net(x_s) ]
+  loss         L = sum_p [ T log sum_{s in p, kind 0, 1} exp((log f(x_s) - log q_mix(x_s))/T)
+                           - lambda mean_{s in p, kind 0, 2} log q_net(x_s) ]
+               (kind 0: accepted samples in both terms; kind 1: points where
+               f/q_mix is large, soft maximum only; kind 2: accepted samples
+               in the likelihood term only)
 with log f the unnormalised target of the paper (eq. for f, Sec. III) and
 q_net, q_mix the oracle's mixture densities (``core.mix_log_q``).
 
@@ -67,14 +70,17 @@ def mixture_params(o, K: int, sigma2, v_amp: float, v_scale: float):
 
 
 def point_loss(K, E0, beta_p, c32, alpha_star, eps, logd, V, rows, kinds, T, lam):
-    """Loss of one point for its rows (unit vectors) and kinds (0 accepted, 1 other)."""
+    """Loss of one point for its rows (unit vectors) and kinds (0 accepted
+    sample, 1 other point: soft maximum only, 2 accepted sample: likelihood
+    only)."""
     m = core.make_mixture(K, eps, logd, V)
     r, nll, n_acc = [], 0.0, 0
     for x, kd in zip(rows, kinds):
         lnet, lmix = core.mix_log_q(K, E0, beta_p, c32, alpha_star, m, x)
         lf = core.log_ratio(x, E0, beta_p, c32, alpha_star, 0)   # log f, unnormalised
-        r.append(lf - lmix)
-        if kd == 0:
+        if kd in (0, 1):
+            r.append(lf - lmix)
+        if kd in (0, 2):
             nll -= lnet
             n_acc += 1
     r = np.array(r) / T

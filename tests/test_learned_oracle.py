@@ -66,3 +66,9 @@ def test_loss_closed_forms():
     lam = 0.7
     with_nll = OL.point_loss(K, 1.0, bp, c, a, 0.2, logd, V, X[:1], [0], 0.05, lam)
     assert abs(with_nll - r[0] + lam * oracle.mix_log_q(K, 1.0, bp, c, a, m, X[0])[0]) < 1e-12
+    # kind 2 (likelihood only): absent from the soft maximum, present in the mean
+    lq = [oracle.mix_log_q(K, 1.0, bp, c, a, m, x)[0] for x in X]
+    mixed = OL.point_loss(K, 1.0, bp, c, a, 0.2, logd, V, X[:3], [1, 2, 2], 0.05, lam)
+    assert abs(mixed - (r[0] - lam * (lq[1] + lq[2]) / 2)) < 1e-12
+    both = OL.point_loss(K, 1.0, bp, c, a, 0.2, logd, V, X[:2], [0, 2], 0.05, lam)
+    assert abs(both - (r[0] - lam * (lq[0] + lq[1]) / 2)) < 1e-12
