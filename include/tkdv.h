@@ -464,12 +464,16 @@ double tkdv_mixture_window(const tkdv_point *pt, const tkdv_plan *mix_plan, cons
  *       the cos block of column 0 and on the sin block of column 1.
  * Weights, one FP64 array, input-major: W1 [3][H], b1 [H], W2 [H][H], b2 [H],
  * W3 [H][5K], b3 [5K].  Training rows of point p are unit vectors x_s of
- * two kinds: accepted samples of the point (kind 0) and points where f/q_mix
- * is large, e.g. the arg max of tkdv_plan_mixture (kind 1).  The loss is
- *   L = sum_p [ T log sum_{s in p} exp((log f(x_s) - log q_mix(x_s))/T)
- *               - lambda mean_{s in p, kind 0} log q_net(x_s) ],
+ * three kinds: accepted samples of the point (kind 0), points where f/q_mix
+ * is large, e.g. the arg max of tkdv_plan_mixture (kind 1), and accepted
+ * samples that enter the likelihood term only (kind 2: a large sample set
+ * whose soft maximum runs over a subsample, the kind-0 rows).  The loss is
+ *   L = sum_p [ T log sum_{s in p, kind 0, 1} exp((log f(x_s) - log q_mix(x_s))/T)
+ *               - lambda mean_{s in p, kind 0, 2} log q_net(x_s) ],
  * a soft maximum of the ratio (whose supremum is log M_mix) plus a
- * likelihood term; Adam on the weights.  K in {8, 16, 32}.
+ * likelihood term; Adam on the weights.  The mixture densities of the rows
+ * and their gradients run as FP64 matrix products (the y products of all
+ * shifts at once).  K in {8, 16, 32}.
  */
 typedef struct {
     int32_t K;
@@ -490,8 +494,9 @@ tkdv_status tkdv_learner_destroy(tkdv_learner *learner);
 /* The training points; sigma_plans are their Sigma plans.  Clears the rows. */
 tkdv_status tkdv_learner_set_points(tkdv_learner *learner, int32_t n_points, const tkdv_point *pts,
                                     const tkdv_plan *sigma_plans);
-/* Append n rows to point `point`: device FP32 rows (row_stride floats apart,
- * first 2K used) or host FP64 rows [n][2K]; rows are normalised in FP64. */
+/* Append n rows of kind 0, 1 or 2 to point `point`: device FP32 rows
+ * (row_stride floats apart, first 2K used) or host FP64 rows [n][2K]; rows
+ * are normalised in FP64. */
 tkdv_status tkdv_learner_add_rows(tkdv_learner *learner, int32_t point, const float *d_xhat, uint64_t row_stride,
                                   uint64_t n, int32_t kind, void *stream);
 tkdv_status tkdv_learner_add_rows_host(tkdv_learner *learner, int32_t point, const double *h_xhat, uint64_t n,

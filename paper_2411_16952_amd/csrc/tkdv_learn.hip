@@ -5,13 +5,13 @@
 //   k_mlp_fwd       per point: z -> h1 -> h2 -> o (tanh layers)
 //   k_mix_prep      per point: o -> log d, V; A = D^-1, G^-1, log|L0| and
 //                   the gradient of log|L0|
-//   k_mix_fwd       per row (one wave, a lane per coordinate): log q_net and
-//                   log q_mix over the S shifts (online log-sum-exp)
+//   k_mix_fwd_mm    per chunk of rows: the y products of all S shifts on the
+//                   FP64 matrix cores, log q_net and log q_mix
 //   k_loss_max      per point maximum of r_s = log f - log q_mix
 //   k_loss_chunk    per chunk of a point's rows: sum of exp(r_s/T - max), NLL
 //   k_loss_final    per point: chunk partials in order -> soft maximum, loss
-//   k_mix_bwd       per chunk: dL/d(log d, V) of the point, accumulated over
-//                   the rows' shifts in row order
+//   k_mix_bwd_mm    per chunk: dL/d(log d, V) of the point from a second
+//                   product X^T C and per-mode rotations
 //   k_param_grad    per point: chunk partials in order, the log|L0| term,
 //                   dL/do
 //   k_mlp_bwd_*     back through the layers; dL/dweights summed over points
@@ -49,6 +49,8 @@ struct LearnPoint {
     uint32_t chunk0, chunk1;  // the point's chunks [chunk0, chunk1)
 };
 
+constexpr int kMixCols = 2 * kMixS;  // columns (shift j, q) -> 2 j + q of the y products
+
 struct LearnParam {
     double logd[kLKMax], a[kLKMax];
     double V[2 * kLKMax][2];
@@ -56,7 +58,11 @@ struct LearnParam {
     double logdet;
     double dld_logd[kLKMax];   // d log|L0| / d log d_k
     double dld_V[2 * kLKMax][2];
+    // y_j = V^T A R_j^T x = B_j^T x for every shift at once: B[n][2 j + q] = (R_j A V)_nq
+    double B[2 * kLKMax][kMixCols];
 };
+
+__constant__ double c_cs[kMixS], c_sn[kMixS];
 
 struct LearnStats {
     unsigned long long maxkey;  // order-preserving key of max_s r_s/T
@@ -253,6 +259,19 @@ __global__ void __launch_bounds__(64) k_mix_prep(const double *out, int n_out, c
     const double own = act ? 1.0 - a * (u0 * V0 + u1 * V1) : 0.0;
     const double partner = __shfl(own, (m + K) & 63, 64);
     if (m < K) Q.dld_logd[m] = own + partner;
+    // the y-product matrix: coordinate n of x enters w = R_j^T x at n (cos c) and at
+    // its partner n +- K (sin s): B[n][2j + q] = a (c V_nq +- s V_{n -+ K, q})
+    const int src = act ? (m < K ? m + K : m - K) : m;
+    const double P0 = __shfl(V0, src, 64), P1 = __shfl(V1, src, 64);
+    if (act) {
+        const double sg = m < K ? 1.0 : -1.0;
+        for (int j = 0; j < kMixS; ++j) {
+            const int mi = ((k + 1) * j) & (kMixS - 1);
+            const double c = c_cs[mi], sn = sg * c_sn[mi];
+            Q.B[m][2 * j] = a * (c * V0 + sn * P0);
+            Q.B[m][2 * j + 1] = a * (c * V1 + sn * P1);
+        }
+    }
     if (m == 0) {
         Q.gi[0][0] = i00;
         Q.gi[0][1] = i01;
@@ -297,89 +316,12 @@ __global__ void k_rows_append(const float *src, unsigned long long stride, unsig
     }
 }
 
-// ---------------------------------------------------------------------------
-// Mixture density of a row, one wave per row, lane m = coordinate m (2K <= 64).
-//   w = R_j^T x, y = V^T A w, g = G^-1 y, e = w - V g, qf_j = e^T A e + |g|^2,
-//   l_j = -K ln qf_j; log q_net = LSE_j(l_j) - ln S - log|L0|/2.
-// ---------------------------------------------------------------------------
-template <int K>
-struct RowMix {
-    double xm, xp;   // own coordinate and the other one of the mode pair
-    double am, v0, v1;
-    int k;           // mode of the lane (1..K)
-    bool act, sinb;
-
-    __device__ void load(const LearnArgs &A, const LearnParam &Q, unsigned long long r, int m)
-    {
-        act = m < 2 * K;
-        sinb = m >= K;
-        k = m % K + 1;
-        const int mp = sinb ? m - K : m + K;
-        xm = act ? A.X[r * 2 * K + m] : 0.0;
-        xp = act ? A.X[r * 2 * K + mp] : 0.0;
-        am = act ? Q.a[k - 1] : 0.0;
-        v0 = act ? Q.V[m][0] : 0.0;
-        v1 = act ? Q.V[m][1] : 0.0;
-    }
-    // shift j: own coordinate of w = R_j^T x, e and qf (all lanes get qf, g)
-    __device__ void shift(const LearnParam &Q, const double *cs, const double *sn, int j, double &w, double &e,
-                          double &qf, double &g0, double &g1) const
-    {
-        const int mi = (k * j) & (kMixS - 1);
-        const double c = cs[mi], s = sn[mi];
-        w = act ? (sinb ? xm * c + xp * s : xm * c - xp * s) : 0.0;
-        const double aw = am * w;
-        const double y0 = wsum(v0 * aw), y1 = wsum(v1 * aw);
-        g0 = Q.gi[0][0] * y0 + Q.gi[0][1] * y1;
-        g1 = Q.gi[1][0] * y0 + Q.gi[1][1] * y1;
-        e = w - (v0 * g0 + v1 * g1);
-        qf = wsum(am * e * e) + g0 * g0 + g1 * g1;
-    }
-};
-
-__constant__ double c_cs[kMixS], c_sn[kMixS];
-
-template <int K>
-__global__ void __launch_bounds__(256) k_mix_fwd(LearnArgs A)
-{
-    const int m = threadIdx.x & 63;
-    const unsigned long long nw = (unsigned long long)gridDim.x * 4;
-    for (unsigned long long r = ((unsigned long long)blockIdx.x * 256 + threadIdx.x) >> 6; r < A.n; r += nw) {
-        const int p = __builtin_amdgcn_readfirstlane(A.row_point[r]);
-        const LearnPoint &L = A.pts[p];
-        const LearnParam &Q = A.par[p];
-        RowMix<K> R;
-        R.load(A, Q, r, m);
-        double mx = -INFINITY, se = 0.0;
-        for (int j = 0; j < kMixS; ++j) {
-            double w, e, qf, g0, g1;
-            R.shift(Q, c_cs, c_sn, j, w, e, qf, g0, g1);
-            const double l = -K * log(qf);
-            if (l > mx) {
-                se = se * exp(mx - l) + 1.0;
-                mx = l;
-            } else {
-                se += exp(l - mx);
-            }
-        }
-        const double t = wsum(R.act ? (double)R.k * R.k * R.xm * R.xm : 0.0);
-        const double lnet = mx + log(se) - log((double)kMixS) - 0.5 * Q.logdet;
-        const double lg = L.lng - K * log1p(L.gc * t);
-        const double a1 = A.log_eps + lg, b1 = A.log_1m_eps + lnet;
-        const double hi = a1 > b1 ? a1 : b1;
-        const double lm = hi + log(exp(a1 - hi) + exp(b1 - hi));
-        if (m == 0) {
-            A.lnet[r] = lnet;
-            A.lmix[r] = lm;
-        }
-    }
-}
-
 __global__ void k_loss_max(LearnArgs A)
 {
     for (unsigned long long r = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; r < A.n;
          r += (unsigned long long)gridDim.x * blockDim.x)
-        atomicMax(&A.st[A.row_point[r]].maxkey, dkey((A.lf[r] - A.lmix[r]) / A.T));
+        if (A.kind[r] != 2)  // kind 2: likelihood term only
+            atomicMax(&A.st[A.row_point[r]].maxkey, dkey((A.lf[r] - A.lmix[r]) / A.T));
 }
 
 // Sum of exp(r_s/T - max) and of -log q_net over the accepted rows, per chunk
@@ -394,8 +336,9 @@ __global__ void __launch_bounds__(256) k_loss_chunk(LearnArgs A)
     double se = 0.0, nll = 0.0;
     for (unsigned q = A.chunk_start[c] + m; q < A.chunk_start[c + 1]; q += 64) {
         const unsigned r = A.order[q];
-        se += exp((A.lf[r] - A.lmix[r]) / A.T - mx);
-        nll += A.kind[r] == 0 ? -A.lnet[r] : 0.0;
+        const uint8_t kd = A.kind[r];
+        se += kd != 2 ? exp((A.lf[r] - A.lmix[r]) / A.T - mx) : 0.0;
+        nll += kd != 1 ? -A.lnet[r] : 0.0;
     }
     se = wsum(se);
     nll = wsum(nll);
@@ -423,54 +366,267 @@ __global__ void k_loss_final(LearnArgs A, int n_points)
                       : A.lambda * nll * L.inv_n_acc;
 }
 
-// dL/d(log d, V) per chunk (one wave, rows in order).  c_s = dL/d log q_net(x_s):
-//   -w_s rho_s - lambda/n_acc [kind 0],  w_s = softmax_s(r_s/T),
-//   rho_s = (1 - eps) q_net/q_mix.
-// d log q_net/dV_mq = sum_j pi_j (2K/qf_j) (A e_j)_m g_jq,
-// d log q_net/d log d_k = sum_j pi_j (K/qf_j) sum_{m in k} a_m e_jm^2
-// (pi_j = softmax_j l_j), without the -log|L0|/2 term (added per point).
-template <int K>
-__global__ void __launch_bounds__(256) k_mix_bwd(LearnArgs A)
+// ---------------------------------------------------------------------------
+// Mixture densities of the rows and their gradients, as products on the FP64
+// matrix cores, one wave per chunk (at most 32 rows of one point, two tiles
+// of 16 rows).  log q_net = LSE_j(-K ln qf_j) - ln S - log|L0|/2 over the S
+// shifts; c_s = dL/d log q_net(x_s) = -w_s rho_s [kinds 0, 1] - lambda/n_acc
+// [kinds 0, 2] with w_s = softmax_s(r_s/T), rho_s = (1 - eps) q_net/q_mix.
+//   Forward: Y = X B (rows x 64, column 2j + q holds y_jq) by 16x16x4 FP64
+//   instructions; qf_j = Q - y_j^T G^-1 y_j with Q = x^T A x (Woodbury; A is
+//   constant on each mode pair, so Q does not depend on the shift); l_j =
+//   -K ln qf_j and the log-sum-exp over the 32 shifts across lanes.
+//   Backward: with f_j = c_s pi_j K/qf_j (pi_j = softmax_j l_j) and
+//   g_j = G^-1 y_j, the chunk's sums
+//     M = X^T C,  C[s][2j + q] = f_sj g_sjq     (a second product),
+//     S = sum_sj f_sj g_sj g_sj^T,  E_m = sum_s (sum_j f_sj) x_sm^2,
+//   and P_mq = sum_j (R_j^T M_(j,q))_m give, per coordinate m of mode k,
+//     dL/dV_mq  = 2 a_k (P_mq - (V_m S)_q),
+//     dL/dlog d_k = a_k sum_{m in k} (E_m - 2 V_m . P_m + V_m S V_m^T)
+//   (with e_j = R_j^T x - V g_j, dqf_j/dV_mq = -2 a_k e_jm g_jq and
+//   dqf_j/dlog d_k = -sum_{m in k} a_k e_jm^2, expanded over the sums).
+// Matrix instruction layout: lane l supplies A[l%16][l/16] and B[l/16][l%16],
+// and element v of its result is D[4v + l/16][l%16].  The backward's C is
+// formed in the D layout of the first product, which is the B layout of the
+// second.
+// ---------------------------------------------------------------------------
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4_t mma_f64(double a, double b, d4_t c)
 {
-    const int m = threadIdx.x & 63;
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Row i of chunk c (rows past the chunk's end repeat its first row; their
+// results are not used).
+__device__ __forceinline__ unsigned chunk_row(const LearnArgs &A, unsigned c0, unsigned nc, int i)
+{
+    return A.order[c0 + (i < (int)nc ? i : 0)];
+}
+
+// y products of 16 rows (this lane's A-operand row: rowA) into acc[t] (column
+// tile t), and the row's Q = x^T A x and t = sum k^2 x_k^2 (lanes l % 16 = i).
+template <int K>
+__device__ __forceinline__ void mix_products(const LearnArgs &A, const LearnParam &Q, unsigned rowA, int lane,
+                                             d4_t (&acc)[4], double &Qr, double &tr)
+{
+    const int g = lane >> 4, i16 = lane & 15;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = d4_t{0.0, 0.0, 0.0, 0.0};
+    double qa = 0.0, ta = 0.0;
+    const double *x = A.X + (size_t)rowA * 2 * K;
+#pragma unroll
+    for (int s = 0; s < K / 2; ++s) {  // k-steps of 4 coordinates
+        const int m = 4 * s + g, k = m % K;
+        const double xv = x[m];
+        qa += Q.a[k] * xv * xv;
+        ta += (double)((k + 1) * (k + 1)) * xv * xv;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = mma_f64(xv, Q.B[m][16 * t + i16], acc[t]);
+    }
+    qa += __shfl_xor(qa, 16, 64);
+    qa += __shfl_xor(qa, 32, 64);
+    ta += __shfl_xor(ta, 16, 64);
+    ta += __shfl_xor(ta, 32, 64);
+    Qr = qa;
+    tr = ta;
+}
+
+template <int K>
+__global__ void __launch_bounds__(256) k_mix_fwd_mm(LearnArgs A)
+{
+    const int lane = threadIdx.x & 63, g = lane >> 4, i16 = lane & 15;
     const unsigned c = __builtin_amdgcn_readfirstlane((blockIdx.x * 256 + threadIdx.x) >> 6);
     if (c >= A.n_chunks) return;
     const int p = A.chunk_point[c];
     const LearnPoint &L = A.pts[p];
     const LearnParam &Q = A.par[p];
-    const LearnStats &S = A.st[p];
-    const double mx = dkey_inv(S.maxkey);
-    double gv0 = 0.0, gv1 = 0.0, gd = 0.0, cs_acc = 0.0;
-    for (unsigned q = A.chunk_start[c]; q < A.chunk_start[c + 1]; ++q) {
-        const unsigned r = A.order[q];
-        const double ws = exp((A.lf[r] - A.lmix[r]) / A.T - mx) / S.sum;
-        const double rho = exp(A.log_1m_eps + A.lnet[r] - A.lmix[r]);
-        const double cf = -ws * rho - (A.kind[r] == 0 ? A.lambda * L.inv_n_acc : 0.0);
-        cs_acc += cf;
-        RowMix<K> R;
-        R.load(A, Q, r, m);
-        // log-sum-exp of l_j: ln(sum_j qf_j^-K) relative to the row's q_net
-        const double lse = A.lnet[r] + log((double)kMixS) + 0.5 * Q.logdet;
-        for (int j = 0; j < kMixS; ++j) {
-            double w, e, qf, g0, g1;
-            R.shift(Q, c_cs, c_sn, j, w, e, qf, g0, g1);
-            const double pi = exp(-K * log(qf) - lse);
-            const double f = cf * pi * K / qf;
-            const double ae = R.am * e;
-            gv0 += 2.0 * f * ae * g0;
-            gv1 += 2.0 * f * ae * g1;
-            gd += f * ae * e;
+    const unsigned c0 = A.chunk_start[c], nc = A.chunk_start[c + 1] - c0;
+    const double gi00 = Q.gi[0][0], gi01 = Q.gi[0][1], gi11 = Q.gi[1][1];
+    const double cst = -log((double)kMixS) - 0.5 * Q.logdet;
+    for (int rt = 0; rt * 16 < (int)nc; ++rt) {
+        d4_t acc[4];
+        double Qa, ta;
+        mix_products<K>(A, Q, chunk_row(A, c0, nc, rt * 16 + i16), lane, acc, Qa, ta);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int ri = 4 * v + g;  // the tile row of this lane's results
+            const double Qr = __shfl(Qa, ri, 64), tr = __shfl(ta, ri, 64);
+            double lj[4], mx = -INFINITY;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {  // shift j = 8t + i16/2; lanes l, l^1 hold q = 0, 1
+                const double y = acc[t][v], yo = __shfl_xor(y, 1, 64);
+                const double y0 = (lane & 1) ? yo : y, y1 = (lane & 1) ? y : yo;
+                const double qf = Qr - (gi00 * y0 * y0 + 2.0 * gi01 * y0 * y1 + gi11 * y1 * y1);
+                lj[t] = -K * log(qf);
+                mx = fmax(mx, lj[t]);
+            }
+            double se = 0.0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) se += exp(lj[t] - mx);
+#pragma unroll
+            for (int o = 2; o <= 8; o <<= 1) {  // the other shifts of the row (lane bits 1..3)
+                const double m2 = __shfl_xor(mx, o, 64), s2 = __shfl_xor(se, o, 64);
+                const double mm = fmax(mx, m2);
+                se = se * exp(mx - mm) + s2 * exp(m2 - mm);
+                mx = mm;
+            }
+            const double lnet = mx + log(se) + cst;
+            const double lg = L.lng - K * log1p(L.gc * tr);
+            const double a1 = A.log_eps + lg, b1 = A.log_1m_eps + lnet;
+            const double hi = fmax(a1, b1);
+            const double lm = hi + log(exp(a1 - hi) + exp(b1 - hi));
+            const int rr = rt * 16 + ri;
+            if (i16 == 0 && rr < (int)nc) {
+                const unsigned row = A.order[c0 + rr];
+                A.lnet[row] = lnet;
+                A.lmix[row] = lm;
+            }
         }
     }
-    // the two coordinates of mode m + 1
-    const double gd_pair = gd + __shfl(gd, (m + K) & 63, 64);
-    double *o = A.part + (size_t)c * A.pt_len;
-    if (m == 0) o[2] = cs_acc;
-    if (m < K) o[3 + m] = gd_pair;
-    if (m < 2 * K) {
-        o[3 + K + 2 * m] = gv0;
-        o[3 + K + 2 * m + 1] = gv1;
+}
+
+template <int K>
+__global__ void __launch_bounds__(256) k_mix_bwd_mm(LearnArgs A)
+{
+    constexpr int MT = 2 * K / 16;  // 16-coordinate tiles of M
+    const int lane = threadIdx.x & 63, g = lane >> 4, i16 = lane & 15, q = lane & 1;
+    const unsigned c = __builtin_amdgcn_readfirstlane((blockIdx.x * 256 + threadIdx.x) >> 6);
+    if (c >= A.n_chunks) return;
+    const int p = A.chunk_point[c];
+    const LearnPoint &L = A.pts[p];
+    const LearnParam &Q = A.par[p];
+    const LearnStats &St = A.st[p];
+    const double mxL = dkey_inv(St.maxkey), inv_sum = 1.0 / St.sum;
+    const unsigned c0 = A.chunk_start[c], nc = A.chunk_start[c + 1] - c0;
+    const double gi00 = Q.gi[0][0], gi01 = Q.gi[0][1], gi11 = Q.gi[1][1];
+    const double lse0 = log((double)kMixS) + 0.5 * Q.logdet;
+    d4_t macc[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) macc[mt][t] = d4_t{0.0, 0.0, 0.0, 0.0};
+    double S00 = 0.0, S01 = 0.0, S11 = 0.0, cs_acc = 0.0;
+    double Epart[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) Epart[mt] = 0.0;
+    for (int rt = 0; rt * 16 < (int)nc; ++rt) {
+        // the row coefficient of this lane's A-operand row
+        const bool valid = rt * 16 + i16 < (int)nc;
+        const unsigned rowA = chunk_row(A, c0, nc, rt * 16 + i16);
+        const double lnet = A.lnet[rowA], lmix = A.lmix[rowA];
+        const uint8_t kd = A.kind[rowA];
+        const double ws = kd != 2 ? exp((A.lf[rowA] - lmix) / A.T - mxL) * inv_sum : 0.0;
+        const double rho = exp(A.log_1m_eps + lnet - lmix);
+        const double cf = valid ? -ws * rho - (kd != 1 ? A.lambda * L.inv_n_acc : 0.0) : 0.0;
+        const double lse = lnet + lse0;
+        if (g == 0) cs_acc += cf;
+        d4_t acc[4];
+        double Qa, ta;
+        mix_products<K>(A, Q, rowA, lane, acc, Qa, ta);
+        double Cv[4][4], Fv[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int ri = 4 * v + g;
+            const double Qr = __shfl(Qa, ri, 64), cfr = __shfl(cf, ri, 64), lser = __shfl(lse, ri, 64);
+            double fsum = 0.0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const double y = acc[t][v], yo = __shfl_xor(y, 1, 64);
+                const double y0 = q ? yo : y, y1 = q ? y : yo;
+                const double qf = Qr - (gi00 * y0 * y0 + 2.0 * gi01 * y0 * y1 + gi11 * y1 * y1);
+                const double g0 = gi00 * y0 + gi01 * y1, g1 = gi01 * y0 + gi11 * y1;
+                const double pi = exp(-K * log(qf) - lser);
+                const double f = cfr * pi * K / qf;
+                Cv[v][t] = f * (q ? g1 : g0);
+                if (!q) {  // each (row, shift) once
+                    S00 += f * g0 * g0;
+                    S01 += f * g0 * g1;
+                    S11 += f * g1 * g1;
+                    fsum += f;
+                }
+            }
+#pragma unroll
+            for (int o = 1; o <= 8; o <<= 1) fsum += __shfl_xor(fsum, o, 64);
+            Fv[v] = fsum;  // sum_j f of tile row 4v + g
+        }
+        // M += X^T C over the tile's rows: k-step s covers rows 4s .. 4s + 3
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const double *xr = A.X + (size_t)chunk_row(A, c0, nc, rt * 16 + 4 * s + g) * 2 * K;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const double xa = xr[16 * mt + i16];
+                Epart[mt] += Fv[s] * xa * xa;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) macc[mt][t] = mma_f64(xa, Cv[s][t], macc[mt][t]);
+            }
+        }
     }
+    // P_mq = sum_j (R_j^T M_(j,q))_m for m = 16 mt + 4v + g
+    double P[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int m = 16 * mt + 4 * v + g, k1 = m % K + 1;
+            // cos coordinate (m < K; a compile-time fact: 4v + g < 16), and the partner
+            // coordinate m -+ K: another tile (K >= 16) or another v (K = 8)
+            constexpr bool big = K >= 16;
+            const bool cosc = big ? mt < K / 16 : v < 2;
+            const int mtp = big ? (cosc ? mt + K / 16 : mt - K / 16) : mt;
+            const int vp = big ? v : (cosc ? v + 2 : v - 2);
+            double acc = 0.0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int j = 8 * t + (i16 >> 1), mi = (k1 * j) & (kMixS - 1);
+                const double Mv = macc[mt][t][v], Mp = macc[mtp][t][vp];
+                acc += cosc ? c_cs[mi] * Mv - c_sn[mi] * Mp : c_cs[mi] * Mv + c_sn[mi] * Mp;
+            }
+#pragma unroll
+            for (int o = 2; o <= 8; o <<= 1) acc += __shfl_xor(acc, o, 64);
+            P[mt][v] = acc;  // lanes with lane & 1 = q
+        }
+#pragma unroll
+    for (int o = 1; o <= 32; o <<= 1) {
+        S00 += __shfl_xor(S00, o, 64);
+        S01 += __shfl_xor(S01, o, 64);
+        S11 += __shfl_xor(S11, o, 64);
+        cs_acc += __shfl_xor(cs_acc, o, 64);
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        Epart[mt] += __shfl_xor(Epart[mt], 16, 64);
+        Epart[mt] += __shfl_xor(Epart[mt], 32, 64);  // E of coordinate 16 mt + i16
+    }
+    double *o = A.part + (size_t)c * A.pt_len;
+    if (lane == 0) o[2] = cs_acc;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int m = 16 * mt + 4 * v + g, k = m % K;
+            const double ak = Q.a[k];
+            const double Pq = P[mt][v], Po = __shfl_xor(Pq, 1, 64);
+            const double P0 = q ? Po : Pq, P1 = q ? Pq : Po;
+            const double V0 = Q.V[m][0], V1 = Q.V[m][1];
+            // dL/dV_mq
+            if ((i16 >> 1) == 0) o[3 + K + 2 * m + q] = 2.0 * ak * (Pq - (q ? V0 * S01 + V1 * S11 : V0 * S00 + V1 * S01));
+            // this coordinate's share of dL/dlog d_k, summed with its partner's in the cos lane
+            const double Em = __shfl(Epart[mt], 4 * v + g, 64);
+            const double term = Em - 2.0 * (V0 * P0 + V1 * P1) + V0 * V0 * S00 + 2.0 * V0 * V1 * S01 + V1 * V1 * S11;
+            constexpr bool big = K >= 16;
+            const bool cosc = big ? mt < K / 16 : v < 2;
+            const int mtp = big ? (cosc ? mt + K / 16 : mt - K / 16) : mt;
+            const int vp = big ? v : (cosc ? v + 2 : v - 2);
+            const int mp = cosc ? m + K : m - K;
+            const double Ppq = P[mtp][vp], Ppo = __shfl_xor(Ppq, 1, 64);
+            const double Pp0 = q ? Ppo : Ppq, Pp1 = q ? Ppq : Ppo;
+            const double W0 = Q.V[mp][0], W1 = Q.V[mp][1];
+            const double Ep = __shfl(Epart[mtp], (16 * mtp + 4 * vp + g) % 16, 64);
+            const double termp = Ep - 2.0 * (W0 * Pp0 + W1 * Pp1) + W0 * W0 * S00 + 2.0 * W0 * W1 * S01 + W1 * W1 * S11;
+            if (cosc && i16 == 0) o[3 + k] = ak * (term + termp);
+        }
 }
 
 // Per point: dL/dtheta = chunk sums (in order) - (1/2) csum d log|L0|/dtheta; dL/do.
@@ -646,15 +802,11 @@ LearnArgs args(tkdv_learner *L)
 template <int K>
 hipError_t launch_rows(tkdv_learner *L, const LearnArgs &A, hipStream_t st, bool bwd)
 {
-    const unsigned long long n = A.n;
-    if (n == 0) return hipSuccess;
-    if (!bwd) {
-        unsigned long long g = (n + 3) / 4;
-        g = std::min<unsigned long long>(g, 64ull * L->n_cu);
-        hipLaunchKernelGGL(k_mix_fwd<K>, dim3((unsigned)g), dim3(256), 0, st, A);
-    } else {
-        hipLaunchKernelGGL(k_mix_bwd<K>, dim3((A.n_chunks + 3) / 4), dim3(256), 0, st, A);
-    }
+    if (A.n == 0) return hipSuccess;
+    if (!bwd)
+        hipLaunchKernelGGL(k_mix_fwd_mm<K>, dim3((A.n_chunks + 3) / 4), dim3(256), 0, st, A);
+    else
+        hipLaunchKernelGGL(k_mix_bwd_mm<K>, dim3((A.n_chunks + 3) / 4), dim3(256), 0, st, A);
     return hipGetLastError();
 }
 
@@ -960,7 +1112,7 @@ tkdv_status tkdv_learner_set_points(tkdv_learner *L, int32_t n_points, const tkd
 tkdv_status tkdv_learner_add_rows(tkdv_learner *L, int32_t point, const float *d_xhat, uint64_t row_stride,
                                   uint64_t n, int32_t kind, void *stream)
 {
-    if (!L || (n > 0 && !d_xhat) || point < 0 || point >= L->n_points || (kind != 0 && kind != 1) ||
+    if (!L || (n > 0 && !d_xhat) || point < 0 || point >= L->n_points || (kind < 0 || kind > 2) ||
         row_stride < (uint64_t)(2 * L->K))
         return record_error(TKDV_E_ARG, "invalid rows");
     if (n == 0) return TKDV_OK;
@@ -978,14 +1130,14 @@ tkdv_status tkdv_learner_add_rows(tkdv_learner *L, int32_t point, const float *d
     LTRY(hipStreamSynchronize(st));
     L->n_rows += n;
     L->h_row_point.insert(L->h_row_point.end(), n, point);
-    if (kind == 0) L->n_acc[point] += n;
+    if (kind != 1) L->n_acc[point] += n;
     return upload_points(L, st);
 }
 
 tkdv_status tkdv_learner_add_rows_host(tkdv_learner *L, int32_t point, const double *h_xhat, uint64_t n,
                                        int32_t kind)
 {
-    if (!L || (n > 0 && !h_xhat) || point < 0 || point >= L->n_points || (kind != 0 && kind != 1))
+    if (!L || (n > 0 && !h_xhat) || point < 0 || point >= L->n_points || (kind < 0 || kind > 2))
         return record_error(TKDV_E_ARG, "invalid rows");
     if (n == 0) return TKDV_OK;
     LTRY(hipSetDevice(L->device));
@@ -1015,14 +1167,14 @@ tkdv_status tkdv_learner_add_rows_host(tkdv_learner *L, int32_t point, const dou
     LTRY(hipDeviceSynchronize());
     L->n_rows += n;
     L->h_row_point.insert(L->h_row_point.end(), n, point);
-    if (kind == 0) L->n_acc[point] += n;
+    if (kind != 1) L->n_acc[point] += n;
     return upload_points(L, nullptr);
 }
 
 tkdv_status tkdv_learner_add_shifted_rows(tkdv_learner *L, int32_t point, const double *h_xhat, uint64_t n,
                                           const double *h_phi, int32_t n_phi, int32_t kind)
 {
-    if (!L || (n > 0 && (!h_xhat || !h_phi)) || point < 0 || point >= L->n_points || (kind != 0 && kind != 1) ||
+    if (!L || (n > 0 && (!h_xhat || !h_phi)) || point < 0 || point >= L->n_points || (kind < 0 || kind > 2) ||
         n_phi < 1 || n_phi > 4096 || n > (1ull << 32))
         return record_error(TKDV_E_ARG, "invalid rows or phases");
     if (n == 0) return TKDV_OK;
@@ -1062,7 +1214,7 @@ tkdv_status tkdv_learner_add_shifted_rows(tkdv_learner *L, int32_t point, const 
     LTRY(hipDeviceSynchronize());
     L->n_rows += n_new;
     L->h_row_point.insert(L->h_row_point.end(), n_new, point);
-    if (kind == 0) L->n_acc[point] += n_new;
+    if (kind != 1) L->n_acc[point] += n_new;
     return upload_points(L, nullptr);
 }
 

@@ -61,16 +61,23 @@ def plan_mixtures(ctx: T.Context, points: list, sigma_plans: list, mixes: list, 
 
 def fit(ctx: T.Context, points: list, cfg: T.LearnerCfg, samples_per_point: int = 4096, rounds: int = 8,
         steps: int = 150, max_proposals: int = 1 << 32, n_shift_copies: int = 7, margin: float = 0.0,
-        precision: int = T.BF16X3, log=None, planner: str = "gpu") -> FitResult:
+        precision: int = T.BF16X3, log=None, planner: str = "gpu", nll_samples_per_point: int = 0) -> FitResult:
+    """nll_samples_per_point > samples_per_point: that many accepted samples per
+    point, the first samples_per_point in both terms of the loss (kind 0), the
+    rest in the likelihood term only (kind 2)."""
     sps = [T.plan_point(p, T.SIGMA) for p in points]
     L = T.Learner(ctx, cfg)
     L.set_points(points, sps)
+    n_draw = max(samples_per_point, nll_samples_per_point)
     for i, (pt, sp) in enumerate(zip(points, sps)):
-        r = ctx.sample(pt, samples_per_point, proposal=T.SIGMA, plan=sp, mode=T.COUNT_ACCEPTED,
-                       max_proposals=max_proposals, precision=precision, capacity=samples_per_point)
+        r = ctx.sample(pt, n_draw, proposal=T.SIGMA, plan=sp, mode=T.COUNT_ACCEPTED,
+                       max_proposals=max_proposals, precision=precision, capacity=n_draw)
         if r["n_written"] == 0:
             raise RuntimeError(f"point {i}: no accepted sample within {max_proposals} proposals")
-        L.add_rows(i, r["xhat"], kind=0)
+        L.add_rows(i, r["xhat"][:samples_per_point], kind=0)
+        if r["n_written"] > samples_per_point:
+            L.add_rows(i, r["xhat"][samples_per_point:], kind=2)
+        del r
     res = FitResult(L, points, sps)
     S = T.MIX_S
     fracs = [2 * math.pi * (q + 1) / ((n_shift_copies + 1) * S) for q in range(n_shift_copies)]

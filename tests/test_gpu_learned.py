@@ -79,11 +79,12 @@ def _setup_small(T, ctx, K=8, H=12, seed=2):
     L.set_points(pts, sps)
     rows, kinds = [], []
     for i in range(len(pts)):
-        X = rng.standard_normal((9, 2 * K))
+        X = rng.standard_normal((41, 2 * K))   # more than one chunk of 32 rows
         X /= np.linalg.norm(X, axis=1)[:, None]
-        kd = [0] * 6 + [1] * 3
-        L.add_rows(i, X[:6], kind=0)
-        L.add_rows(i, X[6:], kind=1)
+        kd = [0] * 20 + [2] * 14 + [1] * 7
+        L.add_rows(i, X[:20], kind=0)
+        L.add_rows(i, X[20:34], kind=2)
+        L.add_rows(i, X[34:], kind=1)
         rows.append(X)
         kinds.append(kd)
     plans = [(sp.alpha_star, np.array(sp.sigma2[:K])) for sp in sps]
@@ -91,8 +92,13 @@ def _setup_small(T, ctx, K=8, H=12, seed=2):
     return L, cfg, W, opts, plans, rows, kinds
 
 
-def test_loss_and_gradients_against_oracle(T, ctx):
-    K, H = 8, 12
+@pytest.mark.parametrize("K", [8, 16, 32])
+def test_loss_and_gradients_against_oracle(T, ctx, K):
+    """Loss, dL/d(log d, V) against central differences of the oracle's loss
+    for every K of the learner (its matrix-product kernels branch on K), with
+    rows of all three kinds over more than one chunk; dL/dweights on a sample
+    of coordinates."""
+    H = 12
     L, cfg, W, opts, plans, rows, kinds = _setup_small(T, ctx, K, H)
     loss, gmix, gw = L.gradients()
     eps, T_, lam = cfg.eps, cfg.temperature, cfg.nll_weight
