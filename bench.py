@@ -3,12 +3,13 @@
 
 Default workload (--workload learned): accepted samples/s at K = 32 with the
 learned defensive-mixture proposal against the paper's Sigma proposal.
-  * before the timed region: the network (3 -> 256 -> 256 -> 5K, FP64 on the
-    GPU) is fitted on 16 training points (beta' = linspace(20, 60, 16),
-    C3/C2 = 9000/beta') from the paper's sampler's accepted samples, and the
-    plans of the evaluation points are made: alpha*, M_Sigma (the paper's
-    step 1) and M_mix of the network's mixture (multi-start L-BFGS of f/q_mix
-    on the GPU);
+  * before the timed region: eight networks (3 -> 256 -> 256 -> 5K, FP64 on
+    the GPU, initialisation seeds 1..8) are fitted on 16 training points
+    (beta' = linspace(20, 60, 16), C3/C2 = 9000/beta') from the paper's
+    sampler's accepted samples, and the plans of the evaluation points are
+    made: alpha*, M_Sigma (the paper's step 1) and M_mix of every network's
+    mixture (multi-start L-BFGS of f/q_mix on the GPU); each point samples
+    with the network whose M_mix there is smallest (acceptance is Z/M_mix);
   * one step: 32 evaluation points (the 16 beta' at beta' C3/C2 = 9000 and
     12000, seeds not used in training), 1e9 proposals per point with the
     mixture sampler, then 1e9 per point with the paper's sampler (one batched
@@ -589,16 +590,18 @@ def learned_bench(args) -> int:
     seeds = [int(v) for v in args.train_seeds.split(",")]
     cfgs = [T.learner_cfg(K, hidden=256, eps=W.LEARNED_EPS, v_amp=0.5, v_scale=1.0, lr=3e-3, seed=sd) for sd in seeds]
     t0 = time.perf_counter()
-    res = learned.fit_best(ctx, train, cfgs, samples_per_point=4096, rounds=args.train_rounds,
-                           steps=args.train_steps, max_proposals=1 << 36, precision=prec,
-                           log=lambda m: print("train " + m, file=sys.stderr, flush=True))
+    ens = learned.fit_ensemble(ctx, train, cfgs, samples_per_point=4096, rounds=args.train_rounds,
+                               steps=args.train_steps, max_proposals=1 << 36, precision=prec,
+                               log=lambda m: print("train " + m, file=sys.stderr, flush=True))
     train_s = time.perf_counter() - t0
-    train_gain = math.exp(float(np.mean(res.history[res.best_round]["log_gain"])))
+    train_gains = [math.exp(float(np.mean(r.history[r.best_round]["log_gain"]))) for r in ens]
 
     specs = W.learned_eval_points()
     pts = [T.make_point(s.K, s.E0, s.beta_p, s.c32, seed=s.seed, point_id=s.point_id) for s in specs]
     t0 = time.perf_counter()
-    mixes, mplans, splans = learned.plan_for_points(ctx, res, pts, margin=0.02)   # M_mix searched on the GPU
+    # M_mix of every network at every point (searched on the GPU); each point samples with the
+    # network whose M_mix there is smallest
+    mixes, mplans, splans, chosen = learned.plan_for_points_ensemble(ctx, ens, pts, margin=0.02)
     plan_s = time.perf_counter() - t0
     log_gain = [learned.log_M_sigma_normalised(sp) - pl.log_M for sp, pl in zip(splans, mplans)]
     n_per = int(args.proposals)
@@ -694,13 +697,15 @@ def learned_bench(args) -> int:
         "data": "synthetic",
         "config": {
             "workload": "learned mixture vs plain Sigma: K=32, N=128, E0=1, 16 beta' in [20, 60] x "
-                        "beta'C3/C2 in {9000, 12000} (32 points), 1e9 proposals/point per sampler; network "
-                        "3-256-256-160 fitted on beta'C3/C2 = 9000 (other seeds), eps = 0.2",
+                        "beta'C3/C2 in {9000, 12000} (32 points), 1e9 proposals/point per sampler; networks "
+                        "3-256-256-160 fitted on beta'C3/C2 = 9000 (other seeds), eps = 0.2; per point the "
+                        "network with the smallest rejection constant",
             "K": K, "N": 4 * K, "points": len(pts), "proposals_per_point": n_per,
             "synthesis": args.precision, "fp64_redecision": True,
         },
-        "training": {"seconds": train_s, "seeds_tried": seeds, "seed_kept": res.learner.cfg.seed,
-                     "train_points_M_gain": train_gain, "best_round": res.best_round},
+        "training": {"seconds": train_s, "network_seeds": seeds, "train_points_M_gain": train_gains,
+                     "networks_chosen": [seeds[c] for c in chosen],
+                     "selection": "per evaluation point, the network with the smallest M_mix (plan time)"},
         "plain_value": acc_p / dt_p,
         "ratio_vs_plain": (acc_m / dt_m) / (acc_p / dt_p) if acc_p else None,
         "proposals_per_s": n_prop / dt_m,
@@ -718,7 +723,8 @@ def learned_bench(args) -> int:
         "cpu_baseline_plain": cpu_plain,
     }
     print(json.dumps(line), flush=True)
-    res.learner.close()
+    for r in ens:
+        r.learner.close()
     ctx.close()
     return 0
 
@@ -836,8 +842,9 @@ def main() -> int:
                     help="oracle proposals per point (0: skip; default 2^22 plain, 2^17 learned)")
     ap.add_argument("--train-rounds", type=int, default=6)
     ap.add_argument("--train-steps", type=int, default=150)
-    ap.add_argument("--train-seeds", default="5,7,11,23",
-                    help="network initialisations tried; the best on the training points is kept")
+    ap.add_argument("--train-seeds", default="1,2,3,4,5,6,7,8",
+                    help="network initialisations trained; each evaluation point samples with the network "
+                         "whose rejection constant there is smallest")
     ap.add_argument("--synthesis", action="store_true",
                     help="only time the standalone synthesis kernel (K = 64, N = 256, 2^20 rows of x^ "
                          "in HBM) for FP32, BF16 and BF16x3 products; prints one JSON line")

@@ -112,24 +112,36 @@ def fit(ctx: T.Context, points: list, cfg: T.LearnerCfg, samples_per_point: int 
     return res
 
 
-def fit_best(ctx: T.Context, points: list, cfgs: list, log=None, **kw) -> FitResult:
-    """fit() from several network initialisations (cfgs differ in their seed);
-    keeps the one whose best round has the largest mean log M_Sigma/M_mix over
-    the training points (only training points enter the choice)."""
-    best, best_gain = None, -math.inf
+def fit_ensemble(ctx: T.Context, points: list, cfgs: list, log=None, **kw) -> list:
+    """fit() from several network initialisations (cfgs differ in their seed):
+    the trained networks, all kept (a point's proposal is chosen among them by
+    its rejection constant, plan_for_points_ensemble)."""
+    out = []
     for cfg in cfgs:
         res = fit(ctx, points, cfg, log=log, **kw)
-        gain = res.history[res.best_round]["log_gain"]
-        g = float(np.mean(gain))
         if log:
+            g = float(np.mean(res.history[res.best_round]["log_gain"]))
             log(f"initialisation seed {cfg.seed}: mean M_Sigma/M_mix {math.exp(g):.2f} over the training points")
-        if g > best_gain:
-            if best is not None:
-                best.learner.close()
-            best, best_gain = res, g
-        else:
-            res.learner.close()
-    return best
+        out.append(res)
+    return out
+
+
+def plan_for_points_ensemble(ctx: T.Context, results: list, points: list, margin: float = 0.02,
+                             planner: str = "gpu"):
+    """Per point, the mixture of the network whose rejection constant M_mix at
+    that point is smallest: a point's acceptance is Z/M_mix with Z the same for
+    every proposal of the point, so the smallest M gives the highest acceptance
+    (plan-time quantities only; every candidate's samples are exact).
+    Returns (mixtures, mixture plans, Sigma plans, index of the chosen network)."""
+    cands = [plan_for_points(ctx, r, points, margin=margin, planner=planner) for r in results]
+    mixes, plans, sps, chosen = [], [], [], []
+    for i in range(len(points)):
+        e = min(range(len(cands)), key=lambda c: cands[c][1][i].log_M)
+        mixes.append(cands[e][0][i])
+        plans.append(cands[e][1][i])
+        sps.append(cands[e][2][i])
+        chosen.append(e)
+    return mixes, plans, sps, chosen
 
 
 def plan_for_points(ctx: T.Context, res_or_learner, points: list, margin: float = 0.02, planner: str = "gpu"):
