@@ -3,11 +3,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/tkdv.h"
@@ -1352,7 +1354,7 @@ tkdv_status tkdv_plan_batch(tkdv_ctx *ctx, int32_t n_points, const tkdv_point *p
     if (flags & ~TKDV_PLAN_SEARCH_ALWAYS) return set_err(ctx, TKDV_E_ARG, "unknown flags");
     if ((int64_t)n_points * n_starts > (int64_t)(1 << 30)) return set_err(ctx, TKDV_E_ARG, "too many starts");
     std::vector<PlanPoint> pp;
-    std::vector<int> which;
+    std::vector<int> which, on_host;
     for (int p = 0; p < n_points; ++p) {
         const int st = plan_base_host(&pts[p], proposal, &out[p]);
         if (st != TKDV_OK)
@@ -1362,9 +1364,7 @@ tkdv_status tkdv_plan_batch(tkdv_ctx *ctx, int32_t n_points, const tkdv_point *p
         const tkdv_point &q = pts[p];
         const int K = q.K;
         if (K > 64) {  // one wave holds at most 128 coordinates: the host search instead
-            const int hs = plan_point_host(&q, proposal, 2, &out[p]);
-            if (hs != TKDV_OK)
-                return set_err(ctx, (tkdv_status)hs, "point " + std::to_string(p) + ": planning failed");
+            on_host.push_back(p);
             continue;
         }
         PlanPoint P{};
@@ -1379,6 +1379,22 @@ tkdv_status tkdv_plan_batch(tkdv_ctx *ctx, int32_t n_points, const tkdv_point *p
         P.a = out[p].alpha_star * q.beta_p / ((double)K * K * K);
         pp.push_back(P);
         which.push_back(p);
+    }
+    if (!on_host.empty()) {  // the host searches of K > 64, on all host threads
+        std::vector<int> hst(on_host.size(), TKDV_OK);
+        std::atomic<size_t> next{0};
+        auto work = [&]() {
+            for (size_t q; (q = next.fetch_add(1)) < on_host.size();)
+                hst[q] = plan_point_host(&pts[on_host[q]], proposal, 2, &out[on_host[q]]);
+        };
+        const size_t nt = std::min<size_t>(on_host.size(), std::max(1u, std::thread::hardware_concurrency()));
+        std::vector<std::thread> pool;
+        for (size_t t = 1; t < nt; ++t) pool.emplace_back(work);
+        work();
+        for (std::thread &t : pool) t.join();
+        for (size_t q = 0; q < on_host.size(); ++q)
+            if (hst[q] != TKDV_OK)
+                return set_err(ctx, (tkdv_status)hst[q], "point " + std::to_string(on_host[q]) + ": planning failed");
     }
     if (which.empty()) return TKDV_OK;
     std::vector<double> val, xb;
@@ -2187,9 +2203,9 @@ tkdv_status tkdv_autotune(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, co
     for (int p = 0; p < np; ++p) {
         const double bp = 20.0 + 40.0 * p / (np - 1);
         pts[p] = tkdv_point{K, (uint32_t)p, 1.0, bp, 6000.0 * (K / 32.0) * (K / 32.0) / bp, 1234567ull + p};
-        tkdv_status s = (tkdv_status)plan_point_host(&pts[p], TKDV_PROP_SIGMA, 0, &plans[p]);
-        if (s != TKDV_OK) return set_err(ctx, s, "autotune planning failed");
     }
+    if (tkdv_plan_batch(ctx, np, pts.data(), TKDV_PROP_SIGMA, 16, 7, 0, plans.data(), nullptr, nullptr) != TKDV_OK)
+        return set_err(ctx, TKDV_E_DEVICE, "autotune planning failed: " + ctx->last_error);
     std::vector<tkdv_stats> st(np);
     tkdv_launch_cfg best{0, 1, 1ull << 26, 0, 1};
     double best_rate = -1.0;

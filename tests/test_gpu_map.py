@@ -97,6 +97,16 @@ def test_map_k64_fp32_cell(T, ctx):
     check_cell(T, cells[0], K, E0, seed, pid0, 200, 10**7)
 
 
+def test_map_k128_cells(T, ctx):
+    """K = 128 (N = 512): two cells planned by the host search on parallel
+    threads, sampled by the quarter-period kernels; each against the oracle."""
+    K, E0, seed, pid0 = 128, 1.0, 9, 4000
+    cells = ctx.extremes_map(K, E0, [20.0, 40.0], [40.0], 100, 10**7, seed=seed, point_id0=pid0,
+                             precision=T.BF16X3)
+    for q, cell in enumerate(cells):
+        check_cell(T, cell, K, E0, seed, pid0 + q, 100, 10**7)
+
+
 def test_map_arguments(T, ctx):
     with pytest.raises(T.TkdvError):
         ctx.extremes_map(16, 1.0, [], [0.0], 10, 100)
