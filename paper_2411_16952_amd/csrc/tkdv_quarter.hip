@@ -34,7 +34,6 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 namespace {
 
-constexpr int K128 = 128;
 constexpr int kTile16 = 16;            // proposals per wave tile
 
 // Sizes of the quarter-period form at K (64 or 128): CPL coordinates of each
@@ -106,11 +105,11 @@ __device__ __forceinline__ void add0(unsigned long long *ctr, unsigned long long
     if (bcast0(v) != 0ull) atomicAdd(ctr, lane == 0 ? v : 0ull);
 }
 
-// Block b (0: cos, 1: sin) of proposal i for this lane: the 32 coordinates of
-// modes 32 g + 1 .. 32 g + 32 (coordinate m from word m, Box-Muller on word
-// pairs; X = Sigma^{1/2} z for the paper's proposal), and their contributions
-// to |X|^2, sum (j+1) X^2 and sum (j+1)^2 X^2 (t = sum k^2 X_k^2 over both
-// blocks, k = 32 g + j + 1).
+// Block b (0: cos, 1: sin) of proposal i for this lane: the K/4 coordinates
+// of modes K g/4 + 1 .. K g/4 + K/4 (coordinate m from word m, Box-Muller on
+// word pairs; X = Sigma^{1/2} z for the paper's proposal), and their
+// contributions to |X|^2, sum (j+1) X^2 and sum (j+1)^2 X^2 (t = sum k^2 X_k^2
+// over both blocks, k = K g/4 + j + 1).
 template <int K, int PROP>
 __device__ __forceinline__ void gen_block128(const DevPoint &P, uint32_t c0, uint32_t c1, int g, int b,
                                              float (&v)[K / 4], float &r2, float &a1, float &a2)
@@ -156,7 +155,7 @@ __device__ __forceinline__ float finish_norm128(int g, float r2, float a1, float
     return inv;
 }
 
-// Proposal i of the point: this lane's 32 cos and 32 sin coordinates of X
+// Proposal i of the point: this lane's K/4 cos and K/4 sin coordinates of X
 // (words 0..2K-1 as in every sampler: coordinate m from word m, Box-Muller on
 // word pairs; X = Sigma^{1/2} z for the paper's proposal), |X|^-1, t of the
 // projected point and the acceptance word (word 2K).  With NORMALIZE the
@@ -212,7 +211,7 @@ __device__ __forceinline__ void quarter_operand(const float (&v)[N], int odd, in
     lo = __builtin_bit_cast(bf16x8, wl);
 }
 
-// S3 = sum over the N = 512 offset-grid values of u~^3 for this lane's share
+// S3 = sum over the N = 4K offset-grid values of u~^3 for this lane's share
 // (the caller sums the four lanes), from unprojected coordinates, FP32 products.
 template <int K>
 __device__ __forceinline__ float cube_sum_q128_f32(const float (&c)[K / 4], const float (&s)[K / 4],
