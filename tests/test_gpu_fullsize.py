@@ -1,8 +1,9 @@
 """Parity at full size, in the benchmark's launch configurations.
 
-The samplers run 1e9 proposals per point (the plain GPU and learned
-configurations): the paper's sampler as one batched launch over two K = 32
-points, the mixture sampler on one K = 32 point, and SIR over the same
+The samplers run 1e9 proposals per point (the plain GPU, K = 64, K = 128 and
+learned configurations): the paper's sampler as one batched launch over two
+K = 32 points and on one K = 64 and one K = 128 point (the quarter-period
+kernels), the mixture sampler on one K = 32 point, and SIR over the same
 proposals as the rejection sampler.  The oracle then checks
 sampled outputs one by one: 600 random proposal indices over the whole range
 (decision and, for accepted ones, the stored row), and 300 random accepted
@@ -92,6 +93,33 @@ def test_plain_batch_1e9(T, ctx):
         _check_sampled(o, decide, N_PROP, rng, f"plain beta'={p.beta_p}")
         acc = o["n_accepted"] / N_PROP
         assert 1e-4 < acc < 1e-2
+
+
+@pytest.mark.parametrize("K", [64, 128])
+def test_quarter_period_1e9(T, ctx, K):
+    """The quarter-period path (K = 64, 128) at the benchmarks' size: one point
+    of the K = 64 / K = 128 workloads (the one of lowest acceptance), 1e9
+    proposals in one launch; sampled decisions and rows against the oracle, and
+    the statistics by Parseval (every sample has grid mean 0 and grid mean
+    square E0/pi, so S1 = 0 and S2 = n_grid E0/pi)."""
+    from paper_2411_16952_amd import workloads as W
+    spec = (W.k64_points() if K == 64 else W.k128_points())[-1]
+    pt = T.make_point(spec.K, spec.E0, spec.beta_p, spec.c32, seed=spec.seed, point_id=spec.point_id)
+    pl = T.plan_point(pt, T.SIGMA)
+    o = ctx.sample(pt, N_PROP, proposal=T.SIGMA, plan=pl, precision=T.BF16X3, capacity=1 << 22)
+    assert o["n_proposed"] == N_PROP and o["n_M_violations"] == 0
+    rng = np.random.default_rng(7 + K)
+
+    def decide(i):
+        return oracle.proposal(K, pt.E0, pt.beta_p, pt.c32, 1, pl.alpha_star, pl.log_M, pt.seed, pt.point_id, i)
+
+    _check_sampled(o, decide, N_PROP, rng, f"K={K}")
+    n_grid = o["n_grid_values"]
+    assert n_grid == o["n_accepted"] * 4 * K
+    assert abs(o["S2"] / n_grid - pt.E0 / math.pi) < 1e-6 * pt.E0 / math.pi
+    assert abs(o["S1"]) < 1e-6 * n_grid * math.sqrt(pt.E0 / math.pi)
+    assert 0 < o["n_samples_4sigma"] <= o["n_accepted"] and o["peak_u"] > 4 * math.sqrt(pt.E0 / math.pi)
+    assert o["peak_u"] <= math.sqrt(2 * K * pt.E0 / math.pi) * (1 + 1e-6)   # the Dirichlet bound
 
 
 def test_mixture_1e9(T, ctx):
