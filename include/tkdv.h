@@ -42,8 +42,7 @@
  * host memory.  `stream` is a hipStream_t (NULL = the default stream); calls
  * are stream-ordered and return after the host-side statistics are complete.
  * Supported mode counts on the GPU: K in {8, 16, 32, 64, 128}, grid N = 4K
- * (the learned mixture K <= 32; SIR, the extreme-wave search and the
- * standalone synthesis K <= 64).  At K = 128 the grid sum of cubes behind H3
+ * (the learned mixture K <= 32; SIR and the standalone synthesis K <= 64).  At K = 128 the grid sum of cubes behind H3
  * is formed on the grid offset by half a step (exact there as well, N >= 3K+1)
  * from a quarter of it: the cos and sin blocks and the even and odd modes are
  * synthesised separately, and the four quadrants follow by symmetry.
@@ -250,11 +249,13 @@ tkdv_status tkdv_plan_batch(tkdv_ctx *ctx, int32_t n_points, const tkdv_point *p
  * Extreme wave fields among stored samples (Sec. V: the largest surface
  * displacement among individual samples, against 4 sigma = 4 sqrt(E0/pi)).
  * For each row x^ of d_xhat, u = sqrt(2 E0/pi) Phi^T x^ on the grid
- * xi_j = -pi + 2 pi j/N, N = 4K (FP32 matrix products); its maximum u_max and
+ * xi_j = -pi + 2 pi j/N, N = 4K (FP32 matrix products, at K >= 64 in the
+ * quarter-period form: values at xi, -xi, pi - xi, xi - pi from the cos/sin
+ * sums over even and odd modes at xi in [0, pi/2)); its maximum u_max and
  * the first grid index j attaining it.  Returns the top_k rows by u_max
  * (descending, ties by lower row index) and the number of rows with
  * u_max > threshold.
- *   K in {8,16,32,64}; E0 > 0; d_xhat: device [n][row_stride] floats, 16-byte
+ *   K in {8,16,32,64,128}; E0 > 0; d_xhat: device [n][row_stride] floats, 16-byte
  *     aligned, row_stride >= 2K and a multiple of 4 (the sampler's rows);
  *   top_k in [0, TKDV_EXTREMES_MAX_K]; h_rows, h_umax, h_jmax: host arrays
  *     [top_k] (entries beyond n are UINT64_MAX, NaN, -1); h_n_exceed: host;

@@ -1509,7 +1509,7 @@ tkdv_status tkdv_extremes(tkdv_ctx *ctx, int32_t K, double E0, const float *d_xh
                           uint64_t *h_n_exceed, float *d_umax, int32_t *d_jmax, void *stream)
 {
     if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");
-    if (kindex(K) < 0 || K > 64) return set_err(ctx, TKDV_E_UNSUPPORTED, "tkdv_extremes supports K in {8,16,32,64}");
+    if (kindex(K) < 0) return set_err(ctx, TKDV_E_UNSUPPORTED, "tkdv_extremes supports K in {8,16,32,64,128}");
     if (!std::isfinite(E0) || !(E0 > 0.0)) return set_err(ctx, TKDV_E_ARG, "E0 must be finite and > 0");
     if (top_k < 0 || top_k > TKDV_EXTREMES_MAX_K) return set_err(ctx, TKDV_E_ARG, "top_k out of range");
     if (top_k > 0 && (!h_rows || !h_umax || !h_jmax)) return set_err(ctx, TKDV_E_ARG, "NULL output array");
@@ -1543,7 +1543,7 @@ tkdv_status tkdv_extremes(tkdv_ctx *ctx, int32_t K, double E0, const float *d_xh
     ea.xhat = d_xhat;
     ea.n = n;
     ea.stride = row_stride;
-    ea.phi_f32 = ctx->phi_f32[ki].p;
+    ea.phi_f32 = ki >= 3 ? ctx->qstat[ki - 3].p : ctx->phi_f32[ki].p;  // quarter-period statistics tables
     ea.amp = (float)std::sqrt(2.0 * E0 / kPi);
     ea.threshold = (float)threshold;
     ea.keys = (uint32_t *)ctx->ext_keys.p;

@@ -6,12 +6,12 @@
 
 namespace tkdv {
 
-constexpr int kExtBlock = 256;  // threads per workgroup of k_grid_max
+constexpr int kExtBlock = 256;  // threads per workgroup of k_grid_max (K <= 32)
 
 struct ExtArgs {
     const float *xhat;          // [n][stride] rows of x^ (first 2K entries used)
     unsigned long long n, stride;
-    const void *phi_f32;        // FP32 synthesis tables of K
+    const void *phi_f32;        // FP32 synthesis tables of K (K = 64, 128: quarter-period statistics tables)
     float amp;                  // sqrt(2 E0/pi)
     float threshold;            // rows with max u above it are counted
     uint32_t *keys;             // [n] order-preserving keys of the maxima

@@ -9,6 +9,10 @@
   of the threshold.
 * The Dirichlet kernel planted among random rows is the first, with
   u_max = sqrt(2 K E0/pi) at xi = 0; duplicated rows keep the lower row first.
+* Dirichlet kernels centred on every grid point (each row's maximum is
+  unique, sqrt(2 K E0/pi) at its centre): the grid index of every row is its
+  centre, which covers each branch of the quarter-period form (xi, -xi,
+  pi - xi, xi - pi, +-pi/2) at K = 64 and 128, in rows with a padded stride.
 * Rows from the sampler's own output (row stride 2 KMAX), ragged sizes, empty
   input, top_k beyond n, and argument errors.
 """
@@ -81,7 +85,8 @@ def _check(res, ref, top_k, thr, x64, E0, N, label):
         assert np.array_equal(res["jmax"], jm_g[rows])
 
 
-@pytest.mark.parametrize("K,n,E0", [(8, 100_003, 1.0), (16, 40_001, 2.0), (32, 20_011, 1.0), (64, 5_003, 0.5)])
+@pytest.mark.parametrize("K,n,E0", [(8, 100_003, 1.0), (16, 40_001, 2.0), (32, 20_011, 1.0), (64, 5_003, 0.5),
+                                    (128, 2_503, 1.5)])
 def test_random_rows_against_oracle(T, ctx, K, n, E0):
     import torch
     x64 = _rows(K, n, seed=K)
@@ -144,3 +149,26 @@ def test_edges_and_errors(T, ctx):
     wide = torch.zeros((4, 2 * K + 4), dtype=torch.float32, device="cuda")
     with pytest.raises(T.TkdvError):
         ctx.extremes(wide[:, 1:], K)                                                       # unaligned rows
+
+
+@pytest.mark.parametrize("K", [8, 16, 32, 64, 128])
+def test_centred_kernels_every_grid_index(T, ctx, K):
+    import torch
+    E0, N = 1.25, 4 * K
+    stride = 2 * K + 4
+    k = np.arange(1, K + 1)
+    xi0 = -np.pi + 2 * np.pi * np.arange(N) / N
+    x64 = np.zeros((N, stride))
+    x64[:, :K] = np.cos(np.outer(xi0, k)) / np.sqrt(K)       # u(xi) = amp sum_k cos k (xi - xi0)/sqrt K
+    x64[:, K:2 * K] = np.sin(np.outer(xi0, k)) / np.sqrt(K)
+    x = torch.from_numpy(x64.astype(np.float32)).cuda()
+    res = ctx.extremes(x[:, :2 * K], K, E0, top_k=N, per_row=True)
+    assert x[:, :2 * K].stride(0) == stride
+    jm = res["jmax_rows"].cpu().numpy()
+    um = res["umax_rows"].cpu().numpy().astype(np.float64)
+    cap = math.sqrt(2 * K * E0 / math.pi)
+    say(f"K={K}: {np.sum(jm == np.arange(N))}/{N} centres found, max |u_max - cap| {np.abs(um - cap).max():.2e}")
+    assert np.array_equal(jm, np.arange(N))
+    assert np.abs(um - cap).max() <= TOL * cap
+    ref = oracle.extremes(x64[:, :2 * K].astype(np.float32).astype(np.float64), E0, N, 0, cap)
+    assert np.array_equal(ref["jmax"], np.arange(N))
