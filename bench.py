@@ -159,6 +159,7 @@ def kernel_source_digest(files=("tkdv_device.h", "tkdv_kernels.hip")) -> str:
 
 
 SYNTH_SOURCES = ("tkdv_device.h", "tkdv_synth.hip")
+QUARTER_SOURCES = ("tkdv_device.h", "tkdv_quarter.h", "tkdv_quarter.hip")
 
 
 def load_traffic(K: int, precision: str, proposals_per_launch: int, kernel: str = "k_decide"):
@@ -171,7 +172,7 @@ def load_traffic(K: int, precision: str, proposals_per_launch: int, kernel: str 
         return None
     with open(path) as f:
         d = json.load(f)
-    src = ("tkdv_device.h", "tkdv_quarter.hip") if kernel == "k_decide128" else ("tkdv_device.h", "tkdv_kernels.hip")
+    src = QUARTER_SOURCES if kernel == "k_decide128" else ("tkdv_device.h", "tkdv_kernels.hip")
     if d.get("kernel_source_digest") != kernel_source_digest(src):
         return None
     return d["bytes_per_proposal"] * proposals_per_launch

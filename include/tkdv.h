@@ -42,7 +42,7 @@
  * host memory.  `stream` is a hipStream_t (NULL = the default stream); calls
  * are stream-ordered and return after the host-side statistics are complete.
  * Supported mode counts on the GPU: K in {8, 16, 32, 64, 128}, grid N = 4K
- * (the learned mixture K <= 32; SIR and the standalone synthesis K <= 64).  At K = 128 the grid sum of cubes behind H3
+ * (the learned mixture K <= 32).  At K = 128 the grid sum of cubes behind H3
  * is formed on the grid offset by half a step (exact there as well, N >= 3K+1)
  * from a quarter of it: the cos and sin blocks and the even and odd modes are
  * synthesised separately, and the four quadrants follow by symmetry.
@@ -291,14 +291,19 @@ typedef struct {
  * FP32 with FP32 or BF16x3 synthesis; M cancels in every normalised result).
  * Systematic resampling: draw r = 0..m-1 takes the first proposal whose
  * cumulative weight exceeds (u0 + r) W/m (cumulative sums in FP64, in
- * proposal order, monotone by construction).
+ * proposal order, monotone by construction).  The grid moments are over
+ * xi_j = -pi + 2 pi j/N; at K = 128 they come from the quarter-period
+ * syntheses of the weight, on the grid offset by half a step, where sums of
+ * u^p, p <= 3, are the same and u^4's differs by a closed form in the top
+ * mode's two coordinates, which is added.
+ *   K in {8, 16, 32, 64, 128};
  *   proposal UNIFORM or SIGMA; plan NULL plans internally; 1 <= n < 2^40;
  *   u0 in [0, 1); d_index: device [m] proposal indices (non-decreasing),
  *   required when m > 0; d_xhat: device [m][2K] rows of the drawn proposals
  *   or NULL; d_weight: device [n] weights or NULL; h_stats: host.
  *   stream: HIP stream (NULL: the null stream); the call returns after it.
- * Errors: TKDV_E_ARG, TKDV_E_UNSUPPORTED (K, BF16 precision, all weights
- * zero with m > 0), TKDV_E_DEVICE.
+ * Errors: TKDV_E_ARG, TKDV_E_UNSUPPORTED (BF16 precision, all weights zero
+ * with m > 0), TKDV_E_DEVICE.
  */
 tkdv_status tkdv_sir(tkdv_ctx *ctx, const tkdv_point *pt, tkdv_proposal proposal, const tkdv_plan *plan, uint64_t n,
                      uint64_t m, double u0, tkdv_precision precision, uint64_t *d_index, float *d_xhat,
@@ -381,7 +386,9 @@ tkdv_status tkdv_eval_proposals(tkdv_ctx *ctx, const tkdv_point *pt, tkdv_propos
  * |x^| = 1 (Sec. II.A; N >= 3K + 1).  The products run on the matrix cores in
  * the requested arithmetic with FP32 accumulation; for K >= 16 the sum is
  * formed from the even- and odd-mode syntheses on half the grid (the other
- * half holds their difference).  K in {8, 16, 32, 64}; both pointers are
+ * half holds their difference), for K = 128 from a quarter of the grid
+ * offset by half a step (the same sum in exact arithmetic, N >= 3K + 1).
+ * K in {8, 16, 32, 64, 128}; d_xhat 16-byte aligned; both pointers are
  * device pointers owned by the caller.
  */
 tkdv_status tkdv_synthesize(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, const float *d_xhat,

@@ -1632,7 +1632,6 @@ tkdv_status tkdv_sir(tkdv_ctx *ctx, const tkdv_point *pt, tkdv_proposal proposal
         return set_err(ctx, TKDV_E_ARG, "proposal must be UNIFORM or SIGMA");
     if (precision != TKDV_FP32 && precision != TKDV_BF16X3)
         return set_err(ctx, TKDV_E_UNSUPPORTED, "tkdv_sir computes weights with FP32 or BF16x3 synthesis");
-    if (pt->K > 64) return set_err(ctx, TKDV_E_UNSUPPORTED, "tkdv_sir supports K in {8,16,32,64}");
     if (n == 0 || n >= (1ull << 40)) return set_err(ctx, TKDV_E_ARG, "n must be in [1, 2^40)");
     if (!(u0 >= 0.0 && u0 < 1.0)) return set_err(ctx, TKDV_E_ARG, "u0 must be in [0, 1)");
     if (m > 0 && !d_index) return set_err(ctx, TKDV_E_ARG, "d_index is NULL");
@@ -1654,7 +1653,7 @@ tkdv_status tkdv_sir(tkdv_ctx *ctx, const tkdv_point *pt, tkdv_proposal proposal
     d.n = n;
     d.n_tiles = (n + kTile - 1) / kTile;
     const unsigned long long n_tiles = d.n_tiles, n_chunks = (n_tiles + kSirChunk - 1) / kSirChunk;
-    const int waves = sir_waves(ctx->n_cu);
+    const int waves = sir_waves(K, ctx->n_cu);
     HIP_TRY(ctx, ensure(ctx->sir_pt, sizeof(DevPoint)));
     if (!d_weight) HIP_TRY(ctx, ensure(ctx->sir_w, n * sizeof(float)));
     HIP_TRY(ctx, ensure(ctx->sir_tile, 2 * n_tiles * sizeof(double)));
@@ -1701,8 +1700,8 @@ tkdv_status tkdv_sir(tkdv_ctx *ctx, const tkdv_point *pt, tkdv_proposal proposal
         ctx->timing = tkdv_timing{};
         if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) ctx->timing.decide_ms = ms;
         if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[2]) == hipSuccess) ctx->timing.total_ms = ms;
-        ctx->timing.decide_grid = 4 * ctx->n_cu;
-        ctx->timing.decide_block = kBlock;
+        ctx->timing.decide_grid = K == 128 ? ctx->n_cu : 4 * ctx->n_cu;
+        ctx->timing.decide_block = K == 128 ? decide_block(128) : kBlock;
     }
     // per-wave partials in wave order
     double W2 = 0.0, mx = 0.0, M[4] = {0.0, 0.0, 0.0, 0.0}, over = 0.0;
@@ -1976,10 +1975,11 @@ tkdv_status tkdv_synthesize(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, 
                             float *d_s3, void *stream)
 {
     if (!ctx) return set_err(nullptr, TKDV_E_ARG, "ctx is NULL");
-    if (kindex(K) < 0 || K > 64) return set_err(ctx, TKDV_E_UNSUPPORTED, "tkdv_synthesize supports K in {8,16,32,64}");
+    if (kindex(K) < 0) return set_err(ctx, TKDV_E_UNSUPPORTED, "tkdv_synthesize supports K in {8,16,32,64,128}");
     if (precision < TKDV_FP32 || precision > TKDV_BF16X3) return set_err(ctx, TKDV_E_ARG, "bad precision");
     if (n == 0) return TKDV_OK;
     if (!d_xhat || !d_s3) return set_err(ctx, TKDV_E_ARG, "NULL device pointer");
+    if ((uintptr_t)d_xhat & 15u) return set_err(ctx, TKDV_E_ARG, "d_xhat must be 16-byte aligned");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     tkdv_status s = build_tables(ctx, K);
     if (s != TKDV_OK) return s;
@@ -1988,8 +1988,9 @@ tkdv_status tkdv_synthesize(tkdv_ctx *ctx, int32_t K, tkdv_precision precision, 
     std::memset(&ctx->timing, 0, sizeof(ctx->timing));
     const void *tab_hi = nullptr, *tab_lo = nullptr;
     s3_tables(ctx, ki, precision, tab_hi, tab_lo);
-    HIP_TRY(ctx, launch_synth(K, precision, d_xhat, n, d_s3, tab_hi, tab_lo, ctx->n_cu, st, ctx->ev[0],
-                              &ctx->timing.decide_grid, &ctx->timing.decide_block));
+    auto launch = K == 128 ? launch_synth_quarter : launch_synth;
+    HIP_TRY(ctx, launch(K, precision, d_xhat, n, d_s3, tab_hi, tab_lo, ctx->n_cu, st, ctx->ev[0],
+                        &ctx->timing.decide_grid, &ctx->timing.decide_block));
     HIP_TRY(ctx, hipEventRecord(ctx->ev[1], st));
     HIP_TRY(ctx, hipEventSynchronize(ctx->ev[1]));
     float ms = 0.0f;

@@ -34,6 +34,10 @@ hipError_t launch_finalize(const KernelArgs &a, const unsigned long long *seg_cn
 hipError_t launch_synth(int K, int prec, const float *xhat, unsigned long long n, float *s3, const void *phi_hi,
                         const void *phi_lo, int n_cu, hipStream_t st, hipEvent_t ev_start, int *grid_out,
                         int *block_out);
+// the same at K = 128 in the quarter-period form (tkdv_quarter.hip)
+hipError_t launch_synth_quarter(int K, int prec, const float *xhat, unsigned long long n, float *s3,
+                                const void *phi_hi, const void *phi_lo, int n_cu, hipStream_t st,
+                                hipEvent_t ev_start, int *grid_out, int *block_out);
 // Quarter-period form (tkdv_quarter.hip): the decision kernel at K = 128 and,
 // as a tile variant, at K = 64; workgroup size, occupancy, the bytes of one
 // table (FP32, or one BF16 table of hi/lo); the ordered output with

@@ -1,93 +1,16 @@
 // Quarter-period kernels of the TKdV rejection sampler at K = 64 and 128
-// (N = 256, 512): the decision kernel, and the ordered output with the
-// statistics.
-//
-// Layout.  One wavefront evaluates a tile of 16 proposals; proposal p of the
-// tile lives in lanes p + 16 g, g = 0..3, and lane group g holds the cos and
-// sin coordinates of the K/4 modes K g/4 + 1 .. K g/4 + K/4 (c[j] =
-// x_{Kg/4+j+1}, s[j] = x_{K+Kg/4+j+1}).  That is the operand layout of the 16x16x32 BF16
-// (and 16x16x4 FP32) matrix instructions with the proposals as the B
-// (column) operand: lane l supplies k-rows 8 (l/16) .. 8 (l/16) + 7 of column
-// l % 16, and receives rows 4 (l/16) .. 4 (l/16) + 3 of the result.
-//
-// Quarter-period synthesis.  H3 = (1/6) int u^3 dxi (Sec. II.A) is the
-// trapezoid sum of u^3 on any equispaced grid of N >= 3K + 1 points; this
-// kernel takes the grid offset by half a step, xi_j = -pi + 2 pi (j + 1/2)/N,
-// whose points come in orbits {xi, -xi, xi + pi, pi - xi} with one
-// representative in (0, pi/2): xi_rho = pi (2 rho + 1)/N, rho < N/4.  With Ce,
-// Co (cos block, even / odd modes) and Se, So (sin block) at a representative,
-// the four field values are (Ce + Co) +- (Se + So) and (Ce - Co) +- (Se - So),
-// and their cubes sum to 4 Ce (Ce^2 + 3 Co^2 + 3 Se^2 + 3 So^2) + 24 Co Se So.
-// The tables carry the Co, Se, So rows times sqrt(3) (co = sqrt 3 Co, ...):
-// 4 Ce (Ce^2 + co^2 + se^2 + so^2) + (8/sqrt 3) co se so.  Each of the four
-// syntheses contracts K/2 coordinates: a quarter of the plain product's matrix
-// work, and tables of N/4 x 2K entries (64 KB per BF16 table at K = 128) that
-// fit in LDS.
+// (N = 256, 512): the decision kernel, the ordered output with the
+// statistics, and the standalone synthesis at K = 128.  The layout and the quarter-period synthesis are described
+// in tkdv_quarter.h.
 #include <hip/hip_runtime.h>
 
 #include "tkdv_device.h"
 #include "tkdv_kernels.h"
+#include "tkdv_quarter.h"
 
 namespace tkdv {
 
-typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
-
 namespace {
-
-constexpr int kTile16 = 16;            // proposals per wave tile
-
-// Sizes of the quarter-period form at K (64 or 128): CPL coordinates of each
-// block per lane, K/16 tiles of 16 representatives (N/4 = K of them), K/64
-// BF16 k-steps and K/32 groups of four FP32 k-steps per synthesis.
-template <int K>
-struct Quarter {
-    static constexpr int CPL = K / 4;
-    static constexpr int NB = CPL / 4;        // Philox blocks of one block's coordinates per lane
-    static constexpr int TILES = K / 16;
-    static constexpr int STEPS = K / 64;      // BF16 k-steps (32 k-rows, 8 per lane group)
-    static constexpr int QG = K / 32;         // FP32 k-steps in groups of 4
-    // bytes of one table: BF16 [tile][out][step][64 lanes][8], FP32 [tile][out][group][64 lanes][4]
-    static constexpr int BF16_BYTES = TILES * 4 * STEPS * 64 * 16;
-    static constexpr int F32_BYTES = TILES * 4 * QG * 64 * 16;
-    // workgroup: at K = 128 the 128 KB of tables leave one workgroup per CU;
-    // 8 waves (2 per SIMD) share them with every register they need (12 waves
-    // spill some 30 registers a lane, whose stores reach HBM, for no gain in
-    // speed); at K = 64 (32 KB) workgroups of 256
-    static constexpr int BLOCK = K == 128 ? 512 : 256;
-    static constexpr int lds(int prec) { return prec == PREC_FP32 ? F32_BYTES : 2 * BF16_BYTES; }
-};
-
-__device__ __forceinline__ unsigned long long wave_sum_u64_128(unsigned long long v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ float wave_max_128(float v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ double wave_sum_f64_128(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ unsigned long long bcast0(unsigned long long v)
-{
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((unsigned long long)hi << 32) | lo;
-}
-// sum over the four lanes of a proposal (l, l^16, l^32, l^48); every lane
-// gets the same two operands in the last addition, hence the same bits
-__device__ __forceinline__ float sum4(float v)
-{
-    v = v + __shfl_xor(v, 16, 64);
-    return v + __shfl_xor(v, 32, 64);
-}
 
 // Work-queue claim as in the other decision kernels: every lane issues the
 // atomic (lane 0 adds), lane 0's old value broadcast; ~0 when the target is met.
@@ -105,176 +28,6 @@ __device__ __forceinline__ void add0(unsigned long long *ctr, unsigned long long
     if (bcast0(v) != 0ull) atomicAdd(ctr, lane == 0 ? v : 0ull);
 }
 
-// Block b (0: cos, 1: sin) of proposal i for this lane: the K/4 coordinates
-// of modes K g/4 + 1 .. K g/4 + K/4 (coordinate m from word m, Box-Muller on
-// word pairs; X = Sigma^{1/2} z for the paper's proposal), and their
-// contributions to |X|^2, sum (j+1) X^2 and sum (j+1)^2 X^2 (t = sum k^2 X_k^2
-// over both blocks, k = K g/4 + j + 1).
-template <int K, int PROP>
-__device__ __forceinline__ void gen_block128(const DevPoint &P, uint32_t c0, uint32_t c1, int g, int b,
-                                             float (&v)[K / 4], float &r2, float &a1, float &a2)
-{
-    constexpr int NB = Quarter<K>::NB;
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-        const uint4 w = philox4x32_10(c0, c1, P.point_id, (uint32_t)(b * (K / 4) + NB * g + q), P.key0, P.key1);
-        box_muller_f32(w.x, w.y, v[4 * q + 0], v[4 * q + 1]);
-        box_muller_f32(w.z, w.w, v[4 * q + 2], v[4 * q + 3]);
-    }
-    if (PROP == PROP_SIGMA) {
-        const float4 *sg = reinterpret_cast<const float4 *>(P.sig + (K / 4) * g);
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            const float4 sv = sg[q];
-            v[4 * q + 0] *= sv.x;
-            v[4 * q + 1] *= sv.y;
-            v[4 * q + 2] *= sv.z;
-            v[4 * q + 3] *= sv.w;
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < K / 4; ++j) {
-        const float q = v[j] * v[j];
-        r2 += q;
-        a1 = __builtin_fmaf((float)(j + 1), q, a1);
-        a2 = __builtin_fmaf((float)((j + 1) * (j + 1)), q, a2);
-    }
-}
-
-// |X|^-1 and t of the projected point from the lane's partial sums (the four
-// lanes of a proposal end with bitwise identical values).
-template <int K>
-__device__ __forceinline__ float finish_norm128(int g, float r2, float a1, float a2, float &t)
-{
-    const float b = (float)((K / 4) * g);
-    float tk = __builtin_fmaf(b * b, r2, __builtin_fmaf(2.0f * b, a1, a2));
-    r2 = sum4(r2);
-    tk = sum4(tk);
-    const float inv = __builtin_amdgcn_rsqf(r2);
-    t = tk * (inv * inv);
-    return inv;
-}
-
-// Proposal i of the point: this lane's K/4 cos and K/4 sin coordinates of X
-// (words 0..2K-1 as in every sampler: coordinate m from word m, Box-Muller on
-// word pairs; X = Sigma^{1/2} z for the paper's proposal), |X|^-1, t of the
-// projected point and the acceptance word (word 2K).  With NORMALIZE the
-// coordinates are projected onto the sphere.  The four lanes of a proposal
-// hold bitwise identical |X|^2 and t.
-template <int K, int PROP, bool NORMALIZE>
-__device__ __forceinline__ float gen_x128(const DevPoint &P, uint64_t i, int g, float (&c)[K / 4],
-                                          float (&s)[K / 4], float &t, uint32_t &w_acc)
-{
-    const uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32);
-    float r2 = 0.0f, a1 = 0.0f, a2 = 0.0f;
-    gen_block128<K, PROP>(P, c0, c1, g, 0, c, r2, a1, a2);
-    gen_block128<K, PROP>(P, c0, c1, g, 1, s, r2, a1, a2);
-    w_acc = philox4x32_10(c0, c1, P.point_id, (uint32_t)(K / 2), P.key0, P.key1).x;
-    const float inv = finish_norm128<K>(g, r2, a1, a2, t);
-    if (NORMALIZE) {
-#pragma unroll
-        for (int j = 0; j < K / 4; ++j) {
-            c[j] *= inv;
-            s[j] *= inv;
-        }
-    }
-    return inv;
-}
-
-// The cube sums of one representative from its four syntheses (co, se, so
-// carry sqrt(3)): s1 += Ce (Ce^2 + co^2 + se^2 + so^2), s2 += co se so.
-__device__ __forceinline__ void quarter_cubes(const f32x4 &ce, const f32x4 &co, const f32x4 &se, const f32x4 &so,
-                                              float &s1, float &s2)
-{
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const float e = ce[v];
-        const float q = __builtin_fmaf(co[v], co[v], __builtin_fmaf(se[v], se[v], __builtin_fmaf(so[v], so[v], e * e)));
-        s1 = __builtin_fmaf(e, q, s1);
-        s2 = __builtin_fmaf(co[v] * se[v], so[v], s2);
-    }
-}
-
-// BF16 operands of one contraction (out o: 0 Ce, 1 Co, 2 Se, 3 So), k-step r:
-// entry e = the coordinate of mode K g/4 + 2 (8 r + e) + 2 (even) or + 1 (odd).
-template <int N, bool LO>
-__device__ __forceinline__ void quarter_operand(const float (&v)[N], int odd, int r, bf16x8 &hi, bf16x8 &lo)
-{
-    u32x4_t wh, wl = {0u, 0u, 0u, 0u};
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        const int j0 = 16 * r + 4 * w + (odd ? 0 : 1);  // entries 2w, 2w + 1: coordinates j0, j0 + 2
-        wh[w] = pack_hi(v[j0], v[j0 + 2]);
-        if (LO) wl[w] = pack_lo(v[j0], v[j0 + 2], wh[w]);
-    }
-    hi = __builtin_bit_cast(bf16x8, wh);
-    lo = __builtin_bit_cast(bf16x8, wl);
-}
-
-// S3 = sum over the N = 4K offset-grid values of u~^3 for this lane's share
-// (the caller sums the four lanes), from unprojected coordinates, FP32 products.
-template <int K>
-__device__ __forceinline__ float cube_sum_q128_f32(const float (&c)[K / 4], const float (&s)[K / 4],
-                                                   const char *lds_hi, int lane)
-{
-    constexpr int QG = Quarter<K>::QG;
-    float s1 = 0.0f, s2 = 0.0f;
-    {
-        // k-step sg of out o: coordinate 2 sg + 1 (even mode) or 2 sg (odd mode) of the block
-        const float4 *tab = reinterpret_cast<const float4 *>(lds_hi);
-#pragma unroll 1
-        for (int tau = 0; tau < Quarter<K>::TILES; ++tau) {
-            f32x4 acc[4] = {f32x4{}, f32x4{}, f32x4{}, f32x4{}};
-#pragma unroll
-            for (int q4 = 0; q4 < QG; ++q4)
-#pragma unroll
-                for (int o = 0; o < 4; ++o) {
-                    const float4 a = tab[((tau * 4 + o) * QG + q4) * 64 + lane];
-                    const float *v = (o < 2) ? c : s;
-                    const int par = (o == 0 || o == 2) ? 1 : 0;
-                    acc[o] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, v[2 * (4 * q4 + 0) + par], acc[o], 0, 0, 0);
-                    acc[o] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, v[2 * (4 * q4 + 1) + par], acc[o], 0, 0, 0);
-                    acc[o] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, v[2 * (4 * q4 + 2) + par], acc[o], 0, 0, 0);
-                    acc[o] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, v[2 * (4 * q4 + 3) + par], acc[o], 0, 0, 0);
-                }
-            quarter_cubes(acc[0], acc[1], acc[2], acc[3], s1, s2);
-        }
-    }
-    return __builtin_fmaf(4.0f, s1, 4.6188021535170061f * s2);  // 4 s1 + (8/sqrt 3) s2
-}
-
-// The same from BF16 operands [out][step] (hi, and lo for BF16x3) with FP32
-// accumulation.
-template <int K, int PREC>
-__device__ __forceinline__ float cube_sum_q128_bf16(const bf16x8 (&bh)[4][K / 64], const bf16x8 (&bl)[4][K / 64],
-                                                    const char *lds_hi, const char *lds_lo, int lane)
-{
-    constexpr int R = Quarter<K>::STEPS;
-    float s1 = 0.0f, s2 = 0.0f;
-    {
-        const bf16x8 *th = reinterpret_cast<const bf16x8 *>(lds_hi);
-        const bf16x8 *tl = reinterpret_cast<const bf16x8 *>(lds_lo);
-#pragma unroll 1
-        for (int tau = 0; tau < Quarter<K>::TILES; ++tau) {
-            f32x4 acc[4] = {f32x4{}, f32x4{}, f32x4{}, f32x4{}};
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int o = 0; o < 4; ++o) {
-                    const int idx = ((tau * 4 + o) * R + r) * 64 + lane;
-                    const bf16x8 ah = th[idx];
-                    if constexpr (PREC == PREC_BF16X3) {
-                        const bf16x8 al = tl[idx];
-                        acc[o] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[o][r], acc[o], 0, 0, 0);
-                        acc[o] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[o][r], acc[o], 0, 0, 0);
-                    }
-                    acc[o] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[o][r], acc[o], 0, 0, 0);
-                }
-            quarter_cubes(acc[0], acc[1], acc[2], acc[3], s1, s2);
-        }
-    }
-    return __builtin_fmaf(4.0f, s1, 4.6188021535170061f * s2);  // 4 s1 + (8/sqrt 3) s2
-}
 
 // ---------------------------------------------------------------------------
 // k_decide128: persistent; claims of 64 accept words (2048 proposals, 128
@@ -663,6 +416,109 @@ __global__ void __launch_bounds__(MatQ<K>::W * kWave) k_materialize_q(KernelArgs
     }
 }
 
+// ---------------------------------------------------------------------------
+// k_synth_q: the standalone synthesis (rows of x^ in HBM -> S3 = sum of the
+// cubes of the grid values of each row) at K = 128, in the quarter-period form
+// on the grid offset by half a step, whose trapezoid sum of u~^3 equals that on
+// xi_j = -pi + 2 pi j/N (both are exact for N >= 3K + 1), with the decision
+// kernel's tables and arithmetic.
+// ---------------------------------------------------------------------------  Sixteen
+// rows per wave: lane l holds coordinates K/4 (l/16) .. K/4 (l/16) + K/4 - 1 of
+// both blocks of row l % 16 (the column operand of the 16x16 products); the
+// BF16 paths split each block into operands as it arrives.  Workgroups of
+// Quarter<K>::BLOCK threads share the tables (128 KB for FP32 and BF16x3).
+template <int K, int PREC>
+__global__ void __launch_bounds__(Quarter<K>::BLOCK) k_synth_q(const float *__restrict__ xhat, unsigned long long n,
+                                                               float *__restrict__ s3_out, const void *phi_hi,
+                                                               const void *phi_lo)
+{
+    constexpr int B = Quarter<K>::BLOCK, CPL = K / 4, R = Quarter<K>::STEPS;
+    constexpr int one = (PREC == PREC_FP32 ? Quarter<K>::F32_BYTES : Quarter<K>::BF16_BYTES) / 16;
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    {
+        const uint4 *s0 = reinterpret_cast<const uint4 *>(phi_hi);
+        const uint4 *s1 = reinterpret_cast<const uint4 *>(phi_lo);
+        uint4 *d = reinterpret_cast<uint4 *>(lds);
+        for (int v = threadIdx.x; v < one; v += B) d[v] = s0[v];
+        if constexpr (PREC == PREC_BF16X3)
+            for (int v = threadIdx.x; v < one; v += B) d[one + v] = s1[v];
+    }
+    __syncthreads();
+    const char *lds_hi = lds, *lds_lo = lds + (PREC == PREC_BF16X3 ? one * 16 : 0);
+    const int lane = threadIdx.x & 63, g = lane >> 4, pl = lane & 15;
+    const unsigned long long n_chunks = (n + 15) / 16;
+    const unsigned long long waves = (unsigned long long)gridDim.x * (B / kWave);
+    for (unsigned long long ch = (unsigned long long)blockIdx.x * (B / kWave) + (threadIdx.x >> 6); ch < n_chunks;
+         ch += waves) {
+        const unsigned long long row = ch * 16 + pl;
+        const bool valid = row < n;
+        const float *src = xhat + (valid ? row : 0ull) * (2 * K) + CPL * g;
+        auto load = [&](int blk, float (&v)[CPL]) {
+            const float4 *p = reinterpret_cast<const float4 *>(src + blk * K);
+#pragma unroll
+            for (int q = 0; q < CPL / 4; ++q) {
+                const float4 w = p[q];
+                v[4 * q + 0] = w.x;
+                v[4 * q + 1] = w.y;
+                v[4 * q + 2] = w.z;
+                v[4 * q + 3] = w.w;
+            }
+        };
+        float s3l;
+        if constexpr (PREC == PREC_FP32) {
+            float c[CPL], s[CPL];
+            load(0, c);
+            load(1, s);
+            s3l = cube_sum_q128_f32<K>(c, s, lds_hi, lane);
+        } else {
+            bf16x8 bh[4][R], bl[4][R];
+#pragma unroll
+            for (int blk = 0; blk < 2; ++blk) {
+                float v[CPL];
+                load(blk, v);
+#pragma unroll
+                for (int odd = 0; odd < 2; ++odd)
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        quarter_operand<CPL, PREC == PREC_BF16X3>(v, odd, r, bh[2 * blk + odd][r], bl[2 * blk + odd][r]);
+            }
+            s3l = cube_sum_q128_bf16<K, PREC>(bh, bl, lds_hi, lds_lo, lane);
+        }
+        const float s3 = sum4(s3l);
+        if (valid && g == 0) s3_out[row] = s3;
+    }
+}
+
+template <int K, int PREC>
+hipError_t launch_synth_q_t(const float *xhat, unsigned long long n, float *s3, const void *phi_hi,
+                            const void *phi_lo, int n_cu, hipStream_t st, hipEvent_t ev_start, int *grid_out,
+                            int *block_out)
+{
+    constexpr int B = Quarter<K>::BLOCK;
+    constexpr int lds = PREC == PREC_FP32 ? Quarter<K>::F32_BYTES
+                                          : (PREC == PREC_BF16X3 ? 2 : 1) * Quarter<K>::BF16_BYTES;
+    auto kern = k_synth_q<K, PREC>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, B, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    const unsigned long long chunks = (n + 15) / 16;
+    unsigned long long grid = (unsigned long long)per_cu * n_cu;
+    const unsigned long long want = (chunks + B / kWave - 1) / (B / kWave);
+    if (want < grid) grid = want;
+    if (grid < 1) grid = 1;
+    if (grid_out) *grid_out = (int)grid;
+    if (block_out) *block_out = B;
+    if (ev_start) {
+        e = hipEventRecord(ev_start, st);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(B), lds, st, xhat, n, s3, phi_hi, phi_lo);
+    return hipGetLastError();
+}
+
 template <int K, int PROP>
 hipError_t launch_materialize_q_t(const KernelArgs &a, unsigned long long total_segs,
                                   const unsigned long long *seg_cnt, const unsigned long long *seg_base,
@@ -816,6 +672,21 @@ hipError_t launch_materialize_quarter(int K, int prop, const KernelArgs &a, unsi
     TKDV_DISPATCH_MQ(128, PROP_SIGMA)
     TKDV_DISPATCH_MQ(128, PROP_UNIFORM)
 #undef TKDV_DISPATCH_MQ
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_synth_quarter(int K, int prec, const float *xhat, unsigned long long n, float *s3,
+                                const void *phi_hi, const void *phi_lo, int n_cu, hipStream_t st,
+                                hipEvent_t ev_start, int *grid_out, int *block_out)
+{
+    if (K != 128) return hipErrorInvalidValue;
+    if (prec == PREC_FP32)
+        return launch_synth_q_t<128, PREC_FP32>(xhat, n, s3, phi_hi, phi_lo, n_cu, st, ev_start, grid_out, block_out);
+    if (prec == PREC_BF16)
+        return launch_synth_q_t<128, PREC_BF16>(xhat, n, s3, phi_hi, phi_lo, n_cu, st, ev_start, grid_out, block_out);
+    if (prec == PREC_BF16X3)
+        return launch_synth_q_t<128, PREC_BF16X3>(xhat, n, s3, phi_hi, phi_lo, n_cu, st, ev_start, grid_out,
+                                                  block_out);
     return hipErrorInvalidValue;
 }
 

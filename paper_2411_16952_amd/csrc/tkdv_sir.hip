@@ -15,7 +15,11 @@
 //                   clamped to the tile's range [A(off_t), A(off_t+1)), so the
 //                   m draws are partitioned exactly; each lane writes its own
 //                   proposal's draws (no atomics), and the rows of x^ when asked.
+// At K = 128 the weights and the rows come from the quarter-period kernels'
+// draw and synthesis (k_sir_weights_q, k_sir_resample_q: tkdv_quarter.h), so
+// that w = f/(M g) is the decision kernel's and the rows are the sampler's.
 #include "tkdv_device.h"
+#include "tkdv_quarter.h"
 #include "tkdv_sir.h"
 
 namespace tkdv {
@@ -246,6 +250,119 @@ __global__ void __launch_bounds__(kBlock) k_sir_weights(SirArgs a)
     }
 }
 
+// K = 128: the same outputs in the quarter-period layout (16 proposals per
+// wave pass, two passes per 32-proposal tile; lane group g = l/16 holds modes
+// K g/4 + 1 .. K g/4 + K/4).  log a takes the decision kernel's operations
+// (the same draw, products and cube sum on the grid offset by half a step), so
+// each weight is exp of the rejection step's fast-path log a; the power sums
+// come from the same four syntheses (QuarterPowers), with S4 carried over to
+// the grid xi_j = -pi + 2 pi j/N by the closed-form difference of the two
+// grids.  One 512-thread workgroup per CU holds the 128 KB of tables.
+template <int K, int PREC, int PROP>
+__global__ void __launch_bounds__(Quarter<K>::BLOCK) k_sir_weights_q(SirArgs a)
+{
+    constexpr int B = Quarter<K>::BLOCK, CPL = K / 4, R = Quarter<K>::STEPS;
+    constexpr int one = (PREC == PREC_FP32 ? Quarter<K>::F32_BYTES : Quarter<K>::BF16_BYTES) / 16;
+    static_assert(PREC != PREC_BF16, "weights are computed with FP32 or BF16x3 products");
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    {
+        const uint4 *s0 = reinterpret_cast<const uint4 *>(a.phi_hi);
+        const uint4 *s1 = reinterpret_cast<const uint4 *>(a.phi_lo);
+        uint4 *d = reinterpret_cast<uint4 *>(lds);
+        for (int v = threadIdx.x; v < one; v += B) d[v] = s0[v];
+        if constexpr (PREC == PREC_BF16X3)
+            for (int v = threadIdx.x; v < one; v += B) d[one + v] = s1[v];
+    }
+    __syncthreads();
+    const char *lds_hi = lds, *lds_lo = lds + (PREC == PREC_BF16X3 ? one * 16 : 0);
+    const DevPoint &P = *a.pt;
+    const int lane = threadIdx.x & 63, g = lane >> 4, pl = lane & 15;
+    const unsigned long long gwave = (unsigned long long)blockIdx.x * (B / kWave) + (threadIdx.x >> 6);
+    const unsigned long long nwaves = (unsigned long long)gridDim.x * (B / kWave);
+    double w2 = 0.0, mx = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0, m4 = 0.0, over = 0.0;
+    for (unsigned long long tile = gwave; tile < a.n_tiles; tile += nwaves) {
+        double ts = 0.0;
+#pragma unroll 1
+        for (int h = 0; h < 2; ++h) {
+            const unsigned long long local = tile * kTile + 16 * h + pl;
+            const bool valid = local < a.n;
+            const uint64_t i = P.i0 + local;
+            const uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32);
+            float r2 = 0.0f, a1 = 0.0f, a2 = 0.0f, top_c, top_s;
+            QuarterPowers pw;
+            auto fold = [&](const f32x4 &ce, const f32x4 &co, const f32x4 &se, const f32x4 &so) {
+                pw.fold(ce, co, se, so);
+            };
+            if constexpr (PREC == PREC_FP32) {
+                float c[CPL], s[CPL];
+                gen_block128<K, PROP>(P, c0, c1, g, 0, c, r2, a1, a2);
+                gen_block128<K, PROP>(P, c0, c1, g, 1, s, r2, a1, a2);
+                top_c = c[CPL - 1];
+                top_s = s[CPL - 1];
+                quarter_tiles_f32<K>(c, s, lds_hi, lane, fold);
+            } else {
+                bf16x8 bh[4][R], bl[4][R];
+#pragma unroll
+                for (int blk = 0; blk < 2; ++blk) {
+                    float v[CPL];
+                    gen_block128<K, PROP>(P, c0, c1, g, blk, v, r2, a1, a2);
+                    if (blk == 0) top_c = v[CPL - 1];
+                    else top_s = v[CPL - 1];
+#pragma unroll
+                    for (int odd = 0; odd < 2; ++odd)
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            quarter_operand<CPL, true>(v, odd, r, bh[2 * blk + odd][r], bl[2 * blk + odd][r]);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                quarter_tiles_bf16<K, PREC>(bh, bl, lds_hi, lds_lo, lane, fold);
+            }
+            float s1, s2, s3, s4;
+            pw.result(s1, s2, s3, s4);
+            if (g == 3) s4 += s4_grid_correction<K>(top_c, top_s);  // mode K: last coordinate of group 3
+            float t;
+            const float inv = finish_norm128<K>(g, r2, a1, a2, t);
+            const float i2 = inv * inv;
+            s1 = sum4(s1) * inv;
+            s2 = sum4(s2) * i2;
+            s3 = sum4(s3) * (inv * inv * inv);  // as the decision kernel
+            s4 = sum4(s4) * (i2 * i2);
+            const float la = log_a_f32<PROP>(P, t, s3);
+            const float w = __builtin_amdgcn_exp2f(la * 1.4426950408889634f);
+            const bool mine = valid && g == 0;
+            if (mine) a.w[local] = w;
+            const double wd = mine ? (double)w : 0.0;
+            ts += sum64(wd);
+            w2 += wd * wd;
+            mx = fmax(mx, wd);
+            m1 += wd * (double)s1;
+            m2 += wd * (double)s2;
+            m3 += wd * (double)s3;
+            m4 += wd * (double)s4;
+            over += (mine && w > 1.0f) ? 1.0 : 0.0;
+        }
+        if (lane == 0) a.tile_sum[tile] = ts;
+    }
+    w2 = sum64(w2);
+    mx = max64(mx);
+    m1 = sum64(m1);
+    m2 = sum64(m2);
+    m3 = sum64(m3);
+    m4 = sum64(m4);
+    over = sum64(over);
+    if (lane == 0) {
+        double *o = a.wave_part + gwave * kSirPart;
+        o[0] = w2;
+        o[1] = mx;
+        o[2] = m1;
+        o[3] = m2;
+        o[4] = m3;
+        o[5] = m4;
+        o[6] = over;
+        o[7] = 0.0;
+    }
+}
+
 // The cumulative sums must be monotone in the proposal index, so that the
 // draw ranges of consecutive tiles never overlap: every level adds
 // non-negative terms sequentially (FP rounding is monotone), and a fixed FP64
@@ -325,7 +442,9 @@ __device__ __forceinline__ unsigned long long draw_of(double c, const SirArgs &a
     return r < lo ? lo : (r > hi ? hi : r);
 }
 
-template <int K, int PROP>
+// QROWS (K = 128): the rows of x^ from the quarter-period draw (gen_x128, the
+// sampler's rows), proposal 16 h + l % 16 of the tile in lanes l, h = 0, 1.
+template <int K, int PROP, bool QROWS>
 __global__ void __launch_bounds__(kBlock) k_sir_resample(SirArgs a)
 {
     const DevPoint &P = *a.pt;
@@ -361,14 +480,36 @@ __global__ void __launch_bounds__(kBlock) k_sir_resample(SirArgs a)
         if (half == 0)
             for (unsigned long long r = q0; r < q1; ++r) a.index[r] = i;
         if (a.xhat && __ballot(q1 > q0) != 0ull) {
-            float x[K];
-            float t;
-            uint32_t w_acc;
-            gen_xhat<K, PROP, true>(P, i, half, x, t, w_acc);
-            for (unsigned long long r = q0; r < q1; ++r) {
-                float *dst = a.xhat + r * (2 * K) + half * K;
+            if constexpr (QROWS) {
+                constexpr int CPL = K / 4;
+                const int g = lane >> 4;
+#pragma unroll 1
+                for (int h = 0; h < 2; ++h) {
+                    const int pp = 16 * h + (lane & 15);  // proposal of the tile
+                    const unsigned long long d0 = __shfl(r0, pp, 64), d1 = __shfl(r1, pp, 64);
+                    if (__ballot(d1 > d0) == 0ull) continue;
+                    float c[CPL], s[CPL], t;
+                    uint32_t w_acc;
+                    gen_x128<K, PROP, true>(P, P.i0 + tile * kTile + pp, g, c, s, t, w_acc);
+                    for (unsigned long long r = d0; r < d1; ++r) {
+                        float *dst = a.xhat + r * (2 * K) + CPL * g;
 #pragma unroll
-                for (int j = 0; j < K; ++j) dst[j] = x[j];
+                        for (int j = 0; j < CPL; ++j) {
+                            dst[j] = c[j];
+                            dst[K + j] = s[j];
+                        }
+                    }
+                }
+            } else {
+                float x[K];
+                float t;
+                uint32_t w_acc;
+                gen_xhat<K, PROP, true>(P, i, half, x, t, w_acc);
+                for (unsigned long long r = q0; r < q1; ++r) {
+                    float *dst = a.xhat + r * (2 * K) + half * K;
+#pragma unroll
+                    for (int j = 0; j < K; ++j) dst[j] = x[j];
+                }
             }
         }
     }
@@ -376,11 +517,36 @@ __global__ void __launch_bounds__(kBlock) k_sir_resample(SirArgs a)
 
 }  // namespace
 
-int sir_waves(int n_cu) { return 4 * n_cu * (kBlock / kWave); }
+int sir_waves(int K, int n_cu)
+{
+    return K == 128 ? n_cu * (Quarter<128>::BLOCK / kWave) : 4 * n_cu * (kBlock / kWave);
+}
+
+template <int PREC, int PROP>
+hipError_t launch_sir_weights_q128(const SirArgs &a, int n_cu, hipStream_t st)
+{
+    constexpr int K = 128;
+    constexpr int lds = PREC == PREC_FP32 ? Quarter<K>::F32_BYTES : 2 * Quarter<K>::BF16_BYTES;
+    auto kern = k_sir_weights_q<K, PREC, PROP>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    // one workgroup per CU (the tables fill LDS): sir_waves(128, n_cu) waves
+    hipLaunchKernelGGL(kern, dim3(n_cu), dim3(Quarter<K>::BLOCK), lds, st, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_sir_weights(int K, int prec, int proposal, const SirArgs &a, int n_cu, hipStream_t st)
 {
-    const int grid = 4 * n_cu;  // sir_waves(n_cu) waves
+    if (K == 128) {
+        if (prec == PREC_FP32)
+            return proposal == PROP_SIGMA ? launch_sir_weights_q128<PREC_FP32, PROP_SIGMA>(a, n_cu, st)
+                                          : launch_sir_weights_q128<PREC_FP32, PROP_UNIFORM>(a, n_cu, st);
+        if (prec == PREC_BF16X3)
+            return proposal == PROP_SIGMA ? launch_sir_weights_q128<PREC_BF16X3, PROP_SIGMA>(a, n_cu, st)
+                                          : launch_sir_weights_q128<PREC_BF16X3, PROP_UNIFORM>(a, n_cu, st);
+        return hipErrorInvalidValue;
+    }
+    const int grid = 4 * n_cu;  // sir_waves(K, n_cu) waves
 #define TKDV_SIRW(KK, PR, PP)                                                                            \
     if (K == KK && prec == PR && proposal == PP) {                                                       \
         constexpr int tab = sir_tab_bytes<KK, PR>();                                                     \
@@ -419,11 +585,11 @@ hipError_t launch_sir_resample(int K, int proposal, const SirArgs &a, int n_cu, 
     const dim3 g(12 * n_cu), b(kBlock);  // three waves per SIMD: the tile scan is latency-bound
 #define TKDV_SIRR(KK)                                                                                    \
     if (K == KK) {                                                                                       \
-        if (proposal == PROP_SIGMA) hipLaunchKernelGGL((k_sir_resample<KK, PROP_SIGMA>), g, b, 0, st, a); \
-        else hipLaunchKernelGGL((k_sir_resample<KK, PROP_UNIFORM>), g, b, 0, st, a);                    \
+        if (proposal == PROP_SIGMA) hipLaunchKernelGGL((k_sir_resample<KK, PROP_SIGMA, KK == 128>), g, b, 0, st, a); \
+        else hipLaunchKernelGGL((k_sir_resample<KK, PROP_UNIFORM, KK == 128>), g, b, 0, st, a);                    \
         return hipGetLastError();                                                                        \
     }
-    TKDV_SIRR(8) TKDV_SIRR(16) TKDV_SIRR(32) TKDV_SIRR(64)
+    TKDV_SIRR(8) TKDV_SIRR(16) TKDV_SIRR(32) TKDV_SIRR(64) TKDV_SIRR(128)
 #undef TKDV_SIRR
     return hipErrorInvalidValue;
 }

@@ -204,14 +204,3 @@ def test_k128_in_a_batch_with_k32(T, ctx, case):
         assert np.array_equal(out[p]["index"].cpu().numpy(), single["index"].cpu().numpy())
         assert np.array_equal(out[p]["xhat"].cpu().numpy()[:, : 2 * pts[p].K], single["xhat"].cpu().numpy())
         assert out[p]["S3"] == single["S3"]
-
-
-def test_k128_refused_where_not_built(T, ctx, case):
-    import torch
-    pt, plan = case
-    with pytest.raises(T.TkdvError) as e:
-        ctx.synthesize(torch.zeros((16, 2 * K), device="cuda"), precision=T.BF16X3)
-    assert e.value.status == -5
-    with pytest.raises(T.TkdvError) as e:
-        ctx.sir(pt, 1000, 10, 0.5, plan=plan)
-    assert e.value.status == -5

@@ -11,6 +11,9 @@
 * Equal weights (beta' = 0, uniform proposal, log M = 0): draw r is proposal
   floor((u0 + r) n/m) exactly.
 * Ragged n, m = 0, n = 1, determinism, argument errors.
+* K = 128 (the quarter-period kernels): the same checks; S4 there is formed on
+  the grid offset by half a step and carried to the grid xi_j by the closed
+  form of the difference, which the m4 and kurtosis checks cover.
 """
 import math
 import sys
@@ -51,6 +54,8 @@ CASES = [  # K, E0, beta', C3/C2, proposal, n, m, u0, precision name
     (32, 1.0, 40.0, 75.0, 1, 60_000, 2000, 0.91, "bf16x3"),
     (16, 1.0, 40.0, 30.0, 0, 150_000, 1000, 0.5, "fp32"),
     (64, 1.0, 40.0, 150.0, 1, 20_000, 700, 0.2, "bf16x3"),
+    (128, 1.0, 40.0, 1000.0, 1, 12_011, 600, 0.45, "bf16x3"),  # quarter-period weights and rows
+    (128, 1.5, 40.0, 750.0, 1, 8_003, 400, 0.05, "fp32"),
 ]
 
 

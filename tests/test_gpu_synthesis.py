@@ -11,8 +11,10 @@ of 1e-3 in the worst case, 5.9e-3 at K = 8 and 2.9e-3 at K = 64; its median
 must stay below 1e-3).
 K >= 16 takes the half-period form (on the first half of the grid the even-
 and odd-mode syntheses E, O; the second half holds E - O, and the cubes of
-both halves sum to 2E(E^2 + 3O^2)); K = 8 the plain product.  Edge cases: one
-row, one partial tile, rows that end inside the last wave's tile.
+both halves sum to 2E(E^2 + 3O^2)); K = 8 the plain product; K = 128 the
+quarter-period form on the grid offset by half a step (the same sum in exact
+arithmetic).  Edge cases: one row, one partial tile, rows that end inside the
+last wave's tile; the Dirichlet kernel's closed-form H3 at K = 16 and 128.
 """
 import math
 import sys
@@ -50,7 +52,7 @@ def _rows(K, n, seed):
     return (x / np.linalg.norm(x, axis=1, keepdims=True)).astype(np.float32)
 
 
-@pytest.mark.parametrize("K,n", [(8, 3_001), (16, 2_047), (32, 1_057), (64, 777)])
+@pytest.mark.parametrize("K,n", [(8, 3_001), (16, 2_047), (32, 1_057), (64, 777), (128, 401)])
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16"])
 def test_synthesis_against_oracle(T, ctx, K, n, prec):
     import torch
@@ -75,15 +77,21 @@ def test_synthesis_edges(T, ctx):
     x = torch.from_numpy(_rows(16, 1, seed=1)).cuda()
     one = ctx.synthesize(x, precision=T.BF16X3)
     assert one.shape == (1,)
-    d = np.zeros((1, 32), dtype=np.float32)
-    d[0, :16] = 1.0 / 4.0                      # the Dirichlet kernel: H3 = (K-1)/(2 sqrt(2 pi K)) at E0 = 1
-    s3 = ctx.synthesize(torch.from_numpy(d).cuda(), precision=T.FP32).cpu().numpy()[0]
+
+
+@pytest.mark.parametrize("K", [16, 128])
+def test_synthesis_dirichlet_closed_form(T, ctx, K):
+    import torch
+    d = np.zeros((1, 2 * K), dtype=np.float32)
+    d[0, :K] = 1.0 / math.sqrt(K)              # the Dirichlet kernel: H3 = (K-1)/(2 sqrt(2 pi K)) at E0 = 1
     amp = math.sqrt(2.0 / math.pi)
-    h3 = math.pi / (3 * 64) * amp ** 3 * s3
-    assert h3 == pytest.approx(15 / (2 * math.sqrt(2 * math.pi * 16)), rel=1e-5)
+    for prec, rel in (("fp32", 1e-5), ("bf16x3", 3e-5)):
+        s3 = ctx.synthesize(torch.from_numpy(d).cuda(), precision=T.PRECISIONS[prec]).cpu().numpy()[0]
+        h3 = math.pi / (3 * 4 * K) * amp ** 3 * s3
+        assert h3 == pytest.approx((K - 1) / (2 * math.sqrt(2 * math.pi * K)), rel=rel), (K, prec)
 
 
-@pytest.mark.parametrize("K", [32, 64])
+@pytest.mark.parametrize("K", [32, 64, 128])
 @pytest.mark.parametrize("n", [1, 33, 4099])
 def test_synthesis_small_and_partial(T, ctx, K, n):
     import torch

@@ -194,3 +194,89 @@ def test_quarter_form_operand_layout_covers_every_coordinate_once():
                         assert (k % 2 == 0) == (parity == 0)
                         seen[block * K + k - 1] += 1
     assert np.all(seen == 1)
+
+
+@pytest.mark.parametrize("K", [64, 128])
+def test_power_sums_from_the_orbits_and_the_grid_difference(K):
+    """The SIR weights kernel at K = 128 forms S_p = sum_j u~^p, p = 1..4, from
+    the four offset-grid syntheses (co, se, so carrying sqrt 3), with
+    Q = Ce^2 + co^2 + se^2 + so^2, sg = co^2 + se^2 + so^2 and
+    m = co^2 se^2 + co^2 so^2 + se^2 so^2 per representative:
+        S1 = 4 sum Ce,  S2 = (4/3) sum (2 Ce^2 + Q),
+        S4 = 4 sum (Q^2 - (8/9) sg^2 + (4/9) m) + (32/sqrt 3) sum Ce co se so,
+    and carries S4 to the grid xi_j = -pi + 2 pi j/N by adding
+    (N/4) (a^4 - 6 a^2 b^2 + b^4), a = x_K, b = x_2K (u~^4 reaches frequency N
+    through the top mode alone; the two grids see it with opposite signs).
+    S1..S3 need no correction (no frequency N)."""
+    N = 4 * K
+    rng = np.random.default_rng(K + 7)
+    amp = math.sqrt(2.0 / math.pi)
+    r3 = math.sqrt(3.0)
+    for trial in range(12):
+        x = rng.standard_normal(2 * K) / np.sqrt(1.0 + np.tile(np.arange(K), 2) ** (0.3 * (trial % 3)))
+        if trial == 0:                       # the top mode alone: the difference at its largest
+            x[:] = 0.0
+            x[K - 1], x[2 * K - 1] = 0.6, 0.8
+        x /= np.linalg.norm(x)
+        u = oracle.grid(x, 1.0, N) / amp     # the grid xi_j
+        Ce, Co, Se, So = _quarter_syntheses(x, K, N)
+        co, se, so = r3 * Co, r3 * Se, r3 * So
+        Q = Ce ** 2 + co ** 2 + se ** 2 + so ** 2
+        sg = co ** 2 + se ** 2 + so ** 2
+        m = co ** 2 * se ** 2 + co ** 2 * so ** 2 + se ** 2 * so ** 2
+        S1 = 4 * np.sum(Ce)
+        S2 = 4 / 3 * np.sum(2 * Ce ** 2 + Q)
+        S3 = 4 * np.sum(Ce * Q) + 8 / r3 * np.sum(co * se * so)
+        S4_off = 4 * np.sum(Q ** 2 - 8 / 9 * sg ** 2 + 4 / 9 * m) + 32 / r3 * np.sum(Ce * co * se * so)
+        a, b = x[K - 1], x[2 * K - 1]
+        S4 = S4_off + N / 4 * (a ** 4 - 6 * a ** 2 * b ** 2 + b ** 4)
+        # the offset grid's own sums, directly
+        jj = np.arange(N)
+        xa = -math.pi + 2 * math.pi * (jj + 0.5) / N
+        kk = np.arange(1, K + 1)
+        uo = np.cos(np.outer(xa, kk)) @ x[:K] + np.sin(np.outer(xa, kk)) @ x[K:]
+        scale = np.sum(u ** 4) + 1.0
+        assert abs(S4_off - np.sum(uo ** 4)) < 1e-12 * scale
+        assert abs(S1 - np.sum(u)) < 1e-12 * scale
+        assert abs(S2 - np.sum(u ** 2)) < 1e-12 * scale
+        assert abs(S3 - np.sum(u ** 3)) < 1e-12 * scale
+        assert abs(S4 - np.sum(u ** 4)) < 1e-12 * scale
+        if trial == 0:
+            # u~ = 0.6 cos K xi + 0.8 sin K xi: the grids differ by (N/4) Re((a - ib)^4) != 0
+            assert abs(np.sum(u ** 4) - np.sum(uo ** 4)) > 0.1 * N
+
+
+@pytest.mark.parametrize("K", [64, 128])
+def test_statistics_grid_orbits_cover_every_index_once(K):
+    """On the grid xi_j = -pi + 2 pi j/N itself (the statistics and the extremes
+    search at K >= 64), representative rho < K at xi = 2 pi rho/N gives u~ at
+    xi (index 2K + rho), xi - pi (rho), -xi (2K - rho) and pi - xi (4K - rho), the
+    last two for rho > 0 only; +-pi/2 (indices 3K, K) come from direct sums
+    (cos k pi/2 and sin k pi/2 are 0 or +-1).  Every index is reached exactly
+    once, with the field values of those combinations."""
+    N = 4 * K
+    rng = np.random.default_rng(K + 3)
+    x = rng.standard_normal(2 * K)
+    x /= np.linalg.norm(x)
+    u = oracle.grid(x, 1.0, N) / math.sqrt(2.0 / math.pi)
+    k = np.arange(1, K + 1)
+    ev = k % 2 == 0
+    seen = np.zeros(N, dtype=int)
+    for rho in range(K):
+        xi = 2 * math.pi * rho / N
+        c, s = np.cos(k * xi), np.sin(k * xi)
+        Ce, Co = c[ev] @ x[:K][ev], c[~ev] @ x[:K][~ev]
+        Se, So = s[ev] @ x[K:][ev], s[~ev] @ x[K:][~ev]
+        pe, me, ps, ms = Ce + Co, Ce - Co, Se + So, Se - So
+        pairs = [(2 * K + rho, pe + ps), (rho, me + ms)]
+        if rho:
+            pairs += [(2 * K - rho, pe - ps), (4 * K - rho, me - ms)]
+        for j, val in pairs:
+            seen[j] += 1
+            assert abs(u[j] - val) < 1e-12
+    A = np.sum(x[3:K:4] - x[1:K:4])            # sum_k a_k cos(k pi/2): k = 0 mod 4 minus k = 2 mod 4
+    B = np.sum(x[K:2 * K:4] - x[K + 2:2 * K:4])  # sum_k b_k sin(k pi/2): k = 1 mod 4 minus k = 3 mod 4
+    for j, val in ((3 * K, A + B), (K, A - B)):
+        seen[j] += 1
+        assert abs(u[j] - val) < 1e-12
+    assert np.all(seen == 1)
