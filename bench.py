@@ -3,8 +3,8 @@
 
 Default workload (--workload learned): accepted samples/s at K = 32 with the
 learned defensive-mixture proposal against the paper's Sigma proposal.
-  * before the timed region: eight networks (3 -> 256 -> 256 -> 5K, FP64 on
-    the GPU, initialisation seeds 1..8) are fitted on 16 training points
+  * before the timed region: 24 networks (3 -> 256 -> 256 -> 5K, FP64 on
+    the GPU, initialisation seeds 1..24) are fitted on 16 training points
     (beta' = linspace(20, 60, 16), C3/C2 = 9000/beta') from the paper's
     sampler's accepted samples, and the plans of the evaluation points are
     made: alpha*, M_Sigma (the paper's step 1) and M_mix of every network's
@@ -845,7 +845,7 @@ def main() -> int:
                     help="oracle proposals per point (0: skip; default 2^22 plain, 2^17 learned)")
     ap.add_argument("--train-rounds", type=int, default=6)
     ap.add_argument("--train-steps", type=int, default=150)
-    ap.add_argument("--train-seeds", default="1,2,3,4,5,6,7,8",
+    ap.add_argument("--train-seeds", default=",".join(str(v) for v in range(1, 25)),
                     help="network initialisations trained; each evaluation point samples with the network "
                          "whose rejection constant there is smallest")
     ap.add_argument("--synthesis", action="store_true",
