@@ -141,17 +141,18 @@ def test_mixture_1e9(T, ctx):
     _check_sampled(o, decide, N_PROP, rng, "mixture")
 
 
-def test_sir_1e9(T, ctx):
+@pytest.mark.parametrize("K,bp,c", [(32, 40.0, 150.0), (128, 40.0, 750.0)])
+def test_sir_1e9(T, ctx, K, bp, c):
     """SIR at the benchmark size: sampled weights against the oracle, and
     sum_i a_i = W against the rejection sampler's accepted count on the same
-    proposals (the expected number of accepts is exactly W)."""
-    K, bp, c = 32, 40.0, 150.0
+    proposals (the expected number of accepts is exactly W); K = 128 through
+    the quarter-period weight kernel."""
     pt = T.make_point(K, 1.0, bp, c, seed=1, point_id=7)
     pl = T.plan_point(pt, T.SIGMA)
     tau = T.decision_window(pt, T.SIGMA, T.BF16X3)
     g = ctx.sir(pt, N_PROP, 100_000, 0.5, plan=pl, precision=T.BF16X3, weights=True)
     r = ctx.sample(pt, N_PROP, proposal=T.SIGMA, plan=pl, precision=T.BF16X3, capacity=0)
-    say(f"SIR 1e9: W {g['W']:.6g}, ESS {g['ess']:.6g}; rejection accepted {r['n_accepted']}")
+    say(f"SIR 1e9 K={K}: W {g['W']:.6g}, ESS {g['ess']:.6g}; rejection accepted {r['n_accepted']}")
     assert r["n_M_violations"] == 0 and g["n_over_one"] == 0
     assert abs(r["n_accepted"] - g["W"]) < 6.0 * math.sqrt(g["W"])
     assert 0 < g["ess"] <= N_PROP
