@@ -36,7 +36,7 @@ def shift_one_step(x, N):
     return np.concatenate([a * c - b * s, b * c + a * s])
 
 
-@pytest.mark.parametrize("K,E0", [(8, 1.0), (16, 2.0), (32, 0.5), (64, 1.0)])
+@pytest.mark.parametrize("K,E0", [(8, 1.0), (16, 2.0), (32, 0.5), (64, 1.0), (128, 1.5)])
 def test_dirichlet_kernel_is_the_largest_wave(K, E0):
     N = 4 * K
     rng = np.random.default_rng(K)
@@ -50,7 +50,7 @@ def test_dirichlet_kernel_is_the_largest_wave(K, E0):
     assert np.all(r["umax"] <= math.sqrt(2 * K * E0 / math.pi) * (1 + 1e-13))
 
 
-@pytest.mark.parametrize("K", [8, 32])
+@pytest.mark.parametrize("K", [8, 32, 128])
 def test_single_modes(K):
     N = 4 * K
     amp = math.sqrt(2 / math.pi)

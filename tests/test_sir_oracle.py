@@ -29,10 +29,15 @@ def test_equal_weights_closed_forms():
     assert abs(r["skewness"]) < 0.03
 
 
-@pytest.mark.parametrize("K,E0,bp,c", [(8, 1.0, 40.0, 20.0), (16, 2.0, 40.0, 60.0)])
-def test_parseval_moments_for_any_weights(K, E0, bp, c):
-    p = OP.plan_point(K, E0, bp, c, proposal=1, n_random=0)
-    r = oracle.sir(K, E0, bp, c, 1, p.alpha_star, p.log_M, 1, 2, 5000, 10, 0.5)
+@pytest.mark.parametrize("K,E0,bp,c,n", [(8, 1.0, 40.0, 20.0, 5000), (16, 2.0, 40.0, 60.0, 5000),
+                                         (128, 1.5, 40.0, 750.0, 400)])
+def test_parseval_moments_for_any_weights(K, E0, bp, c, n):
+    if K == 128:  # the plan only sets the weights' scale; any log M keeps Parseval
+        alpha, log_M = 1.0, 0.0
+    else:
+        p = OP.plan_point(K, E0, bp, c, proposal=1, n_random=0)
+        alpha, log_M = p.alpha_star, p.log_M
+    r = oracle.sir(K, E0, bp, c, 1, alpha, log_M, 1, 2, n, 10, 0.5)
     assert abs(r["moments"][0]) < 1e-12
     assert r["moments"][1] == pytest.approx(E0 / math.pi, rel=1e-12)
 
