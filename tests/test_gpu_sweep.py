@@ -10,8 +10,8 @@
   the same sequence directly, and to itself on a second call;
 * every tile variant of the decision kernel gives bit-identical results;
 * a point that reaches its proposal cap stops there;
-* against the oracle: the first n accepted samples of a K = 8, 16, 32 and 64
-  point;
+* against the oracle: the first n accepted samples of a K = 8, 16, 32, 64
+  and 128 point (K = 128 also with its 1024-thread tile variant);
 * the autotuner returns a valid configuration (variant, workgroups per
   compute unit, first window) and reads it back from its cache.
 """
@@ -55,6 +55,7 @@ SPECS = [  # K, beta', C3/C2, target, max proposals (acceptance ~3e-3, 3e-2, 3e-
     (64, 40.0, 150.0, 20000, 1 << 26),
     (32, 20.0, 300.0, 5000, 3_000_017),   # cap reached before the target
     (16, 40.0, 30.0, 12000, 1 << 26),
+    (128, 40.0, 750.0, 3000, 1 << 24),    # the quarter-period kernels
 ]
 
 
@@ -134,7 +135,8 @@ def test_sweep_tile_variants_are_bit_identical(T, ctx):
 
 @pytest.mark.parametrize("K,bp,c,target,variant", [(8, 40.0, 20.0, 400, 0), (16, 20.0, 60.0, 500, 0),
                                                    (32, 40.0, 75.0, 400, 0), (64, 40.0, 150.0, 300, 0),
-                                                   (64, 40.0, 300.0, 300, 3)])
+                                                   (64, 40.0, 300.0, 300, 3), (128, 40.0, 750.0, 300, 0),
+                                                   (128, 40.0, 750.0, 200, 2)])
 def test_sweep_against_oracle(T, ctx, K, bp, c, target, variant):
     pt = T.make_point(K, 1.0, bp, c, seed=0, point_id=0)
     pl = T.plan_point(pt, T.SIGMA)
