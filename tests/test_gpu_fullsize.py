@@ -4,7 +4,8 @@ The samplers run 1e9 proposals per point (the plain GPU, K = 64, K = 128 and
 learned configurations): the paper's sampler as one batched launch over two
 K = 32 points and on one K = 64 and one K = 128 point (the quarter-period
 kernels), the mixture sampler on one K = 32 point, and SIR over the same
-proposals as the rejection sampler.  The oracle then checks
+proposals as the rejection sampler; the batched sweep runs the benchmark's
+256 points to their accepted targets.  The oracle then checks
 sampled outputs one by one: 600 random proposal indices over the whole range
 (decision and, for accepted ones, the stored row), and 300 random accepted
 samples (an accept in FP64, the same row); the accepted count must be
@@ -185,3 +186,64 @@ def test_sir_draws_against_the_weights_2e27(T, ctx):
         lo, hi = sorted((d[r], ref[r]))
         assert np.min(np.abs(C[lo:hi] - pos[r])) <= 1e-9 * W
     say(f"SIR 2^27: {len(bad)} of {m} draws differ from the host search, all at boundaries")
+
+
+def test_sweep_at_benchmark_size(T, ctx):
+    """The batched sweep in the benchmark's configuration: the same 256 points
+    (the seeded candidates screened at 1e6 proposals), accepted targets
+    1e4..1e6, the autotuned launch configuration, windows replayed as a
+    hipGraph.  Every target is met; on eight points spread over K = 16, 32, 64
+    the stored rows (the first 2^14 accepted) and random proposal indices up
+    to the last stored one are checked against the oracle one by one."""
+    from paper_2411_16952_amd import workloads as W
+    prec = T.BF16X3
+    for K in (16, 32, 64):
+        ctx.autotune(K, prec, None)
+    cands = W.sweep_candidates()
+    kept, plans = [], []
+    for b0 in range(0, len(cands), 64):
+        batch = [sp for sp in cands[b0:b0 + 64]
+                 if sp.point.beta_p < sp.point.K ** 2 * sum(1.0 / (k * k) for k in range(1, sp.point.K + 1))]
+        cpts = [T.make_point(sp.point.K, sp.point.E0, sp.point.beta_p, sp.point.c32, seed=sp.point.seed,
+                             point_id=sp.point.point_id) for sp in batch]
+        cplans, _ = ctx.plan_batch(cpts, T.SIGMA, n_starts=16, seed=2024)
+        out, _, _ = ctx.sample_batch(cpts, [10**6] * len(cpts), plans=cplans, precision=prec)
+        for sp, p, pl, o in zip(batch, cpts, cplans, out):
+            if o["n_accepted"] >= 100 and len(kept) < W.SWEEP_N:
+                kept.append((sp, p))
+                plans.append(pl)
+        if len(kept) >= W.SWEEP_N:
+            break
+    assert len(kept) == W.SWEEP_N
+    pts = [p for _, p in kept]
+    targets = [int(sp.target) for sp, _ in kept]
+    caps = [min(t, 1 << 14) for t in targets]
+    out, _, _ = ctx.sample_sweep(pts, targets, [W.SWEEP_CAP] * len(pts), plans=plans, precision=prec, capacity=caps)
+    tm = ctx.timing()
+    say(f"sweep: {len(pts)} points, {sum(o['n_accepted'] for o in out)} accepted, {tm['windows']} windows, "
+        f"{tm['graph_launches']} graph launches, {tm['total_ms']:.0f} ms")
+    for o, t, c in zip(out, targets, caps):
+        assert o["n_accepted"] == t and o["n_written"] == c and o["n_M_violations"] == 0
+    rng = np.random.default_rng(11)
+    by_k = {K: [q for q, p in enumerate(pts) if p.K == K] for K in (16, 32, 64)}
+    picks = [q for K in (16, 32, 64) for q in rng.choice(by_k[K], size=min(3, len(by_k[K])), replace=False)][:8]
+    for q in picks:
+        p, pl, o = pts[q], plans[q], out[q]
+        idx = o["index"].cpu().numpy().astype(np.int64)
+        rows = o["xhat"].cpu().numpy().astype(np.float64)
+        assert np.all(np.diff(idx) > 0) and o["n_proposed"] > idx[-1]
+
+        def decide(i, p=p, pl=pl):
+            return oracle.proposal(p.K, p.E0, p.beta_p, p.c32, 1, pl.alpha_star, pl.log_M, p.seed, p.point_id, i)
+
+        for r in rng.integers(0, len(idx), 60):
+            x, la, lu = decide(int(idx[r]))
+            assert lu < la + AMBIG, f"point {q}: proposal {idx[r]} accepted on the GPU, rejected in FP64"
+            assert np.linalg.norm(rows[r] - x) < 1e-5
+        stored = set(idx.tolist())
+        for i in rng.integers(0, idx[-1] + 1, 120):
+            x, la, lu = decide(int(i))
+            if abs(la - lu) < AMBIG:
+                continue
+            assert (int(i) in stored) == (lu < la), f"point {q}: decision of proposal {i} differs"
+        say(f"   point {q} K={p.K}: target {targets[q]}, {o['n_proposed']} proposals, rows and decisions checked")
