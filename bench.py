@@ -508,15 +508,14 @@ def quarter_bench(args) -> int:
     K, workload = QUARTER_WORKLOADS[args.workload]
     specs = W.k64_points() if K == 64 else W.k128_points()
     pts = [T.make_point(s.K, s.E0, s.beta_p, s.c32, seed=s.seed, point_id=s.point_id) for s in specs]
+    ctx = T.Context(0)
     t0 = time.perf_counter()
-    with cf.ThreadPoolExecutor(max_workers=len(pts)) as ex:   # the host search of log M (2K coordinates)
-        plans = list(ex.map(lambda p: T.plan_point(p, T.SIGMA), pts))
+    plans, _ = ctx.plan_batch(pts, T.SIGMA, n_starts=16, seed=2024)   # log M searched on the GPU
     plan_s = time.perf_counter() - t0
     n_per = int(args.proposals)
     n = [n_per] * len(pts)
     cap = [1 << 20] * len(pts)
     prec = T.PRECISIONS[args.precision]
-    ctx = T.Context(0)
     print(f"bench: K={K}, {len(pts)} points, {n_per:.3g} proposals/point, {args.precision}, plans {plan_s:.1f}s",
           file=sys.stderr, flush=True)
 

@@ -3,13 +3,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <string>
-#include <thread>
 #include <vector>
 
 #include "../../include/tkdv.h"
@@ -1276,7 +1274,7 @@ tkdv_status tkdv_plan_point(const tkdv_point *pt, tkdv_proposal proposal, tkdv_p
 namespace {
 
 // The multi-start search of k_plan_search for the points pp (mixtures and
-// caller starts optional): values, final iterates [item][128] and evaluation
+// caller starts optional): values, final iterates [item][kPlanStride] and evaluation
 // counts per item, item = point * (n_starts + n_user) + start.
 tkdv_status run_plan_search(tkdv_ctx *ctx, const std::vector<PlanPoint> &pp, const std::vector<PlanMix> *mix,
                             const std::vector<double> *user, int n_user, int n_starts, uint64_t seed,
@@ -1288,7 +1286,7 @@ tkdv_status run_plan_search(tkdv_ctx *ctx, const std::vector<PlanPoint> &pp, con
     const int n_items = (int)pp.size() * per;
     HIP_TRY(ctx, ensure(ctx->plan_pts, pp.size() * sizeof(PlanPoint)));
     HIP_TRY(ctx, ensure(ctx->plan_val, (size_t)n_items * sizeof(double)));
-    HIP_TRY(ctx, ensure(ctx->plan_x, (size_t)n_items * 128 * sizeof(double)));
+    HIP_TRY(ctx, ensure(ctx->plan_x, (size_t)n_items * kPlanStride * sizeof(double)));
     HIP_TRY(ctx, ensure(ctx->plan_ev, (size_t)n_items * sizeof(int)));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->plan_pts.p, pp.data(), pp.size() * sizeof(PlanPoint), hipMemcpyHostToDevice, st));
     PlanArgs a{};
@@ -1313,9 +1311,11 @@ tkdv_status run_plan_search(tkdv_ctx *ctx, const std::vector<PlanPoint> &pp, con
     a.val = (double *)ctx->plan_val.p;
     a.xbest = (double *)ctx->plan_x.p;
     a.evals = (int *)ctx->plan_ev.p;
-    HIP_TRY(ctx, launch_plan_search(a, st));
+    int max_K = 0;
+    for (const PlanPoint &q : pp) max_K = std::max(max_K, q.K);
+    HIP_TRY(ctx, launch_plan_search(a, max_K, st));
     val.assign(n_items, 0.0);
-    xb.assign((size_t)n_items * 128, 0.0);
+    xb.assign((size_t)n_items * kPlanStride, 0.0);
     ev.assign(n_items, 0);
     HIP_TRY(ctx, hipMemcpyAsync(val.data(), a.val, val.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(ctx, hipMemcpyAsync(xb.data(), a.xbest, xb.size() * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1354,7 +1354,7 @@ tkdv_status tkdv_plan_batch(tkdv_ctx *ctx, int32_t n_points, const tkdv_point *p
     if (flags & ~TKDV_PLAN_SEARCH_ALWAYS) return set_err(ctx, TKDV_E_ARG, "unknown flags");
     if ((int64_t)n_points * n_starts > (int64_t)(1 << 30)) return set_err(ctx, TKDV_E_ARG, "too many starts");
     std::vector<PlanPoint> pp;
-    std::vector<int> which, on_host;
+    std::vector<int> which;
     for (int p = 0; p < n_points; ++p) {
         const int st = plan_base_host(&pts[p], proposal, &out[p]);
         if (st != TKDV_OK)
@@ -1363,10 +1363,6 @@ tkdv_status tkdv_plan_batch(tkdv_ctx *ctx, int32_t n_points, const tkdv_point *p
         if (out[p].M_source == 0 && !(flags & TKDV_PLAN_SEARCH_ALWAYS)) continue;
         const tkdv_point &q = pts[p];
         const int K = q.K;
-        if (K > 64) {  // one wave holds at most 128 coordinates: the host search instead
-            on_host.push_back(p);
-            continue;
-        }
         PlanPoint P{};
         P.K = K;
         P.N = 4 * K;
@@ -1379,22 +1375,6 @@ tkdv_status tkdv_plan_batch(tkdv_ctx *ctx, int32_t n_points, const tkdv_point *p
         P.a = out[p].alpha_star * q.beta_p / ((double)K * K * K);
         pp.push_back(P);
         which.push_back(p);
-    }
-    if (!on_host.empty()) {  // the host searches of K > 64, on all host threads
-        std::vector<int> hst(on_host.size(), TKDV_OK);
-        std::atomic<size_t> next{0};
-        auto work = [&]() {
-            for (size_t q; (q = next.fetch_add(1)) < on_host.size();)
-                hst[q] = plan_point_host(&pts[on_host[q]], proposal, 2, &out[on_host[q]]);
-        };
-        const size_t nt = std::min<size_t>(on_host.size(), std::max(1u, std::thread::hardware_concurrency()));
-        std::vector<std::thread> pool;
-        for (size_t t = 1; t < nt; ++t) pool.emplace_back(work);
-        work();
-        for (std::thread &t : pool) t.join();
-        for (size_t q = 0; q < on_host.size(); ++q)
-            if (hst[q] != TKDV_OK)
-                return set_err(ctx, (tkdv_status)hst[q], "point " + std::to_string(on_host[q]) + ": planning failed");
     }
     if (which.empty()) return TKDV_OK;
     std::vector<double> val, xb;
@@ -1410,7 +1390,7 @@ tkdv_status tkdv_plan_batch(tkdv_ctx *ctx, int32_t n_points, const tkdv_point *p
         out[p].M_source = 2;
         out[p].n_optimiser_evals = (int32_t)std::min<long>(total, INT32_MAX);
         if (xhat_best)
-            for (int m = 0; m < 2 * pts[p].K; ++m) xhat_best[(size_t)p * 2 * TKDV_KMAX + m] = xb[(size_t)bi * 128 + m];
+            for (int m = 0; m < 2 * pts[p].K; ++m) xhat_best[(size_t)p * 2 * TKDV_KMAX + m] = xb[(size_t)bi * kPlanStride + m];
     }
     return TKDV_OK;
 }
@@ -1430,7 +1410,7 @@ tkdv_status tkdv_plan_mixture_batch(tkdv_ctx *ctx, int32_t n_points, const tkdv_
     if ((int64_t)n_points * (n_starts + n_user) > (int64_t)(1 << 30)) return set_err(ctx, TKDV_E_ARG, "too many starts");
     std::vector<PlanPoint> pp(n_points);
     std::vector<PlanMix> pm(n_points);
-    std::vector<double> user((size_t)n_points * std::max(n_user, 0) * 128, 0.0);
+    std::vector<double> user((size_t)n_points * std::max(n_user, 0) * kPlanStride, 0.0);
     std::vector<double> cap(n_points), log_eps(n_points);
     for (int p = 0; p < n_points; ++p) {
         const tkdv_point &q = pts[p];
@@ -1478,7 +1458,7 @@ tkdv_status tkdv_plan_mixture_batch(tkdv_ctx *ctx, int32_t n_points, const tkdv_
             for (int c = 0; c < n2; ++c) r2 += src[c] * src[c];
             if (!(r2 > 0.0) || !std::isfinite(r2))
                 return set_err(ctx, TKDV_E_ARG, "point " + std::to_string(p) + ": a caller start is zero or not finite");
-            for (int c = 0; c < n2; ++c) user[((size_t)p * n_user + u) * 128 + c] = src[c];
+            for (int c = 0; c < n2; ++c) user[((size_t)p * n_user + u) * kPlanStride + c] = src[c];
         }
     }
     std::vector<double> val, xb;
@@ -1498,7 +1478,7 @@ tkdv_status tkdv_plan_mixture_batch(tkdv_ctx *ctx, int32_t n_points, const tkdv_
         out[p].n_optimiser_evals = (int32_t)std::min<long>(total, INT32_MAX);
         if (xhat_best) {
             std::fill(xhat_best + (size_t)p * 2 * TKDV_KMAX, xhat_best + (size_t)(p + 1) * 2 * TKDV_KMAX, 0.0);
-            for (int m = 0; m < 2 * pts[p].K; ++m) xhat_best[(size_t)p * 2 * TKDV_KMAX + m] = xb[(size_t)bi * 128 + m];
+            for (int m = 0; m < 2 * pts[p].K; ++m) xhat_best[(size_t)p * 2 * TKDV_KMAX + m] = xb[(size_t)bi * kPlanStride + m];
         }
     }
     return TKDV_OK;

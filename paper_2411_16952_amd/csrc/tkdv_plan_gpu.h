@@ -12,6 +12,7 @@ constexpr int kPlanWaves = 4;          // wavefronts (starts) per workgroup
 constexpr int kPlanMem = 8;            // L-BFGS memory (pairs)
 constexpr int kPlanMaxIter = 400;      // ascent iterations per start
 constexpr int kPlanMaxBacktrack = 50;  // step halvings per line search
+constexpr int kPlanStride = 256;       // doubles per start / final iterate (2 TKDV_KMAX)
 
 // One point of the search: the objective is
 //   phi(x^) = dt0 t + cH (pi/(3N)) amp^3 sum_j u~_j^3 [+ K log(1 + a t)]
@@ -41,16 +42,17 @@ struct PlanMix {
 struct PlanArgs {
     const PlanPoint *pts;
     const PlanMix *mix;     // [points] or nullptr: the mixture objective
-    const double *x_user;   // [points][n_user][128] caller starts or nullptr
+    const double *x_user;   // [points][n_user][kPlanStride] caller starts or nullptr
     int n_user;             // caller starts per point (items n_starts .. n_starts + n_user - 1)
     int n_items;        // points x (n_starts + n_user)
     int n_starts;       // generated starts per point
     uint32_t seed_lo, seed_hi;
     double *val;        // [n_items] objective at the final iterate
-    double *xbest;      // [n_items][128] final iterate (unit vector)
+    double *xbest;      // [n_items][kPlanStride] final iterate (unit vector)
     int *evals;         // [n_items] objective evaluations
 };
 
-hipError_t launch_plan_search(const PlanArgs &a, hipStream_t st);
+// max_K: the largest K among the points (at most kPlanStride / 2)
+hipError_t launch_plan_search(const PlanArgs &a, int max_K, hipStream_t st);
 
 }  // namespace tkdv

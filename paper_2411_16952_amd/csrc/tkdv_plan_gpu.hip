@@ -11,8 +11,8 @@
 //   H3 = (pi/(3N)) amp^3 sum_j u~_j^3 (exact for N >= 3K + 1),
 //   d/dx^_m sum_j u~_j^3 = 3 sum_j u~_j^2 Phi_mj,
 // with one table of cos(2 pi r/N) in LDS (sin by a quarter-period offset).
-// Lane l holds coordinates l and l + 64 of x^ and the gradient, and grid
-// points l + 64 r.  Every branch taken on a wave-reduced quantity goes
+// Lane l holds coordinates l + 64 c of x^ and the gradient (c < C: C = 2 for
+// K <= 64, 4 for K = 128), and grid points l + 64 r.  Every branch taken on a wave-reduced quantity goes
 // through readfirstlane, so all lanes of a wave follow one path.
 #include "tkdv_device.h"
 #include "tkdv_plan_gpu.h"
@@ -88,21 +88,31 @@ __device__ double mix_log_q(const PlanMix &M, int K, int lane, double x0, double
     return lm;
 }
 
-// phi at the unit vector (x0, x1) and its tangent gradient (g0, g1).
+// phi at the unit vector x (lane l holds coordinates l + 64 c, c < C) and its
+// tangent gradient g.  Sums over a lane's coordinates run in the order c = 0,
+// 1, ..., so C = 4 gives K <= 64 the bits of C = 2 (the extra terms are zeros).
+template <int C>
 __device__ double plan_eval(const PlanPoint &P, const PlanMix *mix, double *xs, double *us, const double *ct,
-                            int lane, double x0, double x1, double &g0, double &g1)
+                            int lane, const double (&x)[C], double (&g)[C])
 {
     const int K = P.K, N = P.N, n2 = 2 * K, q = N / 4;
-    const int m0 = lane, m1 = lane + 64;
-    const bool v0 = m0 < n2, v1 = m1 < n2;
-    if (v0) xs[m0] = x0;
-    if (v1) xs[m1] = x1;
+    bool v[C];
+    int kk[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int m = lane + 64 * c;
+        v[c] = m < n2;
+        kk[c] = m % K + 1;
+        if (v[c]) xs[m] = x[c];
+    }
     wave_sync_lds();
-    const int k0 = m0 % K + 1, k1 = m1 % K + 1;
-    const double t = wsum((v0 ? (double)k0 * k0 * x0 * x0 : 0.0) + (v1 ? (double)k1 * k1 * x1 * x1 : 0.0));
+    double tl = v[0] ? (double)kk[0] * kk[0] * x[0] * x[0] : 0.0;
+#pragma unroll
+    for (int c = 1; c < C; ++c) tl += v[c] ? (double)kk[c] * kk[c] * x[c] * x[c] : 0.0;
+    const double t = wsum(tl);
     double s3 = 0.0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < 2 * C; ++r) {  // grid points lane + 64 r (N <= 128 C)
         const int j = lane + 64 * r;
         if (j < N) {
             double u = 0.0;
@@ -135,7 +145,6 @@ __device__ double plan_eval(const PlanPoint &P, const PlanMix *mix, double *xs, 
         }
         return (k & 1) ? -acc : acc;
     };
-    const double d0 = v0 ? dh(m0) : 0.0, d1 = v1 ? dh(m1) : 0.0;
     double val = P.dt0 * t + P.cH * (kPiP / (3.0 * N)) * P.amp3 * S3;
     double dt = P.dt0;
     if (P.sigma) {
@@ -143,25 +152,44 @@ __device__ double plan_eval(const PlanPoint &P, const PlanMix *mix, double *xs, 
         dt += K * P.a / (1.0 + P.a * t);
     }
     const double cg = P.cH * kPiP * P.amp3 / N;
-    g0 = v0 ? dt * 2.0 * k0 * k0 * x0 + cg * d0 : 0.0;
-    g1 = v1 ? dt * 2.0 * k1 * k1 * x1 + cg * d1 : 0.0;
-    if (mix) {  // phi = log f - log q_mix (K <= 32: x1 is unused)
-        double dq;
-        val -= mix_log_q(*mix, K, lane, x0, t, dq);
-        g0 -= dq;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const double d = v[c] ? dh(lane + 64 * c) : 0.0;
+        g[c] = v[c] ? dt * 2.0 * kk[c] * kk[c] * x[c] + cg * d : 0.0;
     }
-    const double gx = wsum(g0 * x0 + g1 * x1);
-    g0 -= gx * x0;
-    g1 -= gx * x1;
+    if constexpr (C == 2) {
+        if (mix) {  // phi = log f - log q_mix (K <= 32: coordinate `lane` only)
+            double dq;
+            val -= mix_log_q(*mix, K, lane, x[0], t, dq);
+            g[0] -= dq;
+        }
+    }
+    double gxl = g[0] * x[0];
+#pragma unroll
+    for (int c = 1; c < C; ++c) gxl += g[c] * x[c];
+    const double gx = wsum(gxl);
+#pragma unroll
+    for (int c = 0; c < C; ++c) g[c] -= gx * x[c];
     wave_sync_lds();  // the next evaluation overwrites xs and us
     return val;
 }
 
+// Lane sums of a . b over the lane's C coordinates, in the order c = 0, 1, ...
+template <int C>
+__device__ __forceinline__ double dotl(const double (&a)[C], const double (&b)[C])
+{
+    double s = a[0] * b[0];
+#pragma unroll
+    for (int c = 1; c < C; ++c) s += a[c] * b[c];
+    return s;
+}
+
+template <int C>
 __global__ void __launch_bounds__(64 * kPlanWaves) k_plan_search(PlanArgs a)
 {
-    __shared__ double xs_all[kPlanWaves][128];
-    __shared__ double us_all[kPlanWaves][256];
-    __shared__ double ct_all[kPlanWaves][256];
+    __shared__ double xs_all[kPlanWaves][64 * C];
+    __shared__ double us_all[kPlanWaves][128 * C];
+    __shared__ double ct_all[kPlanWaves][128 * C];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int item = blockIdx.x * kPlanWaves + w;
@@ -173,17 +201,17 @@ __global__ void __launch_bounds__(64 * kPlanWaves) k_plan_search(PlanArgs a)
     double *xs = xs_all[w], *us = us_all[w], *ct = ct_all[w];
     const int K = P.K, N = P.N, n2 = 2 * K;
     for (int r = lane; r < N; r += 64) ct[r] = cos(2.0 * kPiP * r / N);
-    const int m0 = lane, m1 = lane + 64;
-    double x0 = 0.0, x1 = 0.0;
+    double x[C];
     if (s >= a.n_starts) {  // a caller start
-        const double *u = a.x_user + ((size_t)p * a.n_user + (s - a.n_starts)) * 128;
-        x0 = m0 < n2 ? u[m0] : 0.0;
-        x1 = m1 < n2 ? u[m1] : 0.0;
+        const double *u = a.x_user + ((size_t)p * a.n_user + (s - a.n_starts)) * kPlanStride;
+#pragma unroll
+        for (int c = 0; c < C; ++c) x[c] = lane + 64 * c < n2 ? u[lane + 64 * c] : 0.0;
     } else if (s == 0) {  // zero-mean Dirichlet kernel: equal cos coefficients
-        x0 = m0 < K ? 1.0 : 0.0;
-        x1 = m1 < K ? 1.0 : 0.0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) x[c] = lane + 64 * c < K ? 1.0 : 0.0;
     } else if (s == 1) {  // all energy in mode 1
-        x0 = m0 == 0 ? 1.0 : 0.0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) x[c] = lane + 64 * c == 0 ? 1.0 : 0.0;
     } else {  // independent normal coordinates, Box-Muller pairs of Philox words
         auto normal = [&](int m) {
             const uint4 wd = philox4x32_10((uint32_t)s, P.point_id, (uint32_t)(m >> 1), 0x504C414Eu, a.seed_lo,
@@ -192,68 +220,76 @@ __global__ void __launch_bounds__(64 * kPlanWaves) k_plan_search(PlanArgs a)
             const double r = sqrt(-2.0 * log(u1)), th = 2.0 * kPiP * u2;
             return (m & 1) ? r * sin(th) : r * cos(th);
         };
-        x0 = m0 < n2 ? normal(m0) : 0.0;
-        x1 = m1 < n2 ? normal(m1) : 0.0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) x[c] = lane + 64 * c < n2 ? normal(lane + 64 * c) : 0.0;
     }
     {
-        const double r = sqrt(wsum(x0 * x0 + x1 * x1));
-        x0 /= r;
-        x1 /= r;
+        const double r = sqrt(wsum(dotl<C>(x, x)));
+#pragma unroll
+        for (int c = 0; c < C; ++c) x[c] /= r;
     }
     wave_sync_lds();  // cos table
-    double g0, g1;
-    double f = plan_eval(P, M, xs, us, ct, lane, x0, x1, g0, g1);
+    double g[C];
+    double f = plan_eval<C>(P, M, xs, us, ct, lane, x, g);
     int evals = 1;
     // curvature pairs, newest first: s = x_new - x_old, y = g_old - g_new
-    double S0[kPlanMem], S1[kPlanMem], Y0[kPlanMem], Y1[kPlanMem], RHO[kPlanMem];
+    double S[kPlanMem][C], Y[kPlanMem][C], RHO[kPlanMem];
 #pragma unroll
-    for (int i = 0; i < kPlanMem; ++i) S0[i] = S1[i] = Y0[i] = Y1[i] = RHO[i] = 0.0;
+    for (int i = 0; i < kPlanMem; ++i) {
+        RHO[i] = 0.0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) S[i][c] = Y[i][c] = 0.0;
+    }
     int mc = 0;
     double gamma = 1.0;
     for (int it = 0; it < kPlanMaxIter; ++it) {
-        const double gn = sqrt(wsum(g0 * g0 + g1 * g1));
+        const double gn = sqrt(wsum(dotl<C>(g, g)));
         if (uniform(!(gn > 1e-13 * (1.0 + fabs(f))))) break;
         // two-loop recursion on the ascent problem: d = H g
-        double q0 = g0, q1 = g1, al[kPlanMem];
+        double qv[C], al[kPlanMem];
+#pragma unroll
+        for (int c = 0; c < C; ++c) qv[c] = g[c];
 #pragma unroll
         for (int i = 0; i < kPlanMem; ++i) {
             al[i] = 0.0;
             if (i < mc) {
-                al[i] = RHO[i] * wsum(S0[i] * q0 + S1[i] * q1);
-                q0 -= al[i] * Y0[i];
-                q1 -= al[i] * Y1[i];
+                al[i] = RHO[i] * wsum(dotl<C>(S[i], qv));
+#pragma unroll
+                for (int c = 0; c < C; ++c) qv[c] -= al[i] * Y[i][c];
             }
         }
-        q0 *= gamma;
-        q1 *= gamma;
+#pragma unroll
+        for (int c = 0; c < C; ++c) qv[c] *= gamma;
 #pragma unroll
         for (int i = kPlanMem - 1; i >= 0; --i) {
             if (i < mc) {
-                const double b = RHO[i] * wsum(Y0[i] * q0 + Y1[i] * q1);
-                q0 += S0[i] * (al[i] - b);
-                q1 += S1[i] * (al[i] - b);
+                const double b = RHO[i] * wsum(dotl<C>(Y[i], qv));
+#pragma unroll
+                for (int c = 0; c < C; ++c) qv[c] += S[i][c] * (al[i] - b);
             }
         }
-        double d0 = q0, d1 = q1;
-        double slope = wsum(d0 * g0 + d1 * g1);
+        double d[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) d[c] = qv[c];
+        double slope = wsum(dotl<C>(d, g));
         double step = 1.0;
         if (uniform(!(slope > 0.0)) || mc == 0) {  // steepest ascent, at most half a radian
-            d0 = g0;
-            d1 = g1;
+#pragma unroll
+            for (int c = 0; c < C; ++c) d[c] = g[c];
             slope = gn * gn;
             mc = 0;
             gamma = 1.0;
             step = fmin(1.0, 0.5 / gn);
         }
-        double f2 = f, x20 = x0, x21 = x1, g20 = g0, g21 = g1;
+        double f2 = f, x2[C], g2[C];
         bool ok = false;
         for (int ls = 0; ls < kPlanMaxBacktrack; ++ls) {
-            x20 = x0 + step * d0;
-            x21 = x1 + step * d1;
-            const double r = sqrt(wsum(x20 * x20 + x21 * x21));
-            x20 /= r;
-            x21 /= r;
-            f2 = plan_eval(P, M, xs, us, ct, lane, x20, x21, g20, g21);
+#pragma unroll
+            for (int c = 0; c < C; ++c) x2[c] = x[c] + step * d[c];
+            const double r = sqrt(wsum(dotl<C>(x2, x2)));
+#pragma unroll
+            for (int c = 0; c < C; ++c) x2[c] /= r;
+            f2 = plan_eval<C>(P, M, xs, us, ct, lane, x2, g2);
             ++evals;
             if (uniform(f2 >= f + 1e-4 * step * slope)) {
                 ok = true;
@@ -262,36 +298,44 @@ __global__ void __launch_bounds__(64 * kPlanWaves) k_plan_search(PlanArgs a)
             step *= 0.5;
         }
         if (!ok) break;
-        const double sx0 = x20 - x0, sx1 = x21 - x1, yv0 = g0 - g20, yv1 = g1 - g21;
-        const double sy = wsum(sx0 * yv0 + sx1 * yv1), yy = wsum(yv0 * yv0 + yv1 * yv1);
+        double sx[C], yv[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            sx[c] = x2[c] - x[c];
+            yv[c] = g[c] - g2[c];
+        }
+        const double sy = wsum(dotl<C>(sx, yv)), yy = wsum(dotl<C>(yv, yv));
         const double gain = f2 - f;
-        x0 = x20;
-        x1 = x21;
-        g0 = g20;
-        g1 = g21;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            x[c] = x2[c];
+            g[c] = g2[c];
+        }
         f = f2;
         if (uniform(sy > 1e-300 && yy > 0.0)) {
 #pragma unroll
             for (int i = kPlanMem - 1; i > 0; --i) {
-                S0[i] = S0[i - 1];
-                S1[i] = S1[i - 1];
-                Y0[i] = Y0[i - 1];
-                Y1[i] = Y1[i - 1];
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    S[i][c] = S[i - 1][c];
+                    Y[i][c] = Y[i - 1][c];
+                }
                 RHO[i] = RHO[i - 1];
             }
-            S0[0] = sx0;
-            S1[0] = sx1;
-            Y0[0] = yv0;
-            Y1[0] = yv1;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                S[0][c] = sx[c];
+                Y[0][c] = yv[c];
+            }
             RHO[0] = 1.0 / sy;
             gamma = sy / yy;
             mc = mc < kPlanMem ? mc + 1 : kPlanMem;
         }
         if (uniform(gain < 1e-16 * (1.0 + fabs(f)) && it > 5)) break;
     }
-    double *xo = a.xbest + (size_t)item * 128;
-    xo[m0] = m0 < n2 ? x0 : 0.0;
-    xo[m1] = m1 < n2 ? x1 : 0.0;
+    double *xo = a.xbest + (size_t)item * kPlanStride;
+#pragma unroll
+    for (int c = 0; c < C; ++c) xo[lane + 64 * c] = lane + 64 * c < n2 ? x[c] : 0.0;
     if (lane == 0) {
         a.val[item] = f;
         a.evals[item] = evals;
@@ -300,11 +344,13 @@ __global__ void __launch_bounds__(64 * kPlanWaves) k_plan_search(PlanArgs a)
 
 }  // namespace
 
-hipError_t launch_plan_search(const PlanArgs &a, hipStream_t st)
+hipError_t launch_plan_search(const PlanArgs &a, int max_K, hipStream_t st)
 {
     if (a.n_items <= 0) return hipSuccess;
+    if (max_K > kPlanStride / 2) return hipErrorInvalidValue;
     const unsigned grid = (unsigned)((a.n_items + kPlanWaves - 1) / kPlanWaves);
-    hipLaunchKernelGGL(k_plan_search, dim3(grid), dim3(64 * kPlanWaves), 0, st, a);
+    if (max_K <= 64) hipLaunchKernelGGL(k_plan_search<2>, dim3(grid), dim3(64 * kPlanWaves), 0, st, a);
+    else hipLaunchKernelGGL(k_plan_search<4>, dim3(grid), dim3(64 * kPlanWaves), 0, st, a);
     return hipGetLastError();
 }
 
