@@ -126,8 +126,11 @@ __global__ void __launch_bounds__(BL) k_decide128(KernelArgs a, const int *plist
             const float alin = __builtin_amdgcn_exp2f(la * 1.4426950408889634f);
             const float lo_edge = alin * P.e_lo, hi_edge = alin * P.e_hi;
             const bool mine = valid && g == 0;
-            const bool defer = mine && U >= lo_edge && U < hi_edge;
-            const bool accept = mine && U < lo_edge;
+            // above the bound by no more than the fast path's error (0 < log a <= tau):
+            // the decision and the check of eq. (M_sup) are left to the FP64 pass
+            const bool near_bound = la > 0.0f && la <= P.tau;
+            const bool defer = mine && ((U >= lo_edge && U < hi_edge) || near_bound);
+            const bool accept = mine && U < lo_edge && !near_bound;
             const unsigned long long bacc = __ballot(accept);
             const unsigned long long bdef = __ballot(defer);
             if (lane == (c2 >> 1)) my_word |= (uint32_t)(bacc & 0xffffull) << (16 * (c2 & 1));
