@@ -249,6 +249,29 @@ def test_sample_raises_a_violated_M(T, ctx):
     assert np.array_equal(out[0]["index"].cpu().numpy(), r["index"].cpu().numpy())
 
 
+@pytest.mark.parametrize("K,bp", [(8, 20.0), (16, 20.0), (32, 60.0), (64, 40.0)])
+def test_exact_M_is_kept_at_linear_points(T, ctx, K, bp):
+    """C3/C2 = 0: log M is the closed form, the exact supremum, so f/(M g) <= 1
+    holds everywhere and no proposal may count as a violation.  Near the
+    maximiser the fast path's log a can round above 0 by a few ulps; those
+    proposals are settled in FP64, M is kept (no raise), and the accepted set
+    is the oracle's at that M (acceptance 0.8-0.99 here, so nearly every
+    proposal's decision is compared)."""
+    n = 100_003
+    pt = T.make_point(K, 1.0, bp, 0.0, seed=21, point_id=4)
+    plan = T.plan_point(pt, T.SIGMA)
+    assert plan.M_source == 0
+    r = ctx.sample(pt, n, plan=plan, precision=T.BF16X3, capacity=n)
+    say(f"K={K} beta'={bp}: accepted {r['n_accepted']} of {n}, max fast-path log a {r['max_log_a']:.2e}, "
+        f"raises {r['M_raises']}, FP64 re-decisions {r['n_fp64_fixups']}")
+    assert r["M_raises"] == 0 and r["n_M_violations"] == 0 and r["log_M_used"] == plan.log_M
+    o = oracle_run(pt, plan, T.SIGMA, n, cap=n)
+    amb = np.abs(o["log_u"] - o["log_a"]) < AMBIG
+    acc_g = np.zeros(n, dtype=bool)
+    acc_g[r["index"].cpu().numpy().astype(np.int64)] = True
+    assert not ((acc_g != o["accept"].astype(bool)) & ~amb).any()
+
+
 def test_invalid_arguments_are_rejected(T, ctx):
     with pytest.raises(T.TkdvError) as e:
         ctx.sample(T.make_point(12, 1.0, 10.0, 1.0), 100)
