@@ -249,7 +249,7 @@ def test_sample_raises_a_violated_M(T, ctx):
     assert np.array_equal(out[0]["index"].cpu().numpy(), r["index"].cpu().numpy())
 
 
-@pytest.mark.parametrize("K,bp", [(8, 20.0), (16, 20.0), (32, 60.0), (64, 40.0)])
+@pytest.mark.parametrize("K,bp", [(8, 20.0), (16, 20.0), (32, 60.0), (64, 40.0), (128, 40.0)])
 def test_exact_M_is_kept_at_linear_points(T, ctx, K, bp):
     """C3/C2 = 0: log M is the closed form, the exact supremum, so f/(M g) <= 1
     holds everywhere and no proposal may count as a violation.  Near the
