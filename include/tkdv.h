@@ -273,7 +273,8 @@ tkdv_status tkdv_extremes(tkdv_ctx *ctx, int32_t K, double E0, const float *d_xh
 typedef struct {
     uint64_t n;            /* proposals weighted                                          */
     uint64_t m;            /* draws                                                       */
-    uint64_t n_over_one;   /* weights above 1 (where M is not a bound on f/g)             */
+    uint64_t n_over_one;   /* weights above 1 by more than the fast path's error bound    */
+                           /* (log w > tau: M is not a bound on f/g there)                */
     uint64_t pad;
     double W;              /* sum of the weights w_i = f/(M g) at proposal i               */
     double W2;             /* sum of w_i^2                                                 */

@@ -228,7 +228,7 @@ __global__ void __launch_bounds__(kBlock) k_sir_weights(SirArgs a)
         m2 += wd * (double)s2;
         m3 += wd * (double)s3;
         m4 += wd * (double)s4;
-        over += (mine && w > 1.0f) ? 1.0 : 0.0;
+        over += (mine && la > P.tau) ? 1.0 : 0.0;  // above 1 beyond the fast path's error
     }
     w2 = sum64(w2);
     mx = max64(mx);
@@ -339,7 +339,7 @@ __global__ void __launch_bounds__(Quarter<K>::BLOCK) k_sir_weights_q(SirArgs a)
             m2 += wd * (double)s2;
             m3 += wd * (double)s3;
             m4 += wd * (double)s4;
-            over += (mine && w > 1.0f) ? 1.0 : 0.0;
+            over += (mine && la > P.tau) ? 1.0 : 0.0;  // above 1 beyond the fast path's error
         }
         if (lane == 0) a.tile_sum[tile] = ts;
     }
