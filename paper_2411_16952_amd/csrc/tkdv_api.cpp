@@ -1681,7 +1681,7 @@ tkdv_status tkdv_sir(tkdv_ctx *ctx, const tkdv_point *pt, tkdv_proposal proposal
         if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) ctx->timing.decide_ms = ms;
         if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[2]) == hipSuccess) ctx->timing.total_ms = ms;
         ctx->timing.decide_grid = K == 128 ? ctx->n_cu : 4 * ctx->n_cu;
-        ctx->timing.decide_block = K == 128 ? decide_block(128) : kBlock;
+        ctx->timing.decide_block = sir_block(K);
     }
     // per-wave partials in wave order
     double W2 = 0.0, mx = 0.0, M[4] = {0.0, 0.0, 0.0, 0.0}, over = 0.0;

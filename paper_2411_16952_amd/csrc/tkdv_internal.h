@@ -14,9 +14,9 @@ constexpr int kBlock = 256;        // threads per workgroup of the sampling kern
 // Workgroup of the default decision kernel of each K: at K <= 32 the
 // half-period k_decide; at K = 64 and K = 128 the quarter-period kernel
 // (tkdv_quarter.hip): workgroups of 256 threads at K = 64 (32 KB of tables
-// with BF16x3, several workgroups per CU), of 512 at K = 128 (128 KB of
-// tables, one workgroup of 8 waves per CU).
-constexpr int decide_block(int K) { return K == 128 ? 512 : kBlock; }
+// with BF16x3, several workgroups per CU), of 768 at K = 128 (128 KB of
+// tables, one workgroup of 12 waves per CU, 3 per SIMD).
+constexpr int decide_block(int K) { return K == 128 ? 768 : kBlock; }
 // The half-period k_decide at K = 64 (a tile variant of the sweep's tuner):
 // one copy of its 64 KB of tables served 12 waves, 3 per SIMD (168 registers a
 // lane; four waves spill inside the tile loop).

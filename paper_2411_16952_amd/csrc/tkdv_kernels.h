@@ -46,7 +46,6 @@ hipError_t launch_decide128(int prec, int prop, const KernelArgs &a, const int *
                             unsigned long long total_tiles, hipStream_t st, int *grid_out);
 hipError_t launch_decide_quarter64(int prec, int prop, const KernelArgs &a, const int *plist, int n_plist, int n_cu,
                                    unsigned long long total_tiles, hipStream_t st, int *grid_out);
-int decide128_block();
 int decide128_max_blocks_per_cu(int prec);
 int decide_quarter64_max_blocks_per_cu(int prec);
 // K = 128 tile variants (BF16x3, the paper's proposal); variant 0 is launch_decide128's

@@ -48,10 +48,12 @@ struct Quarter {
     // bytes of one table: BF16 [tile][out][step][64 lanes][8], FP32 [tile][out][group][64 lanes][4]
     static constexpr int BF16_BYTES = TILES * 4 * STEPS * 64 * 16;
     static constexpr int F32_BYTES = TILES * 4 * QG * 64 * 16;
-    // workgroup: at K = 128 the 128 KB of tables leave one workgroup per CU;
-    // 8 waves (2 per SIMD) share them with every register they need (12 waves
-    // spill some 30 registers a lane, whose stores reach HBM, for no gain in
-    // speed); at K = 64 (32 KB) workgroups of 256
+    // workgroup of the kernels that hold a whole proposal's power sums (the
+    // SIR weights, the synthesis, the verification instantiation of the
+    // decision kernel): at K = 128 the 128 KB of tables leave one workgroup
+    // per CU, 8 waves (2 per SIMD) with every register they need; at K = 64
+    // (32 KB) workgroups of 256.  The sampling decision kernel takes
+    // decide_block(K).
     static constexpr int BLOCK = K == 128 ? 512 : 256;
     static constexpr int lds(int prec) { return prec == PREC_FP32 ? F32_BYTES : 2 * BF16_BYTES; }
 };
@@ -226,15 +228,16 @@ __device__ __forceinline__ void quarter_tiles_f32(const float (&c)[K / 4], const
 }
 
 // The same from BF16 operands [out][step] (hi, and lo for BF16x3) with FP32
-// accumulation.
-template <int K, int PREC, class Fold>
+// accumulation; UNR tiles per loop trip (two let one tile's products run
+// beside the previous tile's fold).
+template <int K, int PREC, class Fold, int UNR = 1>
 __device__ __forceinline__ void quarter_tiles_bf16(const bf16x8 (&bh)[4][K / 64], const bf16x8 (&bl)[4][K / 64],
                                                    const char *lds_hi, const char *lds_lo, int lane, Fold &&fold)
 {
     constexpr int R = Quarter<K>::STEPS;
     const bf16x8 *th = reinterpret_cast<const bf16x8 *>(lds_hi);
     const bf16x8 *tl = reinterpret_cast<const bf16x8 *>(lds_lo);
-#pragma unroll 1
+#pragma unroll UNR
     for (int tau = 0; tau < Quarter<K>::TILES; ++tau) {
         f32x4 acc[4] = {f32x4{}, f32x4{}, f32x4{}, f32x4{}};
 #pragma unroll
@@ -269,15 +272,15 @@ __device__ __forceinline__ float cube_sum_q128_f32(const float (&c)[K / 4], cons
 }
 
 // The same from BF16 operands.
-template <int K, int PREC>
+template <int K, int PREC, int UNR = 1>
 __device__ __forceinline__ float cube_sum_q128_bf16(const bf16x8 (&bh)[4][K / 64], const bf16x8 (&bl)[4][K / 64],
                                                     const char *lds_hi, const char *lds_lo, int lane)
 {
     float s1 = 0.0f, s2 = 0.0f;
-    quarter_tiles_bf16<K, PREC>(bh, bl, lds_hi, lds_lo, lane,
-                                [&](const f32x4 &ce, const f32x4 &co, const f32x4 &se, const f32x4 &so) {
-                                    quarter_cubes(ce, co, se, so, s1, s2);
-                                });
+    auto fold = [&](const f32x4 &ce, const f32x4 &co, const f32x4 &se, const f32x4 &so) {
+        quarter_cubes(ce, co, se, so, s1, s2);
+    };
+    quarter_tiles_bf16<K, PREC, decltype(fold) &, UNR>(bh, bl, lds_hi, lds_lo, lane, fold);
     return __builtin_fmaf(4.0f, s1, 4.6188021535170061f * s2);  // 4 s1 + (8/sqrt 3) s2
 }
 

@@ -33,10 +33,14 @@ __device__ __forceinline__ void add0(unsigned long long *ctr, unsigned long long
 // k_decide128: persistent; claims of 64 accept words (2048 proposals, 128
 // tiles of 16) from per-point queues, as the other decision kernels.
 // ---------------------------------------------------------------------------
-// DBG: the verification entry's instantiation (per-proposal outputs written);
-// the sampling calls run the one without, which needs fewer registers.
-// BL: workgroup threads (Quarter<K>::BLOCK, or a tile variant's).
-template <int K, int PREC, int PROP, bool DBG, int BL = Quarter<K>::BLOCK>
+// DBG: the verification entry's instantiation (per-proposal outputs written,
+// workgroups of Quarter<K>::BLOCK); the sampling calls run the one without,
+// which needs fewer registers.  BL: workgroup threads (decide_block(K), or a
+// tile variant's).  |X| and t are finished before the synthesis: left for
+// after it, the compiler keeps the sin block's 32 coordinates (K = 128) live
+// through the products to sum their squares there, which leaves room for 2
+// waves per SIMD instead of 3.
+template <int K, int PREC, int PROP, bool DBG, int BL = decide_block(K)>
 __global__ void __launch_bounds__(BL) k_decide128(KernelArgs a, const int *plist, int n_plist)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
@@ -92,11 +96,13 @@ __global__ void __launch_bounds__(BL) k_decide128(KernelArgs a, const int *plist
                 }
             }
             const uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32);
-            float r2 = 0.0f, a1 = 0.0f, a2 = 0.0f, s3l;
+            float r2 = 0.0f, a1 = 0.0f, a2 = 0.0f, s3l, t, inv;
             if constexpr (PREC == PREC_FP32) {
                 float c[CPL], s[CPL];
                 gen_block128<K, PROP>(P, c0, c1, g, 0, c, r2, a1, a2);
                 gen_block128<K, PROP>(P, c0, c1, g, 1, s, r2, a1, a2);
+                inv = finish_norm128<K>(g, r2, a1, a2, t);
+                __builtin_amdgcn_sched_barrier(0);
                 s3l = cube_sum_q128_f32<K>(c, s, lds_hi, lane);
             } else {
                 // one block at a time: its coordinates die once split into operands
@@ -115,11 +121,11 @@ __global__ void __launch_bounds__(BL) k_decide128(KernelArgs a, const int *plist
                     // keep the next block's generation after this split (register pressure)
                     __builtin_amdgcn_sched_barrier(0);
                 }
-                s3l = cube_sum_q128_bf16<K, PREC>(bh, bl, lds_hi, lds_lo, lane);
+                inv = finish_norm128<K>(g, r2, a1, a2, t);
+                __builtin_amdgcn_sched_barrier(0);
+                s3l = cube_sum_q128_bf16<K, PREC, K == 128 ? 2 : 1>(bh, bl, lds_hi, lds_lo, lane);
             }
             const uint32_t w_acc = philox4x32_10(c0, c1, P.point_id, (uint32_t)(K / 2), P.key0, P.key1).x;
-            float t;
-            const float inv = finish_norm128<K>(g, r2, a1, a2, t);
             const float s3 = sum4(s3l) * (inv * inv * inv);
             const float la = log_a_f32<PROP>(P, t, s3);
             const float U = __builtin_fmaf((float)w_acc, 2.3283064365386963e-10f, 1.1641532182693481e-10f);
@@ -544,13 +550,14 @@ hipError_t launch_materialize_q_t(const KernelArgs &a, unsigned long long total_
     return hipGetLastError();
 }
 
-template <int K, int PREC, int PROP, int BL = Quarter<K>::BLOCK>
+template <int K, int PREC, int PROP, int BL = decide_block(K)>
 hipError_t launch_decide128_t(const KernelArgs &a, const int *plist, int n_plist, int n_cu,
                               unsigned long long total_tiles, hipStream_t st, int *grid_out)
 {
-    constexpr int lds = Quarter<K>::lds(PREC), B = BL;
+    constexpr int lds = Quarter<K>::lds(PREC), BD = Quarter<K>::BLOCK;
     const bool dbg = a.dbg_xhat != nullptr || a.dbg_t != nullptr;
-    auto kern = dbg ? k_decide128<K, PREC, PROP, true> : k_decide128<K, PREC, PROP, false, BL>;
+    const int B = dbg ? BD : BL;
+    auto kern = dbg ? k_decide128<K, PREC, PROP, true, BD> : k_decide128<K, PREC, PROP, false, BL>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     int per_cu = 0;
@@ -568,7 +575,7 @@ hipError_t launch_decide128_t(const KernelArgs &a, const int *plist, int n_plist
     return hipGetLastError();
 }
 
-template <int K, int PREC, int PROP, int BL = Quarter<K>::BLOCK>
+template <int K, int PREC, int PROP, int BL = decide_block(K)>
 int blocks_per_cu128_t()
 {
     constexpr int lds = Quarter<K>::lds(PREC);
@@ -580,11 +587,11 @@ int blocks_per_cu128_t()
     return per_cu < 1 ? 1 : per_cu;
 }
 
-// Tile variants at K = 128 (BF16x3, the paper's proposal): workgroups of 512
-// threads (the default: 2 waves per SIMD, no register spills), 768 (3 waves
-// per SIMD, some 30 registers spilled) and 1024 (4 waves per SIMD).
+// Tile variants at K = 128 (BF16x3, the paper's proposal): workgroups of 768
+// threads (the default: 3 waves per SIMD, no register spills), 512 (2 waves
+// per SIMD) and 1024 (4 waves per SIMD, some 13 registers spilled).
 constexpr int kVariants128 = 3;
-constexpr int kVariant128Block[kVariants128] = {Quarter<128>::BLOCK, 768, 1024};
+constexpr int kVariant128Block[kVariants128] = {decide_block(128), 512, 1024};
 
 template <int K>
 hipError_t launch_quarter_k(int prec, int prop, const KernelArgs &a, const int *plist, int n_plist, int n_cu,
@@ -605,7 +612,6 @@ hipError_t launch_quarter_k(int prec, int prop, const KernelArgs &a, const int *
 
 }  // namespace
 
-int decide128_block() { return Quarter<128>::BLOCK; }
 size_t quarter_table_bytes(int K, int prec)
 {
     if (K == 64) return prec == PREC_FP32 ? Quarter<64>::F32_BYTES : Quarter<64>::BF16_BYTES;
@@ -627,7 +633,7 @@ hipError_t launch_decide_quarter64(int prec, int prop, const KernelArgs &a, cons
 int decide128_n_variants() { return kVariants128; }
 int decide128_variant_block(int variant)
 {
-    return variant > 0 && variant < kVariants128 ? kVariant128Block[variant] : Quarter<128>::BLOCK;
+    return variant > 0 && variant < kVariants128 ? kVariant128Block[variant] : decide_block(128);
 }
 
 hipError_t launch_decide128_variant(int variant, const KernelArgs &a, const int *plist, int n_plist, int n_cu,

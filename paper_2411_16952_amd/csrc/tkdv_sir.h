@@ -29,6 +29,7 @@ struct SirArgs {
     float *xhat;                  // [m][2K] rows or nullptr
 };
 
+int sir_block(int K);            // threads per workgroup of the weights kernel
 int sir_waves(int K, int n_cu);  // waves of the weights kernel (one FP64 partial row each)
 hipError_t launch_sir_weights(int K, int prec, int proposal, const SirArgs &a, int n_cu, hipStream_t st);
 hipError_t launch_sir_scan(const SirArgs &a, hipStream_t st);

@@ -517,6 +517,7 @@ __global__ void __launch_bounds__(kBlock) k_sir_resample(SirArgs a)
 
 }  // namespace
 
+int sir_block(int K) { return K == 128 ? Quarter<128>::BLOCK : kBlock; }
 int sir_waves(int K, int n_cu)
 {
     return K == 128 ? n_cu * (Quarter<128>::BLOCK / kWave) : 4 * n_cu * (kBlock / kWave);
