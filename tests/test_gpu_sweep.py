@@ -8,7 +8,8 @@
   adaptive sweep of these points is one graph launch;
 * the hipGraph launch of 16 windows gives bit-identical results to launching
   the same sequence directly, and to itself on a second call;
-* every tile variant of the decision kernel gives bit-identical results;
+* every tile variant of the decision kernel gives bit-identical results (at
+  K = 16, 32, 64 and, with its workgroup sizes, at K = 128);
 * a point that reaches its proposal cap stops there;
 * against the oracle: the first n accepted samples of a K = 8, 16, 32, 64
   and 128 point (K = 128 also with its 1024-thread tile variant);
@@ -131,6 +132,21 @@ def test_sweep_tile_variants_are_bit_identical(T, ctx):
         res.append([(o["n_accepted"], o["n_proposed"], o["S3"], o["index"].cpu().numpy().tobytes(),
                      o["xhat"].cpu().numpy().tobytes()) for o in out])
     assert res[0] == res[1] == res[2] == res[3]
+
+
+def test_k128_tile_variants_are_bit_identical(T, ctx):
+    """At K = 128 the variants are the decision kernel's workgroup sizes
+    (768, 512 and 1024 threads: 3, 2 and 4 waves per SIMD)."""
+    pts, plans = _points(T)
+    i = 6
+    res = []
+    for v in range(3):
+        out, _, _ = ctx.sample_sweep([pts[i]], [SPECS[i][3]], [SPECS[i][4]], plans=[plans[i]], precision=T.BF16X3,
+                                     cfg=T.LaunchCfg(0, 1, 1 << 20, v, 1), capacity=[SPECS[i][3]])
+        say(f"K=128 variant {v} (block {ctx.timing()['decide_block']}): {out[0]['n_accepted']}")
+        res.append((out[0]["n_accepted"], out[0]["n_proposed"], out[0]["S3"], out[0]["index"].cpu().numpy().tobytes(),
+                    out[0]["xhat"].cpu().numpy().tobytes()))
+    assert res[0] == res[1] == res[2]
 
 
 @pytest.mark.parametrize("K,bp,c,target,variant", [(8, 40.0, 20.0, 400, 0), (16, 20.0, 60.0, 500, 0),
