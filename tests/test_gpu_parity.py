@@ -218,12 +218,14 @@ def test_batch_equals_single_point_runs(T, ctx):
         assert np.array_equal(out[p]["hist_u0"], single["hist_u0"])
 
 
-def test_sample_raises_a_violated_M(T, ctx):
+@pytest.mark.parametrize("K,bp,c,n", [(16, 40.0, 60.0, 200_003), (64, 40.0, 150.0, 100_003),
+                                     (128, 40.0, 750.0, 100_003)])
+def test_sample_raises_a_violated_M(T, ctx, K, bp, c, n):
     """A Sigma plan whose log M is set half a nat below the largest log a of the
     proposals: under the default policy the sampler raises log M above every
     log a seen and runs the point again, which then equals the oracle at the
-    raised M; the batch call does the same for the violating point only."""
-    K, bp, c, n = 16, 40.0, 60.0, 200_003
+    raised M; the batch call does the same for the violating point only (the
+    half-period kernel at K = 16, the quarter-period kernel at K = 64, 128)."""
     pt = T.make_point(K, 1.0, bp, c, seed=5, point_id=9)
     plan = T.plan_point(pt, T.SIGMA)
     pilot = ctx.sample(pt, n, plan=plan, precision=T.BF16X3)
@@ -247,6 +249,22 @@ def test_sample_raises_a_violated_M(T, ctx):
     assert out[0]["M_raises"] == r["M_raises"] and out[0]["log_M_used"] == r["log_M_used"]
     assert out[0]["n_accepted"] == r["n_accepted"] and out[1]["M_raises"] == 0
     assert np.array_equal(out[0]["index"].cpu().numpy(), r["index"].cpu().numpy())
+    # the other policies at the low M: counted (every proposal whose FP64 log a
+    # is above 0 by more than the fast path's error, at most those above 0), or
+    # the call fails
+    o_low = oracle_run(pt, low, T.SIGMA, n, cap=0)
+    try:
+        ctx.set_violation_policy(T.MV_COUNT)
+        g = ctx.sample(pt, n, plan=low, precision=T.BF16X3)
+        say(f"counted {g['n_M_violations']} violations; oracle: {(o_low['log_a'] > 0).sum()} above 0")
+        assert (o_low["log_a"] > 1e-2).sum() <= g["n_M_violations"] <= (o_low["log_a"] > 0).sum()
+        assert g["M_raises"] == 0 and g["log_M_used"] == low.log_M
+        ctx.set_violation_policy(T.MV_FAIL)
+        with pytest.raises(T.TkdvError) as e:
+            ctx.sample(pt, n, plan=low, precision=T.BF16X3)
+        assert e.value.status == -6
+    finally:
+        ctx.set_violation_policy(T.MV_RAISE)
 
 
 @pytest.mark.parametrize("K,bp", [(8, 20.0), (16, 20.0), (32, 60.0), (64, 40.0), (128, 40.0)])
