@@ -70,13 +70,37 @@ __device__ __forceinline__ float neg2_log_u_word(uint32_t w)
     return (upper && d < 0x1p-12f) ? ser : lg;
 }
 
+// The same -2 ln U with three instructions fewer: the word read as a signed
+// integer s (s = w - 2^32 for w >= 2^31) gives qs = (s + 1/2) 2^-32, which is
+// U below 1/2 and -(1 - U) above, both exact while |s| < 2^24, so one
+// conversion yields d = |qs| without the integer fold, and fract(qs) is the
+// log's argument (U, or 1 - d rounded) without a subtraction and a selection.
+// The error bound is that of neg2_log_u_word; the last bits differ.
+__device__ __forceinline__ float neg2_log_u_word_signed(uint32_t w)
+{
+    const float two_m32 = 2.3283064365386963e-10f;
+    const float qs = __builtin_fmaf((float)(int32_t)w, two_m32, 0.5f * two_m32);
+    const bool upper = qs < 0.0f;
+    const float d = __builtin_fabsf(qs);
+    const float ser = __builtin_fmaf(d, d, d + d);
+    const float lg = log2_hw(__builtin_amdgcn_fractf(qs)) * -1.3862943611198906f;  // -2 ln 2
+    return (upper && d < 0x1p-12f) ? ser : lg;
+}
+
 // ln U of a word (the same arithmetic, scaled by -1/2).
 __device__ __forceinline__ float log_u_word(uint32_t w) { return -0.5f * neg2_log_u_word(w); }
 
 // One Box-Muller pair: r = sqrt(-2 ln U1), (r cos 2 pi U2, r sin 2 pi U2).
+// FAST takes -2 ln U1 in the signed-word form: the decision and weight
+// kernels, whose FP32 values only steer the exact FP64 decision.  The kernels
+// that write rows for the caller keep the folded-word form, so that the rows'
+// bits (and what is fitted to them, such as the learned proposal's networks)
+// do not move with that choice.
+template <bool FAST = false>
 __device__ __forceinline__ void box_muller_f32(uint32_t w1, uint32_t w2, float &z0, float &z1)
 {
-    const float r = __builtin_amdgcn_sqrtf(neg2_log_u_word(w1));  // argument in [6e-10, 45]
+    const float r = __builtin_amdgcn_sqrtf(FAST ? neg2_log_u_word_signed(w1)
+                                                : neg2_log_u_word(w1));  // argument in [6e-10, 45]
     // U2 - 1/2 = (w2 - 2^31 + 1/2) 2^-32 in revolutions, centred on zero for
     // the hardware sin/cos; the signed integer w2 - 2^31 is formed exactly.
     const float rev = __builtin_fmaf((float)(int32_t)(w2 ^ 0x80000000u), 2.3283064365386963e-10f,
@@ -104,9 +128,11 @@ __device__ __forceinline__ float xor32(float v) { return __shfl_xor(v, 32, 64); 
 // point, and the acceptance word.  With NORMALIZE the coordinates are
 // projected onto the sphere (x^ = x |x|^-1); otherwise the caller scales
 // whatever it derives from x.  Both lanes of a proposal compute bitwise
-// identical |x|^2 and t.
+// identical |x|^2 and t.  FAST selects the Box-Muller form (box_muller_f32):
+// by default the signed-word form where the draw only feeds a decision or a
+// weight, the folded-word form where rows are written.
 // ---------------------------------------------------------------------------
-template <int K, int PROP, bool NORMALIZE>
+template <int K, int PROP, bool NORMALIZE, bool FAST = !NORMALIZE>
 __device__ __forceinline__ float gen_xhat(const DevPoint &P, uint64_t i, int half, float (&x)[K],
                                           float &t, uint32_t &w_acc)
 {
@@ -114,8 +140,8 @@ __device__ __forceinline__ float gen_xhat(const DevPoint &P, uint64_t i, int hal
 #pragma unroll
     for (int b = 0; b < K / 4; ++b) {
         uint4 w = philox4x32_10(c0, c1, c2, (uint32_t)(half * (K / 4) + b), P.key0, P.key1);
-        box_muller_f32(w.x, w.y, x[4 * b + 0], x[4 * b + 1]);
-        box_muller_f32(w.z, w.w, x[4 * b + 2], x[4 * b + 3]);
+        box_muller_f32<FAST>(w.x, w.y, x[4 * b + 0], x[4 * b + 1]);
+        box_muller_f32<FAST>(w.z, w.w, x[4 * b + 2], x[4 * b + 3]);
     }
     w_acc = philox4x32_10(c0, c1, c2, (uint32_t)(K / 2), P.key0, P.key1).x;
     if (PROP == PROP_SIGMA) {
@@ -557,8 +583,9 @@ __device__ __forceinline__ int mix_component(const DevMix &M, uint32_t w)
 // 0..2K-1 as for the paper's proposal, word 2K the acceptance word, 2K+1 the
 // component word, 2K+2 and 2K+3 the pair eta), |X|^-1, t of the projected
 // point and Qa = sum over this proposal of a_c X_c^2 (unprojected).  rv
-// points to the RV table of the point (LDS or global memory).
-template <int K, bool NORMALIZE>
+// points to the RV table of the point (LDS or global memory).  FAST as for
+// gen_xhat.
+template <int K, bool NORMALIZE, bool FAST = !NORMALIZE>
 __device__ __forceinline__ float gen_x_mix(const DevPoint &P, const DevMix &M, const float *rv, uint64_t i,
                                            int half, float (&x)[K], float &t, float &Qa, uint32_t &w_acc)
 {
@@ -566,15 +593,15 @@ __device__ __forceinline__ float gen_x_mix(const DevPoint &P, const DevMix &M, c
 #pragma unroll
     for (int b = 0; b < K / 4; ++b) {
         uint4 w = philox4x32_10(c0, c1, c2, (uint32_t)(half * (K / 4) + b), P.key0, P.key1);
-        box_muller_f32(w.x, w.y, x[4 * b + 0], x[4 * b + 1]);
-        box_muller_f32(w.z, w.w, x[4 * b + 2], x[4 * b + 3]);
+        box_muller_f32<FAST>(w.x, w.y, x[4 * b + 0], x[4 * b + 1]);
+        box_muller_f32<FAST>(w.z, w.w, x[4 * b + 2], x[4 * b + 3]);
     }
     const uint4 wl = philox4x32_10(c0, c1, c2, (uint32_t)(K / 2), P.key0, P.key1);
     w_acc = wl.x;
     const int comp = mix_component(M, wl.y);
     const bool def = comp < 0;
     float e0, e1;
-    box_muller_f32(wl.z, wl.w, e0, e1);
+    box_muller_f32<FAST>(wl.z, wl.w, e0, e1);
     e0 = def ? 0.0f : e0;
     e1 = def ? 0.0f : e1;
     const float2 *row = reinterpret_cast<const float2 *>(rv + (2 * (def ? 0 : comp) + half) * (2 * K + 2));

@@ -95,8 +95,9 @@ __device__ __forceinline__ float sum4(float v)
 // of modes K g/4 + 1 .. K g/4 + K/4 (coordinate m from word m, Box-Muller on
 // word pairs; X = Sigma^{1/2} z for the paper's proposal), and their
 // contributions to |X|^2, sum (j+1) X^2 and sum (j+1)^2 X^2 (t = sum k^2 X_k^2
-// over both blocks, k = K g/4 + j + 1).
-template <int K, int PROP>
+// over both blocks, k = K g/4 + j + 1).  FAST: the Box-Muller form of the
+// decision and weight kernels (box_muller_f32).
+template <int K, int PROP, bool FAST = true>
 __device__ __forceinline__ void gen_block128(const DevPoint &P, uint32_t c0, uint32_t c1, int g, int b,
                                              float (&v)[K / 4], float &r2, float &a1, float &a2)
 {
@@ -104,8 +105,8 @@ __device__ __forceinline__ void gen_block128(const DevPoint &P, uint32_t c0, uin
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         const uint4 w = philox4x32_10(c0, c1, P.point_id, (uint32_t)(b * (K / 4) + NB * g + q), P.key0, P.key1);
-        box_muller_f32(w.x, w.y, v[4 * q + 0], v[4 * q + 1]);
-        box_muller_f32(w.z, w.w, v[4 * q + 2], v[4 * q + 3]);
+        box_muller_f32<FAST>(w.x, w.y, v[4 * q + 0], v[4 * q + 1]);
+        box_muller_f32<FAST>(w.z, w.w, v[4 * q + 2], v[4 * q + 3]);
     }
     if (PROP == PROP_SIGMA) {
         const float4 *sg = reinterpret_cast<const float4 *>(P.sig + (K / 4) * g);
@@ -145,16 +146,17 @@ __device__ __forceinline__ float finish_norm128(int g, float r2, float a1, float
 // (words 0..2K-1 as in every sampler: coordinate m from word m, Box-Muller on
 // word pairs; X = Sigma^{1/2} z for the paper's proposal), |X|^-1, t of the
 // projected point and the acceptance word (word 2K).  With NORMALIZE the
-// coordinates are projected onto the sphere.  The four lanes of a proposal
+// coordinates are projected onto the sphere (rows for the caller, drawn with
+// the folded-word Box-Muller form unless FAST).  The four lanes of a proposal
 // hold bitwise identical |X|^2 and t.
-template <int K, int PROP, bool NORMALIZE>
+template <int K, int PROP, bool NORMALIZE, bool FAST = !NORMALIZE>
 __device__ __forceinline__ float gen_x128(const DevPoint &P, uint64_t i, int g, float (&c)[K / 4],
                                           float (&s)[K / 4], float &t, uint32_t &w_acc)
 {
     const uint32_t c0 = (uint32_t)i, c1 = (uint32_t)(i >> 32);
     float r2 = 0.0f, a1 = 0.0f, a2 = 0.0f;
-    gen_block128<K, PROP>(P, c0, c1, g, 0, c, r2, a1, a2);
-    gen_block128<K, PROP>(P, c0, c1, g, 1, s, r2, a1, a2);
+    gen_block128<K, PROP, FAST>(P, c0, c1, g, 0, c, r2, a1, a2);
+    gen_block128<K, PROP, FAST>(P, c0, c1, g, 1, s, r2, a1, a2);
     w_acc = philox4x32_10(c0, c1, P.point_id, (uint32_t)(K / 2), P.key0, P.key1).x;
     const float inv = finish_norm128<K>(g, r2, a1, a2, t);
     if (NORMALIZE) {

@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(BL) k_decide128(KernelArgs a, const int *plist
             if (DBG && a.dbg_xhat) {  // verification: the projected point, generated once more
                 float c[CPL], s[CPL], tt;
                 uint32_t ww;
-                gen_x128<K, PROP, true>(P, i, g, c, s, tt, ww);
+                gen_x128<K, PROP, true, true>(P, i, g, c, s, tt, ww);  // the decision's draw
                 if (valid) {
                     float *row = a.dbg_xhat + local * (2 * K);
 #pragma unroll
