@@ -70,20 +70,22 @@ __device__ __forceinline__ float neg2_log_u_word(uint32_t w)
     return (upper && d < 0x1p-12f) ? ser : lg;
 }
 
-// The same -2 ln U with three instructions fewer: the word read as a signed
-// integer s (s = w - 2^32 for w >= 2^31) gives qs = (s + 1/2) 2^-32, which is
-// U below 1/2 and -(1 - U) above, both exact while |s| < 2^24, so one
-// conversion yields d = |qs| without the integer fold, and fract(qs) is the
-// log's argument (U, or 1 - d rounded) without a subtraction and a selection.
-// The error bound is that of neg2_log_u_word; the last bits differ.
-__device__ __forceinline__ float neg2_log_u_word_signed(uint32_t w)
+// -log2 U = (-2 ln U)/(2 ln 2) of a word, four instructions fewer than
+// neg2_log_u_word with its error bound (the last bits differ): the word read
+// as a signed integer s (s = w - 2^32 for w >= 2^31) gives qs = (s + 1/2) 2^-32,
+// which is U below 1/2 and -(1 - U) above, both exact while |s| < 2^24, so one
+// conversion yields d = |qs| without the integer fold; fract(qs) is the log's
+// argument (U, or 1 - d rounded) without a subtraction and a selection; and
+// the factor 2 ln 2 is left out.  Series below d = 2^-12:
+// -log2(1 - d) = d (1 + d/2)/ln 2, truncation below d^2/3 relative.
+__device__ __forceinline__ float neg_log2_u_word_signed(uint32_t w)
 {
     const float two_m32 = 2.3283064365386963e-10f;
     const float qs = __builtin_fmaf((float)(int32_t)w, two_m32, 0.5f * two_m32);
     const bool upper = qs < 0.0f;
     const float d = __builtin_fabsf(qs);
-    const float ser = __builtin_fmaf(d, d, d + d);
-    const float lg = log2_hw(__builtin_amdgcn_fractf(qs)) * -1.3862943611198906f;  // -2 ln 2
+    const float ser = d * __builtin_fmaf(d, 0.72134752044448170f, 1.4426950408889634f);  // 1/(2 ln 2), 1/ln 2
+    const float lg = -log2_hw(__builtin_amdgcn_fractf(qs));
     return (upper && d < 0x1p-12f) ? ser : lg;
 }
 
@@ -91,23 +93,34 @@ __device__ __forceinline__ float neg2_log_u_word_signed(uint32_t w)
 __device__ __forceinline__ float log_u_word(uint32_t w) { return -0.5f * neg2_log_u_word(w); }
 
 // One Box-Muller pair: r = sqrt(-2 ln U1), (r cos 2 pi U2, r sin 2 pi U2).
-// FAST takes -2 ln U1 in the signed-word form: the decision and weight
-// kernels, whose FP32 values only steer the exact FP64 decision.  The kernels
-// that write rows for the caller keep the folded-word form, so that the rows'
-// bits (and what is fitted to them, such as the learned proposal's networks)
-// do not move with that choice.
+// FAST, for the decision and weight kernels, whose FP32 values only steer the
+// exact FP64 decision: r from the signed-word -log2 U1, i.e. every coordinate
+// scaled by 1/sqrt(2 ln 2), a common factor that the projection onto the
+// sphere removes (x^, t, S3 |x|^-3 and the mixture's ratios are invariant),
+// and the angle from the signed word without the shift by half a turn.  The
+// kernels that write rows for the caller keep the folded-word form and the
+// unit scale, so that the rows' bits (and what is fitted to them, such as the
+// learned proposal's networks) do not move with that choice.
 template <bool FAST = false>
 __device__ __forceinline__ void box_muller_f32(uint32_t w1, uint32_t w2, float &z0, float &z1)
 {
-    const float r = __builtin_amdgcn_sqrtf(FAST ? neg2_log_u_word_signed(w1)
-                                                : neg2_log_u_word(w1));  // argument in [6e-10, 45]
-    // U2 - 1/2 = (w2 - 2^31 + 1/2) 2^-32 in revolutions, centred on zero for
-    // the hardware sin/cos; the signed integer w2 - 2^31 is formed exactly.
-    const float rev = __builtin_fmaf((float)(int32_t)(w2 ^ 0x80000000u), 2.3283064365386963e-10f,
-                                     1.1641532182693481e-10f);
-    // sin/cos(2 pi (U2 - 1/2)) = -sin/-cos(2 pi U2)
-    z0 = -r * __builtin_amdgcn_cosf(rev);
-    z1 = -r * __builtin_amdgcn_sinf(rev);
+    const float r = __builtin_amdgcn_sqrtf(FAST ? neg_log2_u_word_signed(w1)
+                                                : neg2_log_u_word(w1));  // argument below 45
+    if constexpr (FAST) {
+        // w2 read as a signed integer: (s2 + 1/2) 2^-32 is U2 or U2 - 1, the same
+        // angle in revolutions, in [-1/2, 1/2) as below
+        const float rev = __builtin_fmaf((float)(int32_t)w2, 2.3283064365386963e-10f, 1.1641532182693481e-10f);
+        z0 = r * __builtin_amdgcn_cosf(rev);
+        z1 = r * __builtin_amdgcn_sinf(rev);
+    } else {
+        // U2 - 1/2 = (w2 - 2^31 + 1/2) 2^-32 in revolutions, centred on zero for
+        // the hardware sin/cos; the signed integer w2 - 2^31 is formed exactly.
+        const float rev = __builtin_fmaf((float)(int32_t)(w2 ^ 0x80000000u), 2.3283064365386963e-10f,
+                                         1.1641532182693481e-10f);
+        // sin/cos(2 pi (U2 - 1/2)) = -sin/-cos(2 pi U2)
+        z0 = -r * __builtin_amdgcn_cosf(rev);
+        z1 = -r * __builtin_amdgcn_sinf(rev);
+    }
 }
 
 // ln(1 + y) for 0 <= y: the rounding of 1 + y is corrected to first order
