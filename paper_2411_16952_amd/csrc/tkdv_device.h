@@ -76,17 +76,17 @@ __device__ __forceinline__ float neg2_log_u_word(uint32_t w)
 // which is U below 1/2 and -(1 - U) above, both exact while |s| < 2^24, so one
 // conversion yields d = |qs| without the integer fold; fract(qs) is the log's
 // argument (U, or 1 - d rounded) without a subtraction and a selection; and
-// the factor 2 ln 2 is left out.  Series below d = 2^-12:
+// the factor 2 ln 2 is left out.  Series below d = 2^-12, i.e. for words
+// w >= 2^32 - 2^20 (one integer comparison):
 // -log2(1 - d) = d (1 + d/2)/ln 2, truncation below d^2/3 relative.
 __device__ __forceinline__ float neg_log2_u_word_signed(uint32_t w)
 {
     const float two_m32 = 2.3283064365386963e-10f;
     const float qs = __builtin_fmaf((float)(int32_t)w, two_m32, 0.5f * two_m32);
-    const bool upper = qs < 0.0f;
     const float d = __builtin_fabsf(qs);
     const float ser = d * __builtin_fmaf(d, 0.72134752044448170f, 1.4426950408889634f);  // 1/(2 ln 2), 1/ln 2
     const float lg = -log2_hw(__builtin_amdgcn_fractf(qs));
-    return (upper && d < 0x1p-12f) ? ser : lg;
+    return w >= 0xFFF00000u ? ser : lg;
 }
 
 // ln U of a word (the same arithmetic, scaled by -1/2).
