@@ -748,9 +748,12 @@ __device__ __forceinline__ float mix_log_q_f32(const DevPoint &P, const DevMix &
         lmin = fminf(lmin, l[v]);
     }
     lmin = fminf(lmin, xor32(lmin));
-    float sum = 0.0f;
+    // K (lmin - l) as one FMA: K is a power of two (8, 16, 32), so K lmin is
+    // exact and the FMA rounds the same exact value as the difference scaled
+    const float klmin = Kf * lmin;
+    float sum = __builtin_amdgcn_exp2f(__builtin_fmaf(-Kf, l[0], klmin));
 #pragma unroll
-    for (int v = 0; v < 16; ++v) sum += __builtin_amdgcn_exp2f((lmin - l[v]) * Kf);
+    for (int v = 1; v < 16; ++v) sum += __builtin_amdgcn_exp2f(__builtin_fmaf(-Kf, l[v], klmin));
     sum = sum + xor32(sum);
     const float ln2 = 0.69314718055994531f;
     const float LN = M.c_net + ln2 * (log2_hw(sum) - Kf * (lmin + log2_hw(Qa * inv2)));
