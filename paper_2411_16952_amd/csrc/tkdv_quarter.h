@@ -237,16 +237,22 @@ __device__ __forceinline__ void quarter_tiles_bf16(const bf16x8 (&bh)[4][K / 64]
                                                    const char *lds_hi, const char *lds_lo, int lane, Fold &&fold)
 {
     constexpr int R = Quarter<K>::STEPS;
-    const bf16x8 *th = reinterpret_cast<const bf16x8 *>(lds_hi);
-    const bf16x8 *tl = reinterpret_cast<const bf16x8 *>(lds_lo);
+    constexpr int TILE = 4 * R * 64;  // entries of one tile's table
 #pragma unroll UNR
     for (int tau = 0; tau < Quarter<K>::TILES; ++tau) {
+        // this tile's entry offset, opaque to the compiler: the two tables'
+        // reads then address from one base each with immediate offsets, not a
+        // separate addition for every read past 64 KB (K = 128)
+        uint32_t e = (uint32_t)(tau * TILE + lane) * (uint32_t)sizeof(bf16x8);  // bytes
+        asm volatile("" : "+v"(e));
+        const bf16x8 *th = reinterpret_cast<const bf16x8 *>(lds_hi + e);
+        const bf16x8 *tl = reinterpret_cast<const bf16x8 *>(lds_lo + e);
         f32x4 acc[4] = {f32x4{}, f32x4{}, f32x4{}, f32x4{}};
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int o = 0; o < 4; ++o) {
-                const int idx = ((tau * 4 + o) * R + r) * 64 + lane;
+                const int idx = (o * R + r) * 64;
                 const bf16x8 ah = th[idx];
                 if constexpr (PREC == PREC_BF16X3) {
                     const bf16x8 al = tl[idx];
