@@ -70,7 +70,7 @@ __device__ __forceinline__ float neg2_log_u_word(uint32_t w)
     return (upper && d < 0x1p-12f) ? ser : lg;
 }
 
-// -log2 U = (-2 ln U)/(2 ln 2) of a word, four instructions fewer than
+// -log2 U = (-2 ln U)/(2 ln 2) of a word, five instructions fewer than
 // neg2_log_u_word with its error bound (the last bits differ): the word read
 // as a signed integer s (s = w - 2^32 for w >= 2^31) gives qs = (s + 1/2) 2^-32,
 // which is U below 1/2 and -(1 - U) above, both exact while |s| < 2^24, so one
