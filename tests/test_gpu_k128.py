@@ -75,6 +75,33 @@ def oracle_S3(xhat):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_eval_k128_uniform_against_oracle(T, ctx, prec):
+    """The uniform proposal (no Sigma scaling of the draw) per proposal at K = 128."""
+    pt = T.make_point(K, 1.0, 20.0, 1500.0, seed=13, point_id=5)
+    plan = T.plan_point(pt, T.UNIFORM)
+    n, i0 = 16 * 9 + 7, 12345
+    P = T.PRECISIONS[prec]
+    g = {k: v.cpu().numpy() for k, v in ctx.eval_proposals(pt, i0, n, proposal=T.UNIFORM, plan=plan,
+                                                            precision=P).items()}
+    o = oracle.sample(K, pt.E0, pt.beta_p, pt.c32, 0, plan.alpha_star, plan.log_M, pt.seed, pt.point_id, n, N,
+                      i0=i0, cap=0, want_log=True)
+    xo = np.stack([oracle.proposal(K, 1.0, pt.beta_p, pt.c32, 0, plan.alpha_star, plan.log_M, pt.seed,
+                                   pt.point_id, i0 + q)[0] for q in range(n)])
+    dx = np.linalg.norm(g["xhat"].astype(np.float64) - xo, axis=1)
+    say(f"uniform K=128 {prec}: max |dx^| = {dx.max():.3e}")
+    assert dx.max() < 2e-6
+    k2 = (np.arange(1, K + 1) ** 2).astype(np.float64)
+    to = (xo[:, :K] ** 2 + xo[:, K:] ** 2) @ k2
+    assert np.max(np.abs(g["t"] - to) / to) < 1e-5
+    tau = T.decision_window(pt, T.UNIFORM, P)
+    err = np.abs(g["log_a"].astype(np.float64) - o["log_a"])
+    say(f"   max|dlog a| = {err.max():.3e}, window = {tau:.3e}")
+    assert err.max() < tau / 2
+    amb = np.abs(o["log_u"] - o["log_a"]) < AMBIG
+    assert not ((g["accept"].astype(bool) != o["accept"].astype(bool)) & ~amb).any()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("n,i0", [(16 * 67 + 5, 0), (16 * 3 + 9, (1 << 33) + 7)])
 def test_eval_k128_against_oracle(T, ctx, case, prec, n, i0):
     pt, plan = case

@@ -68,6 +68,7 @@ EVAL_CASES = [  # K, beta', C3/C2, proposal, n, i0
     (32, 40.0, 150.0, 1, 1024 + 31, 0),
     (32, 20.0, 300.0, 0, 1024 + 3, (1 << 33) + 7),
     (64, 40.0, 300.0, 1, 512 + 9, 0),
+    (64, 20.0, 150.0, 0, 256 + 7, 1 << 20),   # the quarter-period kernel with the uniform proposal
 ]
 
 
